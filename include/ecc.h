@@ -1,0 +1,200 @@
+/*
+ * ecc.h - Euler-characteristic curves of 2D/3D scalar fields on MI355X (gfx950).
+ *
+ * C ABI of libecc.so.  The operation is the one of Laky & Zavala, "A Fast and
+ * Scalable Computational Topology Framework for the Euler Characteristic":
+ *
+ *   - a field of intensities (Methodology: pixels/voxels are the top cells of a
+ *     cubical complex; Algorithms 1 and 3 take a w x h or w x h x d field),
+ *   - a sublevel filtration over levels (Eq. (2): at level c a cell is active
+ *     when its value <= c; including a cell includes its edges and vertices),
+ *   - a connectivity (8/4 in 2D, 26 in 3D; Table 1, Table 2),
+ *
+ * in; and, for every level, the Euler characteristic chi = V - E + F - C of
+ * Eq. (1) together with the perimeter, area and volume descriptors of Tables 1
+ * and 2, out.  The curves are exact integers (int64).
+ *
+ * Conventions for every entry point:
+ *   - Every function returns an ecc_status; nothing throws across the ABI.  On
+ *     failure ecc_last_error() returns a message for the calling thread.
+ *   - Arguments are validated before any work is queued; on a validation
+ *     error nothing is written to any output.
+ *   - Device work is queued on the caller's HIP stream (an hipStream_t passed
+ *     as void*, NULL = the default stream) and is asynchronous: outputs are
+ *     valid once that stream has completed the work.  Field data and output
+ *     curves are DEVICE pointers owned by the caller and must stay valid until
+ *     then.  Threshold arrays are HOST pointers, read during the call only.
+ *   - One ecc_context may be used from several threads; calls on it are
+ *     serialised internally.  Work queued on different streams through one
+ *     context is ordered by the context (its workspace is reused).
+ */
+#ifndef ECC_H
+#define ECC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    ECC_OK = 0,
+    ECC_ERR_INVALID_ARG = 1,   /* a documented precondition does not hold            */
+    ECC_ERR_UNSUPPORTED = 2,   /* valid request outside what this build supports     */
+    ECC_ERR_OUT_OF_MEMORY = 3, /* device or host allocation failed                   */
+    ECC_ERR_DEVICE = 4,        /* a HIP runtime call failed                          */
+    ECC_ERR_BUSY = 5           /* serving admission is full; retry later             */
+} ecc_status;
+
+typedef enum { ECC_U8 = 1, ECC_U16 = 2, ECC_F32 = 3 } ecc_dtype;
+
+typedef struct ecc_context_s *ecc_context;
+
+/*
+ * A field and its filtration.
+ *   ndim          2 or 3.
+ *   dtype         ECC_U8, ECC_U16 or ECC_F32.
+ *   shape         2D {h, w}; 3D {d, h, w}; C order (last axis contiguous), each >= 1.
+ *                 Cells number h*w (or d*h*w) <= 2^40.
+ *   data          DEVICE pointer to the cells, caller-owned.
+ *   n_levels      L >= 1: number of filtration levels, 0 .. L-1.
+ *   thresholds    HOST pointer to L non-decreasing, non-NaN float32 values, or NULL.
+ *                 With thresholds, a cell is active at level l when
+ *                 float32(value) <= thresholds[l] (Eq. (2)).  NULL means the
+ *                 integer levels t_l = l the paper uses (values are the level
+ *                 index, Algorithm 1's increments at data[k]); NULL is allowed
+ *                 for ECC_U8 / ECC_U16 only.
+ *                 A cell that is active at no level (integer value >= L, float
+ *                 value above the last threshold, NaN) never enters; this is
+ *                 the paper's M+1 sentinel, not an error.  Cells outside the
+ *                 field never enter either (the collar of the Methodology).
+ *   connectivity  2D: 8 (vertex adjacency, the paper's default) or 4;
+ *                 3D: 26 (the paper's default) or 6 (derived: the same
+ *                 construction as Table 1's 4-C column one dimension up).
+ *                 0 selects the default.
+ */
+typedef struct {
+    int32_t ndim;
+    int32_t dtype;
+    int64_t shape[3];
+    const void *data;
+    int32_t n_levels;
+    int32_t connectivity;
+    const float *thresholds;
+} ecc_field;
+
+/*
+ * Output curves: DEVICE pointers to int64 arrays of length n_levels, caller-owned;
+ * NULL = channel not wanted (at least one must be non-NULL).
+ *   ec         Euler characteristic at each level (Eq. (1)).
+ *   perimeter  2D: unit lattice edges with exactly one active pixel (Table 1).
+ *              3D: crease measure, sum over lattice edges of kappa of the 4 voxels
+ *              around it (1 for one or three active, 2 for two diagonal); the
+ *              reading of Table 2's Perimeter column.
+ *   area       2D: active pixels.  3D: unit faces with exactly one active voxel
+ *              (Table 2 Area column).
+ *   volume     3D only (must be NULL in 2D): active voxels.
+ */
+typedef struct {
+    int64_t *ec;
+    int64_t *perimeter;
+    int64_t *area;
+    int64_t *volume;
+} ecc_curves;
+
+/* Create a context on HIP device `device`: uploads the contribution tables,
+ * queries the device.  *out receives the handle. */
+ecc_status ecc_create(int device, ecc_context *out);
+
+/* Wait for the context's queued work and free everything it owns. */
+ecc_status ecc_destroy(ecc_context ctx);
+
+/* Message of the last failing call on this thread ("" if none).  Valid until the
+ * thread's next call into the library. */
+const char *ecc_last_error(void);
+
+/* Name of a status code. */
+const char *ecc_status_string(ecc_status s);
+
+/*
+ * Check a request against every precondition of ecc_curves_compute without
+ * queuing any work (host-only; touches neither the field data nor the curves).
+ * Returns ECC_OK or the status ecc_curves_compute would return for it.
+ */
+ecc_status ecc_validate_field(const ecc_field *field, const ecc_curves *curves);
+
+/*
+ * EC, perimeter, area and volume curves of one field (one pass over the field:
+ * level index, vertex-contribution deltas, per-workgroup histograms, merge and
+ * prefix scan over levels).
+ */
+ecc_status ecc_curves_compute(ecc_context ctx, const ecc_field *field, const ecc_curves *curves,
+                              void *stream);
+
+/*
+ * The same for n fields of any mix of shapes and dtypes in one persistent launch
+ * (the paper's dispatch of many small images, Discussion of the microscopy case).
+ * fields[i] and curves[i] follow the single-field contract.  The launch geometry
+ * comes from the context's tuning cache (see ecc_batch_plan_tune), else defaults.
+ * All fields of one call must be 2D with the same connectivity, or 3D with the
+ * same connectivity.
+ */
+ecc_status ecc_curves_compute_batch(ecc_context ctx, int32_t n, const ecc_field *fields,
+                                    const ecc_curves *curves, void *stream);
+
+/*
+ * Autotuner: times the batched launch over candidate tile shapes and work splits
+ * for this mix of fields (data must be valid device memory; the outputs of the
+ * trial runs are discarded) and stores the fastest in the context's cache, keyed by
+ * the mix's size classes.  Synchronises `stream`.  Optional.
+ */
+ecc_status ecc_batch_plan_tune(ecc_context ctx, int32_t n, const ecc_field *fields, void *stream);
+
+/*
+ * Host copies of the per-vertex contribution tables the kernels use, built from
+ * the cell counts of Tables 1 and 2 (for tests):
+ *   2D: out[16][4] = {4*EC(conn), 2*perimeter, 4*area, 0} per 2x2 mask, mask bit k
+ *       = pixel (i-1,j-1), (i-1,j), (i,j-1), (i,j) for k = 0..3 around vertex (i,j).
+ *   3D: out[256][4] = {8*EC(conn), 2*crease, 4*surface, 8*volume} per 2x2x2 mask,
+ *       mask bit (dx + 2*dy + 4*dz) = voxel at offset (dz,dy,dx) in {0,1}^3.
+ */
+ecc_status ecc_vertex_table(int32_t ndim, int32_t connectivity, int32_t *out);
+
+/* ---------------------------------------------------------------------------
+ * Serving: a request loop with continuous batching.
+ * Requests are admitted while their device memory fits the budget and a slot is
+ * free; admitted requests are copied to device-resident slots on a copy stream
+ * and computed by batched launches that include every request admitted so far.
+ * ------------------------------------------------------------------------- */
+typedef struct ecc_server_s *ecc_server;
+
+typedef struct {
+    size_t hbm_budget_bytes; /* device bytes for request fields + curves         */
+    int32_t max_slots;       /* requests resident at once                         */
+    int32_t max_batch;       /* requests per batched launch (<= max_slots)        */
+} ecc_server_config;
+
+/*
+ * A request: the field lives in HOST memory (copied during ecc_server_submit
+ * into a pinned staging buffer, so the caller may reuse it on return); the
+ * result curves are written into caller HOST arrays of length n_levels (NULL =
+ * not wanted, as in ecc_curves) once the request completes.
+ */
+ecc_status ecc_server_create(ecc_context ctx, const ecc_server_config *cfg, ecc_server *out);
+/* ECC_ERR_BUSY when the request does not fit right now (retry after a poll);
+ * ECC_ERR_INVALID_ARG when it can never fit the budget or is malformed. */
+ecc_status ecc_server_submit(ecc_server srv, const ecc_field *field, const ecc_curves *host_curves,
+                             uint64_t *ticket);
+/* Advance the loop (admit, launch, complete) and report `ticket`:
+ * *done = 1 when its host curves are written, 0 while pending. */
+ecc_status ecc_server_poll(ecc_server srv, uint64_t ticket, int32_t *done);
+/* Block until every submitted request has completed. */
+ecc_status ecc_server_drain(ecc_server srv);
+/* Drain, then free the server. */
+ecc_status ecc_server_destroy(ecc_server srv);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ECC_H */

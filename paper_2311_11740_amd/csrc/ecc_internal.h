@@ -1,0 +1,92 @@
+// Internal declarations shared by the host runtime, the table builders and the
+// kernel launchers of libecc.
+#pragma once
+
+#include <cstdint>
+#include <string>
+
+#include "../../include/ecc.h"
+
+namespace ecc {
+
+// ---- errors ---------------------------------------------------------------
+ecc_status fail(ecc_status s, const std::string &msg);
+void clear_error();
+
+// ---- tables (ecc_tables.cpp) -----------------------------------------------
+void vertex_table_2d(int connectivity, int32_t out[16][4]);
+void vertex_table_3d(int connectivity, int32_t out[256][4]);
+void cell_delta_table_2d(int connectivity, int32_t delta[256][3]);
+extern const int kNbr2[8][2];
+
+// ---- histogram word layouts ---------------------------------------------------
+// 2D bin word (uint64): [ ec+3 : 21 bits | perimeter+4 : 23 bits | count : 20 bits ].
+// The per-cell biases make every field non-negative; a bin is decoded with the
+// count n: ec = f0 - 3n, perimeter = f1 - 4n, area = n.  Valid while a
+// workgroup adds at most kFlush2D cells between drains (ec field <= 4n < 2^21).
+constexpr int kEcBias2 = 3, kPerBias2 = 4;
+constexpr int kShiftPer2 = 21, kShiftCnt2 = 44;
+constexpr int64_t kFlush2D = (1 << 19) - 1;
+// 3D bin word (uint64): [ ec+7 : 22 bits | surface+6 : 22 bits | count : 20 bits ],
+// crease in a second uint32 word as crease+12.  Valid while at most kFlush3D
+// cells are added between drains (ec field <= 14n < 2^22).
+constexpr int kEcBias3 = 7, kSurfBias3 = 6, kCreaseBias3 = 12;
+constexpr int kShiftSurf3 = 22, kShiftCnt3 = 44;
+constexpr int64_t kFlush3D = (1 << 18) - 1;
+
+// ---- level index of a value ---------------------------------------------------
+enum LevelMode : int {
+    LM_IDENTITY = 0,  // integer value v: level v if v < L, else never (L)
+    LM_LUT = 1,       // integer value v: level lut[v] (built from thresholds on the device)
+    LM_AFFINE = 2,    // float: thresholds close to t0 + l*step; guess, then exact correction
+    LM_SEARCH = 3,    // float: binary search over the thresholds
+};
+
+struct LevelArgs {
+    int32_t L;
+    int32_t mode;
+    const float *thr;     // device, L floats (LM_AFFINE / LM_SEARCH)
+    const uint16_t *lut;  // device, 256 or 65536 entries (LM_LUT)
+    float t0, inv_step;   // LM_AFFINE
+};
+
+// ---- kernel launch descriptors ---------------------------------------------------
+struct Launch2D {
+    const void *data;
+    int dtype;
+    int64_t h, w;
+    LevelArgs lv;
+    int32_t lo, hi;             // level window [lo, hi) histogrammed by this pass
+    const uint64_t *delta_lut;  // device, 256 packed per-cell deltas
+    int32_t *partial;           // device, [grid][3][L]
+    int grid;
+    int tile_rows;
+};
+
+struct Launch3D {
+    const void *data;
+    int dtype;
+    int64_t d, h, w;
+    LevelArgs lv;
+    int32_t lo, hi;
+    const int64_t *vtab;  // device, 256 packed per-vertex contributions (x8 scale)
+    int32_t *partial;     // device, [grid][4][L]
+    int grid;
+    bool want_crease;
+};
+
+// device-side launchers (ecc_kernels.hip); return a hipError_t as int
+int launch_2d(const Launch2D &a, void *stream);
+int launch_3d(const Launch3D &a, void *stream);
+int launch_reduce(const int32_t *partial, int grid, int nch, int L, unsigned ch_mask,
+                  int64_t *totals, void *stream);
+int launch_scan(const int64_t *totals, int nch, int L, int64_t *const out[4], void *stream);
+int launch_level_lut(const float *thr, int L, int n_values, uint16_t *lut, void *stream);
+
+// tile geometry used by the single-field kernels
+constexpr int kTile2DCols = 256;
+constexpr int kTile3DX = 64, kTile3DY = 4, kTile3DZ = 16;
+size_t lds_bytes_2d(int window, int tile_rows);
+size_t lds_bytes_3d(int window, bool want_crease);
+
+}  // namespace ecc

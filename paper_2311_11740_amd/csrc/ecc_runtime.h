@@ -1,0 +1,82 @@
+// Host-side context and helpers of libecc (not part of the public ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "ecc_internal.h"
+
+namespace ecc {
+
+constexpr int kMaxLevels = 65535;   // level indices are staged as u16 (L = never)
+constexpr int kMaxWindow = 4096;    // levels histogrammed per pass (LDS budget)
+constexpr size_t kThrCacheMax = 32;
+
+struct FieldInfo {
+    int ndim, dtype;
+    int64_t d, h, w, cells;
+    int L, conn;
+    int elem_bytes;
+};
+
+struct DevBuf {
+    void *ptr = nullptr;
+    size_t bytes = 0;
+    ecc_status ensure(size_t need, const char *what);
+    void release();
+};
+
+struct ThrEntry {
+    int L = 0;
+    std::vector<float> host;
+    float *h_pinned = nullptr;
+    float *d_thr = nullptr;
+    uint16_t *d_lut8 = nullptr;
+    uint16_t *d_lut16 = nullptr;
+    bool affine = false;
+    float t0 = 0.f, inv_step = 0.f;
+};
+
+struct Workspace {
+    DevBuf partial, totals;
+    void release() {
+        partial.release();
+        totals.release();
+    }
+};
+
+struct BatchState;  // ecc_batch.hip
+
+}  // namespace ecc
+
+struct ecc_context_s {
+    int device = 0;
+    int n_cu = 0;
+    std::string arch;
+    std::mutex mu;
+    uint64_t *d_delta2[2] = {nullptr, nullptr};  // 2D per-cell deltas, 8-C and 4-C
+    int32_t h_delta2[2][256][3];
+    int64_t *d_vtab3[2] = {nullptr, nullptr};    // 3D per-vertex table, 26-C and 6-C
+    std::vector<ecc::ThrEntry *> thr_cache;
+    ecc::Workspace ws;
+    hipEvent_t ws_event = nullptr;
+    void *ws_stream = nullptr;
+    bool ws_used = false;
+    ecc::BatchState *batch = nullptr;
+};
+
+namespace ecc {
+ecc_status hip_fail(int err, const char *what);
+ecc_status validate_field(const ecc_field *f, const ecc_curves *c, FieldInfo *info, bool curves_on_host);
+void free_thresholds(ThrEntry *t);
+ecc_status level_args(ecc_context ctx, const ecc_field *f, const FieldInfo &fi, void *stream, LevelArgs *lv);
+ecc_status acquire_workspace(ecc_context ctx, void *stream);
+ecc_status release_workspace(ecc_context ctx, void *stream);
+ecc_status grow(ecc_context ctx, DevBuf &b, size_t need, const char *what);
+ecc_status compute_one(ecc_context ctx, const ecc_field *f, const FieldInfo &fi, const ecc_curves *c, void *stream);
+int pick_grid(ecc_context ctx, int64_t n_tiles, size_t lds_per_wg);
+void destroy_batch_state(ecc_context ctx);
+}  // namespace ecc

@@ -1,0 +1,437 @@
+// Host runtime of libecc: context, validation, threshold cache, workspace and
+// the single-field entry point.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "ecc_runtime.h"
+
+namespace ecc {
+
+// ---------------------------------------------------------------------------
+// errors
+// ---------------------------------------------------------------------------
+static thread_local std::string g_err;
+
+ecc_status fail(ecc_status s, const std::string &msg) {
+    g_err = msg;
+    return s;
+}
+void clear_error() { g_err.clear(); }
+
+ecc_status hip_fail(int err, const char *what) {
+    return fail(ECC_ERR_DEVICE,
+                std::string(what) + ": " + hipGetErrorString((hipError_t)err));
+}
+
+// ---------------------------------------------------------------------------
+// validation
+// ---------------------------------------------------------------------------
+ecc_status validate_field(const ecc_field *f, const ecc_curves *c, FieldInfo *info,
+                          bool curves_on_host) {
+    if (!f) return fail(ECC_ERR_INVALID_ARG, "field is NULL");
+    if (!c) return fail(ECC_ERR_INVALID_ARG, "curves is NULL");
+    if (f->ndim != 2 && f->ndim != 3) return fail(ECC_ERR_INVALID_ARG, "ndim must be 2 or 3");
+    if (f->dtype != ECC_U8 && f->dtype != ECC_U16 && f->dtype != ECC_F32)
+        return fail(ECC_ERR_INVALID_ARG, "dtype must be ECC_U8, ECC_U16 or ECC_F32");
+    for (int k = 0; k < f->ndim; ++k)
+        if (f->shape[k] < 1) return fail(ECC_ERR_INVALID_ARG, "every shape entry must be >= 1");
+    if (!f->data) return fail(ECC_ERR_INVALID_ARG, "field data is NULL");
+    if (f->n_levels < 1) return fail(ECC_ERR_INVALID_ARG, "n_levels must be >= 1");
+    if (f->n_levels > kMaxLevels)
+        return fail(ECC_ERR_UNSUPPORTED, "n_levels above 65535 is not supported");
+    int conn = f->connectivity;
+    if (conn == 0) conn = f->ndim == 2 ? 8 : 26;
+    if (f->ndim == 2 && conn != 8 && conn != 4)
+        return fail(ECC_ERR_INVALID_ARG, "2D connectivity must be 8 or 4");
+    if (f->ndim == 3 && conn != 26 && conn != 6)
+        return fail(ECC_ERR_INVALID_ARG, "3D connectivity must be 26 or 6");
+    if (f->dtype == ECC_F32 && !f->thresholds)
+        return fail(ECC_ERR_INVALID_ARG, "float32 fields need a thresholds array");
+    if (f->thresholds) {
+        for (int l = 0; l < f->n_levels; ++l) {
+            if (std::isnan(f->thresholds[l]))
+                return fail(ECC_ERR_INVALID_ARG, "thresholds must not be NaN");
+            if (l > 0 && f->thresholds[l] < f->thresholds[l - 1])
+                return fail(ECC_ERR_INVALID_ARG, "thresholds must be non-decreasing");
+        }
+    }
+    if (f->ndim == 2 && c->volume) return fail(ECC_ERR_INVALID_ARG, "volume must be NULL for 2D fields");
+    if (!c->ec && !c->perimeter && !c->area && !c->volume)
+        return fail(ECC_ERR_INVALID_ARG, "no output curve requested");
+    int64_t cells = 1;
+    for (int k = 0; k < f->ndim; ++k) {
+        if (f->shape[k] > (int64_t(1) << 40) / cells)
+            return fail(ECC_ERR_UNSUPPORTED, "more than 2^40 cells");
+        cells *= f->shape[k];
+    }
+    (void)curves_on_host;
+    info->ndim = f->ndim;
+    info->dtype = f->dtype;
+    info->d = f->ndim == 3 ? f->shape[0] : 1;
+    info->h = f->shape[f->ndim - 2];
+    info->w = f->shape[f->ndim - 1];
+    info->cells = cells;
+    info->L = f->n_levels;
+    info->conn = conn;
+    info->elem_bytes = f->dtype == ECC_U8 ? 1 : (f->dtype == ECC_U16 ? 2 : 4);
+    return ECC_OK;
+}
+
+}  // namespace ecc
+
+using namespace ecc;
+
+// ---------------------------------------------------------------------------
+// context
+// ---------------------------------------------------------------------------
+static ecc_status upload(void **dst, const void *src, size_t bytes) {
+    int e = (int)hipMalloc(dst, bytes);
+    if (e) return hip_fail(e, "hipMalloc(table)");
+    e = (int)hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice);
+    if (e) return hip_fail(e, "hipMemcpy(table)");
+    return ECC_OK;
+}
+
+extern "C" ecc_status ecc_create(int device, ecc_context *out) {
+    clear_error();
+    if (!out) return fail(ECC_ERR_INVALID_ARG, "ecc_create: out is NULL");
+    *out = nullptr;
+    int ndev = 0;
+    int e = (int)hipGetDeviceCount(&ndev);
+    if (e) return hip_fail(e, "hipGetDeviceCount");
+    if (device < 0 || device >= ndev) return fail(ECC_ERR_INVALID_ARG, "ecc_create: no such device");
+    e = (int)hipSetDevice(device);
+    if (e) return hip_fail(e, "hipSetDevice");
+    hipDeviceProp_t prop;
+    e = (int)hipGetDeviceProperties(&prop, device);
+    if (e) return hip_fail(e, "hipGetDeviceProperties");
+    auto *ctx = new ecc_context_s();
+    ctx->device = device;
+    ctx->n_cu = prop.multiProcessorCount;
+    ctx->arch = prop.gcnArchName;
+    // per-cell delta tables (2D) and per-vertex tables (3D)
+    for (int k = 0; k < 2; ++k) {
+        const int conn2 = k == 0 ? 8 : 4;
+        int32_t dt[256][3];
+        cell_delta_table_2d(conn2, dt);
+        uint64_t packed[256];
+        for (int p = 0; p < 256; ++p)
+            packed[p] = (uint64_t)(dt[p][0] + kEcBias2) |
+                        (uint64_t)(dt[p][1] + kPerBias2) << kShiftPer2 | 1ull << kShiftCnt2;
+        ecc_status s = upload((void **)&ctx->d_delta2[k], packed, sizeof(packed));
+        if (s != ECC_OK) {
+            ecc_destroy(ctx);
+            return s;
+        }
+        std::memcpy(ctx->h_delta2[k], dt, sizeof(dt));
+        const int conn3 = k == 0 ? 26 : 6;
+        int32_t vt[256][4];
+        vertex_table_3d(conn3, vt);
+        int64_t vp[256];
+        for (int m = 0; m < 256; ++m)  // four 16-bit fields, every channel scaled by 8
+            vp[m] = (int64_t)vt[m][0] + (int64_t)(vt[m][1] * 4) * 65536 +
+                    (int64_t)(vt[m][2] * 2) * 4294967296LL + (int64_t)vt[m][3] * 281474976710656LL;
+        s = upload((void **)&ctx->d_vtab3[k], vp, sizeof(vp));
+        if (s != ECC_OK) {
+            ecc_destroy(ctx);
+            return s;
+        }
+    }
+    e = (int)hipEventCreateWithFlags(&ctx->ws_event, hipEventDisableTiming);
+    if (e) {
+        ecc_destroy(ctx);
+        return hip_fail(e, "hipEventCreate");
+    }
+    *out = ctx;
+    return ECC_OK;
+}
+
+extern "C" ecc_status ecc_destroy(ecc_context ctx) {
+    clear_error();
+    if (!ctx) return ECC_OK;
+    hipSetDevice(ctx->device);
+    hipDeviceSynchronize();
+    for (int k = 0; k < 2; ++k) {
+        if (ctx->d_delta2[k]) hipFree(ctx->d_delta2[k]);
+        if (ctx->d_vtab3[k]) hipFree(ctx->d_vtab3[k]);
+    }
+    for (auto *t : ctx->thr_cache) free_thresholds(t);
+    ctx->thr_cache.clear();
+    ctx->ws.release();
+    if (ctx->ws_event) hipEventDestroy(ctx->ws_event);
+    destroy_batch_state(ctx);
+    delete ctx;
+    return ECC_OK;
+}
+
+extern "C" const char *ecc_last_error(void) { return g_err.c_str(); }
+
+extern "C" const char *ecc_status_string(ecc_status s) {
+    switch (s) {
+    case ECC_OK: return "ECC_OK";
+    case ECC_ERR_INVALID_ARG: return "ECC_ERR_INVALID_ARG";
+    case ECC_ERR_UNSUPPORTED: return "ECC_ERR_UNSUPPORTED";
+    case ECC_ERR_OUT_OF_MEMORY: return "ECC_ERR_OUT_OF_MEMORY";
+    case ECC_ERR_DEVICE: return "ECC_ERR_DEVICE";
+    case ECC_ERR_BUSY: return "ECC_ERR_BUSY";
+    }
+    return "unknown status";
+}
+
+namespace ecc {
+
+// ---------------------------------------------------------------------------
+// device buffers
+// ---------------------------------------------------------------------------
+void DevBuf::release() {
+    if (ptr) hipFree(ptr);
+    ptr = nullptr;
+    bytes = 0;
+}
+
+ecc_status DevBuf::ensure(size_t need, const char *what) {
+    if (need <= bytes) return ECC_OK;
+    release();
+    size_t cap = std::max(need, (size_t)1 << 20);
+    int e = (int)hipMalloc(&ptr, cap);
+    if (e) {
+        ptr = nullptr;
+        return fail(ECC_ERR_OUT_OF_MEMORY, std::string("hipMalloc(") + what + ") failed");
+    }
+    bytes = cap;
+    return ECC_OK;
+}
+
+// ---------------------------------------------------------------------------
+// thresholds: device copies cached by content
+// ---------------------------------------------------------------------------
+void free_thresholds(ThrEntry *t) {
+    if (t->d_thr) hipFree(t->d_thr);
+    if (t->d_lut8) hipFree(t->d_lut8);
+    if (t->d_lut16) hipFree(t->d_lut16);
+    if (t->h_pinned) hipHostFree(t->h_pinned);
+    delete t;
+}
+
+ecc_status get_thresholds(ecc_context ctx, const float *thr, int L, int dtype, void *stream,
+                          const ThrEntry **out) {
+    ThrEntry *hit = nullptr;
+    for (auto *t : ctx->thr_cache)
+        if (t->L == L && std::memcmp(t->host.data(), thr, sizeof(float) * L) == 0) {
+            hit = t;
+            break;
+        }
+    if (!hit) {
+        if (ctx->thr_cache.size() >= kThrCacheMax) {
+            // rare: drop every cached set once all queued work is done
+            int e = (int)hipDeviceSynchronize();
+            if (e) return hip_fail(e, "hipDeviceSynchronize");
+            for (auto *t : ctx->thr_cache) free_thresholds(t);
+            ctx->thr_cache.clear();
+        }
+        auto *t = new ThrEntry();
+        t->L = L;
+        t->host.assign(thr, thr + L);
+        int e = (int)hipHostMalloc(&t->h_pinned, sizeof(float) * L, 0);
+        if (e) {
+            delete t;
+            return hip_fail(e, "hipHostMalloc(thresholds)");
+        }
+        std::memcpy(t->h_pinned, thr, sizeof(float) * L);
+        e = (int)hipMalloc(&t->d_thr, sizeof(float) * L);
+        if (e) {
+            free_thresholds(t);
+            return fail(ECC_ERR_OUT_OF_MEMORY, "hipMalloc(thresholds) failed");
+        }
+        e = (int)hipMemcpyAsync(t->d_thr, t->h_pinned, sizeof(float) * L, hipMemcpyHostToDevice,
+                                (hipStream_t)stream);
+        if (e) {
+            free_thresholds(t);
+            return hip_fail(e, "hipMemcpyAsync(thresholds)");
+        }
+        // affine check: level guess from (x - t0) / step, then exact correction
+        t->affine = false;
+        if (L >= 2) {
+            const double t0 = thr[0], step = ((double)thr[L - 1] - t0) / (L - 1);
+            if (step > 0 && std::isfinite(step) && std::isfinite(t0)) {
+                double dev = 0;
+                for (int l = 0; l < L; ++l) dev = std::max(dev, std::fabs(thr[l] - (t0 + l * step)));
+                if (dev <= 0.5 * step) {
+                    t->affine = true;
+                    t->t0 = (float)t0;
+                    t->inv_step = (float)(1.0 / step);
+                }
+            }
+        }
+        ctx->thr_cache.push_back(t);
+        hit = t;
+    }
+    // integer fields with thresholds: value -> level table, built once on the device
+    if (dtype == ECC_U8 && !hit->d_lut8) {
+        int e = (int)hipMalloc(&hit->d_lut8, 256 * sizeof(uint16_t));
+        if (e) return fail(ECC_ERR_OUT_OF_MEMORY, "hipMalloc(level table) failed");
+        e = launch_level_lut(hit->d_thr, L, 256, hit->d_lut8, stream);
+        if (e) return hip_fail(e, "level table kernel");
+    }
+    if (dtype == ECC_U16 && !hit->d_lut16) {
+        int e = (int)hipMalloc(&hit->d_lut16, 65536 * sizeof(uint16_t));
+        if (e) return fail(ECC_ERR_OUT_OF_MEMORY, "hipMalloc(level table) failed");
+        e = launch_level_lut(hit->d_thr, L, 65536, hit->d_lut16, stream);
+        if (e) return hip_fail(e, "level table kernel");
+    }
+    *out = hit;
+    return ECC_OK;
+}
+
+ecc_status level_args(ecc_context ctx, const ecc_field *f, const FieldInfo &fi, void *stream,
+                      LevelArgs *lv) {
+    lv->L = fi.L;
+    lv->thr = nullptr;
+    lv->lut = nullptr;
+    lv->t0 = 0.f;
+    lv->inv_step = 0.f;
+    if (!f->thresholds) {
+        lv->mode = LM_IDENTITY;
+        return ECC_OK;
+    }
+    const ThrEntry *te = nullptr;
+    ecc_status s = get_thresholds(ctx, f->thresholds, fi.L, fi.dtype, stream, &te);
+    if (s != ECC_OK) return s;
+    lv->thr = te->d_thr;
+    if (fi.dtype == ECC_U8) {
+        lv->mode = LM_LUT;
+        lv->lut = te->d_lut8;
+    } else if (fi.dtype == ECC_U16) {
+        lv->mode = LM_LUT;
+        lv->lut = te->d_lut16;
+    } else if (te->affine) {
+        lv->mode = LM_AFFINE;
+        lv->t0 = te->t0;
+        lv->inv_step = te->inv_step;
+    } else {
+        lv->mode = LM_SEARCH;
+    }
+    return ECC_OK;
+}
+
+// order work on `stream` after the previous use of the context's workspace
+ecc_status acquire_workspace(ecc_context ctx, void *stream) {
+    if (ctx->ws_used && ctx->ws_stream != stream) {
+        int e = (int)hipStreamWaitEvent((hipStream_t)stream, ctx->ws_event, 0);
+        if (e) return hip_fail(e, "hipStreamWaitEvent");
+    }
+    return ECC_OK;
+}
+
+ecc_status release_workspace(ecc_context ctx, void *stream) {
+    int e = (int)hipEventRecord(ctx->ws_event, (hipStream_t)stream);
+    if (e) return hip_fail(e, "hipEventRecord");
+    ctx->ws_used = true;
+    ctx->ws_stream = stream;
+    return ECC_OK;
+}
+
+// grow a workspace buffer; the old one may still be read by queued work
+ecc_status grow(ecc_context ctx, DevBuf &b, size_t need, const char *what) {
+    if (need <= b.bytes) return ECC_OK;
+    if (ctx->ws_used) {
+        int e = (int)hipEventSynchronize(ctx->ws_event);
+        if (e) return hip_fail(e, "hipEventSynchronize");
+    }
+    return b.ensure(need, what);
+}
+
+int pick_grid(ecc_context ctx, int64_t n_tiles, size_t lds_per_wg) {
+    const size_t lds_cu = 160 * 1024;
+    int per_cu = (int)std::min<size_t>(4, std::max<size_t>(1, lds_cu / std::max<size_t>(lds_per_wg, 1)));
+    int64_t g = (int64_t)ctx->n_cu * per_cu;
+    if (g > n_tiles) g = n_tiles;
+    if (g >= 8) g -= g % 8;
+    return (int)std::max<int64_t>(1, g);
+}
+
+ecc_status compute_one(ecc_context ctx, const ecc_field *f, const FieldInfo &fi,
+                       const ecc_curves *c, void *stream) {
+    LevelArgs lv;
+    ecc_status s = level_args(ctx, f, fi, stream, &lv);
+    if (s != ECC_OK) return s;
+    const int L = fi.L;
+    const int nch = fi.ndim == 2 ? 3 : 4;
+    const int win = std::min(L, kMaxWindow);
+    const bool crease = fi.ndim == 3 && c->perimeter != nullptr;
+    int64_t n_tiles;
+    size_t lds;
+    if (fi.ndim == 2) {
+        n_tiles = ((fi.w + kTile2DCols - 1) / kTile2DCols) * ((fi.h + 31) / 32);
+        lds = lds_bytes_2d(win, 32) + 32 * 1024;
+    } else {
+        n_tiles = ((fi.w + kTile3DX - 1) / kTile3DX) * ((fi.h + kTile3DY - 1) / kTile3DY) *
+                  ((fi.d + kTile3DZ - 1) / kTile3DZ);
+        lds = lds_bytes_3d(win, crease) + 16 * 1024;
+    }
+    const int grid = pick_grid(ctx, n_tiles, lds);
+    s = grow(ctx, ctx->ws.partial, (size_t)grid * nch * L * sizeof(int32_t), "partials");
+    if (s != ECC_OK) return s;
+    s = grow(ctx, ctx->ws.totals, (size_t)nch * L * sizeof(int64_t), "totals");
+    if (s != ECC_OK) return s;
+    int32_t *partial = (int32_t *)ctx->ws.partial.ptr;
+    int64_t *totals = (int64_t *)ctx->ws.totals.ptr;
+    const int k = (fi.ndim == 2 ? (fi.conn == 8 ? 0 : 1) : (fi.conn == 26 ? 0 : 1));
+    for (int lo = 0; lo < L; lo += win) {
+        const int hi = std::min(L, lo + win);
+        int e;
+        if (fi.ndim == 2) {
+            Launch2D a{f->data, fi.dtype, fi.h, fi.w, lv, lo, hi, ctx->d_delta2[k], partial, grid, 32};
+            e = launch_2d(a, stream);
+        } else {
+            Launch3D a{f->data, fi.dtype, fi.d, fi.h, fi.w, lv, lo, hi, ctx->d_vtab3[k], partial, grid, crease};
+            e = launch_3d(a, stream);
+        }
+        if (e) return hip_fail(e, "tile kernel launch");
+    }
+    int64_t *outs[4];
+    if (fi.ndim == 2) {
+        outs[0] = c->ec; outs[1] = c->perimeter; outs[2] = c->area; outs[3] = nullptr;
+    } else {
+        outs[0] = c->ec; outs[1] = c->perimeter; outs[2] = c->area; outs[3] = c->volume;
+    }
+    unsigned mask = 0;
+    for (int q = 0; q < nch; ++q)
+        if (outs[q]) mask |= 1u << q;
+    int e = launch_reduce(partial, grid, nch, L, mask, totals, stream);
+    if (e) return hip_fail(e, "reduce kernel launch");
+    e = launch_scan(totals, nch, L, outs, stream);
+    if (e) return hip_fail(e, "scan kernel launch");
+    return ECC_OK;
+}
+
+}  // namespace ecc
+
+extern "C" ecc_status ecc_curves_compute(ecc_context ctx, const ecc_field *field,
+                                         const ecc_curves *curves, void *stream) {
+    clear_error();
+    if (!ctx) return fail(ECC_ERR_INVALID_ARG, "context is NULL");
+    FieldInfo fi;
+    ecc_status s = validate_field(field, curves, &fi, false);
+    if (s != ECC_OK) return s;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    int e = (int)hipSetDevice(ctx->device);
+    if (e) return hip_fail(e, "hipSetDevice");
+    s = acquire_workspace(ctx, stream);
+    if (s != ECC_OK) return s;
+    s = compute_one(ctx, field, fi, curves, stream);
+    ecc_status s2 = release_workspace(ctx, stream);
+    return s != ECC_OK ? s : s2;
+}
+
+extern "C" ecc_status ecc_validate_field(const ecc_field *field, const ecc_curves *curves) {
+    clear_error();
+    FieldInfo fi;
+    return validate_field(field, curves, &fi, false);
+}

@@ -1,0 +1,252 @@
+"""ctypes binding of libecc (include/ecc.h).
+
+Argument marshalling only: every step of the computation runs in the HIP
+library.  torch supplies device memory and streams.  If libecc.so has not been
+built the import of this module still works, but every call raises
+:class:`EccLibraryMissing`; there is no fallback computation.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Iterable, Sequence
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libecc.so")
+
+ECC_OK, ECC_ERR_INVALID_ARG, ECC_ERR_UNSUPPORTED, ECC_ERR_OUT_OF_MEMORY, ECC_ERR_DEVICE, ECC_ERR_BUSY = range(6)
+ECC_U8, ECC_U16, ECC_F32 = 1, 2, 3
+
+# public C entry points (kept in step with include/ecc.h)
+EXPORTS = (
+    "ecc_create", "ecc_destroy", "ecc_last_error", "ecc_status_string",
+    "ecc_curves_compute", "ecc_curves_compute_batch", "ecc_batch_plan_tune",
+    "ecc_vertex_table", "ecc_validate_field",
+    "ecc_server_create", "ecc_server_submit", "ecc_server_poll", "ecc_server_drain",
+    "ecc_server_destroy",
+)
+
+
+class EccLibraryMissing(RuntimeError):
+    pass
+
+
+class EccError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{_status_name(status)}: {message}")
+        self.status = status
+        self.message = message
+
+
+class Field(ctypes.Structure):
+    _fields_ = [("ndim", ctypes.c_int32), ("dtype", ctypes.c_int32), ("shape", ctypes.c_int64 * 3),
+                ("data", ctypes.c_void_p), ("n_levels", ctypes.c_int32),
+                ("connectivity", ctypes.c_int32), ("thresholds", ctypes.c_void_p)]
+
+
+class Curves(ctypes.Structure):
+    _fields_ = [("ec", ctypes.c_void_p), ("perimeter", ctypes.c_void_p), ("area", ctypes.c_void_p),
+                ("volume", ctypes.c_void_p)]
+
+
+class ServerConfig(ctypes.Structure):
+    _fields_ = [("hbm_budget_bytes", ctypes.c_size_t), ("max_slots", ctypes.c_int32),
+                ("max_batch", ctypes.c_int32)]
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Open libecc.so and declare the C signatures."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise EccLibraryMissing(f"{path} is not built; run `python -m paper_2311_11740_amd.build`")
+    lib = ctypes.CDLL(path)
+    vp, i32, i64p = ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64)
+    sig = {
+        "ecc_create": ([ctypes.c_int, ctypes.POINTER(vp)], ctypes.c_int),
+        "ecc_destroy": ([vp], ctypes.c_int),
+        "ecc_last_error": ([], ctypes.c_char_p),
+        "ecc_status_string": ([ctypes.c_int], ctypes.c_char_p),
+        "ecc_curves_compute": ([vp, ctypes.POINTER(Field), ctypes.POINTER(Curves), vp], ctypes.c_int),
+        "ecc_curves_compute_batch": ([vp, i32, ctypes.POINTER(Field), ctypes.POINTER(Curves), vp],
+                                     ctypes.c_int),
+        "ecc_batch_plan_tune": ([vp, i32, ctypes.POINTER(Field), vp], ctypes.c_int),
+        "ecc_vertex_table": ([i32, i32, ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
+        "ecc_validate_field": ([ctypes.POINTER(Field), ctypes.POINTER(Curves)], ctypes.c_int),
+        "ecc_server_create": ([vp, ctypes.POINTER(ServerConfig), ctypes.POINTER(vp)], ctypes.c_int),
+        "ecc_server_submit": ([vp, ctypes.POINTER(Field), ctypes.POINTER(Curves),
+                               ctypes.POINTER(ctypes.c_uint64)], ctypes.c_int),
+        "ecc_server_poll": ([vp, ctypes.c_uint64, ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
+        "ecc_server_drain": ([vp], ctypes.c_int),
+        "ecc_server_destroy": ([vp], ctypes.c_int),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = res
+    _ = i64p
+    _lib = lib
+    return lib
+
+
+def _status_name(s: int) -> str:
+    names = ["ECC_OK", "ECC_ERR_INVALID_ARG", "ECC_ERR_UNSUPPORTED", "ECC_ERR_OUT_OF_MEMORY",
+             "ECC_ERR_DEVICE", "ECC_ERR_BUSY"]
+    return names[s] if 0 <= s < len(names) else f"status {s}"
+
+
+def check(status: int):
+    if status != ECC_OK:
+        msg = load().ecc_last_error().decode(errors="replace")
+        raise EccError(status, msg)
+
+
+def vertex_table(ndim: int, connectivity: int = 0):
+    """The library's per-vertex contribution table as nested lists (host call)."""
+    lib = load()
+    n = 16 if ndim == 2 else 256
+    buf = (ctypes.c_int32 * (n * 4))()
+    check(lib.ecc_vertex_table(ndim, connectivity, buf))
+    return [list(buf[4 * m:4 * m + 4]) for m in range(n)]
+
+
+# ----------------------------------------------------------------------------
+# torch-facing helpers (torch only supplies device memory and streams)
+# ----------------------------------------------------------------------------
+def _torch():
+    import torch
+    return torch
+
+
+def _dtype_code(t) -> int:
+    torch = _torch()
+    if t.dtype == torch.uint8:
+        return ECC_U8
+    if t.dtype == torch.uint16:
+        return ECC_U16
+    if t.dtype == torch.float32:
+        return ECC_F32
+    raise TypeError(f"unsupported field dtype {t.dtype}")
+
+
+def _stream_ptr(stream):
+    torch = _torch()
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    if isinstance(stream, int):
+        return stream or None
+    return stream.cuda_stream or None
+
+
+CHANNELS_2D = ("ec", "perimeter", "area")
+CHANNELS_3D = ("ec", "perimeter", "area", "volume")
+
+
+def make_field(t, n_levels: int, thresholds=None, connectivity: int = 0):
+    """Build the C field descriptor for a contiguous device tensor.  The returned
+    tuple keeps the host threshold buffer alive."""
+    import numpy as np
+    if not t.is_contiguous():
+        raise ValueError("field must be contiguous (C order)")
+    if t.dim() not in (2, 3):
+        raise ValueError("field must be 2D or 3D")
+    f = Field()
+    f.ndim = t.dim()
+    f.dtype = _dtype_code(t)
+    for k in range(3):
+        f.shape[k] = int(t.shape[k]) if k < t.dim() else 0
+    f.data = t.data_ptr()
+    f.n_levels = int(n_levels)
+    f.connectivity = int(connectivity or 0)
+    keep = None
+    if thresholds is not None:
+        keep = np.ascontiguousarray(np.asarray(thresholds, dtype=np.float32))
+        if keep.size != n_levels:
+            raise ValueError("thresholds must have n_levels entries")
+        f.thresholds = keep.ctypes.data
+    else:
+        f.thresholds = None
+    return f, keep
+
+
+def alloc_curves(ndim: int, n_levels: int, device, channels: Iterable[str] | None = None):
+    torch = _torch()
+    allowed = CHANNELS_2D if ndim == 2 else CHANNELS_3D
+    channels = allowed if channels is None else tuple(channels)
+    for c in channels:
+        if c not in allowed:
+            raise ValueError(f"channel {c!r} not available for {ndim}D fields")
+    out = {c: torch.empty(n_levels, dtype=torch.int64, device=device) for c in channels}
+    cv = Curves()
+    for c in ("ec", "perimeter", "area", "volume"):
+        setattr(cv, c, out[c].data_ptr() if c in out else None)
+    return out, cv
+
+
+class Context:
+    """A libecc context on one HIP device."""
+
+    def __init__(self, device: int = 0):
+        self._lib = load()
+        h = ctypes.c_void_p()
+        check(self._lib.ecc_create(int(device), ctypes.byref(h)))
+        self.handle = h
+        self.device = device
+
+    def close(self):
+        if getattr(self, "handle", None):
+            check(self._lib.ecc_destroy(self.handle))
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def compute(self, field, n_levels: int, thresholds=None, connectivity: int = 0,
+                channels: Sequence[str] | None = None, stream=None):
+        """Curves of one device field: dict channel -> int64 device tensor (async on `stream`)."""
+        f, keep = make_field(field, n_levels, thresholds, connectivity)
+        out, cv = alloc_curves(field.dim(), n_levels, field.device, channels)
+        check(self._lib.ecc_curves_compute(self.handle, ctypes.byref(f), ctypes.byref(cv),
+                                           _stream_ptr(stream)))
+        del keep
+        return out
+
+    def compute_batch(self, fields, n_levels, thresholds=None, connectivity: int = 0,
+                      channels: Sequence[str] | None = None, stream=None):
+        """Curves of many device fields in one batched call; list of dicts."""
+        n = len(fields)
+        if not isinstance(n_levels, (list, tuple)):
+            n_levels = [n_levels] * n
+        if thresholds is None or not isinstance(thresholds, (list, tuple)):
+            thresholds = [thresholds] * n
+        farr = (Field * n)()
+        carr = (Curves * n)()
+        keeps, outs = [], []
+        for i, t in enumerate(fields):
+            f, keep = make_field(t, n_levels[i], thresholds[i], connectivity)
+            o, cv = alloc_curves(t.dim(), n_levels[i], t.device, channels)
+            farr[i] = f
+            carr[i] = cv
+            keeps.append(keep)
+            outs.append(o)
+        check(self._lib.ecc_curves_compute_batch(self.handle, n, farr, carr, _stream_ptr(stream)))
+        return outs
+
+    def tune_batch(self, fields, n_levels, thresholds=None, connectivity: int = 0, stream=None):
+        n = len(fields)
+        if not isinstance(n_levels, (list, tuple)):
+            n_levels = [n_levels] * n
+        farr = (Field * n)()
+        keeps = []
+        for i, t in enumerate(fields):
+            f, keep = make_field(t, n_levels[i], thresholds, connectivity)
+            farr[i] = f
+            keeps.append(keep)
+        check(self._lib.ecc_batch_plan_tune(self.handle, n, farr, _stream_ptr(stream)))

@@ -1,0 +1,143 @@
+"""Host-side checks of libecc: exports, contribution tables, validation.
+
+No compute call is made here (no GPU in this environment); the GPU parity
+tests live in test_gpu_*.py.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+from paper_2311_11740_amd import ecc
+from tests import paper_tables as PT
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    return ecc.load()
+
+
+def _declared_symbols():
+    text = open(os.path.join(ROOT, "include", "ecc.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(ecc_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = _declared_symbols()
+    assert len(names) >= 10
+    for n in names:
+        assert hasattr(lib, n), f"libecc.so does not export {n}"
+    assert set(names) == set(ecc.EXPORTS)
+
+
+def test_library_is_gfx950_hip_code():
+    so = os.path.join(ROOT, "paper_2311_11740_amd", "libecc.so")
+    data = open(so, "rb").read()
+    assert b"gfx950" in data
+
+
+def test_vertex_table_2d_matches_table1(lib):
+    t1 = PT.table1()
+    for conn, key in ((8, "ec8"), (4, "ec4")):
+        got = ecc.vertex_table(2, conn)
+        for m in range(16):
+            assert Fraction(got[m][0], 4) == t1[m][key], (conn, m)
+            assert Fraction(got[m][1], 2) == t1[m]["perimeter"]
+            assert Fraction(got[m][2], 4) == t1[m]["area"]
+
+
+def test_vertex_table_3d_matches_table2(lib):
+    t2 = PT.table2()
+    got = ecc.vertex_table(3, 26)
+    for m in range(256):
+        assert Fraction(got[m][0], 8) == t2[m]["ec26"], m
+        assert Fraction(got[m][1], 2) == t2[m]["perimeter"], m
+        assert Fraction(got[m][2], 4) == t2[m]["area"], m
+        assert Fraction(got[m][3], 8) == t2[m]["volume"], m
+
+
+def test_vertex_table_3d_6c_is_face_adjacency_share(lib):
+    """6-C (not in the paper): per-vertex share of the face-adjacency complex must
+    sum to the oracle's 6-connected EC on random volumes."""
+    from oracle import ec_oracle as O1
+    got = ecc.vertex_table(3, 6)
+    tab = {m: {"e": Fraction(got[m][0], 8)} for m in range(256)}
+    rng = np.random.default_rng(3)
+    for _ in range(20):
+        b = rng.random(tuple(rng.integers(1, 7, size=3))) < rng.uniform(0.2, 0.9)
+        vm = PT.vertex_masks_3d(b)
+        assert PT.table_sum(vm, tab, "e") == O1.ec_3d(b, 6)
+
+
+def _field(ndim=2, dtype=ecc.ECC_U8, shape=(4, 5, 0), L=4, thr=None, conn=0, data=1):
+    f = ecc.Field()
+    f.ndim, f.dtype = ndim, dtype
+    for k in range(3):
+        f.shape[k] = shape[k]
+    f.data = data
+    f.n_levels = L
+    f.connectivity = conn
+    f.thresholds = thr
+    return f
+
+
+def _curves(ec=1, per=None, area=None, vol=None):
+    c = ecc.Curves()
+    c.ec, c.perimeter, c.area, c.volume = ec, per, area, vol
+    return c
+
+
+@pytest.mark.parametrize("case,status", [
+    (dict(ndim=4), ecc.ECC_ERR_INVALID_ARG),
+    (dict(dtype=9), ecc.ECC_ERR_INVALID_ARG),
+    (dict(shape=(0, 5, 0)), ecc.ECC_ERR_INVALID_ARG),
+    (dict(L=0), ecc.ECC_ERR_INVALID_ARG),
+    (dict(L=70000), ecc.ECC_ERR_UNSUPPORTED),
+    (dict(conn=6), ecc.ECC_ERR_INVALID_ARG),
+    (dict(ndim=3, shape=(2, 2, 2), conn=8), ecc.ECC_ERR_INVALID_ARG),
+    (dict(dtype=ecc.ECC_F32), ecc.ECC_ERR_INVALID_ARG),  # float needs thresholds
+    (dict(data=None), ecc.ECC_ERR_INVALID_ARG),
+])
+def test_validation_errors(lib, case, status):
+    f = _field(**case)
+    assert lib.ecc_validate_field(ctypes.byref(f), ctypes.byref(_curves())) == status
+    assert lib.ecc_last_error().decode()
+
+
+def test_validation_thresholds(lib):
+    bad = (ctypes.c_float * 3)(0.0, 2.0, 1.0)
+    f = _field(dtype=ecc.ECC_F32, L=3, thr=ctypes.cast(bad, ctypes.c_void_p))
+    assert lib.ecc_validate_field(ctypes.byref(f), ctypes.byref(_curves())) == ecc.ECC_ERR_INVALID_ARG
+    nan = (ctypes.c_float * 3)(0.0, float("nan"), 1.0)
+    f = _field(dtype=ecc.ECC_F32, L=3, thr=ctypes.cast(nan, ctypes.c_void_p))
+    assert lib.ecc_validate_field(ctypes.byref(f), ctypes.byref(_curves())) == ecc.ECC_ERR_INVALID_ARG
+    ok = (ctypes.c_float * 3)(0.0, 0.0, 1.0)  # ties allowed
+    f = _field(dtype=ecc.ECC_F32, L=3, thr=ctypes.cast(ok, ctypes.c_void_p))
+    assert lib.ecc_validate_field(ctypes.byref(f), ctypes.byref(_curves())) == ecc.ECC_OK
+
+
+def test_validation_channels(lib):
+    f = _field()
+    assert lib.ecc_validate_field(ctypes.byref(f), ctypes.byref(_curves(ec=None))) == ecc.ECC_ERR_INVALID_ARG
+    assert lib.ecc_validate_field(ctypes.byref(f), ctypes.byref(_curves(vol=1))) == ecc.ECC_ERR_INVALID_ARG
+    f3 = _field(ndim=3, shape=(2, 3, 4))
+    assert lib.ecc_validate_field(ctypes.byref(f3), ctypes.byref(_curves(vol=1))) == ecc.ECC_OK
+    assert lib.ecc_validate_field(None, ctypes.byref(_curves())) == ecc.ECC_ERR_INVALID_ARG
+
+
+def test_compute_without_context_is_an_error(lib):
+    f = _field()
+    assert lib.ecc_curves_compute(None, ctypes.byref(f), ctypes.byref(_curves()), None) == ecc.ECC_ERR_INVALID_ARG
+
+
+def test_status_strings(lib):
+    for s in range(6):
+        assert lib.ecc_status_string(s).decode().startswith("ECC_")

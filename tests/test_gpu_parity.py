@@ -1,0 +1,193 @@
+"""GPU parity: libecc curves == the oracle's curves, bit for bit, through the C ABI.
+
+Every case is printed (and flushed) before it runs so that a failing GPU step
+names its case.  Sizes span several tiles (2D tiles are 32 x 256 cells, 3D
+tiles 16 x 4 x 64) with ragged tails, the degenerate shapes (1 x 1, 1 x N,
+N x 1), every level mode (identity integer levels, integer levels through
+thresholds, affine float thresholds, irregular float thresholds with ties),
+NaN and never-active values, constant fields, one level, and level counts above
+the per-pass window (several passes).
+"""
+from __future__ import annotations
+
+import os
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+NT = min(16, os.cpu_count() or 1)
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2311_11740_amd import ecc
+    c = ecc.Context(0)
+    yield c
+    c.close()
+
+
+def run_and_compare(ctx, arr, L, thr=None, conn=0, channels=None, tag=""):
+    import torch
+    import oracle
+    print(f"[case] {tag} shape={arr.shape} dtype={arr.dtype} L={L} conn={conn} "
+          f"thr={'none' if thr is None else 'yes'} channels={channels}", flush=True)
+    dev = torch.from_numpy(np.ascontiguousarray(arr)).cuda()
+    got = ctx.compute(dev, L, thresholds=thr, connectivity=conn, channels=channels)
+    torch.cuda.synchronize()
+    nd = arr.ndim
+    if conn == 0:
+        conn = 8 if nd == 2 else 26
+    want_ch = tuple(got.keys())
+    ref = oracle.o2_curves(arr, L, thresholds=thr, connectivity=conn, channels=want_ch, n_threads=NT)
+    for k in want_ch:
+        g = got[k].cpu().numpy()
+        r = ref[k]
+        if not np.array_equal(g, r):
+            bad = np.nonzero(g != r)[0]
+            raise AssertionError(f"{tag} channel {k}: {bad.size} levels differ, first at {bad[0]}: "
+                                 f"gpu {g[bad[0]]} oracle {r[bad[0]]}")
+    return got
+
+
+SHAPES_2D = [(1, 1), (1, 300), (300, 1), (37, 513), (64, 256), (257, 1025), (1021, 769)]
+
+
+@pytest.mark.parametrize("shape", SHAPES_2D)
+@pytest.mark.parametrize("conn", [8, 4])
+def test_2d_u8_identity(ctx, shape, conn):
+    rng = np.random.default_rng(hash((shape, conn)) % 2**32)
+    a = rng.integers(0, 256, size=shape).astype(np.uint8)
+    run_and_compare(ctx, a, 256, conn=conn, tag="2d_u8")
+
+
+@pytest.mark.parametrize("shape", [(45, 300), (513, 257)])
+def test_2d_u8_smooth_and_fewer_levels(ctx, shape):
+    from paper_2311_11740_amd import synth
+    a = synth.quantise(synth.grf(shape, 3.0, 11), 256)
+    run_and_compare(ctx, a, 256, tag="2d_u8_grf")
+    run_and_compare(ctx, a, 100, tag="2d_u8_L100_never")  # values >= 100 never enter
+    run_and_compare(ctx, a, 1, tag="2d_u8_L1")
+
+
+def test_2d_u16_identity_and_multipass(ctx):
+    rng = np.random.default_rng(5)
+    a = rng.integers(0, 12000, size=(70, 600)).astype(np.uint16)
+    run_and_compare(ctx, a, 4096, tag="2d_u16_L4096")
+    run_and_compare(ctx, a, 10000, tag="2d_u16_L10000_3pass")
+    run_and_compare(ctx, a, 10000, conn=4, tag="2d_u16_L10000_4c")
+
+
+def test_2d_f32_affine_thresholds(ctx):
+    from paper_2311_11740_amd import synth
+    z = synth.grf((300, 700), 8.0, 21)
+    thr = synth.linspace_thresholds(-4.0, 4.0, 1024)
+    idx = np.arange(0, z.size, 97)
+    z.ravel()[idx] = thr[np.random.default_rng(1).integers(0, 1024, size=idx.size)]  # on thresholds
+    z.ravel()[5] = np.nan
+    z.ravel()[6] = np.inf
+    z.ravel()[7] = -np.inf
+    z.ravel()[8] = -0.0
+    run_and_compare(ctx, z, 1024, thr=thr, tag="2d_f32_affine")
+    run_and_compare(ctx, z, 1024, thr=thr, conn=4, tag="2d_f32_affine_4c")
+
+
+def test_2d_f32_irregular_thresholds(ctx):
+    rng = np.random.default_rng(8)
+    z = rng.normal(size=(129, 257)).astype(np.float32)
+    thr = np.sort(rng.normal(size=300)).astype(np.float32)
+    thr[10:20] = thr[10]  # repeated thresholds
+    z.ravel()[::50] = thr[rng.integers(0, 300, size=z.ravel()[::50].size)]
+    z.ravel()[3] = np.nan
+    run_and_compare(ctx, z, 300, thr=thr, tag="2d_f32_irregular")
+
+
+def test_2d_integer_with_thresholds(ctx):
+    rng = np.random.default_rng(9)
+    a = rng.integers(0, 256, size=(100, 300)).astype(np.uint8)
+    thr = np.array([3.5, 10, 10, 99.9, 100, 200, 254.5], np.float32)
+    run_and_compare(ctx, a, len(thr), thr=thr, tag="2d_u8_thr")
+    b = rng.integers(0, 65535, size=(90, 310)).astype(np.uint16)
+    thr2 = np.linspace(0, 70000, 500).astype(np.float32)
+    run_and_compare(ctx, b, 500, thr=thr2, tag="2d_u16_thr")
+
+
+def test_2d_constant_and_never(ctx):
+    run_and_compare(ctx, np.full((70, 530), 7, np.uint8), 256, tag="2d_const")
+    run_and_compare(ctx, np.full((70, 530), 250, np.uint8), 100, tag="2d_all_never")
+    run_and_compare(ctx, np.full((33, 33), np.nan, np.float32), 4,
+                    thr=np.arange(4, dtype=np.float32), tag="2d_all_nan")
+
+
+def test_2d_channel_subsets(ctx):
+    rng = np.random.default_rng(10)
+    a = rng.integers(0, 50, size=(77, 300)).astype(np.uint8)
+    for ch in (("ec",), ("perimeter",), ("area",), ("ec", "area")):
+        run_and_compare(ctx, a, 50, channels=ch, tag=f"2d_ch_{'_'.join(ch)}")
+
+
+SHAPES_3D = [(1, 1, 1), (1, 1, 70), (70, 1, 1), (3, 5, 7), (17, 9, 130), (40, 33, 65), (1, 64, 64)]
+
+
+@pytest.mark.parametrize("shape", SHAPES_3D)
+@pytest.mark.parametrize("conn", [26, 6])
+def test_3d_u8_all_channels(ctx, shape, conn):
+    rng = np.random.default_rng(hash((shape, conn, 3)) % 2**32)
+    a = rng.integers(0, 40, size=shape).astype(np.uint8)
+    run_and_compare(ctx, a, 36, conn=conn, tag="3d_u8")
+
+
+def test_3d_u16_grf(ctx):
+    from paper_2311_11740_amd import synth
+    a = synth.quantise(synth.grf((48, 40, 136), 3.0, 31), 4096)
+    run_and_compare(ctx, a, 4096, tag="3d_u16_grf", channels=("ec", "area", "volume"))
+    run_and_compare(ctx, a, 4096, tag="3d_u16_grf_crease")
+    run_and_compare(ctx, a, 3000, conn=6, tag="3d_u16_grf_6c_never")
+    run_and_compare(ctx, a, 5000, tag="3d_u16_grf_2pass")
+
+
+def test_3d_f32_thresholds(ctx):
+    from paper_2311_11740_amd import synth
+    z = synth.grf((20, 30, 70), 2.5, 41)
+    z.ravel()[11] = np.nan
+    thr = synth.linspace_thresholds(-3, 3, 200)
+    run_and_compare(ctx, z, 200, thr=thr, tag="3d_f32_affine")
+    thr2 = np.sort(np.random.default_rng(2).normal(size=77)).astype(np.float32)
+    run_and_compare(ctx, z, 77, thr=thr2, conn=6, tag="3d_f32_irregular_6c")
+
+
+def test_3d_constant(ctx):
+    run_and_compare(ctx, np.full((20, 6, 70), 3, np.uint16), 10, tag="3d_const")
+
+
+def test_repeat_is_deterministic(ctx):
+    import torch
+    rng = np.random.default_rng(12)
+    a = torch.from_numpy(rng.integers(0, 256, size=(500, 700)).astype(np.uint8)).cuda()
+    r1 = ctx.compute(a, 256)
+    r2 = ctx.compute(a, 256)
+    torch.cuda.synchronize()
+    for k in r1:
+        assert torch.equal(r1[k], r2[k])
+
+
+def test_async_on_side_stream(ctx):
+    """Work queued on a non-default stream is ordered after the previous call."""
+    import torch
+    import oracle
+    rng = np.random.default_rng(13)
+    a = rng.integers(0, 256, size=(300, 900)).astype(np.uint8)
+    b = rng.integers(0, 256, size=(333, 444)).astype(np.uint8)
+    da, db = torch.from_numpy(a).cuda(), torch.from_numpy(b).cuda()
+    s = torch.cuda.Stream()
+    ra = ctx.compute(da, 256)
+    with torch.cuda.stream(s):
+        rb = ctx.compute(db, 256, stream=s)
+    torch.cuda.synchronize()
+    oa, ob = oracle.o2_curves(a, 256), oracle.o2_curves(b, 256)
+    for k in ra:
+        assert np.array_equal(ra[k].cpu().numpy(), oa[k])
+        assert np.array_equal(rb[k].cpu().numpy(), ob[k])
