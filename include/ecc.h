@@ -161,6 +161,18 @@ ecc_status ecc_batch_plan_tune(ecc_context ctx, int32_t n, const ecc_field *fiel
  */
 ecc_status ecc_vertex_table(int32_t ndim, int32_t connectivity, int32_t *out);
 
+/*
+ * Kernel timing for measurement.  While enabled, the context records a pair of
+ * HIP events around every launch of its field-reading pass kernel (the tile
+ * kernel that reads the field from HBM; not the merge and scan kernels that
+ * follow it) on the stream the launch goes to.  ecc_profile_read waits for the
+ * recorded events, returns the summed elapsed milliseconds and the number of
+ * launches, and forgets them when `reset` is non-zero.  Enabling it adds two
+ * event records per launch and nothing else.
+ */
+ecc_status ecc_profile_enable(ecc_context ctx, int32_t on);
+ecc_status ecc_profile_read(ecc_context ctx, double *total_ms, int64_t *launches, int32_t reset);
+
 /* ---------------------------------------------------------------------------
  * Serving: a request loop with continuous batching.
  * Requests are admitted while their device memory fits the budget and a slot is

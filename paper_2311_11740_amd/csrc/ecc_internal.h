@@ -47,8 +47,14 @@ struct LevelArgs {
     int32_t mode;
     const float *thr;     // device, L floats (LM_AFFINE / LM_SEARCH)
     const uint16_t *lut;  // device, 256 or 65536 entries (LM_LUT)
-    float t0, inv_step;   // LM_AFFINE
+    float t0, inv_step;   // LM_AFFINE: u = (x - t0) * inv_step estimates the level
+    float eps;            // LM_AFFINE: fractional parts of u within eps of an integer
+                          // are resolved against the thresholds; elsewhere floor(u)+1
+                          // is exact (the host bounds the grid deviation and rounding)
 };
+
+// thresholds kept in LDS by the kernels when L is at most this
+constexpr int kThrLds = 4096;
 
 // ---- kernel launch descriptors ---------------------------------------------------
 struct Launch2D {
@@ -60,8 +66,12 @@ struct Launch2D {
     const uint64_t *delta_lut;  // device, 256 packed per-cell deltas
     int32_t *partial;           // device, [grid][3][L]
     int grid;
-    int tile_rows;
+    int64_t row_lo, row_hi;     // rows whose cells this launch emits (halo rows are read)
+    bool accumulate;            // add to the partials instead of overwriting them
 };
+
+// cells per lane along the contiguous axis (16 bytes of input per lane)
+inline int vec_2d(int dtype) { return dtype == 1 ? 16 : (dtype == 2 ? 8 : 4); }
 
 struct Launch3D {
     const void *data;
@@ -78,15 +88,17 @@ struct Launch3D {
 // device-side launchers (ecc_kernels.hip); return a hipError_t as int
 int launch_2d(const Launch2D &a, void *stream);
 int launch_3d(const Launch3D &a, void *stream);
-int launch_reduce(const int32_t *partial, int grid, int nch, int L, unsigned ch_mask,
-                  int64_t *totals, void *stream);
-int launch_scan(const int64_t *totals, int nch, int L, int64_t *const out[4], void *stream);
+// partials [grid][nch][L] int32 -> group sums [groups][nch][L] int64
+int launch_reduce(const int32_t *partial, int grid, int nch, int L, unsigned ch_mask, int groups,
+                  int64_t *sums, void *stream);
+// sums over groups and running sum over levels into the caller's curves
+int launch_scan(const int64_t *sums, int groups, int nch, int L, int64_t *const out[4], void *stream);
 int launch_level_lut(const float *thr, int L, int n_values, uint16_t *lut, void *stream);
 
 // tile geometry used by the single-field kernels
-constexpr int kTile2DCols = 256;
+constexpr int kWavesPerWG = 4;
 constexpr int kTile3DX = 64, kTile3DY = 4, kTile3DZ = 16;
-size_t lds_bytes_2d(int window, int tile_rows);
+size_t lds_bytes_2d(int window, int L);
 size_t lds_bytes_3d(int window, bool want_crease);
 
 }  // namespace ecc

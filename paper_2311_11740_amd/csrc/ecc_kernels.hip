@@ -32,50 +32,157 @@ namespace ecc {
 // ---------------------------------------------------------------------------
 // level index: first l with value <= t_l (Eq. (2)); L = never active
 // ---------------------------------------------------------------------------
+template <int LM>
+__device__ __forceinline__ uint32_t level_of_float(float x, const LevelArgs &a, const float *thr) {
+    const int L = a.L;
+    if (!(x == x)) return (uint32_t)L;  // NaN never enters
+    int g;
+    if constexpr (LM == LM_AFFINE) {
+        const float u = (x - a.t0) * a.inv_step;
+        if (u < -1.0f) return 0u;
+        if (u >= (float)L + 1.0f) return (uint32_t)L;
+        const float fu = floorf(u);
+        const float fr = u - fu;
+        g = (int)fu + 1;
+        if (g > L) g = L;
+        if (fr >= a.eps && fr <= 1.0f - a.eps) return (uint32_t)g;
+        // close to a threshold: settle against the caller's values so that
+        // t[g-1] < x <= t[g] (with t[-1] = -inf, t[L] = +inf)
+        if (g < 0) g = 0;
+        while (g > 0 && x <= thr[g - 1]) --g;
+        while (g < L && !(x <= thr[g])) ++g;
+    } else {
+        int lo = 0, hi = L;
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (x <= thr[mid])
+                hi = mid;
+            else
+                lo = mid + 1;
+        }
+        g = lo;
+    }
+    return (uint32_t)g;
+}
+
 template <typename T, int LM>
-__device__ __forceinline__ uint32_t level_of(T v, const LevelArgs &a) {
+__device__ __forceinline__ uint32_t level_of(T v, const LevelArgs &a, const float *thr) {
     if constexpr (LM == LM_IDENTITY) {
         const uint32_t u = (uint32_t)v;
         return u < (uint32_t)a.L ? u : (uint32_t)a.L;
     } else if constexpr (LM == LM_LUT) {
         return a.lut[(uint32_t)v];
     } else {
-        const float x = (float)v;
-        const int L = a.L;
-        if (!(x == x)) return (uint32_t)L;  // NaN never enters
-        int g;
-        if constexpr (LM == LM_AFFINE) {
-            float gf = floorf((x - a.t0) * a.inv_step) + 1.0f;
-            gf = fminf(fmaxf(gf, 0.0f), (float)L);
-            g = (int)gf;
-            // exact correction against the caller's thresholds: afterwards
-            // t[g-1] < x <= t[g] (with t[-1] = -inf, t[L] = +inf)
-            while (g > 0 && x <= a.thr[g - 1]) --g;
-            while (g < L && !(x <= a.thr[g])) ++g;
-        } else {
-            int lo = 0, hi = L;
-            while (lo < hi) {
-                const int mid = (lo + hi) >> 1;
-                if (x <= a.thr[mid])
-                    hi = mid;
-                else
-                    lo = mid + 1;
-            }
-            g = lo;
-        }
-        return (uint32_t)g;
+        return level_of_float<LM>((float)v, a, thr);
     }
 }
 
 __device__ __forceinline__ int xcd_order(int bid, int G) {
     // workgroups are dispatched round-robin over the 8 XCDs; renumber them so
-    // that each XCD holds a contiguous block of workgroup ids
+    // that each XCD holds a contiguous block of workgroup ids (neighbouring
+    // rows and tiles then share an L2)
     return (G & 7) == 0 ? (bid & 7) * (G >> 3) + (bid >> 3) : bid;
 }
 
 // ---------------------------------------------------------------------------
-// 2D
+// 2D: row streaming
 // ---------------------------------------------------------------------------
+// One wave owns a strip of 64*VEC columns (VEC cells per lane, 16 bytes of
+// input per lane and row) and walks down a run of rows, keeping the level
+// indices of three rows (above, current, below) in registers.  The cells left
+// and right of a lane's run come from the neighbouring lanes (ds_bpermute);
+// lanes 0 and 63 read the strip's halo columns themselves.  Raw rows are
+// fetched PF rows ahead into a register ring so that several 1 KiB row loads
+// per wave are in flight.
+template <typename T>
+struct Elem;
+template <>
+struct Elem<uint8_t> {
+    static constexpr int VEC = 16;
+    __device__ static uint32_t get(const uint32_t (&w)[4], int i) { return (w[i >> 2] >> (8 * (i & 3))) & 0xFFu; }
+};
+template <>
+struct Elem<uint16_t> {
+    static constexpr int VEC = 8;
+    __device__ static uint32_t get(const uint32_t (&w)[4], int i) { return (w[i >> 1] >> (16 * (i & 1))) & 0xFFFFu; }
+};
+template <>
+struct Elem<float> {
+    static constexpr int VEC = 4;
+    __device__ static uint32_t get(const uint32_t (&w)[4], int i) { return w[i]; }
+};
+
+template <typename T>
+__device__ __forceinline__ T as_value(uint32_t bits) {
+    if constexpr (sizeof(T) == 4)
+        return __uint_as_float(bits);
+    else
+        return (T)bits;
+}
+
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+struct RawRow {
+    uint32_t w[4];  // 16 bytes: VEC raw elements of this lane
+    uint32_t halo;  // lane 0: element left of the strip; lane 63: right of it
+    bool valid;     // row inside the field
+};
+
+template <typename T, bool ALIGNED>
+__device__ __forceinline__ void fetch_row(const T *__restrict__ data, int64_t r, int64_t h, int64_t w,
+                                          int64_t xs, int64_t x0, int lane, RawRow &raw) {
+    constexpr int VEC = Elem<T>::VEC;
+    raw.valid = r >= 0 && r < h;
+    if (!raw.valid) return;
+    const T *row = data + r * w;
+    if (ALIGNED && x0 + VEC <= w) {
+        const u32x4 q = __builtin_nontemporal_load(reinterpret_cast<const u32x4 *>(row + x0));
+        raw.w[0] = q.x; raw.w[1] = q.y; raw.w[2] = q.z; raw.w[3] = q.w;
+    } else {
+        raw.w[0] = raw.w[1] = raw.w[2] = raw.w[3] = 0;
+#pragma unroll
+        for (int i = 0; i < VEC; ++i) {
+            if (x0 + i < w) {
+                uint32_t bits;
+                if constexpr (sizeof(T) == 4)
+                    bits = __float_as_uint(row[x0 + i]);
+                else
+                    bits = (uint32_t)row[x0 + i];
+                constexpr int per = 4 / sizeof(T);
+                raw.w[i / per] |= bits << (8 * sizeof(T) * (i % per));
+            }
+        }
+    }
+    raw.halo = 0;
+    if (lane == 0 && xs > 0) {
+        if constexpr (sizeof(T) == 4) raw.halo = __float_as_uint(row[xs - 1]);
+        else raw.halo = (uint32_t)row[xs - 1];
+    }
+    if (lane == 63 && xs + 64 * VEC < w) {
+        if constexpr (sizeof(T) == 4) raw.halo = __float_as_uint(row[xs + 64 * VEC]);
+        else raw.halo = (uint32_t)row[xs + 64 * VEC];
+    }
+}
+
+// level indices of a fetched row: lam[1..VEC] own cells, lam[0] / lam[VEC+1]
+// the cells left of the first and right of the last
+template <typename T, int LM>
+__device__ __forceinline__ void convert_row(const RawRow &raw, int64_t w, int64_t xs, int64_t x0, int lane,
+                                            const LevelArgs &lv, const float *thr,
+                                            uint32_t (&lam)[Elem<T>::VEC + 2]) {
+    constexpr int VEC = Elem<T>::VEC;
+    const uint32_t L = (uint32_t)lv.L;
+#pragma unroll
+    for (int i = 0; i < VEC; ++i)
+        lam[i + 1] = (raw.valid && x0 + i < w) ? level_of<T, LM>(as_value<T>(Elem<T>::get(raw.w, i)), lv, thr) : L;
+    uint32_t left = __shfl_up(lam[VEC], 1);
+    uint32_t right = __shfl_down(lam[1], 1);
+    if (lane == 0) left = (raw.valid && xs > 0) ? level_of<T, LM>(as_value<T>(raw.halo), lv, thr) : L;
+    if (lane == 63) right = (raw.valid && xs + 64 * VEC < w) ? level_of<T, LM>(as_value<T>(raw.halo), lv, thr) : L;
+    lam[0] = left;
+    lam[VEC + 1] = right;
+}
+
 __device__ __forceinline__ void drain_2d(uint64_t *hist, int W, int lo, int L, int32_t *slot,
                                          bool first) {
     for (int b = threadIdx.x; b < W; b += blockDim.x) {
@@ -98,73 +205,90 @@ __device__ __forceinline__ void drain_2d(uint64_t *hist, int W, int lo, int L, i
     }
 }
 
-template <typename T, int LM, int TH>
+template <typename T, int LM, bool ALIGNED, int PF>
 __global__ void __launch_bounds__(256)
-    ecc2d_tile(const T *__restrict__ data, int64_t h, int64_t w, LevelArgs lv, int32_t lo,
-               int32_t hi, const uint64_t *__restrict__ delta_lut, int32_t *__restrict__ partial,
-               int64_t tiles_x, int64_t n_tiles, int flush_tiles) {
-    constexpr int TW = kTile2DCols;
-    extern __shared__ uint64_t hist[];
+    ecc2d_stream(const T *__restrict__ data, int64_t h, int64_t w, LevelArgs lv, int32_t lo,
+                 int32_t hi, const uint64_t *__restrict__ delta_lut, int32_t *__restrict__ partial,
+                 int64_t row_lo, int64_t row_hi, int64_t n_segs, int64_t seg_rows, int64_t n_items,
+                 int accumulate) {
+    constexpr int VEC = Elem<T>::VEC;
+    constexpr int CW = 64 * VEC;
+    extern __shared__ uint64_t smem[];
     __shared__ uint64_t dl[256];
-    __shared__ uint16_t lam[TH + 2][TW + 2];
 
-    const int t = threadIdx.x;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int W = hi - lo;
     const int L = lv.L;
-    const int G = gridDim.x;
-    const int wg = xcd_order(blockIdx.x, G);
-    const int64_t t_beg = n_tiles * wg / G, t_end = n_tiles * (wg + 1) / G;
-
-    dl[t] = delta_lut[t];
-    for (int b = t; b < W; b += 256) hist[b] = 0;
-    int32_t *slot = partial + (int64_t)wg * 3 * L;
-    bool first = true;
-    int since = 0;
-    __syncthreads();
-
-    for (int64_t tile = t_beg; tile < t_end; ++tile) {
-        const int64_t r0 = (tile / tiles_x) * TH, c0 = (tile % tiles_x) * TW;
-        // stage the levels of rows r0-1 .. r0+TH and columns c0-1 .. c0+TW
-        for (int rr = 0; rr < TH + 2; ++rr) {
-            const int64_t r = r0 - 1 + rr;
-            const bool row_in = r >= 0 && r < h;
-            for (int cc = t; cc < TW + 2; cc += 256) {
-                const int64_t c = c0 - 1 + cc;
-                uint32_t l = (uint32_t)L;
-                if (row_in && c >= 0 && c < w) l = level_of<T, LM>(data[r * w + c], lv);
-                lam[rr][cc] = (uint16_t)l;
-            }
-        }
-        __syncthreads();
-        if (c0 + t < w) {
-            uint32_t a0 = lam[0][t], a1 = lam[0][t + 1], a2 = lam[0][t + 2];
-            uint32_t b0 = lam[1][t], b1 = lam[1][t + 1], b2 = lam[1][t + 2];
-            const int rows = (int)(h - r0 < TH ? h - r0 : TH);
-            for (int r = 0; r < rows; ++r) {
-                const uint32_t e0 = lam[r + 2][t], e1 = lam[r + 2][t + 1], e2 = lam[r + 2][t + 2];
-                const uint32_t p = b1;
-                if (p - (uint32_t)lo < (uint32_t)W) {
-                    // neighbours that come earlier in memory order precede p on a
-                    // tie, later ones do not
-                    const uint32_t pat = (uint32_t)(a0 <= p) | (uint32_t)(a1 <= p) << 1 |
-                                         (uint32_t)(a2 <= p) << 2 | (uint32_t)(b0 <= p) << 3 |
-                                         (uint32_t)(b2 < p) << 4 | (uint32_t)(e0 < p) << 5 |
-                                         (uint32_t)(e1 < p) << 6 | (uint32_t)(e2 < p) << 7;
-                    atomicAdd((unsigned long long *)&hist[p - lo], (unsigned long long)dl[pat]);
-                }
-                a0 = b0; a1 = b1; a2 = b2;
-                b0 = e0; b1 = e1; b2 = e2;
-            }
-        }
-        __syncthreads();
-        if (++since >= flush_tiles) {
-            drain_2d(hist, W, lo, L, slot, first);
-            first = false;
-            since = 0;
-            __syncthreads();
+    uint64_t *hist = smem;
+    const float *thr = lv.thr;
+    if constexpr (LM == LM_AFFINE || LM == LM_SEARCH) {
+        if (L <= kThrLds) {
+            float *t = reinterpret_cast<float *>(smem + W);
+            for (int i = tid; i < L; i += 256) t[i] = lv.thr[i];
+            thr = t;
         }
     }
-    drain_2d(hist, W, lo, L, slot, first);
+    dl[tid] = delta_lut[tid];
+    for (int b = tid; b < W; b += 256) hist[b] = 0;
+    __syncthreads();
+
+    const int G = gridDim.x;
+    const int wg = xcd_order(blockIdx.x, G);
+    const int64_t gw = (int64_t)wg * kWavesPerWG + wave, NW = (int64_t)G * kWavesPerWG;
+    const int64_t i_beg = n_items * gw / NW, i_end = n_items * (gw + 1) / NW;
+
+    for (int64_t item = i_beg; item < i_end; ++item) {
+        const int64_t strip = item / n_segs, seg = item % n_segs;
+        const int64_t ra = row_lo + seg * seg_rows;
+        const int64_t rb = ra + seg_rows < row_hi ? ra + seg_rows : row_hi;
+        const int64_t xs = strip * CW, x0 = xs + (int64_t)lane * VEC;
+
+        uint32_t up[VEC + 2], mid[VEC + 2], dn[VEC + 2];
+        {
+            RawRow r0, r1;
+            fetch_row<T, ALIGNED>(data, ra - 1, h, w, xs, x0, lane, r0);
+            fetch_row<T, ALIGNED>(data, ra, h, w, xs, x0, lane, r1);
+            convert_row<T, LM>(r0, w, xs, x0, lane, lv, thr, up);
+            convert_row<T, LM>(r1, w, xs, x0, lane, lv, thr, mid);
+        }
+        RawRow ring[PF];
+#pragma unroll
+        for (int k = 0; k < PF; ++k) {
+            ring[k].valid = false;
+            if (ra + 1 + k <= rb) fetch_row<T, ALIGNED>(data, ra + 1 + k, h, w, xs, x0, lane, ring[k]);
+        }
+        for (int64_t r0 = ra; r0 < rb; r0 += PF) {
+#pragma unroll
+            for (int k = 0; k < PF; ++k) {
+                const int64_t r = r0 + k;  // current row; ring[k] holds row r + 1
+                if (r < rb) {
+                    convert_row<T, LM>(ring[k], w, xs, x0, lane, lv, thr, dn);
+                    if (r + 1 + PF <= rb)
+                        fetch_row<T, ALIGNED>(data, r + 1 + PF, h, w, xs, x0, lane, ring[k]);
+#pragma unroll
+                    for (int j = 1; j <= VEC; ++j) {
+                        const uint32_t p = mid[j];
+                        if (p - (uint32_t)lo < (uint32_t)W) {
+                            // a neighbour earlier in memory order precedes p on
+                            // a tie, a later one does not
+                            const uint32_t pat = (uint32_t)(up[j - 1] <= p) | (uint32_t)(up[j] <= p) << 1 |
+                                                 (uint32_t)(up[j + 1] <= p) << 2 | (uint32_t)(mid[j - 1] <= p) << 3 |
+                                                 (uint32_t)(mid[j + 1] < p) << 4 | (uint32_t)(dn[j - 1] < p) << 5 |
+                                                 (uint32_t)(dn[j] < p) << 6 | (uint32_t)(dn[j + 1] < p) << 7;
+                            atomicAdd((unsigned long long *)&hist[p - lo], (unsigned long long)dl[pat]);
+                        }
+                    }
+#pragma unroll
+                    for (int j = 0; j < VEC + 2; ++j) {
+                        up[j] = mid[j];
+                        mid[j] = dn[j];
+                    }
+                }
+            }
+        }
+    }
+    __syncthreads();
+    drain_2d(hist, W, lo, L, partial + (int64_t)wg * 3 * L, accumulate == 0);
 }
 
 // ---------------------------------------------------------------------------
@@ -241,7 +365,7 @@ __global__ void __launch_bounds__(256)
             const int64_t x = x0 - 1 + xx, y = y0 - 1 + yy, z = z0 - 1 + zz;
             uint32_t l = (uint32_t)L;
             if (x >= 0 && x < w && y >= 0 && y < h && z >= 0 && z < d)
-                l = level_of<T, LM>(data[(z * h + y) * w + x], lv);
+                l = level_of<T, LM>(data[(z * h + y) * w + x], lv, lv.thr);
             lam[zz][yy][xx] = (uint16_t)l;
         }
         __syncthreads();
@@ -317,17 +441,19 @@ __global__ void __launch_bounds__(256)
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(256)
     ecc_reduce(const int32_t *__restrict__ partial, int G, int nch, int L, unsigned ch_mask,
-               int64_t *__restrict__ totals) {
+               int64_t *__restrict__ sums) {
     const int ch = blockIdx.y;
     if (!(ch_mask >> ch & 1)) return;
     const int b = blockIdx.x * 256 + threadIdx.x;
     if (b >= L) return;
+    const int groups = gridDim.z, z = blockIdx.z;
+    const int g0 = (int)((int64_t)G * z / groups), g1 = (int)((int64_t)G * (z + 1) / groups);
     int64_t s = 0;
-    const int32_t *p = partial + (int64_t)ch * L + b;
     const int64_t stride = (int64_t)nch * L;
-#pragma unroll 8
-    for (int g = 0; g < G; ++g) s += p[g * stride];
-    totals[(int64_t)ch * L + b] = s;
+    const int32_t *p = partial + (int64_t)ch * L + b;
+#pragma unroll 4
+    for (int g = g0; g < g1; ++g) s += p[g * stride];
+    sums[((int64_t)z * nch + ch) * L + b] = s;
 }
 
 struct OutPtrs {
@@ -335,7 +461,7 @@ struct OutPtrs {
 };
 
 __global__ void __launch_bounds__(1024)
-    ecc_scan(const int64_t *__restrict__ totals, int L, OutPtrs out) {
+    ecc_scan(const int64_t *__restrict__ sums, int groups, int nch, int L, OutPtrs out) {
     __shared__ int64_t part[1024];
     const int ch = blockIdx.x;
     int64_t *dst = out.p[ch];
@@ -343,9 +469,11 @@ __global__ void __launch_bounds__(1024)
     const int t = threadIdx.x;
     const int per = (L + 1023) / 1024;
     const int beg = t * per, end = beg + per < L ? beg + per : L;
-    const int64_t *src = totals + (int64_t)ch * L;
+    const int64_t gstride = (int64_t)nch * L;
+    const int64_t *src = sums + (int64_t)ch * L;
     int64_t s = 0;
-    for (int i = beg; i < end; ++i) s += src[i];
+    for (int i = beg; i < end; ++i)
+        for (int z = 0; z < groups; ++z) s += src[z * gstride + i];
     part[t] = s;
     __syncthreads();
     // Hillis-Steele inclusive scan of the 1024 chunk sums
@@ -357,7 +485,7 @@ __global__ void __launch_bounds__(1024)
     }
     int64_t run = part[t] - s;
     for (int i = beg; i < end; ++i) {
-        run += src[i];
+        for (int z = 0; z < groups; ++z) run += src[z * gstride + i];
         dst[i] = run;
     }
 }
@@ -383,33 +511,47 @@ __global__ void ecc_level_lut(const float *__restrict__ thr, int L, int n_values
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
-size_t lds_bytes_2d(int window, int tile_rows) {
-    (void)tile_rows;
-    return (size_t)window * 8;
+size_t lds_bytes_2d(int window, int L) {
+    return (size_t)window * 8 + (L <= kThrLds ? (size_t)L * 4 : 0);
 }
 size_t lds_bytes_3d(int window, bool want_crease) { return (size_t)window * (want_crease ? 12 : 8); }
 
-template <typename T, int LM>
+template <typename T, int LM, bool AL>
 static int launch_2d_t(const Launch2D &a, hipStream_t s) {
-    constexpr int TH = 32;
-    const int64_t tiles_x = (a.w + kTile2DCols - 1) / kTile2DCols;
-    const int64_t tiles_y = (a.h + TH - 1) / TH;
-    const int64_t n_tiles = tiles_x * tiles_y;
-    const int flush = (int)(kFlush2D / (TH * kTile2DCols));
+    constexpr int VEC = Elem<T>::VEC, PF = 4;
+    const int64_t n_strips = (a.w + 64 * VEC - 1) / (64 * VEC);
+    const int64_t rows = a.row_hi - a.row_lo;
+    const int64_t NW = (int64_t)a.grid * kWavesPerWG;
+    // rows per item: about one item per wave, at least 8 rows
+    int64_t seg = (rows * n_strips + NW - 1) / NW;
+    if (seg < 8) seg = 8;
+    if (seg > rows) seg = rows;
+    const int64_t n_segs = (rows + seg - 1) / seg;
+    const int64_t n_items = n_strips * n_segs;
+    // the packed LDS bins of one workgroup must not see more than kFlush2D cells
+    const int64_t items_per_wave = (n_items + NW - 1) / NW;
+    if (kWavesPerWG * items_per_wave * seg * 64 * VEC > kFlush2D) return (int)hipErrorInvalidValue;
     const int W = a.hi - a.lo;
-    hipLaunchKernelGGL((ecc2d_tile<T, LM, TH>), dim3(a.grid), dim3(256), lds_bytes_2d(W, TH), s,
-                       (const T *)a.data, a.h, a.w, a.lv, a.lo, a.hi, a.delta_lut, a.partial,
-                       tiles_x, n_tiles, flush);
+    hipLaunchKernelGGL((ecc2d_stream<T, LM, AL, PF>), dim3(a.grid), dim3(256),
+                       lds_bytes_2d(W, a.lv.L), s, (const T *)a.data, a.h, a.w, a.lv, a.lo, a.hi,
+                       a.delta_lut, a.partial, a.row_lo, a.row_hi, n_segs, seg, n_items,
+                       a.accumulate ? 1 : 0);
     return (int)hipGetLastError();
+}
+
+template <typename T, int LM>
+static int launch_2d_al(const Launch2D &a, hipStream_t s) {
+    const bool al = ((uintptr_t)a.data % 16 == 0) && (a.w * (int64_t)sizeof(T)) % 16 == 0;
+    return al ? launch_2d_t<T, LM, true>(a, s) : launch_2d_t<T, LM, false>(a, s);
 }
 
 template <typename T>
 static int launch_2d_dt(const Launch2D &a, hipStream_t s) {
     switch (a.lv.mode) {
-    case LM_IDENTITY: return launch_2d_t<T, LM_IDENTITY>(a, s);
-    case LM_LUT: return launch_2d_t<T, LM_LUT>(a, s);
-    case LM_AFFINE: return launch_2d_t<T, LM_AFFINE>(a, s);
-    default: return launch_2d_t<T, LM_SEARCH>(a, s);
+    case LM_IDENTITY: return launch_2d_al<T, LM_IDENTITY>(a, s);
+    case LM_LUT: return launch_2d_al<T, LM_LUT>(a, s);
+    case LM_AFFINE: return launch_2d_al<T, LM_AFFINE>(a, s);
+    default: return launch_2d_al<T, LM_SEARCH>(a, s);
     }
 }
 
@@ -460,17 +602,17 @@ int launch_3d(const Launch3D &a, void *stream) {
     }
 }
 
-int launch_reduce(const int32_t *partial, int grid, int nch, int L, unsigned ch_mask,
-                  int64_t *totals, void *stream) {
-    hipLaunchKernelGGL(ecc_reduce, dim3((L + 255) / 256, nch), dim3(256), 0, (hipStream_t)stream,
-                       partial, grid, nch, L, ch_mask, totals);
+int launch_reduce(const int32_t *partial, int grid, int nch, int L, unsigned ch_mask, int groups,
+                  int64_t *sums, void *stream) {
+    hipLaunchKernelGGL(ecc_reduce, dim3((L + 255) / 256, nch, groups), dim3(256), 0,
+                       (hipStream_t)stream, partial, grid, nch, L, ch_mask, sums);
     return (int)hipGetLastError();
 }
 
-int launch_scan(const int64_t *totals, int nch, int L, int64_t *const out[4], void *stream) {
+int launch_scan(const int64_t *sums, int groups, int nch, int L, int64_t *const out[4], void *stream) {
     OutPtrs o;
     for (int c = 0; c < 4; ++c) o.p[c] = c < nch ? out[c] : nullptr;
-    hipLaunchKernelGGL(ecc_scan, dim3(nch), dim3(1024), 0, (hipStream_t)stream, totals, L, o);
+    hipLaunchKernelGGL(ecc_scan, dim3(nch), dim3(1024), 0, (hipStream_t)stream, sums, groups, nch, L, o);
     return (int)hipGetLastError();
 }
 

@@ -37,7 +37,7 @@ struct ThrEntry {
     uint16_t *d_lut8 = nullptr;
     uint16_t *d_lut16 = nullptr;
     bool affine = false;
-    float t0 = 0.f, inv_step = 0.f;
+    float t0 = 0.f, inv_step = 0.f, eps = 0.f;
 };
 
 struct Workspace {
@@ -66,6 +66,10 @@ struct ecc_context_s {
     void *ws_stream = nullptr;
     bool ws_used = false;
     ecc::BatchState *batch = nullptr;
+    // kernel timing (ecc_profile_enable)
+    bool prof_on = false;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_events;
+    size_t prof_used = 0;
 };
 
 namespace ecc {
@@ -78,5 +82,9 @@ ecc_status release_workspace(ecc_context ctx, void *stream);
 ecc_status grow(ecc_context ctx, DevBuf &b, size_t need, const char *what);
 ecc_status compute_one(ecc_context ctx, const ecc_field *f, const FieldInfo &fi, const ecc_curves *c, void *stream);
 int pick_grid(ecc_context ctx, int64_t n_tiles, size_t lds_per_wg);
+ecc_status merge_and_scan(ecc_context ctx, int grid, int nch, int L, int64_t *const outs[4], void *stream);
 void destroy_batch_state(ecc_context ctx);
+// records the start event of a timed launch on `stream` (no-op unless profiling)
+ecc_status prof_begin(ecc_context ctx, void *stream, int *slot);
+ecc_status prof_end(ecc_context ctx, void *stream, int slot);
 }  // namespace ecc

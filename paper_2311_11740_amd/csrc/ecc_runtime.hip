@@ -4,6 +4,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <string>
@@ -163,6 +164,10 @@ extern "C" ecc_status ecc_destroy(ecc_context ctx) {
     }
     for (auto *t : ctx->thr_cache) free_thresholds(t);
     ctx->thr_cache.clear();
+    for (auto &pe : ctx->prof_events) {
+        hipEventDestroy(pe.first);
+        hipEventDestroy(pe.second);
+    }
     ctx->ws.release();
     if (ctx->ws_event) hipEventDestroy(ctx->ws_event);
     destroy_batch_state(ctx);
@@ -255,17 +260,24 @@ ecc_status get_thresholds(ecc_context ctx, const float *thr, int L, int dtype, v
             free_thresholds(t);
             return hip_fail(e, "hipMemcpyAsync(thresholds)");
         }
-        // affine check: level guess from (x - t0) / step, then exact correction
+        // affine check: the level is estimated from u = (x - t0) / step; where
+        // the fractional part of u is farther than eps from an integer, floor(u)+1
+        // is the exact level.  eps bounds the thresholds' deviation from the
+        // grid t0 + l*step (in steps) plus the float32 rounding of u on the
+        // device, |u| <= L + 2: three roundings of relative size 2^-24.
         t->affine = false;
         if (L >= 2) {
             const double t0 = thr[0], step = ((double)thr[L - 1] - t0) / (L - 1);
-            if (step > 0 && std::isfinite(step) && std::isfinite(t0)) {
+            if (step > 0 && std::isfinite(step) && std::isfinite(t0) && std::isfinite((double)thr[L - 1])) {
                 double dev = 0;
-                for (int l = 0; l < L; ++l) dev = std::max(dev, std::fabs(thr[l] - (t0 + l * step)));
-                if (dev <= 0.5 * step) {
+                for (int l = 0; l < L; ++l) dev = std::max(dev, std::fabs(thr[l] - (t0 + l * step)) / step);
+                const double round_u = (L + 2.0) * 3.1 * std::ldexp(1.0, -24);
+                const double eps = 2.0 * (dev + round_u) + 1e-6;
+                if (eps < 0.25) {
                     t->affine = true;
                     t->t0 = (float)t0;
                     t->inv_step = (float)(1.0 / step);
+                    t->eps = (float)eps;
                 }
             }
         }
@@ -296,6 +308,7 @@ ecc_status level_args(ecc_context ctx, const ecc_field *f, const FieldInfo &fi, 
     lv->lut = nullptr;
     lv->t0 = 0.f;
     lv->inv_step = 0.f;
+    lv->eps = 0.f;
     if (!f->thresholds) {
         lv->mode = LM_IDENTITY;
         return ECC_OK;
@@ -314,6 +327,7 @@ ecc_status level_args(ecc_context ctx, const ecc_field *f, const FieldInfo &fi, 
         lv->mode = LM_AFFINE;
         lv->t0 = te->t0;
         lv->inv_step = te->inv_step;
+        lv->eps = te->eps;
     } else {
         lv->mode = LM_SEARCH;
     }
@@ -356,6 +370,35 @@ int pick_grid(ecc_context ctx, int64_t n_tiles, size_t lds_per_wg) {
     return (int)std::max<int64_t>(1, g);
 }
 
+// Workgroups per CU for the field-reading kernels (environment ECC_WG_PER_CU overrides).
+static int wg_per_cu_default() {
+    static int v = [] {
+        const char *e = std::getenv("ECC_WG_PER_CU");
+        int x = e ? std::atoi(e) : 2;
+        return x < 1 ? 1 : (x > 8 ? 8 : x);
+    }();
+    return v;
+}
+
+ecc_status merge_and_scan(ecc_context ctx, int grid, int nch, int L, int64_t *const outs[4],
+                          void *stream) {
+    unsigned mask = 0;
+    for (int q = 0; q < nch; ++q)
+        if (outs[q]) mask |= 1u << q;
+    // stage 1 sums groups of workgroup partials in parallel, stage 2 (in the
+    // scan kernel) adds the group sums and takes the running sum over levels
+    int gs = std::max(1, std::min(64, grid / 8));
+    while (gs > 1 && (int64_t)gs * L > (1 << 17)) gs >>= 1;
+    ecc_status s = grow(ctx, ctx->ws.totals, (size_t)gs * nch * L * sizeof(int64_t), "totals");
+    if (s != ECC_OK) return s;
+    int64_t *totals = (int64_t *)ctx->ws.totals.ptr;
+    int e = launch_reduce((const int32_t *)ctx->ws.partial.ptr, grid, nch, L, mask, gs, totals, stream);
+    if (e) return hip_fail(e, "reduce kernel launch");
+    e = launch_scan(totals, gs, nch, L, outs, stream);
+    if (e) return hip_fail(e, "scan kernel launch");
+    return ECC_OK;
+}
+
 ecc_status compute_one(ecc_context ctx, const ecc_field *f, const FieldInfo &fi,
                        const ecc_curves *c, void *stream) {
     LevelArgs lv;
@@ -365,50 +408,56 @@ ecc_status compute_one(ecc_context ctx, const ecc_field *f, const FieldInfo &fi,
     const int nch = fi.ndim == 2 ? 3 : 4;
     const int win = std::min(L, kMaxWindow);
     const bool crease = fi.ndim == 3 && c->perimeter != nullptr;
-    int64_t n_tiles;
-    size_t lds;
+    const int k = (fi.ndim == 2 ? (fi.conn == 8 ? 0 : 1) : (fi.conn == 26 ? 0 : 1));
+    int grid;
     if (fi.ndim == 2) {
-        n_tiles = ((fi.w + kTile2DCols - 1) / kTile2DCols) * ((fi.h + 31) / 32);
-        lds = lds_bytes_2d(win, 32) + 32 * 1024;
+        const int vec = vec_2d(fi.dtype);
+        const int64_t strips = (fi.w + 64 * vec - 1) / (64 * vec);
+        grid = (int)std::min<int64_t>((int64_t)ctx->n_cu * wg_per_cu_default(),
+                                      std::max<int64_t>(1, (strips * fi.h + 31) / 32));
+        if (grid >= 8) grid -= grid % 8;
     } else {
-        n_tiles = ((fi.w + kTile3DX - 1) / kTile3DX) * ((fi.h + kTile3DY - 1) / kTile3DY) *
-                  ((fi.d + kTile3DZ - 1) / kTile3DZ);
-        lds = lds_bytes_3d(win, crease) + 16 * 1024;
+        const int64_t n_tiles = ((fi.w + kTile3DX - 1) / kTile3DX) * ((fi.h + kTile3DY - 1) / kTile3DY) *
+                                ((fi.d + kTile3DZ - 1) / kTile3DZ);
+        grid = pick_grid(ctx, n_tiles, lds_bytes_3d(win, crease) + 16 * 1024);
     }
-    const int grid = pick_grid(ctx, n_tiles, lds);
     s = grow(ctx, ctx->ws.partial, (size_t)grid * nch * L * sizeof(int32_t), "partials");
     if (s != ECC_OK) return s;
-    s = grow(ctx, ctx->ws.totals, (size_t)nch * L * sizeof(int64_t), "totals");
-    if (s != ECC_OK) return s;
     int32_t *partial = (int32_t *)ctx->ws.partial.ptr;
-    int64_t *totals = (int64_t *)ctx->ws.totals.ptr;
-    const int k = (fi.ndim == 2 ? (fi.conn == 8 ? 0 : 1) : (fi.conn == 26 ? 0 : 1));
     for (int lo = 0; lo < L; lo += win) {
         const int hi = std::min(L, lo + win);
-        int e;
         if (fi.ndim == 2) {
-            Launch2D a{f->data, fi.dtype, fi.h, fi.w, lv, lo, hi, ctx->d_delta2[k], partial, grid, 32};
-            e = launch_2d(a, stream);
+            // the packed LDS bins of a workgroup hold at most kFlush2D cells:
+            // split tall fields into row chunks that respect it
+            const int vec = vec_2d(fi.dtype);
+            const int64_t strips = (fi.w + 64 * vec - 1) / (64 * vec);
+            const int64_t cap = (int64_t)grid * (kFlush2D / 4);  // cells per launch
+            int64_t chunk = std::max<int64_t>(1, cap / (strips * 64 * vec));
+            for (int64_t r0 = 0; r0 < fi.h; r0 += chunk) {
+                const int64_t r1 = std::min(fi.h, r0 + chunk);
+                int slot = -1;
+                s = prof_begin(ctx, stream, &slot);
+                if (s != ECC_OK) return s;
+                Launch2D a{f->data, fi.dtype, fi.h, fi.w, lv, lo, hi, ctx->d_delta2[k], partial, grid,
+                           r0, r1, r0 > 0};
+                int e = launch_2d(a, stream);
+                if (e) return hip_fail(e, "2D kernel launch");
+                s = prof_end(ctx, stream, slot);
+                if (s != ECC_OK) return s;
+            }
         } else {
+            int slot = -1;
+            s = prof_begin(ctx, stream, &slot);
+            if (s != ECC_OK) return s;
             Launch3D a{f->data, fi.dtype, fi.d, fi.h, fi.w, lv, lo, hi, ctx->d_vtab3[k], partial, grid, crease};
-            e = launch_3d(a, stream);
+            int e = launch_3d(a, stream);
+            if (e) return hip_fail(e, "3D kernel launch");
+            s = prof_end(ctx, stream, slot);
+            if (s != ECC_OK) return s;
         }
-        if (e) return hip_fail(e, "tile kernel launch");
     }
-    int64_t *outs[4];
-    if (fi.ndim == 2) {
-        outs[0] = c->ec; outs[1] = c->perimeter; outs[2] = c->area; outs[3] = nullptr;
-    } else {
-        outs[0] = c->ec; outs[1] = c->perimeter; outs[2] = c->area; outs[3] = c->volume;
-    }
-    unsigned mask = 0;
-    for (int q = 0; q < nch; ++q)
-        if (outs[q]) mask |= 1u << q;
-    int e = launch_reduce(partial, grid, nch, L, mask, totals, stream);
-    if (e) return hip_fail(e, "reduce kernel launch");
-    e = launch_scan(totals, nch, L, outs, stream);
-    if (e) return hip_fail(e, "scan kernel launch");
-    return ECC_OK;
+    int64_t *outs[4] = {c->ec, c->perimeter, c->area, fi.ndim == 3 ? c->volume : nullptr};
+    return merge_and_scan(ctx, grid, nch, L, outs, stream);
 }
 
 }  // namespace ecc
@@ -434,4 +483,57 @@ extern "C" ecc_status ecc_validate_field(const ecc_field *field, const ecc_curve
     clear_error();
     FieldInfo fi;
     return validate_field(field, curves, &fi, false);
+}
+
+namespace ecc {
+ecc_status prof_begin(ecc_context ctx, void *stream, int *slot) {
+    *slot = -1;
+    if (!ctx->prof_on) return ECC_OK;
+    if (ctx->prof_used == ctx->prof_events.size()) {
+        hipEvent_t a, b;
+        int e = (int)hipEventCreate(&a);
+        if (e) return hip_fail(e, "hipEventCreate");
+        e = (int)hipEventCreate(&b);
+        if (e) return hip_fail(e, "hipEventCreate");
+        ctx->prof_events.push_back({a, b});
+    }
+    *slot = (int)ctx->prof_used++;
+    int e = (int)hipEventRecord(ctx->prof_events[*slot].first, (hipStream_t)stream);
+    if (e) return hip_fail(e, "hipEventRecord");
+    return ECC_OK;
+}
+
+ecc_status prof_end(ecc_context ctx, void *stream, int slot) {
+    if (slot < 0) return ECC_OK;
+    int e = (int)hipEventRecord(ctx->prof_events[slot].second, (hipStream_t)stream);
+    if (e) return hip_fail(e, "hipEventRecord");
+    return ECC_OK;
+}
+}  // namespace ecc
+
+extern "C" ecc_status ecc_profile_enable(ecc_context ctx, int32_t on) {
+    clear_error();
+    if (!ctx) return fail(ECC_ERR_INVALID_ARG, "context is NULL");
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    ctx->prof_on = on != 0;
+    return ECC_OK;
+}
+
+extern "C" ecc_status ecc_profile_read(ecc_context ctx, double *total_ms, int64_t *launches, int32_t reset) {
+    clear_error();
+    if (!ctx || !total_ms || !launches) return fail(ECC_ERR_INVALID_ARG, "NULL argument");
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    double tot = 0;
+    for (size_t i = 0; i < ctx->prof_used; ++i) {
+        int e = (int)hipEventSynchronize(ctx->prof_events[i].second);
+        if (e) return hip_fail(e, "hipEventSynchronize");
+        float ms = 0;
+        e = (int)hipEventElapsedTime(&ms, ctx->prof_events[i].first, ctx->prof_events[i].second);
+        if (e) return hip_fail(e, "hipEventElapsedTime");
+        tot += ms;
+    }
+    *total_ms = tot;
+    *launches = (int64_t)ctx->prof_used;
+    if (reset) ctx->prof_used = 0;
+    return ECC_OK;
 }

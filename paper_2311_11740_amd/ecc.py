@@ -21,7 +21,7 @@ ECC_U8, ECC_U16, ECC_F32 = 1, 2, 3
 EXPORTS = (
     "ecc_create", "ecc_destroy", "ecc_last_error", "ecc_status_string",
     "ecc_curves_compute", "ecc_curves_compute_batch", "ecc_batch_plan_tune",
-    "ecc_vertex_table", "ecc_validate_field",
+    "ecc_vertex_table", "ecc_validate_field", "ecc_profile_enable", "ecc_profile_read",
     "ecc_server_create", "ecc_server_submit", "ecc_server_poll", "ecc_server_drain",
     "ecc_server_destroy",
 )
@@ -77,6 +77,9 @@ def load(path: str = LIB_PATH):
         "ecc_batch_plan_tune": ([vp, i32, ctypes.POINTER(Field), vp], ctypes.c_int),
         "ecc_vertex_table": ([i32, i32, ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
         "ecc_validate_field": ([ctypes.POINTER(Field), ctypes.POINTER(Curves)], ctypes.c_int),
+        "ecc_profile_enable": ([vp, i32], ctypes.c_int),
+        "ecc_profile_read": ([vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64), i32],
+                             ctypes.c_int),
         "ecc_server_create": ([vp, ctypes.POINTER(ServerConfig), ctypes.POINTER(vp)], ctypes.c_int),
         "ecc_server_submit": ([vp, ctypes.POINTER(Field), ctypes.POINTER(Curves),
                                ctypes.POINTER(ctypes.c_uint64)], ctypes.c_int),
@@ -208,11 +211,27 @@ class Context:
         except Exception:
             pass
 
+    def profile(self, on: bool = True):
+        check(self._lib.ecc_profile_enable(self.handle, 1 if on else 0))
+
+    def profile_read(self, reset: bool = True):
+        """(total milliseconds, launches) of the field-reading kernel since the last reset."""
+        ms = ctypes.c_double()
+        n = ctypes.c_int64()
+        check(self._lib.ecc_profile_read(self.handle, ctypes.byref(ms), ctypes.byref(n), 1 if reset else 0))
+        return ms.value, n.value
+
     def compute(self, field, n_levels: int, thresholds=None, connectivity: int = 0,
-                channels: Sequence[str] | None = None, stream=None):
-        """Curves of one device field: dict channel -> int64 device tensor (async on `stream`)."""
+                channels: Sequence[str] | None = None, stream=None, out=None):
+        """Curves of one device field: dict channel -> int64 device tensor (async on `stream`).
+        `out` may supply preallocated curves (dict channel -> int64 tensor of n_levels)."""
         f, keep = make_field(field, n_levels, thresholds, connectivity)
-        out, cv = alloc_curves(field.dim(), n_levels, field.device, channels)
+        if out is None:
+            out, cv = alloc_curves(field.dim(), n_levels, field.device, channels)
+        else:
+            cv = Curves()
+            for c in ("ec", "perimeter", "area", "volume"):
+                setattr(cv, c, out[c].data_ptr() if c in out else None)
         check(self._lib.ecc_curves_compute(self.handle, ctypes.byref(f), ctypes.byref(cv),
                                            _stream_ptr(stream)))
         del keep
