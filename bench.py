@@ -103,7 +103,7 @@ def time_field(ctx, spec, steps: int, warmup: int, copies: int):
     res = {c: v.cpu().numpy() for c, v in out.items()}
     del bufs
     return dict(ms_per_step=total_ms / steps, wall_s=wall, kernel_ms=k_ms / max(k_n, 1),
-                kernel_launches=k_n, curves=res)
+                kernel_ms_per_step=k_ms / steps, kernel_launches=k_n, curves=res)
 
 
 def cpu_baseline(spec, gpu_curves):
@@ -120,15 +120,20 @@ def cpu_baseline(spec, gpu_curves):
                        f"all-levels C oracle, one run of {dt:.2f} s"), ok
 
 
+STEPS_CTX = {"steps": 1}
+
+
 def measure(ctx, name, steps, warmup, copies, with_cpu):
+    STEPS_CTX["steps"] = steps
     spec = make_workload(name)
     r = time_field(ctx, spec, steps, warmup, copies)
     cells = spec.data.size
     elem = spec.data.dtype.itemsize
     value = cells / (r["ms_per_step"] / 1e3) / 1e9
-    kernel = "ecc2d_tile" if spec.data.ndim == 2 else "ecc3d_tile"
-    alg_bytes = cells * elem  # the field-reading kernel reads every cell once
-    achieved = alg_bytes / (r["kernel_ms"] / 1e3) / 1e9
+    kernel = "ecc2d_stream" if spec.data.ndim == 2 else "ecc3d_tile"
+    alg_bytes = cells * elem  # the field-reading kernel reads every cell once per step
+    launches_per_step = r["kernel_launches"] / max(1, STEPS_CTX["steps"])
+    achieved = alg_bytes / (r["kernel_ms_per_step"] / 1e3) / 1e9
     traffic = load_traffic(kernel, spec.meta["name"])
     out = dict(
         workload=spec.meta["name"], cells=cells, bytes=alg_bytes,
@@ -136,7 +141,9 @@ def measure(ctx, name, steps, warmup, copies, with_cpu):
         hbm_frac_step=round(alg_bytes / (r["ms_per_step"] / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
         roofline=dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                       frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic, kernel=kernel,
-                      kernel_ms=round(r["kernel_ms"], 4), alg_bytes_per_launch=alg_bytes),
+                      kernel_ms_per_launch=round(r["kernel_ms"], 4),
+                      launches_per_step=launches_per_step,
+                      alg_bytes_per_launch=int(alg_bytes / launches_per_step)),
         spec=spec, curves=r["curves"])
     if with_cpu:
         cb, ok = cpu_baseline(spec, r["curves"])

@@ -47,10 +47,12 @@ struct LevelArgs {
     int32_t mode;
     const float *thr;     // device, L floats (LM_AFFINE / LM_SEARCH)
     const uint16_t *lut;  // device, 256 or 65536 entries (LM_LUT)
-    float t0, inv_step;   // LM_AFFINE: u = (x - t0) * inv_step estimates the level
-    float eps;            // LM_AFFINE: fractional parts of u within eps of an integer
-                          // are resolved against the thresholds; elsewhere floor(u)+1
-                          // is exact (the host bounds the grid deviation and rounding)
+    float u0, inv_step;   // LM_AFFINE: u = fma(x, inv_step, u0) ~ (x - t_0) / step
+    double u0d;           // LM_AFFINE: u0 before rounding to float
+    float eps;            // LM_AFFINE: where the fractional part of u is farther than
+                          // eps from an integer, floor(u)+1 is the exact level (the host
+                          // bounds the grid deviation and the rounding of u by eps/2);
+                          // elsewhere the level is settled against the thresholds
 };
 
 // thresholds kept in LDS by the kernels when L is at most this
@@ -64,7 +66,7 @@ struct Launch2D {
     LevelArgs lv;
     int32_t lo, hi;             // level window [lo, hi) histogrammed by this pass
     const uint64_t *delta_lut;  // device, 256 packed per-cell deltas
-    int32_t *partial;           // device, [grid][3][L]
+    int32_t *partial;           // device, [3][L][grid]
     int grid;
     int64_t row_lo, row_hi;     // rows whose cells this launch emits (halo rows are read)
     bool accumulate;            // add to the partials instead of overwriting them
@@ -80,7 +82,7 @@ struct Launch3D {
     LevelArgs lv;
     int32_t lo, hi;
     const int64_t *vtab;  // device, 256 packed per-vertex contributions (x8 scale)
-    int32_t *partial;     // device, [grid][4][L]
+    int32_t *partial;     // device, [4][L][grid]
     int grid;
     bool want_crease;
 };
@@ -88,11 +90,11 @@ struct Launch3D {
 // device-side launchers (ecc_kernels.hip); return a hipError_t as int
 int launch_2d(const Launch2D &a, void *stream);
 int launch_3d(const Launch3D &a, void *stream);
-// partials [grid][nch][L] int32 -> group sums [groups][nch][L] int64
-int launch_reduce(const int32_t *partial, int grid, int nch, int L, unsigned ch_mask, int groups,
-                  int64_t *sums, void *stream);
-// sums over groups and running sum over levels into the caller's curves
-int launch_scan(const int64_t *sums, int groups, int nch, int L, int64_t *const out[4], void *stream);
+// partials [nch][L][grid] int32 -> per-level totals -> running sums into the
+// caller's curves (channels with a NULL output are skipped); `counter` is a
+// zero-initialised device word that the kernel leaves at zero
+int launch_merge(const int32_t *partial, int grid, int nch, int L, int64_t *const out[4],
+                 int64_t *totals, unsigned *counter, void *stream);
 int launch_level_lut(const float *thr, int L, int n_values, uint16_t *lut, void *stream);
 
 // tile geometry used by the single-field kernels

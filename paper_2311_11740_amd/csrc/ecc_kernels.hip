@@ -25,6 +25,8 @@
 //     (no global atomics), merged by ecc_reduce and prefix-summed by ecc_scan.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "ecc_internal.h"
 
 namespace ecc {
@@ -32,25 +34,40 @@ namespace ecc {
 // ---------------------------------------------------------------------------
 // level index: first l with value <= t_l (Eq. (2)); L = never active
 // ---------------------------------------------------------------------------
-template <int LM>
-__device__ __forceinline__ uint32_t level_of_float(float x, const LevelArgs &a, const float *thr) {
+// Thresholds are read through one of two accessors so that the compiler
+// emits LDS reads (ds_read) or global reads, never generic flat accesses.
+// ThrLds holds the window of thresholds [base, base + n) of one level pass.
+struct ThrLds {
+    const float *p;
+    int base;
+    __device__ float operator[](int i) const { return p[i - base]; }
+};
+struct ThrGlobal {
+    const float *__restrict__ p;
+    __device__ float operator[](int i) const { return p[i]; }
+};
+
+template <int LM, typename TH>
+__device__ __forceinline__ uint32_t level_of_float(float x, const LevelArgs &a, const TH &thr) {
     const int L = a.L;
     if (!(x == x)) return (uint32_t)L;  // NaN never enters
-    int g;
     if constexpr (LM == LM_AFFINE) {
-        const float u = (x - a.t0) * a.inv_step;
-        if (u < -1.0f) return 0u;
-        if (u >= (float)L + 1.0f) return (uint32_t)L;
-        const float fu = floorf(u);
-        const float fr = u - fu;
-        g = (int)fu + 1;
-        if (g > L) g = L;
-        if (fr >= a.eps && fr <= 1.0f - a.eps) return (uint32_t)g;
-        // close to a threshold: settle against the caller's values so that
-        // t[g-1] < x <= t[g] (with t[-1] = -inf, t[L] = +inf)
-        if (g < 0) g = 0;
-        while (g > 0 && x <= thr[g - 1]) --g;
-        while (g < L && !(x <= thr[g])) ++g;
+        const float u = __builtin_fmaf(x, a.inv_step, a.u0);
+        const float fr = __builtin_amdgcn_fractf(u);
+        const float uc = __builtin_amdgcn_fmed3f(u, -2.0f, (float)L + 2.0f);
+        int g = (int)__builtin_floorf(uc) + 1;
+        g = g < 0 ? 0 : (g > L ? L : g);
+        if (!(__builtin_fabsf(fr - 0.5f) <= 0.5f - a.eps)) {
+            // within eps of a grid point: the level is g-1, g or g+1 (the
+            // host bounds the grid deviation plus rounding below one step);
+            // settle it against the caller's thresholds
+            const float ta = thr[g > 0 ? g - 1 : 0], tb = thr[g < L ? g : L - 1];
+            if (g > 0 && x <= ta)
+                --g;
+            else if (g < L && !(x <= tb))
+                ++g;
+        }
+        return (uint32_t)g;
     } else {
         int lo = 0, hi = L;
         while (lo < hi) {
@@ -60,13 +77,12 @@ __device__ __forceinline__ uint32_t level_of_float(float x, const LevelArgs &a, 
             else
                 lo = mid + 1;
         }
-        g = lo;
+        return (uint32_t)lo;
     }
-    return (uint32_t)g;
 }
 
-template <typename T, int LM>
-__device__ __forceinline__ uint32_t level_of(T v, const LevelArgs &a, const float *thr) {
+template <typename T, int LM, typename TH>
+__device__ __forceinline__ uint32_t level_of(T v, const LevelArgs &a, const TH &thr) {
     if constexpr (LM == LM_IDENTITY) {
         const uint32_t u = (uint32_t)v;
         return u < (uint32_t)a.L ? u : (uint32_t)a.L;
@@ -87,13 +103,23 @@ __device__ __forceinline__ int xcd_order(int bid, int G) {
 // ---------------------------------------------------------------------------
 // 2D: row streaming
 // ---------------------------------------------------------------------------
-// One wave owns a strip of 64*VEC columns (VEC cells per lane, 16 bytes of
-// input per lane and row) and walks down a run of rows, keeping the level
-// indices of three rows (above, current, below) in registers.  The cells left
-// and right of a lane's run come from the neighbouring lanes (ds_bpermute);
-// lanes 0 and 63 read the strip's halo columns themselves.  Raw rows are
-// fetched PF rows ahead into a register ring so that several 1 KiB row loads
-// per wave are in flight.
+// One wave walks down a run of rows of a strip of columns, keeping the level
+// indices of three rows (above, current, below) in registers.  Each lane
+// holds VEC consecutive cells of a row (16 bytes of input).  Strips overlap by
+// one lane on each side: lanes 1..62 own the strip's 62*VEC cells, lanes 0
+// and 63 hold the cells just left and right of them and only serve as halo,
+// so a full strip reads each row with one unconditional 16-byte load per lane
+// and gets every horizontal neighbour by a lane shuffle.  Raw rows are fetched
+// PF rows ahead into a register ring so that several row loads per wave are
+// in flight.
+//
+// Level indices of a row are kept as VEC+1 packed 16-bit pairs
+// P[i] = (lam[i], lam[i+1]) where lam[0] and lam[VEC+1] are the neighbours
+// from the adjacent lanes.  For the two cells (j, j+1) of P[j] every
+// neighbour pair is one of these words (W = P[j-1], E = P[j+1], and P[j-1..j+1]
+// of the rows above and below), so each "entered before" relation of both
+// cells is one packed subtraction: q precedes p  <=>  q < p (later
+// neighbours) or q < p + 1 (earlier neighbours, which win ties).
 template <typename T>
 struct Elem;
 template <>
@@ -121,181 +147,420 @@ __device__ __forceinline__ T as_value(uint32_t bits) {
 }
 
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+typedef short i16x2 __attribute__((ext_vector_type(2)));
+
+// per 16-bit half: 1 when q < ref (both in [0, 2^15)), else 0
+__device__ __forceinline__ uint32_t pk_lt(uint32_t q, uint32_t ref) {
+    const i16x2 d = __builtin_bit_cast(i16x2, q) - __builtin_bit_cast(i16x2, ref);
+    return __builtin_bit_cast(uint32_t, __builtin_bit_cast(u16x2, d) >> (unsigned short)15);
+}
 
 struct RawRow {
-    uint32_t w[4];  // 16 bytes: VEC raw elements of this lane
-    uint32_t halo;  // lane 0: element left of the strip; lane 63: right of it
-    bool valid;     // row inside the field
+    uint32_t w[4];   // 16 bytes: VEC raw elements of this lane
+    uint32_t valid;  // bit i: element i lies inside the field
 };
 
+// ALIGNED: the field's base and row pitch are multiples of 16 bytes, so each
+// lane's 16-byte block is either wholly inside the row or wholly outside it;
+// every lane then issues one unconditional 16-byte load (clamped to column 0
+// when outside).  Otherwise elements are loaded one by one.  The row index is
+// clamped into the field by the caller: loads are never skipped, so the
+// compiler can keep several of them in flight (a skipped load would make it
+// wait for all outstanding ones).
 template <typename T, bool ALIGNED>
-__device__ __forceinline__ void fetch_row(const T *__restrict__ data, int64_t r, int64_t h, int64_t w,
-                                          int64_t xs, int64_t x0, int lane, RawRow &raw) {
+__device__ __forceinline__ void fetch_row(const T *__restrict__ data, int r, int64_t w, int64_t x0,
+                                          RawRow &raw) {
     constexpr int VEC = Elem<T>::VEC;
-    raw.valid = r >= 0 && r < h;
-    if (!raw.valid) return;
-    const T *row = data + r * w;
-    if (ALIGNED && x0 + VEC <= w) {
-        const u32x4 q = __builtin_nontemporal_load(reinterpret_cast<const u32x4 *>(row + x0));
+    const T *row = data + (int64_t)r * w;
+    if constexpr (ALIGNED) {
+        const bool in = x0 >= 0 && x0 < w;
+        const u32x4 q = __builtin_nontemporal_load(reinterpret_cast<const u32x4 *>(row + (in ? x0 : 0)));
         raw.w[0] = q.x; raw.w[1] = q.y; raw.w[2] = q.z; raw.w[3] = q.w;
+        raw.valid = in ? (1u << VEC) - 1u : 0u;
     } else {
         raw.w[0] = raw.w[1] = raw.w[2] = raw.w[3] = 0;
+        raw.valid = 0;
 #pragma unroll
         for (int i = 0; i < VEC; ++i) {
-            if (x0 + i < w) {
-                uint32_t bits;
-                if constexpr (sizeof(T) == 4)
-                    bits = __float_as_uint(row[x0 + i]);
-                else
-                    bits = (uint32_t)row[x0 + i];
-                constexpr int per = 4 / sizeof(T);
-                raw.w[i / per] |= bits << (8 * sizeof(T) * (i % per));
-            }
+            const int64_t x = x0 + i;
+            const bool in = x >= 0 && x < w;
+            uint32_t bits;
+            if constexpr (sizeof(T) == 4)
+                bits = __float_as_uint(row[in ? x : 0]);
+            else
+                bits = (uint32_t)row[in ? x : 0];
+            constexpr int per = 4 / sizeof(T);
+            raw.w[i / per] |= (in ? bits : 0u) << (8 * sizeof(T) * (i % per));
+            raw.valid |= (in ? 1u : 0u) << i;
         }
     }
-    raw.halo = 0;
-    if (lane == 0 && xs > 0) {
-        if constexpr (sizeof(T) == 4) raw.halo = __float_as_uint(row[xs - 1]);
-        else raw.halo = (uint32_t)row[xs - 1];
-    }
-    if (lane == 63 && xs + 64 * VEC < w) {
-        if constexpr (sizeof(T) == 4) raw.halo = __float_as_uint(row[xs + 64 * VEC]);
-        else raw.halo = (uint32_t)row[xs + 64 * VEC];
-    }
 }
 
-// level indices of a fetched row: lam[1..VEC] own cells, lam[0] / lam[VEC+1]
-// the cells left of the first and right of the last
-template <typename T, int LM>
-__device__ __forceinline__ void convert_row(const RawRow &raw, int64_t w, int64_t xs, int64_t x0, int lane,
-                                            const LevelArgs &lv, const float *thr,
-                                            uint32_t (&lam)[Elem<T>::VEC + 2]) {
+// Level index of a float value with the affine estimate, without the
+// threshold check; `near` is set where that check is needed.
+__device__ __forceinline__ uint32_t level_affine_fast(float x, const LevelArgs &a, float half_m_eps,
+                                                      bool &near) {
+    const float u = __builtin_fmaf(x, a.inv_step, a.u0);
+    const float fr = __builtin_amdgcn_fractf(u);
+    near = !(__builtin_fabsf(fr - 0.5f) <= half_m_eps);  // also true for NaN and inf
+    const float uc = __builtin_amdgcn_fmed3f(u, -2.0f, (float)a.L + 2.0f);
+    int g = (int)__builtin_floorf(uc) + 1;
+    g = g < 0 ? 0 : (g > a.L ? a.L : g);
+    return (uint32_t)g;
+}
+
+// exact level of x given an estimate g that is off by at most one; only
+// called for g in [lo - 1, hi], whose neighbouring thresholds are staged
+template <typename TH>
+__device__ __forceinline__ uint32_t level_settle(float x, uint32_t g, int L, const TH &thr) {
+    if (!(x == x)) return (uint32_t)L;
+    const int gi = (int)g;
+    const float a = thr[gi > 0 ? gi - 1 : 0], b = thr[gi < L ? gi : L - 1];
+    const int dec = (gi > 0 && x <= a) ? 1 : 0;
+    const int inc = (gi < L && !(x <= b)) ? 1 : 0;
+    return (uint32_t)(gi - dec + inc);
+}
+
+// level of x mapped into the pass window (see convert_row) by a binary search
+// over the staged thresholds [lo - 1, hi)
+template <typename TH>
+__device__ __forceinline__ uint32_t level_search_window(float x, int lo, int hi, const TH &thr) {
+    const int W = hi - lo;
+    if (lo > 0 && x <= thr[lo - 1]) return 0u;
+    if (!(x <= thr[hi - 1])) return (uint32_t)(W + 1);  // also NaN
+    int a = lo, b = hi - 1;                              // x <= thr[b]
+    while (a < b) {
+        const int m = (a + b) >> 1;
+        if (x <= thr[m])
+            b = m;
+        else
+            a = m + 1;
+    }
+    return (uint32_t)(a - lo + 1);
+}
+
+// Level indices of one row mapped into the pass window [lo, lo + W) as
+// lam' = clamp(lam - lo + 1, 0, W + 1): 0 below the window, 1..W inside, W+1
+// above it and for cells that never enter.  For a cell inside the window every
+// "entered before" relation is unchanged, and lam' <= 4097 fits the packed
+// 16-bit compares.  Packed as pairs P[i] = (lam'[i-1], lam'[i]) of the lane's
+// cells, with the neighbouring lanes' cells at both ends.
+//
+// Float fields with (nearly) evenly spaced thresholds: y = fma(x, 1/step, c)
+// with c = -t0/step + 1.5 - lo estimates lam' - 0.5; adding 1.5*2^23 rounds y
+// to an integer k in the low mantissa bits of m (exact for |y| < 2^22), and
+// r = y - k is the rounding residual.  k = lam' unless |r| is within eps of
+// 1/2, i.e. x sits within the host's error bound of a threshold; those cells
+// are settled against the thresholds.
+constexpr float kMagic = 12582912.0f;  // 1.5 * 2^23
+constexpr uint32_t kMagicBits = 0x4B400000u;
+
+__device__ __forceinline__ uint32_t pack_lo16(uint32_t a, uint32_t b) {  // (a.lo, b.lo)
+    return __builtin_amdgcn_perm(b, a, 0x05040100u);
+}
+
+template <typename T, int LM, typename TH>
+__device__ __forceinline__ void convert_row(const RawRow &raw, bool row_ok, bool full, const LevelArgs &lv,
+                                            const TH &thr, int lo, int W, float cpass,
+                                            uint32_t (&P)[Elem<T>::VEC + 1]) {
     constexpr int VEC = Elem<T>::VEC;
-    const uint32_t L = (uint32_t)lv.L;
+    const uint32_t never = (uint32_t)(W + 1);
+    if (!row_ok) {  // uniform
 #pragma unroll
-    for (int i = 0; i < VEC; ++i)
-        lam[i + 1] = (raw.valid && x0 + i < w) ? level_of<T, LM>(as_value<T>(Elem<T>::get(raw.w, i)), lv, thr) : L;
-    uint32_t left = __shfl_up(lam[VEC], 1);
-    uint32_t right = __shfl_down(lam[1], 1);
-    if (lane == 0) left = (raw.valid && xs > 0) ? level_of<T, LM>(as_value<T>(raw.halo), lv, thr) : L;
-    if (lane == 63) right = (raw.valid && xs + 64 * VEC < w) ? level_of<T, LM>(as_value<T>(raw.halo), lv, thr) : L;
-    lam[0] = left;
-    lam[VEC + 1] = right;
+        for (int i = 0; i <= VEC; ++i) P[i] = never | never << 16;
+        return;
+    }
+    uint32_t lam[VEC];  // low 16 bits: lam'
+    const int base = lo - 1;
+    if constexpr (LM == LM_AFFINE) {
+        const float hme = 0.5f - lv.eps;
+        const float mhi = kMagic + (float)never;
+        bool nr[VEC];
+        bool any = false;
+#pragma unroll
+        for (int i = 0; i < VEC; ++i) {
+            const float y = __builtin_fmaf(__uint_as_float(raw.w[i]), lv.inv_step, cpass);
+            const float m = y + kMagic;
+            const float r = y - (m - kMagic);
+            nr[i] = !(__builtin_fabsf(r) <= hme);  // also NaN and +-inf
+            lam[i] = __float_as_uint(__builtin_amdgcn_fmed3f(m, kMagic, mhi));
+            any |= nr[i];
+        }
+        if (__any(any)) {  // rare: a value within eps of a threshold
+#pragma unroll
+            for (int i = 0; i < VEC; ++i) {
+                const int k = (int)(lam[i] - kMagicBits);  // clamped estimate of lam'
+                if (nr[i] && k >= 0 && k <= W + 1) {
+                    // only estimates inside or next to the window can matter;
+                    // the estimate is a level, so at least 0 (k = 0 with lo = 0
+                    // would otherwise stand for level -1)
+                    const int g0 = k + base < 0 ? 0 : k + base;
+                    const int g = level_settle(__uint_as_float(raw.w[i]), (uint32_t)g0, lv.L, thr);
+                    lam[i] = (uint32_t)min(max(g - base, 0), (int)never);
+                }
+            }
+        }
+    } else if constexpr (LM == LM_SEARCH) {
+#pragma unroll
+        for (int i = 0; i < VEC; ++i) lam[i] = level_search_window(as_value<float>(raw.w[i]), lo, lo + W, thr);
+    } else {
+#pragma unroll
+        for (int i = 0; i < VEC; ++i) {
+            const int l = (int)level_of<T, LM>(as_value<T>(Elem<T>::get(raw.w, i)), lv, thr);
+            lam[i] = (uint32_t)min(max(l - base, 0), (int)never);
+        }
+    }
+    if (!full) {  // uniform: some lanes hold cells outside the field
+#pragma unroll
+        for (int i = 0; i < VEC; ++i)
+            if (!(raw.valid >> i & 1u)) lam[i] = never;
+    }
+    // neighbours from the adjacent lanes by DPP wave shifts (lane 0's left and
+    // lane 63's right are never used: those lanes only serve as halo)
+    const uint32_t left = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)lam[VEC - 1], 0x138, 0xf, 0xf, false);
+    const uint32_t right = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)lam[0], 0x130, 0xf, 0xf, false);
+    P[0] = pack_lo16(left, lam[0]);
+#pragma unroll
+    for (int i = 1; i < VEC; ++i) P[i] = pack_lo16(lam[i - 1], lam[i]);
+    P[VEC] = pack_lo16(lam[VEC - 1], right);
 }
 
-__device__ __forceinline__ void drain_2d(uint64_t *hist, int W, int lo, int L, int32_t *slot,
-                                         bool first) {
+// Partials are stored level-major, [channel][level][workgroup] (int32), so that
+// the merge reads the values of one bin contiguously.
+__device__ __forceinline__ void drain_2d(const uint64_t *hist, int W, int lo, int L, int G, int wg,
+                                         int32_t *__restrict__ partial, bool first) {
     for (int b = threadIdx.x; b < W; b += blockDim.x) {
         const uint64_t v = hist[b];
-        hist[b] = 0;
         const int64_t n = (int64_t)(v >> kShiftCnt2);
         const int64_t per = (int64_t)((v >> kShiftPer2) & ((1ull << (kShiftCnt2 - kShiftPer2)) - 1)) -
                             kPerBias2 * n;
         const int64_t ec = (int64_t)(v & ((1ull << kShiftPer2) - 1)) - kEcBias2 * n;
-        int32_t *s0 = slot + lo + b, *s1 = slot + L + lo + b, *s2 = slot + 2 * L + lo + b;
+        const int64_t i0 = ((int64_t)(lo + b)) * G + wg, cs = (int64_t)L * G;
         if (first) {
-            *s0 = (int32_t)ec;
-            *s1 = (int32_t)per;
-            *s2 = (int32_t)n;
+            partial[i0] = (int32_t)ec;
+            partial[i0 + cs] = (int32_t)per;
+            partial[i0 + 2 * cs] = (int32_t)n;
         } else {
-            *s0 += (int32_t)ec;
-            *s1 += (int32_t)per;
-            *s2 += (int32_t)n;
+            partial[i0] += (int32_t)ec;
+            partial[i0 + cs] += (int32_t)per;
+            partial[i0 + 2 * cs] += (int32_t)n;
         }
     }
 }
 
-template <typename T, int LM, bool ALIGNED, int PF>
+// The deltas of the VEC cells of `mid` into the LDS bins.
+// SINGLE (one pass over all levels): the bin of a cell is lam' itself
+// (hist[1..W] are the levels, hist[W+1] collects cells that never enter);
+// the halo lanes mask their bins to hist[0], which holds nothing else.
+// Otherwise bins are lam' - 1 for cells inside the window, and cells outside
+// it (and the halo lanes' cells) go to a per-lane scratch bin W + lane, so
+// that masses of out-of-window cells do not pile onto one LDS address.
+template <int VEC, bool SINGLE>
+__device__ __forceinline__ void emit_row(const uint32_t (&up)[VEC + 1], const uint32_t (&mid)[VEC + 1],
+                                         const uint32_t (&dn)[VEC + 1], uint32_t mask_or_off, uint32_t scratch,
+                                         const uint64_t *dl, uint64_t *hist) {
+#pragma unroll
+    for (int j = 1; j < VEC + 1; j += 2) {
+        const uint32_t self = mid[j], self1 = self + 0x00010001u;
+        // bit k of each half: neighbour k precedes the cell, k = NW N NE W E SW S SE
+        uint32_t acc = pk_lt(dn[j + 1], self);
+        acc = acc << 1 | pk_lt(dn[j], self);
+        acc = acc << 1 | pk_lt(dn[j - 1], self);
+        acc = acc << 1 | pk_lt(mid[j + 1], self);
+        acc = acc << 1 | pk_lt(mid[j - 1], self1);
+        acc = acc << 1 | pk_lt(up[j + 1], self1);
+        acc = acc << 1 | pk_lt(up[j], self1);
+        acc = acc << 1 | pk_lt(up[j - 1], self1);
+        uint32_t b0, b1;
+        if constexpr (SINGLE) {
+            const uint32_t sm = self & mask_or_off;  // 0 for the halo lanes
+            b0 = sm & 0xFFFFu;
+            b1 = sm >> 16;
+        } else {
+            b0 = min((self & 0xFFFFu) + mask_or_off, scratch);
+            b1 = min((self >> 16) + mask_or_off, scratch);
+        }
+        atomicAdd((unsigned long long *)&hist[b0], (unsigned long long)dl[acc & 0xFFu]);
+        atomicAdd((unsigned long long *)&hist[b1], (unsigned long long)dl[(acc >> 16) & 0xFFu]);
+    }
+}
+
+// rows [ra, rb) of one strip; three row buffers whose roles rotate with the
+// row index (PF is a multiple of 3, so the unrolled loop needs no copies)
+template <typename T, int LM, bool ALIGNED, int PF, bool SINGLE, typename TH>
+__device__ __forceinline__ void stream_run_2d(const T *__restrict__ data, int h, int64_t w,
+                                              const LevelArgs &lv, const TH &thr, int32_t lo, int W,
+                                              float cpass, const uint64_t *dl, uint64_t *hist, int64_t strip,
+                                              int ra, int rb, int lane, uint32_t mask_or_off, uint32_t scratch) {
+    static_assert(PF % 3 == 0, "PF must be a multiple of 3");
+    constexpr int VEC = Elem<T>::VEC;
+    constexpr int CE = 62 * VEC;  // cells owned per strip
+    const int64_t xs = strip * CE - VEC;  // first column of lane 0
+    const int64_t x0 = xs + (int64_t)lane * VEC;
+    const bool full = xs >= 0 && xs + 64 * VEC <= w;
+    auto clamp_row = [h](int r) { return r < 0 ? 0 : (r >= h ? h - 1 : r); };
+
+    uint32_t R[3][VEC + 1];  // R[r % 3] holds row r (relative to ra)
+    RawRow ring[PF];
+    {
+        RawRow r0, r1;
+        fetch_row<T, ALIGNED>(data, clamp_row(ra - 1), w, x0, r0);
+        fetch_row<T, ALIGNED>(data, ra, w, x0, r1);
+        // ring[k] holds row ra + 1 + k (rows past rb are clamped reloads)
+#pragma unroll
+        for (int k = 0; k < PF; ++k) {
+            const int rr = ra + 1 + k < rb ? ra + 1 + k : rb;
+            fetch_row<T, ALIGNED>(data, clamp_row(rr), w, x0, ring[k]);
+        }
+        convert_row<T, LM>(r0, ra - 1 >= 0, full, lv, thr, lo, W, cpass, R[2]);
+        convert_row<T, LM>(r1, true, full, lv, thr, lo, W, cpass, R[0]);
+    }
+    int r0 = ra;
+    // full blocks of PF rows: no conditional loads, so PF loads stay in flight
+    for (; r0 + PF <= rb; r0 += PF) {
+#pragma unroll
+        for (int k = 0; k < PF; ++k) {
+            const int r = r0 + k;  // current row (buffer k%3); ring[k] holds row r + 1
+            convert_row<T, LM>(ring[k], r + 1 < h, full, lv, thr, lo, W, cpass, R[(k + 1) % 3]);
+            const int nx = r + 1 + PF < rb ? r + 1 + PF : rb;
+            fetch_row<T, ALIGNED>(data, clamp_row(nx), w, x0, ring[k]);
+            emit_row<VEC, SINGLE>(R[(k + 2) % 3], R[k % 3], R[(k + 1) % 3], mask_or_off, scratch, dl, hist);
+        }
+    }
+    // remaining rows (fewer than PF); here r - ra = r0 - ra + k with r0 - ra
+    // a multiple of PF, so the buffer roles are those of k again
+#pragma unroll
+    for (int k = 0; k < PF; ++k) {
+        const int r = r0 + k;
+        if (r < rb) {
+            convert_row<T, LM>(ring[k], r + 1 < h, full, lv, thr, lo, W, cpass, R[(k + 1) % 3]);
+            emit_row<VEC, SINGLE>(R[(k + 2) % 3], R[k % 3], R[(k + 1) % 3], mask_or_off, scratch, dl, hist);
+        }
+    }
+}
+
+// rows [ra, rb) of one strip
+template <typename T, int LM, bool ALIGNED, int PF, typename TH>
+__device__ __forceinline__ void stream_run_2d(const T *__restrict__ data, int h, int64_t w,
+                                              const LevelArgs &lv, const TH &thr, int32_t lo, int W,
+                                              const uint64_t *dl, uint64_t *hist, int64_t strip, int ra,
+                                              int rb, int lane, uint32_t off, uint32_t scratch) {
+    constexpr int VEC = Elem<T>::VEC;
+    constexpr int CE = 62 * VEC;  // cells owned per strip
+    const int64_t xs = strip * CE - VEC;  // first column of lane 0
+    const int64_t x0 = xs + (int64_t)lane * VEC;
+    const bool full = xs >= 0 && xs + 64 * VEC <= w;
+    auto clamp_row = [h](int r) { return r < 0 ? 0 : (r >= h ? h - 1 : r); };
+
+    uint32_t up[VEC + 1], mid[VEC + 1], dn[VEC + 1];
+    RawRow ring[PF];
+    {
+        RawRow r0, r1;
+        fetch_row<T, ALIGNED>(data, clamp_row(ra - 1), w, x0, r0);
+        fetch_row<T, ALIGNED>(data, ra, w, x0, r1);
+        // ring[k] holds row ra + 1 + k (rows past rb are clamped reloads)
+#pragma unroll
+        for (int k = 0; k < PF; ++k) {
+            const int rr = ra + 1 + k < rb ? ra + 1 + k : rb;
+            fetch_row<T, ALIGNED>(data, clamp_row(rr), w, x0, ring[k]);
+        }
+        convert_row<T, LM>(r0, ra - 1 >= 0, full, lv, thr, lo, W, up);
+        convert_row<T, LM>(r1, true, full, lv, thr, lo, W, mid);
+    }
+    int r0 = ra;
+    // full blocks of PF rows: no conditional loads, so PF loads stay in flight
+    for (; r0 + PF <= rb; r0 += PF) {
+#pragma unroll
+        for (int k = 0; k < PF; ++k) {
+            const int r = r0 + k;  // current row; ring[k] holds row r + 1
+            convert_row<T, LM>(ring[k], r + 1 < h, full, lv, thr, lo, W, dn);
+            const int nx = r + 1 + PF < rb ? r + 1 + PF : rb;
+            fetch_row<T, ALIGNED>(data, clamp_row(nx), w, x0, ring[k]);
+            emit_row<VEC>(up, mid, dn, off, scratch, dl, hist);
+#pragma unroll
+            for (int j = 0; j < VEC + 1; ++j) {
+                up[j] = mid[j];
+                mid[j] = dn[j];
+            }
+        }
+    }
+    // remaining rows (fewer than PF)
+#pragma unroll
+    for (int k = 0; k < PF; ++k) {
+        const int r = r0 + k;
+        if (r < rb) {
+            convert_row<T, LM>(ring[k], r + 1 < h, full, lv, thr, lo, W, dn);
+            emit_row<VEC>(up, mid, dn, off, scratch, dl, hist);
+#pragma unroll
+            for (int j = 0; j < VEC + 1; ++j) {
+                up[j] = mid[j];
+                mid[j] = dn[j];
+            }
+        }
+    }
+}
+
+// Work split: the (strip, row) units of rows [row_lo, row_hi), strip-major,
+// are divided into equal contiguous ranges, one per wave (a range may run from
+// the end of one strip into the next).
+template <typename T, int LM, bool ALIGNED, int PF, bool SINGLE>
 __global__ void __launch_bounds__(256)
     ecc2d_stream(const T *__restrict__ data, int64_t h, int64_t w, LevelArgs lv, int32_t lo,
-                 int32_t hi, const uint64_t *__restrict__ delta_lut, int32_t *__restrict__ partial,
-                 int64_t row_lo, int64_t row_hi, int64_t n_segs, int64_t seg_rows, int64_t n_items,
-                 int accumulate) {
+                 int32_t hi, float cpass, const uint64_t *__restrict__ delta_lut, int32_t *__restrict__ partial,
+                 int64_t row_lo, int64_t row_hi, int accumulate) {
     constexpr int VEC = Elem<T>::VEC;
-    constexpr int CW = 64 * VEC;
+    constexpr int CE = 62 * VEC;
     extern __shared__ uint64_t smem[];
     __shared__ uint64_t dl[256];
 
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform: keeps loop control scalar
     const int W = hi - lo;
     const int L = lv.L;
+    // LDS: bins (W + 2 with SINGLE, else W + 64), then thresholds [lo-2, hi+1)
+    const int n_bins = SINGLE ? W + 2 : W + 64;
     uint64_t *hist = smem;
-    const float *thr = lv.thr;
-    if constexpr (LM == LM_AFFINE || LM == LM_SEARCH) {
-        if (L <= kThrLds) {
-            float *t = reinterpret_cast<float *>(smem + W);
-            for (int i = tid; i < L; i += 256) t[i] = lv.thr[i];
-            thr = t;
+    float *thr_s = reinterpret_cast<float *>(smem + n_bins);
+    constexpr bool kThr = LM == LM_AFFINE || LM == LM_SEARCH;
+    if (kThr)
+        for (int i = tid; i < W + 3; i += 256) {
+            int k = lo - 2 + i;
+            k = k < 0 ? 0 : (k >= L ? L - 1 : k);
+            thr_s[i] = lv.thr[k];
         }
-    }
     dl[tid] = delta_lut[tid];
-    for (int b = tid; b < W; b += 256) hist[b] = 0;
+    for (int b = tid; b < n_bins; b += 256) hist[b] = 0;
     __syncthreads();
 
     const int G = gridDim.x;
     const int wg = xcd_order(blockIdx.x, G);
     const int64_t gw = (int64_t)wg * kWavesPerWG + wave, NW = (int64_t)G * kWavesPerWG;
-    const int64_t i_beg = n_items * gw / NW, i_end = n_items * (gw + 1) / NW;
-
-    for (int64_t item = i_beg; item < i_end; ++item) {
-        const int64_t strip = item / n_segs, seg = item % n_segs;
-        const int64_t ra = row_lo + seg * seg_rows;
-        const int64_t rb = ra + seg_rows < row_hi ? ra + seg_rows : row_hi;
-        const int64_t xs = strip * CW, x0 = xs + (int64_t)lane * VEC;
-
-        uint32_t up[VEC + 2], mid[VEC + 2], dn[VEC + 2];
-        {
-            RawRow r0, r1;
-            fetch_row<T, ALIGNED>(data, ra - 1, h, w, xs, x0, lane, r0);
-            fetch_row<T, ALIGNED>(data, ra, h, w, xs, x0, lane, r1);
-            convert_row<T, LM>(r0, w, xs, x0, lane, lv, thr, up);
-            convert_row<T, LM>(r1, w, xs, x0, lane, lv, thr, mid);
-        }
-        RawRow ring[PF];
-#pragma unroll
-        for (int k = 0; k < PF; ++k) {
-            ring[k].valid = false;
-            if (ra + 1 + k <= rb) fetch_row<T, ALIGNED>(data, ra + 1 + k, h, w, xs, x0, lane, ring[k]);
-        }
-        for (int64_t r0 = ra; r0 < rb; r0 += PF) {
-#pragma unroll
-            for (int k = 0; k < PF; ++k) {
-                const int64_t r = r0 + k;  // current row; ring[k] holds row r + 1
-                if (r < rb) {
-                    convert_row<T, LM>(ring[k], w, xs, x0, lane, lv, thr, dn);
-                    if (r + 1 + PF <= rb)
-                        fetch_row<T, ALIGNED>(data, r + 1 + PF, h, w, xs, x0, lane, ring[k]);
-#pragma unroll
-                    for (int j = 1; j <= VEC; ++j) {
-                        const uint32_t p = mid[j];
-                        if (p - (uint32_t)lo < (uint32_t)W) {
-                            // a neighbour earlier in memory order precedes p on
-                            // a tie, a later one does not
-                            const uint32_t pat = (uint32_t)(up[j - 1] <= p) | (uint32_t)(up[j] <= p) << 1 |
-                                                 (uint32_t)(up[j + 1] <= p) << 2 | (uint32_t)(mid[j - 1] <= p) << 3 |
-                                                 (uint32_t)(mid[j + 1] < p) << 4 | (uint32_t)(dn[j - 1] < p) << 5 |
-                                                 (uint32_t)(dn[j] < p) << 6 | (uint32_t)(dn[j + 1] < p) << 7;
-                            atomicAdd((unsigned long long *)&hist[p - lo], (unsigned long long)dl[pat]);
-                        }
-                    }
-#pragma unroll
-                    for (int j = 0; j < VEC + 2; ++j) {
-                        up[j] = mid[j];
-                        mid[j] = dn[j];
-                    }
-                }
-            }
-        }
+    const int64_t H = row_hi - row_lo;
+    const int64_t n_strips = (w + CE - 1) / CE;
+    const int64_t units = n_strips * H;
+    const int64_t u_end = units * (gw + 1) / NW;
+    const bool halo_lane = lane == 0 || lane == 63;
+    const uint32_t mask_or_off = SINGLE ? (halo_lane ? 0u : 0xFFFFFFFFu) : (halo_lane ? 0x7FFFFFFEu : 0xFFFFFFFFu);
+    const uint32_t scratch = (uint32_t)(W + lane);
+    const ThrLds thr{thr_s, lo - 2};
+    for (int64_t u = units * gw / NW; u < u_end;) {
+        const int64_t strip = u / H, ra = u % H;
+        const int64_t rb = ra + (u_end - u) < H ? ra + (u_end - u) : H;
+        stream_run_2d<T, LM, ALIGNED, PF, SINGLE>(data, (int)h, w, lv, thr, lo, W, cpass, dl, hist, strip,
+                                                  (int)(row_lo + ra), (int)(row_lo + rb), lane, mask_or_off,
+                                                  scratch);
+        u += rb - ra;
     }
     __syncthreads();
-    drain_2d(hist, W, lo, L, partial + (int64_t)wg * 3 * L, accumulate == 0);
+    drain_2d(hist + (SINGLE ? 1 : 0), W, lo, L, G, wg, partial, accumulate == 0);
 }
 
 // ---------------------------------------------------------------------------
 // 3D (generic: every channel, table lookups over the 8 corner blocks)
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ void drain_3d(uint64_t *hist, uint32_t *hc, bool crease, int W, int lo,
-                                         int L, int32_t *slot, bool first) {
+                                         int L, int G, int wg, int32_t *__restrict__ partial, bool first) {
     for (int b = threadIdx.x; b < W; b += blockDim.x) {
         const uint64_t v = hist[b];
         hist[b] = 0;
@@ -308,17 +573,17 @@ __device__ __forceinline__ void drain_3d(uint64_t *hist, uint32_t *hc, bool crea
             cr = (int64_t)hc[b] - kCreaseBias3 * n;
             hc[b] = 0;
         }
-        int32_t *s = slot + lo + b;
+        const int64_t i0 = ((int64_t)(lo + b)) * G + wg, cs = (int64_t)L * G;
         if (first) {
-            s[0] = (int32_t)ec;
-            s[L] = (int32_t)cr;
-            s[2 * L] = (int32_t)surf;
-            s[3 * L] = (int32_t)n;
+            partial[i0] = (int32_t)ec;
+            partial[i0 + cs] = (int32_t)cr;
+            partial[i0 + 2 * cs] = (int32_t)surf;
+            partial[i0 + 3 * cs] = (int32_t)n;
         } else {
-            s[0] += (int32_t)ec;
-            s[L] += (int32_t)cr;
-            s[2 * L] += (int32_t)surf;
-            s[3 * L] += (int32_t)n;
+            partial[i0] += (int32_t)ec;
+            partial[i0 + cs] += (int32_t)cr;
+            partial[i0 + 2 * cs] += (int32_t)surf;
+            partial[i0 + 3 * cs] += (int32_t)n;
         }
     }
 }
@@ -349,7 +614,6 @@ __global__ void __launch_bounds__(256)
         hist[b] = 0;
         if (CREASE) hc[b] = 0;
     }
-    int32_t *slot = partial + (int64_t)wg * 4 * L;
     bool first = true;
     int since = 0;
     const int lx = t % TX, ly = t / TX;
@@ -365,7 +629,7 @@ __global__ void __launch_bounds__(256)
             const int64_t x = x0 - 1 + xx, y = y0 - 1 + yy, z = z0 - 1 + zz;
             uint32_t l = (uint32_t)L;
             if (x >= 0 && x < w && y >= 0 && y < h && z >= 0 && z < d)
-                l = level_of<T, LM>(data[(z * h + y) * w + x], lv, lv.thr);
+                l = level_of<T, LM>(data[(z * h + y) * w + x], lv, ThrGlobal{lv.thr});
             lam[zz][yy][xx] = (uint16_t)l;
         }
         __syncthreads();
@@ -427,67 +691,77 @@ __global__ void __launch_bounds__(256)
         }
         __syncthreads();
         if (++since >= flush_tiles) {
-            drain_3d(hist, hc, CREASE, W, lo, L, slot, first);
+            drain_3d(hist, hc, CREASE, W, lo, L, G, wg, partial, first);
             first = false;
             since = 0;
             __syncthreads();
         }
     }
-    drain_3d(hist, hc, CREASE, W, lo, L, slot, first);
+    drain_3d(hist, hc, CREASE, W, lo, L, G, wg, partial, first);
 }
 
 // ---------------------------------------------------------------------------
 // merge of per-workgroup partials and prefix scan over levels
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256)
-    ecc_reduce(const int32_t *__restrict__ partial, int G, int nch, int L, unsigned ch_mask,
-               int64_t *__restrict__ sums) {
-    const int ch = blockIdx.y;
-    if (!(ch_mask >> ch & 1)) return;
-    const int b = blockIdx.x * 256 + threadIdx.x;
-    if (b >= L) return;
-    const int groups = gridDim.z, z = blockIdx.z;
-    const int g0 = (int)((int64_t)G * z / groups), g1 = (int)((int64_t)G * (z + 1) / groups);
-    int64_t s = 0;
-    const int64_t stride = (int64_t)nch * L;
-    const int32_t *p = partial + (int64_t)ch * L + b;
-#pragma unroll 4
-    for (int g = g0; g < g1; ++g) s += p[g * stride];
-    sums[((int64_t)z * nch + ch) * L + b] = s;
-}
-
 struct OutPtrs {
     int64_t *p[4];
 };
 
+// One wave per (channel, level) sums the G workgroup partials of that bin
+// (coalesced reads, shuffle reduction).  The block that finishes last (ticket
+// on a counter that it then resets) takes the running sum over levels of
+// every requested channel and writes the caller's int64 curves.
 __global__ void __launch_bounds__(1024)
-    ecc_scan(const int64_t *__restrict__ sums, int groups, int nch, int L, OutPtrs out) {
+    ecc_merge(const int32_t *__restrict__ partial, int G, int nch, int L, OutPtrs out,
+              int64_t *__restrict__ totals, unsigned *__restrict__ counter) {
     __shared__ int64_t part[1024];
-    const int ch = blockIdx.x;
-    int64_t *dst = out.p[ch];
-    if (!dst) return;
-    const int t = threadIdx.x;
-    const int per = (L + 1023) / 1024;
-    const int beg = t * per, end = beg + per < L ? beg + per : L;
-    const int64_t gstride = (int64_t)nch * L;
-    const int64_t *src = sums + (int64_t)ch * L;
-    int64_t s = 0;
-    for (int i = beg; i < end; ++i)
-        for (int z = 0; z < groups; ++z) s += src[z * gstride + i];
-    part[t] = s;
+    __shared__ bool last;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int waves = blockDim.x >> 6;
+    const int64_t n_bins = (int64_t)nch * L;
+    for (int64_t bin = (int64_t)blockIdx.x * waves + wave; bin < n_bins; bin += (int64_t)gridDim.x * waves) {
+        const int ch = (int)(bin / L);
+        if (!out.p[ch]) continue;
+        const int32_t *src = partial + bin * G;
+        int64_t s = 0;
+        for (int g = lane; g < G; g += 64) s += src[g];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+        if (lane == 0) totals[bin] = s;
+    }
+    // publish this block's totals (release), take a ticket; the last block
+    // acquires everything the others published
     __syncthreads();
-    // Hillis-Steele inclusive scan of the 1024 chunk sums
-    for (int off = 1; off < 1024; off <<= 1) {
-        const int64_t v = t >= off ? part[t - off] : 0;
+    if (threadIdx.x == 0)
+        last = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT) == gridDim.x - 1;
+    __syncthreads();
+    if (!last) return;
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    const int t = threadIdx.x, nt = blockDim.x;
+    const int per = (L + nt - 1) / nt;
+    const int beg = t * per, end = beg + per < L ? beg + per : L;
+    for (int ch = 0; ch < nch; ++ch) {
+        int64_t *dst = out.p[ch];
+        if (!dst) continue;  // uniform
+        const int64_t *src = totals + (int64_t)ch * L;
+        int64_t s = 0;
+        for (int i = beg; i < end; ++i) s += src[i];
+        part[t] = s;
         __syncthreads();
-        part[t] += v;
+        for (int off = 1; off < nt; off <<= 1) {  // Hillis-Steele inclusive scan
+            const int64_t v = t >= off ? part[t - off] : 0;
+            __syncthreads();
+            part[t] += v;
+            __syncthreads();
+        }
+        int64_t run = part[t] - s;
+        for (int i = beg; i < end; ++i) {
+            run += src[i];
+            dst[i] = run;
+        }
         __syncthreads();
     }
-    int64_t run = part[t] - s;
-    for (int i = beg; i < end; ++i) {
-        for (int z = 0; z < groups; ++z) run += src[z * gstride + i];
-        dst[i] = run;
-    }
+    if (threadIdx.x == 0) *counter = 0u;  // ready for the next merge
 }
 
 // level index of every integer value from the thresholds (integer fields with
@@ -512,37 +786,50 @@ __global__ void ecc_level_lut(const float *__restrict__ thr, int L, int n_values
 // launchers
 // ---------------------------------------------------------------------------
 size_t lds_bytes_2d(int window, int L) {
-    return (size_t)window * 8 + (L <= kThrLds ? (size_t)L * 4 : 0);
+    (void)L;
+    return (size_t)(window + 64) * 8 + (size_t)(window + 3) * 4 + 2048;
 }
 size_t lds_bytes_3d(int window, bool want_crease) { return (size_t)window * (want_crease ? 12 : 8); }
 
-template <typename T, int LM, bool AL>
+// cells one workgroup may add to its LDS bins in a launch of `rows` rows
+static int64_t max_wg_cells_2d(int64_t rows, int64_t w, int vec, int grid) {
+    const int64_t ce = 62 * vec;
+    const int64_t units = ((w + ce - 1) / ce) * rows;
+    const int64_t NW = (int64_t)grid * kWavesPerWG;
+    return kWavesPerWG * ((units + NW - 1) / NW + 1) * ce;
+}
+
+template <typename T, int LM, bool AL, bool SINGLE>
 static int launch_2d_t(const Launch2D &a, hipStream_t s) {
-    constexpr int VEC = Elem<T>::VEC, PF = 4;
-    const int64_t n_strips = (a.w + 64 * VEC - 1) / (64 * VEC);
-    const int64_t rows = a.row_hi - a.row_lo;
-    const int64_t NW = (int64_t)a.grid * kWavesPerWG;
-    // rows per item: about one item per wave, at least 8 rows
-    int64_t seg = (rows * n_strips + NW - 1) / NW;
-    if (seg < 8) seg = 8;
-    if (seg > rows) seg = rows;
-    const int64_t n_segs = (rows + seg - 1) / seg;
-    const int64_t n_items = n_strips * n_segs;
-    // the packed LDS bins of one workgroup must not see more than kFlush2D cells
-    const int64_t items_per_wave = (n_items + NW - 1) / NW;
-    if (kWavesPerWG * items_per_wave * seg * 64 * VEC > kFlush2D) return (int)hipErrorInvalidValue;
+    constexpr int VEC = Elem<T>::VEC, PF = sizeof(T) == 1 ? 3 : 6;
     const int W = a.hi - a.lo;
-    hipLaunchKernelGGL((ecc2d_stream<T, LM, AL, PF>), dim3(a.grid), dim3(256),
-                       lds_bytes_2d(W, a.lv.L), s, (const T *)a.data, a.h, a.w, a.lv, a.lo, a.hi,
-                       a.delta_lut, a.partial, a.row_lo, a.row_hi, n_segs, seg, n_items,
-                       a.accumulate ? 1 : 0);
-    return (int)hipGetLastError();
+    // the packed LDS bins of one workgroup may see at most kFlush2D cells:
+    // split tall fields into row chunks that respect it (later chunks add to
+    // the partials of the first)
+    int64_t chunk = a.row_hi - a.row_lo;
+    while (chunk > 1 && max_wg_cells_2d(chunk, a.w, VEC, a.grid) > kFlush2D) chunk = (chunk + 1) / 2;
+    if (max_wg_cells_2d(chunk, a.w, VEC, a.grid) > kFlush2D) return (int)hipErrorInvalidValue;
+    // affine levels: the pass constant -t0/step + 1.5 - lo, rounded once
+    const float cpass = (float)(a.lv.u0d + 1.5 - a.lo);
+    const size_t lds = (size_t)(SINGLE ? W + 2 : W + 64) * 8 + (size_t)(W + 3) * 4;
+    for (int64_t r0 = a.row_lo; r0 < a.row_hi; r0 += chunk) {
+        const int64_t r1 = r0 + chunk < a.row_hi ? r0 + chunk : a.row_hi;
+        const bool acc = a.accumulate || r0 > a.row_lo;
+        hipLaunchKernelGGL((ecc2d_stream<T, LM, AL, PF, SINGLE>), dim3(a.grid), dim3(256), lds, s,
+                           (const T *)a.data, a.h, a.w, a.lv, a.lo, a.hi, cpass, a.delta_lut, a.partial, r0, r1,
+                           acc ? 1 : 0);
+        const int e = (int)hipGetLastError();
+        if (e) return e;
+    }
+    return 0;
 }
 
 template <typename T, int LM>
 static int launch_2d_al(const Launch2D &a, hipStream_t s) {
     const bool al = ((uintptr_t)a.data % 16 == 0) && (a.w * (int64_t)sizeof(T)) % 16 == 0;
-    return al ? launch_2d_t<T, LM, true>(a, s) : launch_2d_t<T, LM, false>(a, s);
+    const bool single = a.lo == 0 && a.hi == a.lv.L;
+    if (single) return al ? launch_2d_t<T, LM, true, true>(a, s) : launch_2d_t<T, LM, false, true>(a, s);
+    return al ? launch_2d_t<T, LM, true, false>(a, s) : launch_2d_t<T, LM, false, false>(a, s);
 }
 
 template <typename T>
@@ -602,17 +889,14 @@ int launch_3d(const Launch3D &a, void *stream) {
     }
 }
 
-int launch_reduce(const int32_t *partial, int grid, int nch, int L, unsigned ch_mask, int groups,
-                  int64_t *sums, void *stream) {
-    hipLaunchKernelGGL(ecc_reduce, dim3((L + 255) / 256, nch, groups), dim3(256), 0,
-                       (hipStream_t)stream, partial, grid, nch, L, ch_mask, sums);
-    return (int)hipGetLastError();
-}
-
-int launch_scan(const int64_t *sums, int groups, int nch, int L, int64_t *const out[4], void *stream) {
+int launch_merge(const int32_t *partial, int grid, int nch, int L, int64_t *const out[4],
+                 int64_t *totals, unsigned *counter, void *stream) {
     OutPtrs o;
     for (int c = 0; c < 4; ++c) o.p[c] = c < nch ? out[c] : nullptr;
-    hipLaunchKernelGGL(ecc_scan, dim3(nch), dim3(1024), 0, (hipStream_t)stream, sums, groups, nch, L, o);
+    const int64_t bins = (int64_t)nch * L;
+    const int blocks = (int)std::min<int64_t>(1024, (bins + 15) / 16);
+    hipLaunchKernelGGL(ecc_merge, dim3(blocks), dim3(1024), 0, (hipStream_t)stream, partial, grid, nch, L,
+                       o, totals, counter);
     return (int)hipGetLastError();
 }
 

@@ -37,7 +37,8 @@ struct ThrEntry {
     uint16_t *d_lut8 = nullptr;
     uint16_t *d_lut16 = nullptr;
     bool affine = false;
-    float t0 = 0.f, inv_step = 0.f, eps = 0.f;
+    float u0 = 0.f, inv_step = 0.f, eps = 0.f;
+    double u0d = 0.0;
 };
 
 struct Workspace {
@@ -66,6 +67,7 @@ struct ecc_context_s {
     void *ws_stream = nullptr;
     bool ws_used = false;
     ecc::BatchState *batch = nullptr;
+    void *d_counter = nullptr;  // merge kernel's completion ticket (kept at zero)
     // kernel timing (ecc_profile_enable)
     bool prof_on = false;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_events;

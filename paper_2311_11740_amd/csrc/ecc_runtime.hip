@@ -65,6 +65,8 @@ ecc_status validate_field(const ecc_field *f, const ecc_curves *c, FieldInfo *in
     if (f->ndim == 2 && c->volume) return fail(ECC_ERR_INVALID_ARG, "volume must be NULL for 2D fields");
     if (!c->ec && !c->perimeter && !c->area && !c->volume)
         return fail(ECC_ERR_INVALID_ARG, "no output curve requested");
+    for (int k = 0; k < f->ndim; ++k)
+        if (f->shape[k] >= (int64_t(1) << 31)) return fail(ECC_ERR_UNSUPPORTED, "a dimension of 2^31 or more");
     int64_t cells = 1;
     for (int k = 0; k < f->ndim; ++k) {
         if (f->shape[k] > (int64_t(1) << 40) / cells)
@@ -169,6 +171,7 @@ extern "C" ecc_status ecc_destroy(ecc_context ctx) {
         hipEventDestroy(pe.second);
     }
     ctx->ws.release();
+    if (ctx->d_counter) hipFree(ctx->d_counter);
     if (ctx->ws_event) hipEventDestroy(ctx->ws_event);
     destroy_batch_state(ctx);
     delete ctx;
@@ -260,23 +263,29 @@ ecc_status get_thresholds(ecc_context ctx, const float *thr, int L, int dtype, v
             free_thresholds(t);
             return hip_fail(e, "hipMemcpyAsync(thresholds)");
         }
-        // affine check: the level is estimated from u = (x - t0) / step; where
-        // the fractional part of u is farther than eps from an integer, floor(u)+1
-        // is the exact level.  eps bounds the thresholds' deviation from the
-        // grid t0 + l*step (in steps) plus the float32 rounding of u on the
-        // device, |u| <= L + 2: three roundings of relative size 2^-24.
+        // affine check: the level is estimated from u = fma(x, 1/step, -t0/step)
+        // in float32; where the fractional part of u is farther than eps from
+        // an integer, floor(u)+1 is the exact level.  eps/2 bounds the
+        // thresholds' deviation from the grid t0 + l*step (in steps) plus the
+        // rounding of u: 1/step and -t0/step are rounded once each and the
+        // fma once, which for |u| <= L + 2 moves u by at most
+        // (2 (L + 2) + |t0/step|) 2^-24 (with a 1 % margin).
         t->affine = false;
         if (L >= 2) {
             const double t0 = thr[0], step = ((double)thr[L - 1] - t0) / (L - 1);
             if (step > 0 && std::isfinite(step) && std::isfinite(t0) && std::isfinite((double)thr[L - 1])) {
                 double dev = 0;
                 for (int l = 0; l < L; ++l) dev = std::max(dev, std::fabs(thr[l] - (t0 + l * step)) / step);
-                const double round_u = (L + 2.0) * 3.1 * std::ldexp(1.0, -24);
+                const float inv_f = (float)(1.0 / step);
+                const double u0_d = -t0 * (double)inv_f;
+                const float u0_f = (float)u0_d;
+                const double round_u = (2.0 * (L + 2.0) + std::fabs(t0 / step) + 2.0) * 1.01 * std::ldexp(1.0, -24);
                 const double eps = 2.0 * (dev + round_u) + 1e-6;
                 if (eps < 0.25) {
                     t->affine = true;
-                    t->t0 = (float)t0;
-                    t->inv_step = (float)(1.0 / step);
+                    t->u0 = u0_f;
+                    t->u0d = u0_d;
+                    t->inv_step = inv_f;
                     t->eps = (float)eps;
                 }
             }
@@ -306,7 +315,8 @@ ecc_status level_args(ecc_context ctx, const ecc_field *f, const FieldInfo &fi, 
     lv->L = fi.L;
     lv->thr = nullptr;
     lv->lut = nullptr;
-    lv->t0 = 0.f;
+    lv->u0 = 0.f;
+    lv->u0d = 0.0;
     lv->inv_step = 0.f;
     lv->eps = 0.f;
     if (!f->thresholds) {
@@ -325,7 +335,8 @@ ecc_status level_args(ecc_context ctx, const ecc_field *f, const FieldInfo &fi, 
         lv->lut = te->d_lut16;
     } else if (te->affine) {
         lv->mode = LM_AFFINE;
-        lv->t0 = te->t0;
+        lv->u0 = te->u0;
+        lv->u0d = te->u0d;
         lv->inv_step = te->inv_step;
         lv->eps = te->eps;
     } else {
@@ -374,7 +385,7 @@ int pick_grid(ecc_context ctx, int64_t n_tiles, size_t lds_per_wg) {
 static int wg_per_cu_default() {
     static int v = [] {
         const char *e = std::getenv("ECC_WG_PER_CU");
-        int x = e ? std::atoi(e) : 2;
+        int x = e ? std::atoi(e) : 4;
         return x < 1 ? 1 : (x > 8 ? 8 : x);
     }();
     return v;
@@ -382,20 +393,17 @@ static int wg_per_cu_default() {
 
 ecc_status merge_and_scan(ecc_context ctx, int grid, int nch, int L, int64_t *const outs[4],
                           void *stream) {
-    unsigned mask = 0;
-    for (int q = 0; q < nch; ++q)
-        if (outs[q]) mask |= 1u << q;
-    // stage 1 sums groups of workgroup partials in parallel, stage 2 (in the
-    // scan kernel) adds the group sums and takes the running sum over levels
-    int gs = std::max(1, std::min(64, grid / 8));
-    while (gs > 1 && (int64_t)gs * L > (1 << 17)) gs >>= 1;
-    ecc_status s = grow(ctx, ctx->ws.totals, (size_t)gs * nch * L * sizeof(int64_t), "totals");
+    ecc_status s = grow(ctx, ctx->ws.totals, (size_t)nch * L * sizeof(int64_t), "totals");
     if (s != ECC_OK) return s;
-    int64_t *totals = (int64_t *)ctx->ws.totals.ptr;
-    int e = launch_reduce((const int32_t *)ctx->ws.partial.ptr, grid, nch, L, mask, gs, totals, stream);
-    if (e) return hip_fail(e, "reduce kernel launch");
-    e = launch_scan(totals, gs, nch, L, outs, stream);
-    if (e) return hip_fail(e, "scan kernel launch");
+    if (!ctx->d_counter) {
+        int e = (int)hipMalloc(&ctx->d_counter, 256);
+        if (e) return fail(ECC_ERR_OUT_OF_MEMORY, "hipMalloc(counter) failed");
+        e = (int)hipMemset(ctx->d_counter, 0, 256);
+        if (e) return hip_fail(e, "hipMemset(counter)");
+    }
+    int e = launch_merge((const int32_t *)ctx->ws.partial.ptr, grid, nch, L, outs,
+                         (int64_t *)ctx->ws.totals.ptr, (unsigned *)ctx->d_counter, stream);
+    if (e) return hip_fail(e, "merge kernel launch");
     return ECC_OK;
 }
 
@@ -412,7 +420,7 @@ ecc_status compute_one(ecc_context ctx, const ecc_field *f, const FieldInfo &fi,
     int grid;
     if (fi.ndim == 2) {
         const int vec = vec_2d(fi.dtype);
-        const int64_t strips = (fi.w + 64 * vec - 1) / (64 * vec);
+        const int64_t strips = (fi.w + 62 * vec - 1) / (62 * vec);
         grid = (int)std::min<int64_t>((int64_t)ctx->n_cu * wg_per_cu_default(),
                                       std::max<int64_t>(1, (strips * fi.h + 31) / 32));
         if (grid >= 8) grid -= grid % 8;
@@ -427,24 +435,15 @@ ecc_status compute_one(ecc_context ctx, const ecc_field *f, const FieldInfo &fi,
     for (int lo = 0; lo < L; lo += win) {
         const int hi = std::min(L, lo + win);
         if (fi.ndim == 2) {
-            // the packed LDS bins of a workgroup hold at most kFlush2D cells:
-            // split tall fields into row chunks that respect it
-            const int vec = vec_2d(fi.dtype);
-            const int64_t strips = (fi.w + 64 * vec - 1) / (64 * vec);
-            const int64_t cap = (int64_t)grid * (kFlush2D / 4);  // cells per launch
-            int64_t chunk = std::max<int64_t>(1, cap / (strips * 64 * vec));
-            for (int64_t r0 = 0; r0 < fi.h; r0 += chunk) {
-                const int64_t r1 = std::min(fi.h, r0 + chunk);
-                int slot = -1;
-                s = prof_begin(ctx, stream, &slot);
-                if (s != ECC_OK) return s;
-                Launch2D a{f->data, fi.dtype, fi.h, fi.w, lv, lo, hi, ctx->d_delta2[k], partial, grid,
-                           r0, r1, r0 > 0};
-                int e = launch_2d(a, stream);
-                if (e) return hip_fail(e, "2D kernel launch");
-                s = prof_end(ctx, stream, slot);
-                if (s != ECC_OK) return s;
-            }
+            int slot = -1;
+            s = prof_begin(ctx, stream, &slot);
+            if (s != ECC_OK) return s;
+            Launch2D a{f->data, fi.dtype, fi.h, fi.w, lv, lo, hi, ctx->d_delta2[k], partial, grid,
+                       0, fi.h, false};
+            int e = launch_2d(a, stream);
+            if (e) return hip_fail(e, "2D kernel launch");
+            s = prof_end(ctx, stream, slot);
+            if (s != ECC_OK) return s;
         } else {
             int slot = -1;
             s = prof_begin(ctx, stream, &slot);
