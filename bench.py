@@ -130,7 +130,7 @@ def measure(ctx, name, steps, warmup, copies, with_cpu):
     cells = spec.data.size
     elem = spec.data.dtype.itemsize
     value = cells / (r["ms_per_step"] / 1e3) / 1e9
-    kernel = "ecc2d_stream" if spec.data.ndim == 2 else "ecc3d_tile"
+    kernel = "ecc2d_stream" if spec.data.ndim == 2 else "ecc3d_stream"
     alg_bytes = cells * elem  # the field-reading kernel reads every cell once per step
     launches_per_step = r["kernel_launches"] / max(1, STEPS_CTX["steps"])
     achieved = alg_bytes / (r["kernel_ms_per_step"] / 1e3) / 1e9

@@ -85,6 +85,9 @@ struct Launch3D {
     int32_t *partial;     // device, [4][L][grid]
     int grid;
     bool want_crease;
+    // z-marching kernel (no crease channel): its two per-pattern tables, else NULL
+    const uint32_t *zm_tables;
+    bool conn6;
 };
 
 // device-side launchers (ecc_kernels.hip); return a hipError_t as int
@@ -100,6 +103,11 @@ int launch_level_lut(const float *thr, int L, int n_values, uint16_t *lut, void 
 // tile geometry used by the single-field kernels
 constexpr int kWavesPerWG = 4;
 constexpr int kTile3DX = 64, kTile3DY = 4, kTile3DZ = 16;
+// z-marching 3D kernel: strips of 64 lanes x 4 cells, blocks of kZmTY rows
+constexpr int kZmTY = 4, kZmStripX = 256, kZmCellsPerUnit = kZmStripX * kZmTY;
+int zmarch_3d_columns(int64_t h, int64_t w);
+// whether one z-plane per wave keeps the workgroup bins within kFlush3D
+bool zmarch_3d_fits(int64_t h, int64_t w, int grid);
 size_t lds_bytes_2d(int window, int L);
 size_t lds_bytes_3d(int window, bool want_crease);
 

@@ -275,6 +275,9 @@ __device__ __forceinline__ void convert_row(const RawRow &raw, bool row_ok, bool
     const int base = lo - 1;
     if constexpr (LM == LM_AFFINE) {
         const float hme = 0.5f - lv.eps;
+        // estimates clamp to [0, W + 1]; in the first pass to [1, W + 1],
+        // since every value at or below t0 (however far) has level 0
+        const float mlo = lo == 0 ? kMagic + 1.0f : kMagic;
         const float mhi = kMagic + (float)never;
         bool nr[VEC];
         bool any = false;
@@ -284,7 +287,7 @@ __device__ __forceinline__ void convert_row(const RawRow &raw, bool row_ok, bool
             const float m = y + kMagic;
             const float r = y - (m - kMagic);
             nr[i] = !(__builtin_fabsf(r) <= hme);  // also NaN and +-inf
-            lam[i] = __float_as_uint(__builtin_amdgcn_fmed3f(m, kMagic, mhi));
+            lam[i] = __float_as_uint(__builtin_amdgcn_fmed3f(m, mlo, mhi));
             any |= nr[i];
         }
         if (__any(any)) {  // rare: a value within eps of a threshold
@@ -557,7 +560,7 @@ __global__ void __launch_bounds__(256)
 }
 
 // ---------------------------------------------------------------------------
-// 3D (generic: every channel, table lookups over the 8 corner blocks)
+// 3D bins -> partials
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ void drain_3d(uint64_t *hist, uint32_t *hc, bool crease, int W, int lo,
                                          int L, int G, int wg, int32_t *__restrict__ partial, bool first) {
@@ -588,6 +591,368 @@ __device__ __forceinline__ void drain_3d(uint64_t *hist, uint32_t *hc, bool crea
     }
 }
 
+// ---------------------------------------------------------------------------
+// 3D: slab decomposition, z-marching waves
+// ---------------------------------------------------------------------------
+// The closure of the active voxels splits into lattice cells that lie in a
+// z-plane Z (vertices, x/y edges, xy faces) and cells that span a voxel layer
+// z (z edges, xz/yz faces, voxels).  A cell in plane Z is present exactly when
+// the 2D cell under it is present in the image min(lam[Z-1], lam[Z]) (the
+// "min image"); a cell spanning layer z when its 2D counterpart is present in
+// layer z, with dimension one higher.  Hence for the 26-connected EC
+//   chi26 = sum_Z chi8(min image Z) - sum_z chi8(layer z),
+// and dually, for the 6-connected complex (cells = voxels),
+//   chi6 = sum_z chi4(layer z) - sum_Z chi4(max(lam[Z-1], lam[Z])).
+// So every voxel needs two 2D 8-neighbour patterns: its own layer's, and the
+// one of the min (max) image between its layer and the next.  The 2D event of
+// a min-image pixel happens at the level of the voxel that enters first of
+// the two (last, for the max image), so it is added to that voxel's event:
+// one LDS atomic per voxel.  The surface adds the two vertical faces, the
+// volume is the count.  (The crease measure needs the 3x3x3 neighbourhood and
+// is left to the generic kernel below.)
+//
+// A wave owns TY rows of a strip of 64*VEC columns and marches z, holding the
+// level indices of planes z-1, z, z+1 (TY+2 rows each, packed as in 2D) in
+// three buffers that rotate with z.  The cells left and right of the strip
+// come from one extra unconditional element load per lane and row.
+template <typename T>
+struct Elem3 {
+    static constexpr int VEC = 4;                    // cells per lane
+    static constexpr int WORDS = 4 * sizeof(T) / 4;  // raw dwords per lane and row
+};
+
+struct RawRow3 {
+    uint32_t w[4];
+    uint32_t halo;  // lane 0: element left of the strip; lane 63: right of it
+};
+
+template <typename T>
+__device__ __forceinline__ uint32_t elem_bits(const T *p) {
+    if constexpr (sizeof(T) == 4)
+        return __float_as_uint(*p);
+    else
+        return (uint32_t)*p;
+}
+
+template <typename T>
+__device__ __forceinline__ uint32_t elem3(const RawRow3 &r, int i) {
+    if constexpr (sizeof(T) == 1) return (r.w[0] >> (8 * i)) & 0xFFu;
+    else if constexpr (sizeof(T) == 2) return (r.w[i >> 1] >> (16 * (i & 1))) & 0xFFFFu;
+    else return r.w[i];
+}
+
+// row y of plane z (both clamped into the field by the caller); unconditional
+template <typename T, bool ALIGNED>
+__device__ __forceinline__ void fetch_row3(const T *__restrict__ data, int64_t h, int64_t w, int z, int y,
+                                           int64_t xs, int64_t x0, int lane, RawRow3 &raw) {
+    constexpr int VEC = Elem3<T>::VEC;
+    const T *row = data + ((int64_t)z * h + y) * w;
+    if constexpr (ALIGNED) {  // whole 4-cell groups: inside or outside the row
+        const int64_t xc = x0 < w ? x0 : 0;
+        if constexpr (sizeof(T) == 1) {
+            raw.w[0] = __builtin_nontemporal_load(reinterpret_cast<const uint32_t *>(row + xc));
+        } else if constexpr (sizeof(T) == 2) {
+            typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+            const u32x2 q = __builtin_nontemporal_load(reinterpret_cast<const u32x2 *>(row + xc));
+            raw.w[0] = q.x; raw.w[1] = q.y;
+        } else {
+            const u32x4 q = __builtin_nontemporal_load(reinterpret_cast<const u32x4 *>(row + xc));
+            raw.w[0] = q.x; raw.w[1] = q.y; raw.w[2] = q.z; raw.w[3] = q.w;
+        }
+    } else {
+        raw.w[0] = raw.w[1] = raw.w[2] = raw.w[3] = 0;
+#pragma unroll
+        for (int i = 0; i < VEC; ++i) {
+            const int64_t x = x0 + i;
+            const uint32_t b = elem_bits(row + (x < w ? x : 0));
+            constexpr int per = 4 / sizeof(T);
+            raw.w[i / per] |= (x < w ? b : 0u) << (8 * sizeof(T) * (i % per));
+        }
+    }
+    int64_t hx = lane == 0 ? xs - 1 : (lane == 63 ? xs + 64 * VEC : x0);
+    hx = hx < 0 ? 0 : (hx >= w ? w - 1 : hx);
+    raw.halo = elem_bits(row + hx);
+}
+
+template <typename T, int LM, typename TH>
+__device__ __forceinline__ uint32_t level3(uint32_t bits, const LevelArgs &lv, const TH &thr, int lo, int W,
+                                           float cpass) {
+    const int base = lo - 1;
+    const uint32_t never = (uint32_t)(W + 1);
+    if constexpr (LM == LM_AFFINE) {
+        const float x = __uint_as_float(bits);
+        const float y = __builtin_fmaf(x, lv.inv_step, cpass);
+        const float m = y + kMagic;
+        const float r = y - (m - kMagic);
+        // clamped estimate of lam' (at least 1 in the first pass: values at
+        // or below t0 have level 0)
+        const float mlo = lo == 0 ? kMagic + 1.0f : kMagic;
+        uint32_t l = __float_as_uint(__builtin_amdgcn_fmed3f(m, mlo, kMagic + (float)never)) - kMagicBits;
+        if (!(__builtin_fabsf(r) <= 0.5f - lv.eps)) {  // near a threshold (or NaN / inf)
+            const int k = (int)l;
+            if (k >= 0 && k <= W + 1) {
+                const int g0 = k + base < 0 ? 0 : k + base;
+                const int g = (int)level_settle(x, (uint32_t)g0, lv.L, thr);
+                l = (uint32_t)min(max(g - base, 0), (int)never);
+            }
+        }
+        return l;
+    } else if constexpr (LM == LM_SEARCH) {
+        return level_search_window(__uint_as_float(bits), lo, lo + W, thr);
+    } else {
+        const int l = (int)level_of<T, LM>(as_value<T>(bits), lv, thr);
+        return (uint32_t)min(max(l - base, 0), (int)never);
+    }
+}
+
+// packed level pairs of one row (P[i] = (lam'[i-1], lam'[i]) with the strip
+// neighbours at both ends); rows outside the field are "never"
+template <typename T, int LM, typename TH>
+__device__ __forceinline__ void convert_row3(const RawRow3 &raw, bool row_ok, int64_t w, int64_t xs, int64_t x0,
+                                             int lane, const LevelArgs &lv, const TH &thr, int lo, int W,
+                                             float cpass, uint32_t (&P)[Elem3<T>::VEC + 1]) {
+    constexpr int VEC = Elem3<T>::VEC;
+    const uint32_t never = (uint32_t)(W + 1);
+    if (!row_ok) {  // uniform
+#pragma unroll
+        for (int i = 0; i <= VEC; ++i) P[i] = never | never << 16;
+        return;
+    }
+    uint32_t lam[VEC];
+#pragma unroll
+    for (int i = 0; i < VEC; ++i)
+        lam[i] = x0 + i < w ? level3<T, LM>(elem3<T>(raw, i), lv, thr, lo, W, cpass) : never;
+    const uint32_t hl = level3<T, LM>(raw.halo, lv, thr, lo, W, cpass);
+    uint32_t left = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)lam[VEC - 1], 0x138, 0xf, 0xf, false);
+    uint32_t right = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)lam[0], 0x130, 0xf, 0xf, false);
+    if (lane == 0) left = xs > 0 ? hl : never;
+    if (lane == 63) right = xs + 64 * VEC < w ? hl : never;
+    P[0] = pack_lo16(left, lam[0]);
+#pragma unroll
+    for (int i = 1; i < VEC; ++i) P[i] = pack_lo16(lam[i - 1], lam[i]);
+    P[VEC] = pack_lo16(lam[VEC - 1], right);
+}
+
+// 8-neighbour "entered before" pattern of the two cells of pair j (low / high
+// half), rows u (above), m (current), d (below)
+template <int VEC>
+__device__ __forceinline__ uint32_t pattern_pair(const uint32_t (&u)[VEC + 1], const uint32_t (&m)[VEC + 1],
+                                                 const uint32_t (&d)[VEC + 1], int j) {
+    const uint32_t self = m[j], self1 = self + 0x00010001u;
+    uint32_t acc = pk_lt(d[j + 1], self);
+    acc = acc << 1 | pk_lt(d[j], self);
+    acc = acc << 1 | pk_lt(d[j - 1], self);
+    acc = acc << 1 | pk_lt(m[j + 1], self);
+    acc = acc << 1 | pk_lt(m[j - 1], self1);
+    acc = acc << 1 | pk_lt(u[j + 1], self1);
+    acc = acc << 1 | pk_lt(u[j], self1);
+    acc = acc << 1 | pk_lt(u[j - 1], self1);
+    return acc;
+}
+
+// per-pixel image of two planes: min (26-C) or max (6-C), packed
+template <bool MAXIMG>
+__device__ __forceinline__ uint32_t pk_merge(uint32_t a, uint32_t b) {
+    const u16x2 x = __builtin_bit_cast(u16x2, a), y = __builtin_bit_cast(u16x2, b);
+    if constexpr (MAXIMG)
+        return __builtin_bit_cast(uint32_t, __builtin_elementwise_max(x, y));
+    else
+        return __builtin_bit_cast(uint32_t, __builtin_elementwise_min(x, y));
+}
+
+// LDS tables (set up by the host, 256 entries each):
+//   tl[p]: layer term of a voxel with layer pattern p, packed as the low
+//          word of a 3D bin: (+-EC of the 2D cell) + 7 + (perimeter + 8) << 22
+//   tm[p]: 2D EC delta of an image pixel with pattern p, sign included
+// A voxel's low word is tl[p_layer] + (its share of the two images' deltas)
+// - 2 * (vertical neighbours that entered before it) << 22.
+template <typename T, int LM, bool ALIGNED, bool MAXIMG, bool SINGLE, int TY, typename TH>
+struct March3D {
+    static constexpr int VEC = Elem3<T>::VEC;
+    static constexpr int NR = TY + 2;
+    const T *__restrict__ data;
+    int d;
+    int64_t h, w;
+    const LevelArgs &lv;
+    const TH &thr;
+    int lo, W;
+    float cpass;
+    const uint32_t *tl;
+    const int32_t *tm;
+    uint64_t *hist;
+    int64_t xs, x0;
+    int y0, zb, lane;
+    uint32_t scratch;
+
+    uint32_t R[3][NR][VEC + 1];  // level planes; R[(z - za + 1) % 3] holds plane z
+    int32_t E[TY][VEC];          // image delta of the pixel below each voxel of the current plane
+    RawRow3 ring[3][NR];         // raw rows of upcoming planes; ring[(z - za) % 3] holds plane z + 1
+
+    __device__ __forceinline__ int clampz(int z) const { return z < 0 ? 0 : (z >= d ? d - 1 : z); }
+    __device__ __forceinline__ int clampy(int y) const { return y < 0 ? 0 : (y >= (int)h ? (int)h - 1 : y); }
+    __device__ __forceinline__ bool row_ok(int z, int y) const { return z >= 0 && z < d && y >= 0 && y < (int)h; }
+
+    __device__ __forceinline__ void fetch_plane(int z, RawRow3 (&dst)[NR]) {
+#pragma unroll
+        for (int r = 0; r < NR; ++r) fetch_row3<T, ALIGNED>(data, h, w, clampz(z), clampy(y0 - 1 + r), xs, x0, lane, dst[r]);
+    }
+    __device__ __forceinline__ void convert_plane(int z, const RawRow3 (&src)[NR], uint32_t (&dst)[NR][VEC + 1]) {
+#pragma unroll
+        for (int r = 0; r < NR; ++r)
+            convert_row3<T, LM>(src[r], row_ok(z, y0 - 1 + r), w, xs, x0, lane, lv, thr, lo, W, cpass, dst[r]);
+    }
+    __device__ __forceinline__ void image(const uint32_t (&a)[NR][VEC + 1], const uint32_t (&b)[NR][VEC + 1],
+                                          uint32_t (&m)[NR][VEC + 1]) {
+#pragma unroll
+        for (int r = 0; r < NR; ++r)
+#pragma unroll
+            for (int i = 0; i <= VEC; ++i) m[r][i] = pk_merge<MAXIMG>(a[r][i], b[r][i]);
+    }
+
+    // planes za-1 and za converted, E of the image between them, planes
+    // za+1 .. za+3 in flight
+    __device__ __forceinline__ void prologue(int za) {
+        {
+            RawRow3 a[NR], b[NR];
+            fetch_plane(za - 1, a);
+            fetch_plane(za, b);
+#pragma unroll
+            for (int k = 0; k < 3; ++k) fetch_plane(za + 1 + k < zb ? za + 1 + k : zb, ring[k]);
+            convert_plane(za - 1, a, R[0]);
+            convert_plane(za, b, R[1]);
+        }
+        uint32_t M[NR][VEC + 1];
+        image(R[0], R[1], M);
+#pragma unroll
+        for (int t = 0; t < TY; ++t)
+#pragma unroll
+            for (int j = 1; j < VEC + 1; j += 2) {
+                const uint32_t pm = pattern_pair<VEC>(M[t], M[t + 1], M[t + 2], j);
+                E[t][j - 1] = tm[pm & 0xFFu];
+                E[t][j] = tm[(pm >> 16) & 0xFFu];
+            }
+    }
+
+    // voxels of plane z, with K = (z - za) % 3
+    template <int K>
+    __device__ __forceinline__ void step(int z) {
+        uint32_t(&Pp)[NR][VEC + 1] = R[K];
+        uint32_t(&Pc)[NR][VEC + 1] = R[(K + 1) % 3];
+        uint32_t(&Pn)[NR][VEC + 1] = R[(K + 2) % 3];
+        convert_plane(z + 1, ring[K], Pn);
+        fetch_plane(z + 4 < zb ? z + 4 : zb, ring[K]);
+        uint32_t M[NR][VEC + 1];
+        image(Pc, Pn, M);
+#pragma unroll
+        for (int t = 0; t < TY; ++t) {
+#pragma unroll
+            for (int j = 1; j < VEC + 1; j += 2) {
+                const uint32_t self = Pc[t + 1][j], self1 = self + 0x00010001u;
+                const uint32_t pl = pattern_pair<VEC>(Pc[t], Pc[t + 1], Pc[t + 2], j);
+                const uint32_t pm = pattern_pair<VEC>(M[t], M[t + 1], M[t + 2], j);
+                // vertical neighbours: the one below (z-1) precedes on ties,
+                // the one above (z+1) does not
+                const uint32_t below = pk_lt(Pp[t + 1][j], self1);
+                const uint32_t above = pk_lt(Pn[t + 1][j], self);
+                const int32_t en0 = tm[pm & 0xFFu], en1 = tm[(pm >> 16) & 0xFFu];
+                // an image pixel's event goes to the voxel of its pair that
+                // enters first (min image) or last (max image)
+                const uint32_t tb = MAXIMG ? below : below ^ 0x00010001u;
+                const uint32_t ta = MAXIMG ? above : above ^ 0x00010001u;
+                const uint32_t nb = below + above;  // per half: vertical neighbours already in
+                const uint32_t lo0 = tl[pl & 0xFFu] + (uint32_t)((tb & 1u) ? E[t][j - 1] : 0) +
+                                     (uint32_t)((ta & 1u) ? en0 : 0) - ((nb & 0xFFFFu) << 23);
+                const uint32_t lo1 = tl[(pl >> 16) & 0xFFu] + (uint32_t)((tb >> 16) ? E[t][j] : 0) +
+                                     (uint32_t)((ta >> 16) ? en1 : 0) - ((nb >> 16) << 23);
+                E[t][j - 1] = en0;
+                E[t][j] = en1;
+                uint32_t b0, b1;
+                if constexpr (SINGLE) {
+                    b0 = self & 0xFFFFu;
+                    b1 = self >> 16;
+                } else {
+                    b0 = min((self & 0xFFFFu) - 1u, scratch);
+                    b1 = min((self >> 16) - 1u, scratch);
+                }
+                constexpr uint64_t cnt = 1ull << kShiftCnt3;
+                atomicAdd((unsigned long long *)&hist[b0], (unsigned long long)(cnt | lo0));
+                atomicAdd((unsigned long long *)&hist[b1], (unsigned long long)(cnt | lo1));
+            }
+        }
+    }
+
+    __device__ __forceinline__ void run(int za) {
+        prologue(za);
+        int z = za;
+        for (; z + 3 <= zb; z += 3) {
+            step<0>(z);
+            step<1>(z + 1);
+            step<2>(z + 2);
+        }
+        if (z < zb) step<0>(z);
+        if (z + 1 < zb) step<1>(z + 1);
+    }
+};
+
+// Work split: units (column, z) with column = (strip, block of TY rows), z
+// fastest, in equal contiguous ranges per wave.
+template <typename T, int LM, bool ALIGNED, bool MAXIMG, bool SINGLE, int TY>
+__global__ void __launch_bounds__(256)
+    ecc3d_stream(const T *__restrict__ data, int64_t d, int64_t h, int64_t w, LevelArgs lv, int32_t lo,
+                 int32_t hi, float cpass, const uint32_t *__restrict__ tables, int32_t *__restrict__ partial,
+                 int64_t z_lo, int64_t z_hi, int accumulate) {
+    constexpr int VEC = Elem3<T>::VEC;
+    extern __shared__ uint64_t smem[];
+    __shared__ uint32_t tl[256];
+    __shared__ int32_t tm[256];
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int W = hi - lo;
+    const int L = lv.L;
+    const int n_bins = SINGLE ? W + 2 : W + 64;
+    uint64_t *hist = smem;
+    float *thr_s = reinterpret_cast<float *>(smem + n_bins);
+    constexpr bool kThr = LM == LM_AFFINE || LM == LM_SEARCH;
+    if (kThr)
+        for (int i = tid; i < W + 3; i += 256) {
+            int k = lo - 2 + i;
+            k = k < 0 ? 0 : (k >= L ? L - 1 : k);
+            thr_s[i] = lv.thr[k];
+        }
+    tl[tid] = tables[tid];
+    tm[tid] = (int32_t)tables[256 + tid];
+    for (int b = tid; b < n_bins; b += 256) hist[b] = 0;
+    __syncthreads();
+
+    const int G = gridDim.x;
+    const int wg = xcd_order(blockIdx.x, G);
+    const int64_t gw = (int64_t)wg * kWavesPerWG + wave, NW = (int64_t)G * kWavesPerWG;
+    const int64_t D = z_hi - z_lo;
+    const int64_t n_strips = (w + 64 * VEC - 1) / (64 * VEC);
+    const int64_t n_yb = (h + TY - 1) / TY;
+    const int64_t units = n_strips * n_yb * D;
+    const int64_t u_end = units * (gw + 1) / NW;
+    const uint32_t scratch = (uint32_t)(W + lane);
+    const ThrLds thr{thr_s, lo - 2};
+    for (int64_t u = units * gw / NW; u < u_end;) {
+        const int64_t col = u / D, za = u % D;
+        const int64_t zb = za + (u_end - u) < D ? za + (u_end - u) : D;
+        const int64_t strip = col % n_strips, yb = col / n_strips;
+        const int64_t xs = strip * 64 * VEC;
+        March3D<T, LM, ALIGNED, MAXIMG, SINGLE, TY, ThrLds> m{data, (int)d, h, w, lv, thr, lo, W, cpass, tl, tm,
+                                                               hist, xs, xs + (int64_t)lane * VEC, (int)(yb * TY),
+                                                               (int)(z_lo + zb), lane, scratch};
+        m.run((int)(z_lo + za));
+        u += zb - za;
+    }
+    __syncthreads();
+    drain_3d(hist + (SINGLE ? 1 : 0), nullptr, false, W, lo, L, G, wg, partial, accumulate == 0);
+}
+
+
+// ---------------------------------------------------------------------------
+// 3D (generic: every channel, table lookups over the 8 corner blocks)
+// ---------------------------------------------------------------------------
 template <typename T, int LM, bool CREASE>
 __global__ void __launch_bounds__(256)
     ecc3d_tile(const T *__restrict__ data, int64_t d, int64_t h, int64_t w, LevelArgs lv,
@@ -865,8 +1230,56 @@ static int launch_3d_t(const Launch3D &a, hipStream_t s) {
     return (int)hipGetLastError();
 }
 
+// cells one workgroup of the z-marching kernel may add to its bins
+static int64_t max_wg_cells_3d(int64_t cols, int64_t depth, int grid) {
+    const int64_t NW = (int64_t)grid * kWavesPerWG;
+    return kWavesPerWG * ((cols * depth + NW - 1) / NW) * kZmCellsPerUnit;
+}
+
+int zmarch_3d_columns(int64_t h, int64_t w) {
+    const int64_t n = ((w + kZmStripX - 1) / kZmStripX) * ((h + kZmTY - 1) / kZmTY);
+    return n > INT32_MAX ? INT32_MAX : (int)n;
+}
+
+bool zmarch_3d_fits(int64_t h, int64_t w, int grid) {
+    return max_wg_cells_3d(zmarch_3d_columns(h, w), 1, grid) <= kFlush3D;
+}
+
+template <typename T, int LM, bool AL, bool MAXIMG, bool SINGLE>
+static int launch_zm_t(const Launch3D &a, hipStream_t s) {
+    constexpr bool kThr = LM == LM_AFFINE || LM == LM_SEARCH;
+    const int W = a.hi - a.lo;
+    const int64_t cols = zmarch_3d_columns(a.h, a.w);
+    // bound the cells per workgroup between drains by splitting z
+    int64_t chunk = a.d;
+    while (chunk > 1 && max_wg_cells_3d(cols, chunk, a.grid) > kFlush3D) chunk = (chunk + 1) / 2;
+    if (max_wg_cells_3d(cols, chunk, a.grid) > kFlush3D) return (int)hipErrorInvalidValue;
+    const float cpass = (float)(a.lv.u0d + 1.5 - a.lo);
+    const size_t lds = (size_t)(SINGLE ? W + 2 : W + 64) * 8 + (kThr ? (size_t)(W + 3) * 4 : 0);
+    for (int64_t z0 = 0; z0 < a.d; z0 += chunk) {
+        const int64_t z1 = z0 + chunk < a.d ? z0 + chunk : a.d;
+        const bool acc = z0 > 0;
+        hipLaunchKernelGGL((ecc3d_stream<T, LM, AL, MAXIMG, SINGLE, kZmTY>), dim3(a.grid), dim3(256), lds, s,
+                           (const T *)a.data, a.d, a.h, a.w, a.lv, a.lo, a.hi, cpass, a.zm_tables, a.partial, z0,
+                           z1, acc ? 1 : 0);
+        const int e = (int)hipGetLastError();
+        if (e) return e;
+    }
+    return 0;
+}
+
+template <typename T, int LM, bool MAXIMG>
+static int launch_zm_al(const Launch3D &a, hipStream_t s) {
+    constexpr int VB = Elem3<T>::VEC * (int)sizeof(T);
+    const bool al = ((uintptr_t)a.data % VB == 0) && (a.w * (int64_t)sizeof(T)) % VB == 0;
+    const bool single = a.lo == 0 && a.hi == a.lv.L;
+    if (single) return al ? launch_zm_t<T, LM, true, MAXIMG, true>(a, s) : launch_zm_t<T, LM, false, MAXIMG, true>(a, s);
+    return al ? launch_zm_t<T, LM, true, MAXIMG, false>(a, s) : launch_zm_t<T, LM, false, MAXIMG, false>(a, s);
+}
+
 template <typename T, int LM>
 static int launch_3d_cr(const Launch3D &a, hipStream_t s) {
+    if (a.zm_tables) return a.conn6 ? launch_zm_al<T, LM, true>(a, s) : launch_zm_al<T, LM, false>(a, s);
     return a.want_crease ? launch_3d_t<T, LM, true>(a, s) : launch_3d_t<T, LM, false>(a, s);
 }
 

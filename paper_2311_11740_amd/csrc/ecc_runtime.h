@@ -61,6 +61,7 @@ struct ecc_context_s {
     uint64_t *d_delta2[2] = {nullptr, nullptr};  // 2D per-cell deltas, 8-C and 4-C
     int32_t h_delta2[2][256][3];
     int64_t *d_vtab3[2] = {nullptr, nullptr};    // 3D per-vertex table, 26-C and 6-C
+    uint32_t *d_zm3[2] = {nullptr, nullptr};     // 3D z-marching tables, 26-C and 6-C
     std::vector<ecc::ThrEntry *> thr_cache;
     ecc::Workspace ws;
     hipEvent_t ws_event = nullptr;

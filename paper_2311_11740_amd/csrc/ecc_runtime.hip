@@ -145,6 +145,22 @@ extern "C" ecc_status ecc_create(int device, ecc_context *out) {
             ecc_destroy(ctx);
             return s;
         }
+        // z-marching tables from the 2D per-cell EC deltas of the same pattern
+        // (8-C for the 26-C volume, 4-C for 6-C): [0, 256) the layer term with
+        // the 2D perimeter delta (4 minus 2 per edge neighbour in) and the
+        // biases, [256, 512) the image delta, signs as the decomposition takes them
+        uint32_t zt[512];
+        const int sgn = k == 0 ? -1 : 1;
+        for (int p = 0; p < 256; ++p) {
+            const int per = 4 - 2 * __builtin_popcount(p & 0x5A);  // N, W, E, S bits
+            zt[p] = (uint32_t)(sgn * dt[p][0] + kEcBias3) + ((uint32_t)(per + 8) << kShiftSurf3);
+            zt[256 + p] = (uint32_t)(-sgn * dt[p][0]);
+        }
+        s = upload((void **)&ctx->d_zm3[k], zt, sizeof(zt));
+        if (s != ECC_OK) {
+            ecc_destroy(ctx);
+            return s;
+        }
     }
     e = (int)hipEventCreateWithFlags(&ctx->ws_event, hipEventDisableTiming);
     if (e) {
@@ -163,6 +179,7 @@ extern "C" ecc_status ecc_destroy(ecc_context ctx) {
     for (int k = 0; k < 2; ++k) {
         if (ctx->d_delta2[k]) hipFree(ctx->d_delta2[k]);
         if (ctx->d_vtab3[k]) hipFree(ctx->d_vtab3[k]);
+        if (ctx->d_zm3[k]) hipFree(ctx->d_zm3[k]);
     }
     for (auto *t : ctx->thr_cache) free_thresholds(t);
     ctx->thr_cache.clear();
@@ -417,14 +434,23 @@ ecc_status compute_one(ecc_context ctx, const ecc_field *f, const FieldInfo &fi,
     const int win = std::min(L, kMaxWindow);
     const bool crease = fi.ndim == 3 && c->perimeter != nullptr;
     const int k = (fi.ndim == 2 ? (fi.conn == 8 ? 0 : 1) : (fi.conn == 26 ? 0 : 1));
-    int grid;
+    int grid = 1;
+    bool zmarch = false;
     if (fi.ndim == 2) {
         const int vec = vec_2d(fi.dtype);
         const int64_t strips = (fi.w + 62 * vec - 1) / (62 * vec);
         grid = (int)std::min<int64_t>((int64_t)ctx->n_cu * wg_per_cu_default(),
                                       std::max<int64_t>(1, (strips * fi.h + 31) / 32));
         if (grid >= 8) grid -= grid % 8;
-    } else {
+    } else if (!crease) {
+        // z-marching kernel: at least ~16 planes per wave
+        const int64_t units = (int64_t)zmarch_3d_columns(fi.h, fi.w) * fi.d;
+        grid = (int)std::min<int64_t>((int64_t)ctx->n_cu * wg_per_cu_default(),
+                                      std::max<int64_t>(1, (units + 63) / 64));
+        if (grid >= 8) grid -= grid % 8;
+        zmarch = zmarch_3d_fits(fi.h, fi.w, grid);
+    }
+    if (fi.ndim == 3 && !zmarch) {
         const int64_t n_tiles = ((fi.w + kTile3DX - 1) / kTile3DX) * ((fi.h + kTile3DY - 1) / kTile3DY) *
                                 ((fi.d + kTile3DZ - 1) / kTile3DZ);
         grid = pick_grid(ctx, n_tiles, lds_bytes_3d(win, crease) + 16 * 1024);
@@ -448,7 +474,8 @@ ecc_status compute_one(ecc_context ctx, const ecc_field *f, const FieldInfo &fi,
             int slot = -1;
             s = prof_begin(ctx, stream, &slot);
             if (s != ECC_OK) return s;
-            Launch3D a{f->data, fi.dtype, fi.d, fi.h, fi.w, lv, lo, hi, ctx->d_vtab3[k], partial, grid, crease};
+            Launch3D a{f->data, fi.dtype, fi.d, fi.h, fi.w, lv, lo, hi, ctx->d_vtab3[k], partial, grid, crease,
+                       zmarch ? ctx->d_zm3[k] : nullptr, k == 1};
             int e = launch_3d(a, stream);
             if (e) return hip_fail(e, "3D kernel launch");
             s = prof_end(ctx, stream, slot);

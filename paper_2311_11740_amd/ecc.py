@@ -64,6 +64,11 @@ def load(path: str = LIB_PATH):
         return _lib
     if not os.path.exists(path):
         raise EccLibraryMissing(f"{path} is not built; run `python -m paper_2311_11740_amd.build`")
+    # libecc binds to the HIP runtime already present in the process.  torch
+    # ships its own copy of that runtime: loading torch first makes libecc use
+    # the same one, so torch's device pointers and streams are valid in libecc
+    # (loaded the other way round, two runtimes would compete for the device).
+    import torch  # noqa: F401
     lib = ctypes.CDLL(path)
     vp, i32, i64p = ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64)
     sig = {

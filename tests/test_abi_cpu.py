@@ -141,3 +141,18 @@ def test_compute_without_context_is_an_error(lib):
 def test_status_strings(lib):
     for s in range(6):
         assert lib.ecc_status_string(s).decode().startswith("ECC_")
+
+
+def test_binding_uses_one_hip_runtime():
+    """The binding loads torch before libecc so that both use one HIP runtime
+    (two copies in a process compete for the device)."""
+    import subprocess
+    import sys
+    code = ("import sys; sys.path.insert(0, %r)\n"
+            "from paper_2311_11740_amd import ecc\n"
+            "ecc.load()\n"
+            "maps = open('/proc/self/maps').read().split('\\n')\n"
+            "print(len({l.split()[-1] for l in maps if 'libamdhip64' in l}))\n") % ROOT
+    out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300)
+    assert out.returncode == 0, out.stderr
+    assert out.stdout.strip() == "1", out.stdout

@@ -1,0 +1,108 @@
+"""GPU parity at the full workload sizes, in the launch configuration the
+benchmark times.
+
+* 2D 256 x 256 uint8 (256 levels): every level against the per-level counting
+  oracle (O1) and the all-levels oracle (O2).
+* 2D 8192 x 8192 float32 (1024 thresholds) and 3D 512^3 uint16 (4096 levels):
+  whole curves against O2, and a few sampled levels against O1, which
+  binarises and counts cells at one level at a time.
+* A 3D volume whose z-marching launch is split along z (workgroup bins would
+  otherwise see too many cells), against O2.
+"""
+from __future__ import annotations
+
+import os
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+NT = min(16, os.cpu_count() or 1)
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2311_11740_amd import ecc
+    c = ecc.Context(0)
+    yield c
+    c.close()
+
+
+def gpu_curves(ctx, spec, channels):
+    import torch
+    dev = torch.from_numpy(spec.data).cuda()
+    got = ctx.compute(dev, spec.n_levels, thresholds=spec.thresholds, connectivity=spec.connectivity,
+                      channels=channels)
+    torch.cuda.synchronize()
+    return {k: v.cpu().numpy() for k, v in got.items()}
+
+
+def check_o2(spec, got, tag):
+    import oracle
+    ref = oracle.o2_curves(spec.data, spec.n_levels, thresholds=spec.thresholds,
+                           connectivity=spec.connectivity, channels=tuple(got), n_threads=NT)
+    for k in got:
+        bad = np.nonzero(got[k] != ref[k])[0]
+        assert bad.size == 0, f"{tag} {k}: {bad.size} levels differ, first {bad[:1]}"
+
+
+def check_o1_levels(spec, got, levels, tag):
+    import oracle
+    ref = oracle.o1_curves(spec.data, spec.n_levels, thresholds=spec.thresholds,
+                           connectivity=spec.connectivity, levels=levels, channels=tuple(got))
+    for k in got:
+        for i, lv in enumerate(levels):
+            assert got[k][lv] == ref[k][i], f"{tag} {k} level {lv}: gpu {got[k][lv]} oracle {ref[k][i]}"
+
+
+def test_small_2d_all_levels():
+    from paper_2311_11740_amd import ecc, synth
+    import oracle
+    spec = synth.small_2d_u8()
+    print(f"[case] {spec.meta['name']}", flush=True)
+    c = ecc.Context(0)
+    try:
+        got = gpu_curves(c, spec, None)
+    finally:
+        c.close()
+    ref = oracle.o1_curves(spec.data, spec.n_levels, connectivity=8)
+    for k in got:
+        assert np.array_equal(got[k], ref[k]), k
+    check_o2(spec, got, spec.meta["name"])
+
+
+def test_large_2d_f32(ctx):
+    from paper_2311_11740_amd import synth
+    spec = synth.large_2d_f32()
+    print(f"[case] {spec.meta['name']}", flush=True)
+    got = gpu_curves(ctx, spec, None)
+    check_o2(spec, got, spec.meta["name"])
+    check_o1_levels(spec, got, [0, 300, 511, 512, 700, 1023], spec.meta["name"])
+
+
+@pytest.mark.parametrize("channels", [("ec", "area", "volume"), None], ids=["zmarch", "tile"])
+def test_large_3d_u16(ctx, channels):
+    from paper_2311_11740_amd import synth
+    spec = synth.large_3d_u16()
+    print(f"[case] {spec.meta['name']} channels={channels}", flush=True)
+    got = gpu_curves(ctx, spec, channels)
+    check_o2(spec, got, spec.meta["name"])
+    if channels is not None:
+        check_o1_levels(spec, got, [1500, 2048, 2600], spec.meta["name"])
+
+
+@pytest.mark.parametrize("conn", [26, 6])
+def test_3d_zmarch_split_along_z(ctx, conn):
+    """288 x 1024 x 1024 uint8: 1024 columns x 288 planes exceed what one
+    launch may add to a workgroup's bins, so the launch is split along z."""
+    from paper_2311_11740_amd import synth
+    rng = np.random.default_rng(77)
+    a = rng.integers(0, 200, size=(288, 1024, 1024), dtype=np.uint8)
+    a[rng.integers(0, 288, 64), rng.integers(0, 1024, 64), rng.integers(0, 1024, 64)] = 255  # never
+    spec = synth.FieldSpec(a, 200, None, conn, dict(name=f"3d_288x1024x1024_u8_{conn}c"))
+    print(f"[case] {spec.meta['name']}", flush=True)
+    got = gpu_curves(ctx, spec, ("ec", "area", "volume"))
+    check_o2(spec, got, spec.meta["name"])

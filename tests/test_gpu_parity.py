@@ -91,6 +91,11 @@ def test_2d_f32_affine_thresholds(ctx):
     z.ravel()[6] = np.inf
     z.ravel()[7] = -np.inf
     z.ravel()[8] = -0.0
+    # far below the first threshold (level 0) and far above the last (never)
+    z.ravel()[9::211] = np.float32(-4.0) - np.float32(8 / 1023) * (np.arange(z.ravel()[9::211].size) % 50)
+    z.ravel()[10] = np.float32(-1e30)
+    z.ravel()[14] = np.float32(1e30)
+    z.ravel()[15] = np.float32(4.5)
     run_and_compare(ctx, z, 1024, thr=thr, tag="2d_f32_affine")
     run_and_compare(ctx, z, 1024, thr=thr, conn=4, tag="2d_f32_affine_4c")
 
@@ -129,38 +134,71 @@ def test_2d_channel_subsets(ctx):
         run_and_compare(ctx, a, 50, channels=ch, tag=f"2d_ch_{'_'.join(ch)}")
 
 
-SHAPES_3D = [(1, 1, 1), (1, 1, 70), (70, 1, 1), (3, 5, 7), (17, 9, 130), (40, 33, 65), (1, 64, 64)]
+SHAPES_3D = [(1, 1, 1), (1, 1, 70), (70, 1, 1), (3, 5, 7), (17, 9, 130), (40, 33, 65), (1, 64, 64),
+             (9, 7, 513), (5, 258, 300)]
+# channel sets: without the crease measure the z-marching kernel runs, with it
+# the generic tile kernel
+NO_CREASE = ("ec", "area", "volume")
+ALL_3D = None
 
 
 @pytest.mark.parametrize("shape", SHAPES_3D)
 @pytest.mark.parametrize("conn", [26, 6])
-def test_3d_u8_all_channels(ctx, shape, conn):
+@pytest.mark.parametrize("channels", [NO_CREASE, ALL_3D], ids=["zmarch", "tile"])
+def test_3d_u8(ctx, shape, conn, channels):
     rng = np.random.default_rng(hash((shape, conn, 3)) % 2**32)
     a = rng.integers(0, 40, size=shape).astype(np.uint8)
-    run_and_compare(ctx, a, 36, conn=conn, tag="3d_u8")
+    run_and_compare(ctx, a, 36, conn=conn, channels=channels, tag="3d_u8")
 
 
-def test_3d_u16_grf(ctx):
+@pytest.mark.parametrize("channels", [NO_CREASE, ALL_3D], ids=["zmarch", "tile"])
+def test_3d_u16_grf(ctx, channels):
     from paper_2311_11740_amd import synth
     a = synth.quantise(synth.grf((48, 40, 136), 3.0, 31), 4096)
-    run_and_compare(ctx, a, 4096, tag="3d_u16_grf", channels=("ec", "area", "volume"))
-    run_and_compare(ctx, a, 4096, tag="3d_u16_grf_crease")
-    run_and_compare(ctx, a, 3000, conn=6, tag="3d_u16_grf_6c_never")
-    run_and_compare(ctx, a, 5000, tag="3d_u16_grf_2pass")
+    run_and_compare(ctx, a, 4096, tag="3d_u16_grf", channels=channels)
+    run_and_compare(ctx, a, 3000, conn=6, tag="3d_u16_grf_6c_never", channels=channels)
+    run_and_compare(ctx, a, 5000, tag="3d_u16_grf_2pass", channels=channels)
+    run_and_compare(ctx, a, 5000, conn=6, tag="3d_u16_grf_2pass_6c", channels=channels)
 
 
-def test_3d_f32_thresholds(ctx):
+@pytest.mark.parametrize("channels", [NO_CREASE, ALL_3D], ids=["zmarch", "tile"])
+def test_3d_f32_thresholds(ctx, channels):
     from paper_2311_11740_amd import synth
     z = synth.grf((20, 30, 70), 2.5, 41)
     z.ravel()[11] = np.nan
+    z.ravel()[12] = np.inf
+    z.ravel()[13] = -np.inf
     thr = synth.linspace_thresholds(-3, 3, 200)
-    run_and_compare(ctx, z, 200, thr=thr, tag="3d_f32_affine")
+    z.ravel()[100::37] = thr[np.arange(z.ravel()[100::37].size) % 200]  # values on thresholds
+    z.ravel()[101::53] = np.float32(-3.0) - np.float32(0.03) * (np.arange(z.ravel()[101::53].size) % 40)
+    z.ravel()[102::97] = np.float32(3.0) + np.float32(0.03) * (np.arange(z.ravel()[102::97].size) % 40)
+    run_and_compare(ctx, z, 200, thr=thr, tag="3d_f32_affine", channels=channels)
     thr2 = np.sort(np.random.default_rng(2).normal(size=77)).astype(np.float32)
-    run_and_compare(ctx, z, 77, thr=thr2, conn=6, tag="3d_f32_irregular_6c")
+    run_and_compare(ctx, z, 77, thr=thr2, conn=6, tag="3d_f32_irregular_6c", channels=channels)
 
 
-def test_3d_constant(ctx):
-    run_and_compare(ctx, np.full((20, 6, 70), 3, np.uint16), 10, tag="3d_const")
+def test_3d_integer_with_thresholds(ctx):
+    rng = np.random.default_rng(19)
+    a = rng.integers(0, 256, size=(13, 21, 300)).astype(np.uint8)
+    thr = np.array([3.5, 10, 10, 99.9, 100, 200, 254.5], np.float32)
+    for conn in (26, 6):
+        run_and_compare(ctx, a, len(thr), thr=thr, conn=conn, channels=NO_CREASE, tag="3d_u8_thr")
+    b = rng.integers(0, 65535, size=(11, 17, 150)).astype(np.uint16)
+    thr2 = np.linspace(0, 70000, 500).astype(np.float32)
+    run_and_compare(ctx, b, 500, thr=thr2, channels=NO_CREASE, tag="3d_u16_thr")
+
+
+def test_3d_channel_subsets(ctx):
+    rng = np.random.default_rng(20)
+    a = rng.integers(0, 30, size=(9, 20, 100)).astype(np.uint8)
+    for ch in (("ec",), ("area",), ("volume",), ("perimeter",), ("ec", "perimeter")):
+        run_and_compare(ctx, a, 30, channels=ch, tag=f"3d_ch_{'_'.join(ch)}")
+
+
+@pytest.mark.parametrize("channels", [NO_CREASE, ALL_3D], ids=["zmarch", "tile"])
+def test_3d_constant(ctx, channels):
+    run_and_compare(ctx, np.full((20, 6, 70), 3, np.uint16), 10, tag="3d_const", channels=channels)
+    run_and_compare(ctx, np.full((5, 6, 270), 200, np.uint8), 100, tag="3d_all_never", channels=channels)
 
 
 def test_repeat_is_deterministic(ctx):
