@@ -74,6 +74,9 @@ struct Launch2D {
 
 // cells per lane along the contiguous axis (16 bytes of input per lane)
 inline int vec_2d(int dtype) { return dtype == 1 ? 16 : (dtype == 2 ? 8 : 4); }
+// how the 2D kernels load a row block of this field (kLoadElement = 0,
+// kLoadVector = 1, kLoadAligned = 2)
+int load_mode_2d(const void *data, int64_t h, int64_t w, int elem_bytes);
 
 struct Launch3D {
     const void *data;

@@ -159,42 +159,80 @@ __device__ __forceinline__ uint32_t pk_lt(uint32_t q, uint32_t ref) {
 struct RawRow {
     uint32_t w[4];   // 16 bytes: VEC raw elements of this lane
     uint32_t valid;  // bit i: element i lies inside the field
+    uint32_t shift;  // elements the block must move down (loads clamped at the buffer end)
 };
 
-// ALIGNED: the field's base and row pitch are multiples of 16 bytes, so each
-// lane's 16-byte block is either wholly inside the row or wholly outside it;
-// every lane then issues one unconditional 16-byte load (clamped to column 0
-// when outside).  Otherwise elements are loaded one by one.  The row index is
-// clamped into the field by the caller: loads are never skipped, so the
-// compiler can keep several of them in flight (a skipped load would make it
-// wait for all outstanding ones).
-template <typename T, bool ALIGNED>
+typedef u32x4 u32x4_u __attribute__((aligned(1)));
+
+// How a lane loads its VEC elements of a row:
+//  kLoadAligned: base and row pitch are multiples of 16 bytes, so each lane's
+//    block lies wholly inside the row or wholly outside it; one 16-byte load
+//    (clamped to column 0 when outside).
+//  kLoadVector: any alignment; one 16-byte load at the block's address (the
+//    hardware serves unaligned vector loads).  Elements past the row end come
+//    from the next row and are masked.  A block that would run past the end
+//    of the buffer is loaded from the last 16 bytes of the buffer instead and
+//    shifted back into place when converted (needs at least VEC elements).
+//  kLoadElement: element by element (fields of fewer than VEC elements).
+// The row index is clamped into the field by the caller: loads are never
+// skipped, so the compiler can keep several of them in flight (a skipped load
+// would make it wait for all outstanding ones).
+enum LoadMode : int { kLoadElement = 0, kLoadVector = 1, kLoadAligned = 2 };
+
+template <typename T, int AL>
 __device__ __forceinline__ void fetch_row(const T *__restrict__ data, int r, int64_t w, int64_t x0,
-                                          RawRow &raw) {
+                                          int64_t last_block, RawRow &raw) {
     constexpr int VEC = Elem<T>::VEC;
     const T *row = data + (int64_t)r * w;
-    if constexpr (ALIGNED) {
-        const bool in = x0 >= 0 && x0 < w;
+    const bool in = x0 >= 0 && x0 < w;
+    if constexpr (AL == kLoadAligned) {
         const u32x4 q = __builtin_nontemporal_load(reinterpret_cast<const u32x4 *>(row + (in ? x0 : 0)));
         raw.w[0] = q.x; raw.w[1] = q.y; raw.w[2] = q.z; raw.w[3] = q.w;
         raw.valid = in ? (1u << VEC) - 1u : 0u;
+        raw.shift = 0;
+    } else if constexpr (AL == kLoadVector) {
+        const int64_t li = (int64_t)r * w + (in ? x0 : 0);      // element index of the block
+        const int64_t lc = li < last_block ? li : last_block;  // last_block = h * w - VEC
+        const u32x4 q = __builtin_nontemporal_load(reinterpret_cast<const u32x4_u *>(data + lc));
+        raw.w[0] = q.x; raw.w[1] = q.y; raw.w[2] = q.z; raw.w[3] = q.w;
+        const int64_t n_in = in ? w - x0 : 0;
+        raw.valid = n_in >= VEC ? (1u << VEC) - 1u : (1u << n_in) - 1u;
+        raw.shift = (uint32_t)(li - lc);
     } else {
         raw.w[0] = raw.w[1] = raw.w[2] = raw.w[3] = 0;
         raw.valid = 0;
+        raw.shift = 0;
 #pragma unroll
         for (int i = 0; i < VEC; ++i) {
             const int64_t x = x0 + i;
-            const bool in = x >= 0 && x < w;
+            const bool ok = x >= 0 && x < w;
             uint32_t bits;
             if constexpr (sizeof(T) == 4)
-                bits = __float_as_uint(row[in ? x : 0]);
+                bits = __float_as_uint(row[ok ? x : 0]);
             else
-                bits = (uint32_t)row[in ? x : 0];
+                bits = (uint32_t)row[ok ? x : 0];
             constexpr int per = 4 / sizeof(T);
-            raw.w[i / per] |= (in ? bits : 0u) << (8 * sizeof(T) * (i % per));
-            raw.valid |= (in ? 1u : 0u) << i;
+            raw.w[i / per] |= (ok ? bits : 0u) << (8 * sizeof(T) * (i % per));
+            raw.valid |= (ok ? 1u : 0u) << i;
         }
     }
+}
+
+// moves a block loaded from a clamped address down by raw.shift elements
+template <typename T>
+__device__ __forceinline__ void unshift_row(RawRow &raw) {
+    const uint32_t sb = raw.shift * (uint32_t)sizeof(T);  // bytes, < 16
+    uint64_t lo = (uint64_t)raw.w[0] | (uint64_t)raw.w[1] << 32;
+    uint64_t hi = (uint64_t)raw.w[2] | (uint64_t)raw.w[3] << 32;
+    if (sb >= 8) {
+        lo = hi >> (8 * (sb - 8));
+        hi = 0;
+    } else if (sb > 0) {
+        lo = (lo >> (8 * sb)) | (hi << (64 - 8 * sb));
+        hi >>= 8 * sb;
+    }
+    raw.w[0] = (uint32_t)lo; raw.w[1] = (uint32_t)(lo >> 32);
+    raw.w[2] = (uint32_t)hi; raw.w[3] = (uint32_t)(hi >> 32);
 }
 
 // Level index of a float value with the affine estimate, without the
@@ -261,7 +299,7 @@ __device__ __forceinline__ uint32_t pack_lo16(uint32_t a, uint32_t b) {  // (a.l
 }
 
 template <typename T, int LM, typename TH>
-__device__ __forceinline__ void convert_row(const RawRow &raw, bool row_ok, bool full, const LevelArgs &lv,
+__device__ __forceinline__ void convert_row(const RawRow &raw_in, bool row_ok, bool full, const LevelArgs &lv,
                                             const TH &thr, int lo, int W, float cpass,
                                             uint32_t (&P)[Elem<T>::VEC + 1]) {
     constexpr int VEC = Elem<T>::VEC;
@@ -271,6 +309,8 @@ __device__ __forceinline__ void convert_row(const RawRow &raw, bool row_ok, bool
         for (int i = 0; i <= VEC; ++i) P[i] = never | never << 16;
         return;
     }
+    RawRow raw = raw_in;
+    if (__any(raw.shift != 0)) unshift_row<T>(raw);  // rare: blocks at the end of the buffer
     uint32_t lam[VEC];  // low 16 bits: lam'
     const int base = lo - 1;
     if constexpr (LM == LM_AFFINE) {
@@ -391,7 +431,7 @@ __device__ __forceinline__ void emit_row(const uint32_t (&up)[VEC + 1], const ui
 
 // rows [ra, rb) of one strip; three row buffers whose roles rotate with the
 // row index (PF is a multiple of 3, so the unrolled loop needs no copies)
-template <typename T, int LM, bool ALIGNED, int PF, bool SINGLE, typename TH>
+template <typename T, int LM, int AL, int PF, bool SINGLE, typename TH>
 __device__ __forceinline__ void stream_run_2d(const T *__restrict__ data, int h, int64_t w,
                                               const LevelArgs &lv, const TH &thr, int32_t lo, int W,
                                               float cpass, const uint64_t *dl, uint64_t *hist, int64_t strip,
@@ -403,18 +443,19 @@ __device__ __forceinline__ void stream_run_2d(const T *__restrict__ data, int h,
     const int64_t x0 = xs + (int64_t)lane * VEC;
     const bool full = xs >= 0 && xs + 64 * VEC <= w;
     auto clamp_row = [h](int r) { return r < 0 ? 0 : (r >= h ? h - 1 : r); };
+    const int64_t last_block = (int64_t)h * w - VEC;
 
     uint32_t R[3][VEC + 1];  // R[r % 3] holds row r (relative to ra)
     RawRow ring[PF];
     {
         RawRow r0, r1;
-        fetch_row<T, ALIGNED>(data, clamp_row(ra - 1), w, x0, r0);
-        fetch_row<T, ALIGNED>(data, ra, w, x0, r1);
+        fetch_row<T, AL>(data, clamp_row(ra - 1), w, x0, last_block, r0);
+        fetch_row<T, AL>(data, ra, w, x0, last_block, r1);
         // ring[k] holds row ra + 1 + k (rows past rb are clamped reloads)
 #pragma unroll
         for (int k = 0; k < PF; ++k) {
             const int rr = ra + 1 + k < rb ? ra + 1 + k : rb;
-            fetch_row<T, ALIGNED>(data, clamp_row(rr), w, x0, ring[k]);
+            fetch_row<T, AL>(data, clamp_row(rr), w, x0, last_block, ring[k]);
         }
         convert_row<T, LM>(r0, ra - 1 >= 0, full, lv, thr, lo, W, cpass, R[2]);
         convert_row<T, LM>(r1, true, full, lv, thr, lo, W, cpass, R[0]);
@@ -427,7 +468,7 @@ __device__ __forceinline__ void stream_run_2d(const T *__restrict__ data, int h,
             const int r = r0 + k;  // current row (buffer k%3); ring[k] holds row r + 1
             convert_row<T, LM>(ring[k], r + 1 < h, full, lv, thr, lo, W, cpass, R[(k + 1) % 3]);
             const int nx = r + 1 + PF < rb ? r + 1 + PF : rb;
-            fetch_row<T, ALIGNED>(data, clamp_row(nx), w, x0, ring[k]);
+            fetch_row<T, AL>(data, clamp_row(nx), w, x0, last_block, ring[k]);
             emit_row<VEC, SINGLE>(R[(k + 2) % 3], R[k % 3], R[(k + 1) % 3], mask_or_off, scratch, dl, hist);
         }
     }
@@ -443,71 +484,10 @@ __device__ __forceinline__ void stream_run_2d(const T *__restrict__ data, int h,
     }
 }
 
-// rows [ra, rb) of one strip
-template <typename T, int LM, bool ALIGNED, int PF, typename TH>
-__device__ __forceinline__ void stream_run_2d(const T *__restrict__ data, int h, int64_t w,
-                                              const LevelArgs &lv, const TH &thr, int32_t lo, int W,
-                                              const uint64_t *dl, uint64_t *hist, int64_t strip, int ra,
-                                              int rb, int lane, uint32_t off, uint32_t scratch) {
-    constexpr int VEC = Elem<T>::VEC;
-    constexpr int CE = 62 * VEC;  // cells owned per strip
-    const int64_t xs = strip * CE - VEC;  // first column of lane 0
-    const int64_t x0 = xs + (int64_t)lane * VEC;
-    const bool full = xs >= 0 && xs + 64 * VEC <= w;
-    auto clamp_row = [h](int r) { return r < 0 ? 0 : (r >= h ? h - 1 : r); };
-
-    uint32_t up[VEC + 1], mid[VEC + 1], dn[VEC + 1];
-    RawRow ring[PF];
-    {
-        RawRow r0, r1;
-        fetch_row<T, ALIGNED>(data, clamp_row(ra - 1), w, x0, r0);
-        fetch_row<T, ALIGNED>(data, ra, w, x0, r1);
-        // ring[k] holds row ra + 1 + k (rows past rb are clamped reloads)
-#pragma unroll
-        for (int k = 0; k < PF; ++k) {
-            const int rr = ra + 1 + k < rb ? ra + 1 + k : rb;
-            fetch_row<T, ALIGNED>(data, clamp_row(rr), w, x0, ring[k]);
-        }
-        convert_row<T, LM>(r0, ra - 1 >= 0, full, lv, thr, lo, W, up);
-        convert_row<T, LM>(r1, true, full, lv, thr, lo, W, mid);
-    }
-    int r0 = ra;
-    // full blocks of PF rows: no conditional loads, so PF loads stay in flight
-    for (; r0 + PF <= rb; r0 += PF) {
-#pragma unroll
-        for (int k = 0; k < PF; ++k) {
-            const int r = r0 + k;  // current row; ring[k] holds row r + 1
-            convert_row<T, LM>(ring[k], r + 1 < h, full, lv, thr, lo, W, dn);
-            const int nx = r + 1 + PF < rb ? r + 1 + PF : rb;
-            fetch_row<T, ALIGNED>(data, clamp_row(nx), w, x0, ring[k]);
-            emit_row<VEC>(up, mid, dn, off, scratch, dl, hist);
-#pragma unroll
-            for (int j = 0; j < VEC + 1; ++j) {
-                up[j] = mid[j];
-                mid[j] = dn[j];
-            }
-        }
-    }
-    // remaining rows (fewer than PF)
-#pragma unroll
-    for (int k = 0; k < PF; ++k) {
-        const int r = r0 + k;
-        if (r < rb) {
-            convert_row<T, LM>(ring[k], r + 1 < h, full, lv, thr, lo, W, dn);
-            emit_row<VEC>(up, mid, dn, off, scratch, dl, hist);
-#pragma unroll
-            for (int j = 0; j < VEC + 1; ++j) {
-                up[j] = mid[j];
-                mid[j] = dn[j];
-            }
-        }
-    }
-}
-
 // Work split: the (strip, row) units of rows [row_lo, row_hi), strip-major,
 // are divided into equal contiguous ranges, one per wave (a range may run from
 // the end of one strip into the next).
-template <typename T, int LM, bool ALIGNED, int PF, bool SINGLE>
+template <typename T, int LM, int AL, int PF, bool SINGLE>
 __global__ void __launch_bounds__(256)
     ecc2d_stream(const T *__restrict__ data, int64_t h, int64_t w, LevelArgs lv, int32_t lo,
                  int32_t hi, float cpass, const uint64_t *__restrict__ delta_lut, int32_t *__restrict__ partial,
@@ -550,7 +530,7 @@ __global__ void __launch_bounds__(256)
     for (int64_t u = units * gw / NW; u < u_end;) {
         const int64_t strip = u / H, ra = u % H;
         const int64_t rb = ra + (u_end - u) < H ? ra + (u_end - u) : H;
-        stream_run_2d<T, LM, ALIGNED, PF, SINGLE>(data, (int)h, w, lv, thr, lo, W, cpass, dl, hist, strip,
+        stream_run_2d<T, LM, AL, PF, SINGLE>(data, (int)h, w, lv, thr, lo, W, cpass, dl, hist, strip,
                                                   (int)(row_lo + ra), (int)(row_lo + rb), lane, mask_or_off,
                                                   scratch);
         u += rb - ra;
@@ -623,7 +603,8 @@ struct Elem3 {
 
 struct RawRow3 {
     uint32_t w[4];
-    uint32_t halo;  // lane 0: element left of the strip; lane 63: right of it
+    uint32_t halo;   // lane 0: element left of the strip; lane 63: right of it
+    uint32_t shift;  // elements the block must move down (kLoadVector at the buffer end)
 };
 
 template <typename T>
@@ -641,26 +622,53 @@ __device__ __forceinline__ uint32_t elem3(const RawRow3 &r, int i) {
     else return r.w[i];
 }
 
-// row y of plane z (both clamped into the field by the caller); unconditional
-template <typename T, bool ALIGNED>
-__device__ __forceinline__ void fetch_row3(const T *__restrict__ data, int64_t h, int64_t w, int z, int y,
-                                           int64_t xs, int64_t x0, int lane, RawRow3 &raw) {
-    constexpr int VEC = Elem3<T>::VEC;
-    const T *row = data + ((int64_t)z * h + y) * w;
-    if constexpr (ALIGNED) {  // whole 4-cell groups: inside or outside the row
-        const int64_t xc = x0 < w ? x0 : 0;
-        if constexpr (sizeof(T) == 1) {
-            raw.w[0] = __builtin_nontemporal_load(reinterpret_cast<const uint32_t *>(row + xc));
-        } else if constexpr (sizeof(T) == 2) {
-            typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
-            const u32x2 q = __builtin_nontemporal_load(reinterpret_cast<const u32x2 *>(row + xc));
-            raw.w[0] = q.x; raw.w[1] = q.y;
-        } else {
-            const u32x4 q = __builtin_nontemporal_load(reinterpret_cast<const u32x4 *>(row + xc));
-            raw.w[0] = q.x; raw.w[1] = q.y; raw.w[2] = q.z; raw.w[3] = q.w;
-        }
+// one block of VEC elements (4 * sizeof(T) bytes) at element index e
+template <typename T, bool UNALIGNED>
+__device__ __forceinline__ void load_block3(const T *p, RawRow3 &raw) {
+    if constexpr (sizeof(T) == 1) {
+        typedef uint32_t u32_u __attribute__((aligned(1)));
+        typedef uint32_t u32_a __attribute__((aligned(4)));
+        if constexpr (UNALIGNED)
+            raw.w[0] = __builtin_nontemporal_load(reinterpret_cast<const u32_u *>(p));
+        else
+            raw.w[0] = __builtin_nontemporal_load(reinterpret_cast<const u32_a *>(p));
+    } else if constexpr (sizeof(T) == 2) {
+        typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+        typedef u32x2 u32x2_u __attribute__((aligned(1)));
+        u32x2 q;
+        if constexpr (UNALIGNED)
+            q = __builtin_nontemporal_load(reinterpret_cast<const u32x2_u *>(p));
+        else
+            q = __builtin_nontemporal_load(reinterpret_cast<const u32x2 *>(p));
+        raw.w[0] = q.x; raw.w[1] = q.y;
     } else {
-        raw.w[0] = raw.w[1] = raw.w[2] = raw.w[3] = 0;
+        u32x4 q;
+        if constexpr (UNALIGNED)
+            q = __builtin_nontemporal_load(reinterpret_cast<const u32x4_u *>(p));
+        else
+            q = __builtin_nontemporal_load(reinterpret_cast<const u32x4 *>(p));
+        raw.w[0] = q.x; raw.w[1] = q.y; raw.w[2] = q.z; raw.w[3] = q.w;
+    }
+}
+
+// row y of plane z (both clamped into the field by the caller); unconditional
+// loads, in the three modes of the 2D kernels (a block is 4 elements here)
+template <typename T, int AL>
+__device__ __forceinline__ void fetch_row3(const T *__restrict__ data, int64_t h, int64_t w, int z, int y,
+                                           int64_t xs, int64_t x0, int lane, int64_t last_block, RawRow3 &raw) {
+    constexpr int VEC = Elem3<T>::VEC;
+    const int64_t rbase = ((int64_t)z * h + y) * w;
+    const T *row = data + rbase;
+    raw.w[0] = raw.w[1] = raw.w[2] = raw.w[3] = 0;
+    raw.shift = 0;
+    if constexpr (AL == kLoadAligned) {  // whole blocks: inside or outside the row
+        load_block3<T, false>(row + (x0 < w ? x0 : 0), raw);
+    } else if constexpr (AL == kLoadVector) {
+        const int64_t li = rbase + (x0 < w ? x0 : 0);
+        const int64_t lc = li < last_block ? li : last_block;  // last_block = d * h * w - VEC
+        load_block3<T, true>(data + lc, raw);
+        raw.shift = (uint32_t)(li - lc);
+    } else {
 #pragma unroll
         for (int i = 0; i < VEC; ++i) {
             const int64_t x = x0 + i;
@@ -672,6 +680,22 @@ __device__ __forceinline__ void fetch_row3(const T *__restrict__ data, int64_t h
     int64_t hx = lane == 0 ? xs - 1 : (lane == 63 ? xs + 64 * VEC : x0);
     hx = hx < 0 ? 0 : (hx >= w ? w - 1 : hx);
     raw.halo = elem_bits(row + hx);
+}
+
+template <typename T>
+__device__ __forceinline__ void unshift_row3(RawRow3 &raw) {
+    const uint32_t sb = raw.shift * (uint32_t)sizeof(T);  // bytes, < 4 * sizeof(T)
+    uint64_t lo = (uint64_t)raw.w[0] | (uint64_t)raw.w[1] << 32;
+    uint64_t hi = (uint64_t)raw.w[2] | (uint64_t)raw.w[3] << 32;
+    if (sb >= 8) {
+        lo = hi >> (8 * (sb - 8));
+        hi = 0;
+    } else if (sb > 0) {
+        lo = (lo >> (8 * sb)) | (hi << (64 - 8 * sb));
+        hi >>= 8 * sb;
+    }
+    raw.w[0] = (uint32_t)lo; raw.w[1] = (uint32_t)(lo >> 32);
+    raw.w[2] = (uint32_t)hi; raw.w[3] = (uint32_t)(hi >> 32);
 }
 
 template <typename T, int LM, typename TH>
@@ -708,7 +732,7 @@ __device__ __forceinline__ uint32_t level3(uint32_t bits, const LevelArgs &lv, c
 // packed level pairs of one row (P[i] = (lam'[i-1], lam'[i]) with the strip
 // neighbours at both ends); rows outside the field are "never"
 template <typename T, int LM, typename TH>
-__device__ __forceinline__ void convert_row3(const RawRow3 &raw, bool row_ok, int64_t w, int64_t xs, int64_t x0,
+__device__ __forceinline__ void convert_row3(const RawRow3 &raw_in, bool row_ok, int64_t w, int64_t xs, int64_t x0,
                                              int lane, const LevelArgs &lv, const TH &thr, int lo, int W,
                                              float cpass, uint32_t (&P)[Elem3<T>::VEC + 1]) {
     constexpr int VEC = Elem3<T>::VEC;
@@ -718,6 +742,8 @@ __device__ __forceinline__ void convert_row3(const RawRow3 &raw, bool row_ok, in
         for (int i = 0; i <= VEC; ++i) P[i] = never | never << 16;
         return;
     }
+    RawRow3 raw = raw_in;
+    if (__any(raw.shift != 0)) unshift_row3<T>(raw);  // rare: blocks at the end of the buffer
     uint32_t lam[VEC];
 #pragma unroll
     for (int i = 0; i < VEC; ++i)
@@ -766,7 +792,7 @@ __device__ __forceinline__ uint32_t pk_merge(uint32_t a, uint32_t b) {
 //   tm[p]: 2D EC delta of an image pixel with pattern p, sign included
 // A voxel's low word is tl[p_layer] + (its share of the two images' deltas)
 // - 2 * (vertical neighbours that entered before it) << 22.
-template <typename T, int LM, bool ALIGNED, bool MAXIMG, bool SINGLE, int TY, typename TH>
+template <typename T, int LM, int AL, bool MAXIMG, bool SINGLE, int TY, typename TH>
 struct March3D {
     static constexpr int VEC = Elem3<T>::VEC;
     static constexpr int NR = TY + 2;
@@ -783,6 +809,7 @@ struct March3D {
     int64_t xs, x0;
     int y0, zb, lane;
     uint32_t scratch;
+    int64_t last_block;
 
     uint32_t R[3][NR][VEC + 1];  // level planes; R[(z - za + 1) % 3] holds plane z
     int32_t E[TY][VEC];          // image delta of the pixel below each voxel of the current plane
@@ -794,7 +821,8 @@ struct March3D {
 
     __device__ __forceinline__ void fetch_plane(int z, RawRow3 (&dst)[NR]) {
 #pragma unroll
-        for (int r = 0; r < NR; ++r) fetch_row3<T, ALIGNED>(data, h, w, clampz(z), clampy(y0 - 1 + r), xs, x0, lane, dst[r]);
+        for (int r = 0; r < NR; ++r)
+            fetch_row3<T, AL>(data, h, w, clampz(z), clampy(y0 - 1 + r), xs, x0, lane, last_block, dst[r]);
     }
     __device__ __forceinline__ void convert_plane(int z, const RawRow3 (&src)[NR], uint32_t (&dst)[NR][VEC + 1]) {
 #pragma unroll
@@ -896,7 +924,7 @@ struct March3D {
 
 // Work split: units (column, z) with column = (strip, block of TY rows), z
 // fastest, in equal contiguous ranges per wave.
-template <typename T, int LM, bool ALIGNED, bool MAXIMG, bool SINGLE, int TY>
+template <typename T, int LM, int AL, bool MAXIMG, bool SINGLE, int TY>
 __global__ void __launch_bounds__(256)
     ecc3d_stream(const T *__restrict__ data, int64_t d, int64_t h, int64_t w, LevelArgs lv, int32_t lo,
                  int32_t hi, float cpass, const uint32_t *__restrict__ tables, int32_t *__restrict__ partial,
@@ -939,9 +967,9 @@ __global__ void __launch_bounds__(256)
         const int64_t zb = za + (u_end - u) < D ? za + (u_end - u) : D;
         const int64_t strip = col % n_strips, yb = col / n_strips;
         const int64_t xs = strip * 64 * VEC;
-        March3D<T, LM, ALIGNED, MAXIMG, SINGLE, TY, ThrLds> m{data, (int)d, h, w, lv, thr, lo, W, cpass, tl, tm,
-                                                               hist, xs, xs + (int64_t)lane * VEC, (int)(yb * TY),
-                                                               (int)(z_lo + zb), lane, scratch};
+        March3D<T, LM, AL, MAXIMG, SINGLE, TY, ThrLds> m{data, (int)d, h, w, lv, thr, lo, W, cpass, tl, tm,
+                                                          hist, xs, xs + (int64_t)lane * VEC, (int)(yb * TY),
+                                                          (int)(z_lo + zb), lane, scratch, d * h * w - VEC};
         m.run((int)(z_lo + za));
         u += zb - za;
     }
@@ -1156,6 +1184,12 @@ size_t lds_bytes_2d(int window, int L) {
 }
 size_t lds_bytes_3d(int window, bool want_crease) { return (size_t)window * (want_crease ? 12 : 8); }
 
+int load_mode_2d(const void *data, int64_t h, int64_t w, int elem_bytes) {
+    if ((uintptr_t)data % 16 == 0 && (w * elem_bytes) % 16 == 0) return kLoadAligned;
+    const int vec = 16 / elem_bytes;
+    return h * w >= vec ? kLoadVector : kLoadElement;
+}
+
 // cells one workgroup may add to its LDS bins in a launch of `rows` rows
 static int64_t max_wg_cells_2d(int64_t rows, int64_t w, int vec, int grid) {
     const int64_t ce = 62 * vec;
@@ -1164,7 +1198,7 @@ static int64_t max_wg_cells_2d(int64_t rows, int64_t w, int vec, int grid) {
     return kWavesPerWG * ((units + NW - 1) / NW + 1) * ce;
 }
 
-template <typename T, int LM, bool AL, bool SINGLE>
+template <typename T, int LM, int AL, bool SINGLE>
 static int launch_2d_t(const Launch2D &a, hipStream_t s) {
     constexpr int VEC = Elem<T>::VEC, PF = sizeof(T) == 1 ? 3 : 6;
     const int W = a.hi - a.lo;
@@ -1189,12 +1223,19 @@ static int launch_2d_t(const Launch2D &a, hipStream_t s) {
     return 0;
 }
 
+template <typename T, int LM, bool SINGLE>
+static int launch_2d_sg(const Launch2D &a, hipStream_t s) {
+    switch (load_mode_2d(a.data, a.h, a.w, (int)sizeof(T))) {
+    case kLoadAligned: return launch_2d_t<T, LM, kLoadAligned, SINGLE>(a, s);
+    case kLoadVector: return launch_2d_t<T, LM, kLoadVector, SINGLE>(a, s);
+    default: return launch_2d_t<T, LM, kLoadElement, SINGLE>(a, s);
+    }
+}
+
 template <typename T, int LM>
 static int launch_2d_al(const Launch2D &a, hipStream_t s) {
-    const bool al = ((uintptr_t)a.data % 16 == 0) && (a.w * (int64_t)sizeof(T)) % 16 == 0;
     const bool single = a.lo == 0 && a.hi == a.lv.L;
-    if (single) return al ? launch_2d_t<T, LM, true, true>(a, s) : launch_2d_t<T, LM, false, true>(a, s);
-    return al ? launch_2d_t<T, LM, true, false>(a, s) : launch_2d_t<T, LM, false, false>(a, s);
+    return single ? launch_2d_sg<T, LM, true>(a, s) : launch_2d_sg<T, LM, false>(a, s);
 }
 
 template <typename T>
@@ -1245,7 +1286,7 @@ bool zmarch_3d_fits(int64_t h, int64_t w, int grid) {
     return max_wg_cells_3d(zmarch_3d_columns(h, w), 1, grid) <= kFlush3D;
 }
 
-template <typename T, int LM, bool AL, bool MAXIMG, bool SINGLE>
+template <typename T, int LM, int AL, bool MAXIMG, bool SINGLE>
 static int launch_zm_t(const Launch3D &a, hipStream_t s) {
     constexpr bool kThr = LM == LM_AFFINE || LM == LM_SEARCH;
     const int W = a.hi - a.lo;
@@ -1268,13 +1309,19 @@ static int launch_zm_t(const Launch3D &a, hipStream_t s) {
     return 0;
 }
 
+template <typename T, int LM, bool MAXIMG, bool SINGLE>
+static int launch_zm_sg(const Launch3D &a, hipStream_t s) {
+    constexpr int VEC = Elem3<T>::VEC, VB = VEC * (int)sizeof(T);
+    if ((uintptr_t)a.data % VB == 0 && (a.w * (int64_t)sizeof(T)) % VB == 0)
+        return launch_zm_t<T, LM, kLoadAligned, MAXIMG, SINGLE>(a, s);
+    if (a.d * a.h * a.w >= VEC) return launch_zm_t<T, LM, kLoadVector, MAXIMG, SINGLE>(a, s);
+    return launch_zm_t<T, LM, kLoadElement, MAXIMG, SINGLE>(a, s);
+}
+
 template <typename T, int LM, bool MAXIMG>
 static int launch_zm_al(const Launch3D &a, hipStream_t s) {
-    constexpr int VB = Elem3<T>::VEC * (int)sizeof(T);
-    const bool al = ((uintptr_t)a.data % VB == 0) && (a.w * (int64_t)sizeof(T)) % VB == 0;
     const bool single = a.lo == 0 && a.hi == a.lv.L;
-    if (single) return al ? launch_zm_t<T, LM, true, MAXIMG, true>(a, s) : launch_zm_t<T, LM, false, MAXIMG, true>(a, s);
-    return al ? launch_zm_t<T, LM, true, MAXIMG, false>(a, s) : launch_zm_t<T, LM, false, MAXIMG, false>(a, s);
+    return single ? launch_zm_sg<T, LM, MAXIMG, true>(a, s) : launch_zm_sg<T, LM, MAXIMG, false>(a, s);
 }
 
 template <typename T, int LM>

@@ -229,3 +229,33 @@ def test_async_on_side_stream(ctx):
     for k in ra:
         assert np.array_equal(ra[k].cpu().numpy(), oa[k])
         assert np.array_equal(rb[k].cpu().numpy(), ob[k])
+
+
+@pytest.mark.parametrize("dtype", [np.uint8, np.uint16, np.float32])
+@pytest.mark.parametrize("ndim", [2, 3])
+def test_misaligned_base_and_buffer_end(ctx, dtype, ndim):
+    """Fields that start one element into an allocation (unaligned vector loads)
+    and whose last row ends exactly at the end of the buffer view (loads
+    clamped to the buffer end and shifted back)."""
+    import torch
+    import oracle
+    rng = np.random.default_rng(21 + ndim)
+    shape = (97, 200) if ndim == 2 else (5, 7, 130)
+    for sh in (shape, (3, 5) if ndim == 2 else (2, 1, 3)):
+        n = int(np.prod(sh))
+        if dtype == np.float32:
+            a = rng.normal(size=sh).astype(np.float32)
+            thr, L = np.linspace(-2, 2, 60).astype(np.float32), 60
+        else:
+            a = rng.integers(0, 60, size=sh).astype(dtype)
+            thr, L = None, 50
+        flat = torch.zeros(n + 1, dtype=getattr(torch, np.dtype(dtype).name)).cuda()
+        flat[1:] = torch.from_numpy(a.ravel()).cuda()
+        view = flat[1:].view(*sh)
+        print(f"[case] misaligned ndim={ndim} dtype={np.dtype(dtype).name} shape={sh}", flush=True)
+        ch = None if ndim == 2 else ("ec", "area", "volume")
+        got = ctx.compute(view, L, thresholds=thr, channels=ch)
+        torch.cuda.synchronize()
+        ref = oracle.o2_curves(a, L, thresholds=thr, connectivity=8 if ndim == 2 else 26, channels=tuple(got))
+        for k in got:
+            assert np.array_equal(got[k].cpu().numpy(), ref[k]), (sh, k)
