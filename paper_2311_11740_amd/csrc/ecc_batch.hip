@@ -1,14 +1,425 @@
-// Batched entry point and serving loop (placeholder loop over single fields).
+// Batched entry point and its autotuner.
+//
+// A batch call groups its fields by kernel class: 2D fields with at most
+// kBatchMaxLevels levels and kBatchMaxCells cells go to the persistent batched
+// kernel (one launch per (dtype, level mode) group, normally a single one);
+// every other field (3D, more levels, fewer cells than one vector load) runs
+// through the single-field path on the same stream after it.
+//
+// The plan of a batch (work items, their assignment to workgroups, per-field
+// histograms and tickets, the captured graph) depends only on the shapes,
+// dtypes, level counts, connectivities and level modes of the fields, so it is
+// cached under that key and reused; a call only rewrites the per-field
+// descriptors (data and output pointers, level arguments) with one
+// host-to-device copy and replays the graph.
 #include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <functional>
+#include <map>
+#include <queue>
+#include <string>
+#include <vector>
 
 #include "ecc_runtime.h"
 
 namespace ecc {
-struct BatchState {};
+
+struct BatchGroup {
+    int dtype = 0, lm = 0;
+    std::vector<int> fields;  // descriptor slots
+    int grid = 0, max_L = 0, n_items = 0;
+    BatchItem *d_items = nullptr;
+    int32_t *d_wg_first = nullptr;
+};
+
+struct BatchPlan {
+    std::string key;
+    int item_cells = 0, wg_per_cu = 0;
+    std::vector<BatchGroup> groups;
+    std::vector<int> slot_of;  // field index -> descriptor slot, -1 = single-field path
+    std::vector<int> others;   // fields on the single-field path
+    int n_desc = 0;
+    std::vector<int32_t> n_items_of;  // per slot
+    std::vector<int64_t> hist_off;    // per slot, in int32 elements
+    BatchField2D *d_desc = nullptr, *h_desc = nullptr;
+    int32_t *d_hist = nullptr;
+    uint32_t *d_done = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipEvent_t copy_done = nullptr, last_use = nullptr;
+    bool copy_pending = false, used = false;
+    uint64_t last_tick = 0;
+};
+
+struct BatchState {
+    std::vector<BatchPlan *> plans;
+    std::map<std::string, std::pair<int, int>> tuned;  // key -> (item cells, workgroups per CU)
+    hipStream_t capture = nullptr;
+    uint64_t tick = 0;
+    uint64_t *d_luts = nullptr;  // [2][256] packed 2D per-cell deltas, 8-C then 4-C
+};
+
+constexpr size_t kMaxPlans = 8;
+constexpr int kDefaultItemCells = 64 * 1024;
+constexpr int kDefaultWgPerCu = 4;
+
+static void free_plan(BatchPlan *p) {
+    if (!p) return;
+    for (auto &g : p->groups) {
+        if (g.d_items) hipFree(g.d_items);
+        if (g.d_wg_first) hipFree(g.d_wg_first);
+    }
+    if (p->exec) hipGraphExecDestroy(p->exec);
+    if (p->graph) hipGraphDestroy(p->graph);
+    if (p->d_desc) hipFree(p->d_desc);
+    if (p->h_desc) hipHostFree(p->h_desc);
+    if (p->d_hist) hipFree(p->d_hist);
+    if (p->d_done) hipFree(p->d_done);
+    if (p->copy_done) hipEventDestroy(p->copy_done);
+    if (p->last_use) hipEventDestroy(p->last_use);
+    delete p;
+}
+
 void destroy_batch_state(ecc_context ctx) {
-    delete ctx->batch;
+    BatchState *b = ctx->batch;
+    if (!b) return;
+    for (auto *p : b->plans) free_plan(p);
+    if (b->capture) hipStreamDestroy(b->capture);
+    if (b->d_luts) hipFree(b->d_luts);
+    delete b;
     ctx->batch = nullptr;
 }
+
+static ecc_status batch_state(ecc_context ctx, BatchState **out) {
+    if (!ctx->batch) {
+        auto *b = new BatchState();
+        int e = (int)hipStreamCreateWithFlags(&b->capture, hipStreamNonBlocking);
+        if (e) {
+            delete b;
+            return hip_fail(e, "hipStreamCreate");
+        }
+        e = (int)hipMalloc(&b->d_luts, 2 * 256 * sizeof(uint64_t));
+        if (e) {
+            hipStreamDestroy(b->capture);
+            delete b;
+            return fail(ECC_ERR_OUT_OF_MEMORY, "hipMalloc(batch tables) failed");
+        }
+        for (int k = 0; k < 2; ++k) {
+            e = (int)hipMemcpy(b->d_luts + 256 * k, ctx->d_delta2[k], 256 * sizeof(uint64_t),
+                               hipMemcpyDeviceToDevice);
+            if (e) {
+                hipFree(b->d_luts);
+                hipStreamDestroy(b->capture);
+                delete b;
+                return hip_fail(e, "hipMemcpy(batch tables)");
+            }
+        }
+        ctx->batch = b;
+    }
+    *out = ctx->batch;
+    return ECC_OK;
+}
+
+// fields the batched kernel takes
+static bool batchable(const FieldInfo &fi) {
+    if (fi.ndim != 2 || fi.L > kBatchMaxLevels || fi.cells > kBatchMaxCells) return false;
+    return fi.cells >= vec_2d(fi.dtype);
+}
+
+static std::string plan_key(int n, const FieldInfo *fi, const LevelArgs *lv) {
+    std::string k;
+    k.reserve((size_t)n * 40 + 16);
+    auto put = [&k](int64_t v) { k.append(reinterpret_cast<const char *>(&v), sizeof(v)); };
+    put(n);
+    for (int i = 0; i < n; ++i) {
+        put(fi[i].ndim | fi[i].dtype << 4 | (int64_t)fi[i].conn << 8 | (int64_t)lv[i].mode << 16 |
+            (int64_t)fi[i].L << 24);
+        put(fi[i].d);
+        put(fi[i].h);
+        put(fi[i].w);
+    }
+    return k;
+}
+
+// Cut the batchable fields into items of at most `item_cells` cells (counted
+// as whole strips of 62 lanes x VEC cells per row, the work a wave does per
+// row), and deal the items to workgroups, largest first, each to the least
+// loaded one.
+static ecc_status build_plan(ecc_context ctx, BatchState *bs, int n, const FieldInfo *fi, const LevelArgs *lv,
+                             const std::string &key, int item_cells, int wg_per_cu, BatchPlan **out) {
+    auto *p = new BatchPlan();
+    p->key = key;
+    p->item_cells = item_cells;
+    p->wg_per_cu = wg_per_cu;
+    p->slot_of.assign(n, -1);
+    std::map<std::pair<int, int>, int> group_of;
+    for (int i = 0; i < n; ++i) {
+        if (!batchable(fi[i])) {
+            p->others.push_back(i);
+            continue;
+        }
+        const auto gk = std::make_pair(fi[i].dtype, lv[i].mode);
+        auto it = group_of.find(gk);
+        if (it == group_of.end()) {
+            it = group_of.emplace(gk, (int)p->groups.size()).first;
+            p->groups.emplace_back();
+            p->groups.back().dtype = fi[i].dtype;
+            p->groups.back().lm = lv[i].mode;
+        }
+        p->slot_of[i] = p->n_desc++;
+        p->groups[it->second].fields.push_back(i);
+    }
+    p->n_items_of.assign(p->n_desc, 0);
+    p->hist_off.assign(p->n_desc, 0);
+    int64_t hist_total = 0;
+    for (int i = 0; i < n; ++i)
+        if (p->slot_of[i] >= 0) {
+            p->hist_off[p->slot_of[i]] = hist_total;
+            hist_total += 3 * (int64_t)fi[i].L;
+        }
+    auto cleanup = [&](ecc_status s) {
+        free_plan(p);
+        return s;
+    };
+    for (auto &g : p->groups) {
+        const int vec = vec_2d(g.dtype), ce = 62 * vec;
+        const int64_t max_units = std::max<int64_t>(1, std::min<int64_t>(item_cells, kFlush2D) / ce);
+        std::vector<BatchItem> items;
+        std::vector<int64_t> cost;
+        for (int i : g.fields) {
+            g.max_L = std::max(g.max_L, fi[i].L);
+            const int64_t strips = (fi[i].w + ce - 1) / ce, units = strips * fi[i].h;
+            const int64_t k = (units + max_units - 1) / max_units;  // items of this field
+            for (int64_t j = 0; j < k; ++j) {
+                const int64_t u0 = units * j / k, u1 = units * (j + 1) / k;
+                items.push_back(BatchItem{p->slot_of[i], (int32_t)u0, (int32_t)u1, 0});
+                cost.push_back(u1 - u0);
+            }
+            p->n_items_of[p->slot_of[i]] = (int32_t)k;
+        }
+        const size_t lds = lds_bytes_batch_2d(g.lm, g.max_L) + 6 * 1024;
+        const int fit = std::max<int>(1, (int)((160 * 1024) / lds));
+        const int64_t G = std::min<int64_t>((int64_t)ctx->n_cu * std::min(wg_per_cu, fit), (int64_t)items.size());
+        g.grid = (int)std::max<int64_t>(1, G);
+        g.n_items = (int)items.size();
+        // largest first onto the least loaded workgroup
+        std::vector<int> order(items.size());
+        for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
+        std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
+        typedef std::pair<int64_t, int> Load;
+        std::priority_queue<Load, std::vector<Load>, std::greater<Load>> pq;
+        for (int wg = 0; wg < g.grid; ++wg) pq.push({0, wg});
+        std::vector<std::vector<int>> per_wg(g.grid);
+        for (int i : order) {
+            Load l = pq.top();
+            pq.pop();
+            per_wg[l.second].push_back(i);
+            l.first += cost[i] + 8;  // + a fixed cost per item (drain, ticket)
+            pq.push(l);
+        }
+        std::vector<BatchItem> sorted;
+        std::vector<int32_t> first(g.grid + 1, 0);
+        sorted.reserve(items.size());
+        for (int wg = 0; wg < g.grid; ++wg) {
+            first[wg] = (int32_t)sorted.size();
+            for (int i : per_wg[wg]) sorted.push_back(items[i]);
+        }
+        first[g.grid] = (int32_t)sorted.size();
+        int e = (int)hipMalloc(&g.d_items, sizeof(BatchItem) * std::max<size_t>(1, sorted.size()));
+        if (e) return cleanup(fail(ECC_ERR_OUT_OF_MEMORY, "hipMalloc(batch items) failed"));
+        e = (int)hipMalloc(&g.d_wg_first, sizeof(int32_t) * first.size());
+        if (e) return cleanup(fail(ECC_ERR_OUT_OF_MEMORY, "hipMalloc(batch schedule) failed"));
+        e = (int)hipMemcpy(g.d_items, sorted.data(), sizeof(BatchItem) * sorted.size(), hipMemcpyHostToDevice);
+        if (!e) e = (int)hipMemcpy(g.d_wg_first, first.data(), sizeof(int32_t) * first.size(), hipMemcpyHostToDevice);
+        if (e) return cleanup(hip_fail(e, "hipMemcpy(batch plan)"));
+    }
+    if (p->n_desc > 0) {
+        int e = (int)hipMalloc(&p->d_desc, sizeof(BatchField2D) * p->n_desc);
+        if (e) return cleanup(fail(ECC_ERR_OUT_OF_MEMORY, "hipMalloc(batch descriptors) failed"));
+        e = (int)hipHostMalloc(&p->h_desc, sizeof(BatchField2D) * p->n_desc, 0);
+        if (e) return cleanup(hip_fail(e, "hipHostMalloc(batch descriptors)"));
+        e = (int)hipMalloc(&p->d_hist, sizeof(int32_t) * std::max<int64_t>(1, hist_total));
+        if (e) return cleanup(fail(ECC_ERR_OUT_OF_MEMORY, "hipMalloc(batch histograms) failed"));
+        e = (int)hipMalloc(&p->d_done, sizeof(uint32_t) * p->n_desc);
+        if (e) return cleanup(fail(ECC_ERR_OUT_OF_MEMORY, "hipMalloc(batch tickets) failed"));
+        // the kernel leaves both at zero after every launch
+        e = (int)hipMemset(p->d_hist, 0, sizeof(int32_t) * std::max<int64_t>(1, hist_total));
+        if (!e) e = (int)hipMemset(p->d_done, 0, sizeof(uint32_t) * p->n_desc);
+        if (!e) e = (int)hipDeviceSynchronize();
+        if (e) return cleanup(hip_fail(e, "hipMemset(batch workspace)"));
+    }
+    int e = (int)hipEventCreateWithFlags(&p->copy_done, hipEventDisableTiming);
+    if (!e) e = (int)hipEventCreateWithFlags(&p->last_use, hipEventDisableTiming);
+    if (e) return cleanup(hip_fail(e, "hipEventCreate"));
+    // capture the group launches into a graph; on failure the call launches them directly
+    if (!p->groups.empty()) {
+        bool ok = hipStreamBeginCapture(bs->capture, hipStreamCaptureModeRelaxed) == hipSuccess;
+        bool launched = ok;
+        for (auto &g : p->groups)
+            if (launched)
+                launched = launch_batch_2d(g.dtype, g.lm, p->d_desc, g.d_items, g.d_wg_first, g.grid, bs->d_luts,
+                                           g.max_L, bs->capture) == 0;
+        if (ok) ok = hipStreamEndCapture(bs->capture, &p->graph) == hipSuccess && launched;
+        if (ok) ok = hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0) == hipSuccess;
+        if (!ok) {
+            if (p->exec) hipGraphExecDestroy(p->exec);
+            if (p->graph) hipGraphDestroy(p->graph);
+            p->exec = nullptr;
+            p->graph = nullptr;
+            (void)hipGetLastError();
+        }
+    }
+    *out = p;
+    return ECC_OK;
+}
+
+static ecc_status find_or_build_plan(ecc_context ctx, BatchState *bs, int n, const FieldInfo *fi,
+                                     const LevelArgs *lv, int force_item_cells, int force_wpc, BatchPlan **out) {
+    const std::string key = plan_key(n, fi, lv);
+    const bool forced = force_item_cells > 0;
+    if (!forced)
+        for (auto *p : bs->plans)
+            if (p->key == key) {
+                p->last_tick = ++bs->tick;
+                *out = p;
+                return ECC_OK;
+            }
+    int cells = kDefaultItemCells, wpc = kDefaultWgPerCu;
+    auto t = bs->tuned.find(key);
+    if (t != bs->tuned.end()) {
+        cells = t->second.first;
+        wpc = t->second.second;
+    }
+    if (forced) {
+        cells = force_item_cells;
+        wpc = force_wpc;
+    }
+    BatchPlan *p = nullptr;
+    ecc_status s = build_plan(ctx, bs, n, fi, lv, key, cells, wpc, &p);
+    if (s != ECC_OK) return s;
+    p->last_tick = ++bs->tick;
+    if (!forced) {
+        if (bs->plans.size() >= kMaxPlans) {  // evict the least recently used plan
+            auto lru = std::min_element(bs->plans.begin(), bs->plans.end(),
+                                        [](BatchPlan *a, BatchPlan *b) { return a->last_tick < b->last_tick; });
+            int e = (int)hipEventSynchronize((*lru)->last_use);
+            if (e) {
+                free_plan(p);
+                return hip_fail(e, "hipEventSynchronize");
+            }
+            free_plan(*lru);
+            bs->plans.erase(lru);
+        }
+        bs->plans.push_back(p);
+    }
+    *out = p;
+    return ECC_OK;
+}
+
+// Queue one run of a plan on `stream`: descriptors, the graph (or the group
+// launches), then the fields of the single-field path.
+static ecc_status run_plan(ecc_context ctx, BatchState *bs, BatchPlan *p, int n, const ecc_field *fields,
+                           const ecc_curves *curves, const FieldInfo *fi, const LevelArgs *lv, void *stream) {
+    hipStream_t st = (hipStream_t)stream;
+    int e;
+    if (p->used) {  // after the previous run of this plan (its histograms and tickets)
+        e = (int)hipStreamWaitEvent(st, p->last_use, 0);
+        if (e) return hip_fail(e, "hipStreamWaitEvent");
+    }
+    if (p->n_desc > 0) {
+        if (p->copy_pending) {  // the pinned descriptors may still be in flight
+            e = (int)hipEventSynchronize(p->copy_done);
+            if (e) return hip_fail(e, "hipEventSynchronize");
+        }
+        for (int i = 0; i < n; ++i) {
+            const int sl = p->slot_of[i];
+            if (sl < 0) continue;
+            BatchField2D &d = p->h_desc[sl];
+            std::memset(&d, 0, sizeof(d));
+            d.data = fields[i].data;
+            d.h = fi[i].h;
+            d.w = fi[i].w;
+            d.out[0] = curves[i].ec;
+            d.out[1] = curves[i].perimeter;
+            d.out[2] = curves[i].area;
+            d.hist = p->d_hist + p->hist_off[sl];
+            d.done = p->d_done + sl;
+            d.thr = lv[i].thr;
+            d.lut = lv[i].lut;
+            d.L = fi[i].L;
+            d.n_items = p->n_items_of[sl];
+            d.conn_idx = fi[i].conn == 8 ? 0 : 1;
+            d.inv_step = lv[i].inv_step;
+            d.cpass = (float)(lv[i].u0d + 1.5);
+            d.eps = lv[i].eps;
+        }
+        e = (int)hipMemcpyAsync(p->d_desc, p->h_desc, sizeof(BatchField2D) * p->n_desc, hipMemcpyHostToDevice, st);
+        if (e) return hip_fail(e, "hipMemcpyAsync(batch descriptors)");
+        e = (int)hipEventRecord(p->copy_done, st);
+        if (e) return hip_fail(e, "hipEventRecord");
+        p->copy_pending = true;
+        int slot = -1;
+        ecc_status s = prof_begin(ctx, stream, &slot);
+        if (s != ECC_OK) return s;
+        if (p->exec) {
+            e = (int)hipGraphLaunch(p->exec, st);
+            if (e) return hip_fail(e, "hipGraphLaunch");
+        } else {
+            for (auto &g : p->groups) {
+                e = launch_batch_2d(g.dtype, g.lm, p->d_desc, g.d_items, g.d_wg_first, g.grid, bs->d_luts, g.max_L,
+                                    stream);
+                if (e) return hip_fail(e, "batched kernel launch");
+            }
+        }
+        s = prof_end(ctx, stream, slot);
+        if (s != ECC_OK) return s;
+    }
+    if (!p->others.empty()) {
+        ecc_status s = acquire_workspace(ctx, stream);
+        if (s != ECC_OK) return s;
+        for (int i : p->others) {
+            s = compute_one(ctx, &fields[i], fi[i], &curves[i], stream);
+            if (s != ECC_OK) break;
+        }
+        ecc_status s2 = release_workspace(ctx, stream);
+        if (s != ECC_OK) return s;
+        if (s2 != ECC_OK) return s2;
+    }
+    e = (int)hipEventRecord(p->last_use, st);
+    if (e) return hip_fail(e, "hipEventRecord");
+    p->used = true;
+    return ECC_OK;
+}
+
+// validation and level arguments of every field (thresholds uploaded once per
+// distinct array)
+static ecc_status prepare(ecc_context ctx, int n, const ecc_field *fields, const ecc_curves *curves,
+                          void *stream, std::vector<FieldInfo> &fi, std::vector<LevelArgs> &lv) {
+    fi.resize(n);
+    lv.resize(n);
+    for (int i = 0; i < n; ++i) {
+        ecc_status s = validate_field(&fields[i], &curves[i], &fi[i], false);
+        if (s != ECC_OK) return s;
+    }
+    std::vector<const float *> distinct;
+    for (int i = 0; i < n; ++i) {
+        if (!fields[i].thresholds) continue;
+        bool seen = false;
+        for (const float *t : distinct)
+            if (t == fields[i].thresholds) seen = true;
+        if (!seen) distinct.push_back(fields[i].thresholds);
+    }
+    ecc_status s = reserve_thresholds(ctx, (int)distinct.size());
+    if (s != ECC_OK) return s;
+    for (int i = 0; i < n; ++i) {
+        s = level_args(ctx, &fields[i], fi[i], stream, &lv[i]);
+        if (s != ECC_OK) return s;
+    }
+    return ECC_OK;
+}
+
 }  // namespace ecc
 
 using namespace ecc;
@@ -18,35 +429,110 @@ extern "C" ecc_status ecc_curves_compute_batch(ecc_context ctx, int32_t n, const
     clear_error();
     if (!ctx) return fail(ECC_ERR_INVALID_ARG, "context is NULL");
     if (n < 0 || (n > 0 && (!fields || !curves))) return fail(ECC_ERR_INVALID_ARG, "bad batch arrays");
-    std::vector<FieldInfo> infos(n);
-    for (int i = 0; i < n; ++i) {
-        ecc_status s = validate_field(&fields[i], &curves[i], &infos[i], false);
+    if (n == 0) return ECC_OK;
+    for (int i = 0; i < n; ++i) {  // host-only checks before any device work
+        FieldInfo f;
+        ecc_status s = validate_field(&fields[i], &curves[i], &f, false);
         if (s != ECC_OK) return s;
     }
     std::lock_guard<std::mutex> lk(ctx->mu);
     int e = (int)hipSetDevice(ctx->device);
     if (e) return hip_fail(e, "hipSetDevice");
-    ecc_status s = acquire_workspace(ctx, stream);
+    std::vector<FieldInfo> fi;
+    std::vector<LevelArgs> lv;
+    ecc_status s = prepare(ctx, n, fields, curves, stream, fi, lv);
     if (s != ECC_OK) return s;
-    for (int i = 0; i < n && s == ECC_OK; ++i) s = compute_one(ctx, &fields[i], infos[i], &curves[i], stream);
-    ecc_status s2 = release_workspace(ctx, stream);
-    return s != ECC_OK ? s : s2;
+    BatchState *bs = nullptr;
+    s = batch_state(ctx, &bs);
+    if (s != ECC_OK) return s;
+    BatchPlan *p = nullptr;
+    s = find_or_build_plan(ctx, bs, n, fi.data(), lv.data(), 0, 0, &p);
+    if (s != ECC_OK) return s;
+    return run_plan(ctx, bs, p, n, fields, curves, fi.data(), lv.data(), stream);
 }
 
 extern "C" ecc_status ecc_batch_plan_tune(ecc_context ctx, int32_t n, const ecc_field *fields, void *stream) {
-    (void)n; (void)fields; (void)stream;
+    clear_error();
     if (!ctx) return fail(ECC_ERR_INVALID_ARG, "context is NULL");
+    if (n < 0 || (n > 0 && !fields)) return fail(ECC_ERR_INVALID_ARG, "bad batch arrays");
+    if (n == 0) return ECC_OK;
+    // trial runs write no curves; validation sees one (unused) output so that
+    // it accepts the request
+    std::vector<ecc_curves> none(n), probe(n);
+    std::memset(none.data(), 0, sizeof(ecc_curves) * n);
+    std::memset(probe.data(), 0, sizeof(ecc_curves) * n);
+    static int64_t dummy;
+    for (int i = 0; i < n; ++i) {
+        probe[i].ec = &dummy;
+        FieldInfo f;
+        ecc_status s = validate_field(&fields[i], &probe[i], &f, false);
+        if (s != ECC_OK) return s;
+    }
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    int e = (int)hipSetDevice(ctx->device);
+    if (e) return hip_fail(e, "hipSetDevice");
+    std::vector<FieldInfo> fi;
+    std::vector<LevelArgs> lv;
+    ecc_status s = prepare(ctx, n, fields, probe.data(), stream, fi, lv);
+    if (s != ECC_OK) return s;
+    BatchState *bs = nullptr;
+    s = batch_state(ctx, &bs);
+    if (s != ECC_OK) return s;
+    hipStream_t st = (hipStream_t)stream;
+    hipEvent_t t0, t1;
+    e = (int)hipEventCreate(&t0);
+    if (e) return hip_fail(e, "hipEventCreate");
+    e = (int)hipEventCreate(&t1);
+    if (e) {
+        hipEventDestroy(t0);
+        return hip_fail(e, "hipEventCreate");
+    }
+    const bool prof = ctx->prof_on;
+    ctx->prof_on = false;  // trial runs are not reported
+    const int cells_c[] = {16 * 1024, 32 * 1024, 64 * 1024, 128 * 1024, 256 * 1024};
+    const int wpc_c[] = {2, 4, 8};
+    float best = 1e30f;
+    std::pair<int, int> best_cfg(kDefaultItemCells, kDefaultWgPerCu);
+    for (int cells : cells_c)
+        for (int wpc : wpc_c) {
+            BatchPlan *p = nullptr;
+            s = find_or_build_plan(ctx, bs, n, fi.data(), lv.data(), cells, wpc, &p);
+            if (s != ECC_OK) break;
+            float ms = 1e30f;
+            for (int rep = 0; rep < 3 && s == ECC_OK; ++rep) {
+                e = (int)hipEventRecord(t0, st);
+                if (!e) s = run_plan(ctx, bs, p, n, fields, none.data(), fi.data(), lv.data(), stream);
+                if (!e && s == ECC_OK) e = (int)hipEventRecord(t1, st);
+                if (!e && s == ECC_OK) e = (int)hipEventSynchronize(t1);
+                float t = 0.f;
+                if (!e && s == ECC_OK) e = (int)hipEventElapsedTime(&t, t0, t1);
+                if (e && s == ECC_OK) s = hip_fail(e, "timing a trial run");
+                if (rep > 0 && s == ECC_OK) ms = std::min(ms, t);  // first run warms up
+            }
+            const int e2 = (int)hipStreamSynchronize(st);
+            free_plan(p);
+            if (s != ECC_OK) break;
+            if (e2) {
+                s = hip_fail(e2, "hipStreamSynchronize");
+                break;
+            }
+            if (ms < best) {
+                best = ms;
+                best_cfg = {cells, wpc};
+            }
+        }
+    ctx->prof_on = prof;
+    hipEventDestroy(t0);
+    hipEventDestroy(t1);
+    if (s != ECC_OK) return s;
+    const std::string key = plan_key(n, fi.data(), lv.data());
+    bs->tuned[key] = best_cfg;
+    for (auto it = bs->plans.begin(); it != bs->plans.end(); ++it)  // rebuild with the tuned geometry
+        if ((*it)->key == key) {
+            hipEventSynchronize((*it)->last_use);
+            free_plan(*it);
+            bs->plans.erase(it);
+            break;
+        }
     return ECC_OK;
 }
-
-extern "C" ecc_status ecc_server_create(ecc_context, const ecc_server_config *, ecc_server *) {
-    return fail(ECC_ERR_UNSUPPORTED, "serving is not built yet");
-}
-extern "C" ecc_status ecc_server_submit(ecc_server, const ecc_field *, const ecc_curves *, uint64_t *) {
-    return fail(ECC_ERR_UNSUPPORTED, "serving is not built yet");
-}
-extern "C" ecc_status ecc_server_poll(ecc_server, uint64_t, int32_t *) {
-    return fail(ECC_ERR_UNSUPPORTED, "serving is not built yet");
-}
-extern "C" ecc_status ecc_server_drain(ecc_server) { return fail(ECC_ERR_UNSUPPORTED, "serving is not built yet"); }
-extern "C" ecc_status ecc_server_destroy(ecc_server) { return ECC_OK; }

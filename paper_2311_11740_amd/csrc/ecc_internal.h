@@ -93,6 +93,32 @@ struct Launch3D {
     bool conn6;
 };
 
+// ---- batched 2D launch ----------------------------------------------------------
+// One descriptor per field of the batch (device memory, rewritten every call).
+struct BatchField2D {
+    const void *data;
+    int64_t h, w;
+    int64_t *out[3];      // ec, perimeter, area (NULL = not wanted)
+    int32_t *hist;        // [3][L] per-level deltas; zero between launches
+    uint32_t *done;       // items of this field finished; zero between launches
+    const float *thr;     // LM_AFFINE / LM_SEARCH thresholds (device)
+    const uint16_t *lut;  // LM_LUT level table (device)
+    int32_t L, n_items, conn_idx, pad0;  // conn_idx 0 = 8-C, 1 = 4-C
+    float inv_step, cpass, eps, pad1;    // LM_AFFINE (cpass of the single pass)
+};
+// A work item: (strip, row) units [u0, u1) of one field, strip-major.
+struct BatchItem {
+    int32_t field, u0, u1, pad;
+};
+// Largest field and level count the batched kernel takes (others go through
+// the single-field path).
+constexpr int64_t kBatchMaxCells = int64_t(1) << 28;
+constexpr int kBatchMaxLevels = 4096;
+// Items of workgroup g are items[wg_first[g] .. wg_first[g+1]).
+int launch_batch_2d(int dtype, int lm, const BatchField2D *fields, const BatchItem *items,
+                    const int32_t *wg_first, int grid, const uint64_t *luts, int max_L, void *stream);
+size_t lds_bytes_batch_2d(int lm, int max_L);
+
 // device-side launchers (ecc_kernels.hip); return a hipError_t as int
 int launch_2d(const Launch2D &a, void *stream);
 int launch_3d(const Launch3D &a, void *stream);

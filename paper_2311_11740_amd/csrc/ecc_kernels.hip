@@ -540,6 +540,120 @@ __global__ void __launch_bounds__(256)
 }
 
 // ---------------------------------------------------------------------------
+// 2D batched: many fields in one persistent launch
+// ---------------------------------------------------------------------------
+// The host cuts every field into items of (strip, row) units and assigns
+// items to workgroups.  A workgroup runs its items one after another with the
+// single-field machinery (its four waves split an item's units), draining its
+// LDS bins into the field's global per-level histogram after each item.  The
+// workgroup that finishes a field's last item (a ticket counter per field)
+// scans that histogram into the field's curves and clears it, so one launch
+// covers every field with no second pass.
+template <typename T, int LM>
+__global__ void __launch_bounds__(256)
+    ecc2d_batch(const BatchField2D *__restrict__ fields, const BatchItem *__restrict__ items,
+                const int32_t *__restrict__ wg_first, const uint64_t *__restrict__ luts) {
+    constexpr int PF = sizeof(T) == 1 ? 3 : 6;
+    constexpr bool kThr = LM == LM_AFFINE || LM == LM_SEARCH;
+    extern __shared__ uint64_t smem[];
+    __shared__ uint64_t dl[2][256];
+    __shared__ int64_t part[256];
+    __shared__ int last;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    dl[0][tid] = luts[tid];
+    dl[1][tid] = luts[256 + tid];
+    const int i_beg = wg_first[blockIdx.x], i_end = wg_first[blockIdx.x + 1];
+    const bool halo_lane = lane == 0 || lane == 63;
+    const uint32_t mask_or_off = halo_lane ? 0u : 0xFFFFFFFFu;
+    for (int it = i_beg; it < i_end; ++it) {
+        const BatchItem item = items[it];
+        const BatchField2D &f = fields[item.field];
+        const int L = f.L;
+        const int h = (int)f.h;
+        const int64_t w = f.w;
+        uint64_t *hist = smem;
+        float *thr_s = reinterpret_cast<float *>(smem + L + 2);
+        for (int b = tid; b < L + 2; b += 256) hist[b] = 0;
+        if (kThr)
+            for (int i = tid; i < L + 3; i += 256) {
+                int k = i - 2;
+                k = k < 0 ? 0 : (k >= L ? L - 1 : k);
+                thr_s[i] = f.thr[k];
+            }
+        __syncthreads();
+        LevelArgs lv;
+        lv.L = L;
+        lv.mode = LM;
+        lv.thr = f.thr;
+        lv.lut = f.lut;
+        lv.u0 = 0.f;
+        lv.inv_step = f.inv_step;
+        lv.u0d = 0.0;
+        lv.eps = f.eps;
+        const ThrLds thr{thr_s, -2};
+        const int n = item.u1 - item.u0;
+        const int u_end = item.u0 + (int)((int64_t)n * (wave + 1) / kWavesPerWG);
+        for (int u = item.u0 + (int)((int64_t)n * wave / kWavesPerWG); u < u_end;) {
+            const int strip = u / h, ra = u % h;
+            const int rb = ra + (u_end - u) < h ? ra + (u_end - u) : h;
+            stream_run_2d<T, LM, kLoadVector, PF, true>((const T *)f.data, h, w, lv, thr, 0, L, f.cpass,
+                                                        dl[f.conn_idx], hist, strip, ra, rb, lane, mask_or_off,
+                                                        (uint32_t)(L + lane));
+            u += rb - ra;
+        }
+        __syncthreads();
+        // bins -> the field's global histogram (levels hist[1..L])
+        for (int b = tid + 1; b <= L; b += 256) {
+            const uint64_t v = hist[b];
+            if (v == 0) continue;
+            const int64_t cnt = (int64_t)(v >> kShiftCnt2);
+            const int64_t per = (int64_t)((v >> kShiftPer2) & ((1ull << (kShiftCnt2 - kShiftPer2)) - 1)) -
+                                kPerBias2 * cnt;
+            const int64_t ec = (int64_t)(v & ((1ull << kShiftPer2) - 1)) - kEcBias2 * cnt;
+            int32_t *dst = f.hist + (b - 1);
+            if (ec) atomicAdd(dst, (int32_t)ec);
+            if (per) atomicAdd(dst + L, (int32_t)per);
+            atomicAdd(dst + 2 * L, (int32_t)cnt);
+        }
+        // publish (every thread's atomics), take the field's ticket
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        __syncthreads();
+        if (tid == 0)
+            last = __hip_atomic_fetch_add(f.done, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT) ==
+                   (uint32_t)(f.n_items - 1);
+        __syncthreads();
+        if (last) {  // uniform: scan the field's histogram into its curves and clear it
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            const int per = (L + 255) / 256;
+            const int beg = tid * per, end = beg + per < L ? beg + per : L;
+            for (int ch = 0; ch < 3; ++ch) {
+                int32_t *src = f.hist + (int64_t)ch * L;
+                int64_t *dst = f.out[ch];
+                int64_t s = 0;
+                for (int i = beg; i < end; ++i) s += src[i];
+                part[tid] = s;
+                __syncthreads();
+                for (int off = 1; off < 256; off <<= 1) {  // inclusive scan of the chunk sums
+                    const int64_t v = tid >= off ? part[tid - off] : 0;
+                    __syncthreads();
+                    part[tid] += v;
+                    __syncthreads();
+                }
+                int64_t run = part[tid] - s;
+                for (int i = beg; i < end; ++i) {
+                    run += src[i];
+                    src[i] = 0;
+                    if (dst) dst[i] = run;
+                }
+                __syncthreads();
+            }
+            if (tid == 0) *f.done = 0u;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // 3D bins -> partials
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ void drain_3d(uint64_t *hist, uint32_t *hc, bool crease, int W, int lo,
@@ -1346,6 +1460,42 @@ int launch_3d(const Launch3D &a, void *stream) {
     case ECC_U8: return launch_3d_dt<uint8_t>(a, s);
     case ECC_U16: return launch_3d_dt<uint16_t>(a, s);
     default: return launch_3d_dt<float>(a, s);
+    }
+}
+
+size_t lds_bytes_batch_2d(int lm, int max_L) {
+    const bool thr = lm == LM_AFFINE || lm == LM_SEARCH;
+    return (size_t)(max_L + 2) * 8 + (thr ? (size_t)(max_L + 3) * 4 : 0);
+}
+
+template <typename T>
+static int launch_batch_t(int lm, const BatchField2D *fields, const BatchItem *items, const int32_t *wg_first,
+                          int grid, const uint64_t *luts, size_t lds, hipStream_t s) {
+    switch (lm) {
+    case LM_IDENTITY:
+        hipLaunchKernelGGL((ecc2d_batch<T, LM_IDENTITY>), dim3(grid), dim3(256), lds, s, fields, items, wg_first, luts);
+        break;
+    case LM_LUT:
+        hipLaunchKernelGGL((ecc2d_batch<T, LM_LUT>), dim3(grid), dim3(256), lds, s, fields, items, wg_first, luts);
+        break;
+    case LM_AFFINE:
+        hipLaunchKernelGGL((ecc2d_batch<T, LM_AFFINE>), dim3(grid), dim3(256), lds, s, fields, items, wg_first, luts);
+        break;
+    default:
+        hipLaunchKernelGGL((ecc2d_batch<T, LM_SEARCH>), dim3(grid), dim3(256), lds, s, fields, items, wg_first, luts);
+        break;
+    }
+    return (int)hipGetLastError();
+}
+
+int launch_batch_2d(int dtype, int lm, const BatchField2D *fields, const BatchItem *items,
+                    const int32_t *wg_first, int grid, const uint64_t *luts, int max_L, void *stream) {
+    const size_t lds = lds_bytes_batch_2d(lm, max_L);
+    hipStream_t s = (hipStream_t)stream;
+    switch (dtype) {
+    case ECC_U8: return launch_batch_t<uint8_t>(lm, fields, items, wg_first, grid, luts, lds, s);
+    case ECC_U16: return launch_batch_t<uint16_t>(lm, fields, items, wg_first, grid, luts, lds, s);
+    default: return launch_batch_t<float>(lm, fields, items, wg_first, grid, luts, lds, s);
     }
 }
 

@@ -80,6 +80,9 @@ ecc_status hip_fail(int err, const char *what);
 ecc_status validate_field(const ecc_field *f, const ecc_curves *c, FieldInfo *info, bool curves_on_host);
 void free_thresholds(ThrEntry *t);
 ecc_status level_args(ecc_context ctx, const ecc_field *f, const FieldInfo &fi, void *stream, LevelArgs *lv);
+// make room in the threshold cache for n_new arrays, so that fetching them
+// evicts none of the others (drops the whole cache after a device sync if needed)
+ecc_status reserve_thresholds(ecc_context ctx, int n_new);
 ecc_status acquire_workspace(ecc_context ctx, void *stream);
 ecc_status release_workspace(ecc_context ctx, void *stream);
 ecc_status grow(ecc_context ctx, DevBuf &b, size_t need, const char *what);

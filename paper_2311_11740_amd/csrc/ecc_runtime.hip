@@ -327,6 +327,18 @@ ecc_status get_thresholds(ecc_context ctx, const float *thr, int L, int dtype, v
     return ECC_OK;
 }
 
+ecc_status reserve_thresholds(ecc_context ctx, int n_new) {
+    if (n_new > (int)kThrCacheMax)
+        return fail(ECC_ERR_UNSUPPORTED, "a batch may use at most 32 distinct threshold arrays");
+    if (ctx->thr_cache.size() + (size_t)n_new > kThrCacheMax) {
+        int e = (int)hipDeviceSynchronize();
+        if (e) return hip_fail(e, "hipDeviceSynchronize");
+        for (auto *t : ctx->thr_cache) free_thresholds(t);
+        ctx->thr_cache.clear();
+    }
+    return ECC_OK;
+}
+
 ecc_status level_args(ecc_context ctx, const ecc_field *f, const FieldInfo &fi, void *stream,
                       LevelArgs *lv) {
     lv->L = fi.L;

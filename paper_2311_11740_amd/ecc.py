@@ -242,35 +242,79 @@ class Context:
         del keep
         return out
 
-    def compute_batch(self, fields, n_levels, thresholds=None, connectivity: int = 0,
+    def batch(self, fields, n_levels, thresholds=None, connectivity=0, channels=None):
+        """A reusable batched call over `fields` (device tensors); see Batch."""
+        return Batch(self, fields, n_levels, thresholds, connectivity, channels)
+
+    def compute_batch(self, fields, n_levels, thresholds=None, connectivity=0,
                       channels: Sequence[str] | None = None, stream=None):
         """Curves of many device fields in one batched call; list of dicts."""
+        b = Batch(self, fields, n_levels, thresholds, connectivity, channels)
+        b.run(stream)
+        return b.outputs
+
+    def tune_batch(self, fields, n_levels, thresholds=None, connectivity=0, stream=None):
+        """Run the autotuner for this mix of fields (synchronises `stream`)."""
+        Batch(self, fields, n_levels, thresholds, connectivity, ()).tune(stream)
+
+
+class Batch:
+    """Descriptors of a batched call, built once and run many times.
+
+    fields: device tensors (2D or 3D, any mix); n_levels, thresholds and
+    connectivity: one value for all fields or a list with one per field.
+    `outputs[i]` maps each wanted channel to an int64 device tensor of that
+    field's n_levels (views into one allocation)."""
+
+    def __init__(self, ctx, fields, n_levels, thresholds=None, connectivity=0, channels=None):
+        torch = _torch()
         n = len(fields)
-        if not isinstance(n_levels, (list, tuple)):
-            n_levels = [n_levels] * n
+
+        def per(v):
+            return list(v) if isinstance(v, (list, tuple)) else [v] * n
+
+        n_levels, connectivity = per(n_levels), per(connectivity)
         if thresholds is None or not isinstance(thresholds, (list, tuple)):
             thresholds = [thresholds] * n
-        farr = (Field * n)()
-        carr = (Curves * n)()
-        keeps, outs = [], []
-        for i, t in enumerate(fields):
-            f, keep = make_field(t, n_levels[i], thresholds[i], connectivity)
-            o, cv = alloc_curves(t.dim(), n_levels[i], t.device, channels)
-            farr[i] = f
-            carr[i] = cv
-            keeps.append(keep)
-            outs.append(o)
-        check(self._lib.ecc_curves_compute_batch(self.handle, n, farr, carr, _stream_ptr(stream)))
-        return outs
+        self.ctx = ctx
+        self.n = n
+        self.fields = list(fields)
+        self.farr = (Field * max(n, 1))()
+        self.carr = (Curves * max(n, 1))()
+        self._keep = []
+        chans = []
+        total = 0
+        for i, t in enumerate(self.fields):
+            allowed = CHANNELS_2D if t.dim() == 2 else CHANNELS_3D
+            ch = allowed if channels is None else tuple(c for c in channels if c in allowed)
+            chans.append(ch)
+            total += len(ch) * int(n_levels[i])
+        dev = self.fields[0].device if n else "cpu"
+        self.buffer = torch.empty(max(total, 1), dtype=torch.int64, device=dev)
+        self.outputs = []
+        off = 0
+        for i, t in enumerate(self.fields):
+            f, keep = make_field(t, n_levels[i], thresholds[i], connectivity[i])
+            self.farr[i] = f
+            self._keep.append(keep)
+            o = {}
+            cv = Curves()
+            for c in ("ec", "perimeter", "area", "volume"):
+                if c in chans[i]:
+                    o[c] = self.buffer[off:off + int(n_levels[i])]
+                    off += int(n_levels[i])
+                    setattr(cv, c, o[c].data_ptr())
+                else:
+                    setattr(cv, c, None)
+            self.carr[i] = cv
+            self.outputs.append(o)
 
-    def tune_batch(self, fields, n_levels, thresholds=None, connectivity: int = 0, stream=None):
-        n = len(fields)
-        if not isinstance(n_levels, (list, tuple)):
-            n_levels = [n_levels] * n
-        farr = (Field * n)()
-        keeps = []
-        for i, t in enumerate(fields):
-            f, keep = make_field(t, n_levels[i], thresholds, connectivity)
-            farr[i] = f
-            keeps.append(keep)
-        check(self._lib.ecc_batch_plan_tune(self.handle, n, farr, _stream_ptr(stream)))
+    def run(self, stream=None):
+        """Queue the batched call on `stream` (asynchronous)."""
+        check(self.ctx._lib.ecc_curves_compute_batch(self.ctx.handle, self.n, self.farr, self.carr,
+                                                     _stream_ptr(stream)))
+        return self.outputs
+
+    def tune(self, stream=None):
+        """Autotune the launch geometry for this mix (synchronises `stream`)."""
+        check(self.ctx._lib.ecc_batch_plan_tune(self.ctx.handle, self.n, self.farr, _stream_ptr(stream)))
