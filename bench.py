@@ -120,19 +120,14 @@ def cpu_baseline(spec, gpu_curves):
                        f"all-levels C oracle, one run of {dt:.2f} s"), ok
 
 
-STEPS_CTX = {"steps": 1}
-
-
-def measure(ctx, name, steps, warmup, copies, with_cpu):
-    STEPS_CTX["steps"] = steps
-    spec = make_workload(name)
+def measure(ctx, spec, steps, warmup, copies, with_cpu):
     r = time_field(ctx, spec, steps, warmup, copies)
     cells = spec.data.size
     elem = spec.data.dtype.itemsize
     value = cells / (r["ms_per_step"] / 1e3) / 1e9
     kernel = "ecc2d_stream" if spec.data.ndim == 2 else "ecc3d_stream"
     alg_bytes = cells * elem  # the field-reading kernel reads every cell once per step
-    launches_per_step = r["kernel_launches"] / max(1, STEPS_CTX["steps"])
+    launches_per_step = r["kernel_launches"] / max(1, steps)
     achieved = alg_bytes / (r["kernel_ms_per_step"] / 1e3) / 1e9
     traffic = load_traffic(kernel, spec.meta["name"])
     out = dict(
@@ -152,6 +147,82 @@ def measure(ctx, name, steps, warmup, copies, with_cpu):
     return out
 
 
+def timed_calls(fn, steps):
+    """(ms per call on the GPU clock, ms per call on the host clock) of `steps` calls."""
+    import torch
+    stream = torch.cuda.current_stream()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    t0.record(stream)
+    for _ in range(steps):
+        fn(stream)
+    t1.record(stream)
+    torch.cuda.synchronize()
+    return t0.elapsed_time(t1) / steps, (time.perf_counter() - w0) * 1e3 / steps
+
+
+def measure_batch(ctx, specs, steps, warmup):
+    """Batched call vs one call per field over the same fields (already in HBM)."""
+    import numpy as np
+    import torch
+    import oracle
+    sizes = [s.data.size for s in specs]
+    offs = np.cumsum([0] + sizes)
+    host = np.empty(int(offs[-1]), np.uint8)
+    for i, s in enumerate(specs):
+        host[offs[i]:offs[i + 1]] = s.data.ravel()
+    dev = torch.from_numpy(host).cuda()
+    views = [dev[int(offs[i]):int(offs[i + 1])].view(*specs[i].data.shape) for i in range(len(specs))]
+    L = specs[0].n_levels
+    b = ctx.batch(views, L, connectivity=8)
+    ref = ctx.batch(views, L, connectivity=8)
+    for _ in range(warmup):
+        ref.run_per_field(torch.cuda.current_stream())
+    pf_ms, pf_wall = timed_calls(ref.run_per_field, max(3, steps // 4))
+    for _ in range(warmup):
+        b.run(torch.cuda.current_stream())
+    ctx.profile(True)
+    ctx.profile_read(reset=True)
+    bd_ms, bd_wall = timed_calls(b.run, steps)
+    k_ms, k_n = ctx.profile_read(reset=True)
+    ctx.profile(False)
+    equal_default = bool(torch.equal(b.buffer, ref.buffer))
+    t = time.perf_counter()
+    b.tune(torch.cuda.current_stream())
+    tune_s = time.perf_counter() - t
+    b.buffer.zero_()
+    for _ in range(warmup):
+        b.run(torch.cuda.current_stream())
+    ctx.profile(True)
+    ctx.profile_read(reset=True)
+    bt_ms, bt_wall = timed_calls(b.run, steps)
+    kt_ms, kt_n = ctx.profile_read(reset=True)
+    ctx.profile(False)
+    torch.cuda.synchronize()
+    equal = equal_default and bool(torch.equal(b.buffer, ref.buffer))
+    # a sample of the fields against the oracle
+    sample = list(range(0, len(specs), max(1, len(specs) // 16)))
+    ok = True
+    for i in sample:
+        r = oracle.o2_curves(specs[i].data, L, connectivity=8, channels=tuple(b.outputs[i]),
+                             n_threads=min(16, os.cpu_count() or 1))
+        ok &= all(np.array_equal(b.outputs[i][c].cpu().numpy(), r[c]) for c in r)
+    px = float(sum(sizes))
+    best = min(bd_ms, bt_ms)
+    return dict(
+        workload=f"batch_{len(specs)}x_u8_side64-2048_L{L}", fields=len(specs), gpx=round(px / 1e9, 4),
+        per_field_ms=round(pf_ms, 3), per_field_host_ms=round(pf_wall, 3),
+        batched_ms=round(bd_ms, 3), batched_tuned_ms=round(bt_ms, 3), batched_host_ms=round(bt_wall, 3),
+        per_field_gvox_s=round(px / pf_ms / 1e6, 2), batched_gvox_s=round(px / best / 1e6, 2),
+        speedup=round(pf_ms / best, 2),
+        batched_kernel_ms=round((kt_ms / max(kt_n, 1)) if bt_ms <= bd_ms else (k_ms / max(k_n, 1)), 4),
+        hbm_frac_batched=round(px / best / 1e6 / HBM_PEAK_GBS, 4),
+        tune_seconds=round(tune_s, 2), equal_to_per_field=equal, parity_vs_oracle_sample=bool(ok),
+        oracle_sample_fields=len(sample))
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -160,7 +231,10 @@ def main():
     ap.add_argument("--workload", choices=["2d", "3d", "2d-small"], default="2d")
     ap.add_argument("--copies", type=int, default=4)
     ap.add_argument("--no-secondary", action="store_true", help="skip the 3D secondary measurement")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched vs per-field comparison")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--gen-workers", type=int, default=min(16, os.cpu_count() or 1),
+                    help="processes that draw the synthetic inputs")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="also run a plain device copy of MIB MiB (for counter calibration)")
     args = ap.parse_args()
@@ -171,6 +245,14 @@ def main():
                                    "multi-GPU form in this build (see DESIGN.md for how it would shard)",
                           "n_gpus": args.gpus}), flush=True)
         sys.exit(2)
+
+    # every host input is drawn before the GPU is touched
+    from paper_2311_11740_amd import synth
+    t_gen = time.perf_counter()
+    spec = make_workload(args.workload)
+    sec_spec = make_workload("3d") if args.workload == "2d" and not args.no_secondary else None
+    batch_specs = None if args.no_batch else synth.batch_2d_u8(workers=args.gen_workers)
+    print(f"[bench] inputs drawn in {time.perf_counter() - t_gen:.1f} s", file=sys.stderr, flush=True)
 
     import torch
     from paper_2311_11740_amd import ecc
@@ -184,9 +266,8 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
 
-    main_r = measure(ctx, args.workload, args.steps, args.warmup, args.copies,
-                     with_cpu=not args.no_cpu_baseline)
-    spec = main_r["spec"]
+    main_r = measure(ctx, spec, args.steps, args.warmup, args.copies, with_cpu=not args.no_cpu_baseline)
+    print(f"[bench] {spec.meta['name']}: {main_r['gvox_s']} Gvox/s", file=sys.stderr, flush=True)
     line = {
         "metric": METRIC,
         "value": main_r["gvox_s"],
@@ -210,10 +291,16 @@ def main():
     if "cpu_baseline" in main_r:
         line["cpu_baseline"] = main_r["cpu_baseline"]
         line["parity_vs_oracle"] = main_r["parity_vs_oracle"]
-    if args.workload == "2d" and not args.no_secondary:
-        sec = measure(ctx, "3d", max(3, args.steps // 2), 2, 2, with_cpu=False)
+    del main_r
+    if sec_spec is not None:
+        sec = measure(ctx, sec_spec, max(3, args.steps // 2), 2, 2, with_cpu=False)
         line["secondary"] = {k: sec[k] for k in ("workload", "gvox_s", "ms_per_step", "hbm_frac_step",
                                                   "roofline")}
+        print(f"[bench] {sec_spec.meta['name']}: {sec['gvox_s']} Gvox/s", file=sys.stderr, flush=True)
+        del sec
+    if batch_specs is not None:
+        line["batched"] = measure_batch(ctx, batch_specs, max(5, args.steps // 2), 2)
+        print(f"[bench] batched: {line['batched']['batched_gvox_s']} Gvox/s", file=sys.stderr, flush=True)
     ctx.close()
     print(json.dumps(line), flush=True)
 

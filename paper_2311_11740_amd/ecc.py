@@ -315,6 +315,15 @@ class Batch:
                                                      _stream_ptr(stream)))
         return self.outputs
 
+    def run_per_field(self, stream=None):
+        """The same fields with one single-field call each (the plain path the
+        batched call is compared with)."""
+        lib, h, sp = self.ctx._lib, self.ctx.handle, _stream_ptr(stream)
+        f, c = ctypes.byref, self.carr
+        for i in range(self.n):
+            check(lib.ecc_curves_compute(h, f(self.farr[i]), f(c[i]), sp))
+        return self.outputs
+
     def tune(self, stream=None):
         """Autotune the launch geometry for this mix (synchronises `stream`)."""
         check(self.ctx._lib.ecc_batch_plan_tune(self.ctx.handle, self.n, self.farr, _stream_ptr(stream)))

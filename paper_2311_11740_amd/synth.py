@@ -130,39 +130,59 @@ def batch_shapes(n: int = 4096, seed: int = 4, lo: int = 64, hi: int = 2048, max
     return shapes
 
 
-def batch_2d_u8(n: int = 4096, seed: int = 4, lo: int = 64, hi: int = 2048):
+def _quantised_grf(args):
+    shape, sigma, seed, q = args
+    return quantise(grf(shape, sigma, seed), q)
+
+
+def _map(fn, args, workers: int):
+    """fn over args, in `workers` spawned processes when workers > 1 (the
+    results do not depend on the worker count: every field has its own seed)."""
+    if workers <= 1 or len(args) < 2:
+        return [fn(a) for a in args]
+    import concurrent.futures as cf
+    import multiprocessing as mp
+    with cf.ProcessPoolExecutor(max_workers=workers, mp_context=mp.get_context("spawn")) as ex:
+        return list(ex.map(fn, args, chunksize=max(1, len(args) // (8 * workers))))
+
+
+def batch_2d_u8(n: int = 4096, seed: int = 4, lo: int = 64, hi: int = 2048, workers: int = 1):
     """n uint8 smoothed GRFs of uneven shape, sigma ~ U[2, 16] px, 256 levels."""
     shapes = batch_shapes(n, seed, lo, hi)
     ss = np.random.SeedSequence(seed).spawn(n)
     rng = np.random.default_rng(seed + 1000)
     sigmas = rng.uniform(2.0, 16.0, size=n)
-    out = []
-    for k, (sh, s) in enumerate(zip(shapes, sigmas)):
-        out.append(FieldSpec(quantise(grf(sh, float(s), ss[k]), 256), 256, None, 8,
-                             dict(name=f"batch{k}", sigma=float(s))))
-    return out
+    data = _map(_quantised_grf, [(sh, float(s), ss[k], 256) for k, (sh, s) in enumerate(zip(shapes, sigmas))],
+                workers)
+    return [FieldSpec(a, 256, None, 8, dict(name=f"batch{k}", sigma=float(s)))
+            for k, (a, s) in enumerate(zip(data, sigmas))]
 
 
-def serving_pool(n2d: int = 64, n3d: int = 32, seed: int = 5, max2d: int = 4096, max3d: int = 384):
+def serving_pool(n2d: int = 64, n3d: int = 32, seed: int = 5, max2d: int = 4096, max3d: int = 384,
+                 workers: int = 1):
     """Pool of request fields: 2D uint8 (side log-uniform in [128, max2d], 256
     levels) and 3D uint16 (side log-uniform in [64, max3d], 256/1024/4096
     levels); requests replay fields of this pool by id."""
     rng = np.random.default_rng(seed)
     ss = np.random.SeedSequence(seed).spawn(n2d + n3d)
-    pool = []
+    jobs, meta = [], []
     for k in range(n2d):
         h, w = (int(round(x)) for x in np.exp(rng.uniform(math.log(128), math.log(max2d), size=2)))
         s = float(rng.uniform(2.0, 16.0))
-        pool.append(FieldSpec(quantise(grf((h, w), s, ss[k]), 256), 256, None, 8,
-                              dict(name=f"pool2d{k}", sigma=s)))
+        jobs.append(((h, w), s, ss[k], 256))
+        meta.append((256, 8, dict(name=f"pool2d{k}", sigma=s)))
     for k in range(n3d):
         d, h, w = (int(round(x)) for x in np.exp(rng.uniform(math.log(64), math.log(max3d), size=3)))
         s = float(rng.uniform(3.0, 8.0))
         L = int(rng.choice([256, 1024, 4096]))
-        q = quantise(grf((d, h, w), s, ss[n2d + k]), 4096)
-        if L < 4096:  # rescale to L levels
+        jobs.append(((d, h, w), s, ss[n2d + k], 4096))
+        meta.append((L, 26, dict(name=f"pool3d{k}", sigma=s)))
+    data = _map(_quantised_grf, jobs, workers)
+    pool = []
+    for q, (L, conn, m) in zip(data, meta):
+        if q.ndim == 3 and L < 4096:  # rescale to L levels
             q = (q.astype(np.uint32) * L // 4096).astype(np.uint16)
-        pool.append(FieldSpec(q, L, None, 26, dict(name=f"pool3d{k}", sigma=s)))
+        pool.append(FieldSpec(q, L, None, conn, m))
     return pool
 
 
