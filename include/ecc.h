@@ -174,36 +174,51 @@ ecc_status ecc_profile_enable(ecc_context ctx, int32_t on);
 ecc_status ecc_profile_read(ecc_context ctx, double *total_ms, int64_t *launches, int32_t reset);
 
 /* ---------------------------------------------------------------------------
- * Serving: a request loop with continuous batching.
- * Requests are admitted while their device memory fits the budget and a slot is
- * free; admitted requests are copied to device-resident slots on a copy stream
- * and computed by batched launches that include every request admitted so far.
+ * Serving: a request loop with continuous batching (the paper's real-time use,
+ * Discussion: many small images per second).
+ *
+ * At creation the server reserves a device arena of hbm_budget_bytes, a pinned
+ * host staging arena of the same size and max_slots slots, and starts a worker
+ * thread on the context's device.  A request is admitted when a slot is free
+ * and its field plus curves fit in the arena (first fit); its field is staged
+ * in pinned memory, copied to the device on a copy stream, and computed as
+ * soon as it has landed: all ready 2D requests (up to max_batch) in one
+ * launch of the batched kernel, others (3D, more than 4096 levels) through the
+ * single-field path on a second stream.  Requests that arrive while earlier
+ * ones run are copied meanwhile and join the next launch.  Results go back to
+ * pinned memory and then to the caller's host arrays, and the request's slot
+ * and memory are released.
  * ------------------------------------------------------------------------- */
 typedef struct ecc_server_s *ecc_server;
 
 typedef struct {
-    size_t hbm_budget_bytes; /* device bytes for request fields + curves         */
-    int32_t max_slots;       /* requests resident at once                         */
+    size_t hbm_budget_bytes; /* device bytes for resident request fields + curves */
+    int32_t max_slots;       /* requests resident at once (1..65536)              */
     int32_t max_batch;       /* requests per batched launch (<= max_slots)        */
 } ecc_server_config;
 
-/*
- * A request: the field lives in HOST memory (copied during ecc_server_submit
- * into a pinned staging buffer, so the caller may reuse it on return); the
- * result curves are written into caller HOST arrays of length n_levels (NULL =
- * not wanted, as in ecc_curves) once the request completes.
- */
+/* Allocates the arenas (device and pinned host, hbm_budget_bytes each) and
+ * starts the worker.  ECC_ERR_INVALID_ARG for a config outside the ranges
+ * above; ECC_ERR_OUT_OF_MEMORY when the arenas cannot be allocated. */
 ecc_status ecc_server_create(ecc_context ctx, const ecc_server_config *cfg, ecc_server *out);
-/* ECC_ERR_BUSY when the request does not fit right now (retry after a poll);
- * ECC_ERR_INVALID_ARG when it can never fit the budget or is malformed. */
+/*
+ * A request: field->data is a HOST pointer (copied into the pinned staging
+ * arena before this returns, so the caller may reuse it); host_curves are HOST
+ * arrays of length n_levels (NULL = not wanted, as in ecc_curves) that must
+ * stay valid until the request is reported done.  Thresholds are copied.
+ * ECC_ERR_BUSY when no slot is free or the arena has no room right now (retry
+ * after a poll); ECC_ERR_INVALID_ARG when the request is malformed or larger
+ * than the whole budget.  Thread-safe.
+ */
 ecc_status ecc_server_submit(ecc_server srv, const ecc_field *field, const ecc_curves *host_curves,
                              uint64_t *ticket);
-/* Advance the loop (admit, launch, complete) and report `ticket`:
- * *done = 1 when its host curves are written, 0 while pending. */
+/* *done = 1 once the request's host curves are written (the ticket is then
+ * forgotten: polling it again is ECC_ERR_INVALID_ARG), 0 while pending.  A
+ * request that failed reports *done = 1 and returns its error status. */
 ecc_status ecc_server_poll(ecc_server srv, uint64_t ticket, int32_t *done);
 /* Block until every submitted request has completed. */
 ecc_status ecc_server_drain(ecc_server srv);
-/* Drain, then free the server. */
+/* Drain, stop the worker and free the server and its arenas. */
 ecc_status ecc_server_destroy(ecc_server srv);
 
 #ifdef __cplusplus

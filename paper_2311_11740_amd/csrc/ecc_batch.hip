@@ -123,7 +123,7 @@ static ecc_status batch_state(ecc_context ctx, BatchState **out) {
 }
 
 // fields the batched kernel takes
-static bool batchable(const FieldInfo &fi) {
+bool batchable(const FieldInfo &fi) {
     if (fi.ndim != 2 || fi.L > kBatchMaxLevels || fi.cells > kBatchMaxCells) return false;
     return fi.cells >= vec_2d(fi.dtype);
 }
@@ -143,10 +143,61 @@ static std::string plan_key(int n, const FieldInfo *fi, const LevelArgs *lv) {
     return k;
 }
 
-// Cut the batchable fields into items of at most `item_cells` cells (counted
-// as whole strips of 62 lanes x VEC cells per row, the work a wave does per
-// row), and deal the items to workgroups, largest first, each to the least
-// loaded one.
+// Cut fields into items of at most `item_cells` cells (counted as whole
+// strips of 62 lanes x VEC cells per row, the work a wave does per row), and
+// deal the items to workgroups, largest first, each to the least loaded one.
+// Returns the grid; items come out grouped by workgroup (wg_first, grid + 1
+// entries), n_items gets the item count of each field.
+int schedule_batch_2d(int n_cu, int dtype, int lm, int max_L, const std::vector<SchedField> &fields,
+                      int item_cells, int wg_per_cu, std::vector<BatchItem> &sorted, std::vector<int32_t> &first,
+                      std::vector<int32_t> &n_items) {
+    const int vec = vec_2d(dtype), ce = 62 * vec;
+    const int64_t max_units = std::max<int64_t>(1, std::min<int64_t>(item_cells, kFlush2D) / ce);
+    std::vector<BatchItem> items;
+    std::vector<int64_t> cost;
+    n_items.assign(fields.size(), 0);
+    for (size_t f = 0; f < fields.size(); ++f) {
+        const int64_t strips = (fields[f].w + ce - 1) / ce, units = strips * fields[f].h;
+        const int64_t k = (units + max_units - 1) / max_units;  // items of this field
+        for (int64_t j = 0; j < k; ++j) {
+            const int64_t u0 = units * j / k, u1 = units * (j + 1) / k;
+            items.push_back(BatchItem{fields[f].slot, (int32_t)u0, (int32_t)u1, 0});
+            cost.push_back(u1 - u0);
+        }
+        n_items[f] = (int32_t)k;
+    }
+    const size_t lds = lds_bytes_batch_2d(lm, max_L) + 6 * 1024;
+    const int fit = std::max<int>(1, (int)((160 * 1024) / lds));
+    const int64_t G = std::min<int64_t>((int64_t)n_cu * std::min(wg_per_cu, fit), (int64_t)items.size());
+    const int grid = (int)std::max<int64_t>(1, G);
+    std::vector<int> order(items.size());
+    for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
+    typedef std::pair<int64_t, int> Load;
+    std::priority_queue<Load, std::vector<Load>, std::greater<Load>> pq;
+    for (int wg = 0; wg < grid; ++wg) pq.push({0, wg});
+    std::vector<std::vector<int>> per_wg(grid);
+    for (int i : order) {
+        Load l = pq.top();
+        pq.pop();
+        per_wg[l.second].push_back(i);
+        l.first += cost[i] + 8;  // + a fixed cost per item (drain, ticket)
+        pq.push(l);
+    }
+    sorted.clear();
+    sorted.reserve(items.size());
+    first.assign(grid + 1, 0);
+    for (int wg = 0; wg < grid; ++wg) {
+        first[wg] = (int32_t)sorted.size();
+        for (int i : per_wg[wg]) sorted.push_back(items[i]);
+    }
+    first[grid] = (int32_t)sorted.size();
+    return grid;
+}
+
+// A cached plan: batchable fields grouped by (dtype, level mode), each group
+// scheduled as above, device copies of the schedules, per-field histograms
+// and tickets, and the group launches captured as a graph.
 static ecc_status build_plan(ecc_context ctx, BatchState *bs, int n, const FieldInfo *fi, const LevelArgs *lv,
                              const std::string &key, int item_cells, int wg_per_cu, BatchPlan **out) {
     auto *p = new BatchPlan();
@@ -184,49 +235,18 @@ static ecc_status build_plan(ecc_context ctx, BatchState *bs, int n, const Field
         return s;
     };
     for (auto &g : p->groups) {
-        const int vec = vec_2d(g.dtype), ce = 62 * vec;
-        const int64_t max_units = std::max<int64_t>(1, std::min<int64_t>(item_cells, kFlush2D) / ce);
-        std::vector<BatchItem> items;
-        std::vector<int64_t> cost;
+        std::vector<SchedField> sf;
         for (int i : g.fields) {
             g.max_L = std::max(g.max_L, fi[i].L);
-            const int64_t strips = (fi[i].w + ce - 1) / ce, units = strips * fi[i].h;
-            const int64_t k = (units + max_units - 1) / max_units;  // items of this field
-            for (int64_t j = 0; j < k; ++j) {
-                const int64_t u0 = units * j / k, u1 = units * (j + 1) / k;
-                items.push_back(BatchItem{p->slot_of[i], (int32_t)u0, (int32_t)u1, 0});
-                cost.push_back(u1 - u0);
-            }
-            p->n_items_of[p->slot_of[i]] = (int32_t)k;
-        }
-        const size_t lds = lds_bytes_batch_2d(g.lm, g.max_L) + 6 * 1024;
-        const int fit = std::max<int>(1, (int)((160 * 1024) / lds));
-        const int64_t G = std::min<int64_t>((int64_t)ctx->n_cu * std::min(wg_per_cu, fit), (int64_t)items.size());
-        g.grid = (int)std::max<int64_t>(1, G);
-        g.n_items = (int)items.size();
-        // largest first onto the least loaded workgroup
-        std::vector<int> order(items.size());
-        for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
-        std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
-        typedef std::pair<int64_t, int> Load;
-        std::priority_queue<Load, std::vector<Load>, std::greater<Load>> pq;
-        for (int wg = 0; wg < g.grid; ++wg) pq.push({0, wg});
-        std::vector<std::vector<int>> per_wg(g.grid);
-        for (int i : order) {
-            Load l = pq.top();
-            pq.pop();
-            per_wg[l.second].push_back(i);
-            l.first += cost[i] + 8;  // + a fixed cost per item (drain, ticket)
-            pq.push(l);
+            sf.push_back(SchedField{p->slot_of[i], fi[i].h, fi[i].w});
         }
         std::vector<BatchItem> sorted;
-        std::vector<int32_t> first(g.grid + 1, 0);
-        sorted.reserve(items.size());
-        for (int wg = 0; wg < g.grid; ++wg) {
-            first[wg] = (int32_t)sorted.size();
-            for (int i : per_wg[wg]) sorted.push_back(items[i]);
-        }
-        first[g.grid] = (int32_t)sorted.size();
+        std::vector<int32_t> first;
+        std::vector<int32_t> n_items;
+        g.grid = schedule_batch_2d(ctx->n_cu, g.dtype, g.lm, g.max_L, sf, item_cells, wg_per_cu, sorted, first,
+                                   n_items);
+        g.n_items = (int)sorted.size();
+        for (size_t j = 0; j < sf.size(); ++j) p->n_items_of[sf[j].slot] = n_items[j];
         int e = (int)hipMalloc(&g.d_items, sizeof(BatchItem) * std::max<size_t>(1, sorted.size()));
         if (e) return cleanup(fail(ECC_ERR_OUT_OF_MEMORY, "hipMalloc(batch items) failed"));
         e = (int)hipMalloc(&g.d_wg_first, sizeof(int32_t) * first.size());

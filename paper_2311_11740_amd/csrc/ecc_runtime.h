@@ -90,6 +90,15 @@ ecc_status compute_one(ecc_context ctx, const ecc_field *f, const FieldInfo &fi,
 int pick_grid(ecc_context ctx, int64_t n_tiles, size_t lds_per_wg);
 ecc_status merge_and_scan(ecc_context ctx, int grid, int nch, int L, int64_t *const outs[4], void *stream);
 void destroy_batch_state(ecc_context ctx);
+// batched 2D scheduling (ecc_batch.hip), shared with the serving loop
+struct SchedField {
+    int32_t slot;  // descriptor index the items refer to
+    int64_t h, w;
+};
+bool batchable(const FieldInfo &fi);
+int schedule_batch_2d(int n_cu, int dtype, int lm, int max_L, const std::vector<SchedField> &fields,
+                      int item_cells, int wg_per_cu, std::vector<BatchItem> &sorted, std::vector<int32_t> &first,
+                      std::vector<int32_t> &n_items);
 // records the start event of a timed launch on `stream` (no-op unless profiling)
 ecc_status prof_begin(ecc_context ctx, void *stream, int *slot);
 ecc_status prof_end(ecc_context ctx, void *stream, int slot);

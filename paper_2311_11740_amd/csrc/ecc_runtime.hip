@@ -167,6 +167,20 @@ extern "C" ecc_status ecc_create(int device, ecc_context *out) {
         ecc_destroy(ctx);
         return hip_fail(e, "hipEventCreate");
     }
+    // the merge kernel's completion ticket, zeroed here once and for all (the
+    // kernel leaves it at zero): zeroing it lazily on the null stream would not
+    // order the clear before a first merge queued on a non-blocking stream
+    e = (int)hipMalloc(&ctx->d_counter, 256);
+    if (e) {
+        ecc_destroy(ctx);
+        return fail(ECC_ERR_OUT_OF_MEMORY, "hipMalloc(counter) failed");
+    }
+    e = (int)hipMemset(ctx->d_counter, 0, 256);
+    if (!e) e = (int)hipDeviceSynchronize();
+    if (e) {
+        ecc_destroy(ctx);
+        return hip_fail(e, "hipMemset(counter)");
+    }
     *out = ctx;
     return ECC_OK;
 }
@@ -394,10 +408,11 @@ ecc_status release_workspace(ecc_context ctx, void *stream) {
 // grow a workspace buffer; the old one may still be read by queued work
 ecc_status grow(ecc_context ctx, DevBuf &b, size_t need, const char *what) {
     if (need <= b.bytes) return ECC_OK;
-    if (ctx->ws_used) {
-        int e = (int)hipEventSynchronize(ctx->ws_event);
-        if (e) return hip_fail(e, "hipEventSynchronize");
-    }
+    // the old buffer may still be in use by work queued on any stream (earlier
+    // fields of the same call included): wait for the device before freeing it
+    (void)ctx;
+    int e = (int)hipDeviceSynchronize();
+    if (e) return hip_fail(e, "hipDeviceSynchronize");
     return b.ensure(need, what);
 }
 
@@ -424,12 +439,6 @@ ecc_status merge_and_scan(ecc_context ctx, int grid, int nch, int L, int64_t *co
                           void *stream) {
     ecc_status s = grow(ctx, ctx->ws.totals, (size_t)nch * L * sizeof(int64_t), "totals");
     if (s != ECC_OK) return s;
-    if (!ctx->d_counter) {
-        int e = (int)hipMalloc(&ctx->d_counter, 256);
-        if (e) return fail(ECC_ERR_OUT_OF_MEMORY, "hipMalloc(counter) failed");
-        e = (int)hipMemset(ctx->d_counter, 0, 256);
-        if (e) return hip_fail(e, "hipMemset(counter)");
-    }
     int e = launch_merge((const int32_t *)ctx->ws.partial.ptr, grid, nch, L, outs,
                          (int64_t *)ctx->ws.totals.ptr, (unsigned *)ctx->d_counter, stream);
     if (e) return hip_fail(e, "merge kernel launch");

@@ -1,18 +1,586 @@
-// Serving loop (not built yet).
+// Serving loop: continuous batching of EC-curve requests.
+//
+// Memory.  At creation the server takes one device arena of the HBM budget and
+// a pinned host arena of the same size, and a fixed number of slots (each
+// with a per-level histogram and ticket for the batched kernel).  A request
+// is admitted when a slot is free and both arenas have room for its field and
+// curves (first fit); otherwise the submit returns ECC_ERR_BUSY.  An admitted
+// request keeps its device copy of the field and its curves resident until
+// its results are back on the host, then releases them.
+//
+// Work.  A worker thread advances every request through
+//   staged (field in pinned memory) -> copying (H2D on the copy stream)
+//   -> ready -> running (on a compute stream) -> complete (curves copied to
+//   the caller's host arrays),
+// and whenever requests are ready it launches them at once: the 2D requests
+// the batched kernel takes go into one launch of that kernel (as many as are
+// ready, up to max_batch), the others (3D, more than 4096 levels) run the
+// single-field path on a second compute stream.  Requests that arrive while
+// earlier ones are on the GPU are copied in meanwhile and join the next
+// launch, so copies and kernels of different requests overlap.
 #include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <thread>
+#include <unordered_map>
+#include <vector>
 
 #include "ecc_runtime.h"
 
+namespace ecc {
+
+// first-fit allocator of byte ranges in [0, size), 256-byte granules
+class Arena {
+  public:
+    void init(size_t size) {
+        free_.clear();
+        if (size) free_[0] = size;
+    }
+    bool alloc(size_t n, size_t *off) {
+        n = round(n);
+        for (auto it = free_.begin(); it != free_.end(); ++it)
+            if (it->second >= n) {
+                *off = it->first;
+                const size_t rest = it->second - n, at = it->first + n;
+                free_.erase(it);
+                if (rest) free_[at] = rest;
+                return true;
+            }
+        return false;
+    }
+    void release(size_t off, size_t n) {
+        n = round(n);
+        auto it = free_.emplace(off, n).first;
+        auto nx = std::next(it);
+        if (nx != free_.end() && it->first + it->second == nx->first) {
+            it->second += nx->second;
+            free_.erase(nx);
+        }
+        if (it != free_.begin()) {
+            auto pv = std::prev(it);
+            if (pv->first + pv->second == it->first) {
+                pv->second += it->second;
+                free_.erase(it);
+            }
+        }
+    }
+    static size_t round(size_t n) { return (n + 255) & ~size_t(255); }
+
+  private:
+    std::map<size_t, size_t> free_;
+};
+
+enum ReqState { kReserving, kStaged, kCopying, kReady, kRunning, kComplete, kFailed };
+
+struct Request {
+    uint64_t ticket = 0;
+    ecc_field field{};   // data points into the device arena once admitted
+    FieldInfo fi{};
+    std::vector<float> thr;
+    ecc_curves host_out{};
+    int nch = 0;
+    size_t field_bytes = 0, total_bytes = 0, off = 0;
+    int slot = -1;
+    ReqState state = kReserving;
+    ecc_status err = ECC_OK;
+    hipEvent_t ev_h2d = nullptr;
+    int launch = -1;  // index of the completion event in the server's ring
+};
+
+}  // namespace ecc
+
 using namespace ecc;
 
-extern "C" ecc_status ecc_server_create(ecc_context, const ecc_server_config *, ecc_server *) {
-    return fail(ECC_ERR_UNSUPPORTED, "serving is not built yet");
+struct ecc_server_s {
+    ecc_context ctx = nullptr;
+    ecc_server_config cfg{};
+    std::mutex mu;
+    std::condition_variable cv_work, cv_done;
+    std::thread worker;
+    bool stop = false;
+    hipStream_t s_copy = nullptr, s_2d = nullptr, s_other = nullptr;
+    char *d_arena = nullptr, *h_arena = nullptr;
+    Arena dev;
+    std::vector<int> free_slots;
+    int32_t *d_hist = nullptr;  // [slots][3][kBatchMaxLevels]
+    uint32_t *d_done = nullptr;  // [slots]
+    uint64_t *d_luts = nullptr;  // [2][256]
+    // per-launch schedule buffers (device + pinned), reused once their launch is done
+    struct Launch {
+        BatchField2D *d_desc = nullptr, *h_desc = nullptr;
+        BatchItem *d_items = nullptr, *h_items = nullptr;
+        int32_t *d_first = nullptr, *h_first = nullptr;
+        size_t cap_desc = 0, cap_items = 0, cap_first = 0;
+        hipEvent_t done = nullptr;
+        bool busy = false;
+    };
+    std::vector<Launch> ring;
+    std::unordered_map<uint64_t, Request *> reqs;
+    std::deque<Request *> staged, copying, ready;
+    std::vector<Request *> running;
+    uint64_t next_ticket = 1;
+    int64_t inflight = 0;
+};
+
+namespace {
+
+constexpr int kRing = 4;
+
+ecc_status grow_pair(void **d, void **h, size_t *cap, size_t need) {
+    if (need <= *cap) return ECC_OK;
+    size_t n = std::max(need, *cap * 2);
+    if (*d) hipFree(*d);
+    if (*h) hipHostFree(*h);
+    *d = *h = nullptr;
+    *cap = 0;
+    int e = (int)hipMalloc(d, n);
+    if (e) return fail(ECC_ERR_OUT_OF_MEMORY, "hipMalloc(serving schedule) failed");
+    e = (int)hipHostMalloc(h, n, 0);
+    if (e) return hip_fail(e, "hipHostMalloc(serving schedule)");
+    *cap = n;
+    return ECC_OK;
 }
-extern "C" ecc_status ecc_server_submit(ecc_server, const ecc_field *, const ecc_curves *, uint64_t *) {
-    return fail(ECC_ERR_UNSUPPORTED, "serving is not built yet");
+
+void finish(ecc_server srv, Request *r, ecc_status err) {
+    if (err == ECC_OK) {
+        const char *res = srv->h_arena + r->off + Arena::round(r->field_bytes);
+        int64_t *dst[4] = {r->host_out.ec, r->host_out.perimeter, r->host_out.area, r->host_out.volume};
+        int k = 0;
+        for (int c = 0; c < 4; ++c)
+            if (dst[c]) {
+                std::memcpy(dst[c], res + (size_t)k * r->fi.L * 8, (size_t)r->fi.L * 8);
+                ++k;
+            }
+    }
+    srv->dev.release(r->off, r->total_bytes);
+    srv->free_slots.push_back(r->slot);
+    if (r->ev_h2d) hipEventDestroy(r->ev_h2d);
+    r->ev_h2d = nullptr;
+    r->err = err;
+    r->state = err == ECC_OK ? kComplete : kFailed;
+    --srv->inflight;
 }
-extern "C" ecc_status ecc_server_poll(ecc_server, uint64_t, int32_t *) {
-    return fail(ECC_ERR_UNSUPPORTED, "serving is not built yet");
+
+// device curves of a request (channels packed in ec, perimeter, area, volume order)
+int64_t *dev_curves(ecc_server srv, Request *r) {
+    return reinterpret_cast<int64_t *>(srv->d_arena + r->off + Arena::round(r->field_bytes));
 }
-extern "C" ecc_status ecc_server_drain(ecc_server) { return fail(ECC_ERR_UNSUPPORTED, "serving is not built yet"); }
-extern "C" ecc_status ecc_server_destroy(ecc_server) { return ECC_OK; }
+
+ecc_curves dev_curve_ptrs(ecc_server srv, Request *r) {
+    ecc_curves c{};
+    int64_t *base = dev_curves(srv, r);
+    int64_t **dst[4] = {&c.ec, &c.perimeter, &c.area, &c.volume};
+    int64_t *want[4] = {r->host_out.ec, r->host_out.perimeter, r->host_out.area, r->host_out.volume};
+    int k = 0;
+    for (int ch = 0; ch < 4; ++ch)
+        if (want[ch]) *dst[ch] = base + (size_t)(k++) * r->fi.L;
+    return c;
+}
+
+// queue the D2H copy of a request's curves into its pinned slot
+ecc_status copy_back(ecc_server srv, Request *r, hipStream_t s) {
+    const size_t off = r->off + Arena::round(r->field_bytes);
+    int e = (int)hipMemcpyAsync(srv->h_arena + off, srv->d_arena + off, (size_t)r->nch * r->fi.L * 8,
+                                hipMemcpyDeviceToHost, s);
+    return e ? hip_fail(e, "hipMemcpyAsync(results)") : ECC_OK;
+}
+
+int free_launch(ecc_server srv) {
+    for (int i = 0; i < (int)srv->ring.size(); ++i)
+        if (!srv->ring[i].busy) return i;
+    return -1;
+}
+
+// launch every ready request; called with srv->mu held
+ecc_status launch_ready(ecc_server srv) {
+    ecc_context ctx = srv->ctx;
+    std::vector<Request *> batch2d, other;
+    const int li = free_launch(srv);
+    std::deque<Request *> keep;
+    for (Request *r : srv->ready) {
+        if (batchable(r->fi) && li >= 0 && (int)batch2d.size() < srv->cfg.max_batch)
+            batch2d.push_back(r);
+        else if (!batchable(r->fi))
+            other.push_back(r);
+        else
+            keep.push_back(r);  // waits for the next launch
+    }
+    if (batch2d.empty() && other.empty()) return ECC_OK;
+    srv->ready.swap(keep);
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    ecc_status s = ECC_OK;
+    if (!batch2d.empty()) {
+        auto &L = srv->ring[li];
+        std::vector<LevelArgs> lv(batch2d.size());
+        std::vector<const float *> distinct;
+        for (Request *r : batch2d)
+            if (r->field.thresholds) distinct.push_back(r->field.thresholds);
+        s = reserve_thresholds(ctx, (int)distinct.size());
+        for (size_t i = 0; i < batch2d.size() && s == ECC_OK; ++i)
+            s = level_args(ctx, &batch2d[i]->field, batch2d[i]->fi, srv->s_2d, &lv[i]);
+        // group by (dtype, level mode); one schedule per group, items appended
+        std::map<std::pair<int, int>, std::vector<int>> groups;
+        for (size_t i = 0; i < batch2d.size(); ++i) groups[{batch2d[i]->fi.dtype, lv[i].mode}].push_back((int)i);
+        std::vector<BatchItem> all_items;
+        std::vector<int32_t> all_first;
+        struct G {
+            int dtype, lm, max_L, grid;
+            size_t item0, first0;
+        };
+        std::vector<G> gl;
+        std::vector<int32_t> n_items_of(batch2d.size(), 0);
+        for (auto &kv : groups) {
+            std::vector<SchedField> sf;
+            int max_L = 0;
+            for (int i : kv.second) {
+                sf.push_back(SchedField{i, batch2d[i]->fi.h, batch2d[i]->fi.w});
+                max_L = std::max(max_L, batch2d[i]->fi.L);
+            }
+            std::vector<BatchItem> items;
+            std::vector<int32_t> first, n_items;
+            const int grid = schedule_batch_2d(ctx->n_cu, kv.first.first, kv.first.second, max_L, sf, 64 * 1024,
+                                               4, items, first, n_items);
+            for (size_t j = 0; j < sf.size(); ++j) n_items_of[sf[j].slot] = n_items[j];
+            gl.push_back(G{kv.first.first, kv.first.second, max_L, grid, all_items.size(), all_first.size()});
+            all_items.insert(all_items.end(), items.begin(), items.end());
+            all_first.insert(all_first.end(), first.begin(), first.end());
+        }
+        if (s == ECC_OK) s = grow_pair((void **)&L.d_desc, (void **)&L.h_desc, &L.cap_desc,
+                                       sizeof(BatchField2D) * batch2d.size());
+        if (s == ECC_OK) s = grow_pair((void **)&L.d_items, (void **)&L.h_items, &L.cap_items,
+                                       sizeof(BatchItem) * std::max<size_t>(1, all_items.size()));
+        if (s == ECC_OK) s = grow_pair((void **)&L.d_first, (void **)&L.h_first, &L.cap_first,
+                                       sizeof(int32_t) * std::max<size_t>(1, all_first.size()));
+        if (s == ECC_OK) {
+            for (size_t i = 0; i < batch2d.size(); ++i) {
+                Request *r = batch2d[i];
+                BatchField2D &d = L.h_desc[i];
+                std::memset(&d, 0, sizeof(d));
+                const ecc_curves c = dev_curve_ptrs(srv, r);
+                d.data = r->field.data;
+                d.h = r->fi.h;
+                d.w = r->fi.w;
+                d.out[0] = c.ec;
+                d.out[1] = c.perimeter;
+                d.out[2] = c.area;
+                d.hist = srv->d_hist + (size_t)r->slot * 3 * kBatchMaxLevels;
+                d.done = srv->d_done + r->slot;
+                d.thr = lv[i].thr;
+                d.lut = lv[i].lut;
+                d.L = r->fi.L;
+                d.n_items = n_items_of[i];
+                d.conn_idx = r->fi.conn == 8 ? 0 : 1;
+                d.inv_step = lv[i].inv_step;
+                d.cpass = (float)(lv[i].u0d + 1.5);
+                d.eps = lv[i].eps;
+            }
+            std::memcpy(L.h_items, all_items.data(), sizeof(BatchItem) * all_items.size());
+            std::memcpy(L.h_first, all_first.data(), sizeof(int32_t) * all_first.size());
+            int e = (int)hipMemcpyAsync(L.d_desc, L.h_desc, sizeof(BatchField2D) * batch2d.size(),
+                                        hipMemcpyHostToDevice, srv->s_2d);
+            if (!e) e = (int)hipMemcpyAsync(L.d_items, L.h_items, sizeof(BatchItem) * all_items.size(),
+                                            hipMemcpyHostToDevice, srv->s_2d);
+            if (!e) e = (int)hipMemcpyAsync(L.d_first, L.h_first, sizeof(int32_t) * all_first.size(),
+                                            hipMemcpyHostToDevice, srv->s_2d);
+            for (size_t g = 0; g < gl.size() && !e; ++g)
+                e = launch_batch_2d(gl[g].dtype, gl[g].lm, L.d_desc, L.d_items + gl[g].item0,
+                                    L.d_first + gl[g].first0, gl[g].grid, srv->d_luts, gl[g].max_L, srv->s_2d);
+            if (e) s = hip_fail(e, "serving batched launch");
+        }
+        for (Request *r : batch2d)
+            if (s == ECC_OK) s = copy_back(srv, r, srv->s_2d);
+        if (s == ECC_OK) {
+            int e = (int)hipEventRecord(L.done, srv->s_2d);
+            if (e) s = hip_fail(e, "hipEventRecord");
+        }
+        for (Request *r : batch2d) {
+            if (s == ECC_OK) {
+                r->state = kRunning;
+                r->launch = li;
+                srv->running.push_back(r);
+            } else {
+                finish(srv, r, s);
+                srv->cv_done.notify_all();
+            }
+        }
+        if (s == ECC_OK) L.busy = true;
+    }
+    for (Request *r : other) {
+        // the single-field path, one request after the other on its own stream
+        ecc_status so = acquire_workspace(ctx, srv->s_other);
+        const ecc_curves c = dev_curve_ptrs(srv, r);
+        if (so == ECC_OK) so = compute_one(ctx, &r->field, r->fi, &c, srv->s_other);
+        const ecc_status s2 = release_workspace(ctx, srv->s_other);
+        if (so == ECC_OK) so = s2;
+        if (so == ECC_OK) so = copy_back(srv, r, srv->s_other);
+        if (so == ECC_OK && !r->ev_h2d) {
+            int e = (int)hipEventCreateWithFlags(&r->ev_h2d, hipEventDisableTiming);
+            if (e) so = hip_fail(e, "hipEventCreate");
+        }
+        if (so == ECC_OK) {
+            int e = (int)hipEventRecord(r->ev_h2d, srv->s_other);  // reused as the completion event
+            if (e) so = hip_fail(e, "hipEventRecord");
+        }
+        if (so == ECC_OK) {
+            r->state = kRunning;
+            r->launch = -1;
+            srv->running.push_back(r);
+        } else {
+            finish(srv, r, so);
+            srv->cv_done.notify_all();
+        }
+    }
+    return ECC_OK;
+}
+
+// one pass over all requests; returns whether anything changed
+bool advance(ecc_server srv) {
+    bool moved = false;
+    // copies of staged requests
+    while (!srv->staged.empty()) {
+        Request *r = srv->staged.front();
+        srv->staged.pop_front();
+        ecc_status s = ECC_OK;
+        int e = (int)hipEventCreateWithFlags(&r->ev_h2d, hipEventDisableTiming);
+        if (!e) e = (int)hipMemcpyAsync(srv->d_arena + r->off, srv->h_arena + r->off, r->field_bytes,
+                                        hipMemcpyHostToDevice, srv->s_copy);
+        if (!e) e = (int)hipEventRecord(r->ev_h2d, srv->s_copy);
+        if (e) s = hip_fail(e, "serving copy");
+        if (s != ECC_OK) {
+            finish(srv, r, s);
+            srv->cv_done.notify_all();
+        } else {
+            r->state = kCopying;
+            srv->copying.push_back(r);
+        }
+        moved = true;
+    }
+    // copies that have landed
+    for (auto it = srv->copying.begin(); it != srv->copying.end();) {
+        if (hipEventQuery((*it)->ev_h2d) == hipSuccess) {
+            (*it)->state = kReady;
+            srv->ready.push_back(*it);
+            it = srv->copying.erase(it);
+            moved = true;
+        } else {
+            ++it;
+        }
+    }
+    if (!srv->ready.empty()) {
+        const size_t before = srv->ready.size();
+        launch_ready(srv);
+        moved |= srv->ready.size() != before;
+    }
+    // finished launches
+    std::vector<bool> ring_done(srv->ring.size(), false);
+    for (size_t i = 0; i < srv->ring.size(); ++i)
+        ring_done[i] = srv->ring[i].busy && hipEventQuery(srv->ring[i].done) == hipSuccess;
+    for (auto it = srv->running.begin(); it != srv->running.end();) {
+        Request *r = *it;
+        const bool done = r->launch >= 0 ? ring_done[r->launch] : hipEventQuery(r->ev_h2d) == hipSuccess;
+        if (done) {
+            finish(srv, r, ECC_OK);
+            it = srv->running.erase(it);
+            moved = true;
+        } else {
+            ++it;
+        }
+    }
+    for (size_t i = 0; i < srv->ring.size(); ++i)
+        if (ring_done[i]) srv->ring[i].busy = false;
+    if (moved) srv->cv_done.notify_all();
+    return moved;
+}
+
+void worker_main(ecc_server srv) {
+    hipSetDevice(srv->ctx->device);
+    std::unique_lock<std::mutex> lk(srv->mu);
+    for (;;) {
+        const bool moved = advance(srv);
+        const bool busy = !srv->copying.empty() || !srv->ready.empty() || !srv->running.empty();
+        if (srv->stop && !busy && srv->staged.empty()) break;
+        if (!moved) {
+            if (busy)  // GPU work in flight: check again shortly
+                srv->cv_work.wait_for(lk, std::chrono::microseconds(20));
+            else
+                srv->cv_work.wait(lk, [srv] { return srv->stop || !srv->staged.empty(); });
+        }
+    }
+}
+
+void release_server(ecc_server srv) {
+    for (auto &L : srv->ring) {
+        if (L.d_desc) hipFree(L.d_desc);
+        if (L.h_desc) hipHostFree(L.h_desc);
+        if (L.d_items) hipFree(L.d_items);
+        if (L.h_items) hipHostFree(L.h_items);
+        if (L.d_first) hipFree(L.d_first);
+        if (L.h_first) hipHostFree(L.h_first);
+        if (L.done) hipEventDestroy(L.done);
+    }
+    for (auto &kv : srv->reqs) {
+        if (kv.second->ev_h2d) hipEventDestroy(kv.second->ev_h2d);
+        delete kv.second;
+    }
+    if (srv->d_arena) hipFree(srv->d_arena);
+    if (srv->h_arena) hipHostFree(srv->h_arena);
+    if (srv->d_hist) hipFree(srv->d_hist);
+    if (srv->d_done) hipFree(srv->d_done);
+    if (srv->d_luts) hipFree(srv->d_luts);
+    if (srv->s_copy) hipStreamDestroy(srv->s_copy);
+    if (srv->s_2d) hipStreamDestroy(srv->s_2d);
+    if (srv->s_other) hipStreamDestroy(srv->s_other);
+    delete srv;
+}
+
+}  // namespace
+
+extern "C" ecc_status ecc_server_create(ecc_context ctx, const ecc_server_config *cfg, ecc_server *out) {
+    clear_error();
+    if (!ctx || !cfg || !out) return fail(ECC_ERR_INVALID_ARG, "NULL argument");
+    if (cfg->hbm_budget_bytes < 4096 || cfg->max_slots < 1 || cfg->max_slots > 65536 || cfg->max_batch < 1)
+        return fail(ECC_ERR_INVALID_ARG, "server config: budget >= 4096 bytes, 1 <= max_slots <= 65536, "
+                                         "max_batch >= 1");
+    auto *srv = new ecc_server_s();
+    srv->ctx = ctx;
+    srv->cfg = *cfg;
+    srv->cfg.max_batch = std::min(cfg->max_batch, cfg->max_slots);
+    int e = (int)hipSetDevice(ctx->device);
+    auto bail = [&](ecc_status s) {
+        release_server(srv);
+        return s;
+    };
+    if (e) return bail(hip_fail(e, "hipSetDevice"));
+    const size_t budget = Arena::round(cfg->hbm_budget_bytes);
+    e = (int)hipMalloc(&srv->d_arena, budget);
+    if (e) return bail(fail(ECC_ERR_OUT_OF_MEMORY, "hipMalloc(serving arena) failed"));
+    e = (int)hipHostMalloc(&srv->h_arena, budget, 0);
+    if (e) return bail(hip_fail(e, "hipHostMalloc(serving staging)"));
+    srv->dev.init(budget);
+    const size_t hist = (size_t)cfg->max_slots * 3 * kBatchMaxLevels * sizeof(int32_t);
+    e = (int)hipMalloc(&srv->d_hist, hist);
+    if (!e) e = (int)hipMalloc(&srv->d_done, (size_t)cfg->max_slots * sizeof(uint32_t));
+    if (e) return bail(fail(ECC_ERR_OUT_OF_MEMORY, "hipMalloc(serving histograms) failed"));
+    // zero once; the batched kernel leaves every slot's histogram and ticket at zero
+    e = (int)hipMemset(srv->d_hist, 0, hist);
+    if (!e) e = (int)hipMemset(srv->d_done, 0, (size_t)cfg->max_slots * sizeof(uint32_t));
+    if (!e) e = (int)hipMalloc(&srv->d_luts, 2 * 256 * sizeof(uint64_t));
+    for (int k = 0; k < 2 && !e; ++k)
+        e = (int)hipMemcpy(srv->d_luts + 256 * k, ctx->d_delta2[k], 256 * sizeof(uint64_t), hipMemcpyDeviceToDevice);
+    if (!e) e = (int)hipDeviceSynchronize();
+    if (e) return bail(hip_fail(e, "serving set-up"));
+    e = (int)hipStreamCreateWithFlags(&srv->s_copy, hipStreamNonBlocking);
+    if (!e) e = (int)hipStreamCreateWithFlags(&srv->s_2d, hipStreamNonBlocking);
+    if (!e) e = (int)hipStreamCreateWithFlags(&srv->s_other, hipStreamNonBlocking);
+    if (e) return bail(hip_fail(e, "hipStreamCreate"));
+    srv->ring.resize(kRing);
+    for (auto &L : srv->ring) {
+        e = (int)hipEventCreateWithFlags(&L.done, hipEventDisableTiming);
+        if (e) return bail(hip_fail(e, "hipEventCreate"));
+    }
+    for (int i = cfg->max_slots - 1; i >= 0; --i) srv->free_slots.push_back(i);
+    srv->worker = std::thread(worker_main, srv);
+    *out = srv;
+    return ECC_OK;
+}
+
+extern "C" ecc_status ecc_server_submit(ecc_server srv, const ecc_field *field, const ecc_curves *host_curves,
+                                        uint64_t *ticket) {
+    clear_error();
+    if (!srv || !field || !host_curves || !ticket) return fail(ECC_ERR_INVALID_ARG, "NULL argument");
+    FieldInfo fi;
+    ecc_status s = validate_field(field, host_curves, &fi, true);
+    if (s != ECC_OK) return s;
+    if (!field->data) return fail(ECC_ERR_INVALID_ARG, "field data is NULL");
+    int nch = 0;
+    for (const int64_t *p : {host_curves->ec, host_curves->perimeter, host_curves->area, host_curves->volume})
+        nch += p ? 1 : 0;
+    auto *r = new Request();
+    r->fi = fi;
+    r->field = *field;
+    r->host_out = *host_curves;
+    r->nch = nch;
+    r->field_bytes = (size_t)fi.cells * fi.elem_bytes;
+    r->total_bytes = Arena::round(r->field_bytes) + (size_t)nch * fi.L * 8;
+    if (Arena::round(r->total_bytes) > Arena::round(srv->cfg.hbm_budget_bytes)) {
+        delete r;
+        return fail(ECC_ERR_INVALID_ARG, "request larger than the server's memory budget");
+    }
+    if (field->thresholds) {
+        r->thr.assign(field->thresholds, field->thresholds + fi.L);
+        r->field.thresholds = r->thr.data();
+    }
+    {
+        std::lock_guard<std::mutex> lk(srv->mu);
+        if (srv->stop) {
+            delete r;
+            return fail(ECC_ERR_INVALID_ARG, "server is shutting down");
+        }
+        if (srv->free_slots.empty() || !srv->dev.alloc(r->total_bytes, &r->off)) {
+            delete r;
+            return fail(ECC_ERR_BUSY, "no free slot or memory; retry after a poll");
+        }
+        r->slot = srv->free_slots.back();
+        srv->free_slots.pop_back();
+        r->ticket = srv->next_ticket++;
+        r->field.data = srv->d_arena + r->off;
+        srv->reqs[r->ticket] = r;
+        ++srv->inflight;
+    }
+    // stage the field in pinned memory outside the lock (the range is ours)
+    std::memcpy(srv->h_arena + r->off, field->data, r->field_bytes);
+    {
+        std::lock_guard<std::mutex> lk(srv->mu);
+        r->state = kStaged;
+        srv->staged.push_back(r);
+    }
+    srv->cv_work.notify_one();
+    *ticket = r->ticket;
+    return ECC_OK;
+}
+
+extern "C" ecc_status ecc_server_poll(ecc_server srv, uint64_t ticket, int32_t *done) {
+    clear_error();
+    if (!srv || !done) return fail(ECC_ERR_INVALID_ARG, "NULL argument");
+    std::lock_guard<std::mutex> lk(srv->mu);
+    auto it = srv->reqs.find(ticket);
+    if (it == srv->reqs.end()) return fail(ECC_ERR_INVALID_ARG, "unknown ticket");
+    Request *r = it->second;
+    if (r->state == kComplete || r->state == kFailed) {
+        const ecc_status s = r->err;
+        srv->reqs.erase(it);
+        delete r;
+        *done = 1;
+        return s == ECC_OK ? ECC_OK : fail(s, "request failed");
+    }
+    *done = 0;
+    return ECC_OK;
+}
+
+extern "C" ecc_status ecc_server_drain(ecc_server srv) {
+    clear_error();
+    if (!srv) return fail(ECC_ERR_INVALID_ARG, "NULL argument");
+    std::unique_lock<std::mutex> lk(srv->mu);
+    srv->cv_work.notify_one();
+    srv->cv_done.wait(lk, [srv] { return srv->inflight == 0; });
+    return ECC_OK;
+}
+
+extern "C" ecc_status ecc_server_destroy(ecc_server srv) {
+    clear_error();
+    if (!srv) return ECC_OK;
+    {
+        std::lock_guard<std::mutex> lk(srv->mu);
+        srv->stop = true;
+    }
+    srv->cv_work.notify_one();
+    if (srv->worker.joinable()) srv->worker.join();
+    hipSetDevice(srv->ctx->device);
+    hipDeviceSynchronize();
+    release_server(srv);
+    return ECC_OK;
+}

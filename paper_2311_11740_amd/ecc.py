@@ -327,3 +327,76 @@ class Batch:
     def tune(self, stream=None):
         """Autotune the launch geometry for this mix (synchronises `stream`)."""
         check(self.ctx._lib.ecc_batch_plan_tune(self.ctx.handle, self.n, self.farr, _stream_ptr(stream)))
+
+
+class Server:
+    """A serving loop on one context: requests are host arrays, results host
+    int64 arrays (see ecc_server_* in the C header)."""
+
+    def __init__(self, ctx, hbm_budget_bytes: int, max_slots: int = 256, max_batch: int = 256):
+        self.ctx = ctx
+        self._lib = ctx._lib
+        cfg = ServerConfig()
+        cfg.hbm_budget_bytes = int(hbm_budget_bytes)
+        cfg.max_slots = int(max_slots)
+        cfg.max_batch = int(max_batch)
+        h = ctypes.c_void_p()
+        check(self._lib.ecc_server_create(ctx.handle, ctypes.byref(cfg), ctypes.byref(h)))
+        self.handle = h
+        self._pending = {}
+
+    def submit(self, array, n_levels: int, thresholds=None, connectivity: int = 0, channels=None):
+        """Submit a host numpy field; returns the ticket, or None when the server
+        is full right now (retry after a poll)."""
+        import numpy as np
+        a = np.ascontiguousarray(array)
+        if a.ndim not in (2, 3):
+            raise ValueError("field must be 2D or 3D")
+        f = Field()
+        f.ndim = a.ndim
+        f.dtype = {np.dtype(np.uint8): ECC_U8, np.dtype(np.uint16): ECC_U16,
+                   np.dtype(np.float32): ECC_F32}[a.dtype]
+        for k in range(3):
+            f.shape[k] = a.shape[k] if k < a.ndim else 0
+        f.data = a.ctypes.data
+        f.n_levels = int(n_levels)
+        f.connectivity = int(connectivity or 0)
+        keep = None
+        if thresholds is not None:
+            keep = np.ascontiguousarray(np.asarray(thresholds, dtype=np.float32))
+            f.thresholds = keep.ctypes.data
+        allowed = CHANNELS_2D if a.ndim == 2 else CHANNELS_3D
+        chans = allowed if channels is None else tuple(c for c in channels if c in allowed)
+        out = {c: np.empty(int(n_levels), np.int64) for c in chans}
+        cv = Curves()
+        for c in ("ec", "perimeter", "area", "volume"):
+            setattr(cv, c, out[c].ctypes.data if c in out else None)
+        t = ctypes.c_uint64()
+        st = self._lib.ecc_server_submit(self.handle, ctypes.byref(f), ctypes.byref(cv), ctypes.byref(t))
+        if st == ECC_ERR_BUSY:
+            return None
+        check(st)
+        self._pending[t.value] = out
+        return t.value
+
+    def poll(self, ticket: int):
+        """The result dict once the request is complete, else None."""
+        d = ctypes.c_int32()
+        check(self._lib.ecc_server_poll(self.handle, ctypes.c_uint64(ticket), ctypes.byref(d)))
+        if d.value:
+            return self._pending.pop(ticket)
+        return None
+
+    def drain(self):
+        check(self._lib.ecc_server_drain(self.handle))
+
+    def close(self):
+        if getattr(self, "handle", None):
+            check(self._lib.ecc_server_destroy(self.handle))
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -259,3 +259,32 @@ def test_misaligned_base_and_buffer_end(ctx, dtype, ndim):
         ref = oracle.o2_curves(a, L, thresholds=thr, connectivity=8 if ndim == 2 else 26, channels=tuple(got))
         for k in got:
             assert np.array_equal(got[k].cpu().numpy(), ref[k]), (sh, k)
+
+
+def test_first_call_of_fresh_context_on_side_stream():
+    """The very first call of a new context, queued on a side stream, is exact
+    (the context's one-time device state is ready before any stream uses it)."""
+    import torch
+    import oracle
+    from paper_2311_11740_amd import ecc
+    rng = np.random.default_rng(14)
+    a = rng.integers(0, 300, size=(37, 13, 27)).astype(np.uint16)
+    b = rng.integers(0, 256, size=(300, 500)).astype(np.uint8)
+    print("[case] fresh context, side stream", flush=True)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        da, db = torch.from_numpy(a).cuda(), torch.from_numpy(b).cuda()
+    s.synchronize()
+    c = ecc.Context(0)
+    try:
+        with torch.cuda.stream(s):
+            ra = c.compute(da, 256, connectivity=26, stream=s)
+            rb = c.compute(db, 256, stream=s)
+        s.synchronize()
+    finally:
+        c.close()
+    oa, ob = oracle.o2_curves(a, 256, connectivity=26), oracle.o2_curves(b, 256)
+    for k in ra:
+        assert np.array_equal(ra[k].cpu().numpy(), oa[k]), k
+    for k in rb:
+        assert np.array_equal(rb[k].cpu().numpy(), ob[k]), k
