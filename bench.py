@@ -25,6 +25,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -223,6 +225,95 @@ def measure_batch(ctx, specs, steps, warmup):
         oracle_sample_fields=len(sample))
 
 
+def serve_trace(submit, poll, t_arr, ids, pool, warm):
+    """Replay a Poisson trace: requests are offered at their arrival times,
+    retried while the server is full, and polled until done.  Returns the
+    latencies (s, arrival to result on the host) of the requests after the
+    first `warm`, the elapsed time of those, and the results by request."""
+    from collections import deque
+    n = len(t_arr)
+    lat = np.zeros(n)
+    results = [None] * n
+    backlog, pending = deque(), {}
+    i = 0
+    start = time.perf_counter()
+    while i < n or backlog or pending:
+        now = time.perf_counter() - start
+        progressed = False
+        while i < n and t_arr[i] <= now:
+            backlog.append(i)
+            i += 1
+        while backlog:
+            k = backlog[0]
+            t = submit(pool[ids[k]])
+            if t is None:
+                break
+            pending[t] = k
+            backlog.popleft()
+            progressed = True
+        for t in list(pending):
+            r = poll(t)
+            if r is not None:
+                k = pending.pop(t)
+                lat[k] = time.perf_counter() - start - t_arr[k]
+                results[k] = r
+                progressed = True
+        if not progressed:
+            time.sleep(2e-5)
+    elapsed = time.perf_counter() - start - t_arr[warm]
+    return lat[warm:], elapsed, results
+
+
+def measure_serving(ctx, pool, n_requests, rates, warm=100):
+    """Continuous-batching server vs the plain path (copy in, one call, copy
+    out, one request at a time) on the same Poisson traces."""
+    import torch
+    from paper_2311_11740_amd import ecc, synth
+    n2d = sum(1 for p in pool if p.data.ndim == 2)
+    ch = lambda p: ("ec", "perimeter", "area") if p.data.ndim == 2 else ("ec", "area", "volume")  # noqa: E731
+    # reference curves of every pool field from the single-field call
+    ref = []
+    for p in pool:
+        r = ctx.compute(torch.from_numpy(p.data).cuda(), p.n_levels, connectivity=p.connectivity, channels=ch(p))
+        ref.append({c: v.cpu().numpy() for c, v in r.items()})
+    srv = ecc.Server(ctx, 2 << 30, max_slots=256, max_batch=128)
+
+    def srv_submit(p):
+        return srv.submit(p.data, p.n_levels, connectivity=p.connectivity, channels=ch(p))
+
+    plain_state = {}
+
+    def plain_submit(p):  # synchronous: the request is complete when this returns
+        d = torch.from_numpy(p.data).cuda()
+        r = ctx.compute(d, p.n_levels, connectivity=p.connectivity, channels=ch(p))
+        t = len(plain_state) + 1
+        plain_state[t] = {c: v.cpu().numpy() for c, v in r.items()}
+        return t
+
+    out = []
+    equal = True
+    try:
+        for rate in rates:
+            t_arr, ids = synth.poisson_trace(n_requests + warm, rate, len(pool), 0.7, n2d)
+            row = {"rate_rps": rate}
+            for name, sub, pol in (("server", srv_submit, srv.poll),
+                                   ("per_field", plain_submit, lambda t: plain_state.pop(t, None))):
+                lat, el, res = serve_trace(sub, pol, t_arr, ids, pool, warm)
+                vox = float(sum(pool[k].data.size for k in ids[warm:]))
+                row[name] = dict(throughput_rps=round(n_requests / el, 1), gvox_s=round(vox / el / 1e9, 3),
+                                 p50_ms=round(float(np.percentile(lat, 50)) * 1e3, 3),
+                                 p99_ms=round(float(np.percentile(lat, 99)) * 1e3, 3))
+                for k in range(len(res)):
+                    equal &= all(np.array_equal(res[k][c], ref[ids[k]][c]) for c in res[k])
+            out.append(row)
+            print(f"[bench] serving {rate} req/s: {row}", file=sys.stderr, flush=True)
+    finally:
+        srv.close()
+    return dict(workload=f"serving_pool{n2d}x2d_u8+{len(pool) - n2d}x3d_u16_poisson",
+                requests_per_rate=n_requests, warmup_requests=warm, rates=out,
+                results_equal_single_field=bool(equal))
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -232,6 +323,10 @@ def main():
     ap.add_argument("--copies", type=int, default=4)
     ap.add_argument("--no-secondary", action="store_true", help="skip the 3D secondary measurement")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched vs per-field comparison")
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving comparison")
+    ap.add_argument("--serving-requests", type=int, default=2000)
+    ap.add_argument("--serving-rates", type=str, default="500,2000,4000,8000",
+                    help="Poisson arrival rates (requests/s), comma separated")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--gen-workers", type=int, default=min(16, os.cpu_count() or 1),
                     help="processes that draw the synthetic inputs")
@@ -252,6 +347,7 @@ def main():
     spec = make_workload(args.workload)
     sec_spec = make_workload("3d") if args.workload == "2d" and not args.no_secondary else None
     batch_specs = None if args.no_batch else synth.batch_2d_u8(workers=args.gen_workers)
+    pool = None if args.no_serving else synth.serving_pool(workers=args.gen_workers)
     print(f"[bench] inputs drawn in {time.perf_counter() - t_gen:.1f} s", file=sys.stderr, flush=True)
 
     import torch
@@ -301,6 +397,10 @@ def main():
     if batch_specs is not None:
         line["batched"] = measure_batch(ctx, batch_specs, max(5, args.steps // 2), 2)
         print(f"[bench] batched: {line['batched']['batched_gvox_s']} Gvox/s", file=sys.stderr, flush=True)
+    if pool is not None:
+        del batch_specs
+        rates = [float(r) for r in args.serving_rates.split(",") if r]
+        line["serving"] = measure_serving(ctx, pool, args.serving_requests, rates)
     ctx.close()
     print(json.dumps(line), flush=True)
 
