@@ -29,10 +29,12 @@ constexpr int kShiftPer2 = 21, kShiftCnt2 = 44;
 constexpr int64_t kFlush2D = (1 << 19) - 1;
 // 3D bin word (uint64): [ ec+7 : 22 bits | surface+6 : 22 bits | count : 20 bits ],
 // crease in a second uint32 word as crease+12.  Valid while at most kFlush3D
-// cells are added between drains (ec field <= 14n < 2^22).
+// cells are added between drains: ec+7 <= 14 and surface+6 <= 12 per cell keep
+// both fields below 2^22 (14 * 299000 < 2^22), the count below 2^20 and the
+// crease word (<= 24 per cell) below 2^32.
 constexpr int kEcBias3 = 7, kSurfBias3 = 6, kCreaseBias3 = 12;
 constexpr int kShiftSurf3 = 22, kShiftCnt3 = 44;
-constexpr int64_t kFlush3D = (1 << 18) - 1;
+constexpr int64_t kFlush3D = 299000;
 
 // ---- level index of a value ---------------------------------------------------
 enum LevelMode : int {

@@ -25,6 +25,8 @@
 //     (no global atomics), merged by ecc_reduce and prefix-summed by ecc_scan.
 #include <hip/hip_runtime.h>
 
+#include <cstdlib>
+
 #include <algorithm>
 
 #include "ecc_internal.h"
@@ -403,29 +405,39 @@ template <int VEC, bool SINGLE>
 __device__ __forceinline__ void emit_row(const uint32_t (&up)[VEC + 1], const uint32_t (&mid)[VEC + 1],
                                          const uint32_t (&dn)[VEC + 1], uint32_t mask_or_off, uint32_t scratch,
                                          const uint64_t *dl, uint64_t *hist) {
+    // groups of up to 4 cell pairs: all table reads of a group are issued
+    // before its atomics, so the atomics wait for one LDS round trip, not one each
+    constexpr int NP = VEC / 2, GP = NP < 4 ? NP : 4;
 #pragma unroll
-    for (int j = 1; j < VEC + 1; j += 2) {
-        const uint32_t self = mid[j], self1 = self + 0x00010001u;
-        // bit k of each half: neighbour k precedes the cell, k = NW N NE W E SW S SE
-        uint32_t acc = pk_lt(dn[j + 1], self);
-        acc = acc << 1 | pk_lt(dn[j], self);
-        acc = acc << 1 | pk_lt(dn[j - 1], self);
-        acc = acc << 1 | pk_lt(mid[j + 1], self);
-        acc = acc << 1 | pk_lt(mid[j - 1], self1);
-        acc = acc << 1 | pk_lt(up[j + 1], self1);
-        acc = acc << 1 | pk_lt(up[j], self1);
-        acc = acc << 1 | pk_lt(up[j - 1], self1);
-        uint32_t b0, b1;
-        if constexpr (SINGLE) {
-            const uint32_t sm = self & mask_or_off;  // 0 for the halo lanes
-            b0 = sm & 0xFFFFu;
-            b1 = sm >> 16;
-        } else {
-            b0 = min((self & 0xFFFFu) + mask_or_off, scratch);
-            b1 = min((self >> 16) + mask_or_off, scratch);
+    for (int g0 = 0; g0 < NP; g0 += GP) {
+        uint64_t dv[2 * GP];
+        uint32_t bin[2 * GP];
+#pragma unroll
+        for (int q = 0; q < GP; ++q) {
+            const int j = 2 * (g0 + q) + 1;
+            const uint32_t self = mid[j], self1 = self + 0x00010001u;
+            // bit k of each half: neighbour k precedes the cell, k = NW N NE W E SW S SE
+            uint32_t acc = pk_lt(dn[j + 1], self);
+            acc = acc << 1 | pk_lt(dn[j], self);
+            acc = acc << 1 | pk_lt(dn[j - 1], self);
+            acc = acc << 1 | pk_lt(mid[j + 1], self);
+            acc = acc << 1 | pk_lt(mid[j - 1], self1);
+            acc = acc << 1 | pk_lt(up[j + 1], self1);
+            acc = acc << 1 | pk_lt(up[j], self1);
+            acc = acc << 1 | pk_lt(up[j - 1], self1);
+            if constexpr (SINGLE) {
+                const uint32_t sm = self & mask_or_off;  // 0 for the halo lanes
+                bin[2 * q] = sm & 0xFFFFu;
+                bin[2 * q + 1] = sm >> 16;
+            } else {
+                bin[2 * q] = min((self & 0xFFFFu) + mask_or_off, scratch);
+                bin[2 * q + 1] = min((self >> 16) + mask_or_off, scratch);
+            }
+            dv[2 * q] = dl[acc & 0xFFu];
+            dv[2 * q + 1] = dl[(acc >> 16) & 0xFFu];
         }
-        atomicAdd((unsigned long long *)&hist[b0], (unsigned long long)dl[acc & 0xFFu]);
-        atomicAdd((unsigned long long *)&hist[b1], (unsigned long long)dl[(acc >> 16) & 0xFFu]);
+#pragma unroll
+        for (int q = 0; q < 2 * GP; ++q) atomicAdd((unsigned long long *)&hist[bin[q]], (unsigned long long)dv[q]);
     }
 }
 
@@ -671,14 +683,16 @@ __device__ __forceinline__ void drain_3d(uint64_t *hist, uint32_t *hc, bool crea
             hc[b] = 0;
         }
         const int64_t i0 = ((int64_t)(lo + b)) * G + wg, cs = (int64_t)L * G;
+        // (the crease slot is left alone when the crease is not computed: the
+        // merge skips that channel)
         if (first) {
             partial[i0] = (int32_t)ec;
-            partial[i0 + cs] = (int32_t)cr;
+            if (crease) partial[i0 + cs] = (int32_t)cr;
             partial[i0 + 2 * cs] = (int32_t)surf;
             partial[i0 + 3 * cs] = (int32_t)n;
         } else {
             partial[i0] += (int32_t)ec;
-            partial[i0 + cs] += (int32_t)cr;
+            if (crease) partial[i0 + cs] += (int32_t)cr;
             partial[i0 + 2 * cs] += (int32_t)surf;
             partial[i0 + 3 * cs] += (int32_t)n;
         }
@@ -987,27 +1001,40 @@ struct March3D {
         image(Pc, Pn, M);
 #pragma unroll
         for (int t = 0; t < TY; ++t) {
+            // table reads of the row's VEC voxels first, then their atomics
+            uint32_t tlv[VEC], pm[VEC / 2], selfv[VEC / 2], below[VEC / 2], above[VEC / 2];
+            int32_t en[VEC];
 #pragma unroll
-            for (int j = 1; j < VEC + 1; j += 2) {
+            for (int q = 0; q < VEC / 2; ++q) {
+                const int j = 2 * q + 1;
                 const uint32_t self = Pc[t + 1][j], self1 = self + 0x00010001u;
                 const uint32_t pl = pattern_pair<VEC>(Pc[t], Pc[t + 1], Pc[t + 2], j);
-                const uint32_t pm = pattern_pair<VEC>(M[t], M[t + 1], M[t + 2], j);
+                pm[q] = pattern_pair<VEC>(M[t], M[t + 1], M[t + 2], j);
                 // vertical neighbours: the one below (z-1) precedes on ties,
                 // the one above (z+1) does not
-                const uint32_t below = pk_lt(Pp[t + 1][j], self1);
-                const uint32_t above = pk_lt(Pn[t + 1][j], self);
-                const int32_t en0 = tm[pm & 0xFFu], en1 = tm[(pm >> 16) & 0xFFu];
+                below[q] = pk_lt(Pp[t + 1][j], self1);
+                above[q] = pk_lt(Pn[t + 1][j], self);
+                selfv[q] = self;
+                tlv[2 * q] = tl[pl & 0xFFu];
+                tlv[2 * q + 1] = tl[(pl >> 16) & 0xFFu];
+                en[2 * q] = tm[pm[q] & 0xFFu];
+                en[2 * q + 1] = tm[(pm[q] >> 16) & 0xFFu];
+            }
+#pragma unroll
+            for (int q = 0; q < VEC / 2; ++q) {
+                const int j = 2 * q + 1;
                 // an image pixel's event goes to the voxel of its pair that
                 // enters first (min image) or last (max image)
-                const uint32_t tb = MAXIMG ? below : below ^ 0x00010001u;
-                const uint32_t ta = MAXIMG ? above : above ^ 0x00010001u;
-                const uint32_t nb = below + above;  // per half: vertical neighbours already in
-                const uint32_t lo0 = tl[pl & 0xFFu] + (uint32_t)((tb & 1u) ? E[t][j - 1] : 0) +
-                                     (uint32_t)((ta & 1u) ? en0 : 0) - ((nb & 0xFFFFu) << 23);
-                const uint32_t lo1 = tl[(pl >> 16) & 0xFFu] + (uint32_t)((tb >> 16) ? E[t][j] : 0) +
-                                     (uint32_t)((ta >> 16) ? en1 : 0) - ((nb >> 16) << 23);
-                E[t][j - 1] = en0;
-                E[t][j] = en1;
+                const uint32_t tb = MAXIMG ? below[q] : below[q] ^ 0x00010001u;
+                const uint32_t ta = MAXIMG ? above[q] : above[q] ^ 0x00010001u;
+                const uint32_t nb = below[q] + above[q];  // per half: vertical neighbours already in
+                const uint32_t lo0 = tlv[2 * q] + (uint32_t)((tb & 1u) ? E[t][j - 1] : 0) +
+                                     (uint32_t)((ta & 1u) ? en[2 * q] : 0) - ((nb & 0xFFFFu) << 23);
+                const uint32_t lo1 = tlv[2 * q + 1] + (uint32_t)((tb >> 16) ? E[t][j] : 0) +
+                                     (uint32_t)((ta >> 16) ? en[2 * q + 1] : 0) - ((nb >> 16) << 23);
+                E[t][j - 1] = en[2 * q];
+                E[t][j] = en[2 * q + 1];
+                const uint32_t self = selfv[q];
                 uint32_t b0, b1;
                 if constexpr (SINGLE) {
                     b0 = self & 0xFFFFu;
@@ -1221,7 +1248,7 @@ struct OutPtrs {
 __global__ void __launch_bounds__(1024)
     ecc_merge(const int32_t *__restrict__ partial, int G, int nch, int L, OutPtrs out,
               int64_t *__restrict__ totals, unsigned *__restrict__ counter) {
-    __shared__ int64_t part[1024];
+    __shared__ int64_t wsum[16];
     __shared__ bool last;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int waves = blockDim.x >> 6;
@@ -1231,7 +1258,17 @@ __global__ void __launch_bounds__(1024)
         if (!out.p[ch]) continue;
         const int32_t *src = partial + bin * G;
         int64_t s = 0;
-        for (int g = lane; g < G; g += 64) s += src[g];
+        if ((G & 3) == 0) {  // 16-byte loads, several in flight per lane
+            const u32x4 *s4 = reinterpret_cast<const u32x4 *>(src);
+            const int G4 = G >> 2;
+#pragma unroll 4
+            for (int g = lane; g < G4; g += 64) {
+                const u32x4 v = __builtin_nontemporal_load(s4 + g);
+                s += (int64_t)(int32_t)v.x + (int32_t)v.y + (int32_t)v.z + (int32_t)v.w;
+            }
+        } else {
+            for (int g = lane; g < G; g += 64) s += src[g];
+        }
 #pragma unroll
         for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
         if (lane == 0) totals[bin] = s;
@@ -1253,20 +1290,32 @@ __global__ void __launch_bounds__(1024)
         const int64_t *src = totals + (int64_t)ch * L;
         int64_t s = 0;
         for (int i = beg; i < end; ++i) s += src[i];
-        part[t] = s;
-        __syncthreads();
-        for (int off = 1; off < nt; off <<= 1) {  // Hillis-Steele inclusive scan
-            const int64_t v = t >= off ? part[t - off] : 0;
-            __syncthreads();
-            part[t] += v;
-            __syncthreads();
+        // inclusive scan of the chunk sums: within each wave by shuffles,
+        // then over the wave totals
+        int64_t x = s;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const int64_t y = __shfl_up(x, off);
+            if (lane >= off) x += y;
         }
-        int64_t run = part[t] - s;
+        if (lane == 63) wsum[wave] = x;
+        __syncthreads();
+        if (wave == 0) {
+            int64_t v = lane < waves ? wsum[lane] : 0;
+#pragma unroll
+            for (int off = 1; off < 16; off <<= 1) {
+                const int64_t y = __shfl_up(v, off);
+                if (lane >= off) v += y;
+            }
+            if (lane < waves) wsum[lane] = v;
+        }
+        __syncthreads();
+        int64_t run = (wave > 0 ? wsum[wave - 1] : 0) + x - s;
         for (int i = beg; i < end; ++i) {
             run += src[i];
             dst[i] = run;
         }
-        __syncthreads();
+        __syncthreads();  // wsum is reused by the next channel
     }
     if (threadIdx.x == 0) *counter = 0u;  // ready for the next merge
 }
@@ -1504,7 +1553,12 @@ int launch_merge(const int32_t *partial, int grid, int nch, int L, int64_t *cons
     OutPtrs o;
     for (int c = 0; c < 4; ++c) o.p[c] = c < nch ? out[c] : nullptr;
     const int64_t bins = (int64_t)nch * L;
-    const int blocks = (int)std::min<int64_t>(1024, (bins + 15) / 16);
+    static const int max_blocks = [] {
+        const char *e = std::getenv("ECC_MERGE_BLOCKS");
+        const int x = e ? std::atoi(e) : 256;
+        return x < 1 ? 1 : (x > 4096 ? 4096 : x);
+    }();
+    const int blocks = (int)std::min<int64_t>(max_blocks, (bins + 15) / 16);
     hipLaunchKernelGGL(ecc_merge, dim3(blocks), dim3(1024), 0, (hipStream_t)stream, partial, grid, nch, L,
                        o, totals, counter);
     return (int)hipGetLastError();

@@ -435,6 +435,16 @@ static int wg_per_cu_default() {
     return v;
 }
 
+// Workgroups per CU for the z-marching 3D kernel (environment ECC_ZM_WG_PER_CU overrides).
+static int zm_wg_per_cu() {
+    static int v = [] {
+        const char *e = std::getenv("ECC_ZM_WG_PER_CU");
+        int x = e ? std::atoi(e) : 2;
+        return x < 1 ? 1 : (x > 8 ? 8 : x);
+    }();
+    return v;
+}
+
 ecc_status merge_and_scan(ecc_context ctx, int grid, int nch, int L, int64_t *const outs[4],
                           void *stream) {
     ecc_status s = grow(ctx, ctx->ws.totals, (size_t)nch * L * sizeof(int64_t), "totals");
@@ -464,9 +474,11 @@ ecc_status compute_one(ecc_context ctx, const ecc_field *f, const FieldInfo &fi,
                                       std::max<int64_t>(1, (strips * fi.h + 31) / 32));
         if (grid >= 8) grid -= grid % 8;
     } else if (!crease) {
-        // z-marching kernel: at least ~16 planes per wave
+        // z-marching kernel: at least ~16 planes per wave; its register use
+        // leaves room for two 4-wave workgroups per CU, so one round of
+        // 2 x CUs workgroups (fewer partials than more, smaller rounds)
         const int64_t units = (int64_t)zmarch_3d_columns(fi.h, fi.w) * fi.d;
-        grid = (int)std::min<int64_t>((int64_t)ctx->n_cu * wg_per_cu_default(),
+        grid = (int)std::min<int64_t>((int64_t)ctx->n_cu * zm_wg_per_cu(),
                                       std::max<int64_t>(1, (units + 63) / 64));
         if (grid >= 8) grid -= grid % 8;
         zmarch = zmarch_3d_fits(fi.h, fi.w, grid);
