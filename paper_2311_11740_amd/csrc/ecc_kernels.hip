@@ -174,12 +174,12 @@ typedef u32x4 u32x4_u __attribute__((aligned(1)));
 //    hardware serves unaligned vector loads).  Elements past the row end come
 //    from the next row and are masked.  A block that would run past the end
 //    of the buffer is loaded from the last 16 bytes of the buffer instead and
-//    shifted back into place when converted (needs at least VEC elements).
-//  kLoadElement: element by element (fields of fewer than VEC elements).
+//    shifted back into place when converted.  Fields of fewer than VEC
+//    elements are handed over padded to VEC elements by the host.
 // The row index is clamped into the field by the caller: loads are never
 // skipped, so the compiler can keep several of them in flight (a skipped load
 // would make it wait for all outstanding ones).
-enum LoadMode : int { kLoadElement = 0, kLoadVector = 1, kLoadAligned = 2 };
+enum LoadMode : int { kLoadVector = 1, kLoadAligned = 2 };
 
 template <typename T, int AL>
 __device__ __forceinline__ void fetch_row(const T *__restrict__ data, int r, int64_t w, int64_t x0,
@@ -192,7 +192,7 @@ __device__ __forceinline__ void fetch_row(const T *__restrict__ data, int r, int
         raw.w[0] = q.x; raw.w[1] = q.y; raw.w[2] = q.z; raw.w[3] = q.w;
         raw.valid = in ? (1u << VEC) - 1u : 0u;
         raw.shift = 0;
-    } else if constexpr (AL == kLoadVector) {
+    } else {
         const int64_t li = (int64_t)r * w + (in ? x0 : 0);      // element index of the block
         const int64_t lc = li < last_block ? li : last_block;  // last_block = h * w - VEC
         const u32x4 q = __builtin_nontemporal_load(reinterpret_cast<const u32x4_u *>(data + lc));
@@ -200,23 +200,6 @@ __device__ __forceinline__ void fetch_row(const T *__restrict__ data, int r, int
         const int64_t n_in = in ? w - x0 : 0;
         raw.valid = n_in >= VEC ? (1u << VEC) - 1u : (1u << n_in) - 1u;
         raw.shift = (uint32_t)(li - lc);
-    } else {
-        raw.w[0] = raw.w[1] = raw.w[2] = raw.w[3] = 0;
-        raw.valid = 0;
-        raw.shift = 0;
-#pragma unroll
-        for (int i = 0; i < VEC; ++i) {
-            const int64_t x = x0 + i;
-            const bool ok = x >= 0 && x < w;
-            uint32_t bits;
-            if constexpr (sizeof(T) == 4)
-                bits = __float_as_uint(row[ok ? x : 0]);
-            else
-                bits = (uint32_t)row[ok ? x : 0];
-            constexpr int per = 4 / sizeof(T);
-            raw.w[i / per] |= (ok ? bits : 0u) << (8 * sizeof(T) * (i % per));
-            raw.valid |= (ok ? 1u : 0u) << i;
-        }
     }
 }
 
@@ -455,7 +438,8 @@ __device__ __forceinline__ void stream_run_2d(const T *__restrict__ data, int h,
     const int64_t x0 = xs + (int64_t)lane * VEC;
     const bool full = xs >= 0 && xs + 64 * VEC <= w;
     auto clamp_row = [h](int r) { return r < 0 ? 0 : (r >= h ? h - 1 : r); };
-    const int64_t last_block = (int64_t)h * w - VEC;
+    // tiny fields arrive padded to one whole block, so the clamp stays at or above 0
+    const int64_t last_block = (int64_t)h * w > VEC ? (int64_t)h * w - VEC : 0;
 
     uint32_t R[3][VEC + 1];  // R[r % 3] holds row r (relative to ra)
     RawRow ring[PF];
@@ -780,7 +764,7 @@ __device__ __forceinline__ void load_block3(const T *p, RawRow3 &raw) {
 }
 
 // row y of plane z (both clamped into the field by the caller); unconditional
-// loads, in the three modes of the 2D kernels (a block is 4 elements here)
+// loads, in the two modes of the 2D kernels (a block is 4 elements here)
 template <typename T, int AL>
 __device__ __forceinline__ void fetch_row3(const T *__restrict__ data, int64_t h, int64_t w, int z, int y,
                                            int64_t xs, int64_t x0, int lane, int64_t last_block, RawRow3 &raw) {
@@ -791,19 +775,11 @@ __device__ __forceinline__ void fetch_row3(const T *__restrict__ data, int64_t h
     raw.shift = 0;
     if constexpr (AL == kLoadAligned) {  // whole blocks: inside or outside the row
         load_block3<T, false>(row + (x0 < w ? x0 : 0), raw);
-    } else if constexpr (AL == kLoadVector) {
+    } else {
         const int64_t li = rbase + (x0 < w ? x0 : 0);
         const int64_t lc = li < last_block ? li : last_block;  // last_block = d * h * w - VEC
         load_block3<T, true>(data + lc, raw);
         raw.shift = (uint32_t)(li - lc);
-    } else {
-#pragma unroll
-        for (int i = 0; i < VEC; ++i) {
-            const int64_t x = x0 + i;
-            const uint32_t b = elem_bits(row + (x < w ? x : 0));
-            constexpr int per = 4 / sizeof(T);
-            raw.w[i / per] |= (x < w ? b : 0u) << (8 * sizeof(T) * (i % per));
-        }
     }
     int64_t hx = lane == 0 ? xs - 1 : (lane == 63 ? xs + 64 * VEC : x0);
     hx = hx < 0 ? 0 : (hx >= w ? w - 1 : hx);
@@ -1110,7 +1086,7 @@ __global__ void __launch_bounds__(256)
         const int64_t xs = strip * 64 * VEC;
         March3D<T, LM, AL, MAXIMG, SINGLE, TY, ThrLds> m{data, (int)d, h, w, lv, thr, lo, W, cpass, tl, tm,
                                                           hist, xs, xs + (int64_t)lane * VEC, (int)(yb * TY),
-                                                          (int)(z_lo + zb), lane, scratch, d * h * w - VEC};
+                                                          (int)(z_lo + zb), lane, scratch, d * h * w > VEC ? d * h * w - VEC : 0};
         m.run((int)(z_lo + za));
         u += zb - za;
     }
@@ -1348,9 +1324,8 @@ size_t lds_bytes_2d(int window, int L) {
 size_t lds_bytes_3d(int window, bool want_crease) { return (size_t)window * (want_crease ? 12 : 8); }
 
 int load_mode_2d(const void *data, int64_t h, int64_t w, int elem_bytes) {
-    if ((uintptr_t)data % 16 == 0 && (w * elem_bytes) % 16 == 0) return kLoadAligned;
-    const int vec = 16 / elem_bytes;
-    return h * w >= vec ? kLoadVector : kLoadElement;
+    (void)h;
+    return ((uintptr_t)data % 16 == 0 && (w * elem_bytes) % 16 == 0) ? kLoadAligned : kLoadVector;
 }
 
 // cells one workgroup may add to its LDS bins in a launch of `rows` rows
@@ -1388,11 +1363,9 @@ static int launch_2d_t(const Launch2D &a, hipStream_t s) {
 
 template <typename T, int LM, bool SINGLE>
 static int launch_2d_sg(const Launch2D &a, hipStream_t s) {
-    switch (load_mode_2d(a.data, a.h, a.w, (int)sizeof(T))) {
-    case kLoadAligned: return launch_2d_t<T, LM, kLoadAligned, SINGLE>(a, s);
-    case kLoadVector: return launch_2d_t<T, LM, kLoadVector, SINGLE>(a, s);
-    default: return launch_2d_t<T, LM, kLoadElement, SINGLE>(a, s);
-    }
+    return load_mode_2d(a.data, a.h, a.w, (int)sizeof(T)) == kLoadAligned
+               ? launch_2d_t<T, LM, kLoadAligned, SINGLE>(a, s)
+               : launch_2d_t<T, LM, kLoadVector, SINGLE>(a, s);
 }
 
 template <typename T, int LM>
@@ -1403,12 +1376,12 @@ static int launch_2d_al(const Launch2D &a, hipStream_t s) {
 
 template <typename T>
 static int launch_2d_dt(const Launch2D &a, hipStream_t s) {
-    switch (a.lv.mode) {
-    case LM_IDENTITY: return launch_2d_al<T, LM_IDENTITY>(a, s);
-    case LM_LUT: return launch_2d_al<T, LM_LUT>(a, s);
-    case LM_AFFINE: return launch_2d_al<T, LM_AFFINE>(a, s);
-    default: return launch_2d_al<T, LM_SEARCH>(a, s);
-    }
+    // integer fields have identity levels or a value -> level table; float
+    // fields always have thresholds (affine or searched)
+    if constexpr (sizeof(T) < 4)
+        return a.lv.mode == LM_LUT ? launch_2d_al<T, LM_LUT>(a, s) : launch_2d_al<T, LM_IDENTITY>(a, s);
+    else
+        return a.lv.mode == LM_AFFINE ? launch_2d_al<T, LM_AFFINE>(a, s) : launch_2d_al<T, LM_SEARCH>(a, s);
 }
 
 int launch_2d(const Launch2D &a, void *stream) {
@@ -1475,10 +1448,10 @@ static int launch_zm_t(const Launch3D &a, hipStream_t s) {
 template <typename T, int LM, bool MAXIMG, bool SINGLE>
 static int launch_zm_sg(const Launch3D &a, hipStream_t s) {
     constexpr int VEC = Elem3<T>::VEC, VB = VEC * (int)sizeof(T);
+    (void)VEC;
     if ((uintptr_t)a.data % VB == 0 && (a.w * (int64_t)sizeof(T)) % VB == 0)
         return launch_zm_t<T, LM, kLoadAligned, MAXIMG, SINGLE>(a, s);
-    if (a.d * a.h * a.w >= VEC) return launch_zm_t<T, LM, kLoadVector, MAXIMG, SINGLE>(a, s);
-    return launch_zm_t<T, LM, kLoadElement, MAXIMG, SINGLE>(a, s);
+    return launch_zm_t<T, LM, kLoadVector, MAXIMG, SINGLE>(a, s);
 }
 
 template <typename T, int LM, bool MAXIMG>
@@ -1495,12 +1468,10 @@ static int launch_3d_cr(const Launch3D &a, hipStream_t s) {
 
 template <typename T>
 static int launch_3d_dt(const Launch3D &a, hipStream_t s) {
-    switch (a.lv.mode) {
-    case LM_IDENTITY: return launch_3d_cr<T, LM_IDENTITY>(a, s);
-    case LM_LUT: return launch_3d_cr<T, LM_LUT>(a, s);
-    case LM_AFFINE: return launch_3d_cr<T, LM_AFFINE>(a, s);
-    default: return launch_3d_cr<T, LM_SEARCH>(a, s);
-    }
+    if constexpr (sizeof(T) < 4)
+        return a.lv.mode == LM_LUT ? launch_3d_cr<T, LM_LUT>(a, s) : launch_3d_cr<T, LM_IDENTITY>(a, s);
+    else
+        return a.lv.mode == LM_AFFINE ? launch_3d_cr<T, LM_AFFINE>(a, s) : launch_3d_cr<T, LM_SEARCH>(a, s);
 }
 
 int launch_3d(const Launch3D &a, void *stream) {
@@ -1520,19 +1491,19 @@ size_t lds_bytes_batch_2d(int lm, int max_L) {
 template <typename T>
 static int launch_batch_t(int lm, const BatchField2D *fields, const BatchItem *items, const int32_t *wg_first,
                           int grid, const uint64_t *luts, size_t lds, hipStream_t s) {
-    switch (lm) {
-    case LM_IDENTITY:
-        hipLaunchKernelGGL((ecc2d_batch<T, LM_IDENTITY>), dim3(grid), dim3(256), lds, s, fields, items, wg_first, luts);
-        break;
-    case LM_LUT:
-        hipLaunchKernelGGL((ecc2d_batch<T, LM_LUT>), dim3(grid), dim3(256), lds, s, fields, items, wg_first, luts);
-        break;
-    case LM_AFFINE:
-        hipLaunchKernelGGL((ecc2d_batch<T, LM_AFFINE>), dim3(grid), dim3(256), lds, s, fields, items, wg_first, luts);
-        break;
-    default:
-        hipLaunchKernelGGL((ecc2d_batch<T, LM_SEARCH>), dim3(grid), dim3(256), lds, s, fields, items, wg_first, luts);
-        break;
+    if constexpr (sizeof(T) < 4) {
+        if (lm == LM_LUT)
+            hipLaunchKernelGGL((ecc2d_batch<T, LM_LUT>), dim3(grid), dim3(256), lds, s, fields, items, wg_first, luts);
+        else
+            hipLaunchKernelGGL((ecc2d_batch<T, LM_IDENTITY>), dim3(grid), dim3(256), lds, s, fields, items, wg_first,
+                               luts);
+    } else {
+        if (lm == LM_AFFINE)
+            hipLaunchKernelGGL((ecc2d_batch<T, LM_AFFINE>), dim3(grid), dim3(256), lds, s, fields, items, wg_first,
+                               luts);
+        else
+            hipLaunchKernelGGL((ecc2d_batch<T, LM_SEARCH>), dim3(grid), dim3(256), lds, s, fields, items, wg_first,
+                               luts);
     }
     return (int)hipGetLastError();
 }

@@ -69,6 +69,7 @@ struct ecc_context_s {
     bool ws_used = false;
     ecc::BatchState *batch = nullptr;
     void *d_counter = nullptr;  // merge kernel's completion ticket (kept at zero)
+    void *d_tiny = nullptr;     // 256 B: padded copy of fields smaller than one vector load
     // kernel timing (ecc_profile_enable)
     bool prof_on = false;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_events;

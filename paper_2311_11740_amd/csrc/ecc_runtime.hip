@@ -176,6 +176,8 @@ extern "C" ecc_status ecc_create(int device, ecc_context *out) {
         return fail(ECC_ERR_OUT_OF_MEMORY, "hipMalloc(counter) failed");
     }
     e = (int)hipMemset(ctx->d_counter, 0, 256);
+    if (!e) e = (int)hipMalloc(&ctx->d_tiny, 256);
+    if (!e) e = (int)hipMemset(ctx->d_tiny, 0, 256);
     if (!e) e = (int)hipDeviceSynchronize();
     if (e) {
         ecc_destroy(ctx);
@@ -203,6 +205,7 @@ extern "C" ecc_status ecc_destroy(ecc_context ctx) {
     }
     ctx->ws.release();
     if (ctx->d_counter) hipFree(ctx->d_counter);
+    if (ctx->d_tiny) hipFree(ctx->d_tiny);
     if (ctx->ws_event) hipEventDestroy(ctx->ws_event);
     destroy_batch_state(ctx);
     delete ctx;
@@ -491,13 +494,24 @@ ecc_status compute_one(ecc_context ctx, const ecc_field *f, const FieldInfo &fi,
     s = grow(ctx, ctx->ws.partial, (size_t)grid * nch * L * sizeof(int32_t), "partials");
     if (s != ECC_OK) return s;
     int32_t *partial = (int32_t *)ctx->ws.partial.ptr;
+    // the kernels load whole blocks of 16 bytes (2D) or 4 elements (3D), clamped
+    // to the end of the field: a field smaller than one block is copied into a
+    // buffer that holds a whole block
+    const void *data = f->data;
+    const int64_t block = fi.ndim == 2 ? vec_2d(fi.dtype) : 4;
+    if (fi.cells < block) {
+        int e = (int)hipMemcpyAsync(ctx->d_tiny, f->data, (size_t)fi.cells * fi.elem_bytes,
+                                    hipMemcpyDeviceToDevice, (hipStream_t)stream);
+        if (e) return hip_fail(e, "hipMemcpyAsync(small field)");
+        data = ctx->d_tiny;
+    }
     for (int lo = 0; lo < L; lo += win) {
         const int hi = std::min(L, lo + win);
         if (fi.ndim == 2) {
             int slot = -1;
             s = prof_begin(ctx, stream, &slot);
             if (s != ECC_OK) return s;
-            Launch2D a{f->data, fi.dtype, fi.h, fi.w, lv, lo, hi, ctx->d_delta2[k], partial, grid,
+            Launch2D a{data, fi.dtype, fi.h, fi.w, lv, lo, hi, ctx->d_delta2[k], partial, grid,
                        0, fi.h, false};
             int e = launch_2d(a, stream);
             if (e) return hip_fail(e, "2D kernel launch");
@@ -507,7 +521,7 @@ ecc_status compute_one(ecc_context ctx, const ecc_field *f, const FieldInfo &fi,
             int slot = -1;
             s = prof_begin(ctx, stream, &slot);
             if (s != ECC_OK) return s;
-            Launch3D a{f->data, fi.dtype, fi.d, fi.h, fi.w, lv, lo, hi, ctx->d_vtab3[k], partial, grid, crease,
+            Launch3D a{data, fi.dtype, fi.d, fi.h, fi.w, lv, lo, hi, ctx->d_vtab3[k], partial, grid, crease,
                        zmarch ? ctx->d_zm3[k] : nullptr, k == 1};
             int e = launch_3d(a, stream);
             if (e) return hip_fail(e, "3D kernel launch");
