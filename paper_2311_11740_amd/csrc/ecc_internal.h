@@ -17,6 +17,10 @@ void clear_error();
 void vertex_table_2d(int connectivity, int32_t out[16][4]);
 void vertex_table_3d(int connectivity, int32_t out[256][4]);
 void cell_delta_table_2d(int connectivity, int32_t delta[256][3]);
+// The kernels index per-cell tables by a permuted pattern: index bit i (i < 4)
+// is neighbour 2i and bit 4+i neighbour 2i+1 of kNbr2.  Returns the kNbr2-order
+// pattern of kernel index n.
+int pattern_of_index(int n);
 extern const int kNbr2[8][2];
 
 // ---- histogram word layouts ---------------------------------------------------

@@ -158,6 +158,33 @@ __device__ __forceinline__ uint32_t pk_lt(uint32_t q, uint32_t ref) {
     return __builtin_bit_cast(uint32_t, __builtin_bit_cast(u16x2, d) >> (unsigned short)15);
 }
 
+// Pattern of the 8 neighbours of two cells.  d[k] = q_k - ref_k per 16-bit
+// half (k = NW N NE W E SW S SE, ref = cell level, +1 for neighbours that win
+// ties), so the sign bit of each half says whether neighbour k entered
+// before that cell.  A byte permute turns the sign bits of two such words
+// into 0x00/0xFF bytes (selectors 8-11), four bit-selects gather them, and a
+// final shuffle leaves the index of the low cell in bits 0-7 and of the high
+// cell in bits 16-23.  Index bit i (i < 4) is neighbour 2i, bit 4+i is
+// neighbour 2i+1 (the host tables are built in this order).
+__device__ __forceinline__ uint32_t pk_diff(uint32_t q, uint32_t ref) {
+    return __builtin_bit_cast(uint32_t, __builtin_bit_cast(i16x2, q) - __builtin_bit_cast(i16x2, ref));
+}
+
+__device__ __forceinline__ uint32_t gather_pattern(uint32_t d0, uint32_t d1, uint32_t d2, uint32_t d3, uint32_t d4,
+                                                   uint32_t d5, uint32_t d6, uint32_t d7) {
+    // bytes: [low cell, even k | low cell, odd k | high cell, even k | high cell, odd k]
+    constexpr uint32_t kSel = 0x0B090A08u;
+    const uint32_t p0 = __builtin_amdgcn_perm(d1, d0, kSel);
+    const uint32_t p1 = __builtin_amdgcn_perm(d3, d2, kSel);
+    const uint32_t p2 = __builtin_amdgcn_perm(d5, d4, kSel);
+    const uint32_t p3 = __builtin_amdgcn_perm(d7, d6, kSel);
+    uint32_t r = p0 & 0x01010101u;
+    r = (p1 & 0x02020202u) | (r & ~0x02020202u);
+    r = (p2 & 0x04040404u) | (r & ~0x04040404u);
+    r = (p3 & 0x08080808u) | (r & ~0x08080808u);
+    return (r & 0x000F000Fu) | ((r >> 4) & 0x00F000F0u);
+}
+
 struct RawRow {
     uint32_t w[4];   // 16 bytes: VEC raw elements of this lane
     uint32_t valid;  // bit i: element i lies inside the field
@@ -399,15 +426,10 @@ __device__ __forceinline__ void emit_row(const uint32_t (&up)[VEC + 1], const ui
         for (int q = 0; q < GP; ++q) {
             const int j = 2 * (g0 + q) + 1;
             const uint32_t self = mid[j], self1 = self + 0x00010001u;
-            // bit k of each half: neighbour k precedes the cell, k = NW N NE W E SW S SE
-            uint32_t acc = pk_lt(dn[j + 1], self);
-            acc = acc << 1 | pk_lt(dn[j], self);
-            acc = acc << 1 | pk_lt(dn[j - 1], self);
-            acc = acc << 1 | pk_lt(mid[j + 1], self);
-            acc = acc << 1 | pk_lt(mid[j - 1], self1);
-            acc = acc << 1 | pk_lt(up[j + 1], self1);
-            acc = acc << 1 | pk_lt(up[j], self1);
-            acc = acc << 1 | pk_lt(up[j - 1], self1);
+            const uint32_t acc = gather_pattern(pk_diff(up[j - 1], self1), pk_diff(up[j], self1),
+                                                pk_diff(up[j + 1], self1), pk_diff(mid[j - 1], self1),
+                                                pk_diff(mid[j + 1], self), pk_diff(dn[j - 1], self),
+                                                pk_diff(dn[j], self), pk_diff(dn[j + 1], self));
             if constexpr (SINGLE) {
                 const uint32_t sm = self & mask_or_off;  // 0 for the halo lanes
                 bin[2 * q] = sm & 0xFFFFu;
@@ -869,15 +891,9 @@ template <int VEC>
 __device__ __forceinline__ uint32_t pattern_pair(const uint32_t (&u)[VEC + 1], const uint32_t (&m)[VEC + 1],
                                                  const uint32_t (&d)[VEC + 1], int j) {
     const uint32_t self = m[j], self1 = self + 0x00010001u;
-    uint32_t acc = pk_lt(d[j + 1], self);
-    acc = acc << 1 | pk_lt(d[j], self);
-    acc = acc << 1 | pk_lt(d[j - 1], self);
-    acc = acc << 1 | pk_lt(m[j + 1], self);
-    acc = acc << 1 | pk_lt(m[j - 1], self1);
-    acc = acc << 1 | pk_lt(u[j + 1], self1);
-    acc = acc << 1 | pk_lt(u[j], self1);
-    acc = acc << 1 | pk_lt(u[j - 1], self1);
-    return acc;
+    return gather_pattern(pk_diff(u[j - 1], self1), pk_diff(u[j], self1), pk_diff(u[j + 1], self1),
+                          pk_diff(m[j - 1], self1), pk_diff(m[j + 1], self), pk_diff(d[j - 1], self),
+                          pk_diff(d[j], self), pk_diff(d[j + 1], self));
 }
 
 // per-pixel image of two planes: min (26-C) or max (6-C), packed

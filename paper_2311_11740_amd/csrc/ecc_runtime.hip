@@ -123,10 +123,12 @@ extern "C" ecc_status ecc_create(int device, ecc_context *out) {
         const int conn2 = k == 0 ? 8 : 4;
         int32_t dt[256][3];
         cell_delta_table_2d(conn2, dt);
-        uint64_t packed[256];
-        for (int p = 0; p < 256; ++p)
-            packed[p] = (uint64_t)(dt[p][0] + kEcBias2) |
+        uint64_t packed[256];  // in the kernels' index order
+        for (int n = 0; n < 256; ++n) {
+            const int p = pattern_of_index(n);
+            packed[n] = (uint64_t)(dt[p][0] + kEcBias2) |
                         (uint64_t)(dt[p][1] + kPerBias2) << kShiftPer2 | 1ull << kShiftCnt2;
+        }
         ecc_status s = upload((void **)&ctx->d_delta2[k], packed, sizeof(packed));
         if (s != ECC_OK) {
             ecc_destroy(ctx);
@@ -151,10 +153,11 @@ extern "C" ecc_status ecc_create(int device, ecc_context *out) {
         // biases, [256, 512) the image delta, signs as the decomposition takes them
         uint32_t zt[512];
         const int sgn = k == 0 ? -1 : 1;
-        for (int p = 0; p < 256; ++p) {
+        for (int n = 0; n < 256; ++n) {  // in the kernels' index order
+            const int p = pattern_of_index(n);
             const int per = 4 - 2 * __builtin_popcount(p & 0x5A);  // N, W, E, S bits
-            zt[p] = (uint32_t)(sgn * dt[p][0] + kEcBias3) + ((uint32_t)(per + 8) << kShiftSurf3);
-            zt[256 + p] = (uint32_t)(-sgn * dt[p][0]);
+            zt[n] = (uint32_t)(sgn * dt[p][0] + kEcBias3) + ((uint32_t)(per + 8) << kShiftSurf3);
+            zt[256 + n] = (uint32_t)(-sgn * dt[p][0]);
         }
         s = upload((void **)&ctx->d_zm3[k], zt, sizeof(zt));
         if (s != ECC_OK) {

@@ -62,6 +62,15 @@ void vertex_table_2d(int connectivity, int32_t out[16][4]) {
 // neighbour order of the 8-bit per-cell pattern (row offset, column offset)
 const int kNbr2[8][2] = {{-1, -1}, {-1, 0}, {-1, 1}, {0, -1}, {0, 1}, {1, -1}, {1, 0}, {1, 1}};
 
+int pattern_of_index(int n) {
+    int p = 0;
+    for (int i = 0; i < 4; ++i) {
+        p |= ((n >> i) & 1) << (2 * i);            // index bit i: neighbour 2i
+        p |= ((n >> (4 + i)) & 1) << (2 * i + 1);  // index bit 4+i: neighbour 2i+1
+    }
+    return p;
+}
+
 void cell_delta_table_2d(int connectivity, int32_t delta[256][3]) {
     int32_t T[16][4];
     vertex_table_2d(connectivity, T);
