@@ -310,6 +310,31 @@ __device__ __forceinline__ uint32_t pack_lo16(uint32_t a, uint32_t b) {  // (a.l
     return __builtin_amdgcn_perm(b, a, 0x05040100u);
 }
 
+// Integer values with identity levels, two per word: the pair of values in
+// the 16-bit halves of q mapped to lam' = min(max(v + 1 - lo, 0), W + 1) with
+// saturating packed arithmetic (a value at or above L lands on W + 1 too).
+__device__ __forceinline__ uint32_t identity_pair(uint32_t q, uint32_t lo2, uint32_t never2) {
+    u16x2 v = __builtin_bit_cast(u16x2, q);
+    v = __builtin_elementwise_add_sat(v, (u16x2){1, 1});
+    v = __builtin_elementwise_sub_sat(v, __builtin_bit_cast(u16x2, lo2));
+    v = __builtin_elementwise_min(v, __builtin_bit_cast(u16x2, never2));
+    return __builtin_bit_cast(uint32_t, v);
+}
+
+// values k and k+1 (k even) of a lane's raw block as the halves of a word
+template <typename T>
+__device__ __forceinline__ uint32_t raw_pair(const uint32_t *w, int k) {
+    if constexpr (sizeof(T) == 2)
+        return w[k >> 1];
+    else  // bytes k, k+1 of the block into the low bytes of the two halves
+        return __builtin_amdgcn_perm(0u, w[k >> 2], (k & 2) ? 0x0C030C02u : 0x0C010C00u);
+}
+
+// (a.hi, b.lo): the 16-bit value just below b's low half
+__device__ __forceinline__ uint32_t straddle(uint32_t a, uint32_t b) {
+    return __builtin_amdgcn_alignbit(b, a, 16);
+}
+
 template <typename T, int LM, typename TH>
 __device__ __forceinline__ void convert_row(const RawRow &raw_in, bool row_ok, bool full, const LevelArgs &lv,
                                             const TH &thr, int lo, int W, float cpass,
@@ -323,6 +348,29 @@ __device__ __forceinline__ void convert_row(const RawRow &raw_in, bool row_ok, b
     }
     RawRow raw = raw_in;
     if (__any(raw.shift != 0)) unshift_row<T>(raw);  // rare: blocks at the end of the buffer
+    if constexpr (LM == LM_IDENTITY) {  // integer values, two per packed operation
+        const uint32_t lo2 = (uint32_t)lo * 0x10001u, nv2 = never * 0x10001u;
+        uint32_t Q[VEC / 2];  // Q[k] = (lam'[2k], lam'[2k+1])
+#pragma unroll
+        for (int k = 0; k < VEC / 2; ++k) Q[k] = identity_pair(raw_pair<T>(raw.w, 2 * k), lo2, nv2);
+        if (!full) {  // uniform: cells outside the field never enter
+#pragma unroll
+            for (int k = 0; k < VEC / 2; ++k) {
+                const uint32_t m = ((raw.valid >> (2 * k)) & 1u ? 0u : 0xFFFFu) |
+                                   ((raw.valid >> (2 * k + 1)) & 1u ? 0u : 0xFFFF0000u);
+                Q[k] = (Q[k] & ~m) | (nv2 & m);
+            }
+        }
+        const uint32_t lq = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)Q[VEC / 2 - 1], 0x138, 0xf, 0xf, false);
+        const uint32_t rq = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)Q[0], 0x130, 0xf, 0xf, false);
+        P[0] = straddle(lq, Q[0]);
+#pragma unroll
+        for (int k = 0; k < VEC / 2; ++k) {
+            P[2 * k + 1] = Q[k];
+            P[2 * k + 2] = straddle(Q[k], k + 1 < VEC / 2 ? Q[k + 1] : rq);
+        }
+        return;
+    }
     uint32_t lam[VEC];  // low 16 bits: lam'
     const int base = lo - 1;
     if constexpr (LM == LM_AFFINE) {
@@ -870,6 +918,28 @@ __device__ __forceinline__ void convert_row3(const RawRow3 &raw_in, bool row_ok,
     }
     RawRow3 raw = raw_in;
     if (__any(raw.shift != 0)) unshift_row3<T>(raw);  // rare: blocks at the end of the buffer
+    if constexpr (LM == LM_IDENTITY) {  // integer values, two per packed operation
+        const uint32_t lo2 = (uint32_t)lo * 0x10001u, nv2 = never * 0x10001u;
+        uint32_t Q0 = identity_pair(raw_pair<T>(raw.w, 0), lo2, nv2);
+        uint32_t Q1 = identity_pair(raw_pair<T>(raw.w, 2), lo2, nv2);
+        if (!(xs + 64 * VEC <= w)) {  // uniform: cells outside the field never enter
+            const uint32_t m0 = (x0 < w ? 0u : 0xFFFFu) | (x0 + 1 < w ? 0u : 0xFFFF0000u);
+            const uint32_t m1 = (x0 + 2 < w ? 0u : 0xFFFFu) | (x0 + 3 < w ? 0u : 0xFFFF0000u);
+            Q0 = (Q0 & ~m0) | (nv2 & m0);
+            Q1 = (Q1 & ~m1) | (nv2 & m1);
+        }
+        const uint32_t hl = level3<T, LM>(raw.halo, lv, thr, lo, W, cpass);
+        uint32_t lq = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)Q1, 0x138, 0xf, 0xf, false);
+        uint32_t rq = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)Q0, 0x130, 0xf, 0xf, false);
+        if (lane == 0) lq = (xs > 0 ? hl : never) << 16;
+        if (lane == 63) rq = xs + 64 * VEC < w ? hl : never;
+        P[0] = straddle(lq, Q0);
+        P[1] = Q0;
+        P[2] = straddle(Q0, Q1);
+        P[3] = Q1;
+        P[4] = straddle(Q1, rq);
+        return;
+    }
     uint32_t lam[VEC];
 #pragma unroll
     for (int i = 0; i < VEC; ++i)
