@@ -11,18 +11,19 @@
 // without p to its mask with p.  The sum of those differences, the cell's
 // delta, depends only on which of p's neighbours entered before p.
 //
-// Kernel layout:
-//   * one workgroup = 256 threads = 4 wave64s; persistent grid, each
-//     workgroup takes a contiguous range of tiles (XCD-aware numbering so
-//     neighbouring tiles share an L2);
-//   * a tile plus a one-cell halo is read from HBM (coalesced along the
-//     contiguous axis), mapped to level indices once, and staged in LDS as u16;
-//   * each thread marches a column of the tile, keeping its 3x3 (2D) or 3x3x3
-//     (3D) window of levels in registers, forms the "entered before p" pattern
-//     and adds the cell's packed delta to an LDS histogram with one 64-bit
-//     atomic (fields biased to stay non-negative, see ecc_internal.h);
-//   * histograms are drained into a per-workgroup slice of a partials buffer
-//     (no global atomics), merged by ecc_reduce and prefix-summed by ecc_scan.
+// Kernel layout (details at each kernel):
+//   * 2D (`ecc2d_stream`): a wave streams the rows of a strip of columns from
+//     HBM (one vector load per lane and row, several rows in flight), maps
+//     values to level indices once, forms each cell's "entered before"
+//     neighbour pattern from packed 16-bit differences and adds the cell's
+//     packed delta to the workgroup's LDS histogram with one 64-bit atomic
+//     (fields biased to stay non-negative, see ecc_internal.h);
+//   * 3D (`ecc3d_stream`): a wave marches the z-planes of a column of 4 rows
+//     x 256 columns with a slab decomposition that needs two 2D patterns per
+//     voxel; `ecc3d_tile` (LDS-staged 3x3x3 windows) also computes the crease;
+//   * each workgroup drains its histogram into its slice of level-major
+//     partials; `ecc_merge` sums them per level and its last block scans;
+//   * `ecc2d_batch` runs many fields in one persistent launch.
 #include <hip/hip_runtime.h>
 
 #include <cstdlib>
@@ -245,19 +246,6 @@ __device__ __forceinline__ void unshift_row(RawRow &raw) {
     }
     raw.w[0] = (uint32_t)lo; raw.w[1] = (uint32_t)(lo >> 32);
     raw.w[2] = (uint32_t)hi; raw.w[3] = (uint32_t)(hi >> 32);
-}
-
-// Level index of a float value with the affine estimate, without the
-// threshold check; `near` is set where that check is needed.
-__device__ __forceinline__ uint32_t level_affine_fast(float x, const LevelArgs &a, float half_m_eps,
-                                                      bool &near) {
-    const float u = __builtin_fmaf(x, a.inv_step, a.u0);
-    const float fr = __builtin_amdgcn_fractf(u);
-    near = !(__builtin_fabsf(fr - 0.5f) <= half_m_eps);  // also true for NaN and inf
-    const float uc = __builtin_amdgcn_fmed3f(u, -2.0f, (float)a.L + 2.0f);
-    int g = (int)__builtin_floorf(uc) + 1;
-    g = g < 0 ? 0 : (g > a.L ? a.L : g);
-    return (uint32_t)g;
 }
 
 // exact level of x given an estimate g that is off by at most one; only

@@ -156,3 +156,32 @@ def test_binding_uses_one_hip_runtime():
     out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300)
     assert out.returncode == 0, out.stderr
     assert out.stdout.strip() == "1", out.stdout
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py runs on one GPU: --gpus 2 exits with status 2 and says why."""
+    import json
+    import subprocess
+    import sys
+    out = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                         capture_output=True, text=True, timeout=300)
+    assert out.returncode == 2
+    msg = json.loads(out.stdout.strip().splitlines()[-1])
+    assert "one GPU" in msg["error"] and msg["n_gpus"] == 2
+
+
+def test_synthetic_inputs_do_not_depend_on_worker_count():
+    """Every generated field has its own seed: one process or several give the same data."""
+    from paper_2311_11740_amd import synth
+    a = synth.batch_2d_u8(n=6, lo=16, hi=64, workers=1)
+    b = synth.batch_2d_u8(n=6, lo=16, hi=64, workers=2)
+    assert [x.data.shape for x in a] == [x.data.shape for x in b]
+    assert all(np.array_equal(x.data, y.data) for x, y in zip(a, b))
+    assert all(x.data.dtype == np.uint8 and x.n_levels == 256 for x in a)
+
+
+def test_binding_reports_missing_library(tmp_path, monkeypatch):
+    """Without libecc.so every binding call raises; nothing falls back to the CPU."""
+    monkeypatch.setattr(ecc, "_lib", None)
+    with pytest.raises(ecc.EccLibraryMissing):
+        ecc.load(str(tmp_path / "libecc.so"))
