@@ -325,7 +325,7 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the batched vs per-field comparison")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving comparison")
     ap.add_argument("--serving-requests", type=int, default=2000)
-    ap.add_argument("--serving-rates", type=str, default="500,2000,4000,8000",
+    ap.add_argument("--serving-rates", type=str, default="500,2000,4000,8000,16000",
                     help="Poisson arrival rates (requests/s), comma separated")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--gen-workers", type=int, default=min(16, os.cpu_count() or 1),

@@ -178,16 +178,16 @@ ecc_status ecc_profile_read(ecc_context ctx, double *total_ms, int64_t *launches
  * Discussion: many small images per second).
  *
  * At creation the server reserves a device arena of hbm_budget_bytes, a pinned
- * host staging arena of the same size and max_slots slots, and starts a worker
- * thread on the context's device.  A request is admitted when a slot is free
- * and its field plus curves fit in the arena (first fit); its field is staged
- * in pinned memory, copied to the device on a copy stream, and computed as
- * soon as it has landed: all ready 2D requests (up to max_batch) in one
- * launch of the batched kernel, others (3D, more than 4096 levels) through the
- * single-field path on a second stream.  Requests that arrive while earlier
- * ones run are copied meanwhile and join the next launch.  Results go back to
- * pinned memory and then to the caller's host arrays, and the request's slot
- * and memory are released.
+ * host arena of the same size for staging and results and max_slots slots, and
+ * starts a worker thread on the context's device.  A request is admitted when a
+ * slot is free and its field plus curves fit in the arena (first fit); its field
+ * is staged in pinned memory during the submit, copied to the device on a copy
+ * stream, and computed as soon as it has landed:
+ * all ready 2D requests (up to max_batch) in one launch of the batched kernel,
+ * others (3D, more than 4096 levels) through the single-field path on a second
+ * stream.  Requests submitted while earlier ones run join the next launch.
+ * Results go back to pinned memory and then to the caller's host arrays, and
+ * the request's slot and memory are released.
  * ------------------------------------------------------------------------- */
 typedef struct ecc_server_s *ecc_server;
 

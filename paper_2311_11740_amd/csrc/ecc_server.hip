@@ -1,26 +1,28 @@
 // Serving loop: continuous batching of EC-curve requests.
 //
-// Memory.  At creation the server takes one device arena of the HBM budget and
-// a pinned host arena of the same size, and a fixed number of slots (each
-// with a per-level histogram and ticket for the batched kernel).  A request
-// is admitted when a slot is free and both arenas have room for its field and
-// curves (first fit); otherwise the submit returns ECC_ERR_BUSY.  An admitted
-// request keeps its device copy of the field and its curves resident until
-// its results are back on the host, then releases them.
+// Memory.  At creation the server takes one device arena of the HBM budget, a
+// pinned host arena of the same layout for staging and results, and a fixed number of
+// slots (each with a per-level histogram and ticket for the batched kernel).
+// A request is admitted when a slot is free and the arena has room for its
+// field and curves (first fit); otherwise the submit returns ECC_ERR_BUSY.
+// An admitted request keeps its device copy of the field and its curves
+// resident until its results are back on the host, then releases them.
 //
-// Work.  A worker thread advances every request through
-//   staged (field in pinned memory) -> copying (H2D on the copy stream)
-//   -> ready -> running (on a compute stream) -> complete (curves copied to
-//   the caller's host arrays),
-// and whenever requests are ready it launches them at once: the 2D requests
+// Work.  The submitting thread stages the field in its pinned range (large
+// fields with several copy threads).  A worker thread copies staged fields to
+// the device on a copy stream and launches every request whose copy has
+// landed, all at once: the 2D requests
 // the batched kernel takes go into one launch of that kernel (as many as are
 // ready, up to max_batch), the others (3D, more than 4096 levels) run the
-// single-field path on a second compute stream.  Requests that arrive while
-// earlier ones are on the GPU are copied in meanwhile and join the next
-// launch, so copies and kernels of different requests overlap.
+// single-field path on a second compute stream; results come back to pinned
+// memory and then to the caller's arrays.  Requests submitted while earlier
+// ones are on the GPU are copied meanwhile and join the next launch, so
+// copies and kernels of different requests overlap.  The worker holds the
+// server's lock only to take new requests and to retire finished ones.
 #include <hip/hip_runtime.h>
 
 #include <chrono>
+#include <atomic>
 #include <condition_variable>
 #include <cstring>
 #include <deque>
@@ -74,6 +76,81 @@ class Arena {
     std::map<size_t, size_t> free_;
 };
 
+// Host copies split over a few persistent threads (a single thread's memcpy
+// is what limits how fast large requests can be staged).
+class Copier {
+  public:
+    Copier() {
+        for (int i = 0; i < kThreads; ++i) th_.emplace_back([this] { loop(); });
+    }
+    ~Copier() {
+        {
+            std::lock_guard<std::mutex> lk(m_);
+            stop_ = true;
+        }
+        cv_.notify_all();
+        for (auto &t : th_) t.join();
+    }
+    // copy n bytes; returns when every byte is copied
+    void copy(char *dst, const char *src, size_t n) {
+        const size_t parts = std::min<size_t>(kThreads + 1, std::max<size_t>(1, n / kChunk));
+        if (parts <= 1) {
+            std::memcpy(dst, src, n);
+            return;
+        }
+        Call call;
+        call.left = (int)parts - 1;
+        const size_t step = (n / parts + 4095) & ~size_t(4095);
+        {
+            std::lock_guard<std::mutex> lk(m_);
+            for (size_t k = 1; k < parts; ++k) {
+                const size_t a = std::min(n, k * step), b = std::min(n, (k + 1) * step);
+                if (k + 1 == parts) q_.push_back({dst + a, src + a, n - a, &call});
+                else q_.push_back({dst + a, src + a, b - a, &call});
+            }
+        }
+        cv_.notify_all();
+        std::memcpy(dst, src, std::min(n, step));  // this thread takes the first part
+        std::unique_lock<std::mutex> lk(call.m);
+        call.cv.wait(lk, [&call] { return call.left == 0; });
+    }
+
+  private:
+    static constexpr int kThreads = 7;
+    static constexpr size_t kChunk = size_t(1) << 20;
+    struct Call {
+        std::mutex m;
+        std::condition_variable cv;
+        int left = 0;
+    };
+    struct Job {
+        char *dst;
+        const char *src;
+        size_t n;
+        Call *call;
+    };
+    void loop() {
+        for (;;) {
+            Job j;
+            {
+                std::unique_lock<std::mutex> lk(m_);
+                cv_.wait(lk, [this] { return stop_ || !q_.empty(); });
+                if (q_.empty()) return;
+                j = q_.front();
+                q_.pop_front();
+            }
+            std::memcpy(j.dst, j.src, j.n);
+            std::lock_guard<std::mutex> lk(j.call->m);
+            if (--j.call->left == 0) j.call->cv.notify_all();
+        }
+    }
+    std::vector<std::thread> th_;
+    std::mutex m_;
+    std::condition_variable cv_;
+    std::deque<Job> q_;
+    bool stop_ = false;
+};
+
 enum ReqState { kReserving, kStaged, kCopying, kReady, kRunning, kComplete, kFailed };
 
 struct Request {
@@ -85,7 +162,7 @@ struct Request {
     int nch = 0;
     size_t field_bytes = 0, total_bytes = 0, off = 0;
     int slot = -1;
-    ReqState state = kReserving;
+    std::atomic<int> state{kReserving};  // written by the worker, read by poll
     ecc_status err = ECC_OK;
     hipEvent_t ev_h2d = nullptr;
     int launch = -1;  // index of the completion event in the server's ring
@@ -121,6 +198,7 @@ struct ecc_server_s {
     std::vector<Launch> ring;
     std::unordered_map<uint64_t, Request *> reqs;
     std::deque<Request *> staged, copying, ready;
+    Copier copier;
     std::vector<Request *> running;
     uint64_t next_ticket = 1;
     int64_t inflight = 0;
@@ -145,17 +223,20 @@ ecc_status grow_pair(void **d, void **h, size_t *cap, size_t need) {
     return ECC_OK;
 }
 
-void finish(ecc_server srv, Request *r, ecc_status err) {
-    if (err == ECC_OK) {
-        const char *res = srv->h_arena + r->off + Arena::round(r->field_bytes);
-        int64_t *dst[4] = {r->host_out.ec, r->host_out.perimeter, r->host_out.area, r->host_out.volume};
-        int k = 0;
-        for (int c = 0; c < 4; ++c)
-            if (dst[c]) {
-                std::memcpy(dst[c], res + (size_t)k * r->fi.L * 8, (size_t)r->fi.L * 8);
-                ++k;
-            }
-    }
+// a finished request's curves, from its pinned slot into the caller's arrays
+void copy_results(ecc_server srv, Request *r) {
+    const char *res = srv->h_arena + r->off + Arena::round(r->field_bytes);
+    int64_t *dst[4] = {r->host_out.ec, r->host_out.perimeter, r->host_out.area, r->host_out.volume};
+    int k = 0;
+    for (int c = 0; c < 4; ++c)
+        if (dst[c]) {
+            std::memcpy(dst[c], res + (size_t)k * r->fi.L * 8, (size_t)r->fi.L * 8);
+            ++k;
+        }
+}
+
+// release a request's memory and slot and report it done; srv->mu held
+void retire(ecc_server srv, Request *r, ecc_status err) {
     srv->dev.release(r->off, r->total_bytes);
     srv->free_slots.push_back(r->slot);
     if (r->ev_h2d) hipEventDestroy(r->ev_h2d);
@@ -195,8 +276,10 @@ int free_launch(ecc_server srv) {
     return -1;
 }
 
-// launch every ready request; called with srv->mu held
-ecc_status launch_ready(ecc_server srv) {
+// Launch every ready request (worker thread, without srv->mu: the ready,
+// running and launch lists belong to the worker).  Requests that fail to
+// launch go to `failed`.
+ecc_status launch_ready(ecc_server srv, std::vector<std::pair<Request *, ecc_status>> &failed) {
     ecc_context ctx = srv->ctx;
     std::vector<Request *> batch2d, other;
     const int li = free_launch(srv);
@@ -303,8 +386,7 @@ ecc_status launch_ready(ecc_server srv) {
                 r->launch = li;
                 srv->running.push_back(r);
             } else {
-                finish(srv, r, s);
-                srv->cv_done.notify_all();
+                failed.push_back({r, s});
             }
         }
         if (s == ECC_OK) L.busy = true;
@@ -330,29 +412,31 @@ ecc_status launch_ready(ecc_server srv) {
             r->launch = -1;
             srv->running.push_back(r);
         } else {
-            finish(srv, r, so);
-            srv->cv_done.notify_all();
+            failed.push_back({r, so});
         }
     }
     return ECC_OK;
 }
 
-// one pass over all requests; returns whether anything changed
+// One pass over all requests (worker thread); returns whether anything
+// changed.  srv->mu is taken only to take new requests and to retire
+// finished ones, so submit and poll never wait for the GPU calls.
 bool advance(ecc_server srv) {
     bool moved = false;
+    std::deque<Request *> fresh;
+    std::vector<std::pair<Request *, ecc_status>> done;
+    {
+        std::lock_guard<std::mutex> lk(srv->mu);
+        fresh.swap(srv->staged);
+    }
     // copies of staged requests
-    while (!srv->staged.empty()) {
-        Request *r = srv->staged.front();
-        srv->staged.pop_front();
-        ecc_status s = ECC_OK;
+    for (Request *r : fresh) {
         int e = (int)hipEventCreateWithFlags(&r->ev_h2d, hipEventDisableTiming);
         if (!e) e = (int)hipMemcpyAsync(srv->d_arena + r->off, srv->h_arena + r->off, r->field_bytes,
                                         hipMemcpyHostToDevice, srv->s_copy);
         if (!e) e = (int)hipEventRecord(r->ev_h2d, srv->s_copy);
-        if (e) s = hip_fail(e, "serving copy");
-        if (s != ECC_OK) {
-            finish(srv, r, s);
-            srv->cv_done.notify_all();
+        if (e) {
+            done.push_back({r, hip_fail(e, "serving copy")});
         } else {
             r->state = kCopying;
             srv->copying.push_back(r);
@@ -372,18 +456,19 @@ bool advance(ecc_server srv) {
     }
     if (!srv->ready.empty()) {
         const size_t before = srv->ready.size();
-        launch_ready(srv);
+        launch_ready(srv, done);
         moved |= srv->ready.size() != before;
     }
-    // finished launches
+    // finished launches: results to the callers' arrays
     std::vector<bool> ring_done(srv->ring.size(), false);
     for (size_t i = 0; i < srv->ring.size(); ++i)
         ring_done[i] = srv->ring[i].busy && hipEventQuery(srv->ring[i].done) == hipSuccess;
     for (auto it = srv->running.begin(); it != srv->running.end();) {
         Request *r = *it;
-        const bool done = r->launch >= 0 ? ring_done[r->launch] : hipEventQuery(r->ev_h2d) == hipSuccess;
-        if (done) {
-            finish(srv, r, ECC_OK);
+        const bool fin = r->launch >= 0 ? ring_done[r->launch] : hipEventQuery(r->ev_h2d) == hipSuccess;
+        if (fin) {
+            copy_results(srv, r);
+            done.push_back({r, ECC_OK});
             it = srv->running.erase(it);
             moved = true;
         } else {
@@ -392,18 +477,22 @@ bool advance(ecc_server srv) {
     }
     for (size_t i = 0; i < srv->ring.size(); ++i)
         if (ring_done[i]) srv->ring[i].busy = false;
-    if (moved) srv->cv_done.notify_all();
+    if (!done.empty()) {
+        std::lock_guard<std::mutex> lk(srv->mu);
+        for (auto &d : done) retire(srv, d.first, d.second);
+        srv->cv_done.notify_all();
+    }
     return moved;
 }
 
 void worker_main(ecc_server srv) {
     hipSetDevice(srv->ctx->device);
-    std::unique_lock<std::mutex> lk(srv->mu);
     for (;;) {
         const bool moved = advance(srv);
         const bool busy = !srv->copying.empty() || !srv->ready.empty() || !srv->running.empty();
+        std::unique_lock<std::mutex> lk(srv->mu);
         if (srv->stop && !busy && srv->staged.empty()) break;
-        if (!moved) {
+        if (!moved && srv->staged.empty()) {
             if (busy)  // GPU work in flight: check again shortly
                 srv->cv_work.wait_for(lk, std::chrono::microseconds(20));
             else
@@ -482,6 +571,14 @@ extern "C" ecc_status ecc_server_create(ecc_context ctx, const ecc_server_config
         e = (int)hipEventCreateWithFlags(&L.done, hipEventDisableTiming);
         if (e) return bail(hip_fail(e, "hipEventCreate"));
     }
+    {
+        // the single-field path's workspace, grown now for up to 4096 levels,
+        // so that a request does not wait for the device to grow it later
+        std::lock_guard<std::mutex> lk(ctx->mu);
+        ecc_status s = grow(ctx, ctx->ws.partial, (size_t)4 * 4096 * 4 * ctx->n_cu * sizeof(int32_t), "partials");
+        if (s == ECC_OK) s = grow(ctx, ctx->ws.totals, (size_t)4 * 4096 * sizeof(int64_t), "totals");
+        if (s != ECC_OK) return bail(s);
+    }
     for (int i = cfg->max_slots - 1; i >= 0; --i) srv->free_slots.push_back(i);
     srv->worker = std::thread(worker_main, srv);
     *out = srv;
@@ -531,8 +628,9 @@ extern "C" ecc_status ecc_server_submit(ecc_server srv, const ecc_field *field, 
         srv->reqs[r->ticket] = r;
         ++srv->inflight;
     }
-    // stage the field in pinned memory outside the lock (the range is ours)
-    std::memcpy(srv->h_arena + r->off, field->data, r->field_bytes);
+    // stage the field in its pinned range outside the lock (the range is ours);
+    // large fields are copied by several threads
+    srv->copier.copy(srv->h_arena + r->off, static_cast<const char *>(field->data), r->field_bytes);
     {
         std::lock_guard<std::mutex> lk(srv->mu);
         r->state = kStaged;
