@@ -143,7 +143,6 @@ constexpr int kZmTY = 4, kZmStripX = 256, kZmCellsPerUnit = kZmStripX * kZmTY;
 int zmarch_3d_columns(int64_t h, int64_t w);
 // whether one z-plane per wave keeps the workgroup bins within kFlush3D
 bool zmarch_3d_fits(int64_t h, int64_t w, int grid);
-size_t lds_bytes_2d(int window, int L);
 size_t lds_bytes_3d(int window, bool want_crease);
 
 }  // namespace ecc

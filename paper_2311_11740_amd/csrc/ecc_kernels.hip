@@ -440,16 +440,14 @@ __device__ __forceinline__ void drain_2d(const uint64_t *hist, int W, int lo, in
     }
 }
 
-// The deltas of the VEC cells of `mid` into the LDS bins.
-// SINGLE (one pass over all levels): the bin of a cell is lam' itself
-// (hist[1..W] are the levels, hist[W+1] collects cells that never enter);
-// the halo lanes mask their bins to hist[0], which holds nothing else.
-// Otherwise bins are lam' - 1 for cells inside the window, and cells outside
-// it (and the halo lanes' cells) go to a per-lane scratch bin W + lane, so
-// that masses of out-of-window cells do not pile onto one LDS address.
-template <int VEC, bool SINGLE>
+// The deltas of the VEC cells of `mid` into the LDS bins: the bin of a cell
+// is lam' itself (hist[1..W] are the levels of the pass window).  Cells
+// outside the window (lam' = 0 or W + 1, among them every cell outside the
+// field) and the halo lanes' cells (masked to 0) add nothing, so their lanes
+// skip the atomic: masses of such cells would otherwise all hit one address.
+template <int VEC>
 __device__ __forceinline__ void emit_row(const uint32_t (&up)[VEC + 1], const uint32_t (&mid)[VEC + 1],
-                                         const uint32_t (&dn)[VEC + 1], uint32_t mask_or_off, uint32_t scratch,
+                                         const uint32_t (&dn)[VEC + 1], uint32_t halo_mask, uint32_t W,
                                          const uint64_t *dl, uint64_t *hist) {
     // groups of up to 4 cell pairs: all table reads of a group are issued
     // before its atomics, so the atomics wait for one LDS round trip, not one each
@@ -466,29 +464,25 @@ __device__ __forceinline__ void emit_row(const uint32_t (&up)[VEC + 1], const ui
                                                 pk_diff(up[j + 1], self1), pk_diff(mid[j - 1], self1),
                                                 pk_diff(mid[j + 1], self), pk_diff(dn[j - 1], self),
                                                 pk_diff(dn[j], self), pk_diff(dn[j + 1], self));
-            if constexpr (SINGLE) {
-                const uint32_t sm = self & mask_or_off;  // 0 for the halo lanes
-                bin[2 * q] = sm & 0xFFFFu;
-                bin[2 * q + 1] = sm >> 16;
-            } else {
-                bin[2 * q] = min((self & 0xFFFFu) + mask_or_off, scratch);
-                bin[2 * q + 1] = min((self >> 16) + mask_or_off, scratch);
-            }
+            const uint32_t sm = self & halo_mask;  // 0 for the halo lanes
+            bin[2 * q] = sm & 0xFFFFu;
+            bin[2 * q + 1] = sm >> 16;
             dv[2 * q] = dl[acc & 0xFFu];
             dv[2 * q + 1] = dl[(acc >> 16) & 0xFFu];
         }
 #pragma unroll
-        for (int q = 0; q < 2 * GP; ++q) atomicAdd((unsigned long long *)&hist[bin[q]], (unsigned long long)dv[q]);
+        for (int q = 0; q < 2 * GP; ++q)
+            if (bin[q] - 1u < W) atomicAdd((unsigned long long *)&hist[bin[q]], (unsigned long long)dv[q]);
     }
 }
 
 // rows [ra, rb) of one strip; three row buffers whose roles rotate with the
 // row index (PF is a multiple of 3, so the unrolled loop needs no copies)
-template <typename T, int LM, int AL, int PF, bool SINGLE, typename TH>
+template <typename T, int LM, int AL, int PF, typename TH>
 __device__ __forceinline__ void stream_run_2d(const T *__restrict__ data, int h, int64_t w,
                                               const LevelArgs &lv, const TH &thr, int32_t lo, int W,
                                               float cpass, const uint64_t *dl, uint64_t *hist, int64_t strip,
-                                              int ra, int rb, int lane, uint32_t mask_or_off, uint32_t scratch) {
+                                              int ra, int rb, int lane, uint32_t halo_mask) {
     static_assert(PF % 3 == 0, "PF must be a multiple of 3");
     constexpr int VEC = Elem<T>::VEC;
     constexpr int CE = 62 * VEC;  // cells owned per strip
@@ -523,7 +517,7 @@ __device__ __forceinline__ void stream_run_2d(const T *__restrict__ data, int h,
             convert_row<T, LM>(ring[k], r + 1 < h, full, lv, thr, lo, W, cpass, R[(k + 1) % 3]);
             const int nx = r + 1 + PF < rb ? r + 1 + PF : rb;
             fetch_row<T, AL>(data, clamp_row(nx), w, x0, last_block, ring[k]);
-            emit_row<VEC, SINGLE>(R[(k + 2) % 3], R[k % 3], R[(k + 1) % 3], mask_or_off, scratch, dl, hist);
+            emit_row<VEC>(R[(k + 2) % 3], R[k % 3], R[(k + 1) % 3], halo_mask, (uint32_t)W, dl, hist);
         }
     }
     // remaining rows (fewer than PF); here r - ra = r0 - ra + k with r0 - ra
@@ -533,7 +527,7 @@ __device__ __forceinline__ void stream_run_2d(const T *__restrict__ data, int h,
         const int r = r0 + k;
         if (r < rb) {
             convert_row<T, LM>(ring[k], r + 1 < h, full, lv, thr, lo, W, cpass, R[(k + 1) % 3]);
-            emit_row<VEC, SINGLE>(R[(k + 2) % 3], R[k % 3], R[(k + 1) % 3], mask_or_off, scratch, dl, hist);
+            emit_row<VEC>(R[(k + 2) % 3], R[k % 3], R[(k + 1) % 3], halo_mask, (uint32_t)W, dl, hist);
         }
     }
 }
@@ -541,7 +535,7 @@ __device__ __forceinline__ void stream_run_2d(const T *__restrict__ data, int h,
 // Work split: the (strip, row) units of rows [row_lo, row_hi), strip-major,
 // are divided into equal contiguous ranges, one per wave (a range may run from
 // the end of one strip into the next).
-template <typename T, int LM, int AL, int PF, bool SINGLE>
+template <typename T, int LM, int AL, int PF>
 __global__ void __launch_bounds__(256)
     ecc2d_stream(const T *__restrict__ data, int64_t h, int64_t w, LevelArgs lv, int32_t lo,
                  int32_t hi, float cpass, const uint64_t *__restrict__ delta_lut, int32_t *__restrict__ partial,
@@ -555,8 +549,8 @@ __global__ void __launch_bounds__(256)
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform: keeps loop control scalar
     const int W = hi - lo;
     const int L = lv.L;
-    // LDS: bins (W + 2 with SINGLE, else W + 64), then thresholds [lo-2, hi+1)
-    const int n_bins = SINGLE ? W + 2 : W + 64;
+    // LDS: bins 0..W+1 (1..W are the window's levels), then thresholds [lo-2, hi+1)
+    const int n_bins = W + 2;
     uint64_t *hist = smem;
     float *thr_s = reinterpret_cast<float *>(smem + n_bins);
     constexpr bool kThr = LM == LM_AFFINE || LM == LM_SEARCH;
@@ -578,19 +572,17 @@ __global__ void __launch_bounds__(256)
     const int64_t units = n_strips * H;
     const int64_t u_end = units * (gw + 1) / NW;
     const bool halo_lane = lane == 0 || lane == 63;
-    const uint32_t mask_or_off = SINGLE ? (halo_lane ? 0u : 0xFFFFFFFFu) : (halo_lane ? 0x7FFFFFFEu : 0xFFFFFFFFu);
-    const uint32_t scratch = (uint32_t)(W + lane);
+    const uint32_t halo_mask = halo_lane ? 0u : 0xFFFFFFFFu;
     const ThrLds thr{thr_s, lo - 2};
     for (int64_t u = units * gw / NW; u < u_end;) {
         const int64_t strip = u / H, ra = u % H;
         const int64_t rb = ra + (u_end - u) < H ? ra + (u_end - u) : H;
-        stream_run_2d<T, LM, AL, PF, SINGLE>(data, (int)h, w, lv, thr, lo, W, cpass, dl, hist, strip,
-                                                  (int)(row_lo + ra), (int)(row_lo + rb), lane, mask_or_off,
-                                                  scratch);
+        stream_run_2d<T, LM, AL, PF>(data, (int)h, w, lv, thr, lo, W, cpass, dl, hist, strip, (int)(row_lo + ra),
+                                     (int)(row_lo + rb), lane, halo_mask);
         u += rb - ra;
     }
     __syncthreads();
-    drain_2d(hist + (SINGLE ? 1 : 0), W, lo, L, G, wg, partial, accumulate == 0);
+    drain_2d(hist + 1, W, lo, L, G, wg, partial, accumulate == 0);
 }
 
 // ---------------------------------------------------------------------------
@@ -619,7 +611,7 @@ __global__ void __launch_bounds__(256)
     dl[1][tid] = luts[256 + tid];
     const int i_beg = wg_first[blockIdx.x], i_end = wg_first[blockIdx.x + 1];
     const bool halo_lane = lane == 0 || lane == 63;
-    const uint32_t mask_or_off = halo_lane ? 0u : 0xFFFFFFFFu;
+    const uint32_t halo_mask = halo_lane ? 0u : 0xFFFFFFFFu;
     for (int it = i_beg; it < i_end; ++it) {
         const BatchItem item = items[it];
         const BatchField2D &f = fields[item.field];
@@ -651,9 +643,8 @@ __global__ void __launch_bounds__(256)
         for (int u = item.u0 + (int)((int64_t)n * wave / kWavesPerWG); u < u_end;) {
             const int strip = u / h, ra = u % h;
             const int rb = ra + (u_end - u) < h ? ra + (u_end - u) : h;
-            stream_run_2d<T, LM, kLoadVector, PF, true>((const T *)f.data, h, w, lv, thr, 0, L, f.cpass,
-                                                        dl[f.conn_idx], hist, strip, ra, rb, lane, mask_or_off,
-                                                        (uint32_t)(L + lane));
+            stream_run_2d<T, LM, kLoadVector, PF>((const T *)f.data, h, w, lv, thr, 0, L, f.cpass, dl[f.conn_idx],
+                                                  hist, strip, ra, rb, lane, halo_mask);
             u += rb - ra;
         }
         __syncthreads();
@@ -970,7 +961,7 @@ __device__ __forceinline__ uint32_t pk_merge(uint32_t a, uint32_t b) {
 //   tm[p]: 2D EC delta of an image pixel with pattern p, sign included
 // A voxel's low word is tl[p_layer] + (its share of the two images' deltas)
 // - 2 * (vertical neighbours that entered before it) << 22.
-template <typename T, int LM, int AL, bool MAXIMG, bool SINGLE, int TY, typename TH>
+template <typename T, int LM, int AL, bool MAXIMG, int TY, typename TH>
 struct March3D {
     static constexpr int VEC = Elem3<T>::VEC;
     static constexpr int NR = TY + 2;
@@ -986,8 +977,8 @@ struct March3D {
     uint64_t *hist;
     int64_t xs, x0;
     int y0, zb, lane;
-    uint32_t scratch;
     int64_t last_block;
+    uint32_t scratch;  // this lane's scratch bin, W + 2 + lane
 
     uint32_t R[3][NR][VEC + 1];  // level planes; R[(z - za + 1) % 3] holds plane z
     int32_t E[TY][VEC];          // image delta of the pixel below each voxel of the current plane
@@ -1085,14 +1076,12 @@ struct March3D {
                 E[t][j - 1] = en[2 * q];
                 E[t][j] = en[2 * q + 1];
                 const uint32_t self = selfv[q];
-                uint32_t b0, b1;
-                if constexpr (SINGLE) {
-                    b0 = self & 0xFFFFu;
-                    b1 = self >> 16;
-                } else {
-                    b0 = min((self & 0xFFFFu) - 1u, scratch);
-                    b1 = min((self >> 16) - 1u, scratch);
-                }
+                // bins lam' (1..W); a voxel outside the window or the field goes
+                // to its lane's own scratch bin (never drained) rather than
+                // branching: one address per lane keeps such voxels apart
+                uint32_t b0 = self & 0xFFFFu, b1 = self >> 16;
+                b0 = b0 - 1u < (uint32_t)W ? b0 : scratch;
+                b1 = b1 - 1u < (uint32_t)W ? b1 : scratch;
                 constexpr uint64_t cnt = 1ull << kShiftCnt3;
                 atomicAdd((unsigned long long *)&hist[b0], (unsigned long long)(cnt | lo0));
                 atomicAdd((unsigned long long *)&hist[b1], (unsigned long long)(cnt | lo1));
@@ -1115,7 +1104,7 @@ struct March3D {
 
 // Work split: units (column, z) with column = (strip, block of TY rows), z
 // fastest, in equal contiguous ranges per wave.
-template <typename T, int LM, int AL, bool MAXIMG, bool SINGLE, int TY>
+template <typename T, int LM, int AL, bool MAXIMG, int TY>
 __global__ void __launch_bounds__(256)
     ecc3d_stream(const T *__restrict__ data, int64_t d, int64_t h, int64_t w, LevelArgs lv, int32_t lo,
                  int32_t hi, float cpass, const uint32_t *__restrict__ tables, int32_t *__restrict__ partial,
@@ -1128,7 +1117,7 @@ __global__ void __launch_bounds__(256)
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int W = hi - lo;
     const int L = lv.L;
-    const int n_bins = SINGLE ? W + 2 : W + 64;
+    const int n_bins = W + 2 + 64;  // 1..W are the window's levels, then a scratch bin per lane
     uint64_t *hist = smem;
     float *thr_s = reinterpret_cast<float *>(smem + n_bins);
     constexpr bool kThr = LM == LM_AFFINE || LM == LM_SEARCH;
@@ -1151,21 +1140,21 @@ __global__ void __launch_bounds__(256)
     const int64_t n_yb = (h + TY - 1) / TY;
     const int64_t units = n_strips * n_yb * D;
     const int64_t u_end = units * (gw + 1) / NW;
-    const uint32_t scratch = (uint32_t)(W + lane);
     const ThrLds thr{thr_s, lo - 2};
     for (int64_t u = units * gw / NW; u < u_end;) {
         const int64_t col = u / D, za = u % D;
         const int64_t zb = za + (u_end - u) < D ? za + (u_end - u) : D;
         const int64_t strip = col % n_strips, yb = col / n_strips;
         const int64_t xs = strip * 64 * VEC;
-        March3D<T, LM, AL, MAXIMG, SINGLE, TY, ThrLds> m{data, (int)d, h, w, lv, thr, lo, W, cpass, tl, tm,
-                                                          hist, xs, xs + (int64_t)lane * VEC, (int)(yb * TY),
-                                                          (int)(z_lo + zb), lane, scratch, d * h * w > VEC ? d * h * w - VEC : 0};
+        March3D<T, LM, AL, MAXIMG, TY, ThrLds> m{data, (int)d, h, w, lv, thr, lo, W, cpass, tl, tm,
+                                                  hist, xs, xs + (int64_t)lane * VEC, (int)(yb * TY),
+                                                  (int)(z_lo + zb), lane, d * h * w > VEC ? d * h * w - VEC : 0,
+                                                  (uint32_t)(W + 2 + lane)};
         m.run((int)(z_lo + za));
         u += zb - za;
     }
     __syncthreads();
-    drain_3d(hist + (SINGLE ? 1 : 0), nullptr, false, W, lo, L, G, wg, partial, accumulate == 0);
+    drain_3d(hist + 1, nullptr, false, W, lo, L, G, wg, partial, accumulate == 0);
 }
 
 
@@ -1391,10 +1380,6 @@ __global__ void ecc_level_lut(const float *__restrict__ thr, int L, int n_values
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
-size_t lds_bytes_2d(int window, int L) {
-    (void)L;
-    return (size_t)(window + 64) * 8 + (size_t)(window + 3) * 4 + 2048;
-}
 size_t lds_bytes_3d(int window, bool want_crease) { return (size_t)window * (want_crease ? 12 : 8); }
 
 int load_mode_2d(const void *data, int64_t h, int64_t w, int elem_bytes) {
@@ -1410,7 +1395,7 @@ static int64_t max_wg_cells_2d(int64_t rows, int64_t w, int vec, int grid) {
     return kWavesPerWG * ((units + NW - 1) / NW + 1) * ce;
 }
 
-template <typename T, int LM, int AL, bool SINGLE>
+template <typename T, int LM, int AL>
 static int launch_2d_t(const Launch2D &a, hipStream_t s) {
     constexpr int VEC = Elem<T>::VEC, PF = sizeof(T) == 1 ? 3 : 6;
     const int W = a.hi - a.lo;
@@ -1422,11 +1407,11 @@ static int launch_2d_t(const Launch2D &a, hipStream_t s) {
     if (max_wg_cells_2d(chunk, a.w, VEC, a.grid) > kFlush2D) return (int)hipErrorInvalidValue;
     // affine levels: the pass constant -t0/step + 1.5 - lo, rounded once
     const float cpass = (float)(a.lv.u0d + 1.5 - a.lo);
-    const size_t lds = (size_t)(SINGLE ? W + 2 : W + 64) * 8 + (size_t)(W + 3) * 4;
+    const size_t lds = (size_t)(W + 2) * 8 + (size_t)(W + 3) * 4;
     for (int64_t r0 = a.row_lo; r0 < a.row_hi; r0 += chunk) {
         const int64_t r1 = r0 + chunk < a.row_hi ? r0 + chunk : a.row_hi;
         const bool acc = a.accumulate || r0 > a.row_lo;
-        hipLaunchKernelGGL((ecc2d_stream<T, LM, AL, PF, SINGLE>), dim3(a.grid), dim3(256), lds, s,
+        hipLaunchKernelGGL((ecc2d_stream<T, LM, AL, PF>), dim3(a.grid), dim3(256), lds, s,
                            (const T *)a.data, a.h, a.w, a.lv, a.lo, a.hi, cpass, a.delta_lut, a.partial, r0, r1,
                            acc ? 1 : 0);
         const int e = (int)hipGetLastError();
@@ -1435,17 +1420,10 @@ static int launch_2d_t(const Launch2D &a, hipStream_t s) {
     return 0;
 }
 
-template <typename T, int LM, bool SINGLE>
-static int launch_2d_sg(const Launch2D &a, hipStream_t s) {
-    return load_mode_2d(a.data, a.h, a.w, (int)sizeof(T)) == kLoadAligned
-               ? launch_2d_t<T, LM, kLoadAligned, SINGLE>(a, s)
-               : launch_2d_t<T, LM, kLoadVector, SINGLE>(a, s);
-}
-
 template <typename T, int LM>
 static int launch_2d_al(const Launch2D &a, hipStream_t s) {
-    const bool single = a.lo == 0 && a.hi == a.lv.L;
-    return single ? launch_2d_sg<T, LM, true>(a, s) : launch_2d_sg<T, LM, false>(a, s);
+    return load_mode_2d(a.data, a.h, a.w, (int)sizeof(T)) == kLoadAligned ? launch_2d_t<T, LM, kLoadAligned>(a, s)
+                                                                          : launch_2d_t<T, LM, kLoadVector>(a, s);
 }
 
 template <typename T>
@@ -1496,7 +1474,7 @@ bool zmarch_3d_fits(int64_t h, int64_t w, int grid) {
     return max_wg_cells_3d(zmarch_3d_columns(h, w), 1, grid) <= kFlush3D;
 }
 
-template <typename T, int LM, int AL, bool MAXIMG, bool SINGLE>
+template <typename T, int LM, int AL, bool MAXIMG>
 static int launch_zm_t(const Launch3D &a, hipStream_t s) {
     constexpr bool kThr = LM == LM_AFFINE || LM == LM_SEARCH;
     const int W = a.hi - a.lo;
@@ -1506,11 +1484,11 @@ static int launch_zm_t(const Launch3D &a, hipStream_t s) {
     while (chunk > 1 && max_wg_cells_3d(cols, chunk, a.grid) > kFlush3D) chunk = (chunk + 1) / 2;
     if (max_wg_cells_3d(cols, chunk, a.grid) > kFlush3D) return (int)hipErrorInvalidValue;
     const float cpass = (float)(a.lv.u0d + 1.5 - a.lo);
-    const size_t lds = (size_t)(SINGLE ? W + 2 : W + 64) * 8 + (kThr ? (size_t)(W + 3) * 4 : 0);
+    const size_t lds = (size_t)(W + 2 + 64) * 8 + (kThr ? (size_t)(W + 3) * 4 : 0);
     for (int64_t z0 = 0; z0 < a.d; z0 += chunk) {
         const int64_t z1 = z0 + chunk < a.d ? z0 + chunk : a.d;
         const bool acc = z0 > 0;
-        hipLaunchKernelGGL((ecc3d_stream<T, LM, AL, MAXIMG, SINGLE, kZmTY>), dim3(a.grid), dim3(256), lds, s,
+        hipLaunchKernelGGL((ecc3d_stream<T, LM, AL, MAXIMG, kZmTY>), dim3(a.grid), dim3(256), lds, s,
                            (const T *)a.data, a.d, a.h, a.w, a.lv, a.lo, a.hi, cpass, a.zm_tables, a.partial, z0,
                            z1, acc ? 1 : 0);
         const int e = (int)hipGetLastError();
@@ -1519,20 +1497,14 @@ static int launch_zm_t(const Launch3D &a, hipStream_t s) {
     return 0;
 }
 
-template <typename T, int LM, bool MAXIMG, bool SINGLE>
-static int launch_zm_sg(const Launch3D &a, hipStream_t s) {
-    constexpr int VEC = Elem3<T>::VEC, VB = VEC * (int)sizeof(T);
-    (void)VEC;
-    if ((uintptr_t)a.data % VB == 0 && (a.w * (int64_t)sizeof(T)) % VB == 0)
-        return launch_zm_t<T, LM, kLoadAligned, MAXIMG, SINGLE>(a, s);
-    return launch_zm_t<T, LM, kLoadVector, MAXIMG, SINGLE>(a, s);
-}
-
 template <typename T, int LM, bool MAXIMG>
 static int launch_zm_al(const Launch3D &a, hipStream_t s) {
-    const bool single = a.lo == 0 && a.hi == a.lv.L;
-    return single ? launch_zm_sg<T, LM, MAXIMG, true>(a, s) : launch_zm_sg<T, LM, MAXIMG, false>(a, s);
+    constexpr int VB = Elem3<T>::VEC * (int)sizeof(T);
+    if ((uintptr_t)a.data % VB == 0 && (a.w * (int64_t)sizeof(T)) % VB == 0)
+        return launch_zm_t<T, LM, kLoadAligned, MAXIMG>(a, s);
+    return launch_zm_t<T, LM, kLoadVector, MAXIMG>(a, s);
 }
+
 
 template <typename T, int LM>
 static int launch_3d_cr(const Launch3D &a, hipStream_t s) {
