@@ -110,7 +110,7 @@ struct BatchField2D {
     const float *thr;     // LM_AFFINE / LM_SEARCH thresholds (device)
     const uint16_t *lut;  // LM_LUT level table (device)
     int32_t L, n_items, conn_idx, pad0;  // conn_idx 0 = 8-C, 1 = 4-C
-    float inv_step, cpass, eps, pad1;    // LM_AFFINE (cpass of the single pass)
+    float inv_step, cpass, eps, pad1;    // LM_AFFINE (cpass of the pass over all L <= 4096 levels)
 };
 // A work item: (strip, row) units [u0, u1) of one field, strip-major.
 struct BatchItem {
