@@ -75,31 +75,38 @@ def channels_for(spec):
 
 
 def time_field(ctx, spec, steps: int, warmup: int, copies: int):
+    """Whole-call time per step (no profiling events in the stream), then the
+    field-reading kernel's own time per launch from HIP events around it."""
     import torch
     dev0 = torch.from_numpy(spec.data).cuda()
     bufs = [dev0] + [dev0.clone() for _ in range(copies - 1)]
     ch = channels_for(spec)
     out = {c: torch.empty(spec.n_levels, dtype=torch.int64, device="cuda") for c in ch}
     thr = spec.thresholds
-    for i in range(warmup):
-        ctx.compute(bufs[i % copies], spec.n_levels, thresholds=thr, connectivity=spec.connectivity,
-                    out=out)
-    torch.cuda.synchronize()
-    ctx.profile(True)
-    ctx.profile_read(reset=True)
     stream = torch.cuda.current_stream()
+
+    def run(i):
+        ctx.compute(bufs[i % copies], spec.n_levels, thresholds=thr, connectivity=spec.connectivity,
+                    out=out, stream=stream)
+
+    for i in range(warmup):
+        run(i)
     t0 = torch.cuda.Event(enable_timing=True)
     t1 = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     wall0 = time.perf_counter()
     t0.record(stream)
     for i in range(steps):
-        ctx.compute(bufs[i % copies], spec.n_levels, thresholds=thr, connectivity=spec.connectivity,
-                    out=out, stream=stream)
+        run(i)
     t1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - wall0
     total_ms = t0.elapsed_time(t1)
+    ctx.profile(True)
+    ctx.profile_read(reset=True)
+    for i in range(steps):
+        run(i)
+    torch.cuda.synchronize()
     k_ms, k_n = ctx.profile_read(reset=True)
     ctx.profile(False)
     res = {c: v.cpu().numpy() for c, v in out.items()}

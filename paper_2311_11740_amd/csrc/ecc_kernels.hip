@@ -1287,7 +1287,6 @@ struct OutPtrs {
 __global__ void __launch_bounds__(1024)
     ecc_merge(const int32_t *__restrict__ partial, int G, int nch, int L, OutPtrs out,
               int64_t *__restrict__ totals, unsigned *__restrict__ counter) {
-    __shared__ int64_t wsum[16];
     __shared__ bool last;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int waves = blockDim.x >> 6;
@@ -1320,41 +1319,54 @@ __global__ void __launch_bounds__(1024)
     __syncthreads();
     if (!last) return;
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    // running sums over levels, all channels at once (independent loads and
+    // shuffle chains overlap): each thread sums a chunk of levels, the chunk
+    // sums are scanned within waves by shuffles, then over the wave totals
     const int t = threadIdx.x, nt = blockDim.x;
     const int per = (L + nt - 1) / nt;
     const int beg = t * per, end = beg + per < L ? beg + per : L;
-    for (int ch = 0; ch < nch; ++ch) {
-        int64_t *dst = out.p[ch];
-        if (!dst) continue;  // uniform
-        const int64_t *src = totals + (int64_t)ch * L;
-        int64_t s = 0;
-        for (int i = beg; i < end; ++i) s += src[i];
-        // inclusive scan of the chunk sums: within each wave by shuffles,
-        // then over the wave totals
-        int64_t x = s;
+    int64_t sum[4] = {0, 0, 0, 0}, x[4];
 #pragma unroll
-        for (int off = 1; off < 64; off <<= 1) {
-            const int64_t y = __shfl_up(x, off);
-            if (lane >= off) x += y;
+    for (int ch = 0; ch < 4; ++ch)
+        if (ch < nch && out.p[ch])
+            for (int i = beg; i < end; ++i) sum[ch] += totals[(int64_t)ch * L + i];
+#pragma unroll
+    for (int ch = 0; ch < 4; ++ch) x[ch] = sum[ch];
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+#pragma unroll
+        for (int ch = 0; ch < 4; ++ch) {
+            const int64_t y = __shfl_up(x[ch], off);
+            if (lane >= off) x[ch] += y;
         }
-        if (lane == 63) wsum[wave] = x;
-        __syncthreads();
-        if (wave == 0) {
-            int64_t v = lane < waves ? wsum[lane] : 0;
+    }
+    __shared__ int64_t wtot[4][16];
+    if (lane == 63)
+#pragma unroll
+        for (int ch = 0; ch < 4; ++ch) wtot[ch][wave] = x[ch];
+    __syncthreads();
+    if (wave == 0) {
+#pragma unroll
+        for (int ch = 0; ch < 4; ++ch) {
+            int64_t v = lane < waves ? wtot[ch][lane] : 0;
 #pragma unroll
             for (int off = 1; off < 16; off <<= 1) {
                 const int64_t y = __shfl_up(v, off);
                 if (lane >= off) v += y;
             }
-            if (lane < waves) wsum[lane] = v;
+            if (lane < waves) wtot[ch][lane] = v;
         }
-        __syncthreads();
-        int64_t run = (wave > 0 ? wsum[wave - 1] : 0) + x - s;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int ch = 0; ch < 4; ++ch) {
+        int64_t *dst = ch < nch ? out.p[ch] : nullptr;
+        if (!dst) continue;  // uniform
+        int64_t run = (wave > 0 ? wtot[ch][wave - 1] : 0) + x[ch] - sum[ch];
         for (int i = beg; i < end; ++i) {
-            run += src[i];
+            run += totals[(int64_t)ch * L + i];
             dst[i] = run;
         }
-        __syncthreads();  // wsum is reused by the next channel
     }
     if (threadIdx.x == 0) *counter = 0u;  // ready for the next merge
 }
