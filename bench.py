@@ -232,6 +232,60 @@ def measure_batch(ctx, specs, steps, warmup):
         oracle_sample_fields=len(sample))
 
 
+# The paper's own synthetic workloads (white noise translated to 0..255, 8-C
+# in 2D and 26-C in 3D) and its 24-core CPU throughput for them (Computational
+# Results, Tables 3 and 4), as context for the same inputs here.
+PAPER_WORKLOADS = [
+    ("2d_1280x720_u8_uniform", (720, 1280), "uniform", 97.7, "Table 3"),
+    ("2d_1280x720_u8_normal", (720, 1280), "normal", 99.3, "Table 3"),
+    ("2d_1920x1080_u8_uniform", (1080, 1920), "uniform", 107.4, "Table 3"),
+    ("2d_1920x1080_u8_normal", (1080, 1920), "normal", 110.8, "Table 3"),
+    ("2d_2048x2048_u8_uniform", (2048, 2048), "uniform", 96.5, "Table 3"),
+    ("2d_2048x2048_u8_normal", (2048, 2048), "normal", 110.4, "Table 3"),
+    ("2d_4096x4096_u8_uniform", (4096, 4096), "uniform", 82.2, "Table 3"),
+    ("2d_4096x4096_u8_normal", (4096, 4096), "normal", 81.95, "Table 3"),
+    ("3d_128^3_u8_uniform", (128, 128, 128), "uniform", 26.67, "Table 4"),
+    ("3d_128^3_u8_normal", (128, 128, 128), "normal", 27.47, "Table 4"),
+    ("3d_256^3_u8_uniform", (256, 256, 256), "uniform", 27.90, "Table 4"),
+    ("3d_256^3_u8_normal", (256, 256, 256), "normal", 28.38, "Table 4"),
+]
+
+
+def measure_paper_workloads(ctx, steps):
+    """Per-call throughput on the paper's white-noise inputs (field resident in
+    HBM, all 256 levels, every output channel the paper computes: EC,
+    perimeter and area in 2D; EC, perimeter (crease), surface and volume in 3D,
+    and in 3D also without the crease measure), checked against the oracle."""
+    import torch
+    import oracle
+    from paper_2311_11740_amd import synth
+    rows = []
+    for k, (name, shape, kind, paper_mps, table) in enumerate(PAPER_WORKLOADS):
+        a = synth.white_noise(shape, 500 + k, 256, kind)
+        dev = torch.from_numpy(a).cuda()
+        conn = 8 if a.ndim == 2 else 26
+        variants = [None] if a.ndim == 2 else [None, ("ec", "area", "volume")]
+        row = dict(workload=name, cells=int(a.size), paper_cpu_24_cores_mcells_s=paper_mps, paper_source=table)
+        for ch in variants:
+            out = ctx.compute(dev, 256, connectivity=conn, channels=ch)
+
+            def call(stream, _ch=ch, _out=out):
+                ctx.compute(dev, 256, connectivity=conn, channels=_ch, out=_out, stream=stream)
+
+            for _ in range(3):
+                call(torch.cuda.current_stream())
+            ms, _ = timed_calls(call, steps)
+            got = {c: v.cpu().numpy() for c, v in out.items()}
+            ref = oracle.o2_curves(a, 256, connectivity=conn, channels=tuple(got),
+                                   n_threads=min(16, os.cpu_count() or 1))
+            ok = all(np.array_equal(got[c], ref[c]) for c in got)
+            key = "all_channels" if ch is None else "no_crease"
+            row[key] = dict(ms_per_call=round(ms, 4), gcells_s=round(a.size / ms / 1e6, 2),
+                            x_paper=round(a.size / ms / 1e3 / paper_mps, 1), parity_vs_oracle=bool(ok))
+        rows.append(row)
+    return rows
+
+
 def serve_trace(submit, poll, t_arr, ids, pool, warm):
     """Replay a Poisson trace: requests are offered at their arrival times,
     retried while the server is full, and polled until done.  Returns the
@@ -331,6 +385,8 @@ def main():
     ap.add_argument("--no-secondary", action="store_true", help="skip the 3D secondary measurement")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched vs per-field comparison")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving comparison")
+    ap.add_argument("--no-paper-workloads", action="store_true",
+                    help="skip the paper's white-noise workloads (context against its CPU timings)")
     ap.add_argument("--serving-requests", type=int, default=2000)
     ap.add_argument("--serving-rates", type=str, default="500,2000,4000,8000,16000",
                     help="Poisson arrival rates (requests/s), comma separated")
@@ -404,6 +460,9 @@ def main():
     if batch_specs is not None:
         line["batched"] = measure_batch(ctx, batch_specs, max(5, args.steps // 2), 2)
         print(f"[bench] batched: {line['batched']['batched_gvox_s']} Gvox/s", file=sys.stderr, flush=True)
+    if not args.no_paper_workloads:
+        line["paper_workloads"] = measure_paper_workloads(ctx, max(5, args.steps // 2))
+        print("[bench] paper workloads done", file=sys.stderr, flush=True)
     if pool is not None:
         del batch_specs
         rates = [float(r) for r in args.serving_rates.split(",") if r]
