@@ -162,28 +162,49 @@ __device__ __forceinline__ uint32_t pk_lt(uint32_t q, uint32_t ref) {
 // Pattern of the 8 neighbours of two cells.  d[k] = q_k - ref_k per 16-bit
 // half (k = NW N NE W E SW S SE, ref = cell level, +1 for neighbours that win
 // ties), so the sign bit of each half says whether neighbour k entered
-// before that cell.  A byte permute turns the sign bits of two such words
-// into 0x00/0xFF bytes (selectors 8-11), four bit-selects gather them, and a
-// final shuffle leaves the index of the low cell in bits 0-7 and of the high
-// cell in bits 16-23.  Index bit i (i < 4) is neighbour 2i, bit 4+i is
-// neighbour 2i+1 (the host tables are built in this order).
+// before that cell.  The index of a cell has bit i (i < 4) for neighbour 2i
+// and bit 4 + i for neighbour 2i + 1 (the host tables are built in this
+// order).  Returned as byte offsets into a table of 2^S-byte entries: the low
+// cell's is y & (0xFF << S), the high cell's (y >> 8) & (0xFF << S); the
+// other bits of y are garbage.
 __device__ __forceinline__ uint32_t pk_diff(uint32_t q, uint32_t ref) {
     return __builtin_bit_cast(uint32_t, __builtin_bit_cast(i16x2, q) - __builtin_bit_cast(i16x2, ref));
 }
 
-__device__ __forceinline__ uint32_t gather_pattern(uint32_t d0, uint32_t d1, uint32_t d2, uint32_t d3, uint32_t d4,
+// (m & a) | (~m & b) in one three-input bitwise operation (truth table 0xCA:
+// the first operand selects between the other two)
+__device__ __forceinline__ uint32_t bit_select(uint32_t m, uint32_t a, uint32_t b) {
+    return __builtin_amdgcn_bitop3_b32(m, a, b, (unsigned char)0xCA);
+}
+
+template <int S>
+__device__ __forceinline__ uint32_t gather_offsets(uint32_t d0, uint32_t d1, uint32_t d2, uint32_t d3, uint32_t d4,
                                                    uint32_t d5, uint32_t d6, uint32_t d7) {
-    // bytes: [low cell, even k | low cell, odd k | high cell, even k | high cell, odd k]
-    constexpr uint32_t kSel = 0x0B090A08u;
+    // a byte permute with selectors 8-11 turns the sign bits of two words into
+    // 0x00/0xFF bytes: [low cell, even k | high cell, even k | low cell, odd k
+    // | high cell, odd k]
+    constexpr uint32_t kSel = 0x0B0A0908u;
     const uint32_t p0 = __builtin_amdgcn_perm(d1, d0, kSel);
     const uint32_t p1 = __builtin_amdgcn_perm(d3, d2, kSel);
     const uint32_t p2 = __builtin_amdgcn_perm(d5, d4, kSel);
     const uint32_t p3 = __builtin_amdgcn_perm(d7, d6, kSel);
-    uint32_t r = p0 & 0x01010101u;
-    r = (p1 & 0x02020202u) | (r & ~0x02020202u);
-    r = (p2 & 0x04040404u) | (r & ~0x04040404u);
-    r = (p3 & 0x08080808u) | (r & ~0x08080808u);
-    return (r & 0x000F000Fu) | ((r >> 4) & 0x00F000F0u);
+    // bit S + i of every byte from p_i (bit selects; the other bits are don't-care)
+    constexpr uint32_t B = 0x01010101u << S, B2 = 0x01010101u << (S + 2), B01 = 0x03030303u << S;
+    const uint32_t t01 = bit_select(B, p0, p1);
+    const uint32_t t23 = bit_select(B2, p2, p3);
+    const uint32_t r = bit_select(B01, t01, t23);
+    // even-k nibbles stay, odd-k nibbles (bytes 2, 3) move down next to them
+    constexpr uint32_t M = (0x0Fu << S) | (0x0Fu << (S + 8));
+    return bit_select(M, r, r >> 12);
+}
+
+template <typename E, int S>
+__device__ __forceinline__ E lut_lo(const E *t, uint32_t y) {
+    return *reinterpret_cast<const E *>(reinterpret_cast<const char *>(t) + (y & (0xFFu << S)));
+}
+template <typename E, int S>
+__device__ __forceinline__ E lut_hi(const E *t, uint32_t y) {
+    return *reinterpret_cast<const E *>(reinterpret_cast<const char *>(t) + ((y >> 8) & (0xFFu << S)));
 }
 
 struct RawRow {
@@ -443,11 +464,13 @@ __device__ __forceinline__ void drain_2d(const uint64_t *hist, int W, int lo, in
 // The deltas of the VEC cells of `mid` into the LDS bins: the bin of a cell
 // is lam' itself (hist[1..W] are the levels of the pass window).  Cells
 // outside the window (lam' = 0 or W + 1, among them every cell outside the
-// field) and the halo lanes' cells (masked to 0) add nothing, so their lanes
-// skip the atomic: masses of such cells would otherwise all hit one address.
+// field) and every cell of a halo lane (whose window wl is 0) go to the
+// lane's own scratch bin, which is never drained: masses of such cells would
+// otherwise all hit one address, and the atomics stay unconditional, so all
+// table reads of a group can be issued before its atomics.
 template <int VEC>
 __device__ __forceinline__ void emit_row(const uint32_t (&up)[VEC + 1], const uint32_t (&mid)[VEC + 1],
-                                         const uint32_t (&dn)[VEC + 1], uint32_t halo_mask, uint32_t W,
+                                         const uint32_t (&dn)[VEC + 1], uint32_t wl, uint32_t scratch,
                                          const uint64_t *dl, uint64_t *hist) {
     // groups of up to 4 cell pairs: all table reads of a group are issued
     // before its atomics, so the atomics wait for one LDS round trip, not one each
@@ -460,19 +483,18 @@ __device__ __forceinline__ void emit_row(const uint32_t (&up)[VEC + 1], const ui
         for (int q = 0; q < GP; ++q) {
             const int j = 2 * (g0 + q) + 1;
             const uint32_t self = mid[j], self1 = self + 0x00010001u;
-            const uint32_t acc = gather_pattern(pk_diff(up[j - 1], self1), pk_diff(up[j], self1),
-                                                pk_diff(up[j + 1], self1), pk_diff(mid[j - 1], self1),
-                                                pk_diff(mid[j + 1], self), pk_diff(dn[j - 1], self),
-                                                pk_diff(dn[j], self), pk_diff(dn[j + 1], self));
-            const uint32_t sm = self & halo_mask;  // 0 for the halo lanes
-            bin[2 * q] = sm & 0xFFFFu;
-            bin[2 * q + 1] = sm >> 16;
-            dv[2 * q] = dl[acc & 0xFFu];
-            dv[2 * q + 1] = dl[(acc >> 16) & 0xFFu];
+            const uint32_t acc = gather_offsets<3>(pk_diff(up[j - 1], self1), pk_diff(up[j], self1),
+                                                   pk_diff(up[j + 1], self1), pk_diff(mid[j - 1], self1),
+                                                   pk_diff(mid[j + 1], self), pk_diff(dn[j - 1], self),
+                                                   pk_diff(dn[j], self), pk_diff(dn[j + 1], self));
+            const uint32_t b0 = self & 0xFFFFu, b1 = self >> 16;
+            bin[2 * q] = b0 - 1u < wl ? b0 : scratch;
+            bin[2 * q + 1] = b1 - 1u < wl ? b1 : scratch;
+            dv[2 * q] = lut_lo<uint64_t, 3>(dl, acc);
+            dv[2 * q + 1] = lut_hi<uint64_t, 3>(dl, acc);
         }
 #pragma unroll
-        for (int q = 0; q < 2 * GP; ++q)
-            if (bin[q] - 1u < W) atomicAdd((unsigned long long *)&hist[bin[q]], (unsigned long long)dv[q]);
+        for (int q = 0; q < 2 * GP; ++q) atomicAdd((unsigned long long *)&hist[bin[q]], (unsigned long long)dv[q]);
     }
 }
 
@@ -482,7 +504,7 @@ template <typename T, int LM, int AL, int PF, typename TH>
 __device__ __forceinline__ void stream_run_2d(const T *__restrict__ data, int h, int64_t w,
                                               const LevelArgs &lv, const TH &thr, int32_t lo, int W,
                                               float cpass, const uint64_t *dl, uint64_t *hist, int64_t strip,
-                                              int ra, int rb, int lane, uint32_t halo_mask) {
+                                              int ra, int rb, int lane, uint32_t wl, uint32_t scratch) {
     static_assert(PF % 3 == 0, "PF must be a multiple of 3");
     constexpr int VEC = Elem<T>::VEC;
     constexpr int CE = 62 * VEC;  // cells owned per strip
@@ -517,7 +539,7 @@ __device__ __forceinline__ void stream_run_2d(const T *__restrict__ data, int h,
             convert_row<T, LM>(ring[k], r + 1 < h, full, lv, thr, lo, W, cpass, R[(k + 1) % 3]);
             const int nx = r + 1 + PF < rb ? r + 1 + PF : rb;
             fetch_row<T, AL>(data, clamp_row(nx), w, x0, last_block, ring[k]);
-            emit_row<VEC>(R[(k + 2) % 3], R[k % 3], R[(k + 1) % 3], halo_mask, (uint32_t)W, dl, hist);
+            emit_row<VEC>(R[(k + 2) % 3], R[k % 3], R[(k + 1) % 3], wl, scratch, dl, hist);
         }
     }
     // remaining rows (fewer than PF); here r - ra = r0 - ra + k with r0 - ra
@@ -527,7 +549,7 @@ __device__ __forceinline__ void stream_run_2d(const T *__restrict__ data, int h,
         const int r = r0 + k;
         if (r < rb) {
             convert_row<T, LM>(ring[k], r + 1 < h, full, lv, thr, lo, W, cpass, R[(k + 1) % 3]);
-            emit_row<VEC>(R[(k + 2) % 3], R[k % 3], R[(k + 1) % 3], halo_mask, (uint32_t)W, dl, hist);
+            emit_row<VEC>(R[(k + 2) % 3], R[k % 3], R[(k + 1) % 3], wl, scratch, dl, hist);
         }
     }
 }
@@ -549,8 +571,9 @@ __global__ void __launch_bounds__(256)
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform: keeps loop control scalar
     const int W = hi - lo;
     const int L = lv.L;
-    // LDS: bins 0..W+1 (1..W are the window's levels), then thresholds [lo-2, hi+1)
-    const int n_bins = W + 2;
+    // LDS: bins 0..W+1 (1..W are the window's levels), a scratch bin per
+    // lane, then thresholds [lo-2, hi+1)
+    const int n_bins = W + 2 + 64;
     uint64_t *hist = smem;
     float *thr_s = reinterpret_cast<float *>(smem + n_bins);
     constexpr bool kThr = LM == LM_AFFINE || LM == LM_SEARCH;
@@ -571,14 +594,14 @@ __global__ void __launch_bounds__(256)
     const int64_t n_strips = (w + CE - 1) / CE;
     const int64_t units = n_strips * H;
     const int64_t u_end = units * (gw + 1) / NW;
-    const bool halo_lane = lane == 0 || lane == 63;
-    const uint32_t halo_mask = halo_lane ? 0u : 0xFFFFFFFFu;
+    // lanes 0 and 63 only serve as halo: their window is empty
+    const uint32_t wl = lane == 0 || lane == 63 ? 0u : (uint32_t)W;
     const ThrLds thr{thr_s, lo - 2};
     for (int64_t u = units * gw / NW; u < u_end;) {
         const int64_t strip = u / H, ra = u % H;
         const int64_t rb = ra + (u_end - u) < H ? ra + (u_end - u) : H;
         stream_run_2d<T, LM, AL, PF>(data, (int)h, w, lv, thr, lo, W, cpass, dl, hist, strip, (int)(row_lo + ra),
-                                     (int)(row_lo + rb), lane, halo_mask);
+                                     (int)(row_lo + rb), lane, wl, (uint32_t)(W + 2 + lane));
         u += rb - ra;
     }
     __syncthreads();
@@ -611,15 +634,14 @@ __global__ void __launch_bounds__(256)
     dl[1][tid] = luts[256 + tid];
     const int i_beg = wg_first[blockIdx.x], i_end = wg_first[blockIdx.x + 1];
     const bool halo_lane = lane == 0 || lane == 63;
-    const uint32_t halo_mask = halo_lane ? 0u : 0xFFFFFFFFu;
     for (int it = i_beg; it < i_end; ++it) {
         const BatchItem item = items[it];
         const BatchField2D &f = fields[item.field];
         const int L = f.L;
         const int h = (int)f.h;
         const int64_t w = f.w;
-        uint64_t *hist = smem;
-        float *thr_s = reinterpret_cast<float *>(smem + L + 2);
+        uint64_t *hist = smem;  // bins 0..L+1, then a scratch bin per lane
+        float *thr_s = reinterpret_cast<float *>(smem + L + 2 + 64);
         for (int b = tid; b < L + 2; b += 256) hist[b] = 0;
         if (kThr)
             for (int i = tid; i < L + 3; i += 256) {
@@ -644,7 +666,8 @@ __global__ void __launch_bounds__(256)
             const int strip = u / h, ra = u % h;
             const int rb = ra + (u_end - u) < h ? ra + (u_end - u) : h;
             stream_run_2d<T, LM, kLoadVector, PF>((const T *)f.data, h, w, lv, thr, 0, L, f.cpass, dl[f.conn_idx],
-                                                  hist, strip, ra, rb, lane, halo_mask);
+                                                  hist, strip, ra, rb, lane, halo_lane ? 0u : (uint32_t)L,
+                                                  (uint32_t)(L + 2 + lane));
             u += rb - ra;
         }
         __syncthreads();
@@ -935,14 +958,15 @@ __device__ __forceinline__ void convert_row3(const RawRow3 &raw_in, bool row_ok,
 }
 
 // 8-neighbour "entered before" pattern of the two cells of pair j (low / high
-// half), rows u (above), m (current), d (below)
+// half), rows u (above), m (current), d (below), as offsets into tables of
+// 4-byte entries (lut_lo / lut_hi)
 template <int VEC>
 __device__ __forceinline__ uint32_t pattern_pair(const uint32_t (&u)[VEC + 1], const uint32_t (&m)[VEC + 1],
                                                  const uint32_t (&d)[VEC + 1], int j) {
     const uint32_t self = m[j], self1 = self + 0x00010001u;
-    return gather_pattern(pk_diff(u[j - 1], self1), pk_diff(u[j], self1), pk_diff(u[j + 1], self1),
-                          pk_diff(m[j - 1], self1), pk_diff(m[j + 1], self), pk_diff(d[j - 1], self),
-                          pk_diff(d[j], self), pk_diff(d[j + 1], self));
+    return gather_offsets<2>(pk_diff(u[j - 1], self1), pk_diff(u[j], self1), pk_diff(u[j + 1], self1),
+                             pk_diff(m[j - 1], self1), pk_diff(m[j + 1], self), pk_diff(d[j - 1], self),
+                             pk_diff(d[j], self), pk_diff(d[j + 1], self));
 }
 
 // per-pixel image of two planes: min (26-C) or max (6-C), packed
@@ -1025,8 +1049,8 @@ struct March3D {
 #pragma unroll
             for (int j = 1; j < VEC + 1; j += 2) {
                 const uint32_t pm = pattern_pair<VEC>(M[t], M[t + 1], M[t + 2], j);
-                E[t][j - 1] = tm[pm & 0xFFu];
-                E[t][j] = tm[(pm >> 16) & 0xFFu];
+                E[t][j - 1] = lut_lo<int32_t, 2>(tm, pm);
+                E[t][j] = lut_hi<int32_t, 2>(tm, pm);
             }
     }
 
@@ -1056,10 +1080,10 @@ struct March3D {
                 below[q] = pk_lt(Pp[t + 1][j], self1);
                 above[q] = pk_lt(Pn[t + 1][j], self);
                 selfv[q] = self;
-                tlv[2 * q] = tl[pl & 0xFFu];
-                tlv[2 * q + 1] = tl[(pl >> 16) & 0xFFu];
-                en[2 * q] = tm[pm[q] & 0xFFu];
-                en[2 * q + 1] = tm[(pm[q] >> 16) & 0xFFu];
+                tlv[2 * q] = lut_lo<uint32_t, 2>(tl, pl);
+                tlv[2 * q + 1] = lut_hi<uint32_t, 2>(tl, pl);
+                en[2 * q] = lut_lo<int32_t, 2>(tm, pm[q]);
+                en[2 * q + 1] = lut_hi<int32_t, 2>(tm, pm[q]);
             }
 #pragma unroll
             for (int q = 0; q < VEC / 2; ++q) {
@@ -1419,7 +1443,7 @@ static int launch_2d_t(const Launch2D &a, hipStream_t s) {
     if (max_wg_cells_2d(chunk, a.w, VEC, a.grid) > kFlush2D) return (int)hipErrorInvalidValue;
     // affine levels: the pass constant -t0/step + 1.5 - lo, rounded once
     const float cpass = (float)(a.lv.u0d + 1.5 - a.lo);
-    const size_t lds = (size_t)(W + 2) * 8 + (size_t)(W + 3) * 4;
+    const size_t lds = (size_t)(W + 2 + 64) * 8 + (size_t)(W + 3) * 4;
     for (int64_t r0 = a.row_lo; r0 < a.row_hi; r0 += chunk) {
         const int64_t r1 = r0 + chunk < a.row_hi ? r0 + chunk : a.row_hi;
         const bool acc = a.accumulate || r0 > a.row_lo;
@@ -1543,7 +1567,7 @@ int launch_3d(const Launch3D &a, void *stream) {
 
 size_t lds_bytes_batch_2d(int lm, int max_L) {
     const bool thr = lm == LM_AFFINE || lm == LM_SEARCH;
-    return (size_t)(max_L + 2) * 8 + (thr ? (size_t)(max_L + 3) * 4 : 0);
+    return (size_t)(max_L + 2 + 64) * 8 + (thr ? (size_t)(max_L + 3) * 4 : 0);
 }
 
 template <typename T>
