@@ -156,6 +156,48 @@ def measure(ctx, spec, steps, warmup, copies, with_cpu):
     return out
 
 
+def measure_vertex_classes(ctx, spec, steps, warmup, copies, curves):
+    """The contribution map (vertex counts per Table 1 class and level) of the
+    main 2D field: per-call time with the field in HBM, the class-count
+    kernel's own time, and the check that its Table 1 weightings reproduce the
+    main run's EC, perimeter and area curves."""
+    import numpy as np
+    import torch
+    dev0 = torch.from_numpy(spec.data).cuda()
+    bufs = [dev0] + [dev0.clone() for _ in range(copies - 1)]
+    out = torch.empty((5, spec.n_levels), dtype=torch.int64, device="cuda")
+    it = [0]
+
+    def call(stream):
+        ctx.vertex_classes(bufs[it[0] % copies], spec.n_levels, thresholds=spec.thresholds, out=out,
+                           stream=stream)
+        it[0] += 1
+
+    for _ in range(warmup):
+        call(torch.cuda.current_stream())
+    ms, _ = timed_calls(call, steps)
+    ctx.profile(True)
+    ctx.profile_read(reset=True)
+    for _ in range(steps):
+        call(torch.cuda.current_stream())
+    torch.cuda.synchronize()
+    k_ms, k_n = ctx.profile_read(reset=True)
+    ctx.profile(False)
+    one, adj, diag, three, four = out.cpu().numpy()
+    ok = (np.array_equal(one - 2 * diag - three, 4 * curves["ec"]) and
+          np.array_equal(2 * one + 2 * adj + 4 * diag + 2 * three, 2 * curves["perimeter"]) and
+          np.array_equal(one + 2 * adj + 2 * diag + 3 * three + 4 * four, 4 * curves["area"]))
+    cells = spec.data.size
+    alg = cells * spec.data.dtype.itemsize
+    kern = k_ms / max(k_n, 1)
+    del bufs
+    return dict(workload=spec.meta["name"], classes=["one", "adjacent", "diagonal", "three", "four"],
+                ms_per_call=round(ms, 4), gvox_s=round(cells / ms / 1e6, 2),
+                kernel="ecc2d_stream (class counts)", kernel_ms_per_launch=round(kern, 4),
+                kernel_hbm_frac=round(alg / (kern / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+                weightings_equal_curves=bool(ok))
+
+
 def timed_calls(fn, steps):
     """(ms per call on the GPU clock, ms per call on the host clock) of `steps` calls."""
     import torch
@@ -385,6 +427,8 @@ def main():
     ap.add_argument("--no-secondary", action="store_true", help="skip the 3D secondary measurement")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched vs per-field comparison")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving comparison")
+    ap.add_argument("--no-vertex-classes", action="store_true",
+                    help="skip the contribution-map (vertex class counts) measurement")
     ap.add_argument("--no-paper-workloads", action="store_true",
                     help="skip the paper's white-noise workloads (context against its CPU timings)")
     ap.add_argument("--serving-requests", type=int, default=2000)
@@ -450,6 +494,10 @@ def main():
     if "cpu_baseline" in main_r:
         line["cpu_baseline"] = main_r["cpu_baseline"]
         line["parity_vs_oracle"] = main_r["parity_vs_oracle"]
+    if spec.data.ndim == 2 and spec.connectivity == 8 and not args.no_vertex_classes:
+        line["vertex_classes"] = measure_vertex_classes(ctx, spec, args.steps, args.warmup, args.copies,
+                                                        main_r["curves"])
+        print(f"[bench] vertex classes: {line['vertex_classes']['gvox_s']} Gvox/s", file=sys.stderr, flush=True)
     del main_r
     if sec_spec is not None:
         sec = measure(ctx, sec_spec, max(3, args.steps // 2), 2, 2, with_cpu=False)

@@ -162,6 +162,38 @@ ecc_status ecc_batch_plan_tune(ecc_context ctx, int32_t n, const ecc_field *fiel
 ecc_status ecc_vertex_table(int32_t ndim, int32_t connectivity, int32_t *out);
 
 /*
+ * Vertex class counts of a 2D field per level (the vertex-contribution map
+ * behind Table 1 and Eq. 4, the quantity the curves are weighted sums of).
+ * The lattice vertices are the (h+1) x (w+1) corners of the pixels; at level l
+ * the quadrant of a vertex (its up to four pixels with level <= l, pixels
+ * outside the field never in) falls in one of the classes of Table 1:
+ *   counts[0*L + l]  one pixel
+ *   counts[1*L + l]  two pixels sharing an edge
+ *   counts[2*L + l]  two pixels on a diagonal
+ *   counts[3*L + l]  three pixels
+ *   counts[4*L + l]  four pixels
+ * (empty quadrants are the rest).  Any per-vertex descriptor of Table 1 at
+ * either connectivity is a fixed weighting of these counts, e.g.
+ * 4*EC(8-C) = one - 2*diagonal - three, 4*EC(4-C) = one + 2*diagonal - three,
+ * 2*perimeter = 2*one + 2*adjacent + 4*diagonal + 2*three.
+ *
+ * field: as for ecc_curves_compute; ndim must be 2 (3D: ECC_ERR_UNSUPPORTED);
+ *        the connectivity is checked but does not matter.
+ * counts: DEVICE pointer, caller-owned, 5 * n_levels int64, class-major as
+ *        above; written only by the queued work.
+ * Asynchronous on `stream`; same validation and error behaviour as
+ * ecc_curves_compute (nothing is queued on error).
+ */
+ecc_status ecc_vertex_classes_compute(ecc_context ctx, const ecc_field *field, int64_t *counts, void *stream);
+
+/*
+ * Class (0..4 as for ecc_vertex_classes_compute, -1 for the empty mask) of each
+ * of the 16 masks of a 2D vertex, mask bits as for ecc_vertex_table (for tests).
+ * ndim must be 2 (3D: ECC_ERR_UNSUPPORTED).  out: HOST, 16 int32.
+ */
+ecc_status ecc_vertex_class_table(int32_t ndim, int32_t *out);
+
+/*
  * Kernel timing for measurement.  While enabled, the context records a pair of
  * HIP events around every launch of its field-reading pass kernel (the tile
  * kernel that reads the field from HBM; not the merge and scan kernels that

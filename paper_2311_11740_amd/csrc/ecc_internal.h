@@ -17,6 +17,12 @@ void clear_error();
 void vertex_table_2d(int connectivity, int32_t out[16][4]);
 void vertex_table_3d(int connectivity, int32_t out[256][4]);
 void cell_delta_table_2d(int connectivity, int32_t delta[256][3]);
+// class of a 2D quadrant mask (bit a*2+b: pixel (i-1+a, j-1+b) of vertex
+// (i, j)): -1 empty, 0 one pixel, 1 two adjacent, 2 two diagonal, 3 three, 4 four
+int vertex_class_2d(int mask);
+// per-cell change of the five class counts when the pixel enters, by the
+// "entered before" pattern of its 8 neighbours (bit k = neighbour k)
+void class_delta_table_2d(int32_t delta[256][5]);
 // The kernels index per-cell tables by a permuted pattern: index bit i (i < 4)
 // is neighbour 2i and bit 4+i neighbour 2i+1 of kNbr2.  Returns the kNbr2-order
 // pattern of kernel index n.
@@ -31,6 +37,16 @@ extern const int kNbr2[8][2];
 constexpr int kEcBias2 = 3, kPerBias2 = 4;
 constexpr int kShiftPer2 = 21, kShiftCnt2 = 44;
 constexpr int64_t kFlush2D = (1 << 19) - 1;
+// 2D class-count bins (two uint64 words per level), for the counts of lattice
+// vertices by quadrant class (one pixel, two adjacent, two diagonal, three,
+// four).  Per-cell class deltas lie in [-4, 4] (four: [0, 4]):
+//   word 0: [ one+4 : 21 | adjacent+4 : 21 | count : 22 ]
+//   word 1: [ diagonal+4 : 21 | three+4 : 21 | four : 22 ]
+// decoded with the count n (class c = field - 4n, four as is).  Valid while a
+// workgroup adds at most kFlushCls cells between drains (8n < 2^21).
+constexpr int kClsBias = 4, kClsShift1 = 21, kClsShift2 = 42;
+constexpr int64_t kFlushCls = (1 << 18) - 1;
+constexpr int kNumClasses2D = 5;
 // 3D bin word (uint64): [ ec+7 : 22 bits | surface+6 : 22 bits | count : 20 bits ],
 // crease in a second uint32 word as crease+12.  Valid while at most kFlush3D
 // cells are added between drains: ec+7 <= 14 and surface+6 <= 12 per cell keep
@@ -76,6 +92,7 @@ struct Launch2D {
     int grid;
     int64_t row_lo, row_hi;     // rows whose cells this launch emits (halo rows are read)
     bool accumulate;            // add to the partials instead of overwriting them
+    bool classes;               // class counts: delta_lut holds 2 x 256 words, partial is [5][L][grid]
 };
 
 // cells per lane along the contiguous axis (16 bytes of input per lane)

@@ -461,6 +461,30 @@ __device__ __forceinline__ void drain_2d(const uint64_t *hist, int W, int lo, in
     }
 }
 
+// class-count bins (two words per level) -> partials [class][level][workgroup]
+__device__ __forceinline__ void drain_cls(const uint64_t *hist, int W, int lo, int L, int G, int wg,
+                                          int32_t *__restrict__ partial, bool first) {
+    constexpr uint64_t m21 = (1ull << kClsShift1) - 1;
+    for (int b = threadIdx.x; b < W; b += blockDim.x) {
+        const uint64_t v0 = hist[2 * b], v1 = hist[2 * b + 1];
+        const int64_t n = (int64_t)(v0 >> kClsShift2);
+        int32_t c[5];
+        c[0] = (int32_t)((int64_t)(v0 & m21) - kClsBias * n);
+        c[1] = (int32_t)((int64_t)((v0 >> kClsShift1) & m21) - kClsBias * n);
+        c[2] = (int32_t)((int64_t)(v1 & m21) - kClsBias * n);
+        c[3] = (int32_t)((int64_t)((v1 >> kClsShift1) & m21) - kClsBias * n);
+        c[4] = (int32_t)(v1 >> kClsShift2);
+        const int64_t i0 = ((int64_t)(lo + b)) * G + wg, cs = (int64_t)L * G;
+#pragma unroll
+        for (int k = 0; k < 5; ++k) {
+            if (first)
+                partial[i0 + k * cs] = c[k];
+            else
+                partial[i0 + k * cs] += c[k];
+        }
+    }
+}
+
 // The deltas of the VEC cells of `mid` into the LDS bins: the bin of a cell
 // is lam' itself (hist[1..W] are the levels of the pass window).  Cells
 // outside the window (lam' = 0 or W + 1, among them every cell outside the
@@ -468,16 +492,18 @@ __device__ __forceinline__ void drain_2d(const uint64_t *hist, int W, int lo, in
 // lane's own scratch bin, which is never drained: masses of such cells would
 // otherwise all hit one address, and the atomics stay unconditional, so all
 // table reads of a group can be issued before its atomics.
-template <int VEC>
+// With CLS the bins hold class counts: two words per bin (hist[2 * bin] and
+// hist[2 * bin + 1]) and two tables (dl[0..255], dl[256..511]).
+template <int VEC, bool CLS>
 __device__ __forceinline__ void emit_row(const uint32_t (&up)[VEC + 1], const uint32_t (&mid)[VEC + 1],
                                          const uint32_t (&dn)[VEC + 1], uint32_t wl, uint32_t scratch,
                                          const uint64_t *dl, uint64_t *hist) {
     // groups of up to 4 cell pairs: all table reads of a group are issued
     // before its atomics, so the atomics wait for one LDS round trip, not one each
-    constexpr int NP = VEC / 2, GP = NP < 4 ? NP : 4;
+    constexpr int NP = VEC / 2, GP = CLS ? (NP < 2 ? NP : 2) : (NP < 4 ? NP : 4);
 #pragma unroll
     for (int g0 = 0; g0 < NP; g0 += GP) {
-        uint64_t dv[2 * GP];
+        uint64_t dv[2 * GP], dv2[CLS ? 2 * GP : 1];
         uint32_t bin[2 * GP];
 #pragma unroll
         for (int q = 0; q < GP; ++q) {
@@ -492,15 +518,26 @@ __device__ __forceinline__ void emit_row(const uint32_t (&up)[VEC + 1], const ui
             bin[2 * q + 1] = b1 - 1u < wl ? b1 : scratch;
             dv[2 * q] = lut_lo<uint64_t, 3>(dl, acc);
             dv[2 * q + 1] = lut_hi<uint64_t, 3>(dl, acc);
+            if constexpr (CLS) {
+                dv2[2 * q] = lut_lo<uint64_t, 3>(dl + 256, acc);
+                dv2[2 * q + 1] = lut_hi<uint64_t, 3>(dl + 256, acc);
+            }
         }
 #pragma unroll
-        for (int q = 0; q < 2 * GP; ++q) atomicAdd((unsigned long long *)&hist[bin[q]], (unsigned long long)dv[q]);
+        for (int q = 0; q < 2 * GP; ++q) {
+            if constexpr (CLS) {
+                atomicAdd((unsigned long long *)&hist[2 * bin[q]], (unsigned long long)dv[q]);
+                atomicAdd((unsigned long long *)&hist[2 * bin[q] + 1], (unsigned long long)dv2[q]);
+            } else {
+                atomicAdd((unsigned long long *)&hist[bin[q]], (unsigned long long)dv[q]);
+            }
+        }
     }
 }
 
 // rows [ra, rb) of one strip; three row buffers whose roles rotate with the
 // row index (PF is a multiple of 3, so the unrolled loop needs no copies)
-template <typename T, int LM, int AL, int PF, typename TH>
+template <typename T, int LM, int AL, int PF, bool CLS, typename TH>
 __device__ __forceinline__ void stream_run_2d(const T *__restrict__ data, int h, int64_t w,
                                               const LevelArgs &lv, const TH &thr, int32_t lo, int W,
                                               float cpass, const uint64_t *dl, uint64_t *hist, int64_t strip,
@@ -539,7 +576,7 @@ __device__ __forceinline__ void stream_run_2d(const T *__restrict__ data, int h,
             convert_row<T, LM>(ring[k], r + 1 < h, full, lv, thr, lo, W, cpass, R[(k + 1) % 3]);
             const int nx = r + 1 + PF < rb ? r + 1 + PF : rb;
             fetch_row<T, AL>(data, clamp_row(nx), w, x0, last_block, ring[k]);
-            emit_row<VEC>(R[(k + 2) % 3], R[k % 3], R[(k + 1) % 3], wl, scratch, dl, hist);
+            emit_row<VEC, CLS>(R[(k + 2) % 3], R[k % 3], R[(k + 1) % 3], wl, scratch, dl, hist);
         }
     }
     // remaining rows (fewer than PF); here r - ra = r0 - ra + k with r0 - ra
@@ -549,7 +586,7 @@ __device__ __forceinline__ void stream_run_2d(const T *__restrict__ data, int h,
         const int r = r0 + k;
         if (r < rb) {
             convert_row<T, LM>(ring[k], r + 1 < h, full, lv, thr, lo, W, cpass, R[(k + 1) % 3]);
-            emit_row<VEC>(R[(k + 2) % 3], R[k % 3], R[(k + 1) % 3], wl, scratch, dl, hist);
+            emit_row<VEC, CLS>(R[(k + 2) % 3], R[k % 3], R[(k + 1) % 3], wl, scratch, dl, hist);
         }
     }
 }
@@ -557,15 +594,16 @@ __device__ __forceinline__ void stream_run_2d(const T *__restrict__ data, int h,
 // Work split: the (strip, row) units of rows [row_lo, row_hi), strip-major,
 // are divided into equal contiguous ranges, one per wave (a range may run from
 // the end of one strip into the next).
-template <typename T, int LM, int AL, int PF>
+template <typename T, int LM, int AL, int PF, bool CLS>
 __global__ void __launch_bounds__(256)
     ecc2d_stream(const T *__restrict__ data, int64_t h, int64_t w, LevelArgs lv, int32_t lo,
                  int32_t hi, float cpass, const uint64_t *__restrict__ delta_lut, int32_t *__restrict__ partial,
                  int64_t row_lo, int64_t row_hi, int accumulate) {
     constexpr int VEC = Elem<T>::VEC;
     constexpr int CE = 62 * VEC;
+    constexpr int BW = CLS ? 2 : 1;  // words per bin
     extern __shared__ uint64_t smem[];
-    __shared__ uint64_t dl[256];
+    __shared__ uint64_t dl[256 * BW];
 
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform: keeps loop control scalar
@@ -575,7 +613,7 @@ __global__ void __launch_bounds__(256)
     // lane, then thresholds [lo-2, hi+1)
     const int n_bins = W + 2 + 64;
     uint64_t *hist = smem;
-    float *thr_s = reinterpret_cast<float *>(smem + n_bins);
+    float *thr_s = reinterpret_cast<float *>(smem + BW * n_bins);
     constexpr bool kThr = LM == LM_AFFINE || LM == LM_SEARCH;
     if (kThr)
         for (int i = tid; i < W + 3; i += 256) {
@@ -583,8 +621,9 @@ __global__ void __launch_bounds__(256)
             k = k < 0 ? 0 : (k >= L ? L - 1 : k);
             thr_s[i] = lv.thr[k];
         }
-    dl[tid] = delta_lut[tid];
-    for (int b = tid; b < n_bins; b += 256) hist[b] = 0;
+#pragma unroll
+    for (int k = 0; k < BW; ++k) dl[256 * k + tid] = delta_lut[256 * k + tid];
+    for (int b = tid; b < BW * n_bins; b += 256) hist[b] = 0;
     __syncthreads();
 
     const int G = gridDim.x;
@@ -600,12 +639,15 @@ __global__ void __launch_bounds__(256)
     for (int64_t u = units * gw / NW; u < u_end;) {
         const int64_t strip = u / H, ra = u % H;
         const int64_t rb = ra + (u_end - u) < H ? ra + (u_end - u) : H;
-        stream_run_2d<T, LM, AL, PF>(data, (int)h, w, lv, thr, lo, W, cpass, dl, hist, strip, (int)(row_lo + ra),
-                                     (int)(row_lo + rb), lane, wl, (uint32_t)(W + 2 + lane));
+        stream_run_2d<T, LM, AL, PF, CLS>(data, (int)h, w, lv, thr, lo, W, cpass, dl, hist, strip,
+                                          (int)(row_lo + ra), (int)(row_lo + rb), lane, wl, (uint32_t)(W + 2 + lane));
         u += rb - ra;
     }
     __syncthreads();
-    drain_2d(hist + 1, W, lo, L, G, wg, partial, accumulate == 0);
+    if constexpr (CLS)
+        drain_cls(hist + 2, W, lo, L, G, wg, partial, accumulate == 0);
+    else
+        drain_2d(hist + 1, W, lo, L, G, wg, partial, accumulate == 0);
 }
 
 // ---------------------------------------------------------------------------
@@ -665,7 +707,7 @@ __global__ void __launch_bounds__(256)
         for (int u = item.u0 + (int)((int64_t)n * wave / kWavesPerWG); u < u_end;) {
             const int strip = u / h, ra = u % h;
             const int rb = ra + (u_end - u) < h ? ra + (u_end - u) : h;
-            stream_run_2d<T, LM, kLoadVector, PF>((const T *)f.data, h, w, lv, thr, 0, L, f.cpass, dl[f.conn_idx],
+            stream_run_2d<T, LM, kLoadVector, PF, false>((const T *)f.data, h, w, lv, thr, 0, L, f.cpass, dl[f.conn_idx],
                                                   hist, strip, ra, rb, lane, halo_lane ? 0u : (uint32_t)L,
                                                   (uint32_t)(L + 2 + lane));
             u += rb - ra;
@@ -1431,23 +1473,24 @@ static int64_t max_wg_cells_2d(int64_t rows, int64_t w, int vec, int grid) {
     return kWavesPerWG * ((units + NW - 1) / NW + 1) * ce;
 }
 
-template <typename T, int LM, int AL>
+template <typename T, int LM, int AL, bool CLS>
 static int launch_2d_t(const Launch2D &a, hipStream_t s) {
     constexpr int VEC = Elem<T>::VEC, PF = sizeof(T) == 1 ? 3 : 6;
     const int W = a.hi - a.lo;
-    // the packed LDS bins of one workgroup may see at most kFlush2D cells:
-    // split tall fields into row chunks that respect it (later chunks add to
-    // the partials of the first)
+    // the packed LDS bins of one workgroup may see at most kFlush2D (class
+    // counts: kFlushCls) cells: split tall fields into row chunks that respect
+    // it (later chunks add to the partials of the first)
+    const int64_t flush = CLS ? kFlushCls : kFlush2D;
     int64_t chunk = a.row_hi - a.row_lo;
-    while (chunk > 1 && max_wg_cells_2d(chunk, a.w, VEC, a.grid) > kFlush2D) chunk = (chunk + 1) / 2;
-    if (max_wg_cells_2d(chunk, a.w, VEC, a.grid) > kFlush2D) return (int)hipErrorInvalidValue;
+    while (chunk > 1 && max_wg_cells_2d(chunk, a.w, VEC, a.grid) > flush) chunk = (chunk + 1) / 2;
+    if (max_wg_cells_2d(chunk, a.w, VEC, a.grid) > flush) return (int)hipErrorInvalidValue;
     // affine levels: the pass constant -t0/step + 1.5 - lo, rounded once
     const float cpass = (float)(a.lv.u0d + 1.5 - a.lo);
-    const size_t lds = (size_t)(W + 2 + 64) * 8 + (size_t)(W + 3) * 4;
+    const size_t lds = (size_t)(CLS ? 2 : 1) * (W + 2 + 64) * 8 + (size_t)(W + 3) * 4;
     for (int64_t r0 = a.row_lo; r0 < a.row_hi; r0 += chunk) {
         const int64_t r1 = r0 + chunk < a.row_hi ? r0 + chunk : a.row_hi;
         const bool acc = a.accumulate || r0 > a.row_lo;
-        hipLaunchKernelGGL((ecc2d_stream<T, LM, AL, PF>), dim3(a.grid), dim3(256), lds, s,
+        hipLaunchKernelGGL((ecc2d_stream<T, LM, AL, PF, CLS>), dim3(a.grid), dim3(256), lds, s,
                            (const T *)a.data, a.h, a.w, a.lv, a.lo, a.hi, cpass, a.delta_lut, a.partial, r0, r1,
                            acc ? 1 : 0);
         const int e = (int)hipGetLastError();
@@ -1458,8 +1501,11 @@ static int launch_2d_t(const Launch2D &a, hipStream_t s) {
 
 template <typename T, int LM>
 static int launch_2d_al(const Launch2D &a, hipStream_t s) {
-    return load_mode_2d(a.data, a.h, a.w, (int)sizeof(T)) == kLoadAligned ? launch_2d_t<T, LM, kLoadAligned>(a, s)
-                                                                          : launch_2d_t<T, LM, kLoadVector>(a, s);
+    // class counts load at any alignment (one variant per dtype and level mode)
+    if (a.classes) return launch_2d_t<T, LM, kLoadVector, true>(a, s);
+    return load_mode_2d(a.data, a.h, a.w, (int)sizeof(T)) == kLoadAligned
+               ? launch_2d_t<T, LM, kLoadAligned, false>(a, s)
+               : launch_2d_t<T, LM, kLoadVector, false>(a, s);
 }
 
 template <typename T>

@@ -165,6 +165,24 @@ extern "C" ecc_status ecc_create(int device, ecc_context *out) {
             return s;
         }
     }
+    {
+        // class-count deltas, two words per pattern in the kernels' index order
+        int32_t ct[256][5];
+        class_delta_table_2d(ct);
+        uint64_t packed[512];
+        for (int n = 0; n < 256; ++n) {
+            const int p = pattern_of_index(n);
+            packed[n] = (uint64_t)(ct[p][0] + kClsBias) | (uint64_t)(ct[p][1] + kClsBias) << kClsShift1 |
+                        1ull << kClsShift2;
+            packed[256 + n] = (uint64_t)(ct[p][2] + kClsBias) | (uint64_t)(ct[p][3] + kClsBias) << kClsShift1 |
+                              (uint64_t)ct[p][4] << kClsShift2;
+        }
+        ecc_status s = upload((void **)&ctx->d_cls2, packed, sizeof(packed));
+        if (s != ECC_OK) {
+            ecc_destroy(ctx);
+            return s;
+        }
+    }
     e = (int)hipEventCreateWithFlags(&ctx->ws_event, hipEventDisableTiming);
     if (e) {
         ecc_destroy(ctx);
@@ -200,6 +218,7 @@ extern "C" ecc_status ecc_destroy(ecc_context ctx) {
         if (ctx->d_vtab3[k]) hipFree(ctx->d_vtab3[k]);
         if (ctx->d_zm3[k]) hipFree(ctx->d_zm3[k]);
     }
+    if (ctx->d_cls2) hipFree(ctx->d_cls2);
     for (auto *t : ctx->thr_cache) free_thresholds(t);
     ctx->thr_cache.clear();
     for (auto &pe : ctx->prof_events) {
@@ -515,7 +534,7 @@ ecc_status compute_one(ecc_context ctx, const ecc_field *f, const FieldInfo &fi,
             s = prof_begin(ctx, stream, &slot);
             if (s != ECC_OK) return s;
             Launch2D a{data, fi.dtype, fi.h, fi.w, lv, lo, hi, ctx->d_delta2[k], partial, grid,
-                       0, fi.h, false};
+                       0, fi.h, false, false};
             int e = launch_2d(a, stream);
             if (e) return hip_fail(e, "2D kernel launch");
             s = prof_end(ctx, stream, slot);
@@ -536,7 +555,75 @@ ecc_status compute_one(ecc_context ctx, const ecc_field *f, const FieldInfo &fi,
     return merge_and_scan(ctx, grid, nch, L, outs, stream);
 }
 
+// Class counts of a 2D field: the single-field 2D path with the class-count
+// bins (five channels), merged as channels 0-2 and 3-4.
+static ecc_status compute_classes(ecc_context ctx, const ecc_field *f, const FieldInfo &fi, int64_t *counts,
+                                  void *stream) {
+    LevelArgs lv;
+    ecc_status s = level_args(ctx, f, fi, stream, &lv);
+    if (s != ECC_OK) return s;
+    const int L = fi.L, nch = kNumClasses2D;
+    const int win = std::min(L, kMaxWindow);
+    const int vec = vec_2d(fi.dtype);
+    const int64_t strips = (fi.w + 62 * vec - 1) / (62 * vec);
+    int grid = (int)std::min<int64_t>((int64_t)ctx->n_cu * wg_per_cu_default(),
+                                      std::max<int64_t>(1, (strips * fi.h + 31) / 32));
+    if (grid >= 8) grid -= grid % 8;
+    s = grow(ctx, ctx->ws.partial, (size_t)grid * nch * L * sizeof(int32_t), "partials");
+    if (s != ECC_OK) return s;
+    int32_t *partial = (int32_t *)ctx->ws.partial.ptr;
+    const void *data = f->data;
+    if (fi.cells < vec) {  // smaller than one vector load: padded copy
+        int e = (int)hipMemcpyAsync(ctx->d_tiny, f->data, (size_t)fi.cells * fi.elem_bytes,
+                                    hipMemcpyDeviceToDevice, (hipStream_t)stream);
+        if (e) return hip_fail(e, "hipMemcpyAsync(small field)");
+        data = ctx->d_tiny;
+    }
+    for (int lo = 0; lo < L; lo += win) {
+        const int hi = std::min(L, lo + win);
+        int slot = -1;
+        s = prof_begin(ctx, stream, &slot);
+        if (s != ECC_OK) return s;
+        Launch2D a{data, fi.dtype, fi.h, fi.w, lv, lo, hi, ctx->d_cls2, partial, grid, 0, fi.h, false, true};
+        int e = launch_2d(a, stream);
+        if (e) return hip_fail(e, "2D class-count kernel launch");
+        s = prof_end(ctx, stream, slot);
+        if (s != ECC_OK) return s;
+    }
+    s = grow(ctx, ctx->ws.totals, (size_t)3 * L * sizeof(int64_t), "totals");
+    if (s != ECC_OK) return s;
+    int64_t *const outs_a[4] = {counts, counts + L, counts + 2 * (int64_t)L, nullptr};
+    int64_t *const outs_b[4] = {counts + 3 * (int64_t)L, counts + 4 * (int64_t)L, nullptr, nullptr};
+    int e = launch_merge(partial, grid, 3, L, outs_a, (int64_t *)ctx->ws.totals.ptr, (unsigned *)ctx->d_counter,
+                         stream);
+    if (!e)
+        e = launch_merge(partial + (size_t)3 * L * grid, grid, 2, L, outs_b, (int64_t *)ctx->ws.totals.ptr,
+                         (unsigned *)ctx->d_counter, stream);
+    if (e) return hip_fail(e, "merge kernel launch");
+    return ECC_OK;
+}
+
 }  // namespace ecc
+
+extern "C" ecc_status ecc_vertex_classes_compute(ecc_context ctx, const ecc_field *field, int64_t *counts,
+                                                 void *stream) {
+    clear_error();
+    if (!ctx) return fail(ECC_ERR_INVALID_ARG, "context is NULL");
+    if (!counts) return fail(ECC_ERR_INVALID_ARG, "counts is NULL");
+    FieldInfo fi;
+    const ecc_curves probe{counts, nullptr, nullptr, nullptr};
+    ecc_status s = validate_field(field, &probe, &fi, false);
+    if (s != ECC_OK) return s;
+    if (fi.ndim != 2) return fail(ECC_ERR_UNSUPPORTED, "vertex class counts are computed for 2D fields only");
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    int e = (int)hipSetDevice(ctx->device);
+    if (e) return hip_fail(e, "hipSetDevice");
+    s = acquire_workspace(ctx, stream);
+    if (s != ECC_OK) return s;
+    s = compute_classes(ctx, field, fi, counts, stream);
+    ecc_status s2 = release_workspace(ctx, stream);
+    return s != ECC_OK ? s : s2;
+}
 
 extern "C" ecc_status ecc_curves_compute(ecc_context ctx, const ecc_field *field,
                                          const ecc_curves *curves, void *stream) {

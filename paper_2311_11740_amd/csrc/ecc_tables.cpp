@@ -62,6 +62,46 @@ void vertex_table_2d(int connectivity, int32_t out[16][4]) {
 // neighbour order of the 8-bit per-cell pattern (row offset, column offset)
 const int kNbr2[8][2] = {{-1, -1}, {-1, 0}, {-1, 1}, {0, -1}, {0, 1}, {1, -1}, {1, 0}, {1, 1}};
 
+int vertex_class_2d(int m) {
+    switch (__builtin_popcount(m)) {
+    case 0: return -1;
+    case 1: return 0;
+    case 2: return (m == 6 || m == 9) ? 2 : 1;  // pixels on a diagonal: b0 b3 or b1 b2
+    case 3: return 3;
+    default: return 4;
+    }
+}
+
+void class_delta_table_2d(int32_t delta[256][5]) {
+    // the four vertices at the corners (cr, cc) of pixel p = (0,0), as in
+    // cell_delta_table_2d: one class leaves (unless the quadrant was empty)
+    // and one arrives
+    for (int pat = 0; pat < 256; ++pat) {
+        auto precedes = [&](int dr, int dc) -> int {
+            for (int k = 0; k < 8; ++k)
+                if (kNbr2[k][0] == dr && kNbr2[k][1] == dc) return pat >> k & 1;
+            return 0;
+        };
+        int32_t s[5] = {0, 0, 0, 0, 0};
+        for (int cr = 0; cr < 2; ++cr)
+            for (int cc = 0; cc < 2; ++cc) {
+                int m0 = 0, pbit = 0;
+                for (int a = 0; a < 2; ++a)
+                    for (int b = 0; b < 2; ++b) {
+                        const int dr = cr - 1 + a, dc = cc - 1 + b, bit = a * 2 + b;
+                        if (dr == 0 && dc == 0)
+                            pbit = bit;
+                        else if (precedes(dr, dc))
+                            m0 |= 1 << bit;
+                    }
+                const int c0 = vertex_class_2d(m0), c1 = vertex_class_2d(m0 | 1 << pbit);
+                if (c0 >= 0) --s[c0];
+                ++s[c1];
+            }
+        for (int c = 0; c < 5; ++c) delta[pat][c] = s[c];
+    }
+}
+
 int pattern_of_index(int n) {
     int p = 0;
     for (int i = 0; i < 4; ++i) {
@@ -187,4 +227,11 @@ extern "C" ecc_status ecc_vertex_table(int32_t ndim, int32_t connectivity, int32
         return ECC_OK;
     }
     return ecc::fail(ECC_ERR_INVALID_ARG, "ecc_vertex_table: ndim must be 2 or 3");
+}
+
+extern "C" ecc_status ecc_vertex_class_table(int32_t ndim, int32_t *out) {
+    if (!out) return ecc::fail(ECC_ERR_INVALID_ARG, "ecc_vertex_class_table: out is NULL");
+    if (ndim != 2) return ecc::fail(ECC_ERR_UNSUPPORTED, "ecc_vertex_class_table: only 2D vertex classes");
+    for (int m = 0; m < 16; ++m) out[m] = ecc::vertex_class_2d(m);
+    return ECC_OK;
 }

@@ -21,7 +21,8 @@ ECC_U8, ECC_U16, ECC_F32 = 1, 2, 3
 EXPORTS = (
     "ecc_create", "ecc_destroy", "ecc_last_error", "ecc_status_string",
     "ecc_curves_compute", "ecc_curves_compute_batch", "ecc_batch_plan_tune",
-    "ecc_vertex_table", "ecc_validate_field", "ecc_profile_enable", "ecc_profile_read",
+    "ecc_vertex_table", "ecc_vertex_classes_compute", "ecc_vertex_class_table",
+    "ecc_validate_field", "ecc_profile_enable", "ecc_profile_read",
     "ecc_server_create", "ecc_server_submit", "ecc_server_poll", "ecc_server_drain",
     "ecc_server_destroy",
 )
@@ -81,6 +82,8 @@ def load(path: str = LIB_PATH):
                                      ctypes.c_int),
         "ecc_batch_plan_tune": ([vp, i32, ctypes.POINTER(Field), vp], ctypes.c_int),
         "ecc_vertex_table": ([i32, i32, ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
+        "ecc_vertex_classes_compute": ([vp, ctypes.POINTER(Field), vp, vp], ctypes.c_int),
+        "ecc_vertex_class_table": ([i32, ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
         "ecc_validate_field": ([ctypes.POINTER(Field), ctypes.POINTER(Curves)], ctypes.c_int),
         "ecc_profile_enable": ([vp, i32], ctypes.c_int),
         "ecc_profile_read": ([vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64), i32],
@@ -120,6 +123,17 @@ def vertex_table(ndim: int, connectivity: int = 0):
     buf = (ctypes.c_int32 * (n * 4))()
     check(lib.ecc_vertex_table(ndim, connectivity, buf))
     return [list(buf[4 * m:4 * m + 4]) for m in range(n)]
+
+
+def vertex_class_table(ndim: int = 2):
+    """Class (0..4, -1 empty) of each 2D vertex mask, as the library assigns it."""
+    lib = load()
+    buf = (ctypes.c_int32 * 16)()
+    check(lib.ecc_vertex_class_table(ndim, buf))
+    return list(buf)
+
+
+VERTEX_CLASSES_2D = ("one", "adjacent", "diagonal", "three", "four")
 
 
 # ----------------------------------------------------------------------------
@@ -239,6 +253,21 @@ class Context:
                 setattr(cv, c, out[c].data_ptr() if c in out else None)
         check(self._lib.ecc_curves_compute(self.handle, ctypes.byref(f), ctypes.byref(cv),
                                            _stream_ptr(stream)))
+        del keep
+        return out
+
+    def vertex_classes(self, field, n_levels: int, thresholds=None, stream=None, out=None):
+        """Counts of 2D lattice vertices per quadrant class and level: int64
+        device tensor [5, n_levels], rows in VERTEX_CLASSES_2D order (async on
+        `stream`).  `out` may supply the [5, n_levels] int64 tensor."""
+        torch = _torch()
+        f, keep = make_field(field, n_levels, thresholds, 0)
+        if out is None:
+            out = torch.empty((5, n_levels), dtype=torch.int64, device=field.device)
+        elif tuple(out.shape) != (5, n_levels) or out.dtype != torch.int64 or not out.is_contiguous():
+            raise ValueError("out must be a contiguous int64 tensor of shape (5, n_levels)")
+        check(self._lib.ecc_vertex_classes_compute(self.handle, ctypes.byref(f), out.data_ptr(),
+                                                   _stream_ptr(stream)))
         del keep
         return out
 
