@@ -133,6 +133,30 @@ ecc_status ecc_curves_compute(ecc_context ctx, const ecc_field *field, const ecc
                               void *stream);
 
 /*
+ * Curves of a field that lives in HOST memory, streamed through the device in
+ * slabs (the GPU counterpart of the paper's low-memory mode, Computational
+ * Results on memory scaling and the Conclusions): the field is cut along its
+ * slowest axis (rows in 2D, planes in 3D) into slabs that fit slab_bytes with
+ * one halo row or plane on each side; each slab is copied on an internal stream
+ * into one of two device buffers while the slab before it is histogrammed on
+ * `stream`, and every slab adds to the same per-workgroup partials.  The curves
+ * equal those of ecc_curves_compute on the same field.
+ *
+ * field:  as for ecc_curves_compute, except that data is a HOST pointer
+ *         (pageable or pinned), read during the call only.
+ * curves: HOST pointers, n_levels int64 each, NULL = channel not wanted.  In 3D
+ *         the perimeter (crease) channel must be NULL (ECC_ERR_UNSUPPORTED).
+ * slab_bytes: device bytes per slab buffer (two are allocated for the call and
+ *         freed before it returns); 0 = 256 MiB.  Must hold three rows (2D) or
+ *         planes (3D), else ECC_ERR_INVALID_ARG.
+ * Blocking: returns once the curves are written (synchronises `stream`).  The
+ * device memory used is two slab buffers plus the partials, whatever the
+ * field's size.
+ */
+ecc_status ecc_curves_compute_streamed(ecc_context ctx, const ecc_field *field, const ecc_curves *curves,
+                                       size_t slab_bytes, void *stream);
+
+/*
  * The same for n fields of any mix of shapes and dtypes in one persistent launch
  * (the paper's dispatch of many small images, Discussion of the microscopy case).
  * fields[i] and curves[i] follow the single-field contract.  The launch geometry

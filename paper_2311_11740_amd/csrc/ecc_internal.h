@@ -114,6 +114,11 @@ struct Launch3D {
     // z-marching kernel (no crease channel): its two per-pattern tables, else NULL
     const uint32_t *zm_tables;
     bool conn6;
+    // z-marching kernel only: the planes [z_lo, z_hi) whose voxels this launch
+    // emits (planes z_lo - 1 and z_hi are read when inside the field), and
+    // whether to add to the partials instead of overwriting them
+    int64_t z_lo, z_hi;
+    bool accumulate;
 };
 
 // ---- batched 2D launch ----------------------------------------------------------

@@ -1562,14 +1562,14 @@ static int launch_zm_t(const Launch3D &a, hipStream_t s) {
     const int W = a.hi - a.lo;
     const int64_t cols = zmarch_3d_columns(a.h, a.w);
     // bound the cells per workgroup between drains by splitting z
-    int64_t chunk = a.d;
+    int64_t chunk = a.z_hi - a.z_lo;
     while (chunk > 1 && max_wg_cells_3d(cols, chunk, a.grid) > kFlush3D) chunk = (chunk + 1) / 2;
     if (max_wg_cells_3d(cols, chunk, a.grid) > kFlush3D) return (int)hipErrorInvalidValue;
     const float cpass = (float)(a.lv.u0d + 1.5 - a.lo);
     const size_t lds = (size_t)(W + 2 + 64) * 8 + (kThr ? (size_t)(W + 3) * 4 : 0);
-    for (int64_t z0 = 0; z0 < a.d; z0 += chunk) {
-        const int64_t z1 = z0 + chunk < a.d ? z0 + chunk : a.d;
-        const bool acc = z0 > 0;
+    for (int64_t z0 = a.z_lo; z0 < a.z_hi; z0 += chunk) {
+        const int64_t z1 = z0 + chunk < a.z_hi ? z0 + chunk : a.z_hi;
+        const bool acc = a.accumulate || z0 > a.z_lo;
         hipLaunchKernelGGL((ecc3d_stream<T, LM, AL, MAXIMG, kZmTY>), dim3(a.grid), dim3(256), lds, s,
                            (const T *)a.data, a.d, a.h, a.w, a.lv, a.lo, a.hi, cpass, a.zm_tables, a.partial, z0,
                            z1, acc ? 1 : 0);

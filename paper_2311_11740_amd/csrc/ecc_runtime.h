@@ -90,6 +90,10 @@ ecc_status release_workspace(ecc_context ctx, void *stream);
 ecc_status grow(ecc_context ctx, DevBuf &b, size_t need, const char *what);
 ecc_status compute_one(ecc_context ctx, const ecc_field *f, const FieldInfo &fi, const ecc_curves *c, void *stream);
 int pick_grid(ecc_context ctx, int64_t n_tiles, size_t lds_per_wg);
+// workgroups per CU of the 2D stream kernel and of the 3D z-marching kernel
+// (ECC_WG_PER_CU, ECC_ZM_WG_PER_CU; defaults 4 and 2)
+int wg_per_cu_default();
+int zm_wg_per_cu();
 ecc_status merge_and_scan(ecc_context ctx, int grid, int nch, int L, int64_t *const outs[4], void *stream);
 void destroy_batch_state(ecc_context ctx);
 // batched 2D scheduling (ecc_batch.hip), shared with the serving loop

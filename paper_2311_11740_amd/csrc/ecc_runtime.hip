@@ -451,7 +451,7 @@ int pick_grid(ecc_context ctx, int64_t n_tiles, size_t lds_per_wg) {
 }
 
 // Workgroups per CU for the field-reading kernels (environment ECC_WG_PER_CU overrides).
-static int wg_per_cu_default() {
+int wg_per_cu_default() {
     static int v = [] {
         const char *e = std::getenv("ECC_WG_PER_CU");
         int x = e ? std::atoi(e) : 4;
@@ -461,7 +461,7 @@ static int wg_per_cu_default() {
 }
 
 // Workgroups per CU for the z-marching 3D kernel (environment ECC_ZM_WG_PER_CU overrides).
-static int zm_wg_per_cu() {
+int zm_wg_per_cu() {
     static int v = [] {
         const char *e = std::getenv("ECC_ZM_WG_PER_CU");
         int x = e ? std::atoi(e) : 2;
@@ -544,7 +544,7 @@ ecc_status compute_one(ecc_context ctx, const ecc_field *f, const FieldInfo &fi,
             s = prof_begin(ctx, stream, &slot);
             if (s != ECC_OK) return s;
             Launch3D a{data, fi.dtype, fi.d, fi.h, fi.w, lv, lo, hi, ctx->d_vtab3[k], partial, grid, crease,
-                       zmarch ? ctx->d_zm3[k] : nullptr, k == 1};
+                       zmarch ? ctx->d_zm3[k] : nullptr, k == 1, 0, fi.d, false};
             int e = launch_3d(a, stream);
             if (e) return hip_fail(e, "3D kernel launch");
             s = prof_end(ctx, stream, slot);

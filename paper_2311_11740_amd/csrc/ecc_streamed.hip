@@ -1,0 +1,175 @@
+// Fields in host memory, streamed through the device in slabs.
+//
+// The analogue of the paper's low-memory mode (Computational Results: memory
+// scaling; Conclusions): a field that lives in host memory (and may be larger
+// than device memory) is cut along its slowest axis into slabs of whole rows
+// (2D) or planes (3D).  Each slab is copied with one halo row or plane on each
+// side into one of two device buffers on a copy stream, while the slab before
+// it is histogrammed on the caller's stream; every slab adds to the same
+// per-workgroup partials, so the merge and scan run once at the end.  A cell
+// is counted by the slab that owns it, and its neighbours come from the halo,
+// so the curves are those of the whole field.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+
+#include "ecc_internal.h"
+#include "ecc_runtime.h"
+
+namespace ecc {
+
+namespace {
+
+struct StreamRes {
+    DevBuf buf[2];
+    DevBuf curves;
+    hipStream_t copy = nullptr;
+    hipEvent_t copied[2] = {nullptr, nullptr}, computed[2] = {nullptr, nullptr};
+    ~StreamRes() {
+        if (copy) hipStreamSynchronize(copy);
+        for (int k = 0; k < 2; ++k) {
+            if (copied[k]) hipEventDestroy(copied[k]);
+            if (computed[k]) hipEventDestroy(computed[k]);
+        }
+        if (copy) hipStreamDestroy(copy);
+        buf[0].release();
+        buf[1].release();
+        curves.release();
+    }
+};
+
+ecc_status stream_field(ecc_context ctx, const ecc_field *f, const FieldInfo &fi, const ecc_curves *c,
+                        size_t slab_bytes, void *stream) {
+    const bool is3 = fi.ndim == 3;
+    const int64_t unit_bytes = (is3 ? fi.h * fi.w : fi.w) * fi.elem_bytes;  // one row or plane
+    const int64_t n_units = is3 ? fi.d : fi.h;
+    if (slab_bytes == 0) slab_bytes = (size_t)256 << 20;
+    const int64_t per_slab = (int64_t)(slab_bytes / (size_t)unit_bytes) - 2;  // rows or planes owned
+    if (per_slab < 1)
+        return fail(ECC_ERR_INVALID_ARG, "slab_bytes must hold at least three rows (2D) or planes (3D)");
+    const int64_t R = std::min(per_slab, n_units);
+    const bool crease = is3 && c->perimeter != nullptr;
+    if (crease)
+        return fail(ECC_ERR_UNSUPPORTED, "streamed 3D fields: the crease (perimeter) channel is not available");
+    const int L = fi.L;
+    const int nch = is3 ? 4 : 3;
+    const int win = std::min(L, kMaxWindow);
+    const int k = is3 ? (fi.conn == 26 ? 0 : 1) : (fi.conn == 8 ? 0 : 1);
+    // one launch geometry for every slab (the partials of a workgroup add up)
+    int grid;
+    if (is3) {
+        const int64_t units = (int64_t)zmarch_3d_columns(fi.h, fi.w) * R;
+        grid = (int)std::min<int64_t>((int64_t)ctx->n_cu * zm_wg_per_cu(), std::max<int64_t>(1, (units + 63) / 64));
+        if (grid >= 8) grid -= grid % 8;
+        if (!zmarch_3d_fits(fi.h, fi.w, grid))
+            return fail(ECC_ERR_UNSUPPORTED, "streamed 3D fields: planes too large for the z-marching kernel");
+    } else {
+        const int vec = vec_2d(fi.dtype);
+        const int64_t strips = (fi.w + 62 * vec - 1) / (62 * vec);
+        grid = (int)std::min<int64_t>((int64_t)ctx->n_cu * wg_per_cu_default(),
+                                      std::max<int64_t>(1, (strips * R + 31) / 32));
+        if (grid >= 8) grid -= grid % 8;
+    }
+    LevelArgs lv;
+    ecc_status s = level_args(ctx, f, fi, stream, &lv);
+    if (s != ECC_OK) return s;
+    s = grow(ctx, ctx->ws.partial, (size_t)grid * nch * L * sizeof(int32_t), "partials");
+    if (s != ECC_OK) return s;
+    int32_t *partial = (int32_t *)ctx->ws.partial.ptr;
+
+    StreamRes r;
+    // slab + halo at offset kPad, with kPad bytes after it: the kernels' vector
+    // loads are clamped to the last whole vector of the field they are given
+    // (here: up to the end of the buffer's units), which for a slab of fewer
+    // cells than one vector starts up to 64 bytes before the slab
+    constexpr size_t kPad = 256;
+    const size_t buf_bytes = (size_t)(R + 2) * (size_t)unit_bytes + 2 * kPad;
+    for (int b = 0; b < 2; ++b) {
+        s = r.buf[b].ensure(buf_bytes, "slab buffer");
+        if (s != ECC_OK) return s;
+    }
+    s = r.curves.ensure((size_t)nch * L * sizeof(int64_t), "curves");
+    if (s != ECC_OK) return s;
+    int e = (int)hipStreamCreateWithFlags(&r.copy, hipStreamNonBlocking);
+    for (int b = 0; b < 2 && !e; ++b) {
+        e = (int)hipEventCreateWithFlags(&r.copied[b], hipEventDisableTiming);
+        if (!e) e = (int)hipEventCreateWithFlags(&r.computed[b], hipEventDisableTiming);
+    }
+    if (e) return hip_fail(e, "stream/event creation");
+    // the copy stream starts after the work already queued on the caller's stream
+    e = (int)hipEventRecord(r.computed[0], (hipStream_t)stream);
+    if (!e) e = (int)hipEventRecord(r.computed[1], (hipStream_t)stream);
+    if (e) return hip_fail(e, "hipEventRecord");
+
+    const char *host = (const char *)f->data;
+    int slab = 0;
+    for (int64_t a = 0; a < n_units; a += R, ++slab) {
+        const int64_t b = std::min(n_units, a + R);
+        const int64_t u0 = a > 0 ? a - 1 : 0, u1 = std::min(n_units, b + 1);  // units in the buffer
+        const int bi = slab & 1;
+        char *dev = (char *)r.buf[bi].ptr + kPad;
+        e = (int)hipStreamWaitEvent(r.copy, r.computed[bi], 0);
+        if (!e)
+            e = (int)hipMemcpyAsync(dev, host + u0 * unit_bytes, (size_t)(u1 - u0) * (size_t)unit_bytes,
+                                    hipMemcpyHostToDevice, r.copy);
+        if (!e) e = (int)hipEventRecord(r.copied[bi], r.copy);
+        if (!e) e = (int)hipStreamWaitEvent((hipStream_t)stream, r.copied[bi], 0);
+        if (e) return hip_fail(e, "slab copy");
+        // the buffer seen as the field's units [0, u1) (units below u0 are never read)
+        const void *data_v = dev - u0 * unit_bytes;
+        for (int lo = 0; lo < L; lo += win) {
+            const int hi = std::min(L, lo + win);
+            if (is3) {
+                Launch3D la{data_v, fi.dtype, u1, fi.h, fi.w, lv, lo, hi, ctx->d_vtab3[k], partial, grid, false,
+                            ctx->d_zm3[k], k == 1, a, b, slab > 0};
+                e = launch_3d(la, stream);
+            } else {
+                Launch2D la{data_v, fi.dtype, u1, fi.w, lv, lo, hi, ctx->d_delta2[k], partial, grid,
+                            a, b, slab > 0, false};
+                e = launch_2d(la, stream);
+            }
+            if (e) return hip_fail(e, "slab kernel launch");
+        }
+        e = (int)hipEventRecord(r.computed[bi], (hipStream_t)stream);
+        if (e) return hip_fail(e, "hipEventRecord");
+    }
+    int64_t *dc = (int64_t *)r.curves.ptr;
+    int64_t *host_out[4] = {c->ec, c->perimeter, c->area, is3 ? c->volume : nullptr};
+    int64_t *outs[4];
+    for (int ch = 0; ch < 4; ++ch) outs[ch] = host_out[ch] ? dc + (size_t)ch * L : nullptr;
+    s = merge_and_scan(ctx, grid, nch, L, outs, stream);
+    if (s != ECC_OK) return s;
+    for (int ch = 0; ch < 4; ++ch) {
+        if (!host_out[ch]) continue;
+        e = (int)hipMemcpyAsync(host_out[ch], outs[ch], (size_t)L * sizeof(int64_t), hipMemcpyDeviceToHost,
+                                (hipStream_t)stream);
+        if (e) return hip_fail(e, "curve copy");
+    }
+    e = (int)hipStreamSynchronize((hipStream_t)stream);
+    if (e) return hip_fail(e, "hipStreamSynchronize");
+    return ECC_OK;
+}
+
+}  // namespace
+
+}  // namespace ecc
+
+using namespace ecc;
+
+extern "C" ecc_status ecc_curves_compute_streamed(ecc_context ctx, const ecc_field *field,
+                                                  const ecc_curves *curves, size_t slab_bytes, void *stream) {
+    clear_error();
+    if (!ctx) return fail(ECC_ERR_INVALID_ARG, "context is NULL");
+    FieldInfo fi;
+    ecc_status s = validate_field(field, curves, &fi, true);
+    if (s != ECC_OK) return s;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    int e = (int)hipSetDevice(ctx->device);
+    if (e) return hip_fail(e, "hipSetDevice");
+    s = acquire_workspace(ctx, stream);
+    if (s != ECC_OK) return s;
+    s = stream_field(ctx, field, fi, curves, slab_bytes, stream);
+    ecc_status s2 = release_workspace(ctx, stream);
+    return s != ECC_OK ? s : s2;
+}

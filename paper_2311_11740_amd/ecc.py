@@ -20,7 +20,7 @@ ECC_U8, ECC_U16, ECC_F32 = 1, 2, 3
 # public C entry points (kept in step with include/ecc.h)
 EXPORTS = (
     "ecc_create", "ecc_destroy", "ecc_last_error", "ecc_status_string",
-    "ecc_curves_compute", "ecc_curves_compute_batch", "ecc_batch_plan_tune",
+    "ecc_curves_compute", "ecc_curves_compute_streamed", "ecc_curves_compute_batch", "ecc_batch_plan_tune",
     "ecc_vertex_table", "ecc_vertex_classes_compute", "ecc_vertex_class_table",
     "ecc_validate_field", "ecc_profile_enable", "ecc_profile_read",
     "ecc_server_create", "ecc_server_submit", "ecc_server_poll", "ecc_server_drain",
@@ -78,6 +78,8 @@ def load(path: str = LIB_PATH):
         "ecc_last_error": ([], ctypes.c_char_p),
         "ecc_status_string": ([ctypes.c_int], ctypes.c_char_p),
         "ecc_curves_compute": ([vp, ctypes.POINTER(Field), ctypes.POINTER(Curves), vp], ctypes.c_int),
+        "ecc_curves_compute_streamed": ([vp, ctypes.POINTER(Field), ctypes.POINTER(Curves), ctypes.c_size_t, vp],
+                                        ctypes.c_int),
         "ecc_curves_compute_batch": ([vp, i32, ctypes.POINTER(Field), ctypes.POINTER(Curves), vp],
                                      ctypes.c_int),
         "ecc_batch_plan_tune": ([vp, i32, ctypes.POINTER(Field), vp], ctypes.c_int),
@@ -254,6 +256,43 @@ class Context:
         check(self._lib.ecc_curves_compute(self.handle, ctypes.byref(f), ctypes.byref(cv),
                                            _stream_ptr(stream)))
         del keep
+        return out
+
+    def compute_streamed(self, field, n_levels: int, thresholds=None, connectivity: int = 0,
+                         channels: Sequence[str] | None = None, slab_bytes: int = 0, stream=None):
+        """Curves of a field in host memory (numpy array), streamed through the
+        device in slabs of at most `slab_bytes` (0: the library's default).
+        Blocking; returns dict channel -> int64 numpy array."""
+        import numpy as np
+        a = np.ascontiguousarray(field)
+        if a.ndim not in (2, 3):
+            raise ValueError("field must be 2D or 3D")
+        codes = {np.dtype(np.uint8): ECC_U8, np.dtype(np.uint16): ECC_U16, np.dtype(np.float32): ECC_F32}
+        if a.dtype not in codes:
+            raise TypeError(f"unsupported field dtype {a.dtype}")
+        f = Field()
+        f.ndim = a.ndim
+        f.dtype = codes[a.dtype]
+        for k in range(3):
+            f.shape[k] = int(a.shape[k]) if k < a.ndim else 0
+        f.data = a.ctypes.data
+        f.n_levels = int(n_levels)
+        f.connectivity = int(connectivity or 0)
+        keep = None
+        if thresholds is not None:
+            keep = np.ascontiguousarray(np.asarray(thresholds, dtype=np.float32))
+            if keep.size != n_levels:
+                raise ValueError("thresholds must have n_levels entries")
+            f.thresholds = keep.ctypes.data
+        allowed = CHANNELS_2D if a.ndim == 2 else ("ec", "area", "volume")
+        channels = allowed if channels is None else tuple(channels)
+        out = {c: np.zeros(n_levels, dtype=np.int64) for c in channels}
+        cv = Curves()
+        for c in ("ec", "perimeter", "area", "volume"):
+            setattr(cv, c, out[c].ctypes.data if c in out else None)
+        check(self._lib.ecc_curves_compute_streamed(self.handle, ctypes.byref(f), ctypes.byref(cv),
+                                                    int(slab_bytes), _stream_ptr(stream)))
+        del keep, a
         return out
 
     def vertex_classes(self, field, n_levels: int, thresholds=None, stream=None, out=None):

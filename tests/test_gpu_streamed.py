@@ -1,0 +1,117 @@
+"""Fields in host memory streamed through the device in slabs (ecc_curves_compute_streamed).
+
+* Curves equal the oracle's bit for bit with slabs of a few rows or planes
+  (many slabs, halos at every seam), in 2D and 3D, every level mode, both
+  connectivities, more levels than one pass holds.
+* Slabs smaller than one vector load (a one-column field, three rows a slab).
+* On a large field the streamed curves equal the device-resident call's.
+* Errors: a slab that cannot hold three rows; the 3D crease channel.
+"""
+from __future__ import annotations
+
+import os
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+NT = min(16, os.cpu_count() or 1)
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2311_11740_amd import ecc
+    c = ecc.Context(0)
+    yield c
+    c.close()
+
+
+def unit_bytes(a):
+    return (a.shape[-1] if a.ndim == 2 else a.shape[-1] * a.shape[-2]) * a.dtype.itemsize
+
+
+def compare(ctx, a, L, thr=None, conn=0, units=3, tag=""):
+    import oracle
+    slab = (units + 2) * unit_bytes(a)
+    print(f"[case] streamed {tag} shape={a.shape} dtype={a.dtype} L={L} conn={conn} units/slab={units}",
+          flush=True)
+    got = ctx.compute_streamed(a, L, thresholds=thr, connectivity=conn, slab_bytes=slab)
+    c = conn or (8 if a.ndim == 2 else 26)
+    ref = oracle.o2_curves(a, L, thresholds=thr, connectivity=c, channels=tuple(got), n_threads=NT)
+    for k in got:
+        assert np.array_equal(got[k], ref[k]), f"{tag}: channel {k}"
+
+
+@pytest.mark.parametrize("conn", [8, 4])
+def test_streamed_2d_u8(ctx, conn):
+    rng = np.random.default_rng(40 + conn)
+    compare(ctx, rng.integers(0, 256, size=(1021, 769)).astype(np.uint8), 256, conn=conn, units=5, tag="u8")
+
+
+def test_streamed_2d_u16_multipass(ctx):
+    rng = np.random.default_rng(41)
+    compare(ctx, rng.integers(0, 6000, size=(257, 301)).astype(np.uint16), 5000, units=7, tag="u16 5000 levels")
+
+
+def test_streamed_2d_f32(ctx):
+    from paper_2311_11740_amd import synth
+    z = synth.grf((700, 513), 4.0, 42)
+    compare(ctx, z, 300, synth.linspace_thresholds(-3, 3, 300), units=64, tag="f32 affine")
+    rng = np.random.default_rng(43)
+    x = rng.normal(size=(211, 333)).astype(np.float32)
+    x[rng.random(x.shape) < 0.05] = np.nan
+    thr = np.sort(rng.normal(size=97)).astype(np.float32)
+    compare(ctx, x, 97, thr, units=4, tag="f32 irregular")
+
+
+@pytest.mark.parametrize("shape", [(1, 1), (1, 300), (300, 1), (5, 3)])
+def test_streamed_2d_small(ctx, shape):
+    rng = np.random.default_rng(44)
+    compare(ctx, rng.integers(0, 50, size=shape).astype(np.uint8), 50, units=3, tag="small")
+
+
+@pytest.mark.parametrize("conn", [26, 6])
+def test_streamed_3d(ctx, conn):
+    rng = np.random.default_rng(45 + conn)
+    a = rng.integers(0, 300, size=(30, 41, 77)).astype(np.uint16)
+    import oracle
+    for units in (1, 3, 30):
+        slab = (units + 2) * unit_bytes(a)
+        print(f"[case] streamed 3D conn={conn} planes/slab={units}", flush=True)
+        got = ctx.compute_streamed(a, 256, connectivity=conn, slab_bytes=slab)
+        ref = oracle.o2_curves(a, 256, connectivity=conn, channels=tuple(got), n_threads=NT)
+        for k in got:
+            assert np.array_equal(got[k], ref[k]), (conn, units, k)
+
+
+def test_streamed_3d_f32(ctx):
+    from paper_2311_11740_amd import synth
+    z = synth.grf((40, 64, 70), 3.0, 46)
+    compare(ctx, z, 200, synth.linspace_thresholds(-3, 3, 200), units=6, tag="3D f32")
+
+
+def test_streamed_equals_device_large(ctx):
+    import torch
+    from paper_2311_11740_amd import synth
+    print("[case] streamed vs device 4096x3000 f32, 16 MiB slabs", flush=True)
+    z = synth.grf((4096, 3000), 8.0, 47)
+    thr = synth.linspace_thresholds(-4, 4, 1024)
+    got = ctx.compute_streamed(z, 1024, thresholds=thr, slab_bytes=16 << 20)
+    dev = ctx.compute(torch.from_numpy(z).cuda(), 1024, thresholds=thr)
+    for k in got:
+        assert np.array_equal(got[k], dev[k].cpu().numpy()), k
+
+
+def test_streamed_errors(ctx):
+    from paper_2311_11740_amd import ecc
+    a = np.zeros((10, 100), np.uint8)
+    with pytest.raises(ecc.EccError) as ei:
+        ctx.compute_streamed(a, 16, slab_bytes=250)
+    assert ei.value.status == ecc.ECC_ERR_INVALID_ARG
+    v = np.zeros((4, 5, 6), np.uint8)
+    with pytest.raises(ecc.EccError) as ei:
+        ctx.compute_streamed(v, 16, channels=("ec", "perimeter"))
+    assert ei.value.status == ecc.ECC_ERR_UNSUPPORTED
