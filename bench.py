@@ -198,6 +198,55 @@ def measure_vertex_classes(ctx, spec, steps, warmup, copies, curves):
                 weightings_equal_curves=bool(ok))
 
 
+def measure_streamed(ctx, spec, curves, steps=3, slab_mib=64):
+    """The main field from host memory through ecc_curves_compute_streamed
+    (slabs of slab_mib MiB, copies overlapped with the slab kernels), from
+    pageable and from pinned host memory, against uploading the whole field
+    and then computing.  Host-to-device copies are inside every time here."""
+    import numpy as np
+    import torch
+    a = np.ascontiguousarray(spec.data)
+    pinned_t = torch.empty(a.shape, dtype=torch.from_numpy(a[:1]).dtype, pin_memory=True)
+    pinned = pinned_t.numpy()
+    pinned[...] = a
+    res = {"workload": spec.meta["name"], "slab_mib": slab_mib, "field_bytes": int(a.nbytes)}
+    ok = True
+    for name, host in (("pageable", a), ("pinned", pinned)):
+        out = None
+        ctx.compute_streamed(host, spec.n_levels, thresholds=spec.thresholds, connectivity=spec.connectivity,
+                             slab_bytes=slab_mib << 20)
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            out = ctx.compute_streamed(host, spec.n_levels, thresholds=spec.thresholds,
+                                       connectivity=spec.connectivity, slab_bytes=slab_mib << 20)
+        ms = (time.perf_counter() - t0) * 1e3 / steps
+        ok = ok and all(np.array_equal(out[k], curves[k]) for k in curves)
+        res[name] = dict(ms_per_call=round(ms, 2), gvox_s=round(a.size / ms / 1e6, 2),
+                         host_gb_s=round(a.nbytes / ms / 1e6, 2))
+    # the copy alone: the whole field from pinned memory in one transfer
+    dst = torch.empty(pinned_t.shape, dtype=pinned_t.dtype, device="cuda")
+    dst.copy_(pinned_t, non_blocking=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        dst.copy_(pinned_t, non_blocking=True)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    res["pinned_copy_only"] = dict(ms_per_call=round(ms, 2), host_gb_s=round(a.nbytes / ms / 1e6, 2))
+    del dst
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        dev = torch.from_numpy(a).cuda()
+        c = ctx.compute(dev, spec.n_levels, thresholds=spec.thresholds, connectivity=spec.connectivity)
+        {k: v.cpu() for k, v in c.items()}
+        del dev
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    res["upload_then_compute_pageable"] = dict(ms_per_call=round(ms, 2), gvox_s=round(a.size / ms / 1e6, 2))
+    res["equal_to_device_curves"] = bool(ok)
+    del pinned, pinned_t
+    return res
+
+
 def timed_calls(fn, steps):
     """(ms per call on the GPU clock, ms per call on the host clock) of `steps` calls."""
     import torch
@@ -427,6 +476,8 @@ def main():
     ap.add_argument("--no-secondary", action="store_true", help="skip the 3D secondary measurement")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched vs per-field comparison")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving comparison")
+    ap.add_argument("--no-streamed", action="store_true",
+                    help="skip the host-resident (streamed in slabs) measurement")
     ap.add_argument("--no-vertex-classes", action="store_true",
                     help="skip the contribution-map (vertex class counts) measurement")
     ap.add_argument("--no-paper-workloads", action="store_true",
@@ -498,6 +549,10 @@ def main():
         line["vertex_classes"] = measure_vertex_classes(ctx, spec, args.steps, args.warmup, args.copies,
                                                         main_r["curves"])
         print(f"[bench] vertex classes: {line['vertex_classes']['gvox_s']} Gvox/s", file=sys.stderr, flush=True)
+    if not args.no_streamed:
+        line["streamed_from_host"] = measure_streamed(ctx, spec, main_r["curves"])
+        print(f"[bench] streamed from host: {line['streamed_from_host']['pinned']['gvox_s']} Gvox/s (pinned)",
+              file=sys.stderr, flush=True)
     del main_r
     if sec_spec is not None:
         sec = measure(ctx, sec_spec, max(3, args.steps // 2), 2, 2, with_cpu=False)
