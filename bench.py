@@ -198,6 +198,35 @@ def measure_vertex_classes(ctx, spec, steps, warmup, copies, curves):
                 weightings_equal_curves=bool(ok))
 
 
+def measure_vertex_classes_3d(ctx, spec, curves, steps=3):
+    """The 3D contribution map (21 octant classes) of a volume: per-call time
+    with the volume in HBM, and the check that weighting the class counts by
+    the library's per-vertex table (Table 2, x8) gives the EC (26-C), surface
+    and volume curves of the curves call."""
+    import numpy as np
+    import torch
+    from paper_2311_11740_amd import ecc
+    dev = torch.from_numpy(spec.data).cuda()
+    out = torch.empty((21, spec.n_levels), dtype=torch.int64, device="cuda")
+
+    def call(stream):
+        ctx.vertex_classes(dev, spec.n_levels, thresholds=spec.thresholds, out=out, stream=stream)
+
+    call(torch.cuda.current_stream())
+    ms, _ = timed_calls(call, steps)
+    n = out.cpu().numpy()
+    vt = np.array(ecc.vertex_table(3, spec.connectivity), dtype=np.int64)  # [256][4] x8 EC, x2 crease, x4 surface, x8 vol
+    cls = np.array(ecc.vertex_class_table(3))
+    rep = {c: int(np.nonzero(cls == c)[0][0]) for c in range(21)}
+    w = np.array([vt[rep[c]] for c in range(21)])  # per-class contributions
+    ok = (np.array_equal((w[:, 0:1] * n).sum(0), 8 * curves["ec"]) and
+          np.array_equal((w[:, 2:3] * n).sum(0), 4 * curves["area"]) and
+          np.array_equal((w[:, 3:4] * n).sum(0), 8 * curves["volume"]))
+    cells = spec.data.size
+    return dict(workload=spec.meta["name"], classes=21, ms_per_call=round(ms, 3),
+                gvox_s=round(cells / ms / 1e6, 2), weightings_equal_curves=bool(ok))
+
+
 def measure_streamed(ctx, spec, curves, steps=3, slab_mib=64):
     """The main field from host memory through ecc_curves_compute_streamed
     (slabs of slab_mib MiB, copies overlapped with the slab kernels), from
@@ -558,6 +587,8 @@ def main():
         sec = measure(ctx, sec_spec, max(3, args.steps // 2), 2, 2, with_cpu=False)
         line["secondary"] = {k: sec[k] for k in ("workload", "gvox_s", "ms_per_step", "hbm_frac_step",
                                                   "roofline")}
+        if not args.no_vertex_classes:
+            line["secondary"]["vertex_classes"] = measure_vertex_classes_3d(ctx, sec_spec, sec["curves"])
         print(f"[bench] {sec_spec.meta['name']}: {sec['gvox_s']} Gvox/s", file=sys.stderr, flush=True)
         del sec
     if batch_specs is not None:

@@ -186,34 +186,41 @@ ecc_status ecc_batch_plan_tune(ecc_context ctx, int32_t n, const ecc_field *fiel
 ecc_status ecc_vertex_table(int32_t ndim, int32_t connectivity, int32_t *out);
 
 /*
- * Vertex class counts of a 2D field per level (the vertex-contribution map
- * behind Table 1 and Eq. 4, the quantity the curves are weighted sums of).
- * The lattice vertices are the (h+1) x (w+1) corners of the pixels; at level l
- * the quadrant of a vertex (its up to four pixels with level <= l, pixels
- * outside the field never in) falls in one of the classes of Table 1:
- *   counts[0*L + l]  one pixel
- *   counts[1*L + l]  two pixels sharing an edge
- *   counts[2*L + l]  two pixels on a diagonal
- *   counts[3*L + l]  three pixels
- *   counts[4*L + l]  four pixels
- * (empty quadrants are the rest).  Any per-vertex descriptor of Table 1 at
- * either connectivity is a fixed weighting of these counts, e.g.
- * 4*EC(8-C) = one - 2*diagonal - three, 4*EC(4-C) = one + 2*diagonal - three,
- * 2*perimeter = 2*one + 2*adjacent + 4*diagonal + 2*three.
+ * Vertex class counts per level (the vertex-contribution map behind Table 1,
+ * Table 2 and Eq. 4, the quantity the curves are weighted sums of).
+ * The lattice vertices are the corners of the cells ((h+1) x (w+1) in 2D,
+ * (d+1) x (h+1) x (w+1) in 3D); at level l the neighbourhood of a vertex (its
+ * 2^n cells with level <= l, cells outside the field never in) falls in one
+ * class; empty neighbourhoods are not counted.
+ *   2D, 5 classes (the rows of Table 1):
+ *     counts[0*L + l]  one pixel
+ *     counts[1*L + l]  two pixels sharing an edge
+ *     counts[2*L + l]  two pixels on a diagonal
+ *     counts[3*L + l]  three pixels
+ *     counts[4*L + l]  four pixels
+ *   Any per-vertex descriptor of Table 1 at either connectivity is a fixed
+ *   weighting of these, e.g. 4*EC(8-C) = one - 2*diagonal - three,
+ *   4*EC(4-C) = one + 2*diagonal - three,
+ *   2*perimeter = 2*one + 2*adjacent + 4*diagonal + 2*three.
+ *   3D, 21 classes (the non-empty rows of Table 2): the orbits of the 2x2x2
+ *   octant masks under the cube's 48 symmetries, numbered by (number of
+ *   voxels, smallest mask in the orbit); ecc_vertex_class_table gives the
+ *   class of every mask.  counts[c*L + l] as in 2D.
  *
- * field: as for ecc_curves_compute; ndim must be 2 (3D: ECC_ERR_UNSUPPORTED);
- *        the connectivity is checked but does not matter.
- * counts: DEVICE pointer, caller-owned, 5 * n_levels int64, class-major as
- *        above; written only by the queued work.
+ * field: as for ecc_curves_compute; the connectivity is checked but does not
+ *        matter.
+ * counts: DEVICE pointer, caller-owned, 5 * n_levels (2D) or 21 * n_levels (3D)
+ *        int64, class-major as above; written only by the queued work.
  * Asynchronous on `stream`; same validation and error behaviour as
  * ecc_curves_compute (nothing is queued on error).
  */
 ecc_status ecc_vertex_classes_compute(ecc_context ctx, const ecc_field *field, int64_t *counts, void *stream);
 
 /*
- * Class (0..4 as for ecc_vertex_classes_compute, -1 for the empty mask) of each
- * of the 16 masks of a 2D vertex, mask bits as for ecc_vertex_table (for tests).
- * ndim must be 2 (3D: ECC_ERR_UNSUPPORTED).  out: HOST, 16 int32.
+ * Class of each vertex mask as ecc_vertex_classes_compute counts it, -1 for
+ * the empty mask (for tests).  ndim 2: 16 masks, bits as for ecc_vertex_table,
+ * classes 0..4; ndim 3: 256 masks, bit dx + 2*dy + 4*dz, classes 0..20.
+ * out: HOST, 16 or 256 int32.
  */
 ecc_status ecc_vertex_class_table(int32_t ndim, int32_t *out);
 

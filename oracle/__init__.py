@@ -10,9 +10,10 @@ never imports this package):
   enters the closure of the active cells, histogrammed by dimension and
   summed over levels; O(N + levels).
 
-* ``vertex_classes_2d`` / ``vertex_classes_per_level``
-  (:mod:`oracle.vertex_classes`): counts of 2D lattice vertices per quadrant
-  class of Table 1 at every level (the vertex-contribution map).
+* ``vertex_classes_2d`` / ``vertex_classes_per_level`` and the 3D pair
+  ``vertex_classes_3d`` / ``vertex_classes_3d_per_level``
+  (:mod:`oracle.vertex_classes`): counts of lattice vertices per class of
+  Table 1 (2D) or Table 2 (3D) at every level (the vertex-contribution map).
 
 Only ``tests/``, ``__graft_entry__.smoke()`` and ``bench.py``'s cpu_baseline
 leg may import this package.
@@ -26,7 +27,8 @@ import subprocess
 import numpy as np
 
 from .ec_oracle import curves_per_level as o1_curves  # noqa: F401
-from .vertex_classes import vertex_classes_2d, vertex_classes_per_level  # noqa: F401
+from .vertex_classes import (class_counts, vertex_classes_2d, vertex_classes_3d,  # noqa: F401
+                             vertex_classes_3d_per_level, vertex_classes_per_level)
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "ec_oracle_o2.c")

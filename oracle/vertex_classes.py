@@ -1,4 +1,4 @@
-"""Oracle for the 2D vertex class counts per level (TEST INFRASTRUCTURE ONLY).
+"""Oracle for the vertex class counts per level (TEST INFRASTRUCTURE ONLY).
 
 Nothing in the product imports this module; only ``tests/``,
 ``__graft_entry__.smoke()`` and ``bench.py``'s checks may call it.  It shares
@@ -28,6 +28,14 @@ Two implementations of the same definition:
 * ``vertex_classes_2d``: each vertex's quadrant only changes at the levels of
   its four pixels, so each vertex adds +1 to its new class and -1 to its old
   class at each of those levels; the counts are the running sums.  O(N + L).
+
+3D (Table 2): the vertex (k, i, j) is the corner of the up to eight voxels
+(k-1..k, i-1..i, j-1..j), its octant mask has bit dx + 2 dy + 4 dz for the
+voxel at offset (dz, dy, dx) from (k-1, i-1, j-1), and its class is the orbit
+of that mask under the 48 symmetries of the cube (Table 2 lists one row per
+orbit).  The 21 non-empty orbits are numbered by (number of voxels, smallest
+mask in the orbit).  ``vertex_classes_3d`` and ``vertex_classes_3d_per_level``
+are the two forms above, one dimension up.
 """
 from __future__ import annotations
 
@@ -114,3 +122,103 @@ def vertex_classes_2d(field, n_levels: int, thresholds=None) -> np.ndarray:
         has_old = old_c >= 0
         np.add.at(hist, (old_c[has_old], lv[has_old]), -1)
     return np.cumsum(hist[:, :L], axis=1)
+
+
+# --------------------------------------------------------------------------
+# 3D
+# --------------------------------------------------------------------------
+def _cube_symmetries():
+    """The 48 maps of octant bit positions: axis permutations with reflections."""
+    import itertools
+    maps = []
+    for perm in itertools.permutations(range(3)):
+        for flips in itertools.product((0, 1), repeat=3):
+            m = []
+            for b in range(8):
+                c = (b & 1, b >> 1 & 1, b >> 2 & 1)
+                c2 = [c[perm[a]] ^ flips[a] for a in range(3)]
+                m.append(c2[0] + 2 * c2[1] + 4 * c2[2])
+            maps.append(m)
+    return maps
+
+
+def _octant_classes():
+    syms = _cube_symmetries()
+    smallest = {}
+    for mask in range(256):
+        smallest[mask] = min(sum(1 << m[b] for b in range(8) if mask >> b & 1) for m in syms)
+    reps = sorted({v for k, v in smallest.items() if k}, key=lambda r: (bin(r).count("1"), r))
+    table = np.full(256, -1, dtype=np.int64)
+    for mask in range(1, 256):
+        table[mask] = reps.index(smallest[mask])
+    return table
+
+
+_CLASS_OF_OCTANT = _octant_classes()
+N_CLASSES_3D = 21
+
+
+def octant_class(mask: int) -> int:
+    """Class (0..20) of a 3D octant mask, -1 when empty."""
+    return int(_CLASS_OF_OCTANT[mask])
+
+
+def _octant_masks(b: np.ndarray) -> np.ndarray:
+    p = np.pad(b.astype(np.int64), 1, mode="constant", constant_values=0)
+    m = np.zeros(tuple(s - 1 for s in p.shape), dtype=np.int64)
+    for dz in (0, 1):
+        for dy in (0, 1):
+            for dx in (0, 1):
+                sl = p[dz:p.shape[0] - 1 + dz, dy:p.shape[1] - 1 + dy, dx:p.shape[2] - 1 + dx]
+                m |= sl << (dx + 2 * dy + 4 * dz)
+    return m
+
+
+def vertex_classes_3d_per_level(field, n_levels: int, thresholds=None) -> np.ndarray:
+    """[21, n_levels] int64: vertices per octant class at each level, by
+    binarising at every level and classifying every octant."""
+    field = np.asarray(field)
+    if field.ndim != 3:
+        raise ValueError("3D field expected")
+    out = np.zeros((N_CLASSES_3D, n_levels), dtype=np.int64)
+    for lvl in range(n_levels):
+        cls = _CLASS_OF_OCTANT[_octant_masks(binarise(field, lvl, thresholds))]
+        cnt = np.bincount(cls[cls >= 0].ravel(), minlength=N_CLASSES_3D)
+        out[:, lvl] = cnt
+    return out
+
+
+def vertex_classes_3d(field, n_levels: int, thresholds=None) -> np.ndarray:
+    """[21, n_levels] int64 class counts from the per-vertex class changes."""
+    field = np.asarray(field)
+    if field.ndim != 3:
+        raise ValueError("3D field expected")
+    L = int(n_levels)
+    lam = np.pad(level_index(field, L, thresholds), 1, mode="constant", constant_values=L)
+    D, H, W = lam.shape
+    q = []
+    for dz in (0, 1):
+        for dy in (0, 1):
+            for dx in (0, 1):  # appended in bit order dx + 2dy + 4dz
+                q.append(lam[dz:D - 1 + dz, dy:H - 1 + dy, dx:W - 1 + dx].ravel())
+    hist = np.zeros((N_CLASSES_3D, L + 1), dtype=np.int64)
+    for k in range(8):
+        at = q[k]
+        mask = sum(((q[b] <= at).astype(np.int64) << b) for b in range(8))
+        before = sum(((q[b] < at).astype(np.int64) << b) for b in range(8))
+        first = np.ones_like(at, dtype=bool)
+        for b in range(k):
+            first &= q[b] != at
+        sel = first & (at < L)
+        new_c, old_c, lv = _CLASS_OF_OCTANT[mask[sel]], _CLASS_OF_OCTANT[before[sel]], at[sel]
+        np.add.at(hist, (new_c, lv), 1)
+        has_old = old_c >= 0
+        np.add.at(hist, (old_c[has_old], lv[has_old]), -1)
+    return np.cumsum(hist[:, :L], axis=1)
+
+
+def class_counts(field, n_levels: int, thresholds=None) -> np.ndarray:
+    """Class counts of a 2D ([5, L]) or 3D ([21, L]) field."""
+    field = np.asarray(field)
+    return (vertex_classes_2d if field.ndim == 2 else vertex_classes_3d)(field, n_levels, thresholds)
+

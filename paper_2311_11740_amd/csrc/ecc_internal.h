@@ -23,6 +23,11 @@ int vertex_class_2d(int mask);
 // per-cell change of the five class counts when the pixel enters, by the
 // "entered before" pattern of its 8 neighbours (bit k = neighbour k)
 void class_delta_table_2d(int32_t delta[256][5]);
+// class of a 3D octant mask (bit dx + 2dy + 4dz): -1 empty, else 0..20, the
+// orbits under the cube's 48 symmetries ordered by (voxels, smallest mask)
+int octant_class_3d(int mask);
+constexpr int kNumClasses3D = 21;
+constexpr int kClsWindow3D = 512;  // levels per pass of the 3D class-count kernel
 // The kernels index per-cell tables by a permuted pattern: index bit i (i < 4)
 // is neighbour 2i and bit 4+i neighbour 2i+1 of kNbr2.  Returns the kNbr2-order
 // pattern of kernel index n.
@@ -119,6 +124,9 @@ struct Launch3D {
     // whether to add to the partials instead of overwriting them
     int64_t z_lo, z_hi;
     bool accumulate;
+    // vertex class counts (tile kernel): vtab holds the class of each octant
+    // mask and partial is [kNumClasses3D][L][grid]
+    bool classes;
 };
 
 // ---- batched 2D launch ----------------------------------------------------------

@@ -182,6 +182,13 @@ extern "C" ecc_status ecc_create(int device, ecc_context *out) {
             ecc_destroy(ctx);
             return s;
         }
+        int64_t c3[256];  // class of each 3D octant mask, -1 for empty
+        for (int m = 0; m < 256; ++m) c3[m] = octant_class_3d(m);
+        s = upload((void **)&ctx->d_cls3, c3, sizeof(c3));
+        if (s != ECC_OK) {
+            ecc_destroy(ctx);
+            return s;
+        }
     }
     e = (int)hipEventCreateWithFlags(&ctx->ws_event, hipEventDisableTiming);
     if (e) {
@@ -219,6 +226,7 @@ extern "C" ecc_status ecc_destroy(ecc_context ctx) {
         if (ctx->d_zm3[k]) hipFree(ctx->d_zm3[k]);
     }
     if (ctx->d_cls2) hipFree(ctx->d_cls2);
+    if (ctx->d_cls3) hipFree(ctx->d_cls3);
     for (auto *t : ctx->thr_cache) free_thresholds(t);
     ctx->thr_cache.clear();
     for (auto &pe : ctx->prof_events) {
@@ -544,7 +552,7 @@ ecc_status compute_one(ecc_context ctx, const ecc_field *f, const FieldInfo &fi,
             s = prof_begin(ctx, stream, &slot);
             if (s != ECC_OK) return s;
             Launch3D a{data, fi.dtype, fi.d, fi.h, fi.w, lv, lo, hi, ctx->d_vtab3[k], partial, grid, crease,
-                       zmarch ? ctx->d_zm3[k] : nullptr, k == 1, 0, fi.d, false};
+                       zmarch ? ctx->d_zm3[k] : nullptr, k == 1, 0, fi.d, false, false};
             int e = launch_3d(a, stream);
             if (e) return hip_fail(e, "3D kernel launch");
             s = prof_end(ctx, stream, slot);
@@ -557,8 +565,56 @@ ecc_status compute_one(ecc_context ctx, const ecc_field *f, const FieldInfo &fi,
 
 // Class counts of a 2D field: the single-field 2D path with the class-count
 // bins (five channels), merged as channels 0-2 and 3-4.
+static ecc_status merge_classes(ecc_context ctx, int grid, int nch, int L, int64_t *counts, void *stream) {
+    ecc_status s = grow(ctx, ctx->ws.totals, (size_t)3 * L * sizeof(int64_t), "totals");
+    if (s != ECC_OK) return s;
+    const int32_t *partial = (const int32_t *)ctx->ws.partial.ptr;
+    for (int c0 = 0; c0 < nch; c0 += 3) {  // the merge kernel scans up to three channels at once
+        int64_t *outs[4] = {nullptr, nullptr, nullptr, nullptr};
+        for (int j = 0; j < 3 && c0 + j < nch; ++j) outs[j] = counts + (int64_t)(c0 + j) * L;
+        const int n = std::min(3, nch - c0);
+        int e = launch_merge(partial + (size_t)c0 * L * grid, grid, n, L, outs, (int64_t *)ctx->ws.totals.ptr,
+                             (unsigned *)ctx->d_counter, stream);
+        if (e) return hip_fail(e, "merge kernel launch");
+    }
+    return ECC_OK;
+}
+
+// Class counts of a 3D field: the tile kernel in class-count mode, passes of
+// kClsWindow3D levels, one workgroup per CU (the class bins take
+// kNumClasses3D x 4 bytes per level of LDS), then the merges.
+static ecc_status compute_classes_3d(ecc_context ctx, const ecc_field *f, const FieldInfo &fi, int64_t *counts,
+                                     void *stream) {
+    LevelArgs lv;
+    ecc_status s = level_args(ctx, f, fi, stream, &lv);
+    if (s != ECC_OK) return s;
+    const int L = fi.L, nch = kNumClasses3D;
+    const int win = std::min(L, kClsWindow3D);
+    const int64_t n_tiles = ((fi.w + kTile3DX - 1) / kTile3DX) * ((fi.h + kTile3DY - 1) / kTile3DY) *
+                            ((fi.d + kTile3DZ - 1) / kTile3DZ);
+    int grid = (int)std::min<int64_t>(ctx->n_cu, n_tiles);
+    if (grid < 1) grid = 1;
+    s = grow(ctx, ctx->ws.partial, (size_t)grid * nch * L * sizeof(int32_t), "partials");
+    if (s != ECC_OK) return s;
+    int32_t *partial = (int32_t *)ctx->ws.partial.ptr;
+    for (int lo = 0; lo < L; lo += win) {
+        const int hi = std::min(L, lo + win);
+        int slot = -1;
+        s = prof_begin(ctx, stream, &slot);
+        if (s != ECC_OK) return s;
+        Launch3D a{f->data, fi.dtype, fi.d, fi.h, fi.w, lv, lo, hi, ctx->d_cls3, partial, grid, false,
+                   nullptr, false, 0, fi.d, false, true};
+        int e = launch_3d(a, stream);
+        if (e) return hip_fail(e, "3D class-count kernel launch");
+        s = prof_end(ctx, stream, slot);
+        if (s != ECC_OK) return s;
+    }
+    return merge_classes(ctx, grid, nch, L, counts, stream);
+}
+
 static ecc_status compute_classes(ecc_context ctx, const ecc_field *f, const FieldInfo &fi, int64_t *counts,
                                   void *stream) {
+    if (fi.ndim == 3) return compute_classes_3d(ctx, f, fi, counts, stream);
     LevelArgs lv;
     ecc_status s = level_args(ctx, f, fi, stream, &lv);
     if (s != ECC_OK) return s;
@@ -590,17 +646,7 @@ static ecc_status compute_classes(ecc_context ctx, const ecc_field *f, const Fie
         s = prof_end(ctx, stream, slot);
         if (s != ECC_OK) return s;
     }
-    s = grow(ctx, ctx->ws.totals, (size_t)3 * L * sizeof(int64_t), "totals");
-    if (s != ECC_OK) return s;
-    int64_t *const outs_a[4] = {counts, counts + L, counts + 2 * (int64_t)L, nullptr};
-    int64_t *const outs_b[4] = {counts + 3 * (int64_t)L, counts + 4 * (int64_t)L, nullptr, nullptr};
-    int e = launch_merge(partial, grid, 3, L, outs_a, (int64_t *)ctx->ws.totals.ptr, (unsigned *)ctx->d_counter,
-                         stream);
-    if (!e)
-        e = launch_merge(partial + (size_t)3 * L * grid, grid, 2, L, outs_b, (int64_t *)ctx->ws.totals.ptr,
-                         (unsigned *)ctx->d_counter, stream);
-    if (e) return hip_fail(e, "merge kernel launch");
-    return ECC_OK;
+    return merge_classes(ctx, grid, nch, L, counts, stream);
 }
 
 }  // namespace ecc
@@ -614,7 +660,6 @@ extern "C" ecc_status ecc_vertex_classes_compute(ecc_context ctx, const ecc_fiel
     const ecc_curves probe{counts, nullptr, nullptr, nullptr};
     ecc_status s = validate_field(field, &probe, &fi, false);
     if (s != ECC_OK) return s;
-    if (fi.ndim != 2) return fail(ECC_ERR_UNSUPPORTED, "vertex class counts are computed for 2D fields only");
     std::lock_guard<std::mutex> lk(ctx->mu);
     int e = (int)hipSetDevice(ctx->device);
     if (e) return hip_fail(e, "hipSetDevice");

@@ -22,7 +22,10 @@
 // four corner masks, so the whole delta is one table lookup.
 #include "ecc_internal.h"
 
+#include <algorithm>
+#include <array>
 #include <cstring>
+#include <vector>
 
 namespace ecc {
 
@@ -70,6 +73,46 @@ int vertex_class_2d(int m) {
     case 3: return 3;
     default: return 4;
     }
+}
+
+// 3D octant classes: the orbits of the 256 masks (bit dx + 2dy + 4dz) under the
+// 48 symmetries of the cube (axis permutations and reflections), the rows of
+// Table 2.  The 21 non-empty orbits are numbered by (number of voxels, smallest
+// mask in the orbit); the empty mask is -1.
+int octant_class_3d(int mask) {
+    static const std::array<int8_t, 256> table = [] {
+        std::array<int, 256> rep{};
+        const int perms[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {2, 0, 1}, {2, 1, 0}};
+        for (int m = 0; m < 256; ++m) {
+            int best = 256;
+            for (const auto &pm : perms)
+                for (int f = 0; f < 8; ++f) {
+                    int img = 0;
+                    for (int b = 0; b < 8; ++b) {
+                        if (!(m >> b & 1)) continue;
+                        const int c[3] = {b & 1, b >> 1 & 1, b >> 2 & 1};
+                        int nb = 0;
+                        for (int a = 0; a < 3; ++a) nb |= (c[pm[a]] ^ (f >> a & 1)) << a;
+                        img |= 1 << nb;
+                    }
+                    best = std::min(best, img);
+                }
+            rep[m] = best;
+        }
+        std::vector<int> reps;
+        for (int m = 1; m < 256; ++m)
+            if (rep[m] == m) reps.push_back(m);
+        std::sort(reps.begin(), reps.end(), [](int a, int b) {
+            const int pa = __builtin_popcount(a), pb = __builtin_popcount(b);
+            return pa != pb ? pa < pb : a < b;
+        });
+        std::array<int8_t, 256> t{};
+        t[0] = -1;
+        for (int m = 1; m < 256; ++m)
+            t[m] = (int8_t)(std::find(reps.begin(), reps.end(), rep[m]) - reps.begin());
+        return t;
+    }();
+    return table[mask & 255];
 }
 
 void class_delta_table_2d(int32_t delta[256][5]) {
@@ -231,7 +274,13 @@ extern "C" ecc_status ecc_vertex_table(int32_t ndim, int32_t connectivity, int32
 
 extern "C" ecc_status ecc_vertex_class_table(int32_t ndim, int32_t *out) {
     if (!out) return ecc::fail(ECC_ERR_INVALID_ARG, "ecc_vertex_class_table: out is NULL");
-    if (ndim != 2) return ecc::fail(ECC_ERR_UNSUPPORTED, "ecc_vertex_class_table: only 2D vertex classes");
-    for (int m = 0; m < 16; ++m) out[m] = ecc::vertex_class_2d(m);
-    return ECC_OK;
+    if (ndim == 2) {
+        for (int m = 0; m < 16; ++m) out[m] = ecc::vertex_class_2d(m);
+        return ECC_OK;
+    }
+    if (ndim == 3) {
+        for (int m = 0; m < 256; ++m) out[m] = ecc::octant_class_3d(m);
+        return ECC_OK;
+    }
+    return ecc::fail(ECC_ERR_INVALID_ARG, "ecc_vertex_class_table: ndim must be 2 or 3");
 }

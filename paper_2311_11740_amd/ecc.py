@@ -128,9 +128,11 @@ def vertex_table(ndim: int, connectivity: int = 0):
 
 
 def vertex_class_table(ndim: int = 2):
-    """Class (0..4, -1 empty) of each 2D vertex mask, as the library assigns it."""
+    """Class of each vertex mask as the library counts it (-1 empty): 16 masks
+    and classes 0..4 in 2D, 256 masks and classes 0..20 in 3D."""
     lib = load()
-    buf = (ctypes.c_int32 * 16)()
+    n = 16 if ndim == 2 else 256
+    buf = (ctypes.c_int32 * n)()
     check(lib.ecc_vertex_class_table(ndim, buf))
     return list(buf)
 
@@ -296,15 +298,17 @@ class Context:
         return out
 
     def vertex_classes(self, field, n_levels: int, thresholds=None, stream=None, out=None):
-        """Counts of 2D lattice vertices per quadrant class and level: int64
-        device tensor [5, n_levels], rows in VERTEX_CLASSES_2D order (async on
-        `stream`).  `out` may supply the [5, n_levels] int64 tensor."""
+        """Counts of lattice vertices per neighbourhood class and level: int64
+        device tensor [5, n_levels] (2D, rows in VERTEX_CLASSES_2D order) or
+        [21, n_levels] (3D, classes as vertex_class_table(3)), async on
+        `stream`.  `out` may supply that tensor."""
         torch = _torch()
         f, keep = make_field(field, n_levels, thresholds, 0)
+        nc = 5 if field.dim() == 2 else 21
         if out is None:
-            out = torch.empty((5, n_levels), dtype=torch.int64, device=field.device)
-        elif tuple(out.shape) != (5, n_levels) or out.dtype != torch.int64 or not out.is_contiguous():
-            raise ValueError("out must be a contiguous int64 tensor of shape (5, n_levels)")
+            out = torch.empty((nc, n_levels), dtype=torch.int64, device=field.device)
+        elif tuple(out.shape) != (nc, n_levels) or out.dtype != torch.int64 or not out.is_contiguous():
+            raise ValueError(f"out must be a contiguous int64 tensor of shape ({nc}, n_levels)")
         check(self._lib.ecc_vertex_classes_compute(self.handle, ctypes.byref(f), out.data_ptr(),
                                                    _stream_ptr(stream)))
         del keep

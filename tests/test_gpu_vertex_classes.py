@@ -1,4 +1,4 @@
-"""GPU parity of the 2D vertex class counts (contribution map), through the C ABI.
+"""GPU parity of the vertex class counts (contribution map), through the C ABI.
 
 * Counts equal the oracle's (oracle.vertex_classes_2d) bit for bit: the
   degenerate shapes, ragged tails over several strips, every level mode
@@ -7,7 +7,9 @@
   per-pass window, a field whose base address is not 16-byte aligned.
 * On a large field the counts, weighted by Table 1, give the same EC (8-C and
   4-C), perimeter and area curves as ecc_curves_compute.
-* A 3D field is refused with ECC_ERR_UNSUPPORTED.
+* 3D: the 21 octant classes equal the oracle's on degenerate shapes, ragged
+  tiles, more levels than one pass holds, float thresholds with NaN, and a
+  smooth volume.
 """
 from __future__ import annotations
 
@@ -36,7 +38,7 @@ def compare(ctx, arr, L, thr=None, tag="", offset=0):
     dev = flat[offset:].view(*arr.shape)
     got = ctx.vertex_classes(dev, L, thresholds=thr)
     torch.cuda.synchronize()
-    ref = oracle.vertex_classes_2d(arr, L, thr)
+    ref = oracle.class_counts(arr, L, thr)
     g = got.cpu().numpy()
     if not np.array_equal(g, ref):
         c, lvl = (int(x[0]) for x in np.nonzero(g != ref))
@@ -102,10 +104,29 @@ def test_classes_weightings_equal_curves_large(ctx):
     assert np.array_equal(one + 2 * adj + 2 * diag + 3 * three + 4 * four, 4 * c8["area"])
 
 
-def test_classes_3d_refused(ctx):
-    import torch
-    from paper_2311_11740_amd import ecc
-    dev = torch.zeros((4, 5, 6), dtype=torch.uint8, device="cuda")
-    with pytest.raises(ecc.EccError) as ei:
-        ctx.vertex_classes(dev, 16)
-    assert ei.value.status == ecc.ECC_ERR_UNSUPPORTED
+SHAPES_3D = [(1, 1, 1), (1, 1, 70), (70, 1, 1), (9, 13, 70), (20, 33, 65)]
+
+
+@pytest.mark.parametrize("shape", SHAPES_3D)
+def test_classes_3d_u8(ctx, shape):
+    rng = np.random.default_rng(sum(shape))
+    compare(ctx, rng.integers(0, 60, size=shape).astype(np.uint8), 50, tag="3D u8")
+
+
+def test_classes_3d_u16_multipass(ctx):
+    rng = np.random.default_rng(60)
+    compare(ctx, rng.integers(0, 700, size=(11, 17, 40)).astype(np.uint16), 600, tag="3D u16 600 levels")
+
+
+def test_classes_3d_f32_nan(ctx):
+    rng = np.random.default_rng(61)
+    x = rng.normal(size=(7, 30, 40)).astype(np.float32)
+    x[rng.random(x.shape) < 0.05] = np.nan
+    thr = np.sort(rng.normal(size=40)).astype(np.float32)
+    compare(ctx, x, 40, thr, tag="3D f32")
+
+
+def test_classes_3d_medium(ctx):
+    from paper_2311_11740_amd import synth
+    v = synth.quantise(synth.grf((64, 96, 128), 3.0, 62), 256)
+    compare(ctx, v, 256, tag="3D GRF 64x96x128")
