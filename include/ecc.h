@@ -144,8 +144,7 @@ ecc_status ecc_curves_compute(ecc_context ctx, const ecc_field *field, const ecc
  *
  * field:  as for ecc_curves_compute, except that data is a HOST pointer
  *         (pageable or pinned), read during the call only.
- * curves: HOST pointers, n_levels int64 each, NULL = channel not wanted.  In 3D
- *         the perimeter (crease) channel must be NULL (ECC_ERR_UNSUPPORTED).
+ * curves: HOST pointers, n_levels int64 each, NULL = channel not wanted.
  * slab_bytes: device bytes per slab buffer (two are allocated for the call and
  *         freed before it returns); 0 = 256 MiB.  Must hold three rows (2D) or
  *         planes (3D), else ECC_ERR_INVALID_ARG.

@@ -23,6 +23,10 @@ int vertex_class_2d(int mask);
 // per-cell change of the five class counts when the pixel enters, by the
 // "entered before" pattern of its 8 neighbours (bit k = neighbour k)
 void class_delta_table_2d(int32_t delta[256][5]);
+// change of the summed kappa of the four 2x2 blocks at a pixel's corners when
+// the pixel enters, by "entered before" pattern (-4..4); the 3D crease delta of
+// a voxel is the sum of this over its three axis planes
+void crease_delta_table_2d(int32_t delta[256]);
 // class of a 3D octant mask (bit dx + 2dy + 4dz): -1 empty, else 0..20, the
 // orbits under the cube's 48 symmetries ordered by (voxels, smallest mask)
 int octant_class_3d(int mask);
@@ -127,6 +131,9 @@ struct Launch3D {
     // vertex class counts (tile kernel): vtab holds the class of each octant
     // mask and partial is [kNumClasses3D][L][grid]
     bool classes;
+    // the crease channel alone by z-marching (channel 1 of the partials,
+    // same grid and z range as the z-marching launch): its table, else NULL
+    const uint32_t *crease_table;
 };
 
 // ---- batched 2D launch ----------------------------------------------------------

@@ -64,6 +64,7 @@ struct ecc_context_s {
     uint32_t *d_zm3[2] = {nullptr, nullptr};     // 3D z-marching tables, 26-C and 6-C
     uint64_t *d_cls2 = nullptr;                  // 2D per-cell class-count deltas, 2 x 256 words
     int64_t *d_cls3 = nullptr;                   // 3D class of each octant mask (-1 empty)
+    uint32_t *d_crease3 = nullptr;               // 3D crease by z-marching: per-plane deltas + 4
     std::vector<ecc::ThrEntry *> thr_cache;
     ecc::Workspace ws;
     hipEvent_t ws_event = nullptr;

@@ -189,6 +189,16 @@ extern "C" ecc_status ecc_create(int device, ecc_context *out) {
             ecc_destroy(ctx);
             return s;
         }
+        // per-plane crease deltas + 4, in the kernels' index order
+        int32_t cd[256];
+        crease_delta_table_2d(cd);
+        uint32_t tc[256];
+        for (int n = 0; n < 256; ++n) tc[n] = (uint32_t)(cd[pattern_of_index(n)] + 4);
+        s = upload((void **)&ctx->d_crease3, tc, sizeof(tc));
+        if (s != ECC_OK) {
+            ecc_destroy(ctx);
+            return s;
+        }
     }
     e = (int)hipEventCreateWithFlags(&ctx->ws_event, hipEventDisableTiming);
     if (e) {
@@ -227,6 +237,7 @@ extern "C" ecc_status ecc_destroy(ecc_context ctx) {
     }
     if (ctx->d_cls2) hipFree(ctx->d_cls2);
     if (ctx->d_cls3) hipFree(ctx->d_cls3);
+    if (ctx->d_crease3) hipFree(ctx->d_crease3);
     for (auto *t : ctx->thr_cache) free_thresholds(t);
     ctx->thr_cache.clear();
     for (auto &pe : ctx->prof_events) {
@@ -506,15 +517,19 @@ ecc_status compute_one(ecc_context ctx, const ecc_field *f, const FieldInfo &fi,
         grid = (int)std::min<int64_t>((int64_t)ctx->n_cu * wg_per_cu_default(),
                                       std::max<int64_t>(1, (strips * fi.h + 31) / 32));
         if (grid >= 8) grid -= grid % 8;
-    } else if (!crease) {
+    } else {
         // z-marching kernel: at least ~16 planes per wave; its register use
         // leaves room for two 4-wave workgroups per CU, so one round of
-        // 2 x CUs workgroups (fewer partials than more, smaller rounds)
+        // 2 x CUs workgroups (fewer partials than more, smaller rounds).  The
+        // crease channel, when wanted, is a second z-marching launch.
         const int64_t units = (int64_t)zmarch_3d_columns(fi.h, fi.w) * fi.d;
         grid = (int)std::min<int64_t>((int64_t)ctx->n_cu * zm_wg_per_cu(),
                                       std::max<int64_t>(1, (units + 63) / 64));
         if (grid >= 8) grid -= grid % 8;
-        zmarch = zmarch_3d_fits(fi.h, fi.w, grid);
+        // ECC_3D_KERNEL=tile selects the generic tile kernel (read per call)
+        const char *ek = std::getenv("ECC_3D_KERNEL");
+        const bool force_tile = ek && std::strcmp(ek, "tile") == 0;
+        zmarch = !force_tile && zmarch_3d_fits(fi.h, fi.w, grid);
     }
     if (fi.ndim == 3 && !zmarch) {
         const int64_t n_tiles = ((fi.w + kTile3DX - 1) / kTile3DX) * ((fi.h + kTile3DY - 1) / kTile3DY) *
@@ -551,9 +566,15 @@ ecc_status compute_one(ecc_context ctx, const ecc_field *f, const FieldInfo &fi,
             int slot = -1;
             s = prof_begin(ctx, stream, &slot);
             if (s != ECC_OK) return s;
-            Launch3D a{data, fi.dtype, fi.d, fi.h, fi.w, lv, lo, hi, ctx->d_vtab3[k], partial, grid, crease,
-                       zmarch ? ctx->d_zm3[k] : nullptr, k == 1, 0, fi.d, false, false};
+            Launch3D a{data, fi.dtype, fi.d, fi.h, fi.w, lv, lo, hi, ctx->d_vtab3[k], partial, grid,
+                       zmarch ? false : crease, zmarch ? ctx->d_zm3[k] : nullptr, k == 1, 0, fi.d, false, false,
+                       nullptr};
             int e = launch_3d(a, stream);
+            if (!e && zmarch && crease) {
+                Launch3D c3 = a;
+                c3.crease_table = ctx->d_crease3;
+                e = launch_3d(c3, stream);
+            }
             if (e) return hip_fail(e, "3D kernel launch");
             s = prof_end(ctx, stream, slot);
             if (s != ECC_OK) return s;
@@ -563,8 +584,8 @@ ecc_status compute_one(ecc_context ctx, const ecc_field *f, const FieldInfo &fi,
     return merge_and_scan(ctx, grid, nch, L, outs, stream);
 }
 
-// Class counts of a 2D field: the single-field 2D path with the class-count
-// bins (five channels), merged as channels 0-2 and 3-4.
+// class channels into counts[c][L], three at a time (the merge kernel scans up
+// to three channels per launch)
 static ecc_status merge_classes(ecc_context ctx, int grid, int nch, int L, int64_t *counts, void *stream) {
     ecc_status s = grow(ctx, ctx->ws.totals, (size_t)3 * L * sizeof(int64_t), "totals");
     if (s != ECC_OK) return s;
@@ -603,7 +624,7 @@ static ecc_status compute_classes_3d(ecc_context ctx, const ecc_field *f, const 
         s = prof_begin(ctx, stream, &slot);
         if (s != ECC_OK) return s;
         Launch3D a{f->data, fi.dtype, fi.d, fi.h, fi.w, lv, lo, hi, ctx->d_cls3, partial, grid, false,
-                   nullptr, false, 0, fi.d, false, true};
+                   nullptr, false, 0, fi.d, false, true, nullptr};
         int e = launch_3d(a, stream);
         if (e) return hip_fail(e, "3D class-count kernel launch");
         s = prof_end(ctx, stream, slot);
@@ -612,6 +633,8 @@ static ecc_status compute_classes_3d(ecc_context ctx, const ecc_field *f, const 
     return merge_classes(ctx, grid, nch, L, counts, stream);
 }
 
+// Class counts of a 2D field: the single-field 2D path with the class-count
+// bins (five channels).
 static ecc_status compute_classes(ecc_context ctx, const ecc_field *f, const FieldInfo &fi, int64_t *counts,
                                   void *stream) {
     if (fi.ndim == 3) return compute_classes_3d(ctx, f, fi, counts, stream);

@@ -50,8 +50,6 @@ ecc_status stream_field(ecc_context ctx, const ecc_field *f, const FieldInfo &fi
         return fail(ECC_ERR_INVALID_ARG, "slab_bytes must hold at least three rows (2D) or planes (3D)");
     const int64_t R = std::min(per_slab, n_units);
     const bool crease = is3 && c->perimeter != nullptr;
-    if (crease)
-        return fail(ECC_ERR_UNSUPPORTED, "streamed 3D fields: the crease (perimeter) channel is not available");
     const int L = fi.L;
     const int nch = is3 ? 4 : 3;
     const int win = std::min(L, kMaxWindow);
@@ -122,8 +120,12 @@ ecc_status stream_field(ecc_context ctx, const ecc_field *f, const FieldInfo &fi
             const int hi = std::min(L, lo + win);
             if (is3) {
                 Launch3D la{data_v, fi.dtype, u1, fi.h, fi.w, lv, lo, hi, ctx->d_vtab3[k], partial, grid, false,
-                            ctx->d_zm3[k], k == 1, a, b, slab > 0, false};
+                            ctx->d_zm3[k], k == 1, a, b, slab > 0, false, nullptr};
                 e = launch_3d(la, stream);
+                if (!e && crease) {  // the crease channel: a second z-marching launch
+                    la.crease_table = ctx->d_crease3;
+                    e = launch_3d(la, stream);
+                }
             } else {
                 Launch2D la{data_v, fi.dtype, u1, fi.w, lv, lo, hi, ctx->d_delta2[k], partial, grid,
                             a, b, slab > 0, false};

@@ -65,6 +65,43 @@ void vertex_table_2d(int connectivity, int32_t out[16][4]) {
 // neighbour order of the 8-bit per-cell pattern (row offset, column offset)
 const int kNbr2[8][2] = {{-1, -1}, {-1, 0}, {-1, 1}, {0, -1}, {0, 1}, {1, -1}, {1, 0}, {1, 1}};
 
+// kappa of a 2x2 block of cells around a lattice edge (the crease measure of
+// Table 2's perimeter column): 1 for one or three cells in, 2 for two cells on
+// a diagonal, else 0.  Mask bits as for the 2D quadrant (a*2 + b).
+static int kappa_of_mask(int m) {
+    const int n = __builtin_popcount(m);
+    if (n == 1 || n == 3) return 1;
+    if (n == 2 && (m == 6 || m == 9)) return 2;
+    return 0;
+}
+
+void crease_delta_table_2d(int32_t delta[256]) {
+    // the four blocks at the corners (cr, cc) of pixel p = (0,0), as in
+    // cell_delta_table_2d
+    for (int pat = 0; pat < 256; ++pat) {
+        auto precedes = [&](int dr, int dc) -> int {
+            for (int k = 0; k < 8; ++k)
+                if (kNbr2[k][0] == dr && kNbr2[k][1] == dc) return pat >> k & 1;
+            return 0;
+        };
+        int32_t s = 0;
+        for (int cr = 0; cr < 2; ++cr)
+            for (int cc = 0; cc < 2; ++cc) {
+                int m0 = 0, pbit = 0;
+                for (int a = 0; a < 2; ++a)
+                    for (int b = 0; b < 2; ++b) {
+                        const int dr = cr - 1 + a, dc = cc - 1 + b, bit = a * 2 + b;
+                        if (dr == 0 && dc == 0)
+                            pbit = bit;
+                        else if (precedes(dr, dc))
+                            m0 |= 1 << bit;
+                    }
+                s += kappa_of_mask(m0 | 1 << pbit) - kappa_of_mask(m0);
+            }
+        delta[pat] = s;
+    }
+}
+
 int vertex_class_2d(int m) {
     switch (__builtin_popcount(m)) {
     case 0: return -1;

@@ -286,7 +286,7 @@ class Context:
             if keep.size != n_levels:
                 raise ValueError("thresholds must have n_levels entries")
             f.thresholds = keep.ctypes.data
-        allowed = CHANNELS_2D if a.ndim == 2 else ("ec", "area", "volume")
+        allowed = CHANNELS_2D if a.ndim == 2 else CHANNELS_3D
         channels = allowed if channels is None else tuple(channels)
         out = {c: np.zeros(n_levels, dtype=np.int64) for c in channels}
         cv = Curves()

@@ -136,34 +136,57 @@ def test_2d_channel_subsets(ctx):
 
 SHAPES_3D = [(1, 1, 1), (1, 1, 70), (70, 1, 1), (3, 5, 7), (17, 9, 130), (40, 33, 65), (1, 64, 64),
              (9, 7, 513), (5, 258, 300)]
-# channel sets: without the crease measure the z-marching kernel runs, with it
-# the generic tile kernel
+# 3D paths: the z-marching kernel without the crease measure, with it (a
+# second z-marching launch adds the crease), and the generic tile kernel
 NO_CREASE = ("ec", "area", "volume")
 ALL_3D = None
+PATHS_3D = {"zmarch": (NO_CREASE, None), "zmarch_crease": (ALL_3D, None), "tile": (ALL_3D, "tile")}
+
+
+class kernel_choice:
+    """Select the 3D kernel for the calls inside the block (ECC_3D_KERNEL)."""
+
+    def __init__(self, which):
+        self.which = which
+
+    def __enter__(self):
+        self.old = os.environ.pop("ECC_3D_KERNEL", None)
+        if self.which:
+            os.environ["ECC_3D_KERNEL"] = self.which
+
+    def __exit__(self, *exc):
+        os.environ.pop("ECC_3D_KERNEL", None)
+        if self.old is not None:
+            os.environ["ECC_3D_KERNEL"] = self.old
 
 
 @pytest.mark.parametrize("shape", SHAPES_3D)
 @pytest.mark.parametrize("conn", [26, 6])
-@pytest.mark.parametrize("channels", [NO_CREASE, ALL_3D], ids=["zmarch", "tile"])
-def test_3d_u8(ctx, shape, conn, channels):
+@pytest.mark.parametrize("path", list(PATHS_3D))
+def test_3d_u8(ctx, shape, conn, path):
+    channels, which = PATHS_3D[path]
     rng = np.random.default_rng(hash((shape, conn, 3)) % 2**32)
     a = rng.integers(0, 40, size=shape).astype(np.uint8)
-    run_and_compare(ctx, a, 36, conn=conn, channels=channels, tag="3d_u8")
+    with kernel_choice(which):
+        run_and_compare(ctx, a, 36, conn=conn, channels=channels, tag=f"3d_u8_{path}")
 
 
-@pytest.mark.parametrize("channels", [NO_CREASE, ALL_3D], ids=["zmarch", "tile"])
-def test_3d_u16_grf(ctx, channels):
+@pytest.mark.parametrize("path", list(PATHS_3D))
+def test_3d_u16_grf(ctx, path):
     from paper_2311_11740_amd import synth
+    channels, which = PATHS_3D[path]
     a = synth.quantise(synth.grf((48, 40, 136), 3.0, 31), 4096)
-    run_and_compare(ctx, a, 4096, tag="3d_u16_grf", channels=channels)
-    run_and_compare(ctx, a, 3000, conn=6, tag="3d_u16_grf_6c_never", channels=channels)
-    run_and_compare(ctx, a, 5000, tag="3d_u16_grf_2pass", channels=channels)
-    run_and_compare(ctx, a, 5000, conn=6, tag="3d_u16_grf_2pass_6c", channels=channels)
+    with kernel_choice(which):
+        run_and_compare(ctx, a, 4096, tag="3d_u16_grf", channels=channels)
+        run_and_compare(ctx, a, 3000, conn=6, tag="3d_u16_grf_6c_never", channels=channels)
+        run_and_compare(ctx, a, 5000, tag="3d_u16_grf_2pass", channels=channels)
+        run_and_compare(ctx, a, 5000, conn=6, tag="3d_u16_grf_2pass_6c", channels=channels)
 
 
-@pytest.mark.parametrize("channels", [NO_CREASE, ALL_3D], ids=["zmarch", "tile"])
-def test_3d_f32_thresholds(ctx, channels):
+@pytest.mark.parametrize("path", list(PATHS_3D))
+def test_3d_f32_thresholds(ctx, path):
     from paper_2311_11740_amd import synth
+    channels, which = PATHS_3D[path]
     z = synth.grf((20, 30, 70), 2.5, 41)
     z.ravel()[11] = np.nan
     z.ravel()[12] = np.inf
@@ -172,9 +195,10 @@ def test_3d_f32_thresholds(ctx, channels):
     z.ravel()[100::37] = thr[np.arange(z.ravel()[100::37].size) % 200]  # values on thresholds
     z.ravel()[101::53] = np.float32(-3.0) - np.float32(0.03) * (np.arange(z.ravel()[101::53].size) % 40)
     z.ravel()[102::97] = np.float32(3.0) + np.float32(0.03) * (np.arange(z.ravel()[102::97].size) % 40)
-    run_and_compare(ctx, z, 200, thr=thr, tag="3d_f32_affine", channels=channels)
     thr2 = np.sort(np.random.default_rng(2).normal(size=77)).astype(np.float32)
-    run_and_compare(ctx, z, 77, thr=thr2, conn=6, tag="3d_f32_irregular_6c", channels=channels)
+    with kernel_choice(which):
+        run_and_compare(ctx, z, 200, thr=thr, tag="3d_f32_affine", channels=channels)
+        run_and_compare(ctx, z, 77, thr=thr2, conn=6, tag="3d_f32_irregular_6c", channels=channels)
 
 
 def test_3d_integer_with_thresholds(ctx):
@@ -195,10 +219,12 @@ def test_3d_channel_subsets(ctx):
         run_and_compare(ctx, a, 30, channels=ch, tag=f"3d_ch_{'_'.join(ch)}")
 
 
-@pytest.mark.parametrize("channels", [NO_CREASE, ALL_3D], ids=["zmarch", "tile"])
-def test_3d_constant(ctx, channels):
-    run_and_compare(ctx, np.full((20, 6, 70), 3, np.uint16), 10, tag="3d_const", channels=channels)
-    run_and_compare(ctx, np.full((5, 6, 270), 200, np.uint8), 100, tag="3d_all_never", channels=channels)
+@pytest.mark.parametrize("path", list(PATHS_3D))
+def test_3d_constant(ctx, path):
+    channels, which = PATHS_3D[path]
+    with kernel_choice(which):
+        run_and_compare(ctx, np.full((20, 6, 70), 3, np.uint16), 10, tag="3d_const", channels=channels)
+        run_and_compare(ctx, np.full((5, 6, 270), 200, np.uint8), 100, tag="3d_all_never", channels=channels)
 
 
 def test_repeat_is_deterministic(ctx):
