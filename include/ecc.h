@@ -225,9 +225,9 @@ ecc_status ecc_vertex_class_table(int32_t ndim, int32_t *out);
 
 /*
  * Kernel timing for measurement.  While enabled, the context records a pair of
- * HIP events around every launch of its field-reading pass kernel (the tile
- * kernel that reads the field from HBM; not the merge and scan kernels that
- * follow it) on the stream the launch goes to.  ecc_profile_read waits for the
+ * HIP events around the launches of each field-reading pass (the kernels that
+ * read the field from HBM: one, or in 3D with the crease channel two; not the
+ * merge and scan kernels that follow) on the stream the launches go to.  ecc_profile_read waits for the
  * recorded events, returns the summed elapsed milliseconds and the number of
  * launches, and forgets them when `reset` is non-zero.  Enabling it adds two
  * event records per launch and nothing else.

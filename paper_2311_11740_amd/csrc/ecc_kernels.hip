@@ -20,7 +20,11 @@
 //     (fields biased to stay non-negative, see ecc_internal.h);
 //   * 3D (`ecc3d_stream`): a wave marches the z-planes of a column of 4 rows
 //     x 256 columns with a slab decomposition that needs two 2D patterns per
-//     voxel; `ecc3d_tile` (LDS-staged 3x3x3 windows) also computes the crease;
+//     voxel; `ecc3d_crease` marches the same way for the crease channel (three
+//     2D patterns per voxel, one per axis plane); `ecc3d_tile` (LDS-staged
+//     3x3x3 windows) computes every channel for planes too large to march, and
+//     the vertex class counts;
+//   * the 2D kernel also counts vertex classes (two words per level bin);
 //   * each workgroup drains its histogram into its slice of level-major
 //     partials; `ecc_merge` sums them per level and its last block scans;
 //   * `ecc2d_batch` runs many fields in one persistent launch.
@@ -814,8 +818,8 @@ __device__ __forceinline__ void drain_3d(uint64_t *hist, uint32_t *hc, bool crea
 // a min-image pixel happens at the level of the voxel that enters first of
 // the two (last, for the max image), so it is added to that voxel's event:
 // one LDS atomic per voxel.  The surface adds the two vertical faces, the
-// volume is the count.  (The crease measure needs the 3x3x3 neighbourhood and
-// is left to the generic kernel below.)
+// volume is the count.  (The crease measure is a second z-marching kernel,
+// `ecc3d_crease`, below.)
 //
 // A wave owns TY rows of a strip of 64*VEC columns and marches z, holding the
 // level indices of planes z-1, z, z+1 (TY+2 rows each, packed as in 2D) in
