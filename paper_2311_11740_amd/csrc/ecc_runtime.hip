@@ -526,10 +526,13 @@ ecc_status compute_one(ecc_context ctx, const ecc_field *f, const FieldInfo &fi,
         grid = (int)std::min<int64_t>((int64_t)ctx->n_cu * zm_wg_per_cu(),
                                       std::max<int64_t>(1, (units + 63) / 64));
         if (grid >= 8) grid -= grid % 8;
-        // ECC_3D_KERNEL=tile selects the generic tile kernel (read per call)
+        // A volume too small to give every CU a z-marching workgroup (its
+        // columns are 256 voxels wide) runs faster on the tile kernel.
+        // ECC_3D_KERNEL=tile or =zmarch overrides the choice (read per call).
         const char *ek = std::getenv("ECC_3D_KERNEL");
         const bool force_tile = ek && std::strcmp(ek, "tile") == 0;
-        zmarch = !force_tile && zmarch_3d_fits(fi.h, fi.w, grid);
+        const bool force_zm = ek && std::strcmp(ek, "zmarch") == 0;
+        zmarch = !force_tile && zmarch_3d_fits(fi.h, fi.w, grid) && (force_zm || grid >= ctx->n_cu);
     }
     if (fi.ndim == 3 && !zmarch) {
         const int64_t n_tiles = ((fi.w + kTile3DX - 1) / kTile3DX) * ((fi.h + kTile3DY - 1) / kTile3DY) *

@@ -83,7 +83,7 @@ def test_large_2d_f32(ctx):
     check_o1_levels(spec, got, [0, 300, 511, 512, 700, 1023], spec.meta["name"])
 
 
-@pytest.mark.parametrize("channels", [("ec", "area", "volume"), None], ids=["zmarch", "tile"])
+@pytest.mark.parametrize("channels", [("ec", "area", "volume"), None], ids=["no_crease", "all_channels"])
 def test_large_3d_u16(ctx, channels):
     from paper_2311_11740_amd import synth
     spec = synth.large_3d_u16()

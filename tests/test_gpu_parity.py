@@ -137,10 +137,13 @@ def test_2d_channel_subsets(ctx):
 SHAPES_3D = [(1, 1, 1), (1, 1, 70), (70, 1, 1), (3, 5, 7), (17, 9, 130), (40, 33, 65), (1, 64, 64),
              (9, 7, 513), (5, 258, 300)]
 # 3D paths: the z-marching kernel without the crease measure, with it (a
-# second z-marching launch adds the crease), and the generic tile kernel
+# second z-marching launch adds the crease), and the generic tile kernel with
+# and without it (forced: by default small volumes take the tile kernel and
+# large ones z-marching)
 NO_CREASE = ("ec", "area", "volume")
 ALL_3D = None
-PATHS_3D = {"zmarch": (NO_CREASE, None), "zmarch_crease": (ALL_3D, None), "tile": (ALL_3D, "tile")}
+PATHS_3D = {"zmarch": (NO_CREASE, "zmarch"), "zmarch_crease": (ALL_3D, "zmarch"), "tile": (ALL_3D, "tile"),
+            "tile_no_crease": (NO_CREASE, "tile")}
 
 
 class kernel_choice:
