@@ -604,9 +604,16 @@ static ecc_status merge_classes(ecc_context ctx, int grid, int nch, int L, int64
     return ECC_OK;
 }
 
+// workgroups per CU of the 3D class-count kernel (ECC_CLS3_WG_PER_CU, default 2)
+static int cls3_wg_per_cu() {
+    const char *e = std::getenv("ECC_CLS3_WG_PER_CU");
+    const int x = e ? std::atoi(e) : 2;
+    return x < 1 ? 1 : (x > 3 ? 3 : x);
+}
+
 // Class counts of a 3D field: the tile kernel in class-count mode, passes of
-// kClsWindow3D levels, one workgroup per CU (the class bins take
-// kNumClasses3D x 4 bytes per level of LDS), then the merges.
+// kClsWindow3D levels (the class bins take kNumClasses3D x 4 bytes per level
+// of LDS), then the merges.
 static ecc_status compute_classes_3d(ecc_context ctx, const ecc_field *f, const FieldInfo &fi, int64_t *counts,
                                      void *stream) {
     LevelArgs lv;
@@ -616,7 +623,8 @@ static ecc_status compute_classes_3d(ecc_context ctx, const ecc_field *f, const 
     const int win = std::min(L, kClsWindow3D);
     const int64_t n_tiles = ((fi.w + kTile3DX - 1) / kTile3DX) * ((fi.h + kTile3DY - 1) / kTile3DY) *
                             ((fi.d + kTile3DZ - 1) / kTile3DZ);
-    int grid = (int)std::min<int64_t>(ctx->n_cu, n_tiles);
+    // two workgroups per CU (the class bins of a 512-level pass take 43 KB of LDS)
+    int grid = (int)std::min<int64_t>((int64_t)ctx->n_cu * cls3_wg_per_cu(), n_tiles);
     if (grid < 1) grid = 1;
     s = grow(ctx, ctx->ws.partial, (size_t)grid * nch * L * sizeof(int32_t), "partials");
     if (s != ECC_OK) return s;
