@@ -21,13 +21,17 @@ namespace ecc {
 
 namespace {
 
+// Buffers, copy stream and events of one call; released when the call returns
+// (after the work queued on both streams has finished, also on an error path).
 struct StreamRes {
     DevBuf buf[2];
     DevBuf curves;
+    hipStream_t caller = nullptr;
     hipStream_t copy = nullptr;
     hipEvent_t copied[2] = {nullptr, nullptr}, computed[2] = {nullptr, nullptr};
     ~StreamRes() {
         if (copy) hipStreamSynchronize(copy);
+        hipStreamSynchronize(caller);
         for (int k = 0; k < 2; ++k) {
             if (copied[k]) hipEventDestroy(copied[k]);
             if (computed[k]) hipEventDestroy(computed[k]);
@@ -77,6 +81,7 @@ ecc_status stream_field(ecc_context ctx, const ecc_field *f, const FieldInfo &fi
     int32_t *partial = (int32_t *)ctx->ws.partial.ptr;
 
     StreamRes r;
+    r.caller = (hipStream_t)stream;
     // slab + halo at offset kPad, with kPad bytes after it: the kernels' vector
     // loads are clamped to the last whole vector of the field they are given
     // (here: up to the end of the buffer's units), which for a slab of fewer
