@@ -124,3 +124,10 @@ def test_streamed_errors(ctx):
     with pytest.raises(ecc.EccError) as ei:
         ctx.compute_streamed(a, 16, slab_bytes=250)
     assert ei.value.status == ecc.ECC_ERR_INVALID_ARG
+
+
+def test_streamed_integer_thresholds(ctx):
+    rng = np.random.default_rng(49)
+    thr = np.sort(rng.uniform(0, 1000, size=64)).astype(np.float32)
+    compare(ctx, rng.integers(0, 1100, size=(97, 301)).astype(np.uint16), 64, thr, units=5, tag="2D u16 thresholds")
+    compare(ctx, rng.integers(0, 1100, size=(9, 31, 75)).astype(np.uint16), 64, thr, units=2, tag="3D u16 thresholds")

@@ -130,3 +130,9 @@ def test_classes_3d_medium(ctx):
     from paper_2311_11740_amd import synth
     v = synth.quantise(synth.grf((64, 96, 128), 3.0, 62), 256)
     compare(ctx, v, 256, tag="3D GRF 64x96x128")
+
+
+def test_classes_3d_integer_thresholds(ctx):
+    rng = np.random.default_rng(63)
+    thr = np.sort(rng.uniform(0, 1000, size=48)).astype(np.float32)
+    compare(ctx, rng.integers(0, 1100, size=(8, 21, 67)).astype(np.uint16), 48, thr, tag="3D u16 thresholds")
