@@ -131,8 +131,8 @@ struct Launch3D {
     // vertex class counts (tile kernel): vtab holds the class of each octant
     // mask and partial is [kNumClasses3D][L][grid]
     bool classes;
-    // the crease channel alone by z-marching (channel 1 of the partials,
-    // same grid and z range as the z-marching launch): its table, else NULL
+    // z-marching kernel: the per-plane crease table when the crease channel
+    // is wanted (it then comes along in the same launch), else NULL
     const uint32_t *crease_table;
 };
 

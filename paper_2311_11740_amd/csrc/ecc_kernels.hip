@@ -20,8 +20,8 @@
 //     (fields biased to stay non-negative, see ecc_internal.h);
 //   * 3D (`ecc3d_stream`): a wave marches the z-planes of a column of 4 rows
 //     x 256 columns with a slab decomposition that needs two 2D patterns per
-//     voxel; `ecc3d_crease` marches the same way for the crease channel (three
-//     2D patterns per voxel, one per axis plane); `ecc3d_tile` (LDS-staged
+//     voxel, and two more (its yz and xz planes) when the crease channel is
+//     wanted; `ecc3d_tile` (LDS-staged
 //     3x3x3 windows) computes every channel for planes too large to march, and
 //     the vertex class counts;
 //   * the 2D kernel also counts vertex classes (two words per level bin);
@@ -818,8 +818,8 @@ __device__ __forceinline__ void drain_3d(uint64_t *hist, uint32_t *hc, bool crea
 // a min-image pixel happens at the level of the voxel that enters first of
 // the two (last, for the max image), so it is added to that voxel's event:
 // one LDS atomic per voxel.  The surface adds the two vertical faces, the
-// volume is the count.  (The crease measure is a second z-marching kernel,
-// `ecc3d_crease`, below.)
+// volume is the count.  The crease measure, when wanted, comes from the same
+// planes (see March3D).
 //
 // A wave owns TY rows of a strip of 64*VEC columns and marches z, holding the
 // level indices of planes z-1, z, z+1 (TY+2 rows each, packed as in 2D) in
@@ -1015,6 +1015,16 @@ __device__ __forceinline__ uint32_t pattern_pair(const uint32_t (&u)[VEC + 1], c
                              pk_diff(d[j], self), pk_diff(d[j + 1], self));
 }
 
+// pattern of the two cells of `self` from their 8 neighbours in one plane:
+// u = the row that precedes in memory order (wins ties), w/e = the neighbours
+// before/after along the in-row axis, d = the row that follows
+__device__ __forceinline__ uint32_t plane_pattern(uint32_t u0, uint32_t u1, uint32_t u2, uint32_t wv, uint32_t ev,
+                                                  uint32_t d0, uint32_t d1, uint32_t d2, uint32_t self) {
+    const uint32_t self1 = self + 0x00010001u;
+    return gather_offsets<2>(pk_diff(u0, self1), pk_diff(u1, self1), pk_diff(u2, self1), pk_diff(wv, self1),
+                             pk_diff(ev, self), pk_diff(d0, self), pk_diff(d1, self), pk_diff(d2, self));
+}
+
 // per-pixel image of two planes: min (26-C) or max (6-C), packed
 template <bool MAXIMG>
 __device__ __forceinline__ uint32_t pk_merge(uint32_t a, uint32_t b) {
@@ -1031,7 +1041,13 @@ __device__ __forceinline__ uint32_t pk_merge(uint32_t a, uint32_t b) {
 //   tm[p]: 2D EC delta of an image pixel with pattern p, sign included
 // A voxel's low word is tl[p_layer] + (its share of the two images' deltas)
 // - 2 * (vertical neighbours that entered before it) << 22.
-template <typename T, int LM, int AL, bool MAXIMG, int TY, typename TH>
+// With CR the crease channel comes along: the crease of a voxel is the change
+// of kappa over the 12 lattice edges around it; the four edges parallel to one
+// axis are the voxel's corners in the plane normal to that axis, so its delta
+// is the sum of three 2D deltas looked up by the 8-neighbour patterns of its
+// xy (the layer pattern), yz and xz planes (tc: delta + 4 per plane), added to
+// a second, 32-bit bin word as crease + 12.
+template <typename T, int LM, int AL, bool MAXIMG, bool CR, int TY, typename TH>
 struct March3D {
     static constexpr int VEC = Elem3<T>::VEC;
     static constexpr int NR = TY + 2;
@@ -1049,6 +1065,8 @@ struct March3D {
     int y0, zb, lane;
     int64_t last_block;
     uint32_t scratch;  // this lane's scratch bin, W + 2 + lane
+    const uint32_t *tc;  // CR: per-plane crease deltas + 4
+    uint32_t *hc;        // CR: crease words of the bins
 
     uint32_t R[3][NR][VEC + 1];  // level planes; R[(z - za + 1) % 3] holds plane z
     int32_t E[TY][VEC];          // image delta of the pixel below each voxel of the current plane
@@ -1114,6 +1132,7 @@ struct March3D {
         for (int t = 0; t < TY; ++t) {
             // table reads of the row's VEC voxels first, then their atomics
             uint32_t tlv[VEC], pm[VEC / 2], selfv[VEC / 2], below[VEC / 2], above[VEC / 2];
+            uint32_t crv[CR ? VEC : 1];
             int32_t en[VEC];
 #pragma unroll
             for (int q = 0; q < VEC / 2; ++q) {
@@ -1130,6 +1149,18 @@ struct March3D {
                 tlv[2 * q + 1] = lut_hi<uint32_t, 2>(tl, pl);
                 en[2 * q] = lut_lo<int32_t, 2>(tm, pm[q]);
                 en[2 * q + 1] = lut_hi<int32_t, 2>(tm, pm[q]);
+                if constexpr (CR) {
+                    // yz plane through the voxel's column, xz plane through its row
+                    const uint32_t pyz = plane_pattern(Pp[t][j], Pp[t + 1][j], Pp[t + 2][j], Pc[t][j], Pc[t + 2][j],
+                                                       Pn[t][j], Pn[t + 1][j], Pn[t + 2][j], self);
+                    const uint32_t pxz = plane_pattern(Pp[t + 1][j - 1], Pp[t + 1][j], Pp[t + 1][j + 1],
+                                                       Pc[t + 1][j - 1], Pc[t + 1][j + 1], Pn[t + 1][j - 1],
+                                                       Pn[t + 1][j], Pn[t + 1][j + 1], self);
+                    crv[2 * q] = lut_lo<uint32_t, 2>(tc, pl) + lut_lo<uint32_t, 2>(tc, pyz) +
+                                 lut_lo<uint32_t, 2>(tc, pxz);
+                    crv[2 * q + 1] = lut_hi<uint32_t, 2>(tc, pl) + lut_hi<uint32_t, 2>(tc, pyz) +
+                                     lut_hi<uint32_t, 2>(tc, pxz);
+                }
             }
 #pragma unroll
             for (int q = 0; q < VEC / 2; ++q) {
@@ -1155,6 +1186,10 @@ struct March3D {
                 constexpr uint64_t cnt = 1ull << kShiftCnt3;
                 atomicAdd((unsigned long long *)&hist[b0], (unsigned long long)(cnt | lo0));
                 atomicAdd((unsigned long long *)&hist[b1], (unsigned long long)(cnt | lo1));
+                if constexpr (CR) {
+                    atomicAdd(&hc[b0], crv[2 * q]);
+                    atomicAdd(&hc[b1], crv[2 * q + 1]);
+                }
             }
         }
     }
@@ -1174,22 +1209,25 @@ struct March3D {
 
 // Work split: units (column, z) with column = (strip, block of TY rows), z
 // fastest, in equal contiguous ranges per wave.
-template <typename T, int LM, int AL, bool MAXIMG, int TY>
+template <typename T, int LM, int AL, bool MAXIMG, bool CR, int TY>
 __global__ void __launch_bounds__(256)
     ecc3d_stream(const T *__restrict__ data, int64_t d, int64_t h, int64_t w, LevelArgs lv, int32_t lo,
-                 int32_t hi, float cpass, const uint32_t *__restrict__ tables, int32_t *__restrict__ partial,
-                 int64_t z_lo, int64_t z_hi, int accumulate) {
+                 int32_t hi, float cpass, const uint32_t *__restrict__ tables,
+                 const uint32_t *__restrict__ crease_table, int32_t *__restrict__ partial, int64_t z_lo,
+                 int64_t z_hi, int accumulate) {
     constexpr int VEC = Elem3<T>::VEC;
     extern __shared__ uint64_t smem[];
     __shared__ uint32_t tl[256];
     __shared__ int32_t tm[256];
+    __shared__ uint32_t tc[CR ? 256 : 1];
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int W = hi - lo;
     const int L = lv.L;
     const int n_bins = W + 2 + 64;  // 1..W are the window's levels, then a scratch bin per lane
     uint64_t *hist = smem;
-    float *thr_s = reinterpret_cast<float *>(smem + n_bins);
+    uint32_t *hc = reinterpret_cast<uint32_t *>(smem + n_bins);  // CR: crease words
+    float *thr_s = reinterpret_cast<float *>(hc + (CR ? n_bins : 0));
     constexpr bool kThr = LM == LM_AFFINE || LM == LM_SEARCH;
     if (kThr)
         for (int i = tid; i < W + 3; i += 256) {
@@ -1199,7 +1237,11 @@ __global__ void __launch_bounds__(256)
         }
     tl[tid] = tables[tid];
     tm[tid] = (int32_t)tables[256 + tid];
-    for (int b = tid; b < n_bins; b += 256) hist[b] = 0;
+    if constexpr (CR) tc[tid] = crease_table[tid];
+    for (int b = tid; b < n_bins; b += 256) {
+        hist[b] = 0;
+        if constexpr (CR) hc[b] = 0;
+    }
     __syncthreads();
 
     const int G = gridDim.x;
@@ -1216,198 +1258,17 @@ __global__ void __launch_bounds__(256)
         const int64_t zb = za + (u_end - u) < D ? za + (u_end - u) : D;
         const int64_t strip = col % n_strips, yb = col / n_strips;
         const int64_t xs = strip * 64 * VEC;
-        March3D<T, LM, AL, MAXIMG, TY, ThrLds> m{data, (int)d, h, w, lv, thr, lo, W, cpass, tl, tm,
-                                                  hist, xs, xs + (int64_t)lane * VEC, (int)(yb * TY),
-                                                  (int)(z_lo + zb), lane, d * h * w > VEC ? d * h * w - VEC : 0,
-                                                  (uint32_t)(W + 2 + lane)};
+        March3D<T, LM, AL, MAXIMG, CR, TY, ThrLds> m{data, (int)d, h, w, lv, thr, lo, W, cpass, tl, tm,
+                                                      hist, xs, xs + (int64_t)lane * VEC, (int)(yb * TY),
+                                                      (int)(z_lo + zb), lane, d * h * w > VEC ? d * h * w - VEC : 0,
+                                                      (uint32_t)(W + 2 + lane), tc, hc};
         m.run((int)(z_lo + za));
         u += zb - za;
     }
     __syncthreads();
-    drain_3d(hist + 1, nullptr, false, W, lo, L, G, wg, partial, accumulate == 0);
+    drain_3d(hist + 1, CR ? hc + 1 : nullptr, CR, W, lo, L, G, wg, partial, accumulate == 0);
 }
 
-
-// ---------------------------------------------------------------------------
-// 3D crease channel by z-marching
-// ---------------------------------------------------------------------------
-// The crease of a voxel is the change of kappa over the 12 lattice edges
-// around it; the four edges parallel to one axis are the corners of the voxel
-// in the plane normal to that axis, so the voxel's delta is the sum of three
-// 2D deltas, one per axis plane, each looked up by that plane's 8-neighbour
-// "entered before" pattern (tc: delta + 4).  Same plane buffers, work split
-// and z range as the z-marching kernel; bins [crease + 12 : 32 | count : 32].
-
-// pattern of the two cells of `self` from their 8 neighbours in one plane:
-// u = the row that precedes in memory order (wins ties), w/e = the neighbours
-// before/after along the in-row axis, d = the row that follows
-__device__ __forceinline__ uint32_t plane_pattern(uint32_t u0, uint32_t u1, uint32_t u2, uint32_t wv, uint32_t ev,
-                                                  uint32_t d0, uint32_t d1, uint32_t d2, uint32_t self) {
-    const uint32_t self1 = self + 0x00010001u;
-    return gather_offsets<2>(pk_diff(u0, self1), pk_diff(u1, self1), pk_diff(u2, self1), pk_diff(wv, self1),
-                             pk_diff(ev, self), pk_diff(d0, self), pk_diff(d1, self), pk_diff(d2, self));
-}
-
-template <typename T, int LM, int AL, int TY, typename TH>
-struct Crease3D {
-    static constexpr int VEC = Elem3<T>::VEC;
-    static constexpr int NR = TY + 2;
-    const T *__restrict__ data;
-    int d;
-    int64_t h, w;
-    const LevelArgs &lv;
-    const TH &thr;
-    int lo, W;
-    float cpass;
-    const uint32_t *tc;
-    uint64_t *hist;
-    int64_t xs, x0;
-    int y0, zb, lane;
-    int64_t last_block;
-    uint32_t scratch;  // this lane's scratch bin, W + 2 + lane
-
-    uint32_t R[3][NR][VEC + 1];  // level planes; R[(z - za + 1) % 3] holds plane z
-    RawRow3 ring[3][NR];         // raw rows of upcoming planes
-
-    __device__ __forceinline__ int clampz(int z) const { return z < 0 ? 0 : (z >= d ? d - 1 : z); }
-    __device__ __forceinline__ int clampy(int y) const { return y < 0 ? 0 : (y >= (int)h ? (int)h - 1 : y); }
-    __device__ __forceinline__ bool row_ok(int z, int y) const { return z >= 0 && z < d && y >= 0 && y < (int)h; }
-
-    __device__ __forceinline__ void fetch_plane(int z, RawRow3 (&dst)[NR]) {
-#pragma unroll
-        for (int r = 0; r < NR; ++r)
-            fetch_row3<T, AL>(data, h, w, clampz(z), clampy(y0 - 1 + r), xs, x0, lane, last_block, dst[r]);
-    }
-    __device__ __forceinline__ void convert_plane(int z, const RawRow3 (&src)[NR], uint32_t (&dst)[NR][VEC + 1]) {
-#pragma unroll
-        for (int r = 0; r < NR; ++r)
-            convert_row3<T, LM>(src[r], row_ok(z, y0 - 1 + r), w, xs, x0, lane, lv, thr, lo, W, cpass, dst[r]);
-    }
-
-    __device__ __forceinline__ void prologue(int za) {
-        RawRow3 a[NR], b[NR];
-        fetch_plane(za - 1, a);
-        fetch_plane(za, b);
-#pragma unroll
-        for (int k = 0; k < 3; ++k) fetch_plane(za + 1 + k < zb ? za + 1 + k : zb, ring[k]);
-        convert_plane(za - 1, a, R[0]);
-        convert_plane(za, b, R[1]);
-    }
-
-    // voxels of plane z, with K = (z - za) % 3
-    template <int K>
-    __device__ __forceinline__ void step(int z) {
-        uint32_t(&Pp)[NR][VEC + 1] = R[K];
-        uint32_t(&Pc)[NR][VEC + 1] = R[(K + 1) % 3];
-        uint32_t(&Pn)[NR][VEC + 1] = R[(K + 2) % 3];
-        convert_plane(z + 1, ring[K], Pn);
-        fetch_plane(z + 4 < zb ? z + 4 : zb, ring[K]);
-#pragma unroll
-        for (int t = 0; t < TY; ++t) {
-            uint32_t c0[VEC / 2], c1[VEC / 2], self[VEC / 2];
-#pragma unroll
-            for (int q = 0; q < VEC / 2; ++q) {
-                const int j = 2 * q + 1;
-                const uint32_t s0 = Pc[t + 1][j];
-                // xy plane: rows y-1, y, y+1 of plane z
-                const uint32_t pxy = plane_pattern(Pc[t][j - 1], Pc[t][j], Pc[t][j + 1], Pc[t + 1][j - 1],
-                                                   Pc[t + 1][j + 1], Pc[t + 2][j - 1], Pc[t + 2][j], Pc[t + 2][j + 1],
-                                                   s0);
-                // yz plane through the voxel's column: planes z-1, z, z+1 at rows y-1, y, y+1
-                const uint32_t pyz = plane_pattern(Pp[t][j], Pp[t + 1][j], Pp[t + 2][j], Pc[t][j], Pc[t + 2][j],
-                                                   Pn[t][j], Pn[t + 1][j], Pn[t + 2][j], s0);
-                // xz plane through the voxel's row: planes z-1, z, z+1 at columns x-1, x, x+1
-                const uint32_t pxz = plane_pattern(Pp[t + 1][j - 1], Pp[t + 1][j], Pp[t + 1][j + 1], Pc[t + 1][j - 1],
-                                                   Pc[t + 1][j + 1], Pn[t + 1][j - 1], Pn[t + 1][j],
-                                                   Pn[t + 1][j + 1], s0);
-                c0[q] = lut_lo<uint32_t, 2>(tc, pxy) + lut_lo<uint32_t, 2>(tc, pyz) + lut_lo<uint32_t, 2>(tc, pxz);
-                c1[q] = lut_hi<uint32_t, 2>(tc, pxy) + lut_hi<uint32_t, 2>(tc, pyz) + lut_hi<uint32_t, 2>(tc, pxz);
-                self[q] = s0;
-            }
-#pragma unroll
-            for (int q = 0; q < VEC / 2; ++q) {
-                uint32_t b0 = self[q] & 0xFFFFu, b1 = self[q] >> 16;
-                b0 = b0 - 1u < (uint32_t)W ? b0 : scratch;
-                b1 = b1 - 1u < (uint32_t)W ? b1 : scratch;
-                atomicAdd((unsigned long long *)&hist[b0], (unsigned long long)c0[q] | (1ull << 32));
-                atomicAdd((unsigned long long *)&hist[b1], (unsigned long long)c1[q] | (1ull << 32));
-            }
-        }
-    }
-
-    __device__ __forceinline__ void run(int za) {
-        prologue(za);
-        int z = za;
-        for (; z + 3 <= zb; z += 3) {
-            step<0>(z);
-            step<1>(z + 1);
-            step<2>(z + 2);
-        }
-        if (z < zb) step<0>(z);
-        if (z + 1 < zb) step<1>(z + 1);
-    }
-};
-
-template <typename T, int LM, int AL, int TY>
-__global__ void __launch_bounds__(256)
-    ecc3d_crease(const T *__restrict__ data, int64_t d, int64_t h, int64_t w, LevelArgs lv, int32_t lo,
-                 int32_t hi, float cpass, const uint32_t *__restrict__ table, int32_t *__restrict__ partial,
-                 int64_t z_lo, int64_t z_hi, int accumulate) {
-    constexpr int VEC = Elem3<T>::VEC;
-    extern __shared__ uint64_t smem[];
-    __shared__ uint32_t tc[256];
-    const int tid = threadIdx.x, lane = tid & 63;
-    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const int W = hi - lo;
-    const int L = lv.L;
-    const int n_bins = W + 2 + 64;  // 1..W are the window's levels, then a scratch bin per lane
-    uint64_t *hist = smem;
-    float *thr_s = reinterpret_cast<float *>(smem + n_bins);
-    constexpr bool kThr = LM == LM_AFFINE || LM == LM_SEARCH;
-    if (kThr)
-        for (int i = tid; i < W + 3; i += 256) {
-            int k = lo - 2 + i;
-            k = k < 0 ? 0 : (k >= L ? L - 1 : k);
-            thr_s[i] = lv.thr[k];
-        }
-    tc[tid] = table[tid];
-    for (int b = tid; b < n_bins; b += 256) hist[b] = 0;
-    __syncthreads();
-
-    const int G = gridDim.x;
-    const int wg = xcd_order(blockIdx.x, G);
-    const int64_t gw = (int64_t)wg * kWavesPerWG + wave, NW = (int64_t)G * kWavesPerWG;
-    const int64_t D = z_hi - z_lo;
-    const int64_t n_strips = (w + 64 * VEC - 1) / (64 * VEC);
-    const int64_t n_yb = (h + TY - 1) / TY;
-    const int64_t units = n_strips * n_yb * D;
-    const int64_t u_end = units * (gw + 1) / NW;
-    const ThrLds thr{thr_s, lo - 2};
-    for (int64_t u = units * gw / NW; u < u_end;) {
-        const int64_t col = u / D, za = u % D;
-        const int64_t zb = za + (u_end - u) < D ? za + (u_end - u) : D;
-        const int64_t strip = col % n_strips, yb = col / n_strips;
-        const int64_t xs = strip * 64 * VEC;
-        Crease3D<T, LM, AL, TY, ThrLds> m{data, (int)d, h, w, lv, thr, lo, W, cpass, tc, hist, xs,
-                                          xs + (int64_t)lane * VEC, (int)(yb * TY), (int)(z_lo + zb), lane,
-                                          d * h * w > VEC ? d * h * w - VEC : 0, (uint32_t)(W + 2 + lane)};
-        m.run((int)(z_lo + za));
-        u += zb - za;
-    }
-    __syncthreads();
-    // bins -> channel 1 (crease) of the partials
-    const int64_t cs = (int64_t)L * G;
-    for (int b = tid; b < W; b += 256) {
-        const uint64_t v = hist[b + 1];
-        const int64_t n = (int64_t)(v >> 32);
-        const int32_t cr = (int32_t)((int64_t)(v & 0xFFFFFFFFu) - kCreaseBias3 * n);
-        const int64_t i0 = cs + ((int64_t)(lo + b)) * G + wg;
-        if (accumulate == 0)
-            partial[i0] = cr;
-        else
-            partial[i0] += cr;
-    }
-}
 
 // 3D class-count bins [level][class] (int32) -> partials [class][level][workgroup]
 __device__ __forceinline__ void drain_cls3(int32_t *hcls, int W, int lo, int L, int G, int wg,
@@ -1786,29 +1647,7 @@ bool zmarch_3d_fits(int64_t h, int64_t w, int grid) {
     return max_wg_cells_3d(zmarch_3d_columns(h, w), 1, grid) <= kFlush3D;
 }
 
-template <typename T, int LM, int AL>
-static int launch_crease_t(const Launch3D &a, hipStream_t s) {
-    constexpr bool kThr = LM == LM_AFFINE || LM == LM_SEARCH;
-    const int W = a.hi - a.lo;
-    const int64_t cols = zmarch_3d_columns(a.h, a.w);
-    // the same z split as the z-marching launch (the bins count cells too)
-    int64_t chunk = a.z_hi - a.z_lo;
-    while (chunk > 1 && max_wg_cells_3d(cols, chunk, a.grid) > kFlush3D) chunk = (chunk + 1) / 2;
-    if (max_wg_cells_3d(cols, chunk, a.grid) > kFlush3D) return (int)hipErrorInvalidValue;
-    const float cpass = (float)(a.lv.u0d + 1.5 - a.lo);
-    const size_t lds = (size_t)(W + 2 + 64) * 8 + (kThr ? (size_t)(W + 3) * 4 : 0);
-    for (int64_t z0 = a.z_lo; z0 < a.z_hi; z0 += chunk) {
-        const int64_t z1 = z0 + chunk < a.z_hi ? z0 + chunk : a.z_hi;
-        const bool acc = a.accumulate || z0 > a.z_lo;
-        hipLaunchKernelGGL((ecc3d_crease<T, LM, AL, kZmTY>), dim3(a.grid), dim3(256), lds, s, (const T *)a.data,
-                           a.d, a.h, a.w, a.lv, a.lo, a.hi, cpass, a.crease_table, a.partial, z0, z1, acc ? 1 : 0);
-        const int e = (int)hipGetLastError();
-        if (e) return e;
-    }
-    return 0;
-}
-
-template <typename T, int LM, int AL, bool MAXIMG>
+template <typename T, int LM, int AL, bool MAXIMG, bool CR>
 static int launch_zm_t(const Launch3D &a, hipStream_t s) {
     constexpr bool kThr = LM == LM_AFFINE || LM == LM_SEARCH;
     const int W = a.hi - a.lo;
@@ -1818,13 +1657,13 @@ static int launch_zm_t(const Launch3D &a, hipStream_t s) {
     while (chunk > 1 && max_wg_cells_3d(cols, chunk, a.grid) > kFlush3D) chunk = (chunk + 1) / 2;
     if (max_wg_cells_3d(cols, chunk, a.grid) > kFlush3D) return (int)hipErrorInvalidValue;
     const float cpass = (float)(a.lv.u0d + 1.5 - a.lo);
-    const size_t lds = (size_t)(W + 2 + 64) * 8 + (kThr ? (size_t)(W + 3) * 4 : 0);
+    const size_t lds = (size_t)(W + 2 + 64) * (CR ? 12 : 8) + (kThr ? (size_t)(W + 3) * 4 : 0);
     for (int64_t z0 = a.z_lo; z0 < a.z_hi; z0 += chunk) {
         const int64_t z1 = z0 + chunk < a.z_hi ? z0 + chunk : a.z_hi;
         const bool acc = a.accumulate || z0 > a.z_lo;
-        hipLaunchKernelGGL((ecc3d_stream<T, LM, AL, MAXIMG, kZmTY>), dim3(a.grid), dim3(256), lds, s,
-                           (const T *)a.data, a.d, a.h, a.w, a.lv, a.lo, a.hi, cpass, a.zm_tables, a.partial, z0,
-                           z1, acc ? 1 : 0);
+        hipLaunchKernelGGL((ecc3d_stream<T, LM, AL, MAXIMG, CR, kZmTY>), dim3(a.grid), dim3(256), lds, s,
+                           (const T *)a.data, a.d, a.h, a.w, a.lv, a.lo, a.hi, cpass, a.zm_tables, a.crease_table,
+                           a.partial, z0, z1, acc ? 1 : 0);
         const int e = (int)hipGetLastError();
         if (e) return e;
     }
@@ -1836,8 +1675,10 @@ static int launch_zm_al(const Launch3D &a, hipStream_t s) {
     constexpr int VB = Elem3<T>::VEC * (int)sizeof(T);
     const bool al = (uintptr_t)a.data % VB == 0 && (a.w * (int64_t)sizeof(T)) % VB == 0;
     if (a.crease_table)
-        return al ? launch_crease_t<T, LM, kLoadAligned>(a, s) : launch_crease_t<T, LM, kLoadVector>(a, s);
-    return al ? launch_zm_t<T, LM, kLoadAligned, MAXIMG>(a, s) : launch_zm_t<T, LM, kLoadVector, MAXIMG>(a, s);
+        return al ? launch_zm_t<T, LM, kLoadAligned, MAXIMG, true>(a, s)
+                  : launch_zm_t<T, LM, kLoadVector, MAXIMG, true>(a, s);
+    return al ? launch_zm_t<T, LM, kLoadAligned, MAXIMG, false>(a, s)
+              : launch_zm_t<T, LM, kLoadVector, MAXIMG, false>(a, s);
 }
 
 

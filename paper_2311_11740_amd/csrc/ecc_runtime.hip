@@ -520,8 +520,8 @@ ecc_status compute_one(ecc_context ctx, const ecc_field *f, const FieldInfo &fi,
     } else {
         // z-marching kernel: at least ~16 planes per wave; its register use
         // leaves room for two 4-wave workgroups per CU, so one round of
-        // 2 x CUs workgroups (fewer partials than more, smaller rounds).  The
-        // crease channel, when wanted, is a second z-marching launch.
+        // 2 x CUs workgroups (fewer partials than more, smaller rounds); the
+        // crease channel, when wanted, comes along in the same kernel.
         const int64_t units = (int64_t)zmarch_3d_columns(fi.h, fi.w) * fi.d;
         grid = (int)std::min<int64_t>((int64_t)ctx->n_cu * zm_wg_per_cu(),
                                       std::max<int64_t>(1, (units + 63) / 64));
@@ -571,13 +571,8 @@ ecc_status compute_one(ecc_context ctx, const ecc_field *f, const FieldInfo &fi,
             if (s != ECC_OK) return s;
             Launch3D a{data, fi.dtype, fi.d, fi.h, fi.w, lv, lo, hi, ctx->d_vtab3[k], partial, grid,
                        zmarch ? false : crease, zmarch ? ctx->d_zm3[k] : nullptr, k == 1, 0, fi.d, false, false,
-                       nullptr};
+                       zmarch && crease ? ctx->d_crease3 : nullptr};
             int e = launch_3d(a, stream);
-            if (!e && zmarch && crease) {
-                Launch3D c3 = a;
-                c3.crease_table = ctx->d_crease3;
-                e = launch_3d(c3, stream);
-            }
             if (e) return hip_fail(e, "3D kernel launch");
             s = prof_end(ctx, stream, slot);
             if (s != ECC_OK) return s;

@@ -125,12 +125,8 @@ ecc_status stream_field(ecc_context ctx, const ecc_field *f, const FieldInfo &fi
             const int hi = std::min(L, lo + win);
             if (is3) {
                 Launch3D la{data_v, fi.dtype, u1, fi.h, fi.w, lv, lo, hi, ctx->d_vtab3[k], partial, grid, false,
-                            ctx->d_zm3[k], k == 1, a, b, slab > 0, false, nullptr};
+                            ctx->d_zm3[k], k == 1, a, b, slab > 0, false, crease ? ctx->d_crease3 : nullptr};
                 e = launch_3d(la, stream);
-                if (!e && crease) {  // the crease channel: a second z-marching launch
-                    la.crease_table = ctx->d_crease3;
-                    e = launch_3d(la, stream);
-                }
             } else {
                 Launch2D la{data_v, fi.dtype, u1, fi.w, lv, lo, hi, ctx->d_delta2[k], partial, grid,
                             a, b, slab > 0, false};
