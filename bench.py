@@ -36,7 +36,7 @@ METRIC = "EC-curve Gvoxels/s & % HBM peak; batched vs per-field launch; p99 late
 
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
-    for name in ("ecc_kernels.hip", "ecc_internal.h"):
+    for name in ("ecc_device.h", "ecc_k2d.hip", "ecc_k3d.hip", "ecc_kmerge.hip", "ecc_internal.h"):
         with open(os.path.join(ROOT, "paper_2311_11740_amd", "csrc", name), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]

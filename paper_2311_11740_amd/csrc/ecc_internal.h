@@ -162,7 +162,7 @@ int launch_batch_2d(int dtype, int lm, const BatchField2D *fields, const BatchIt
                     const int32_t *wg_first, int grid, const uint64_t *luts, int max_L, void *stream);
 size_t lds_bytes_batch_2d(int lm, int max_L);
 
-// device-side launchers (ecc_kernels.hip); return a hipError_t as int
+// device-side launchers (ecc_k2d.hip, ecc_k3d.hip, ecc_kmerge.hip); return a hipError_t as int
 int launch_2d(const Launch2D &a, void *stream);
 int launch_3d(const Launch3D &a, void *stream);
 // partials [nch][L][grid] int32 -> per-level totals -> running sums into the

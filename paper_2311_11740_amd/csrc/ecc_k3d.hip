@@ -1,0 +1,764 @@
+// 3D kernels: the z-marching kernel (slab decomposition) and the generic tile
+// kernel (curves with the crease measure, vertex class counts), with their
+// launchers.
+#include "ecc_device.h"
+
+namespace ecc {
+
+// ---------------------------------------------------------------------------
+// 3D bins -> partials
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void drain_3d(uint64_t *hist, uint32_t *hc, bool crease, int W, int lo,
+                                         int L, int G, int wg, int32_t *__restrict__ partial, bool first) {
+    for (int b = threadIdx.x; b < W; b += blockDim.x) {
+        const uint64_t v = hist[b];
+        hist[b] = 0;
+        const int64_t n = (int64_t)(v >> kShiftCnt3);
+        const int64_t surf = (int64_t)((v >> kShiftSurf3) & ((1ull << (kShiftCnt3 - kShiftSurf3)) - 1)) -
+                             kSurfBias3 * n;
+        const int64_t ec = (int64_t)(v & ((1ull << kShiftSurf3) - 1)) - kEcBias3 * n;
+        int64_t cr = 0;
+        if (crease) {
+            cr = (int64_t)hc[b] - kCreaseBias3 * n;
+            hc[b] = 0;
+        }
+        const int64_t i0 = ((int64_t)(lo + b)) * G + wg, cs = (int64_t)L * G;
+        // (the crease slot is left alone when the crease is not computed: the
+        // merge skips that channel)
+        if (first) {
+            partial[i0] = (int32_t)ec;
+            if (crease) partial[i0 + cs] = (int32_t)cr;
+            partial[i0 + 2 * cs] = (int32_t)surf;
+            partial[i0 + 3 * cs] = (int32_t)n;
+        } else {
+            partial[i0] += (int32_t)ec;
+            if (crease) partial[i0 + cs] += (int32_t)cr;
+            partial[i0 + 2 * cs] += (int32_t)surf;
+            partial[i0 + 3 * cs] += (int32_t)n;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// 3D: slab decomposition, z-marching waves
+// ---------------------------------------------------------------------------
+// The closure of the active voxels splits into lattice cells that lie in a
+// z-plane Z (vertices, x/y edges, xy faces) and cells that span a voxel layer
+// z (z edges, xz/yz faces, voxels).  A cell in plane Z is present exactly when
+// the 2D cell under it is present in the image min(lam[Z-1], lam[Z]) (the
+// "min image"); a cell spanning layer z when its 2D counterpart is present in
+// layer z, with dimension one higher.  Hence for the 26-connected EC
+//   chi26 = sum_Z chi8(min image Z) - sum_z chi8(layer z),
+// and dually, for the 6-connected complex (cells = voxels),
+//   chi6 = sum_z chi4(layer z) - sum_Z chi4(max(lam[Z-1], lam[Z])).
+// So every voxel needs two 2D 8-neighbour patterns: its own layer's, and the
+// one of the min (max) image between its layer and the next.  The 2D event of
+// a min-image pixel happens at the level of the voxel that enters first of
+// the two (last, for the max image), so it is added to that voxel's event:
+// one LDS atomic per voxel.  The surface adds the two vertical faces, the
+// volume is the count.  The crease measure, when wanted, comes from the same
+// planes (see March3D).
+//
+// A wave owns TY rows of a strip of 64*VEC columns and marches z, holding the
+// level indices of planes z-1, z, z+1 (TY+2 rows each, packed as in 2D) in
+// three buffers that rotate with z.  The cells left and right of the strip
+// come from one extra unconditional element load per lane and row.
+template <typename T>
+struct Elem3 {
+    static constexpr int VEC = 4;                    // cells per lane
+    static constexpr int WORDS = 4 * sizeof(T) / 4;  // raw dwords per lane and row
+};
+
+struct RawRow3 {
+    uint32_t w[4];
+    uint32_t halo;   // lane 0: element left of the strip; lane 63: right of it
+    uint32_t shift;  // elements the block must move down (kLoadVector at the buffer end)
+};
+
+template <typename T>
+__device__ __forceinline__ uint32_t elem_bits(const T *p) {
+    if constexpr (sizeof(T) == 4)
+        return __float_as_uint(*p);
+    else
+        return (uint32_t)*p;
+}
+
+template <typename T>
+__device__ __forceinline__ uint32_t elem3(const RawRow3 &r, int i) {
+    if constexpr (sizeof(T) == 1) return (r.w[0] >> (8 * i)) & 0xFFu;
+    else if constexpr (sizeof(T) == 2) return (r.w[i >> 1] >> (16 * (i & 1))) & 0xFFFFu;
+    else return r.w[i];
+}
+
+// one block of VEC elements (4 * sizeof(T) bytes) at element index e
+template <typename T, bool UNALIGNED>
+__device__ __forceinline__ void load_block3(const T *p, RawRow3 &raw) {
+    if constexpr (sizeof(T) == 1) {
+        typedef uint32_t u32_u __attribute__((aligned(1)));
+        typedef uint32_t u32_a __attribute__((aligned(4)));
+        if constexpr (UNALIGNED)
+            raw.w[0] = __builtin_nontemporal_load(reinterpret_cast<const u32_u *>(p));
+        else
+            raw.w[0] = __builtin_nontemporal_load(reinterpret_cast<const u32_a *>(p));
+    } else if constexpr (sizeof(T) == 2) {
+        typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+        typedef u32x2 u32x2_u __attribute__((aligned(1)));
+        u32x2 q;
+        if constexpr (UNALIGNED)
+            q = __builtin_nontemporal_load(reinterpret_cast<const u32x2_u *>(p));
+        else
+            q = __builtin_nontemporal_load(reinterpret_cast<const u32x2 *>(p));
+        raw.w[0] = q.x; raw.w[1] = q.y;
+    } else {
+        u32x4 q;
+        if constexpr (UNALIGNED)
+            q = __builtin_nontemporal_load(reinterpret_cast<const u32x4_u *>(p));
+        else
+            q = __builtin_nontemporal_load(reinterpret_cast<const u32x4 *>(p));
+        raw.w[0] = q.x; raw.w[1] = q.y; raw.w[2] = q.z; raw.w[3] = q.w;
+    }
+}
+
+// row y of plane z (both clamped into the field by the caller); unconditional
+// loads, in the two modes of the 2D kernels (a block is 4 elements here)
+template <typename T, int AL>
+__device__ __forceinline__ void fetch_row3(const T *__restrict__ data, int64_t h, int64_t w, int z, int y,
+                                           int64_t xs, int64_t x0, int lane, int64_t last_block, RawRow3 &raw) {
+    constexpr int VEC = Elem3<T>::VEC;
+    const int64_t rbase = ((int64_t)z * h + y) * w;
+    const T *row = data + rbase;
+    raw.w[0] = raw.w[1] = raw.w[2] = raw.w[3] = 0;
+    raw.shift = 0;
+    if constexpr (AL == kLoadAligned) {  // whole blocks: inside or outside the row
+        load_block3<T, false>(row + (x0 < w ? x0 : 0), raw);
+    } else {
+        const int64_t li = rbase + (x0 < w ? x0 : 0);
+        const int64_t lc = li < last_block ? li : last_block;  // last_block = d * h * w - VEC
+        load_block3<T, true>(data + lc, raw);
+        raw.shift = (uint32_t)(li - lc);
+    }
+    int64_t hx = lane == 0 ? xs - 1 : (lane == 63 ? xs + 64 * VEC : x0);
+    hx = hx < 0 ? 0 : (hx >= w ? w - 1 : hx);
+    raw.halo = elem_bits(row + hx);
+}
+
+template <typename T>
+__device__ __forceinline__ void unshift_row3(RawRow3 &raw) {
+    const uint32_t sb = raw.shift * (uint32_t)sizeof(T);  // bytes, < 4 * sizeof(T)
+    uint64_t lo = (uint64_t)raw.w[0] | (uint64_t)raw.w[1] << 32;
+    uint64_t hi = (uint64_t)raw.w[2] | (uint64_t)raw.w[3] << 32;
+    if (sb >= 8) {
+        lo = hi >> (8 * (sb - 8));
+        hi = 0;
+    } else if (sb > 0) {
+        lo = (lo >> (8 * sb)) | (hi << (64 - 8 * sb));
+        hi >>= 8 * sb;
+    }
+    raw.w[0] = (uint32_t)lo; raw.w[1] = (uint32_t)(lo >> 32);
+    raw.w[2] = (uint32_t)hi; raw.w[3] = (uint32_t)(hi >> 32);
+}
+
+template <typename T, int LM, typename TH>
+__device__ __forceinline__ uint32_t level3(uint32_t bits, const LevelArgs &lv, const TH &thr, int lo, int W,
+                                           float cpass) {
+    const int base = lo - 1;
+    const uint32_t never = (uint32_t)(W + 1);
+    if constexpr (LM == LM_AFFINE) {
+        const float x = __uint_as_float(bits);
+        const float y = __builtin_fmaf(x, lv.inv_step, cpass);
+        const float m = y + kMagic;
+        const float r = y - (m - kMagic);
+        // clamped estimate of lam' (at least 1 in the first pass: values at
+        // or below t0 have level 0)
+        const float mlo = lo == 0 ? kMagic + 1.0f : kMagic;
+        uint32_t l = __float_as_uint(__builtin_amdgcn_fmed3f(m, mlo, kMagic + (float)never)) - kMagicBits;
+        if (!(__builtin_fabsf(r) <= 0.5f - lv.eps)) {  // near a threshold (or NaN / inf)
+            const int k = (int)l;
+            if (k >= 0 && k <= W + 1) {
+                const int g0 = k + base < 0 ? 0 : k + base;
+                const int g = (int)level_settle(x, (uint32_t)g0, lv.L, thr);
+                l = (uint32_t)min(max(g - base, 0), (int)never);
+            }
+        }
+        return l;
+    } else if constexpr (LM == LM_SEARCH) {
+        return level_search_window(__uint_as_float(bits), lo, lo + W, thr);
+    } else {
+        const int l = (int)level_of<T, LM>(as_value<T>(bits), lv, thr);
+        return (uint32_t)min(max(l - base, 0), (int)never);
+    }
+}
+
+// packed level pairs of one row (P[i] = (lam'[i-1], lam'[i]) with the strip
+// neighbours at both ends); rows outside the field are "never"
+template <typename T, int LM, typename TH>
+__device__ __forceinline__ void convert_row3(const RawRow3 &raw_in, bool row_ok, int64_t w, int64_t xs, int64_t x0,
+                                             int lane, const LevelArgs &lv, const TH &thr, int lo, int W,
+                                             float cpass, uint32_t (&P)[Elem3<T>::VEC + 1]) {
+    constexpr int VEC = Elem3<T>::VEC;
+    const uint32_t never = (uint32_t)(W + 1);
+    if (!row_ok) {  // uniform
+#pragma unroll
+        for (int i = 0; i <= VEC; ++i) P[i] = never | never << 16;
+        return;
+    }
+    RawRow3 raw = raw_in;
+    if (__any(raw.shift != 0)) unshift_row3<T>(raw);  // rare: blocks at the end of the buffer
+    if constexpr (LM == LM_IDENTITY) {  // integer values, two per packed operation
+        const uint32_t lo2 = (uint32_t)lo * 0x10001u, nv2 = never * 0x10001u;
+        uint32_t Q0 = identity_pair(raw_pair<T>(raw.w, 0), lo2, nv2);
+        uint32_t Q1 = identity_pair(raw_pair<T>(raw.w, 2), lo2, nv2);
+        if (!(xs + 64 * VEC <= w)) {  // uniform: cells outside the field never enter
+            const uint32_t m0 = (x0 < w ? 0u : 0xFFFFu) | (x0 + 1 < w ? 0u : 0xFFFF0000u);
+            const uint32_t m1 = (x0 + 2 < w ? 0u : 0xFFFFu) | (x0 + 3 < w ? 0u : 0xFFFF0000u);
+            Q0 = (Q0 & ~m0) | (nv2 & m0);
+            Q1 = (Q1 & ~m1) | (nv2 & m1);
+        }
+        const uint32_t hl = level3<T, LM>(raw.halo, lv, thr, lo, W, cpass);
+        uint32_t lq = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)Q1, 0x138, 0xf, 0xf, false);
+        uint32_t rq = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)Q0, 0x130, 0xf, 0xf, false);
+        if (lane == 0) lq = (xs > 0 ? hl : never) << 16;
+        if (lane == 63) rq = xs + 64 * VEC < w ? hl : never;
+        P[0] = straddle(lq, Q0);
+        P[1] = Q0;
+        P[2] = straddle(Q0, Q1);
+        P[3] = Q1;
+        P[4] = straddle(Q1, rq);
+        return;
+    }
+    uint32_t lam[VEC];
+#pragma unroll
+    for (int i = 0; i < VEC; ++i)
+        lam[i] = x0 + i < w ? level3<T, LM>(elem3<T>(raw, i), lv, thr, lo, W, cpass) : never;
+    const uint32_t hl = level3<T, LM>(raw.halo, lv, thr, lo, W, cpass);
+    uint32_t left = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)lam[VEC - 1], 0x138, 0xf, 0xf, false);
+    uint32_t right = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)lam[0], 0x130, 0xf, 0xf, false);
+    if (lane == 0) left = xs > 0 ? hl : never;
+    if (lane == 63) right = xs + 64 * VEC < w ? hl : never;
+    P[0] = pack_lo16(left, lam[0]);
+#pragma unroll
+    for (int i = 1; i < VEC; ++i) P[i] = pack_lo16(lam[i - 1], lam[i]);
+    P[VEC] = pack_lo16(lam[VEC - 1], right);
+}
+
+// 8-neighbour "entered before" pattern of the two cells of pair j (low / high
+// half), rows u (above), m (current), d (below), as offsets into tables of
+// 4-byte entries (lut_lo / lut_hi)
+template <int VEC>
+__device__ __forceinline__ uint32_t pattern_pair(const uint32_t (&u)[VEC + 1], const uint32_t (&m)[VEC + 1],
+                                                 const uint32_t (&d)[VEC + 1], int j) {
+    const uint32_t self = m[j], self1 = self + 0x00010001u;
+    return gather_offsets<2>(pk_diff(u[j - 1], self1), pk_diff(u[j], self1), pk_diff(u[j + 1], self1),
+                             pk_diff(m[j - 1], self1), pk_diff(m[j + 1], self), pk_diff(d[j - 1], self),
+                             pk_diff(d[j], self), pk_diff(d[j + 1], self));
+}
+
+// pattern of the two cells of `self` from their 8 neighbours in one plane:
+// u = the row that precedes in memory order (wins ties), w/e = the neighbours
+// before/after along the in-row axis, d = the row that follows
+__device__ __forceinline__ uint32_t plane_pattern(uint32_t u0, uint32_t u1, uint32_t u2, uint32_t wv, uint32_t ev,
+                                                  uint32_t d0, uint32_t d1, uint32_t d2, uint32_t self) {
+    const uint32_t self1 = self + 0x00010001u;
+    return gather_offsets<2>(pk_diff(u0, self1), pk_diff(u1, self1), pk_diff(u2, self1), pk_diff(wv, self1),
+                             pk_diff(ev, self), pk_diff(d0, self), pk_diff(d1, self), pk_diff(d2, self));
+}
+
+// per-pixel image of two planes: min (26-C) or max (6-C), packed
+template <bool MAXIMG>
+__device__ __forceinline__ uint32_t pk_merge(uint32_t a, uint32_t b) {
+    const u16x2 x = __builtin_bit_cast(u16x2, a), y = __builtin_bit_cast(u16x2, b);
+    if constexpr (MAXIMG)
+        return __builtin_bit_cast(uint32_t, __builtin_elementwise_max(x, y));
+    else
+        return __builtin_bit_cast(uint32_t, __builtin_elementwise_min(x, y));
+}
+
+// LDS tables (set up by the host, 256 entries each):
+//   tl[p]: layer term of a voxel with layer pattern p, packed as the low
+//          word of a 3D bin: (+-EC of the 2D cell) + 7 + (perimeter + 8) << 22
+//   tm[p]: 2D EC delta of an image pixel with pattern p, sign included
+// A voxel's low word is tl[p_layer] + (its share of the two images' deltas)
+// - 2 * (vertical neighbours that entered before it) << 22.
+// With CR the crease channel comes along: the crease of a voxel is the change
+// of kappa over the 12 lattice edges around it; the four edges parallel to one
+// axis are the voxel's corners in the plane normal to that axis, so its delta
+// is the sum of three 2D deltas looked up by the 8-neighbour patterns of its
+// xy (the layer pattern), yz and xz planes (tc: delta + 4 per plane), added to
+// a second, 32-bit bin word as crease + 12.
+template <typename T, int LM, int AL, bool MAXIMG, bool CR, int TY, typename TH>
+struct March3D {
+    static constexpr int VEC = Elem3<T>::VEC;
+    static constexpr int NR = TY + 2;
+    const T *__restrict__ data;
+    int d;
+    int64_t h, w;
+    const LevelArgs &lv;
+    const TH &thr;
+    int lo, W;
+    float cpass;
+    const uint32_t *tl;
+    const int32_t *tm;
+    uint64_t *hist;
+    int64_t xs, x0;
+    int y0, zb, lane;
+    int64_t last_block;
+    uint32_t scratch;  // this lane's scratch bin, W + 2 + lane
+    const uint32_t *tc;  // CR: per-plane crease deltas + 4
+    uint32_t *hc;        // CR: crease words of the bins
+
+    uint32_t R[3][NR][VEC + 1];  // level planes; R[(z - za + 1) % 3] holds plane z
+    int32_t E[TY][VEC];          // image delta of the pixel below each voxel of the current plane
+    RawRow3 ring[3][NR];         // raw rows of upcoming planes; ring[(z - za) % 3] holds plane z + 1
+
+    __device__ __forceinline__ int clampz(int z) const { return z < 0 ? 0 : (z >= d ? d - 1 : z); }
+    __device__ __forceinline__ int clampy(int y) const { return y < 0 ? 0 : (y >= (int)h ? (int)h - 1 : y); }
+    __device__ __forceinline__ bool row_ok(int z, int y) const { return z >= 0 && z < d && y >= 0 && y < (int)h; }
+
+    __device__ __forceinline__ void fetch_plane(int z, RawRow3 (&dst)[NR]) {
+#pragma unroll
+        for (int r = 0; r < NR; ++r)
+            fetch_row3<T, AL>(data, h, w, clampz(z), clampy(y0 - 1 + r), xs, x0, lane, last_block, dst[r]);
+    }
+    __device__ __forceinline__ void convert_plane(int z, const RawRow3 (&src)[NR], uint32_t (&dst)[NR][VEC + 1]) {
+#pragma unroll
+        for (int r = 0; r < NR; ++r)
+            convert_row3<T, LM>(src[r], row_ok(z, y0 - 1 + r), w, xs, x0, lane, lv, thr, lo, W, cpass, dst[r]);
+    }
+    __device__ __forceinline__ void image(const uint32_t (&a)[NR][VEC + 1], const uint32_t (&b)[NR][VEC + 1],
+                                          uint32_t (&m)[NR][VEC + 1]) {
+#pragma unroll
+        for (int r = 0; r < NR; ++r)
+#pragma unroll
+            for (int i = 0; i <= VEC; ++i) m[r][i] = pk_merge<MAXIMG>(a[r][i], b[r][i]);
+    }
+
+    // planes za-1 and za converted, E of the image between them, planes
+    // za+1 .. za+3 in flight
+    __device__ __forceinline__ void prologue(int za) {
+        {
+            RawRow3 a[NR], b[NR];
+            fetch_plane(za - 1, a);
+            fetch_plane(za, b);
+#pragma unroll
+            for (int k = 0; k < 3; ++k) fetch_plane(za + 1 + k < zb ? za + 1 + k : zb, ring[k]);
+            convert_plane(za - 1, a, R[0]);
+            convert_plane(za, b, R[1]);
+        }
+        uint32_t M[NR][VEC + 1];
+        image(R[0], R[1], M);
+#pragma unroll
+        for (int t = 0; t < TY; ++t)
+#pragma unroll
+            for (int j = 1; j < VEC + 1; j += 2) {
+                const uint32_t pm = pattern_pair<VEC>(M[t], M[t + 1], M[t + 2], j);
+                E[t][j - 1] = lut_lo<int32_t, 2>(tm, pm);
+                E[t][j] = lut_hi<int32_t, 2>(tm, pm);
+            }
+    }
+
+    // voxels of plane z, with K = (z - za) % 3
+    template <int K>
+    __device__ __forceinline__ void step(int z) {
+        uint32_t(&Pp)[NR][VEC + 1] = R[K];
+        uint32_t(&Pc)[NR][VEC + 1] = R[(K + 1) % 3];
+        uint32_t(&Pn)[NR][VEC + 1] = R[(K + 2) % 3];
+        convert_plane(z + 1, ring[K], Pn);
+        fetch_plane(z + 4 < zb ? z + 4 : zb, ring[K]);
+        uint32_t M[NR][VEC + 1];
+        image(Pc, Pn, M);
+#pragma unroll
+        for (int t = 0; t < TY; ++t) {
+            // table reads of the row's VEC voxels first, then their atomics
+            uint32_t tlv[VEC], pm[VEC / 2], selfv[VEC / 2], below[VEC / 2], above[VEC / 2];
+            uint32_t crv[CR ? VEC : 1];
+            int32_t en[VEC];
+#pragma unroll
+            for (int q = 0; q < VEC / 2; ++q) {
+                const int j = 2 * q + 1;
+                const uint32_t self = Pc[t + 1][j], self1 = self + 0x00010001u;
+                const uint32_t pl = pattern_pair<VEC>(Pc[t], Pc[t + 1], Pc[t + 2], j);
+                pm[q] = pattern_pair<VEC>(M[t], M[t + 1], M[t + 2], j);
+                // vertical neighbours: the one below (z-1) precedes on ties,
+                // the one above (z+1) does not
+                below[q] = pk_lt(Pp[t + 1][j], self1);
+                above[q] = pk_lt(Pn[t + 1][j], self);
+                selfv[q] = self;
+                tlv[2 * q] = lut_lo<uint32_t, 2>(tl, pl);
+                tlv[2 * q + 1] = lut_hi<uint32_t, 2>(tl, pl);
+                en[2 * q] = lut_lo<int32_t, 2>(tm, pm[q]);
+                en[2 * q + 1] = lut_hi<int32_t, 2>(tm, pm[q]);
+                if constexpr (CR) {
+                    // yz plane through the voxel's column, xz plane through its row
+                    const uint32_t pyz = plane_pattern(Pp[t][j], Pp[t + 1][j], Pp[t + 2][j], Pc[t][j], Pc[t + 2][j],
+                                                       Pn[t][j], Pn[t + 1][j], Pn[t + 2][j], self);
+                    const uint32_t pxz = plane_pattern(Pp[t + 1][j - 1], Pp[t + 1][j], Pp[t + 1][j + 1],
+                                                       Pc[t + 1][j - 1], Pc[t + 1][j + 1], Pn[t + 1][j - 1],
+                                                       Pn[t + 1][j], Pn[t + 1][j + 1], self);
+                    crv[2 * q] = lut_lo<uint32_t, 2>(tc, pl) + lut_lo<uint32_t, 2>(tc, pyz) +
+                                 lut_lo<uint32_t, 2>(tc, pxz);
+                    crv[2 * q + 1] = lut_hi<uint32_t, 2>(tc, pl) + lut_hi<uint32_t, 2>(tc, pyz) +
+                                     lut_hi<uint32_t, 2>(tc, pxz);
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < VEC / 2; ++q) {
+                const int j = 2 * q + 1;
+                // an image pixel's event goes to the voxel of its pair that
+                // enters first (min image) or last (max image)
+                const uint32_t tb = MAXIMG ? below[q] : below[q] ^ 0x00010001u;
+                const uint32_t ta = MAXIMG ? above[q] : above[q] ^ 0x00010001u;
+                const uint32_t nb = below[q] + above[q];  // per half: vertical neighbours already in
+                const uint32_t lo0 = tlv[2 * q] + (uint32_t)((tb & 1u) ? E[t][j - 1] : 0) +
+                                     (uint32_t)((ta & 1u) ? en[2 * q] : 0) - ((nb & 0xFFFFu) << 23);
+                const uint32_t lo1 = tlv[2 * q + 1] + (uint32_t)((tb >> 16) ? E[t][j] : 0) +
+                                     (uint32_t)((ta >> 16) ? en[2 * q + 1] : 0) - ((nb >> 16) << 23);
+                E[t][j - 1] = en[2 * q];
+                E[t][j] = en[2 * q + 1];
+                const uint32_t self = selfv[q];
+                // bins lam' (1..W); a voxel outside the window or the field goes
+                // to its lane's own scratch bin (never drained) rather than
+                // branching: one address per lane keeps such voxels apart
+                uint32_t b0 = self & 0xFFFFu, b1 = self >> 16;
+                b0 = b0 - 1u < (uint32_t)W ? b0 : scratch;
+                b1 = b1 - 1u < (uint32_t)W ? b1 : scratch;
+                constexpr uint64_t cnt = 1ull << kShiftCnt3;
+                atomicAdd((unsigned long long *)&hist[b0], (unsigned long long)(cnt | lo0));
+                atomicAdd((unsigned long long *)&hist[b1], (unsigned long long)(cnt | lo1));
+                if constexpr (CR) {
+                    atomicAdd(&hc[b0], crv[2 * q]);
+                    atomicAdd(&hc[b1], crv[2 * q + 1]);
+                }
+            }
+        }
+    }
+
+    __device__ __forceinline__ void run(int za) {
+        prologue(za);
+        int z = za;
+        for (; z + 3 <= zb; z += 3) {
+            step<0>(z);
+            step<1>(z + 1);
+            step<2>(z + 2);
+        }
+        if (z < zb) step<0>(z);
+        if (z + 1 < zb) step<1>(z + 1);
+    }
+};
+
+// Work split: units (column, z) with column = (strip, block of TY rows), z
+// fastest, in equal contiguous ranges per wave.
+template <typename T, int LM, int AL, bool MAXIMG, bool CR, int TY>
+__global__ void __launch_bounds__(256)
+    ecc3d_stream(const T *__restrict__ data, int64_t d, int64_t h, int64_t w, LevelArgs lv, int32_t lo,
+                 int32_t hi, float cpass, const uint32_t *__restrict__ tables,
+                 const uint32_t *__restrict__ crease_table, int32_t *__restrict__ partial, int64_t z_lo,
+                 int64_t z_hi, int accumulate) {
+    constexpr int VEC = Elem3<T>::VEC;
+    extern __shared__ uint64_t smem[];
+    __shared__ uint32_t tl[256];
+    __shared__ int32_t tm[256];
+    __shared__ uint32_t tc[CR ? 256 : 1];
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int W = hi - lo;
+    const int L = lv.L;
+    const int n_bins = W + 2 + 64;  // 1..W are the window's levels, then a scratch bin per lane
+    uint64_t *hist = smem;
+    uint32_t *hc = reinterpret_cast<uint32_t *>(smem + n_bins);  // CR: crease words
+    float *thr_s = reinterpret_cast<float *>(hc + (CR ? n_bins : 0));
+    constexpr bool kThr = LM == LM_AFFINE || LM == LM_SEARCH;
+    if (kThr)
+        for (int i = tid; i < W + 3; i += 256) {
+            int k = lo - 2 + i;
+            k = k < 0 ? 0 : (k >= L ? L - 1 : k);
+            thr_s[i] = lv.thr[k];
+        }
+    tl[tid] = tables[tid];
+    tm[tid] = (int32_t)tables[256 + tid];
+    if constexpr (CR) tc[tid] = crease_table[tid];
+    for (int b = tid; b < n_bins; b += 256) {
+        hist[b] = 0;
+        if constexpr (CR) hc[b] = 0;
+    }
+    __syncthreads();
+
+    const int G = gridDim.x;
+    const int wg = xcd_order(blockIdx.x, G);
+    const int64_t gw = (int64_t)wg * kWavesPerWG + wave, NW = (int64_t)G * kWavesPerWG;
+    const int64_t D = z_hi - z_lo;
+    const int64_t n_strips = (w + 64 * VEC - 1) / (64 * VEC);
+    const int64_t n_yb = (h + TY - 1) / TY;
+    const int64_t units = n_strips * n_yb * D;
+    const int64_t u_end = units * (gw + 1) / NW;
+    const ThrLds thr{thr_s, lo - 2};
+    for (int64_t u = units * gw / NW; u < u_end;) {
+        const int64_t col = u / D, za = u % D;
+        const int64_t zb = za + (u_end - u) < D ? za + (u_end - u) : D;
+        const int64_t strip = col % n_strips, yb = col / n_strips;
+        const int64_t xs = strip * 64 * VEC;
+        March3D<T, LM, AL, MAXIMG, CR, TY, ThrLds> m{data, (int)d, h, w, lv, thr, lo, W, cpass, tl, tm,
+                                                      hist, xs, xs + (int64_t)lane * VEC, (int)(yb * TY),
+                                                      (int)(z_lo + zb), lane, d * h * w > VEC ? d * h * w - VEC : 0,
+                                                      (uint32_t)(W + 2 + lane), tc, hc};
+        m.run((int)(z_lo + za));
+        u += zb - za;
+    }
+    __syncthreads();
+    drain_3d(hist + 1, CR ? hc + 1 : nullptr, CR, W, lo, L, G, wg, partial, accumulate == 0);
+}
+
+
+// 3D class-count bins [level][class] (int32) -> partials [class][level][workgroup]
+__device__ __forceinline__ void drain_cls3(int32_t *hcls, int W, int lo, int L, int G, int wg,
+                                           int32_t *__restrict__ partial, bool first) {
+    for (int i = threadIdx.x; i < W * kNumClasses3D; i += blockDim.x) {
+        const int b = i / kNumClasses3D, c = i - b * kNumClasses3D;
+        const int32_t v = hcls[i];
+        hcls[i] = 0;
+        const int64_t idx = ((int64_t)c * L + lo + b) * G + wg;
+        if (first)
+            partial[idx] = v;
+        else
+            partial[idx] += v;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// 3D (generic: every channel, table lookups over the 8 corner blocks)
+// ---------------------------------------------------------------------------
+// MODE 0: EC, surface, volume; 1: also the crease; 2: vertex class counts
+// (vtab then holds the class of each octant mask, -1 for empty, and each
+// corner adds +1 to its new class and -1 to its old one in the cell's bin).
+template <typename T, int LM, int MODE>
+__global__ void __launch_bounds__(256)
+    ecc3d_tile(const T *__restrict__ data, int64_t d, int64_t h, int64_t w, LevelArgs lv,
+               int32_t lo, int32_t hi, const int64_t *__restrict__ vtab,
+               int32_t *__restrict__ partial, int64_t tiles_x, int64_t tiles_y, int64_t n_tiles,
+               int flush_tiles) {
+    constexpr bool CREASE = MODE == 1;
+    constexpr int TX = kTile3DX, TY = kTile3DY, TZ = kTile3DZ;
+    constexpr int SX = TX + 2, SY = TY + 2, SZ = TZ + 2;
+    extern __shared__ uint64_t smem[];
+    __shared__ int64_t vt[256];
+    __shared__ uint16_t lam[SZ][SY][SX];
+
+    const int t = threadIdx.x;
+    const int W = hi - lo;
+    const int L = lv.L;
+    uint64_t *hist = smem;
+    uint32_t *hc = reinterpret_cast<uint32_t *>(smem + W);
+    int32_t *hcls = reinterpret_cast<int32_t *>(smem);  // MODE 2: [W][kNumClasses3D]
+    const int G = gridDim.x;
+    const int wg = xcd_order(blockIdx.x, G);
+    const int64_t t_beg = n_tiles * wg / G, t_end = n_tiles * (wg + 1) / G;
+
+    vt[t] = vtab[t];
+    if constexpr (MODE == 2) {
+        for (int b = t; b < W * kNumClasses3D; b += 256) hcls[b] = 0;
+    } else {
+        for (int b = t; b < W; b += 256) {
+            hist[b] = 0;
+            if (CREASE) hc[b] = 0;
+        }
+    }
+    bool first = true;
+    int since = 0;
+    const int lx = t % TX, ly = t / TX;
+    __syncthreads();
+
+    for (int64_t tile = t_beg; tile < t_end; ++tile) {
+        const int64_t x0 = (tile % tiles_x) * TX;
+        const int64_t y0 = ((tile / tiles_x) % tiles_y) * TY;
+        const int64_t z0 = (tile / (tiles_x * tiles_y)) * TZ;
+        for (int e = t; e < SZ * SY * SX; e += 256) {
+            const int xx = e % SX, rest = e / SX;
+            const int yy = rest % SY, zz = rest / SY;
+            const int64_t x = x0 - 1 + xx, y = y0 - 1 + yy, z = z0 - 1 + zz;
+            uint32_t l = (uint32_t)L;
+            if (x >= 0 && x < w && y >= 0 && y < h && z >= 0 && z < d)
+                l = level_of<T, LM>(data[(z * h + y) * w + x], lv, ThrGlobal{lv.thr});
+            lam[zz][yy][xx] = (uint16_t)l;
+        }
+        __syncthreads();
+        if (x0 + lx < w && y0 + ly < h) {
+            // 3x3x3 window: win[k], k = (dz+1)*9 + (dy+1)*3 + (dx+1)
+            uint32_t win[27];
+#pragma unroll
+            for (int pz = 0; pz < 2; ++pz)
+#pragma unroll
+                for (int dy = 0; dy < 3; ++dy)
+#pragma unroll
+                    for (int dx = 0; dx < 3; ++dx) win[9 + pz * 9 + dy * 3 + dx] = lam[pz][ly + dy][lx + dx];
+            const int planes = (int)(d - z0 < TZ ? d - z0 : TZ);
+            for (int z = 0; z < planes; ++z) {
+#pragma unroll
+                for (int k = 0; k < 18; ++k) win[k] = win[k + 9];
+#pragma unroll
+                for (int dy = 0; dy < 3; ++dy)
+#pragma unroll
+                    for (int dx = 0; dx < 3; ++dx) win[18 + dy * 3 + dx] = lam[z + 2][ly + dy][lx + dx];
+                const uint32_t p = win[13];
+                if (p - (uint32_t)lo >= (uint32_t)W) continue;
+                // bit k set when neighbour k entered before p (earlier in memory
+                // order wins ties); the centre bit stands for p itself
+                uint32_t P = 1u << 13;
+#pragma unroll
+                for (int k = 0; k < 27; ++k) {
+                    if (k == 13) continue;
+                    const bool pr = k < 13 ? (win[k] <= p) : (win[k] < p);
+                    P |= (uint32_t)pr << k;
+                }
+                // corner (cz,cy,cx) of p: its 2x2x2 block holds the neighbours
+                // with offsets in {c-1, c} per axis; gather them into the
+                // octant mask (bit bx + 2by + 4bz), with and without p
+                if constexpr (MODE == 2) {
+                    int32_t *row = hcls + (p - lo) * kNumClasses3D;
+#pragma unroll
+                    for (int c = 0; c < 8; ++c) {
+                        const int cx = c & 1, cy = c >> 1 & 1, cz = c >> 2;
+                        const uint32_t y = P >> (cz * 9 + cy * 3 + cx);
+                        const uint32_t m1 = (y & 3u) | ((y >> 1) & 0xCu) | ((y >> 5) & 0x30u) | ((y >> 6) & 0xC0u);
+                        const uint32_t m0 = m1 & ~(1u << (7 - c));
+                        const int cn = (int)vt[m1], co = (int)vt[m0];
+                        atomicAdd(&row[cn], 1);
+                        if (co >= 0) atomicAdd(&row[co], -1);
+                    }
+                    continue;
+                }
+                int64_t acc = 0;
+#pragma unroll
+                for (int c = 0; c < 8; ++c) {
+                    const int cx = c & 1, cy = c >> 1 & 1, cz = c >> 2;
+                    const uint32_t y = P >> (cz * 9 + cy * 3 + cx);
+                    const uint32_t m1 = (y & 3u) | ((y >> 1) & 0xCu) | ((y >> 5) & 0x30u) | ((y >> 6) & 0xC0u);
+                    const uint32_t m0 = m1 & ~(1u << (7 - c));
+                    acc += vt[m1] - vt[m0];
+                }
+                // four signed 16-bit fields, each eight times the cell's delta
+                const int64_t f0 = (int16_t)(acc & 0xFFFF);
+                acc = (acc - f0) >> 16;
+                const int64_t f1 = (int16_t)(acc & 0xFFFF);
+                acc = (acc - f1) >> 16;
+                const int64_t f2 = (int16_t)(acc & 0xFFFF);
+                const int64_t f3 = (acc - f2) >> 16;
+                const int64_t ec = f0 >> 3, cr = f1 >> 3, surf = f2 >> 3;
+                (void)f3;  // volume delta is 1 for every cell; it is the count field
+                const uint64_t word = (uint64_t)(ec + kEcBias3) |
+                                      (uint64_t)(surf + kSurfBias3) << kShiftSurf3 |
+                                      1ull << kShiftCnt3;
+                atomicAdd((unsigned long long *)&hist[p - lo], (unsigned long long)word);
+                if (CREASE) atomicAdd(&hc[p - lo], (uint32_t)(cr + kCreaseBias3));
+            }
+        }
+        __syncthreads();
+        if (++since >= flush_tiles) {
+            if constexpr (MODE == 2)
+                drain_cls3(hcls, W, lo, L, G, wg, partial, first);
+            else
+                drain_3d(hist, hc, CREASE, W, lo, L, G, wg, partial, first);
+            first = false;
+            since = 0;
+            __syncthreads();
+        }
+    }
+    if constexpr (MODE == 2)
+        drain_cls3(hcls, W, lo, L, G, wg, partial, first);
+    else
+        drain_3d(hist, hc, CREASE, W, lo, L, G, wg, partial, first);
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+size_t lds_bytes_3d(int window, bool want_crease) { return (size_t)window * (want_crease ? 12 : 8); }
+
+template <typename T, int LM, int MODE>
+static int launch_3d_t(const Launch3D &a, hipStream_t s) {
+    const int64_t tiles_x = (a.w + kTile3DX - 1) / kTile3DX;
+    const int64_t tiles_y = (a.h + kTile3DY - 1) / kTile3DY;
+    const int64_t tiles_z = (a.d + kTile3DZ - 1) / kTile3DZ;
+    const int64_t n_tiles = tiles_x * tiles_y * tiles_z;
+    const int flush = (int)(kFlush3D / (kTile3DX * kTile3DY * kTile3DZ));
+    const int W = a.hi - a.lo;
+    const size_t lds = MODE == 2 ? (size_t)W * kNumClasses3D * 4 : lds_bytes_3d(W, MODE == 1);
+    hipLaunchKernelGGL((ecc3d_tile<T, LM, MODE>), dim3(a.grid), dim3(256), lds, s,
+                       (const T *)a.data, a.d, a.h, a.w, a.lv, a.lo, a.hi, a.vtab, a.partial,
+                       tiles_x, tiles_y, n_tiles, flush);
+    return (int)hipGetLastError();
+}
+
+// cells one workgroup of the z-marching kernel may add to its bins
+static int64_t max_wg_cells_3d(int64_t cols, int64_t depth, int grid) {
+    const int64_t NW = (int64_t)grid * kWavesPerWG;
+    return kWavesPerWG * ((cols * depth + NW - 1) / NW) * kZmCellsPerUnit;
+}
+
+int zmarch_3d_columns(int64_t h, int64_t w) {
+    const int64_t n = ((w + kZmStripX - 1) / kZmStripX) * ((h + kZmTY - 1) / kZmTY);
+    return n > INT32_MAX ? INT32_MAX : (int)n;
+}
+
+bool zmarch_3d_fits(int64_t h, int64_t w, int grid) {
+    return max_wg_cells_3d(zmarch_3d_columns(h, w), 1, grid) <= kFlush3D;
+}
+
+template <typename T, int LM, int AL, bool MAXIMG, bool CR>
+static int launch_zm_t(const Launch3D &a, hipStream_t s) {
+    constexpr bool kThr = LM == LM_AFFINE || LM == LM_SEARCH;
+    const int W = a.hi - a.lo;
+    const int64_t cols = zmarch_3d_columns(a.h, a.w);
+    // bound the cells per workgroup between drains by splitting z
+    int64_t chunk = a.z_hi - a.z_lo;
+    while (chunk > 1 && max_wg_cells_3d(cols, chunk, a.grid) > kFlush3D) chunk = (chunk + 1) / 2;
+    if (max_wg_cells_3d(cols, chunk, a.grid) > kFlush3D) return (int)hipErrorInvalidValue;
+    const float cpass = (float)(a.lv.u0d + 1.5 - a.lo);
+    const size_t lds = (size_t)(W + 2 + 64) * (CR ? 12 : 8) + (kThr ? (size_t)(W + 3) * 4 : 0);
+    for (int64_t z0 = a.z_lo; z0 < a.z_hi; z0 += chunk) {
+        const int64_t z1 = z0 + chunk < a.z_hi ? z0 + chunk : a.z_hi;
+        const bool acc = a.accumulate || z0 > a.z_lo;
+        hipLaunchKernelGGL((ecc3d_stream<T, LM, AL, MAXIMG, CR, kZmTY>), dim3(a.grid), dim3(256), lds, s,
+                           (const T *)a.data, a.d, a.h, a.w, a.lv, a.lo, a.hi, cpass, a.zm_tables, a.crease_table,
+                           a.partial, z0, z1, acc ? 1 : 0);
+        const int e = (int)hipGetLastError();
+        if (e) return e;
+    }
+    return 0;
+}
+
+template <typename T, int LM, bool MAXIMG>
+static int launch_zm_al(const Launch3D &a, hipStream_t s) {
+    constexpr int VB = Elem3<T>::VEC * (int)sizeof(T);
+    const bool al = (uintptr_t)a.data % VB == 0 && (a.w * (int64_t)sizeof(T)) % VB == 0;
+    if (a.crease_table)
+        return al ? launch_zm_t<T, LM, kLoadAligned, MAXIMG, true>(a, s)
+                  : launch_zm_t<T, LM, kLoadVector, MAXIMG, true>(a, s);
+    return al ? launch_zm_t<T, LM, kLoadAligned, MAXIMG, false>(a, s)
+              : launch_zm_t<T, LM, kLoadVector, MAXIMG, false>(a, s);
+}
+
+
+template <typename T, int LM>
+static int launch_3d_cr(const Launch3D &a, hipStream_t s) {
+    if (a.classes) return launch_3d_t<T, LM, 2>(a, s);
+    if (a.zm_tables) return a.conn6 ? launch_zm_al<T, LM, true>(a, s) : launch_zm_al<T, LM, false>(a, s);
+    return a.want_crease ? launch_3d_t<T, LM, 1>(a, s) : launch_3d_t<T, LM, 0>(a, s);
+}
+
+template <typename T>
+static int launch_3d_dt(const Launch3D &a, hipStream_t s) {
+    if constexpr (sizeof(T) < 4)
+        return a.lv.mode == LM_LUT ? launch_3d_cr<T, LM_LUT>(a, s) : launch_3d_cr<T, LM_IDENTITY>(a, s);
+    else
+        return a.lv.mode == LM_AFFINE ? launch_3d_cr<T, LM_AFFINE>(a, s) : launch_3d_cr<T, LM_SEARCH>(a, s);
+}
+
+int launch_3d(const Launch3D &a, void *stream) {
+    hipStream_t s = (hipStream_t)stream;
+    switch (a.dtype) {
+    case ECC_U8: return launch_3d_dt<uint8_t>(a, s);
+    case ECC_U16: return launch_3d_dt<uint16_t>(a, s);
+    default: return launch_3d_dt<float>(a, s);
+    }
+}
+
+}  // namespace ecc

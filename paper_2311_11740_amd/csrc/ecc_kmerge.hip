@@ -1,0 +1,148 @@
+// Merge of per-workgroup partials with the prefix scan over levels, and the
+// value -> level table kernel.
+#include "ecc_device.h"
+
+namespace ecc {
+
+// ---------------------------------------------------------------------------
+// merge of per-workgroup partials and prefix scan over levels
+// ---------------------------------------------------------------------------
+struct OutPtrs {
+    int64_t *p[4];
+};
+
+// One wave per (channel, level) sums the G workgroup partials of that bin
+// (coalesced reads, shuffle reduction).  The block that finishes last (ticket
+// on a counter that it then resets) takes the running sum over levels of
+// every requested channel and writes the caller's int64 curves.
+__global__ void __launch_bounds__(1024)
+    ecc_merge(const int32_t *__restrict__ partial, int G, int nch, int L, OutPtrs out,
+              int64_t *__restrict__ totals, unsigned *__restrict__ counter) {
+    __shared__ bool last;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int waves = blockDim.x >> 6;
+    const int64_t n_bins = (int64_t)nch * L;
+    for (int64_t bin = (int64_t)blockIdx.x * waves + wave; bin < n_bins; bin += (int64_t)gridDim.x * waves) {
+        const int ch = (int)(bin / L);
+        if (!out.p[ch]) continue;
+        const int32_t *src = partial + bin * G;
+        int64_t s = 0;
+        if ((G & 3) == 0) {  // 16-byte loads, several in flight per lane
+            const u32x4 *s4 = reinterpret_cast<const u32x4 *>(src);
+            const int G4 = G >> 2;
+#pragma unroll 4
+            for (int g = lane; g < G4; g += 64) {
+                const u32x4 v = __builtin_nontemporal_load(s4 + g);
+                s += (int64_t)(int32_t)v.x + (int32_t)v.y + (int32_t)v.z + (int32_t)v.w;
+            }
+        } else {
+            for (int g = lane; g < G; g += 64) s += src[g];
+        }
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+        if (lane == 0) totals[bin] = s;
+    }
+    // publish this block's totals (release), take a ticket; the last block
+    // acquires everything the others published
+    __syncthreads();
+    if (threadIdx.x == 0)
+        last = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT) == gridDim.x - 1;
+    __syncthreads();
+    if (!last) return;
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    // running sums over levels, all channels at once (independent loads and
+    // shuffle chains overlap): each thread sums a chunk of levels, the chunk
+    // sums are scanned within waves by shuffles, then over the wave totals
+    const int t = threadIdx.x, nt = blockDim.x;
+    const int per = (L + nt - 1) / nt;
+    const int beg = t * per, end = beg + per < L ? beg + per : L;
+    int64_t sum[4] = {0, 0, 0, 0}, x[4];
+#pragma unroll
+    for (int ch = 0; ch < 4; ++ch)
+        if (ch < nch && out.p[ch])
+            for (int i = beg; i < end; ++i) sum[ch] += totals[(int64_t)ch * L + i];
+#pragma unroll
+    for (int ch = 0; ch < 4; ++ch) x[ch] = sum[ch];
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+#pragma unroll
+        for (int ch = 0; ch < 4; ++ch) {
+            const int64_t y = __shfl_up(x[ch], off);
+            if (lane >= off) x[ch] += y;
+        }
+    }
+    __shared__ int64_t wtot[4][16];
+    if (lane == 63)
+#pragma unroll
+        for (int ch = 0; ch < 4; ++ch) wtot[ch][wave] = x[ch];
+    __syncthreads();
+    if (wave == 0) {
+#pragma unroll
+        for (int ch = 0; ch < 4; ++ch) {
+            int64_t v = lane < waves ? wtot[ch][lane] : 0;
+#pragma unroll
+            for (int off = 1; off < 16; off <<= 1) {
+                const int64_t y = __shfl_up(v, off);
+                if (lane >= off) v += y;
+            }
+            if (lane < waves) wtot[ch][lane] = v;
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int ch = 0; ch < 4; ++ch) {
+        int64_t *dst = ch < nch ? out.p[ch] : nullptr;
+        if (!dst) continue;  // uniform
+        int64_t run = (wave > 0 ? wtot[ch][wave - 1] : 0) + x[ch] - sum[ch];
+        for (int i = beg; i < end; ++i) {
+            run += totals[(int64_t)ch * L + i];
+            dst[i] = run;
+        }
+    }
+    if (threadIdx.x == 0) *counter = 0u;  // ready for the next merge
+}
+
+// level index of every integer value from the thresholds (integer fields with
+// a threshold array)
+__global__ void ecc_level_lut(const float *__restrict__ thr, int L, int n_values,
+                              uint16_t *__restrict__ lut) {
+    const int v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= n_values) return;
+    const float x = (float)v;
+    int lo = 0, hi = L;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (x <= thr[mid])
+            hi = mid;
+        else
+            lo = mid + 1;
+    }
+    lut[v] = (uint16_t)lo;
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+int launch_merge(const int32_t *partial, int grid, int nch, int L, int64_t *const out[4],
+                 int64_t *totals, unsigned *counter, void *stream) {
+    OutPtrs o;
+    for (int c = 0; c < 4; ++c) o.p[c] = c < nch ? out[c] : nullptr;
+    const int64_t bins = (int64_t)nch * L;
+    static const int max_blocks = [] {
+        const char *e = std::getenv("ECC_MERGE_BLOCKS");
+        const int x = e ? std::atoi(e) : 256;
+        return x < 1 ? 1 : (x > 4096 ? 4096 : x);
+    }();
+    const int blocks = (int)std::min<int64_t>(max_blocks, (bins + 15) / 16);
+    hipLaunchKernelGGL(ecc_merge, dim3(blocks), dim3(1024), 0, (hipStream_t)stream, partial, grid, nch, L,
+                       o, totals, counter);
+    return (int)hipGetLastError();
+}
+
+int launch_level_lut(const float *thr, int L, int n_values, uint16_t *lut, void *stream) {
+    hipLaunchKernelGGL(ecc_level_lut, dim3((n_values + 255) / 256), dim3(256), 0,
+                       (hipStream_t)stream, thr, L, n_values, lut);
+    return (int)hipGetLastError();
+}
+
+}  // namespace ecc
