@@ -156,12 +156,17 @@ ecc_status ecc_curves_compute_streamed(ecc_context ctx, const ecc_field *field, 
                                        size_t slab_bytes, void *stream);
 
 /*
- * The same for n fields of any mix of shapes and dtypes in one persistent launch
- * (the paper's dispatch of many small images, Discussion of the microscopy case).
- * fields[i] and curves[i] follow the single-field contract.  The launch geometry
- * comes from the context's tuning cache (see ecc_batch_plan_tune), else defaults.
- * All fields of one call must be 2D with the same connectivity, or 3D with the
- * same connectivity.
+ * The same for n fields of any mix of shapes, dtypes, level counts and
+ * connectivities (the paper's dispatch of many small images, Discussion of the
+ * microscopy case).  fields[i] and curves[i] follow the single-field contract.
+ * 2D fields with at most 4096 levels go into one persistent launch per (dtype,
+ * level mode) group, replayed from a captured graph; other fields (3D, more
+ * levels) run through the single-field path on the same stream after it.
+ * The launch geometry comes from the context's tuning cache (see
+ * ecc_batch_plan_tune), else defaults.
+ * The threshold arrays of one call are uploaded once per distinct content; a
+ * call may use at most 256 distinct arrays (ECC_ERR_UNSUPPORTED beyond, before
+ * any work is queued).
  */
 ecc_status ecc_curves_compute_batch(ecc_context ctx, int32_t n, const ecc_field *fields,
                                     const ecc_curves *curves, void *stream);
@@ -170,7 +175,9 @@ ecc_status ecc_curves_compute_batch(ecc_context ctx, int32_t n, const ecc_field 
  * Autotuner: times the batched launch over candidate tile shapes and work splits
  * for this mix of fields (data must be valid device memory; the outputs of the
  * trial runs are discarded) and stores the fastest in the context's cache, keyed by
- * the mix's size classes.  Synchronises `stream`.  Optional.
+ * the exact mix (every field's shape, dtype, level count, level mode and
+ * connectivity, in order): later calls with the same mix use it.  Synchronises
+ * `stream`.  Optional.
  */
 ecc_status ecc_batch_plan_tune(ecc_context ctx, int32_t n, const ecc_field *fields, void *stream);
 
@@ -245,7 +252,8 @@ ecc_status ecc_profile_read(ecc_context ctx, double *total_ms, int64_t *launches
  * slot is free and its field plus curves fit in the arena (first fit); its field
  * is staged in pinned memory during the submit, copied to the device on a copy
  * stream, and computed as soon as it has landed:
- * all ready 2D requests (up to max_batch) in one launch of the batched kernel,
+ * all ready 2D requests (up to max_batch, and at most 256 distinct threshold
+ * arrays; the rest join the next launch) in one launch of the batched kernel,
  * others (3D, more than 4096 levels) through the single-field path on a second
  * stream.  Requests submitted while earlier ones run join the next launch.
  * Results go back to pinned memory and then to the caller's host arrays, and

@@ -372,7 +372,7 @@ static ecc_status run_plan(ecc_context ctx, BatchState *bs, BatchPlan *p, int n,
             d.n_items = p->n_items_of[sl];
             d.conn_idx = fi[i].conn == 8 ? 0 : 1;
             d.inv_step = lv[i].inv_step;
-            d.cpass = (float)(lv[i].u0d + 1.5);
+            d.cpass = (float)(lv[i].u0d + kBinOff + 0.5);
             d.eps = lv[i].eps;
         }
         e = (int)hipMemcpyAsync(p->d_desc, p->h_desc, sizeof(BatchField2D) * p->n_desc, hipMemcpyHostToDevice, st);
@@ -395,6 +395,15 @@ static ecc_status run_plan(ecc_context ctx, BatchState *bs, BatchPlan *p, int n,
         }
         s = prof_end(ctx, stream, slot);
         if (s != ECC_OK) return s;
+        for (int i = 0; i < n; ++i) {  // the graph reads these threshold arrays
+            if (p->slot_of[i] < 0 || !lv[i].thr) continue;
+            bool seen = false;
+            for (int j = 0; j < i && !seen; ++j) seen = p->slot_of[j] >= 0 && lv[j].thr == lv[i].thr;
+            if (!seen) {
+                s = note_threshold_use(ctx, lv[i], stream);
+                if (s != ECC_OK) return s;
+            }
+        }
     }
     if (!p->others.empty()) {
         ecc_status s = acquire_workspace(ctx, stream);
@@ -423,15 +432,9 @@ static ecc_status prepare(ecc_context ctx, int n, const ecc_field *fields, const
         ecc_status s = validate_field(&fields[i], &curves[i], &fi[i], false);
         if (s != ECC_OK) return s;
     }
-    std::vector<const float *> distinct;
-    for (int i = 0; i < n; ++i) {
-        if (!fields[i].thresholds) continue;
-        bool seen = false;
-        for (const float *t : distinct)
-            if (t == fields[i].thresholds) seen = true;
-        if (!seen) distinct.push_back(fields[i].thresholds);
-    }
-    ecc_status s = reserve_thresholds(ctx, (int)distinct.size());
+    std::vector<const ecc_field *> fp(n);
+    for (int i = 0; i < n; ++i) fp[i] = &fields[i];
+    ecc_status s = reserve_thresholds(ctx, n, fp.data());
     if (s != ECC_OK) return s;
     for (int i = 0; i < n; ++i) {
         s = level_args(ctx, &fields[i], fi[i], stream, &lv[i]);

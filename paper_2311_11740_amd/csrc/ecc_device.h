@@ -346,10 +346,167 @@ __device__ __forceinline__ uint32_t raw_pair(const uint32_t *w, int k) {
         return __builtin_amdgcn_perm(0u, w[k >> 2], (k & 2) ? 0x0C030C02u : 0x0C010C00u);
 }
 
+// The value of the lane below (wave_shr:1) or above (wave_shl:1) this one;
+// lanes at the ends of the wave get 0 (bound_ctrl), which callers never use.
+__device__ __forceinline__ uint32_t from_lane_below(uint32_t x) {
+    return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x138, 0xf, 0xf, true);
+}
+__device__ __forceinline__ uint32_t from_lane_above(uint32_t x) {
+    return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x130, 0xf, 0xf, true);
+}
+
 // (a.hi, b.lo): the 16-bit value just below b's low half
 __device__ __forceinline__ uint32_t straddle(uint32_t a, uint32_t b) {
     return __builtin_amdgcn_alignbit(b, a, 16);
 }
 
+
+
+// ---------------------------------------------------------------------------
+// bin indices and LDS addresses of the field kernels
+// ---------------------------------------------------------------------------
+// A pass histograms the levels [lo, lo + W) into bins kBinOff .. kBinOff + W - 1
+// (level l -> bin l - lo + kBinOff; kBinOff in ecc_internal.h).  A cell whose
+// level lies below the window takes its lane's own bin `lane` (< kBinOff), a
+// cell above it or never entering the bin W + kBinOff + lane; neither range is drained, and the
+// per-lane bins keep masses of such cells (the outside of the field, the
+// levels of other passes) from piling onto one LDS address.  The bin index is
+// also the rank the "entered before" relations compare: below-window values
+// are smaller and above-window values larger than every in-window one, which
+// is all those relations need for the in-window cells whose deltas count.
+
+// Per-lane constants of the bin convention: a cell
+// below the pass window ranks and is binned as `below` (= lane), a cell above
+// it or never entering as `never` (= W + kBinOff + lane).
+struct LaneBins {
+    uint32_t below, never;
+};
+
+// level of x mapped to its bin index (kBinOff) by a binary search over the
+// staged thresholds [lo - 1, hi)
+template <typename TH>
+__device__ __forceinline__ uint32_t bin_search(float x, int lo, int hi, const TH &thr, const LaneBins &lb) {
+    if (lo > 0 && x <= thr[lo - 1]) return lb.below;
+    if (!(x <= thr[hi - 1])) return lb.never;  // also NaN
+    int a = lo, b = hi - 1;                    // x <= thr[b]
+    while (a < b) {
+        const int m = (a + b) >> 1;
+        if (x <= thr[m])
+            b = m;
+        else
+            a = m + 1;
+    }
+    return (uint32_t)(a - lo + kBinOff);
+}
+
+typedef __attribute__((address_space(3))) unsigned long long lds_u64;
+typedef __attribute__((address_space(3))) unsigned int lds_u32;
+
+// LDS byte address of a shared-memory pointer
+__device__ __forceinline__ uint32_t lds_addr(const void *p) {
+    return (uint32_t)(uintptr_t)(const __attribute__((address_space(3))) void *)p;
+}
+
+// m * (x & 0xFFFF) + c and m * (x >> 16) + c in one operation each (m < 2^16):
+// the LDS address of the bin of the low or high cell of a packed pair
+__device__ __forceinline__ uint32_t mad_lo16(uint32_t x, uint32_t m, uint32_t c) {
+    uint32_t r;
+    asm("v_mad_u32_u16 %0, %1, %2, %3" : "=v"(r) : "v"(x), "v"(m), "v"(c));
+    return r;
+}
+__device__ __forceinline__ uint32_t mad_hi16(uint32_t x, uint32_t m, uint32_t c) {
+    uint32_t r;
+    asm("v_mad_u32_u16 %0, %1, %2, %3 op_sel:[1,0,0,0]" : "=v"(r) : "v"(x), "v"(m), "v"(c));
+    return r;
+}
+
+__device__ __forceinline__ void lds_add64(uint32_t addr, uint64_t v) {
+    __hip_atomic_fetch_add((lds_u64 *)(uintptr_t)addr, (unsigned long long)v, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ __forceinline__ void lds_add32(uint32_t addr, uint32_t v) {
+    __hip_atomic_fetch_add((lds_u32 *)(uintptr_t)addr, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// ---------------------------------------------------------------------------
+// merge of per-workgroup partials and prefix scan over levels
+// ---------------------------------------------------------------------------
+struct OutPtrs {
+    int64_t *p[4];
+};
+
+// the sum of one bin's G workgroup partials (a whole wave; lane 0's result)
+__device__ __forceinline__ int64_t sum_bin_wave(const int32_t *__restrict__ src, int G, int lane) {
+    int64_t s = 0;
+    if ((G & 3) == 0) {  // 16-byte loads, several in flight per lane
+        const u32x4 *s4 = reinterpret_cast<const u32x4 *>(src);
+        const int G4 = G >> 2;
+#pragma unroll 4
+        for (int g = lane; g < G4; g += 64) {
+            const u32x4 v = __builtin_nontemporal_load(s4 + g);
+            s += (int64_t)(int32_t)v.x + (int32_t)v.y + (int32_t)v.z + (int32_t)v.w;
+        }
+    } else {
+        for (int g = lane; g < G; g += 64) s += src[g];
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+    return s;
+}
+
+// Running sums over levels of the per-level totals [nch][L] into the caller's
+// curves (channels with a NULL output skipped), by one whole workgroup of at
+// most 16 waves: each thread sums a chunk of levels, the chunk sums are
+// scanned within waves by shuffles, then over the wave totals.
+__device__ __forceinline__ void scan_totals_block(const int64_t *__restrict__ totals, int nch, int L,
+                                                  const OutPtrs &out) {
+    __shared__ int64_t wtot[4][16];
+    const int t = threadIdx.x, nt = blockDim.x;
+    const int lane = t & 63, wave = t >> 6, waves = nt >> 6;
+    const int per = (L + nt - 1) / nt;
+    const int beg = t * per, end = beg + per < L ? beg + per : L;
+    int64_t sum[4] = {0, 0, 0, 0}, x[4];
+#pragma unroll
+    for (int ch = 0; ch < 4; ++ch)
+        if (ch < nch && out.p[ch])
+            for (int i = beg; i < end; ++i) sum[ch] += totals[(int64_t)ch * L + i];
+#pragma unroll
+    for (int ch = 0; ch < 4; ++ch) x[ch] = sum[ch];
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+#pragma unroll
+        for (int ch = 0; ch < 4; ++ch) {
+            const int64_t y = __shfl_up(x[ch], off);
+            if (lane >= off) x[ch] += y;
+        }
+    }
+    if (lane == 63)
+#pragma unroll
+        for (int ch = 0; ch < 4; ++ch) wtot[ch][wave] = x[ch];
+    __syncthreads();
+    if (wave == 0) {
+#pragma unroll
+        for (int ch = 0; ch < 4; ++ch) {
+            int64_t v = lane < waves ? wtot[ch][lane] : 0;
+#pragma unroll
+            for (int off = 1; off < 16; off <<= 1) {
+                const int64_t y = __shfl_up(v, off);
+                if (lane >= off) v += y;
+            }
+            if (lane < waves) wtot[ch][lane] = v;
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int ch = 0; ch < 4; ++ch) {
+        int64_t *dst = ch < nch ? out.p[ch] : nullptr;
+        if (!dst) continue;  // uniform
+        int64_t run = (wave > 0 ? wtot[ch][wave - 1] : 0) + x[ch] - sum[ch];
+        for (int i = beg; i < end; ++i) {
+            run += totals[(int64_t)ch * L + i];
+            dst[i] = run;
+        }
+    }
+}
 
 }  // namespace ecc

@@ -86,6 +86,10 @@ struct LevelArgs {
                           // elsewhere the level is settled against the thresholds
 };
 
+// bin of the first level of a pass window in the 2D kernels' LDS histograms
+// (the bins below it are per-lane bins for cells below the window)
+constexpr int kBinOff = 64;
+
 // thresholds kept in LDS by the kernels when L is at most this
 constexpr int kThrLds = 4096;
 
@@ -103,6 +107,8 @@ struct Launch2D {
     bool accumulate;            // add to the partials instead of overwriting them
     bool classes;               // class counts: delta_lut holds 2 x 256 words, partial is [5][L][grid]
 };
+
+size_t lds_bytes_2d(int window, bool classes);
 
 // cells per lane along the contiguous axis (16 bytes of input per lane)
 inline int vec_2d(int dtype) { return dtype == 1 ? 16 : (dtype == 2 ? 8 : 4); }

@@ -4,12 +4,21 @@
 
 namespace ecc {
 
+// Bin indices of one row, packed as pairs P[i] = (bin[i-1], bin[i]) of the
+// lane's cells with the neighbouring lanes' cells at both ends.
+//
+// Float fields with (nearly) evenly spaced thresholds: y = fma(x, 1/step, c)
+// with c = -t0/step + kBinOff + 0.5 - lo estimates bin - 0.5; adding 1.5*2^23
+// rounds y to an integer k in the low mantissa bits of m (exact for |y| <
+// 2^22), and r = y - k is the rounding residual.  k is the bin unless |r| is
+// within eps of 1/2, i.e. x sits within the host's error bound of a
+// threshold; those cells are settled against the thresholds.
 template <typename T, int LM, typename TH>
 __device__ __forceinline__ void convert_row(const RawRow &raw_in, bool row_ok, bool full, const LevelArgs &lv,
-                                            const TH &thr, int lo, int W, float cpass,
+                                            const TH &thr, int lo, int W, float cpass, const LaneBins &lb,
                                             uint32_t (&P)[Elem<T>::VEC + 1]) {
     constexpr int VEC = Elem<T>::VEC;
-    const uint32_t never = (uint32_t)(W + 1);
+    const uint32_t never = lb.never;
     if (!row_ok) {  // uniform
 #pragma unroll
         for (int i = 0; i <= VEC; ++i) P[i] = never | never << 16;
@@ -18,20 +27,41 @@ __device__ __forceinline__ void convert_row(const RawRow &raw_in, bool row_ok, b
     RawRow raw = raw_in;
     if (__any(raw.shift != 0)) unshift_row<T>(raw);  // rare: blocks at the end of the buffer
     if constexpr (LM == LM_IDENTITY) {  // integer values, two per packed operation
-        const uint32_t lo2 = (uint32_t)lo * 0x10001u, nv2 = never * 0x10001u;
-        uint32_t Q[VEC / 2];  // Q[k] = (lam'[2k], lam'[2k+1])
+        // bin = v - lo + kBinOff, at most `never` (values at or above the
+        // window, the field's level count included, rank as never) and, past
+        // the first pass, at least `below`
+        const uint32_t nv2 = never * 0x10001u;
+        uint32_t Q[VEC / 2];  // Q[k] = (bin[2k], bin[2k+1])
+        if (lo == 0) {        // uniform
+            const u16x2 off = {(unsigned short)kBinOff, (unsigned short)kBinOff};
 #pragma unroll
-        for (int k = 0; k < VEC / 2; ++k) Q[k] = identity_pair(raw_pair<T>(raw.w, 2 * k), lo2, nv2);
+            for (int k = 0; k < VEC / 2; ++k) {
+                u16x2 v = __builtin_bit_cast(u16x2, raw_pair<T>(raw.w, 2 * k));
+                v = __builtin_elementwise_min(__builtin_elementwise_add_sat(v, off), __builtin_bit_cast(u16x2, nv2));
+                Q[k] = __builtin_bit_cast(uint32_t, v);
+            }
+        } else {
+            const unsigned short sub = (unsigned short)(lo - kBinOff);
+            const u16x2 off = {sub, sub};
+            const uint32_t bl2 = lb.below * 0x10001u;
+#pragma unroll
+            for (int k = 0; k < VEC / 2; ++k) {
+                u16x2 v = __builtin_bit_cast(u16x2, raw_pair<T>(raw.w, 2 * k));
+                v = __builtin_elementwise_max(__builtin_elementwise_sub_sat(v, off), __builtin_bit_cast(u16x2, bl2));
+                v = __builtin_elementwise_min(v, __builtin_bit_cast(u16x2, nv2));
+                Q[k] = __builtin_bit_cast(uint32_t, v);
+            }
+        }
         if (!full) {  // uniform: cells outside the field never enter
 #pragma unroll
             for (int k = 0; k < VEC / 2; ++k) {
                 const uint32_t m = ((raw.valid >> (2 * k)) & 1u ? 0u : 0xFFFFu) |
                                    ((raw.valid >> (2 * k + 1)) & 1u ? 0u : 0xFFFF0000u);
-                Q[k] = (Q[k] & ~m) | (nv2 & m);
+                Q[k] = bit_select(m, nv2, Q[k]);
             }
         }
-        const uint32_t lq = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)Q[VEC / 2 - 1], 0x138, 0xf, 0xf, false);
-        const uint32_t rq = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)Q[0], 0x130, 0xf, 0xf, false);
+        const uint32_t lq = from_lane_below(Q[VEC / 2 - 1]);
+        const uint32_t rq = from_lane_above(Q[0]);
         P[0] = straddle(lq, Q[0]);
 #pragma unroll
         for (int k = 0; k < VEC / 2; ++k) {
@@ -40,13 +70,12 @@ __device__ __forceinline__ void convert_row(const RawRow &raw_in, bool row_ok, b
         }
         return;
     }
-    uint32_t lam[VEC];  // low 16 bits: lam'
-    const int base = lo - 1;
+    uint32_t lam[VEC];  // low 16 bits: the bin
     if constexpr (LM == LM_AFFINE) {
         const float hme = 0.5f - lv.eps;
-        // estimates clamp to [0, W + 1]; in the first pass to [1, W + 1],
-        // since every value at or below t0 (however far) has level 0
-        const float mlo = lo == 0 ? kMagic + 1.0f : kMagic;
+        // estimates clamp to [below, never]; in the first pass to the bin of
+        // level 0, since every value at or below t0 (however far) has level 0
+        const float mlo = kMagic + (float)(lo == 0 ? (uint32_t)kBinOff : lb.below);
         const float mhi = kMagic + (float)never;
         bool nr[VEC];
         bool any = false;
@@ -62,25 +91,24 @@ __device__ __forceinline__ void convert_row(const RawRow &raw_in, bool row_ok, b
         if (__any(any)) {  // rare: a value within eps of a threshold
 #pragma unroll
             for (int i = 0; i < VEC; ++i) {
-                const int k = (int)(lam[i] - kMagicBits);  // clamped estimate of lam'
-                if (nr[i] && k >= 0 && k <= W + 1) {
-                    // only estimates inside or next to the window can matter;
-                    // the estimate is a level, so at least 0 (k = 0 with lo = 0
-                    // would otherwise stand for level -1)
-                    const int g0 = k + base < 0 ? 0 : k + base;
-                    const int g = level_settle(__uint_as_float(raw.w[i]), (uint32_t)g0, lv.L, thr);
-                    lam[i] = (uint32_t)min(max(g - base, 0), (int)never);
+                const int k = (int)(lam[i] - kMagicBits);  // clamped bin estimate
+                // only estimates of the levels [lo - 1, hi] can matter (the
+                // true level is within one of the estimate)
+                if (nr[i] && k >= kBinOff - 1 && k <= W + kBinOff) {
+                    const int g0 = k + lo - kBinOff < 0 ? 0 : k + lo - kBinOff;
+                    const int g = (int)level_settle(__uint_as_float(raw.w[i]), (uint32_t)g0, lv.L, thr);
+                    lam[i] = g < lo ? lb.below : (g >= lo + W ? never : (uint32_t)(g - lo + kBinOff));
                 }
             }
         }
     } else if constexpr (LM == LM_SEARCH) {
 #pragma unroll
-        for (int i = 0; i < VEC; ++i) lam[i] = level_search_window(as_value<float>(raw.w[i]), lo, lo + W, thr);
+        for (int i = 0; i < VEC; ++i) lam[i] = bin_search(as_value<float>(raw.w[i]), lo, lo + W, thr, lb);
     } else {
 #pragma unroll
         for (int i = 0; i < VEC; ++i) {
             const int l = (int)level_of<T, LM>(as_value<T>(Elem<T>::get(raw.w, i)), lv, thr);
-            lam[i] = (uint32_t)min(max(l - base, 0), (int)never);
+            lam[i] = (uint32_t)min(max(l - lo + kBinOff, (int)lb.below), (int)never);
         }
     }
     if (!full) {  // uniform: some lanes hold cells outside the field
@@ -90,8 +118,8 @@ __device__ __forceinline__ void convert_row(const RawRow &raw_in, bool row_ok, b
     }
     // neighbours from the adjacent lanes by DPP wave shifts (lane 0's left and
     // lane 63's right are never used: those lanes only serve as halo)
-    const uint32_t left = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)lam[VEC - 1], 0x138, 0xf, 0xf, false);
-    const uint32_t right = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)lam[0], 0x130, 0xf, 0xf, false);
+    const uint32_t left = from_lane_below(lam[VEC - 1]);
+    const uint32_t right = from_lane_above(lam[0]);
     P[0] = pack_lo16(left, lam[0]);
 #pragma unroll
     for (int i = 1; i < VEC; ++i) P[i] = pack_lo16(lam[i - 1], lam[i]);
@@ -99,7 +127,8 @@ __device__ __forceinline__ void convert_row(const RawRow &raw_in, bool row_ok, b
 }
 
 // Partials are stored level-major, [channel][level][workgroup] (int32), so that
-// the merge reads the values of one bin contiguously.
+// the merge reads the values of one bin contiguously.  `hist` points at the
+// bin of level lo.
 __device__ __forceinline__ void drain_2d(const uint64_t *hist, int W, int lo, int L, int G, int wg,
                                          int32_t *__restrict__ partial, bool first) {
     for (int b = threadIdx.x; b < W; b += blockDim.x) {
@@ -145,26 +174,31 @@ __device__ __forceinline__ void drain_cls(const uint64_t *hist, int W, int lo, i
     }
 }
 
-// The deltas of the VEC cells of `mid` into the LDS bins: the bin of a cell
-// is lam' itself (hist[1..W] are the levels of the pass window).  Cells
-// outside the window (lam' = 0 or W + 1, among them every cell outside the
-// field) and every cell of a halo lane (whose window wl is 0) go to the
-// lane's own scratch bin, which is never drained: masses of such cells would
-// otherwise all hit one address, and the atomics stay unconditional, so all
-// table reads of a group can be issued before its atomics.
-// With CLS the bins hold class counts: two words per bin (hist[2 * bin] and
-// hist[2 * bin + 1]) and two tables (dl[0..255], dl[256..511]).
+// Where a lane's cells go: the LDS address of bin index b is mb * b + base,
+// with mb the bytes per bin and base the LDS address of bin 0 for the lanes
+// that own cells; a halo lane (lanes 0 and 63 of a strip only serve as
+// neighbours) has mb = 0 and base = its own `never` bin, so its cells land
+// there whatever their level.
+struct LaneDst {
+    uint32_t mb, base;
+};
+
+// The deltas of the VEC cells of `mid` into the LDS bins, one 64-bit atomic
+// per cell at the address of its bin (two with CLS: the bins then hold two
+// words and the tables are dl[0..255] and dl[256..511]).  Cells outside the
+// pass window and every cell of a halo lane land in bins that are never
+// drained; the atomics stay unconditional, so all table reads of a group are
+// issued before its atomics.
 template <int VEC, bool CLS>
 __device__ __forceinline__ void emit_row(const uint32_t (&up)[VEC + 1], const uint32_t (&mid)[VEC + 1],
-                                         const uint32_t (&dn)[VEC + 1], uint32_t wl, uint32_t scratch,
-                                         const uint64_t *dl, uint64_t *hist) {
+                                         const uint32_t (&dn)[VEC + 1], const LaneDst &ld, const uint64_t *dl) {
     // groups of up to 4 cell pairs: all table reads of a group are issued
     // before its atomics, so the atomics wait for one LDS round trip, not one each
     constexpr int NP = VEC / 2, GP = CLS ? (NP < 2 ? NP : 2) : (NP < 4 ? NP : 4);
 #pragma unroll
     for (int g0 = 0; g0 < NP; g0 += GP) {
         uint64_t dv[2 * GP], dv2[CLS ? 2 * GP : 1];
-        uint32_t bin[2 * GP];
+        uint32_t addr[2 * GP];
 #pragma unroll
         for (int q = 0; q < GP; ++q) {
             const int j = 2 * (g0 + q) + 1;
@@ -173,9 +207,8 @@ __device__ __forceinline__ void emit_row(const uint32_t (&up)[VEC + 1], const ui
                                                    pk_diff(up[j + 1], self1), pk_diff(mid[j - 1], self1),
                                                    pk_diff(mid[j + 1], self), pk_diff(dn[j - 1], self),
                                                    pk_diff(dn[j], self), pk_diff(dn[j + 1], self));
-            const uint32_t b0 = self & 0xFFFFu, b1 = self >> 16;
-            bin[2 * q] = b0 - 1u < wl ? b0 : scratch;
-            bin[2 * q + 1] = b1 - 1u < wl ? b1 : scratch;
+            addr[2 * q] = mad_lo16(self, ld.mb, ld.base);
+            addr[2 * q + 1] = mad_hi16(self, ld.mb, ld.base);
             dv[2 * q] = lut_lo<uint64_t, 3>(dl, acc);
             dv[2 * q + 1] = lut_hi<uint64_t, 3>(dl, acc);
             if constexpr (CLS) {
@@ -185,12 +218,8 @@ __device__ __forceinline__ void emit_row(const uint32_t (&up)[VEC + 1], const ui
         }
 #pragma unroll
         for (int q = 0; q < 2 * GP; ++q) {
-            if constexpr (CLS) {
-                atomicAdd((unsigned long long *)&hist[2 * bin[q]], (unsigned long long)dv[q]);
-                atomicAdd((unsigned long long *)&hist[2 * bin[q] + 1], (unsigned long long)dv2[q]);
-            } else {
-                atomicAdd((unsigned long long *)&hist[bin[q]], (unsigned long long)dv[q]);
-            }
+            lds_add64(addr[q], dv[q]);
+            if constexpr (CLS) lds_add64(addr[q] + 8, dv2[q]);
         }
     }
 }
@@ -200,8 +229,8 @@ __device__ __forceinline__ void emit_row(const uint32_t (&up)[VEC + 1], const ui
 template <typename T, int LM, int AL, int PF, bool CLS, typename TH>
 __device__ __forceinline__ void stream_run_2d(const T *__restrict__ data, int h, int64_t w,
                                               const LevelArgs &lv, const TH &thr, int32_t lo, int W,
-                                              float cpass, const uint64_t *dl, uint64_t *hist, int64_t strip,
-                                              int ra, int rb, int lane, uint32_t wl, uint32_t scratch) {
+                                              float cpass, const uint64_t *dl, int64_t strip,
+                                              int ra, int rb, int lane, const LaneBins &lb, const LaneDst &ld) {
     static_assert(PF % 3 == 0, "PF must be a multiple of 3");
     constexpr int VEC = Elem<T>::VEC;
     constexpr int CE = 62 * VEC;  // cells owned per strip
@@ -224,8 +253,8 @@ __device__ __forceinline__ void stream_run_2d(const T *__restrict__ data, int h,
             const int rr = ra + 1 + k < rb ? ra + 1 + k : rb;
             fetch_row<T, AL>(data, clamp_row(rr), w, x0, last_block, ring[k]);
         }
-        convert_row<T, LM>(r0, ra - 1 >= 0, full, lv, thr, lo, W, cpass, R[2]);
-        convert_row<T, LM>(r1, true, full, lv, thr, lo, W, cpass, R[0]);
+        convert_row<T, LM>(r0, ra - 1 >= 0, full, lv, thr, lo, W, cpass, lb, R[2]);
+        convert_row<T, LM>(r1, true, full, lv, thr, lo, W, cpass, lb, R[0]);
     }
     int r0 = ra;
     // full blocks of PF rows: no conditional loads, so PF loads stay in flight
@@ -233,10 +262,10 @@ __device__ __forceinline__ void stream_run_2d(const T *__restrict__ data, int h,
 #pragma unroll
         for (int k = 0; k < PF; ++k) {
             const int r = r0 + k;  // current row (buffer k%3); ring[k] holds row r + 1
-            convert_row<T, LM>(ring[k], r + 1 < h, full, lv, thr, lo, W, cpass, R[(k + 1) % 3]);
+            convert_row<T, LM>(ring[k], r + 1 < h, full, lv, thr, lo, W, cpass, lb, R[(k + 1) % 3]);
             const int nx = r + 1 + PF < rb ? r + 1 + PF : rb;
             fetch_row<T, AL>(data, clamp_row(nx), w, x0, last_block, ring[k]);
-            emit_row<VEC, CLS>(R[(k + 2) % 3], R[k % 3], R[(k + 1) % 3], wl, scratch, dl, hist);
+            emit_row<VEC, CLS>(R[(k + 2) % 3], R[k % 3], R[(k + 1) % 3], ld, dl);
         }
     }
     // remaining rows (fewer than PF); here r - ra = r0 - ra + k with r0 - ra
@@ -245,8 +274,8 @@ __device__ __forceinline__ void stream_run_2d(const T *__restrict__ data, int h,
     for (int k = 0; k < PF; ++k) {
         const int r = r0 + k;
         if (r < rb) {
-            convert_row<T, LM>(ring[k], r + 1 < h, full, lv, thr, lo, W, cpass, R[(k + 1) % 3]);
-            emit_row<VEC, CLS>(R[(k + 2) % 3], R[k % 3], R[(k + 1) % 3], wl, scratch, dl, hist);
+            convert_row<T, LM>(ring[k], r + 1 < h, full, lv, thr, lo, W, cpass, lb, R[(k + 1) % 3]);
+            emit_row<VEC, CLS>(R[(k + 2) % 3], R[k % 3], R[(k + 1) % 3], ld, dl);
         }
     }
 }
@@ -269,9 +298,9 @@ __global__ void __launch_bounds__(256)
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform: keeps loop control scalar
     const int W = hi - lo;
     const int L = lv.L;
-    // LDS: bins 0..W+1 (1..W are the window's levels), a scratch bin per
-    // lane, then thresholds [lo-2, hi+1)
-    const int n_bins = W + 2 + 64;
+    // LDS: bins [0, W + 2 kBinOff) (kBinOff .. kBinOff + W - 1 are the
+    // window's levels), then thresholds [lo-2, hi+1)
+    const int n_bins = W + 2 * kBinOff;
     uint64_t *hist = smem;
     float *thr_s = reinterpret_cast<float *>(smem + BW * n_bins);
     constexpr bool kThr = LM == LM_AFFINE || LM == LM_SEARCH;
@@ -293,21 +322,23 @@ __global__ void __launch_bounds__(256)
     const int64_t n_strips = (w + CE - 1) / CE;
     const int64_t units = n_strips * H;
     const int64_t u_end = units * (gw + 1) / NW;
-    // lanes 0 and 63 only serve as halo: their window is empty
-    const uint32_t wl = lane == 0 || lane == 63 ? 0u : (uint32_t)W;
+    const LaneBins lb{(uint32_t)lane, (uint32_t)(W + kBinOff + lane)};
+    const bool halo = lane == 0 || lane == 63;
+    const uint32_t h0 = lds_addr(hist);
+    const LaneDst ld{halo ? 0u : 8u * BW, halo ? h0 + 8u * BW * lb.never : h0};
     const ThrLds thr{thr_s, lo - 2};
     for (int64_t u = units * gw / NW; u < u_end;) {
         const int64_t strip = u / H, ra = u % H;
         const int64_t rb = ra + (u_end - u) < H ? ra + (u_end - u) : H;
-        stream_run_2d<T, LM, AL, PF, CLS>(data, (int)h, w, lv, thr, lo, W, cpass, dl, hist, strip,
-                                          (int)(row_lo + ra), (int)(row_lo + rb), lane, wl, (uint32_t)(W + 2 + lane));
+        stream_run_2d<T, LM, AL, PF, CLS>(data, (int)h, w, lv, thr, lo, W, cpass, dl, strip, (int)(row_lo + ra),
+                                          (int)(row_lo + rb), lane, lb, ld);
         u += rb - ra;
     }
     __syncthreads();
     if constexpr (CLS)
-        drain_cls(hist + 2, W, lo, L, G, wg, partial, accumulate == 0);
+        drain_cls(hist + 2 * kBinOff, W, lo, L, G, wg, partial, accumulate == 0);
     else
-        drain_2d(hist + 1, W, lo, L, G, wg, partial, accumulate == 0);
+        drain_2d(hist + kBinOff, W, lo, L, G, wg, partial, accumulate == 0);
 }
 
 // ---------------------------------------------------------------------------
@@ -342,9 +373,9 @@ __global__ void __launch_bounds__(256)
         const int L = f.L;
         const int h = (int)f.h;
         const int64_t w = f.w;
-        uint64_t *hist = smem;  // bins 0..L+1, then a scratch bin per lane
-        float *thr_s = reinterpret_cast<float *>(smem + L + 2 + 64);
-        for (int b = tid; b < L + 2; b += 256) hist[b] = 0;
+        uint64_t *hist = smem;  // bins [0, L + 2 kBinOff): kBinOff + l is level l
+        float *thr_s = reinterpret_cast<float *>(smem + L + 2 * kBinOff);
+        for (int b = tid; b < L + 2 * kBinOff; b += 256) hist[b] = 0;
         if (kThr)
             for (int i = tid; i < L + 3; i += 256) {
                 int k = i - 2;
@@ -362,26 +393,28 @@ __global__ void __launch_bounds__(256)
         lv.u0d = 0.0;
         lv.eps = f.eps;
         const ThrLds thr{thr_s, -2};
+        const LaneBins lb{(uint32_t)lane, (uint32_t)(L + kBinOff + lane)};
+        const uint32_t h0 = lds_addr(hist);
+        const LaneDst ld{halo_lane ? 0u : 8u, halo_lane ? h0 + 8u * lb.never : h0};
         const int n = item.u1 - item.u0;
         const int u_end = item.u0 + (int)((int64_t)n * (wave + 1) / kWavesPerWG);
         for (int u = item.u0 + (int)((int64_t)n * wave / kWavesPerWG); u < u_end;) {
             const int strip = u / h, ra = u % h;
             const int rb = ra + (u_end - u) < h ? ra + (u_end - u) : h;
-            stream_run_2d<T, LM, kLoadVector, PF, false>((const T *)f.data, h, w, lv, thr, 0, L, f.cpass, dl[f.conn_idx],
-                                                  hist, strip, ra, rb, lane, halo_lane ? 0u : (uint32_t)L,
-                                                  (uint32_t)(L + 2 + lane));
+            stream_run_2d<T, LM, kLoadVector, PF, false>((const T *)f.data, h, w, lv, thr, 0, L, f.cpass,
+                                                         dl[f.conn_idx], strip, ra, rb, lane, lb, ld);
             u += rb - ra;
         }
         __syncthreads();
-        // bins -> the field's global histogram (levels hist[1..L])
-        for (int b = tid + 1; b <= L; b += 256) {
-            const uint64_t v = hist[b];
+        // bins -> the field's global histogram (levels hist[kBinOff .. kBinOff + L))
+        for (int b = tid; b < L; b += 256) {
+            const uint64_t v = hist[kBinOff + b];
             if (v == 0) continue;
             const int64_t cnt = (int64_t)(v >> kShiftCnt2);
             const int64_t per = (int64_t)((v >> kShiftPer2) & ((1ull << (kShiftCnt2 - kShiftPer2)) - 1)) -
                                 kPerBias2 * cnt;
             const int64_t ec = (int64_t)(v & ((1ull << kShiftPer2) - 1)) - kEcBias2 * cnt;
-            int32_t *dst = f.hist + (b - 1);
+            int32_t *dst = f.hist + b;
             if (ec) atomicAdd(dst, (int32_t)ec);
             if (per) atomicAdd(dst + L, (int32_t)per);
             atomicAdd(dst + 2 * L, (int32_t)cnt);
@@ -426,6 +459,10 @@ __global__ void __launch_bounds__(256)
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
+size_t lds_bytes_2d(int window, bool classes) {
+    return (size_t)(classes ? 2 : 1) * (window + 2 * kBinOff) * 8 + (size_t)(window + 3) * 4;
+}
+
 int load_mode_2d(const void *data, int64_t h, int64_t w, int elem_bytes) {
     (void)h;
     return ((uintptr_t)data % 16 == 0 && (w * elem_bytes) % 16 == 0) ? kLoadAligned : kLoadVector;
@@ -450,9 +487,9 @@ static int launch_2d_t(const Launch2D &a, hipStream_t s) {
     int64_t chunk = a.row_hi - a.row_lo;
     while (chunk > 1 && max_wg_cells_2d(chunk, a.w, VEC, a.grid) > flush) chunk = (chunk + 1) / 2;
     if (max_wg_cells_2d(chunk, a.w, VEC, a.grid) > flush) return (int)hipErrorInvalidValue;
-    // affine levels: the pass constant -t0/step + 1.5 - lo, rounded once
-    const float cpass = (float)(a.lv.u0d + 1.5 - a.lo);
-    const size_t lds = (size_t)(CLS ? 2 : 1) * (W + 2 + 64) * 8 + (size_t)(W + 3) * 4;
+    // affine levels: the pass constant -t0/step + kBinOff + 0.5 - lo, rounded once
+    const float cpass = (float)(a.lv.u0d + kBinOff + 0.5 - a.lo);
+    const size_t lds = lds_bytes_2d(W, CLS);
     for (int64_t r0 = a.row_lo; r0 < a.row_hi; r0 += chunk) {
         const int64_t r1 = r0 + chunk < a.row_hi ? r0 + chunk : a.row_hi;
         const bool acc = a.accumulate || r0 > a.row_lo;
@@ -494,7 +531,7 @@ int launch_2d(const Launch2D &a, void *stream) {
 }
 size_t lds_bytes_batch_2d(int lm, int max_L) {
     const bool thr = lm == LM_AFFINE || lm == LM_SEARCH;
-    return (size_t)(max_L + 2 + 64) * 8 + (thr ? (size_t)(max_L + 3) * 4 : 0);
+    return (size_t)(max_L + 2 * kBinOff) * 8 + (thr ? (size_t)(max_L + 3) * 4 : 0);
 }
 
 template <typename T>

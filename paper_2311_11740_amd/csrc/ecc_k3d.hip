@@ -158,87 +158,107 @@ __device__ __forceinline__ void unshift_row3(RawRow3 &raw) {
     raw.w[2] = (uint32_t)hi; raw.w[3] = (uint32_t)(hi >> 32);
 }
 
+// bin index (kBinOff convention) of one value
 template <typename T, int LM, typename TH>
-__device__ __forceinline__ uint32_t level3(uint32_t bits, const LevelArgs &lv, const TH &thr, int lo, int W,
-                                           float cpass) {
-    const int base = lo - 1;
-    const uint32_t never = (uint32_t)(W + 1);
+__device__ __forceinline__ uint32_t bin3(uint32_t bits, const LevelArgs &lv, const TH &thr, int lo, int W,
+                                         float cpass, const LaneBins &lb) {
     if constexpr (LM == LM_AFFINE) {
         const float x = __uint_as_float(bits);
         const float y = __builtin_fmaf(x, lv.inv_step, cpass);
         const float m = y + kMagic;
         const float r = y - (m - kMagic);
-        // clamped estimate of lam' (at least 1 in the first pass: values at
-        // or below t0 have level 0)
-        const float mlo = lo == 0 ? kMagic + 1.0f : kMagic;
-        uint32_t l = __float_as_uint(__builtin_amdgcn_fmed3f(m, mlo, kMagic + (float)never)) - kMagicBits;
+        // clamped bin estimate (in the first pass at least the bin of level
+        // 0: values at or below t0 have level 0)
+        const float mlo = kMagic + (float)(lo == 0 ? (uint32_t)kBinOff : lb.below);
+        uint32_t l = __float_as_uint(__builtin_amdgcn_fmed3f(m, mlo, kMagic + (float)lb.never)) - kMagicBits;
         if (!(__builtin_fabsf(r) <= 0.5f - lv.eps)) {  // near a threshold (or NaN / inf)
             const int k = (int)l;
-            if (k >= 0 && k <= W + 1) {
-                const int g0 = k + base < 0 ? 0 : k + base;
+            if (k >= kBinOff - 1 && k <= W + kBinOff) {
+                const int g0 = k + lo - kBinOff < 0 ? 0 : k + lo - kBinOff;
                 const int g = (int)level_settle(x, (uint32_t)g0, lv.L, thr);
-                l = (uint32_t)min(max(g - base, 0), (int)never);
+                l = g < lo ? lb.below : (g >= lo + W ? lb.never : (uint32_t)(g - lo + kBinOff));
             }
         }
         return l;
     } else if constexpr (LM == LM_SEARCH) {
-        return level_search_window(__uint_as_float(bits), lo, lo + W, thr);
+        return bin_search(__uint_as_float(bits), lo, lo + W, thr, lb);
     } else {
         const int l = (int)level_of<T, LM>(as_value<T>(bits), lv, thr);
-        return (uint32_t)min(max(l - base, 0), (int)never);
+        return (uint32_t)min(max(l - lo + kBinOff, (int)lb.below), (int)lb.never);
     }
 }
 
-// packed level pairs of one row (P[i] = (lam'[i-1], lam'[i]) with the strip
-// neighbours at both ends); rows outside the field are "never"
+// packed bin pairs of one row (P[i] = (bin[i-1], bin[i]) with the strip
+// neighbours at both ends); rows outside the field never enter
 template <typename T, int LM, typename TH>
 __device__ __forceinline__ void convert_row3(const RawRow3 &raw_in, bool row_ok, int64_t w, int64_t xs, int64_t x0,
                                              int lane, const LevelArgs &lv, const TH &thr, int lo, int W,
-                                             float cpass, uint32_t (&P)[Elem3<T>::VEC + 1]) {
+                                             float cpass, const LaneBins &lb, uint32_t (&P)[Elem3<T>::VEC + 1]) {
     constexpr int VEC = Elem3<T>::VEC;
-    const uint32_t never = (uint32_t)(W + 1);
-    if (!row_ok) {  // uniform
-#pragma unroll
-        for (int i = 0; i <= VEC; ++i) P[i] = never | never << 16;
-        return;
-    }
+    const uint32_t never = lb.never;
     RawRow3 raw = raw_in;
     if (__any(raw.shift != 0)) unshift_row3<T>(raw);  // rare: blocks at the end of the buffer
     if constexpr (LM == LM_IDENTITY) {  // integer values, two per packed operation
-        const uint32_t lo2 = (uint32_t)lo * 0x10001u, nv2 = never * 0x10001u;
-        uint32_t Q0 = identity_pair(raw_pair<T>(raw.w, 0), lo2, nv2);
-        uint32_t Q1 = identity_pair(raw_pair<T>(raw.w, 2), lo2, nv2);
+        const uint32_t nv2 = never * 0x10001u;
+        uint32_t Q[2];
+        if (lo == 0) {  // uniform
+            const u16x2 off = {(unsigned short)kBinOff, (unsigned short)kBinOff};
+#pragma unroll
+            for (int k = 0; k < 2; ++k) {
+                u16x2 v = __builtin_bit_cast(u16x2, raw_pair<T>(raw.w, 2 * k));
+                v = __builtin_elementwise_min(__builtin_elementwise_add_sat(v, off), __builtin_bit_cast(u16x2, nv2));
+                Q[k] = __builtin_bit_cast(uint32_t, v);
+            }
+        } else {
+            const unsigned short sub = (unsigned short)(lo - kBinOff);
+            const u16x2 off = {sub, sub};
+            const uint32_t bl2 = lb.below * 0x10001u;
+#pragma unroll
+            for (int k = 0; k < 2; ++k) {
+                u16x2 v = __builtin_bit_cast(u16x2, raw_pair<T>(raw.w, 2 * k));
+                v = __builtin_elementwise_max(__builtin_elementwise_sub_sat(v, off), __builtin_bit_cast(u16x2, bl2));
+                v = __builtin_elementwise_min(v, __builtin_bit_cast(u16x2, nv2));
+                Q[k] = __builtin_bit_cast(uint32_t, v);
+            }
+        }
         if (!(xs + 64 * VEC <= w)) {  // uniform: cells outside the field never enter
             const uint32_t m0 = (x0 < w ? 0u : 0xFFFFu) | (x0 + 1 < w ? 0u : 0xFFFF0000u);
             const uint32_t m1 = (x0 + 2 < w ? 0u : 0xFFFFu) | (x0 + 3 < w ? 0u : 0xFFFF0000u);
-            Q0 = (Q0 & ~m0) | (nv2 & m0);
-            Q1 = (Q1 & ~m1) | (nv2 & m1);
+            Q[0] = bit_select(m0, nv2, Q[0]);
+            Q[1] = bit_select(m1, nv2, Q[1]);
         }
-        const uint32_t hl = level3<T, LM>(raw.halo, lv, thr, lo, W, cpass);
-        uint32_t lq = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)Q1, 0x138, 0xf, 0xf, false);
-        uint32_t rq = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)Q0, 0x130, 0xf, 0xf, false);
+        const uint32_t hl = bin3<T, LM>(raw.halo, lv, thr, lo, W, cpass, lb);
+        uint32_t lq = from_lane_below(Q[1]);
+        uint32_t rq = from_lane_above(Q[0]);
         if (lane == 0) lq = (xs > 0 ? hl : never) << 16;
         if (lane == 63) rq = xs + 64 * VEC < w ? hl : never;
-        P[0] = straddle(lq, Q0);
-        P[1] = Q0;
-        P[2] = straddle(Q0, Q1);
-        P[3] = Q1;
-        P[4] = straddle(Q1, rq);
-        return;
+        P[0] = straddle(lq, Q[0]);
+        P[1] = Q[0];
+        P[2] = straddle(Q[0], Q[1]);
+        P[3] = Q[1];
+        P[4] = straddle(Q[1], rq);
+    } else {
+        uint32_t lam[VEC];
+#pragma unroll
+        for (int i = 0; i < VEC; ++i)
+            lam[i] = x0 + i < w ? bin3<T, LM>(elem3<T>(raw, i), lv, thr, lo, W, cpass, lb) : never;
+        const uint32_t hl = bin3<T, LM>(raw.halo, lv, thr, lo, W, cpass, lb);
+        uint32_t left = from_lane_below(lam[VEC - 1]);
+        uint32_t right = from_lane_above(lam[0]);
+        if (lane == 0) left = xs > 0 ? hl : never;
+        if (lane == 63) right = xs + 64 * VEC < w ? hl : never;
+        P[0] = pack_lo16(left, lam[0]);
+#pragma unroll
+        for (int i = 1; i < VEC; ++i) P[i] = pack_lo16(lam[i - 1], lam[i]);
+        P[VEC] = pack_lo16(lam[VEC - 1], right);
     }
-    uint32_t lam[VEC];
+    // rows outside the field (uniform; rare: the first and last planes and
+    // rows of the volume) never enter; filled after the conversion, which
+    // read a clamped row
+    if (!row_ok) {
 #pragma unroll
-    for (int i = 0; i < VEC; ++i)
-        lam[i] = x0 + i < w ? level3<T, LM>(elem3<T>(raw, i), lv, thr, lo, W, cpass) : never;
-    const uint32_t hl = level3<T, LM>(raw.halo, lv, thr, lo, W, cpass);
-    uint32_t left = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)lam[VEC - 1], 0x138, 0xf, 0xf, false);
-    uint32_t right = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)lam[0], 0x130, 0xf, 0xf, false);
-    if (lane == 0) left = xs > 0 ? hl : never;
-    if (lane == 63) right = xs + 64 * VEC < w ? hl : never;
-    P[0] = pack_lo16(left, lam[0]);
-#pragma unroll
-    for (int i = 1; i < VEC; ++i) P[i] = pack_lo16(lam[i - 1], lam[i]);
-    P[VEC] = pack_lo16(lam[VEC - 1], right);
+        for (int i = 0; i <= VEC; ++i) P[i] = never | never << 16;
+    }
 }
 
 // 8-neighbour "entered before" pattern of the two cells of pair j (low / high
@@ -275,10 +295,19 @@ __device__ __forceinline__ uint32_t pk_merge(uint32_t a, uint32_t b) {
 
 // LDS tables (set up by the host, 256 entries each):
 //   tl[p]: layer term of a voxel with layer pattern p, packed as the low
-//          word of a 3D bin: (+-EC of the 2D cell) + 7 + (perimeter + 8) << 22
-//   tm[p]: 2D EC delta of an image pixel with pattern p, sign included
+//          word of a 3D bin: (+-EC of the 2D cell) + 7 + (perimeter + 8) << 22,
+//          minus 2 << 22 for the min image (see below)
+//   tm[p]: 2D EC delta of an image pixel with pattern p, sign included,
+//          minus 2 << 22 for the max image
 // A voxel's low word is tl[p_layer] + (its share of the two images' deltas)
-// - 2 * (vertical neighbours that entered before it) << 22.
+// - 2 * (vertical neighbours that entered before it) << 22.  Both terms
+// come from one relation per voxel, whether the voxel above entered first:
+// with ab_z that relation for voxel z, the image between z and z+1 belongs
+// to voxel z + 1 when ab_z (min image; to voxel z when ab_z, max image), and
+// the vertical neighbours already in number (1 - ab_(z-1)) + ab_z.  So each
+// voxel computes u = (its part of its own image term, minus 2 ab_z << 22),
+// adds the carry of the voxel below and hands carry = tm - u to the voxel
+// above (the biases of the constant parts are in the tables).
 // With CR the crease channel comes along: the crease of a voxel is the change
 // of kappa over the 12 lattice edges around it; the four edges parallel to one
 // axis are the voxel's corners in the plane normal to that axis, so its delta
@@ -297,17 +326,17 @@ struct March3D {
     int lo, W;
     float cpass;
     const uint32_t *tl;
-    const int32_t *tm;
-    uint64_t *hist;
+    const uint32_t *tm;
+    uint32_t hist_base;  // LDS address of bin 0 (8 bytes per bin)
     int64_t xs, x0;
     int y0, zb, lane;
     int64_t last_block;
-    uint32_t scratch;  // this lane's scratch bin, W + 2 + lane
+    LaneBins lb;
     const uint32_t *tc;  // CR: per-plane crease deltas + 4
-    uint32_t *hc;        // CR: crease words of the bins
+    uint32_t hc_base;    // CR: LDS address of the crease word of bin 0 (4 bytes per bin)
 
     uint32_t R[3][NR][VEC + 1];  // level planes; R[(z - za + 1) % 3] holds plane z
-    int32_t E[TY][VEC];          // image delta of the pixel below each voxel of the current plane
+    uint32_t C[TY][VEC];         // carry from the voxel below each voxel of the current plane
     RawRow3 ring[3][NR];         // raw rows of upcoming planes; ring[(z - za) % 3] holds plane z + 1
 
     __device__ __forceinline__ int clampz(int z) const { return z < 0 ? 0 : (z >= d ? d - 1 : z); }
@@ -322,7 +351,7 @@ struct March3D {
     __device__ __forceinline__ void convert_plane(int z, const RawRow3 (&src)[NR], uint32_t (&dst)[NR][VEC + 1]) {
 #pragma unroll
         for (int r = 0; r < NR; ++r)
-            convert_row3<T, LM>(src[r], row_ok(z, y0 - 1 + r), w, xs, x0, lane, lv, thr, lo, W, cpass, dst[r]);
+            convert_row3<T, LM>(src[r], row_ok(z, y0 - 1 + r), w, xs, x0, lane, lv, thr, lo, W, cpass, lb, dst[r]);
     }
     __device__ __forceinline__ void image(const uint32_t (&a)[NR][VEC + 1], const uint32_t (&b)[NR][VEC + 1],
                                           uint32_t (&m)[NR][VEC + 1]) {
@@ -332,8 +361,21 @@ struct March3D {
             for (int i = 0; i <= VEC; ++i) m[r][i] = pk_merge<MAXIMG>(a[r][i], b[r][i]);
     }
 
-    // planes za-1 and za converted, E of the image between them, planes
-    // za+1 .. za+3 in flight
+    // the share u of a voxel's own image term (see above) from its image
+    // delta and the mask of "the voxel above entered first"
+    __device__ __forceinline__ static uint32_t own_share(uint32_t tmv, uint32_t ab) {
+        if constexpr (MAXIMG)
+            return ab & tmv;
+        else
+            return bit_select(ab, 0xFF800000u, tmv);  // -(2 << 22) when ab
+    }
+    // per voxel of the pair, all ones when the upper neighbour (sign of the
+    // packed difference upper - self) entered first
+    __device__ __forceinline__ static uint32_t mask_lo(uint32_t dz) { return (uint32_t)((int32_t)(dz << 16) >> 31); }
+    __device__ __forceinline__ static uint32_t mask_hi(uint32_t dz) { return (uint32_t)((int32_t)dz >> 31); }
+
+    // planes za-1 and za converted, the carries of the image between them,
+    // planes za+1 .. za+3 in flight
     __device__ __forceinline__ void prologue(int za) {
         {
             RawRow3 a[NR], b[NR];
@@ -351,8 +393,12 @@ struct March3D {
 #pragma unroll
             for (int j = 1; j < VEC + 1; j += 2) {
                 const uint32_t pm = pattern_pair<VEC>(M[t], M[t + 1], M[t + 2], j);
-                E[t][j - 1] = lut_lo<int32_t, 2>(tm, pm);
-                E[t][j] = lut_hi<int32_t, 2>(tm, pm);
+                // voxel za (upper) against voxel za - 1: the upper one is
+                // later in memory, so it precedes only when strictly lower
+                const uint32_t dz = pk_diff(R[1][t + 1][j], R[0][t + 1][j]);
+                const uint32_t t0 = lut_lo<uint32_t, 2>(tm, pm), t1 = lut_hi<uint32_t, 2>(tm, pm);
+                C[t][j - 1] = t0 - own_share(t0, mask_lo(dz));
+                C[t][j] = t1 - own_share(t1, mask_hi(dz));
             }
     }
 
@@ -366,27 +412,27 @@ struct March3D {
         fetch_plane(z + 4 < zb ? z + 4 : zb, ring[K]);
         uint32_t M[NR][VEC + 1];
         image(Pc, Pn, M);
+        (void)Pp;
 #pragma unroll
         for (int t = 0; t < TY; ++t) {
             // table reads of the row's VEC voxels first, then their atomics
-            uint32_t tlv[VEC], pm[VEC / 2], selfv[VEC / 2], below[VEC / 2], above[VEC / 2];
+            uint32_t tlv[VEC], tmv[VEC], dz[VEC / 2], addr[VEC];
             uint32_t crv[CR ? VEC : 1];
-            int32_t en[VEC];
 #pragma unroll
             for (int q = 0; q < VEC / 2; ++q) {
                 const int j = 2 * q + 1;
-                const uint32_t self = Pc[t + 1][j], self1 = self + 0x00010001u;
+                const uint32_t self = Pc[t + 1][j];
                 const uint32_t pl = pattern_pair<VEC>(Pc[t], Pc[t + 1], Pc[t + 2], j);
-                pm[q] = pattern_pair<VEC>(M[t], M[t + 1], M[t + 2], j);
-                // vertical neighbours: the one below (z-1) precedes on ties,
-                // the one above (z+1) does not
-                below[q] = pk_lt(Pp[t + 1][j], self1);
-                above[q] = pk_lt(Pn[t + 1][j], self);
-                selfv[q] = self;
+                const uint32_t pm = pattern_pair<VEC>(M[t], M[t + 1], M[t + 2], j);
+                // the voxel above (z+1) is later in memory: it entered first
+                // only when strictly lower
+                dz[q] = pk_diff(Pn[t + 1][j], self);
+                addr[2 * q] = mad_lo16(self, 8u, hist_base);
+                addr[2 * q + 1] = mad_hi16(self, 8u, hist_base);
                 tlv[2 * q] = lut_lo<uint32_t, 2>(tl, pl);
                 tlv[2 * q + 1] = lut_hi<uint32_t, 2>(tl, pl);
-                en[2 * q] = lut_lo<int32_t, 2>(tm, pm[q]);
-                en[2 * q + 1] = lut_hi<int32_t, 2>(tm, pm[q]);
+                tmv[2 * q] = lut_lo<uint32_t, 2>(tm, pm);
+                tmv[2 * q + 1] = lut_hi<uint32_t, 2>(tm, pm);
                 if constexpr (CR) {
                     // yz plane through the voxel's column, xz plane through its row
                     const uint32_t pyz = plane_pattern(Pp[t][j], Pp[t + 1][j], Pp[t + 2][j], Pc[t][j], Pc[t + 2][j],
@@ -402,31 +448,18 @@ struct March3D {
             }
 #pragma unroll
             for (int q = 0; q < VEC / 2; ++q) {
-                const int j = 2 * q + 1;
-                // an image pixel's event goes to the voxel of its pair that
-                // enters first (min image) or last (max image)
-                const uint32_t tb = MAXIMG ? below[q] : below[q] ^ 0x00010001u;
-                const uint32_t ta = MAXIMG ? above[q] : above[q] ^ 0x00010001u;
-                const uint32_t nb = below[q] + above[q];  // per half: vertical neighbours already in
-                const uint32_t lo0 = tlv[2 * q] + (uint32_t)((tb & 1u) ? E[t][j - 1] : 0) +
-                                     (uint32_t)((ta & 1u) ? en[2 * q] : 0) - ((nb & 0xFFFFu) << 23);
-                const uint32_t lo1 = tlv[2 * q + 1] + (uint32_t)((tb >> 16) ? E[t][j] : 0) +
-                                     (uint32_t)((ta >> 16) ? en[2 * q + 1] : 0) - ((nb >> 16) << 23);
-                E[t][j - 1] = en[2 * q];
-                E[t][j] = en[2 * q + 1];
-                const uint32_t self = selfv[q];
-                // bins lam' (1..W); a voxel outside the window or the field goes
-                // to its lane's own scratch bin (never drained) rather than
-                // branching: one address per lane keeps such voxels apart
-                uint32_t b0 = self & 0xFFFFu, b1 = self >> 16;
-                b0 = b0 - 1u < (uint32_t)W ? b0 : scratch;
-                b1 = b1 - 1u < (uint32_t)W ? b1 : scratch;
-                constexpr uint64_t cnt = 1ull << kShiftCnt3;
-                atomicAdd((unsigned long long *)&hist[b0], (unsigned long long)(cnt | lo0));
-                atomicAdd((unsigned long long *)&hist[b1], (unsigned long long)(cnt | lo1));
-                if constexpr (CR) {
-                    atomicAdd(&hc[b0], crv[2 * q]);
-                    atomicAdd(&hc[b1], crv[2 * q + 1]);
+#pragma unroll
+                for (int hv = 0; hv < 2; ++hv) {
+                    const int i = 2 * q + hv;
+                    const uint32_t u = own_share(tmv[i], hv ? mask_hi(dz[q]) : mask_lo(dz[q]));
+                    const uint32_t low = tlv[i] + C[t][i] + u;
+                    C[t][i] = tmv[i] - u;
+                    constexpr uint64_t cnt = 1ull << kShiftCnt3;
+                    lds_add64(addr[i], cnt | low);
+                    if constexpr (CR) {
+                        const uint32_t self = Pc[t + 1][2 * q + 1];
+                        lds_add32(hv ? mad_hi16(self, 4u, hc_base) : mad_lo16(self, 4u, hc_base), crv[i]);
+                    }
                 }
             }
         }
@@ -456,13 +489,15 @@ __global__ void __launch_bounds__(256)
     constexpr int VEC = Elem3<T>::VEC;
     extern __shared__ uint64_t smem[];
     __shared__ uint32_t tl[256];
-    __shared__ int32_t tm[256];
+    __shared__ uint32_t tm[256];
     __shared__ uint32_t tc[CR ? 256 : 1];
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int W = hi - lo;
     const int L = lv.L;
-    const int n_bins = W + 2 + 64;  // 1..W are the window's levels, then a scratch bin per lane
+    // bins [0, W + 2 kBinOff) (kBinOff .. kBinOff + W - 1 are the window's
+    // levels), the crease words of the same bins, then thresholds
+    const int n_bins = W + 2 * kBinOff;
     uint64_t *hist = smem;
     uint32_t *hc = reinterpret_cast<uint32_t *>(smem + n_bins);  // CR: crease words
     float *thr_s = reinterpret_cast<float *>(hc + (CR ? n_bins : 0));
@@ -474,7 +509,7 @@ __global__ void __launch_bounds__(256)
             thr_s[i] = lv.thr[k];
         }
     tl[tid] = tables[tid];
-    tm[tid] = (int32_t)tables[256 + tid];
+    tm[tid] = tables[256 + tid];
     if constexpr (CR) tc[tid] = crease_table[tid];
     for (int b = tid; b < n_bins; b += 256) {
         hist[b] = 0;
@@ -491,20 +526,21 @@ __global__ void __launch_bounds__(256)
     const int64_t units = n_strips * n_yb * D;
     const int64_t u_end = units * (gw + 1) / NW;
     const ThrLds thr{thr_s, lo - 2};
+    const LaneBins lb{(uint32_t)lane, (uint32_t)(W + kBinOff + lane)};
     for (int64_t u = units * gw / NW; u < u_end;) {
         const int64_t col = u / D, za = u % D;
         const int64_t zb = za + (u_end - u) < D ? za + (u_end - u) : D;
         const int64_t strip = col % n_strips, yb = col / n_strips;
         const int64_t xs = strip * 64 * VEC;
         March3D<T, LM, AL, MAXIMG, CR, TY, ThrLds> m{data, (int)d, h, w, lv, thr, lo, W, cpass, tl, tm,
-                                                      hist, xs, xs + (int64_t)lane * VEC, (int)(yb * TY),
+                                                      lds_addr(hist), xs, xs + (int64_t)lane * VEC, (int)(yb * TY),
                                                       (int)(z_lo + zb), lane, d * h * w > VEC ? d * h * w - VEC : 0,
-                                                      (uint32_t)(W + 2 + lane), tc, hc};
+                                                      lb, tc, lds_addr(hc)};
         m.run((int)(z_lo + za));
         u += zb - za;
     }
     __syncthreads();
-    drain_3d(hist + 1, CR ? hc + 1 : nullptr, CR, W, lo, L, G, wg, partial, accumulate == 0);
+    drain_3d(hist + kBinOff, CR ? hc + kBinOff : nullptr, CR, W, lo, L, G, wg, partial, accumulate == 0);
 }
 
 
@@ -711,8 +747,8 @@ static int launch_zm_t(const Launch3D &a, hipStream_t s) {
     int64_t chunk = a.z_hi - a.z_lo;
     while (chunk > 1 && max_wg_cells_3d(cols, chunk, a.grid) > kFlush3D) chunk = (chunk + 1) / 2;
     if (max_wg_cells_3d(cols, chunk, a.grid) > kFlush3D) return (int)hipErrorInvalidValue;
-    const float cpass = (float)(a.lv.u0d + 1.5 - a.lo);
-    const size_t lds = (size_t)(W + 2 + 64) * (CR ? 12 : 8) + (kThr ? (size_t)(W + 3) * 4 : 0);
+    const float cpass = (float)(a.lv.u0d + kBinOff + 0.5 - a.lo);
+    const size_t lds = (size_t)(W + 2 * kBinOff) * (CR ? 12 : 8) + (kThr ? (size_t)(W + 3) * 4 : 0);
     for (int64_t z0 = a.z_lo; z0 < a.z_hi; z0 += chunk) {
         const int64_t z1 = z0 + chunk < a.z_hi ? z0 + chunk : a.z_hi;
         const bool acc = a.accumulate || z0 > a.z_lo;

@@ -7,10 +7,6 @@ namespace ecc {
 // ---------------------------------------------------------------------------
 // merge of per-workgroup partials and prefix scan over levels
 // ---------------------------------------------------------------------------
-struct OutPtrs {
-    int64_t *p[4];
-};
-
 // One wave per (channel, level) sums the G workgroup partials of that bin
 // (coalesced reads, shuffle reduction).  The block that finishes last (ticket
 // on a counter that it then resets) takes the running sum over levels of
@@ -25,21 +21,7 @@ __global__ void __launch_bounds__(1024)
     for (int64_t bin = (int64_t)blockIdx.x * waves + wave; bin < n_bins; bin += (int64_t)gridDim.x * waves) {
         const int ch = (int)(bin / L);
         if (!out.p[ch]) continue;
-        const int32_t *src = partial + bin * G;
-        int64_t s = 0;
-        if ((G & 3) == 0) {  // 16-byte loads, several in flight per lane
-            const u32x4 *s4 = reinterpret_cast<const u32x4 *>(src);
-            const int G4 = G >> 2;
-#pragma unroll 4
-            for (int g = lane; g < G4; g += 64) {
-                const u32x4 v = __builtin_nontemporal_load(s4 + g);
-                s += (int64_t)(int32_t)v.x + (int32_t)v.y + (int32_t)v.z + (int32_t)v.w;
-            }
-        } else {
-            for (int g = lane; g < G; g += 64) s += src[g];
-        }
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+        const int64_t s = sum_bin_wave(partial + bin * G, G, lane);
         if (lane == 0) totals[bin] = s;
     }
     // publish this block's totals (release), take a ticket; the last block
@@ -50,55 +32,7 @@ __global__ void __launch_bounds__(1024)
     __syncthreads();
     if (!last) return;
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    // running sums over levels, all channels at once (independent loads and
-    // shuffle chains overlap): each thread sums a chunk of levels, the chunk
-    // sums are scanned within waves by shuffles, then over the wave totals
-    const int t = threadIdx.x, nt = blockDim.x;
-    const int per = (L + nt - 1) / nt;
-    const int beg = t * per, end = beg + per < L ? beg + per : L;
-    int64_t sum[4] = {0, 0, 0, 0}, x[4];
-#pragma unroll
-    for (int ch = 0; ch < 4; ++ch)
-        if (ch < nch && out.p[ch])
-            for (int i = beg; i < end; ++i) sum[ch] += totals[(int64_t)ch * L + i];
-#pragma unroll
-    for (int ch = 0; ch < 4; ++ch) x[ch] = sum[ch];
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-#pragma unroll
-        for (int ch = 0; ch < 4; ++ch) {
-            const int64_t y = __shfl_up(x[ch], off);
-            if (lane >= off) x[ch] += y;
-        }
-    }
-    __shared__ int64_t wtot[4][16];
-    if (lane == 63)
-#pragma unroll
-        for (int ch = 0; ch < 4; ++ch) wtot[ch][wave] = x[ch];
-    __syncthreads();
-    if (wave == 0) {
-#pragma unroll
-        for (int ch = 0; ch < 4; ++ch) {
-            int64_t v = lane < waves ? wtot[ch][lane] : 0;
-#pragma unroll
-            for (int off = 1; off < 16; off <<= 1) {
-                const int64_t y = __shfl_up(v, off);
-                if (lane >= off) v += y;
-            }
-            if (lane < waves) wtot[ch][lane] = v;
-        }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int ch = 0; ch < 4; ++ch) {
-        int64_t *dst = ch < nch ? out.p[ch] : nullptr;
-        if (!dst) continue;  // uniform
-        int64_t run = (wave > 0 ? wtot[ch][wave - 1] : 0) + x[ch] - sum[ch];
-        for (int i = beg; i < end; ++i) {
-            run += totals[(int64_t)ch * L + i];
-            dst[i] = run;
-        }
-    }
+    scan_totals_block(totals, nch, L, out);
     if (threadIdx.x == 0) *counter = 0u;  // ready for the next merge
 }
 

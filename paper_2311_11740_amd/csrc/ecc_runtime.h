@@ -13,7 +13,7 @@ namespace ecc {
 
 constexpr int kMaxLevels = 65535;   // level indices are staged as u16 (L = never)
 constexpr int kMaxWindow = 4096;    // levels histogrammed per pass (LDS budget)
-constexpr size_t kThrCacheMax = 32;
+constexpr size_t kThrCacheMax = 256;  // distinct threshold arrays kept on the device
 
 struct FieldInfo {
     int ndim, dtype;
@@ -29,6 +29,11 @@ struct DevBuf {
     void release();
 };
 
+// A threshold array cached on the device (by content).  `ready` follows the
+// last upload or level-table build, queued on `ready_stream`: work on any
+// other stream waits for it before reading the arrays.  `last_use` follows
+// the latest queued work that reads them, so that evicting the entry waits
+// for that work only.
 struct ThrEntry {
     int L = 0;
     std::vector<float> host;
@@ -39,6 +44,10 @@ struct ThrEntry {
     bool affine = false;
     float u0 = 0.f, inv_step = 0.f, eps = 0.f;
     double u0d = 0.0;
+    hipEvent_t ready = nullptr, last_use = nullptr;
+    void *ready_stream = nullptr;
+    bool used = false;
+    uint64_t tick = 0;  // last fetch, for LRU eviction
 };
 
 struct Workspace {
@@ -66,6 +75,7 @@ struct ecc_context_s {
     int64_t *d_cls3 = nullptr;                   // 3D class of each octant mask (-1 empty)
     uint32_t *d_crease3 = nullptr;               // 3D crease by z-marching: per-plane deltas + 4
     std::vector<ecc::ThrEntry *> thr_cache;
+    uint64_t thr_tick = 0;
     ecc::Workspace ws;
     hipEvent_t ws_event = nullptr;
     void *ws_stream = nullptr;
@@ -84,13 +94,30 @@ ecc_status hip_fail(int err, const char *what);
 ecc_status validate_field(const ecc_field *f, const ecc_curves *c, FieldInfo *info, bool curves_on_host);
 void free_thresholds(ThrEntry *t);
 ecc_status level_args(ecc_context ctx, const ecc_field *f, const FieldInfo &fi, void *stream, LevelArgs *lv);
-// make room in the threshold cache for n_new arrays, so that fetching them
-// evicts none of the others (drops the whole cache after a device sync if needed)
-ecc_status reserve_thresholds(ecc_context ctx, int n_new);
+// Makes room in the threshold cache for the distinct (by content) arrays of
+// `fields` that are not cached yet, so that fetching them all evicts none of
+// them; fails when they are more than the cache holds.
+ecc_status reserve_thresholds(ecc_context ctx, int n, const ecc_field *const *fields);
+// the distinct threshold arrays (by content) among `fields`
+int count_distinct_thresholds(int n, const ecc_field *const *fields);
+// records on `stream` that the work queued so far reads lv's threshold arrays
+ecc_status note_threshold_use(ecc_context ctx, const LevelArgs &lv, void *stream);
 ecc_status acquire_workspace(ecc_context ctx, void *stream);
 ecc_status release_workspace(ecc_context ctx, void *stream);
 ecc_status grow(ecc_context ctx, DevBuf &b, size_t need, const char *what);
 ecc_status compute_one(ecc_context ctx, const ecc_field *f, const FieldInfo &fi, const ecc_curves *c, void *stream);
+// launch geometry and buffer sizes of the single-field path
+struct OnePlan {
+    int grid, nch, win, k;
+    bool zmarch, crease;
+    size_t partial_bytes, totals_bytes;
+};
+OnePlan plan_one(ecc_context ctx, const FieldInfo &fi, const ecc_curves *c);
+ecc_status compute_core(ecc_context ctx, const ecc_field *f, const FieldInfo &fi, const ecc_curves *c,
+                        const LevelArgs &lv, const OnePlan &p, int32_t *partial, int64_t *totals,
+                        unsigned *counter, void *stream, bool timing);
+// the affine level estimate of a threshold array, if it has one (host only)
+bool affine_levels(const float *thr, int L, float *u0, double *u0d, float *inv_step, float *eps);
 int pick_grid(ecc_context ctx, int64_t n_tiles, size_t lds_per_wg);
 // workgroups per CU of the 2D stream kernel and of the 3D z-marching kernel
 // (ECC_WG_PER_CU, ECC_ZM_WG_PER_CU; defaults 4 and 2)

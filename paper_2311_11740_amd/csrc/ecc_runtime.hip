@@ -150,14 +150,18 @@ extern "C" ecc_status ecc_create(int device, ecc_context *out) {
         // z-marching tables from the 2D per-cell EC deltas of the same pattern
         // (8-C for the 26-C volume, 4-C for 6-C): [0, 256) the layer term with
         // the 2D perimeter delta (4 minus 2 per edge neighbour in) and the
-        // biases, [256, 512) the image delta, signs as the decomposition takes them
+        // biases, [256, 512) the image delta, signs as the decomposition takes
+        // them; the constant two surface units of the vertical neighbours'
+        // term sit in the layer term (min image) or the image term (max image)
         uint32_t zt[512];
         const int sgn = k == 0 ? -1 : 1;
+        const uint32_t two_faces = 2u << kShiftSurf3;
         for (int n = 0; n < 256; ++n) {  // in the kernels' index order
             const int p = pattern_of_index(n);
             const int per = 4 - 2 * __builtin_popcount(p & 0x5A);  // N, W, E, S bits
-            zt[n] = (uint32_t)(sgn * dt[p][0] + kEcBias3) + ((uint32_t)(per + 8) << kShiftSurf3);
-            zt[256 + n] = (uint32_t)(-sgn * dt[p][0]);
+            zt[n] = (uint32_t)(sgn * dt[p][0] + kEcBias3) + ((uint32_t)(per + 8) << kShiftSurf3) -
+                    (k == 0 ? two_faces : 0u);
+            zt[256 + n] = (uint32_t)(-sgn * dt[p][0]) - (k == 1 ? two_faces : 0u);
         }
         s = upload((void **)&ctx->d_zm3[k], zt, sizeof(zt));
         if (s != ECC_OK) {
@@ -299,32 +303,89 @@ void free_thresholds(ThrEntry *t) {
     if (t->d_lut8) hipFree(t->d_lut8);
     if (t->d_lut16) hipFree(t->d_lut16);
     if (t->h_pinned) hipHostFree(t->h_pinned);
+    if (t->ready) hipEventDestroy(t->ready);
+    if (t->last_use) hipEventDestroy(t->last_use);
     delete t;
+}
+
+static bool same_thresholds(const ThrEntry *t, const float *thr, int L) {
+    return t->L == L && std::memcmp(t->host.data(), thr, sizeof(float) * L) == 0;
+}
+
+static ThrEntry *find_thresholds(ecc_context ctx, const float *thr, int L) {
+    for (auto *t : ctx->thr_cache)
+        if (same_thresholds(t, thr, L)) return t;
+    return nullptr;
+}
+
+// Frees the least recently fetched entry outside `keep`, preferring one that
+// no queued work reads any more; otherwise waits for the latest work that
+// reads it (never for the whole device).
+static ecc_status evict_threshold(ecc_context ctx, const std::vector<const ThrEntry *> &keep) {
+    auto kept = [&keep](const ThrEntry *t) { return std::find(keep.begin(), keep.end(), t) != keep.end(); };
+    auto idle = [](const ThrEntry *t) {
+        return (!t->used || hipEventQuery(t->last_use) == hipSuccess) && hipEventQuery(t->ready) == hipSuccess;
+    };
+    int victim = -1;
+    for (int pass = 0; pass < 2 && victim < 0; ++pass)
+        for (int i = 0; i < (int)ctx->thr_cache.size(); ++i) {
+            ThrEntry *t = ctx->thr_cache[i];
+            if (kept(t) || (pass == 0 && !idle(t))) continue;
+            if (victim < 0 || t->tick < ctx->thr_cache[victim]->tick) victim = i;
+        }
+    if (victim < 0) return fail(ECC_ERR_UNSUPPORTED, "threshold cache: nothing to evict");
+    ThrEntry *t = ctx->thr_cache[victim];
+    int e = (int)hipEventSynchronize(t->ready);
+    if (!e && t->used) e = (int)hipEventSynchronize(t->last_use);
+    if (e) return hip_fail(e, "hipEventSynchronize(thresholds)");
+    free_thresholds(t);
+    ctx->thr_cache.erase(ctx->thr_cache.begin() + victim);
+    return ECC_OK;
+}
+
+// Affine check: the level is estimated from u = fma(x, 1/step, -t0/step) in
+// float32; where the fractional part of u is farther than eps from an
+// integer, floor(u)+1 is the exact level.  eps/2 bounds the thresholds'
+// deviation from the grid t0 + l*step (in steps) plus the rounding of u:
+// 1/step and -t0/step are rounded once each and the fma once, which for
+// |u| <= L + 2 moves u by at most (2 (L + 2) + |t0/step|) 2^-24 (with a 1 %
+// margin).
+bool affine_levels(const float *thr, int L, float *u0, double *u0d, float *inv_step, float *eps) {
+    if (L < 2) return false;
+    const double t0 = thr[0], step = ((double)thr[L - 1] - t0) / (L - 1);
+    if (!(step > 0 && std::isfinite(step) && std::isfinite(t0) && std::isfinite((double)thr[L - 1]))) return false;
+    double dev = 0;
+    for (int l = 0; l < L; ++l) dev = std::max(dev, std::fabs(thr[l] - (t0 + l * step)) / step);
+    const float inv_f = (float)(1.0 / step);
+    const double u0_d = -t0 * (double)inv_f;
+    const double round_u = (2.0 * (L + 2.0) + std::fabs(t0 / step) + 2.0) * 1.01 * std::ldexp(1.0, -24);
+    const double e = 2.0 * (dev + round_u) + 1e-6;
+    if (!(e < 0.25)) return false;
+    *u0 = (float)u0_d;
+    *u0d = u0_d;
+    *inv_step = inv_f;
+    *eps = (float)e;
+    return true;
 }
 
 ecc_status get_thresholds(ecc_context ctx, const float *thr, int L, int dtype, void *stream,
                           const ThrEntry **out) {
-    ThrEntry *hit = nullptr;
-    for (auto *t : ctx->thr_cache)
-        if (t->L == L && std::memcmp(t->host.data(), thr, sizeof(float) * L) == 0) {
-            hit = t;
-            break;
-        }
+    ThrEntry *hit = find_thresholds(ctx, thr, L);
+    hipStream_t st = (hipStream_t)stream;
     if (!hit) {
         if (ctx->thr_cache.size() >= kThrCacheMax) {
-            // rare: drop every cached set once all queued work is done
-            int e = (int)hipDeviceSynchronize();
-            if (e) return hip_fail(e, "hipDeviceSynchronize");
-            for (auto *t : ctx->thr_cache) free_thresholds(t);
-            ctx->thr_cache.clear();
+            ecc_status s = evict_threshold(ctx, {});
+            if (s != ECC_OK) return s;
         }
         auto *t = new ThrEntry();
         t->L = L;
         t->host.assign(thr, thr + L);
-        int e = (int)hipHostMalloc(&t->h_pinned, sizeof(float) * L, 0);
+        int e = (int)hipEventCreateWithFlags(&t->ready, hipEventDisableTiming);
+        if (!e) e = (int)hipEventCreateWithFlags(&t->last_use, hipEventDisableTiming);
+        if (!e) e = (int)hipHostMalloc(&t->h_pinned, sizeof(float) * L, 0);
         if (e) {
-            delete t;
-            return hip_fail(e, "hipHostMalloc(thresholds)");
+            free_thresholds(t);
+            return hip_fail(e, "threshold cache entry");
         }
         std::memcpy(t->h_pinned, thr, sizeof(float) * L);
         e = (int)hipMalloc(&t->d_thr, sizeof(float) * L);
@@ -332,68 +393,86 @@ ecc_status get_thresholds(ecc_context ctx, const float *thr, int L, int dtype, v
             free_thresholds(t);
             return fail(ECC_ERR_OUT_OF_MEMORY, "hipMalloc(thresholds) failed");
         }
-        e = (int)hipMemcpyAsync(t->d_thr, t->h_pinned, sizeof(float) * L, hipMemcpyHostToDevice,
-                                (hipStream_t)stream);
+        e = (int)hipMemcpyAsync(t->d_thr, t->h_pinned, sizeof(float) * L, hipMemcpyHostToDevice, st);
+        if (!e) e = (int)hipEventRecord(t->ready, st);
         if (e) {
             free_thresholds(t);
             return hip_fail(e, "hipMemcpyAsync(thresholds)");
         }
-        // affine check: the level is estimated from u = fma(x, 1/step, -t0/step)
-        // in float32; where the fractional part of u is farther than eps from
-        // an integer, floor(u)+1 is the exact level.  eps/2 bounds the
-        // thresholds' deviation from the grid t0 + l*step (in steps) plus the
-        // rounding of u: 1/step and -t0/step are rounded once each and the
-        // fma once, which for |u| <= L + 2 moves u by at most
-        // (2 (L + 2) + |t0/step|) 2^-24 (with a 1 % margin).
-        t->affine = false;
-        if (L >= 2) {
-            const double t0 = thr[0], step = ((double)thr[L - 1] - t0) / (L - 1);
-            if (step > 0 && std::isfinite(step) && std::isfinite(t0) && std::isfinite((double)thr[L - 1])) {
-                double dev = 0;
-                for (int l = 0; l < L; ++l) dev = std::max(dev, std::fabs(thr[l] - (t0 + l * step)) / step);
-                const float inv_f = (float)(1.0 / step);
-                const double u0_d = -t0 * (double)inv_f;
-                const float u0_f = (float)u0_d;
-                const double round_u = (2.0 * (L + 2.0) + std::fabs(t0 / step) + 2.0) * 1.01 * std::ldexp(1.0, -24);
-                const double eps = 2.0 * (dev + round_u) + 1e-6;
-                if (eps < 0.25) {
-                    t->affine = true;
-                    t->u0 = u0_f;
-                    t->u0d = u0_d;
-                    t->inv_step = inv_f;
-                    t->eps = (float)eps;
-                }
-            }
-        }
+        t->ready_stream = stream;
+        t->affine = affine_levels(thr, L, &t->u0, &t->u0d, &t->inv_step, &t->eps);
         ctx->thr_cache.push_back(t);
         hit = t;
+    } else if (hit->ready_stream != stream) {
+        // the upload (or a level table) was queued on another stream
+        int e = (int)hipStreamWaitEvent(st, hit->ready, 0);
+        if (e) return hip_fail(e, "hipStreamWaitEvent(thresholds)");
     }
+    hit->tick = ++ctx->thr_tick;
     // integer fields with thresholds: value -> level table, built once on the device
-    if (dtype == ECC_U8 && !hit->d_lut8) {
-        int e = (int)hipMalloc(&hit->d_lut8, 256 * sizeof(uint16_t));
-        if (e) return fail(ECC_ERR_OUT_OF_MEMORY, "hipMalloc(level table) failed");
-        e = launch_level_lut(hit->d_thr, L, 256, hit->d_lut8, stream);
+    const bool need8 = dtype == ECC_U8 && !hit->d_lut8, need16 = dtype == ECC_U16 && !hit->d_lut16;
+    if (need8 || need16) {
+        uint16_t **dst = need8 ? &hit->d_lut8 : &hit->d_lut16;
+        const int nv = need8 ? 256 : 65536;
+        int e = (int)hipMalloc(dst, nv * sizeof(uint16_t));
+        if (e) {
+            *dst = nullptr;
+            return fail(ECC_ERR_OUT_OF_MEMORY, "hipMalloc(level table) failed");
+        }
+        e = launch_level_lut(hit->d_thr, L, nv, *dst, stream);
+        if (!e) e = (int)hipEventRecord(hit->ready, st);
         if (e) return hip_fail(e, "level table kernel");
-    }
-    if (dtype == ECC_U16 && !hit->d_lut16) {
-        int e = (int)hipMalloc(&hit->d_lut16, 65536 * sizeof(uint16_t));
-        if (e) return fail(ECC_ERR_OUT_OF_MEMORY, "hipMalloc(level table) failed");
-        e = launch_level_lut(hit->d_thr, L, 65536, hit->d_lut16, stream);
-        if (e) return hip_fail(e, "level table kernel");
+        hit->ready_stream = stream;
     }
     *out = hit;
     return ECC_OK;
 }
 
-ecc_status reserve_thresholds(ecc_context ctx, int n_new) {
-    if (n_new > (int)kThrCacheMax)
-        return fail(ECC_ERR_UNSUPPORTED, "a batch may use at most 32 distinct threshold arrays");
-    if (ctx->thr_cache.size() + (size_t)n_new > kThrCacheMax) {
-        int e = (int)hipDeviceSynchronize();
-        if (e) return hip_fail(e, "hipDeviceSynchronize");
-        for (auto *t : ctx->thr_cache) free_thresholds(t);
-        ctx->thr_cache.clear();
+static int count_distinct(int n, const ecc_field *const *fields, ecc_context ctx, bool uncached_only) {
+    int k = 0;
+    for (int i = 0; i < n; ++i) {
+        const ecc_field *f = fields[i];
+        if (!f->thresholds) continue;
+        bool seen = false;
+        for (int j = 0; j < i && !seen; ++j)
+            seen = fields[j]->thresholds && fields[j]->n_levels == f->n_levels &&
+                   (fields[j]->thresholds == f->thresholds ||
+                    std::memcmp(fields[j]->thresholds, f->thresholds, sizeof(float) * f->n_levels) == 0);
+        if (seen) continue;
+        if (uncached_only && ctx && find_thresholds(ctx, f->thresholds, f->n_levels)) continue;
+        ++k;
     }
+    return k;
+}
+
+int count_distinct_thresholds(int n, const ecc_field *const *fields) {
+    return count_distinct(n, fields, nullptr, false);
+}
+
+ecc_status reserve_thresholds(ecc_context ctx, int n, const ecc_field *const *fields) {
+    if (count_distinct(n, fields, nullptr, false) > (int)kThrCacheMax)
+        return fail(ECC_ERR_UNSUPPORTED, "one call may use at most 256 distinct threshold arrays");
+    const int n_new = count_distinct(n, fields, ctx, true);
+    std::vector<const ThrEntry *> keep;  // the arrays of this call that are cached already
+    for (int i = 0; i < n; ++i)
+        if (fields[i]->thresholds)
+            if (const ThrEntry *t = find_thresholds(ctx, fields[i]->thresholds, fields[i]->n_levels)) keep.push_back(t);
+    while (ctx->thr_cache.size() + (size_t)n_new > kThrCacheMax) {
+        ecc_status s = evict_threshold(ctx, keep);
+        if (s != ECC_OK) return s;
+    }
+    return ECC_OK;
+}
+
+ecc_status note_threshold_use(ecc_context ctx, const LevelArgs &lv, void *stream) {
+    if (!lv.thr) return ECC_OK;
+    for (auto *t : ctx->thr_cache)
+        if (t->d_thr == lv.thr) {
+            int e = (int)hipEventRecord(t->last_use, (hipStream_t)stream);
+            if (e) return hip_fail(e, "hipEventRecord(thresholds)");
+            t->used = true;
+            return ECC_OK;
+        }
     return ECC_OK;
 }
 
@@ -499,49 +578,57 @@ ecc_status merge_and_scan(ecc_context ctx, int grid, int nch, int L, int64_t *co
     return ECC_OK;
 }
 
-ecc_status compute_one(ecc_context ctx, const ecc_field *f, const FieldInfo &fi,
-                       const ecc_curves *c, void *stream) {
-    LevelArgs lv;
-    ecc_status s = level_args(ctx, f, fi, stream, &lv);
-    if (s != ECC_OK) return s;
+// Launch geometry of one field on the single-field path.
+OnePlan plan_one(ecc_context ctx, const FieldInfo &fi, const ecc_curves *c) {
+    OnePlan p;
     const int L = fi.L;
-    const int nch = fi.ndim == 2 ? 3 : 4;
-    const int win = std::min(L, kMaxWindow);
-    const bool crease = fi.ndim == 3 && c->perimeter != nullptr;
-    const int k = (fi.ndim == 2 ? (fi.conn == 8 ? 0 : 1) : (fi.conn == 26 ? 0 : 1));
-    int grid = 1;
-    bool zmarch = false;
+    p.nch = fi.ndim == 2 ? 3 : 4;
+    p.win = std::min(L, kMaxWindow);
+    p.crease = fi.ndim == 3 && c->perimeter != nullptr;
+    p.k = (fi.ndim == 2 ? (fi.conn == 8 ? 0 : 1) : (fi.conn == 26 ? 0 : 1));
+    p.grid = 1;
+    p.zmarch = false;
     if (fi.ndim == 2) {
         const int vec = vec_2d(fi.dtype);
         const int64_t strips = (fi.w + 62 * vec - 1) / (62 * vec);
-        grid = (int)std::min<int64_t>((int64_t)ctx->n_cu * wg_per_cu_default(),
-                                      std::max<int64_t>(1, (strips * fi.h + 31) / 32));
-        if (grid >= 8) grid -= grid % 8;
+        p.grid = (int)std::min<int64_t>((int64_t)ctx->n_cu * wg_per_cu_default(),
+                                        std::max<int64_t>(1, (strips * fi.h + 31) / 32));
+        if (p.grid >= 8) p.grid -= p.grid % 8;
     } else {
         // z-marching kernel: at least ~16 planes per wave; its register use
         // leaves room for two 4-wave workgroups per CU, so one round of
         // 2 x CUs workgroups (fewer partials than more, smaller rounds); the
         // crease channel, when wanted, comes along in the same kernel.
         const int64_t units = (int64_t)zmarch_3d_columns(fi.h, fi.w) * fi.d;
-        grid = (int)std::min<int64_t>((int64_t)ctx->n_cu * zm_wg_per_cu(),
-                                      std::max<int64_t>(1, (units + 63) / 64));
-        if (grid >= 8) grid -= grid % 8;
+        p.grid = (int)std::min<int64_t>((int64_t)ctx->n_cu * zm_wg_per_cu(),
+                                        std::max<int64_t>(1, (units + 63) / 64));
+        if (p.grid >= 8) p.grid -= p.grid % 8;
         // A volume too small to give every CU a z-marching workgroup (its
         // columns are 256 voxels wide) runs faster on the tile kernel.
         // ECC_3D_KERNEL=tile or =zmarch overrides the choice (read per call).
         const char *ek = std::getenv("ECC_3D_KERNEL");
         const bool force_tile = ek && std::strcmp(ek, "tile") == 0;
         const bool force_zm = ek && std::strcmp(ek, "zmarch") == 0;
-        zmarch = !force_tile && zmarch_3d_fits(fi.h, fi.w, grid) && (force_zm || grid >= ctx->n_cu);
+        p.zmarch = !force_tile && zmarch_3d_fits(fi.h, fi.w, p.grid) && (force_zm || p.grid >= ctx->n_cu);
     }
-    if (fi.ndim == 3 && !zmarch) {
+    if (fi.ndim == 3 && !p.zmarch) {
         const int64_t n_tiles = ((fi.w + kTile3DX - 1) / kTile3DX) * ((fi.h + kTile3DY - 1) / kTile3DY) *
                                 ((fi.d + kTile3DZ - 1) / kTile3DZ);
-        grid = pick_grid(ctx, n_tiles, lds_bytes_3d(win, crease) + 16 * 1024);
+        p.grid = pick_grid(ctx, n_tiles, lds_bytes_3d(p.win, p.crease) + 16 * 1024);
     }
-    s = grow(ctx, ctx->ws.partial, (size_t)grid * nch * L * sizeof(int32_t), "partials");
-    if (s != ECC_OK) return s;
-    int32_t *partial = (int32_t *)ctx->ws.partial.ptr;
+    p.partial_bytes = (size_t)p.grid * p.nch * L * sizeof(int32_t);
+    p.totals_bytes = (size_t)p.nch * L * sizeof(int64_t);
+    return p;
+}
+
+// The field kernels, then the merge and scan, into buffers the caller
+// provides (at least plan.partial_bytes and plan.totals_bytes; `counter` a
+// zero word that the merge leaves at zero).  Allocates nothing.
+ecc_status compute_core(ecc_context ctx, const ecc_field *f, const FieldInfo &fi, const ecc_curves *c,
+                        const LevelArgs &lv, const OnePlan &p, int32_t *partial, int64_t *totals,
+                        unsigned *counter, void *stream, bool timing) {
+    const int L = fi.L;
+    int64_t *outs[4] = {c->ec, c->perimeter, c->area, fi.ndim == 3 ? c->volume : nullptr};
     // the kernels load whole blocks of 16 bytes (2D) or 4 elements (3D), clamped
     // to the end of the field: a field smaller than one block is copied into a
     // buffer that holds a whole block
@@ -553,33 +640,46 @@ ecc_status compute_one(ecc_context ctx, const ecc_field *f, const FieldInfo &fi,
         if (e) return hip_fail(e, "hipMemcpyAsync(small field)");
         data = ctx->d_tiny;
     }
-    for (int lo = 0; lo < L; lo += win) {
-        const int hi = std::min(L, lo + win);
+    const int k = p.k;
+    for (int lo = 0; lo < L; lo += p.win) {
+        const int hi = std::min(L, lo + p.win);
+        int slot = -1;
+        ecc_status s = timing ? prof_begin(ctx, stream, &slot) : ECC_OK;
+        if (s != ECC_OK) return s;
         if (fi.ndim == 2) {
-            int slot = -1;
-            s = prof_begin(ctx, stream, &slot);
-            if (s != ECC_OK) return s;
-            Launch2D a{data, fi.dtype, fi.h, fi.w, lv, lo, hi, ctx->d_delta2[k], partial, grid,
+            Launch2D a{data, fi.dtype, fi.h, fi.w, lv, lo, hi, ctx->d_delta2[k], partial, p.grid,
                        0, fi.h, false, false};
             int e = launch_2d(a, stream);
             if (e) return hip_fail(e, "2D kernel launch");
-            s = prof_end(ctx, stream, slot);
-            if (s != ECC_OK) return s;
         } else {
-            int slot = -1;
-            s = prof_begin(ctx, stream, &slot);
-            if (s != ECC_OK) return s;
-            Launch3D a{data, fi.dtype, fi.d, fi.h, fi.w, lv, lo, hi, ctx->d_vtab3[k], partial, grid,
-                       zmarch ? false : crease, zmarch ? ctx->d_zm3[k] : nullptr, k == 1, 0, fi.d, false, false,
-                       zmarch && crease ? ctx->d_crease3 : nullptr};
+            Launch3D a{data, fi.dtype, fi.d, fi.h, fi.w, lv, lo, hi, ctx->d_vtab3[k], partial, p.grid,
+                       p.zmarch ? false : p.crease, p.zmarch ? ctx->d_zm3[k] : nullptr, k == 1, 0, fi.d, false,
+                       false, p.zmarch && p.crease ? ctx->d_crease3 : nullptr};
             int e = launch_3d(a, stream);
             if (e) return hip_fail(e, "3D kernel launch");
-            s = prof_end(ctx, stream, slot);
-            if (s != ECC_OK) return s;
         }
+        s = prof_end(ctx, stream, slot);
+        if (s != ECC_OK) return s;
     }
-    int64_t *outs[4] = {c->ec, c->perimeter, c->area, fi.ndim == 3 ? c->volume : nullptr};
-    return merge_and_scan(ctx, grid, nch, L, outs, stream);
+    int e = launch_merge(partial, p.grid, p.nch, L, outs, totals, counter, stream);
+    if (e) return hip_fail(e, "merge kernel launch");
+    return ECC_OK;
+}
+
+ecc_status compute_one(ecc_context ctx, const ecc_field *f, const FieldInfo &fi,
+                       const ecc_curves *c, void *stream) {
+    LevelArgs lv;
+    ecc_status s = level_args(ctx, f, fi, stream, &lv);
+    if (s != ECC_OK) return s;
+    const OnePlan p = plan_one(ctx, fi, c);
+    s = grow(ctx, ctx->ws.partial, p.partial_bytes, "partials");
+    if (s != ECC_OK) return s;
+    s = grow(ctx, ctx->ws.totals, p.totals_bytes, "totals");
+    if (s != ECC_OK) return s;
+    s = compute_core(ctx, f, fi, c, lv, p, (int32_t *)ctx->ws.partial.ptr, (int64_t *)ctx->ws.totals.ptr,
+                     (unsigned *)ctx->d_counter, stream, true);
+    if (s != ECC_OK) return s;
+    return note_threshold_use(ctx, lv, stream);
 }
 
 // class channels into counts[c][L], three at a time (the merge kernel scans up
@@ -636,7 +736,9 @@ static ecc_status compute_classes_3d(ecc_context ctx, const ecc_field *f, const 
         s = prof_end(ctx, stream, slot);
         if (s != ECC_OK) return s;
     }
-    return merge_classes(ctx, grid, nch, L, counts, stream);
+    s = merge_classes(ctx, grid, nch, L, counts, stream);
+    if (s != ECC_OK) return s;
+    return note_threshold_use(ctx, lv, stream);
 }
 
 // Class counts of a 2D field: the single-field 2D path with the class-count
@@ -675,7 +777,9 @@ static ecc_status compute_classes(ecc_context ctx, const ecc_field *f, const Fie
         s = prof_end(ctx, stream, slot);
         if (s != ECC_OK) return s;
     }
-    return merge_classes(ctx, grid, nch, L, counts, stream);
+    s = merge_classes(ctx, grid, nch, L, counts, stream);
+    if (s != ECC_OK) return s;
+    return note_threshold_use(ctx, lv, stream);
 }
 
 }  // namespace ecc

@@ -284,14 +284,30 @@ ecc_status launch_ready(ecc_server srv, std::vector<std::pair<Request *, ecc_sta
     std::vector<Request *> batch2d, other;
     const int li = free_launch(srv);
     std::deque<Request *> keep;
+    // a launch takes at most as many distinct threshold arrays (by content) as
+    // the context's cache holds at once; requests beyond wait for the next one
+    std::vector<const ecc_field *> thr_fields;
+    int n_thr = 0;
     for (Request *r : srv->ready) {
-        if (batchable(r->fi) && li >= 0 && (int)batch2d.size() < srv->cfg.max_batch)
+        bool take = batchable(r->fi) && li >= 0 && (int)batch2d.size() < srv->cfg.max_batch;
+        if (take && r->field.thresholds) {
+            thr_fields.push_back(&r->field);
+            const int k = count_distinct_thresholds((int)thr_fields.size(), thr_fields.data());
+            if (k > (int)kThrCacheMax) {
+                thr_fields.pop_back();
+                take = false;
+            } else {
+                n_thr = k;
+            }
+        }
+        if (take)
             batch2d.push_back(r);
         else if (!batchable(r->fi))
             other.push_back(r);
         else
             keep.push_back(r);  // waits for the next launch
     }
+    (void)n_thr;
     if (batch2d.empty() && other.empty()) return ECC_OK;
     srv->ready.swap(keep);
     std::lock_guard<std::mutex> lk(ctx->mu);
@@ -299,10 +315,7 @@ ecc_status launch_ready(ecc_server srv, std::vector<std::pair<Request *, ecc_sta
     if (!batch2d.empty()) {
         auto &L = srv->ring[li];
         std::vector<LevelArgs> lv(batch2d.size());
-        std::vector<const float *> distinct;
-        for (Request *r : batch2d)
-            if (r->field.thresholds) distinct.push_back(r->field.thresholds);
-        s = reserve_thresholds(ctx, (int)distinct.size());
+        s = reserve_thresholds(ctx, (int)thr_fields.size(), thr_fields.data());
         for (size_t i = 0; i < batch2d.size() && s == ECC_OK; ++i)
             s = level_args(ctx, &batch2d[i]->field, batch2d[i]->fi, srv->s_2d, &lv[i]);
         // group by (dtype, level mode); one schedule per group, items appended
@@ -358,7 +371,7 @@ ecc_status launch_ready(ecc_server srv, std::vector<std::pair<Request *, ecc_sta
                 d.n_items = n_items_of[i];
                 d.conn_idx = r->fi.conn == 8 ? 0 : 1;
                 d.inv_step = lv[i].inv_step;
-                d.cpass = (float)(lv[i].u0d + 1.5);
+                d.cpass = (float)(lv[i].u0d + kBinOff + 0.5);
                 d.eps = lv[i].eps;
             }
             std::memcpy(L.h_items, all_items.data(), sizeof(BatchItem) * all_items.size());
@@ -373,6 +386,11 @@ ecc_status launch_ready(ecc_server srv, std::vector<std::pair<Request *, ecc_sta
                 e = launch_batch_2d(gl[g].dtype, gl[g].lm, L.d_desc, L.d_items + gl[g].item0,
                                     L.d_first + gl[g].first0, gl[g].grid, srv->d_luts, gl[g].max_L, srv->s_2d);
             if (e) s = hip_fail(e, "serving batched launch");
+            for (size_t i = 0; i < batch2d.size() && s == ECC_OK; ++i) {  // the launch reads these arrays
+                bool seen = false;
+                for (size_t j = 0; j < i && !seen; ++j) seen = lv[j].thr == lv[i].thr;
+                if (!seen) s = note_threshold_use(ctx, lv[i], srv->s_2d);
+            }
         }
         for (Request *r : batch2d)
             if (s == ECC_OK) s = copy_back(srv, r, srv->s_2d);

@@ -1,8 +1,8 @@
 """GPU parity at the full workload sizes, in the launch configuration the
 benchmark times.
 
-* 2D 256 x 256 uint8 (256 levels): every level against the per-level counting
-  oracle (O1) and the all-levels oracle (O2).
+* 2D 256 x 256 uint8 (256 levels), 8- and 4-connectivity: every level against
+  the per-level counting oracle (O1) and the all-levels oracle (O2).
 * 2D 8192 x 8192 float32 (1024 thresholds) and 3D 512^3 uint16 (4096 levels):
   whole curves against O2, and a few sampled levels against O1, which
   binarises and counts cells at one level at a time.
@@ -58,17 +58,22 @@ def check_o1_levels(spec, got, levels, tag):
             assert got[k][lv] == ref[k][i], f"{tag} {k} level {lv}: gpu {got[k][lv]} oracle {ref[k][i]}"
 
 
-def test_small_2d_all_levels():
+@pytest.mark.parametrize("conn", [8, 4])
+def test_small_2d_all_levels(conn):
+    """The 256 x 256 uint8 field at every level, with both readings of its
+    pixels: closed faces (8-connectivity) and grid vertices (4-connectivity)."""
     from paper_2311_11740_amd import ecc, synth
     import oracle
     spec = synth.small_2d_u8()
+    spec = synth.FieldSpec(spec.data, spec.n_levels, spec.thresholds, conn,
+                           dict(spec.meta, name=f"{spec.meta['name']}_{conn}c"))
     print(f"[case] {spec.meta['name']}", flush=True)
     c = ecc.Context(0)
     try:
         got = gpu_curves(c, spec, None)
     finally:
         c.close()
-    ref = oracle.o1_curves(spec.data, spec.n_levels, connectivity=8)
+    ref = oracle.o1_curves(spec.data, spec.n_levels, connectivity=conn)
     for k in got:
         assert np.array_equal(got[k], ref[k]), k
     check_o2(spec, got, spec.meta["name"])
@@ -94,15 +99,17 @@ def test_large_3d_u16(ctx, channels):
         check_o1_levels(spec, got, [1500, 2048, 2600], spec.meta["name"])
 
 
-@pytest.mark.parametrize("conn", [26, 6])
-def test_3d_zmarch_split_along_z(ctx, conn):
+@pytest.mark.parametrize("conn,channels", [(26, ("ec", "area", "volume")), (6, ("ec", "area", "volume")),
+                                           (26, None)], ids=["26c", "6c", "26c_all_channels"])
+def test_3d_zmarch_split_along_z(ctx, conn, channels):
     """288 x 1024 x 1024 uint8: 1024 columns x 288 planes exceed what one
-    launch may add to a workgroup's bins, so the launch is split along z."""
+    launch may add to a workgroup's bins, so the launch is split along z
+    (with the crease channel too, which shares the split)."""
     from paper_2311_11740_amd import synth
     rng = np.random.default_rng(77)
     a = rng.integers(0, 200, size=(288, 1024, 1024), dtype=np.uint8)
     a[rng.integers(0, 288, 64), rng.integers(0, 1024, 64), rng.integers(0, 1024, 64)] = 255  # never
     spec = synth.FieldSpec(a, 200, None, conn, dict(name=f"3d_288x1024x1024_u8_{conn}c"))
     print(f"[case] {spec.meta['name']}", flush=True)
-    got = gpu_curves(ctx, spec, ("ec", "area", "volume"))
+    got = gpu_curves(ctx, spec, channels)
     check_o2(spec, got, spec.meta["name"])

@@ -1,8 +1,9 @@
 """GPU parity: libecc curves == the oracle's curves, bit for bit, through the C ABI.
 
 Every case is printed (and flushed) before it runs so that a failing GPU step
-names its case.  Sizes span several tiles (2D tiles are 32 x 256 cells, 3D
-tiles 16 x 4 x 64) with ragged tails, the degenerate shapes (1 x 1, 1 x N,
+names its case.  Sizes span several work units (2D: strips of 62 lanes x 16
+bytes of a row, streamed down the rows; 3D: columns of 4 rows x 256 voxels
+marched along z, or tiles of 16 x 4 x 64 voxels) with ragged tails, the degenerate shapes (1 x 1, 1 x N,
 N x 1), every level mode (identity integer levels, integer levels through
 thresholds, affine float thresholds, irregular float thresholds with ties),
 NaN and never-active values, constant fields, one level, and level counts above

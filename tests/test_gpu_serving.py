@@ -7,6 +7,9 @@
 * Admission by memory: with a small budget, requests that do not fit are
   refused with BUSY and admitted later; one larger than the whole budget is
   rejected outright; the server's results stay exact throughout.
+* Thresholds: many thresholded float32 requests ready at once (each with its
+  own copy of an array), more distinct arrays than the context caches, and one
+  array shared by the batched 2D stream and the single-field 3D stream.
 """
 from __future__ import annotations
 
@@ -142,3 +145,68 @@ def test_serving_admission_by_memory(ctx):
         srv.close()
     assert busy > 0, "the budget never refused a request"
     check(results, reqs, "admission")
+
+
+def test_serving_many_thresholded_requests(ctx):
+    """More thresholded float32 2D requests ready at once than one launch of
+    the batched kernel used to take (each request carries its own copy of one
+    of three threshold arrays), then more distinct arrays than the context
+    caches at once: every request completes and equals the oracle."""
+    from paper_2311_11740_amd import ecc, synth
+    rng = np.random.default_rng(303)
+    thr_sets = [synth.linspace_thresholds(-3, 3, 64), synth.linspace_thresholds(-2, 2.5, 100),
+                np.sort(rng.normal(size=50)).astype(np.float32)]
+    reqs = []
+    for k in range(120):
+        thr = thr_sets[k % 3]
+        h, w = (int(x) for x in rng.integers(8, 64, size=2))
+        reqs.append((rng.normal(size=(h, w)).astype(np.float32), len(thr), thr.copy(), 8 if k % 2 else 4))
+    print(f"[case] serving {len(reqs)} thresholded f32 requests, max_batch 256", flush=True)
+    srv = ecc.Server(ctx, 256 << 20, max_slots=256, max_batch=256)
+    try:
+        results, _ = serve_all(srv, reqs)
+        srv.drain()
+        many = []
+        for k in range(300):  # 300 distinct arrays: more than the 256 cached at once
+            thr = np.sort(rng.normal(size=int(rng.integers(5, 40)))).astype(np.float32)
+            many.append((rng.normal(size=(int(rng.integers(4, 30)), int(rng.integers(4, 30)))).astype(np.float32),
+                         len(thr), thr, 8))
+        print(f"[case] serving {len(many)} requests with distinct threshold arrays", flush=True)
+        results2, _ = serve_all(srv, many, timeout=120.0)
+        srv.drain()
+    finally:
+        srv.close()
+    check(results, reqs, "thresholded")
+    check(results2, many, "distinct_thresholds")
+
+
+def test_serving_shared_thresholds_2d_and_3d(ctx):
+    """One threshold array used by batched 2D float32 requests and by 3D
+    requests on the single-field stream (float32, and uint16 with its
+    value -> level table), submitted interleaved, twice over."""
+    from paper_2311_11740_amd import ecc, synth
+    rng = np.random.default_rng(304)
+    thr = synth.linspace_thresholds(-2.5, 2.5, 150)
+    thr_int = np.linspace(0.5, 900.5, 150).astype(np.float32)
+    reqs = []
+    for k in range(40):
+        kind = k % 4
+        if kind in (0, 1):
+            h, w = (int(x) for x in rng.integers(16, 200, size=2))
+            reqs.append((synth.grf((h, w), 3.0, int(rng.integers(1 << 30))), 150, thr.copy(), 8))
+        elif kind == 2:
+            d, h, w = (int(x) for x in rng.integers(4, 30, size=3))
+            reqs.append((synth.grf((d, h, w), 2.0, int(rng.integers(1 << 30))), 150, thr.copy(), 26))
+        else:
+            d, h, w = (int(x) for x in rng.integers(4, 30, size=3))
+            reqs.append((rng.integers(0, 1000, size=(d, h, w)).astype(np.uint16), 150, thr_int.copy(), 26))
+    print(f"[case] serving shared thresholds 2D+3D n={len(reqs)}", flush=True)
+    srv = ecc.Server(ctx, 256 << 20, max_slots=64, max_batch=64)
+    try:
+        res_a, _ = serve_all(srv, reqs)
+        res_b, _ = serve_all(srv, reqs[::-1])
+        srv.drain()
+    finally:
+        srv.close()
+    check(res_a, reqs, "shared_thresholds")
+    check(res_b, reqs[::-1], "shared_thresholds_rev")

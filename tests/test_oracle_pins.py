@@ -462,3 +462,35 @@ def test_o1_equals_o2(seed, o2):
         b = o2(f, L, thresholds=thr, connectivity=conn)
         for k in a:
             assert (a[k] == b[k]).all(), (k, conn, a[k], b[k])
+
+
+# ----------------------------------------------------------------------------
+# O2's threaded histogram == its single-threaded one
+# ----------------------------------------------------------------------------
+@pytest.mark.parametrize("seed", range(6))
+def test_o2_threads_equal_single_thread(seed, o2):
+    """The GPU tests and the CPU baseline run O2 with 16 threads (per-thread
+    histograms over slabs of lattice rows or planes, summed): it must give
+    exactly its single-thread result, with every thread owning a slab."""
+    rng = np.random.default_rng(700 + seed)
+    nd = 2 if seed % 2 == 0 else 3
+    shape = (int(rng.integers(40, 90)), int(rng.integers(20, 60))) if nd == 2 else \
+        (int(rng.integers(20, 40)), int(rng.integers(8, 20)), int(rng.integers(8, 20)))
+    kind = seed % 3
+    thr = None
+    if kind == 0:
+        L = 200
+        f = rng.integers(0, 230, size=shape).astype(np.uint8)
+    elif kind == 1:
+        L = 1000
+        f = rng.integers(0, 1100, size=shape).astype(np.uint16)
+    else:
+        L = 97
+        f = rng.normal(size=shape).astype(np.float32)
+        thr = np.sort(rng.normal(size=L)).astype(np.float32)
+        f.ravel()[::17] = np.nan
+    for conn in ((8, 4) if nd == 2 else (26, 6)):
+        one = o2(f, L, thresholds=thr, connectivity=conn, n_threads=1)
+        many = o2(f, L, thresholds=thr, connectivity=conn, n_threads=16)
+        for k in one:
+            assert np.array_equal(one[k], many[k]), (k, conn)
