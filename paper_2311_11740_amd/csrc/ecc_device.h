@@ -355,6 +355,37 @@ __device__ __forceinline__ uint32_t from_lane_above(uint32_t x) {
     return (uint32_t)__builtin_amdgcn_mov_dpp((int)x, 0x130, 0xf, 0xf, true);
 }
 
+// Issue priority of a wave by how far it is through its share of the work:
+// 3 in the first quarter down to 0 in the last.  Waves of equal work share a
+// SIMD; with equal priorities the oldest issues first and the others finish
+// later, one by one, leaving the SIMD with too few waves at the end.  Waves
+// that are ahead step down, so the ones behind catch up.
+struct ProgressPrio {
+    int64_t q1 = 0, q2 = 0, q3 = 0;  // work done at the quarter marks
+    int cur = 3;
+    bool on = false;
+    __device__ void init(bool enable, int64_t total) {
+        on = enable;
+        q1 = total / 4;
+        q2 = total / 2;
+        q3 = total - total / 4;
+        cur = 3;
+        if (on) __builtin_amdgcn_s_setprio(3);
+    }
+    __device__ __forceinline__ void update(int64_t done) {
+        if (!on) return;
+        const int p = done < q1 ? 3 : (done < q2 ? 2 : (done < q3 ? 1 : 0));
+        if (p == cur) return;
+        cur = p;
+        if (p == 2)
+            __builtin_amdgcn_s_setprio(2);
+        else if (p == 1)
+            __builtin_amdgcn_s_setprio(1);
+        else
+            __builtin_amdgcn_s_setprio(0);
+    }
+};
+
 // (a.hi, b.lo): the 16-bit value just below b's low half
 __device__ __forceinline__ uint32_t straddle(uint32_t a, uint32_t b) {
     return __builtin_amdgcn_alignbit(b, a, 16);

@@ -109,6 +109,9 @@ struct Launch2D {
 };
 
 size_t lds_bytes_2d(int window, bool classes);
+// whether the field kernels lower a wave's priority as it progresses
+// (default; environment ECC_PRIO=0 turns it off)
+bool progress_prio();
 
 // cells per lane along the contiguous axis (16 bytes of input per lane)
 inline int vec_2d(int dtype) { return dtype == 1 ? 16 : (dtype == 2 ? 8 : 4); }

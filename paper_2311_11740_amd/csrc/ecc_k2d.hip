@@ -230,7 +230,8 @@ template <typename T, int LM, int AL, int PF, bool CLS, typename TH>
 __device__ __forceinline__ void stream_run_2d(const T *__restrict__ data, int h, int64_t w,
                                               const LevelArgs &lv, const TH &thr, int32_t lo, int W,
                                               float cpass, const uint64_t *dl, int64_t strip,
-                                              int ra, int rb, int lane, const LaneBins &lb, const LaneDst &ld) {
+                                              int ra, int rb, int lane, const LaneBins &lb, const LaneDst &ld,
+                                              ProgressPrio &pp, int64_t done0) {
     static_assert(PF % 3 == 0, "PF must be a multiple of 3");
     constexpr int VEC = Elem<T>::VEC;
     constexpr int CE = 62 * VEC;  // cells owned per strip
@@ -259,6 +260,7 @@ __device__ __forceinline__ void stream_run_2d(const T *__restrict__ data, int h,
     int r0 = ra;
     // full blocks of PF rows: no conditional loads, so PF loads stay in flight
     for (; r0 + PF <= rb; r0 += PF) {
+        pp.update(done0 + (r0 - ra));
 #pragma unroll
         for (int k = 0; k < PF; ++k) {
             const int r = r0 + k;  // current row (buffer k%3); ring[k] holds row r + 1
@@ -287,7 +289,7 @@ template <typename T, int LM, int AL, int PF, bool CLS>
 __global__ void __launch_bounds__(256)
     ecc2d_stream(const T *__restrict__ data, int64_t h, int64_t w, LevelArgs lv, int32_t lo,
                  int32_t hi, float cpass, const uint64_t *__restrict__ delta_lut, int32_t *__restrict__ partial,
-                 int64_t row_lo, int64_t row_hi, int accumulate) {
+                 int64_t row_lo, int64_t row_hi, int accumulate, int prio) {
     constexpr int VEC = Elem<T>::VEC;
     constexpr int CE = 62 * VEC;
     constexpr int BW = CLS ? 2 : 1;  // words per bin
@@ -327,11 +329,14 @@ __global__ void __launch_bounds__(256)
     const uint32_t h0 = lds_addr(hist);
     const LaneDst ld{halo ? 0u : 8u * BW, halo ? h0 + 8u * BW * lb.never : h0};
     const ThrLds thr{thr_s, lo - 2};
-    for (int64_t u = units * gw / NW; u < u_end;) {
+    const int64_t u_beg = units * gw / NW;
+    ProgressPrio pp;
+    pp.init(prio != 0, u_end - u_beg);
+    for (int64_t u = u_beg; u < u_end;) {
         const int64_t strip = u / H, ra = u % H;
         const int64_t rb = ra + (u_end - u) < H ? ra + (u_end - u) : H;
         stream_run_2d<T, LM, AL, PF, CLS>(data, (int)h, w, lv, thr, lo, W, cpass, dl, strip, (int)(row_lo + ra),
-                                          (int)(row_lo + rb), lane, lb, ld);
+                                          (int)(row_lo + rb), lane, lb, ld, pp, u - u_beg);
         u += rb - ra;
     }
     __syncthreads();
@@ -396,13 +401,14 @@ __global__ void __launch_bounds__(256)
         const LaneBins lb{(uint32_t)lane, (uint32_t)(L + kBinOff + lane)};
         const uint32_t h0 = lds_addr(hist);
         const LaneDst ld{halo_lane ? 0u : 8u, halo_lane ? h0 + 8u * lb.never : h0};
+        ProgressPrio pp;  // (off in the batched kernel)
         const int n = item.u1 - item.u0;
         const int u_end = item.u0 + (int)((int64_t)n * (wave + 1) / kWavesPerWG);
         for (int u = item.u0 + (int)((int64_t)n * wave / kWavesPerWG); u < u_end;) {
             const int strip = u / h, ra = u % h;
             const int rb = ra + (u_end - u) < h ? ra + (u_end - u) : h;
             stream_run_2d<T, LM, kLoadVector, PF, false>((const T *)f.data, h, w, lv, thr, 0, L, f.cpass,
-                                                         dl[f.conn_idx], strip, ra, rb, lane, lb, ld);
+                                                         dl[f.conn_idx], strip, ra, rb, lane, lb, ld, pp, 0);
             u += rb - ra;
         }
         __syncthreads();
@@ -495,7 +501,7 @@ static int launch_2d_t(const Launch2D &a, hipStream_t s) {
         const bool acc = a.accumulate || r0 > a.row_lo;
         hipLaunchKernelGGL((ecc2d_stream<T, LM, AL, PF, CLS>), dim3(a.grid), dim3(256), lds, s,
                            (const T *)a.data, a.h, a.w, a.lv, a.lo, a.hi, cpass, a.delta_lut, a.partial, r0, r1,
-                           acc ? 1 : 0);
+                           acc ? 1 : 0, progress_prio() ? 1 : 0);
         const int e = (int)hipGetLastError();
         if (e) return e;
     }

@@ -465,10 +465,11 @@ struct March3D {
         }
     }
 
-    __device__ __forceinline__ void run(int za) {
+    __device__ __forceinline__ void run(int za, ProgressPrio &pp, int64_t done0) {
         prologue(za);
         int z = za;
         for (; z + 3 <= zb; z += 3) {
+            pp.update(done0 + (z - za));
             step<0>(z);
             step<1>(z + 1);
             step<2>(z + 2);
@@ -485,7 +486,7 @@ __global__ void __launch_bounds__(256)
     ecc3d_stream(const T *__restrict__ data, int64_t d, int64_t h, int64_t w, LevelArgs lv, int32_t lo,
                  int32_t hi, float cpass, const uint32_t *__restrict__ tables,
                  const uint32_t *__restrict__ crease_table, int32_t *__restrict__ partial, int64_t z_lo,
-                 int64_t z_hi, int accumulate) {
+                 int64_t z_hi, int accumulate, int prio) {
     constexpr int VEC = Elem3<T>::VEC;
     extern __shared__ uint64_t smem[];
     __shared__ uint32_t tl[256];
@@ -527,7 +528,10 @@ __global__ void __launch_bounds__(256)
     const int64_t u_end = units * (gw + 1) / NW;
     const ThrLds thr{thr_s, lo - 2};
     const LaneBins lb{(uint32_t)lane, (uint32_t)(W + kBinOff + lane)};
-    for (int64_t u = units * gw / NW; u < u_end;) {
+    const int64_t u_beg = units * gw / NW;
+    ProgressPrio pp;
+    pp.init(prio != 0, u_end - u_beg);
+    for (int64_t u = u_beg; u < u_end;) {
         const int64_t col = u / D, za = u % D;
         const int64_t zb = za + (u_end - u) < D ? za + (u_end - u) : D;
         const int64_t strip = col % n_strips, yb = col / n_strips;
@@ -536,7 +540,7 @@ __global__ void __launch_bounds__(256)
                                                       lds_addr(hist), xs, xs + (int64_t)lane * VEC, (int)(yb * TY),
                                                       (int)(z_lo + zb), lane, d * h * w > VEC ? d * h * w - VEC : 0,
                                                       lb, tc, lds_addr(hc)};
-        m.run((int)(z_lo + za));
+        m.run((int)(z_lo + za), pp, u - u_beg);
         u += zb - za;
     }
     __syncthreads();
@@ -754,7 +758,7 @@ static int launch_zm_t(const Launch3D &a, hipStream_t s) {
         const bool acc = a.accumulate || z0 > a.z_lo;
         hipLaunchKernelGGL((ecc3d_stream<T, LM, AL, MAXIMG, CR, kZmTY>), dim3(a.grid), dim3(256), lds, s,
                            (const T *)a.data, a.d, a.h, a.w, a.lv, a.lo, a.hi, cpass, a.zm_tables, a.crease_table,
-                           a.partial, z0, z1, acc ? 1 : 0);
+                           a.partial, z0, z1, acc ? 1 : 0, progress_prio() ? 1 : 0);
         const int e = (int)hipGetLastError();
         if (e) return e;
     }

@@ -558,6 +558,14 @@ int wg_per_cu_default() {
     return v;
 }
 
+bool progress_prio() {
+    static bool v = [] {
+        const char *e = std::getenv("ECC_PRIO");
+        return !(e && std::strcmp(e, "0") == 0);
+    }();
+    return v;
+}
+
 // Workgroups per CU for the z-marching 3D kernel (environment ECC_ZM_WG_PER_CU overrides).
 int zm_wg_per_cu() {
     static int v = [] {
