@@ -133,6 +133,35 @@ ecc_status ecc_curves_compute(ecc_context ctx, const ecc_field *field, const ecc
                               void *stream);
 
 /*
+ * ecc_curves_compute for callers that cannot allocate device memory: code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.
+ * Same arguments, validation, asynchrony and results as ecc_curves_compute,
+ * but every device buffer of the call (the merge ticket, the staged
+ * thresholds, the value -> level table of integer fields with thresholds, the
+ * per-level totals and the per-workgroup partials) lives in one static device
+ * array of ECC_NOALLOC_SCRATCH_BYTES per GPU, held from the first context
+ * created on that GPU until the process ends; the call makes no hipMalloc,
+ * hipFree or other allocating call.
+ *   - Thresholds are copied into the context's pinned staging buffer (made by
+ *     ecc_create); the call first waits on the host until the previous
+ *     staging copy of this context has run.
+ *   - Every call of this entry point on one GPU (any context, stream or
+ *     thread of the process) shares the array and keeps the last call's
+ *     contents: calls that overlap on the device race; order them (one
+ *     stream, or events).  The merge ticket is cleared by each call.
+ *   - Limit: partials (workgroups x channels x n_levels x 4 bytes; the
+ *     workgroups are 4 per CU in 2D, 2 per CU for large 3D volumes) plus
+ *     totals (channels x n_levels x 8 bytes) plus 384 KiB must fit in
+ *     ECC_NOALLOC_SCRATCH_BYTES, e.g. 8192^2 with 1024 levels takes 12 MiB and
+ *     512^3 with 4096 levels 32 MiB; larger requests return
+ *     ECC_ERR_UNSUPPORTED before any work is queued.
+ *   - Kernel timing (ecc_profile_enable) does not record these launches.
+ */
+#define ECC_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+ecc_status ecc_curves_compute_noalloc(ecc_context ctx, const ecc_field *field, const ecc_curves *curves,
+                                      void *stream);
+
+/*
  * Curves of a field that lives in HOST memory, streamed through the device in
  * slabs (the GPU counterpart of the paper's low-memory mode, Computational
  * Results on memory scaling and the Conclusions): the field is cut along its

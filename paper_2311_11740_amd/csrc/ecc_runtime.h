@@ -83,6 +83,12 @@ struct ecc_context_s {
     ecc::BatchState *batch = nullptr;
     void *d_counter = nullptr;  // merge kernel's completion ticket (kept at zero)
     void *d_tiny = nullptr;     // 256 B: padded copy of fields smaller than one vector load
+    // allocation-free entry point: this device's scratch array, and a pinned
+    // staging buffer for thresholds (65536 floats) reused once `stage_event`
+    // (recorded after its last copy) has completed
+    unsigned char *scratch = nullptr;
+    float *h_stage = nullptr;
+    hipEvent_t stage_event = nullptr;
     // kernel timing (ecc_profile_enable)
     bool prof_on = false;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_events;
@@ -116,6 +122,9 @@ OnePlan plan_one(ecc_context ctx, const FieldInfo &fi, const ecc_curves *c);
 ecc_status compute_core(ecc_context ctx, const ecc_field *f, const FieldInfo &fi, const ecc_curves *c,
                         const LevelArgs &lv, const OnePlan &p, int32_t *partial, int64_t *totals,
                         unsigned *counter, void *stream, bool timing);
+// address of the allocation-free entry point's scratch array on `device`
+// (looked up once per device; the device must be current)
+ecc_status noalloc_scratch(int device, unsigned char **out);
 // the affine level estimate of a threshold array, if it has one (host only)
 bool affine_levels(const float *thr, int L, float *u0, double *u0d, float *inv_step, float *eps);
 int pick_grid(ecc_context ctx, int64_t n_tiles, size_t lds_per_wg);

@@ -218,12 +218,20 @@ extern "C" ecc_status ecc_create(int device, ecc_context *out) {
         return fail(ECC_ERR_OUT_OF_MEMORY, "hipMalloc(counter) failed");
     }
     e = (int)hipMemset(ctx->d_counter, 0, 256);
+    if (!e) e = (int)hipHostMalloc(&ctx->h_stage, sizeof(float) * 65536, 0);
+    if (!e) e = (int)hipEventCreateWithFlags(&ctx->stage_event, hipEventDisableTiming);
     if (!e) e = (int)hipMalloc(&ctx->d_tiny, 256);
     if (!e) e = (int)hipMemset(ctx->d_tiny, 0, 256);
     if (!e) e = (int)hipDeviceSynchronize();
     if (e) {
         ecc_destroy(ctx);
         return hip_fail(e, "hipMemset(counter)");
+    }
+    // the allocation-free entry point's scratch array on this device
+    ecc_status ss = noalloc_scratch(device, &ctx->scratch);
+    if (ss != ECC_OK) {
+        ecc_destroy(ctx);
+        return ss;
     }
     *out = ctx;
     return ECC_OK;
@@ -251,6 +259,8 @@ extern "C" ecc_status ecc_destroy(ecc_context ctx) {
     ctx->ws.release();
     if (ctx->d_counter) hipFree(ctx->d_counter);
     if (ctx->d_tiny) hipFree(ctx->d_tiny);
+    if (ctx->h_stage) hipHostFree(ctx->h_stage);
+    if (ctx->stage_event) hipEventDestroy(ctx->stage_event);
     if (ctx->ws_event) hipEventDestroy(ctx->ws_event);
     destroy_batch_state(ctx);
     delete ctx;

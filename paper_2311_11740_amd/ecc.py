@@ -20,7 +20,8 @@ ECC_U8, ECC_U16, ECC_F32 = 1, 2, 3
 # public C entry points (kept in step with include/ecc.h)
 EXPORTS = (
     "ecc_create", "ecc_destroy", "ecc_last_error", "ecc_status_string",
-    "ecc_curves_compute", "ecc_curves_compute_streamed", "ecc_curves_compute_batch", "ecc_batch_plan_tune",
+    "ecc_curves_compute", "ecc_curves_compute_noalloc", "ecc_curves_compute_streamed", "ecc_curves_compute_batch",
+    "ecc_batch_plan_tune",
     "ecc_vertex_table", "ecc_vertex_classes_compute", "ecc_vertex_class_table",
     "ecc_validate_field", "ecc_profile_enable", "ecc_profile_read",
     "ecc_server_create", "ecc_server_submit", "ecc_server_poll", "ecc_server_drain",
@@ -78,6 +79,7 @@ def load(path: str = LIB_PATH):
         "ecc_last_error": ([], ctypes.c_char_p),
         "ecc_status_string": ([ctypes.c_int], ctypes.c_char_p),
         "ecc_curves_compute": ([vp, ctypes.POINTER(Field), ctypes.POINTER(Curves), vp], ctypes.c_int),
+        "ecc_curves_compute_noalloc": ([vp, ctypes.POINTER(Field), ctypes.POINTER(Curves), vp], ctypes.c_int),
         "ecc_curves_compute_streamed": ([vp, ctypes.POINTER(Field), ctypes.POINTER(Curves), ctypes.c_size_t, vp],
                                         ctypes.c_int),
         "ecc_curves_compute_batch": ([vp, i32, ctypes.POINTER(Field), ctypes.POINTER(Curves), vp],
@@ -245,9 +247,11 @@ class Context:
         return ms.value, n.value
 
     def compute(self, field, n_levels: int, thresholds=None, connectivity: int = 0,
-                channels: Sequence[str] | None = None, stream=None, out=None):
+                channels: Sequence[str] | None = None, stream=None, out=None, noalloc: bool = False):
         """Curves of one device field: dict channel -> int64 device tensor (async on `stream`).
-        `out` may supply preallocated curves (dict channel -> int64 tensor of n_levels)."""
+        `out` may supply preallocated curves (dict channel -> int64 tensor of n_levels).
+        `noalloc` calls ecc_curves_compute_noalloc (the library allocates no
+        device memory for the call; `out` avoids torch's allocation too)."""
         f, keep = make_field(field, n_levels, thresholds, connectivity)
         if out is None:
             out, cv = alloc_curves(field.dim(), n_levels, field.device, channels)
@@ -255,8 +259,8 @@ class Context:
             cv = Curves()
             for c in ("ec", "perimeter", "area", "volume"):
                 setattr(cv, c, out[c].data_ptr() if c in out else None)
-        check(self._lib.ecc_curves_compute(self.handle, ctypes.byref(f), ctypes.byref(cv),
-                                           _stream_ptr(stream)))
+        fn = self._lib.ecc_curves_compute_noalloc if noalloc else self._lib.ecc_curves_compute
+        check(fn(self.handle, ctypes.byref(f), ctypes.byref(cv), _stream_ptr(stream)))
         del keep
         return out
 
