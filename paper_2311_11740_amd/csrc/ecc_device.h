@@ -31,6 +31,7 @@
 //   * `ecc2d_batch` runs many fields in one persistent launch.
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <cstdlib>

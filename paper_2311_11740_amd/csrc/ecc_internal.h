@@ -106,6 +106,9 @@ struct Launch2D {
     int64_t row_lo, row_hi;     // rows whose cells this launch emits (halo rows are read)
     bool accumulate;            // add to the partials instead of overwriting them
     bool classes;               // class counts: delta_lut holds 2 x 256 words, partial is [5][L][grid]
+    // timing (hipEvent_t or NULL): the first launch's start and the last
+    // launch's end are recorded by the dispatches themselves
+    void *ev_start = nullptr, *ev_stop = nullptr;
 };
 
 size_t lds_bytes_2d(int window, bool classes);
@@ -143,6 +146,8 @@ struct Launch3D {
     // z-marching kernel: the per-plane crease table when the crease channel
     // is wanted (it then comes along in the same launch), else NULL
     const uint32_t *crease_table;
+    // timing, as in Launch2D
+    void *ev_start = nullptr, *ev_stop = nullptr;
 };
 
 // ---- batched 2D launch ----------------------------------------------------------

@@ -499,9 +499,11 @@ static int launch_2d_t(const Launch2D &a, hipStream_t s) {
     for (int64_t r0 = a.row_lo; r0 < a.row_hi; r0 += chunk) {
         const int64_t r1 = r0 + chunk < a.row_hi ? r0 + chunk : a.row_hi;
         const bool acc = a.accumulate || r0 > a.row_lo;
-        hipLaunchKernelGGL((ecc2d_stream<T, LM, AL, PF, CLS>), dim3(a.grid), dim3(256), lds, s,
-                           (const T *)a.data, a.h, a.w, a.lv, a.lo, a.hi, cpass, a.delta_lut, a.partial, r0, r1,
-                           acc ? 1 : 0, progress_prio() ? 1 : 0);
+        hipExtLaunchKernelGGL((ecc2d_stream<T, LM, AL, PF, CLS>), dim3(a.grid), dim3(256), lds, s,
+                              r0 == a.row_lo ? (hipEvent_t)a.ev_start : nullptr,
+                              r1 == a.row_hi ? (hipEvent_t)a.ev_stop : nullptr, 0, (const T *)a.data, a.h, a.w,
+                              a.lv, a.lo, a.hi, cpass, a.delta_lut, a.partial, r0, r1, acc ? 1 : 0,
+                              progress_prio() ? 1 : 0);
         const int e = (int)hipGetLastError();
         if (e) return e;
     }

@@ -721,9 +721,9 @@ static int launch_3d_t(const Launch3D &a, hipStream_t s) {
     const int flush = (int)(kFlush3D / (kTile3DX * kTile3DY * kTile3DZ));
     const int W = a.hi - a.lo;
     const size_t lds = MODE == 2 ? (size_t)W * kNumClasses3D * 4 : lds_bytes_3d(W, MODE == 1);
-    hipLaunchKernelGGL((ecc3d_tile<T, LM, MODE>), dim3(a.grid), dim3(256), lds, s,
-                       (const T *)a.data, a.d, a.h, a.w, a.lv, a.lo, a.hi, a.vtab, a.partial,
-                       tiles_x, tiles_y, n_tiles, flush);
+    hipExtLaunchKernelGGL((ecc3d_tile<T, LM, MODE>), dim3(a.grid), dim3(256), lds, s, (hipEvent_t)a.ev_start,
+                          (hipEvent_t)a.ev_stop, 0, (const T *)a.data, a.d, a.h, a.w, a.lv, a.lo, a.hi, a.vtab,
+                          a.partial, tiles_x, tiles_y, n_tiles, flush);
     return (int)hipGetLastError();
 }
 
@@ -756,9 +756,11 @@ static int launch_zm_t(const Launch3D &a, hipStream_t s) {
     for (int64_t z0 = a.z_lo; z0 < a.z_hi; z0 += chunk) {
         const int64_t z1 = z0 + chunk < a.z_hi ? z0 + chunk : a.z_hi;
         const bool acc = a.accumulate || z0 > a.z_lo;
-        hipLaunchKernelGGL((ecc3d_stream<T, LM, AL, MAXIMG, CR, kZmTY>), dim3(a.grid), dim3(256), lds, s,
-                           (const T *)a.data, a.d, a.h, a.w, a.lv, a.lo, a.hi, cpass, a.zm_tables, a.crease_table,
-                           a.partial, z0, z1, acc ? 1 : 0, progress_prio() ? 1 : 0);
+        hipExtLaunchKernelGGL((ecc3d_stream<T, LM, AL, MAXIMG, CR, kZmTY>), dim3(a.grid), dim3(256), lds, s,
+                              z0 == a.z_lo ? (hipEvent_t)a.ev_start : nullptr,
+                              z1 == a.z_hi ? (hipEvent_t)a.ev_stop : nullptr, 0, (const T *)a.data, a.d, a.h, a.w,
+                              a.lv, a.lo, a.hi, cpass, a.zm_tables, a.crease_table, a.partial, z0, z1, acc ? 1 : 0,
+                              progress_prio() ? 1 : 0);
         const int e = (int)hipGetLastError();
         if (e) return e;
     }

@@ -131,6 +131,7 @@ int pick_grid(ecc_context ctx, int64_t n_tiles, size_t lds_per_wg);
 // workgroups per CU of the 2D stream kernel and of the 3D z-marching kernel
 // (ECC_WG_PER_CU, ECC_ZM_WG_PER_CU; defaults 4 and 2)
 int wg_per_cu_default();
+int grid_2d(ecc_context ctx, const FieldInfo &fi, int window, bool classes);
 int zm_wg_per_cu();
 ecc_status merge_and_scan(ecc_context ctx, int grid, int nch, int L, int64_t *const outs[4], void *stream);
 void destroy_batch_state(ecc_context ctx);
@@ -146,4 +147,8 @@ int schedule_batch_2d(int n_cu, int dtype, int lm, int max_L, const std::vector<
 // records the start event of a timed launch on `stream` (no-op unless profiling)
 ecc_status prof_begin(ecc_context ctx, void *stream, int *slot);
 ecc_status prof_end(ecc_context ctx, void *stream, int slot);
+// a pair of timing events for the launches of one field-reading pass, which
+// the dispatches record themselves (kernel start and end, no launch overhead);
+// both NULL unless profiling
+ecc_status prof_events(ecc_context ctx, hipEvent_t *start, hipEvent_t *stop);
 }  // namespace ecc

@@ -596,6 +596,21 @@ ecc_status merge_and_scan(ecc_context ctx, int grid, int nch, int L, int64_t *co
     return ECC_OK;
 }
 
+// Workgroups of the 2D stream kernel: wg_per_cu_default() per CU, fewer when
+// a workgroup's LDS (bins of a `window`-level pass, thresholds, tables) would
+// not let that many share a CU's 160 KB, and at most one per 32 (strip, row)
+// units of the field.
+int grid_2d(ecc_context ctx, const FieldInfo &fi, int window, bool classes) {
+    const int vec = vec_2d(fi.dtype);
+    const int64_t strips = (fi.w + 62 * vec - 1) / (62 * vec);
+    const size_t lds = lds_bytes_2d(window, classes) + (classes ? 4096 : 2048);
+    const int fit = std::max<int>(1, (int)((160 * 1024) / lds));
+    int grid = (int)std::min<int64_t>((int64_t)ctx->n_cu * std::min(wg_per_cu_default(), fit),
+                                      std::max<int64_t>(1, (strips * fi.h + 31) / 32));
+    if (grid >= 8) grid -= grid % 8;
+    return grid;
+}
+
 // Launch geometry of one field on the single-field path.
 OnePlan plan_one(ecc_context ctx, const FieldInfo &fi, const ecc_curves *c) {
     OnePlan p;
@@ -607,11 +622,7 @@ OnePlan plan_one(ecc_context ctx, const FieldInfo &fi, const ecc_curves *c) {
     p.grid = 1;
     p.zmarch = false;
     if (fi.ndim == 2) {
-        const int vec = vec_2d(fi.dtype);
-        const int64_t strips = (fi.w + 62 * vec - 1) / (62 * vec);
-        p.grid = (int)std::min<int64_t>((int64_t)ctx->n_cu * wg_per_cu_default(),
-                                        std::max<int64_t>(1, (strips * fi.h + 31) / 32));
-        if (p.grid >= 8) p.grid -= p.grid % 8;
+        p.grid = grid_2d(ctx, fi, p.win, false);
     } else {
         // z-marching kernel: at least ~16 planes per wave; its register use
         // leaves room for two 4-wave workgroups per CU, so one round of
@@ -661,23 +672,25 @@ ecc_status compute_core(ecc_context ctx, const ecc_field *f, const FieldInfo &fi
     const int k = p.k;
     for (int lo = 0; lo < L; lo += p.win) {
         const int hi = std::min(L, lo + p.win);
-        int slot = -1;
-        ecc_status s = timing ? prof_begin(ctx, stream, &slot) : ECC_OK;
+        hipEvent_t ev0 = nullptr, ev1 = nullptr;
+        ecc_status s = timing ? prof_events(ctx, &ev0, &ev1) : ECC_OK;
         if (s != ECC_OK) return s;
         if (fi.ndim == 2) {
             Launch2D a{data, fi.dtype, fi.h, fi.w, lv, lo, hi, ctx->d_delta2[k], partial, p.grid,
                        0, fi.h, false, false};
+            a.ev_start = ev0;
+            a.ev_stop = ev1;
             int e = launch_2d(a, stream);
             if (e) return hip_fail(e, "2D kernel launch");
         } else {
             Launch3D a{data, fi.dtype, fi.d, fi.h, fi.w, lv, lo, hi, ctx->d_vtab3[k], partial, p.grid,
                        p.zmarch ? false : p.crease, p.zmarch ? ctx->d_zm3[k] : nullptr, k == 1, 0, fi.d, false,
                        false, p.zmarch && p.crease ? ctx->d_crease3 : nullptr};
+            a.ev_start = ev0;
+            a.ev_stop = ev1;
             int e = launch_3d(a, stream);
             if (e) return hip_fail(e, "3D kernel launch");
         }
-        s = prof_end(ctx, stream, slot);
-        if (s != ECC_OK) return s;
     }
     int e = launch_merge(partial, p.grid, p.nch, L, outs, totals, counter, stream);
     if (e) return hip_fail(e, "merge kernel launch");
@@ -744,15 +757,15 @@ static ecc_status compute_classes_3d(ecc_context ctx, const ecc_field *f, const 
     int32_t *partial = (int32_t *)ctx->ws.partial.ptr;
     for (int lo = 0; lo < L; lo += win) {
         const int hi = std::min(L, lo + win);
-        int slot = -1;
-        s = prof_begin(ctx, stream, &slot);
-        if (s != ECC_OK) return s;
         Launch3D a{f->data, fi.dtype, fi.d, fi.h, fi.w, lv, lo, hi, ctx->d_cls3, partial, grid, false,
                    nullptr, false, 0, fi.d, false, true, nullptr};
+        hipEvent_t ev0, ev1;
+        s = prof_events(ctx, &ev0, &ev1);
+        if (s != ECC_OK) return s;
+        a.ev_start = ev0;
+        a.ev_stop = ev1;
         int e = launch_3d(a, stream);
         if (e) return hip_fail(e, "3D class-count kernel launch");
-        s = prof_end(ctx, stream, slot);
-        if (s != ECC_OK) return s;
     }
     s = merge_classes(ctx, grid, nch, L, counts, stream);
     if (s != ECC_OK) return s;
@@ -770,10 +783,7 @@ static ecc_status compute_classes(ecc_context ctx, const ecc_field *f, const Fie
     const int L = fi.L, nch = kNumClasses2D;
     const int win = std::min(L, kMaxWindow);
     const int vec = vec_2d(fi.dtype);
-    const int64_t strips = (fi.w + 62 * vec - 1) / (62 * vec);
-    int grid = (int)std::min<int64_t>((int64_t)ctx->n_cu * wg_per_cu_default(),
-                                      std::max<int64_t>(1, (strips * fi.h + 31) / 32));
-    if (grid >= 8) grid -= grid % 8;
+    const int grid = grid_2d(ctx, fi, win, true);
     s = grow(ctx, ctx->ws.partial, (size_t)grid * nch * L * sizeof(int32_t), "partials");
     if (s != ECC_OK) return s;
     int32_t *partial = (int32_t *)ctx->ws.partial.ptr;
@@ -786,14 +796,14 @@ static ecc_status compute_classes(ecc_context ctx, const ecc_field *f, const Fie
     }
     for (int lo = 0; lo < L; lo += win) {
         const int hi = std::min(L, lo + win);
-        int slot = -1;
-        s = prof_begin(ctx, stream, &slot);
-        if (s != ECC_OK) return s;
         Launch2D a{data, fi.dtype, fi.h, fi.w, lv, lo, hi, ctx->d_cls2, partial, grid, 0, fi.h, false, true};
+        hipEvent_t ev0, ev1;
+        s = prof_events(ctx, &ev0, &ev1);
+        if (s != ECC_OK) return s;
+        a.ev_start = ev0;
+        a.ev_stop = ev1;
         int e = launch_2d(a, stream);
         if (e) return hip_fail(e, "2D class-count kernel launch");
-        s = prof_end(ctx, stream, slot);
-        if (s != ECC_OK) return s;
     }
     s = merge_classes(ctx, grid, nch, L, counts, stream);
     if (s != ECC_OK) return s;
@@ -866,6 +876,23 @@ ecc_status prof_end(ecc_context ctx, void *stream, int slot) {
     if (slot < 0) return ECC_OK;
     int e = (int)hipEventRecord(ctx->prof_events[slot].second, (hipStream_t)stream);
     if (e) return hip_fail(e, "hipEventRecord");
+    return ECC_OK;
+}
+
+ecc_status prof_events(ecc_context ctx, hipEvent_t *start, hipEvent_t *stop) {
+    *start = *stop = nullptr;
+    if (!ctx->prof_on) return ECC_OK;
+    if (ctx->prof_used == ctx->prof_events.size()) {
+        hipEvent_t a, b;
+        int e = (int)hipEventCreate(&a);
+        if (e) return hip_fail(e, "hipEventCreate");
+        e = (int)hipEventCreate(&b);
+        if (e) return hip_fail(e, "hipEventCreate");
+        ctx->prof_events.push_back({a, b});
+    }
+    const size_t slot = ctx->prof_used++;
+    *start = ctx->prof_events[slot].first;
+    *stop = ctx->prof_events[slot].second;
     return ECC_OK;
 }
 }  // namespace ecc

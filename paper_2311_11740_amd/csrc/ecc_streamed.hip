@@ -67,11 +67,9 @@ ecc_status stream_field(ecc_context ctx, const ecc_field *f, const FieldInfo &fi
         if (!zmarch_3d_fits(fi.h, fi.w, grid))
             return fail(ECC_ERR_UNSUPPORTED, "streamed 3D fields: planes too large for the z-marching kernel");
     } else {
-        const int vec = vec_2d(fi.dtype);
-        const int64_t strips = (fi.w + 62 * vec - 1) / (62 * vec);
-        grid = (int)std::min<int64_t>((int64_t)ctx->n_cu * wg_per_cu_default(),
-                                      std::max<int64_t>(1, (strips * R + 31) / 32));
-        if (grid >= 8) grid -= grid % 8;
+        FieldInfo slab = fi;
+        slab.h = R;
+        grid = grid_2d(ctx, slab, win, false);
     }
     LevelArgs lv;
     ecc_status s = level_args(ctx, f, fi, stream, &lv);

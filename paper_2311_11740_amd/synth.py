@@ -23,10 +23,10 @@ from dataclasses import dataclass, field as dc_field
 
 import numpy as np
 
+_WORKERS = max(1, min(16, os.cpu_count() or 1))
+
 try:  # scipy's FFT can use several threads
     import scipy.fft as _fft
-
-    _WORKERS = max(1, min(16, os.cpu_count() or 1))
 
     def _rfftn(a):
         return _fft.rfftn(a, workers=_WORKERS)
@@ -79,6 +79,32 @@ def white_noise(shape, seed, q_levels=256, kind="uniform") -> np.ndarray:
     if kind == "uniform":
         return rng.integers(0, q_levels, size=shape).astype(np.uint8 if q_levels <= 256 else np.uint16)
     return quantise(rng.standard_normal(shape), q_levels)
+
+
+# The paper's own benchmark inputs (Computational Results, Tables 3 and 4):
+# white noise translated to 0..255 at these shapes, all 256 levels, 8-C in 2D
+# and 26-C in 3D.  (name, shape, noise, the paper's 24-core CPU figure in
+# Mcells/s, its table); field k is white_noise(shape, 500 + k, 256, noise).
+PAPER_WORKLOADS = [
+    ("2d_1280x720_u8_uniform", (720, 1280), "uniform", 97.7, "Table 3"),
+    ("2d_1280x720_u8_normal", (720, 1280), "normal", 99.3, "Table 3"),
+    ("2d_1920x1080_u8_uniform", (1080, 1920), "uniform", 107.4, "Table 3"),
+    ("2d_1920x1080_u8_normal", (1080, 1920), "normal", 110.8, "Table 3"),
+    ("2d_2048x2048_u8_uniform", (2048, 2048), "uniform", 96.5, "Table 3"),
+    ("2d_2048x2048_u8_normal", (2048, 2048), "normal", 110.4, "Table 3"),
+    ("2d_4096x4096_u8_uniform", (4096, 4096), "uniform", 82.2, "Table 3"),
+    ("2d_4096x4096_u8_normal", (4096, 4096), "normal", 81.95, "Table 3"),
+    ("3d_128^3_u8_uniform", (128, 128, 128), "uniform", 26.67, "Table 4"),
+    ("3d_128^3_u8_normal", (128, 128, 128), "normal", 27.47, "Table 4"),
+    ("3d_256^3_u8_uniform", (256, 256, 256), "uniform", 27.90, "Table 4"),
+    ("3d_256^3_u8_normal", (256, 256, 256), "normal", 28.38, "Table 4"),
+]
+
+
+def paper_workload(k: int) -> np.ndarray:
+    """Field k of PAPER_WORKLOADS."""
+    _, shape, kind, _, _ = PAPER_WORKLOADS[k]
+    return white_noise(shape, 500 + k, 256, kind)
 
 
 # ----------------------------------------------------------------------------
@@ -135,14 +161,25 @@ def _quantised_grf(args):
     return quantise(grf(shape, sigma, seed), q)
 
 
+def _single_threaded_fft():
+    """Worker initializer: the FFT runs in the calling thread (a forked child
+    does not inherit the parent's FFT thread pool)."""
+    global _WORKERS
+    _WORKERS = 1
+
+
 def _map(fn, args, workers: int):
-    """fn over args, in `workers` spawned processes when workers > 1 (the
-    results do not depend on the worker count: every field has its own seed)."""
+    """fn over args, in `workers` forked processes when workers > 1 (the
+    results do not depend on the worker count: every field has its own seed).
+    Forked workers leave no helper process behind (the spawn start method
+    keeps a resource tracker alive until the parent exits); callers draw their
+    inputs before the process touches the GPU."""
     if workers <= 1 or len(args) < 2:
         return [fn(a) for a in args]
     import concurrent.futures as cf
     import multiprocessing as mp
-    with cf.ProcessPoolExecutor(max_workers=workers, mp_context=mp.get_context("spawn")) as ex:
+    with cf.ProcessPoolExecutor(max_workers=workers, mp_context=mp.get_context("fork"),
+                                initializer=_single_threaded_fft) as ex:
         return list(ex.map(fn, args, chunksize=max(1, len(args) // (8 * workers))))
 
 

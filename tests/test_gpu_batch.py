@@ -180,3 +180,23 @@ def test_batch_many_threshold_arrays(ctx):
     with pytest.raises(ecc.EccError) as ei:
         ctx.compute_batch(dev2, 8, thresholds=too_many)
     assert ei.value.status == ecc.ECC_ERR_UNSUPPORTED
+
+
+def test_batch_c4_full(ctx):
+    """The whole batched workload: 4096 uint8 fields, sides log-uniform in
+    [64, 2048], 256 levels, 8-C, as the benchmark runs it: the batched call
+    equals one call per field on every field, and a sample equals the oracle."""
+    import torch
+    from paper_2311_11740_amd import synth
+    specs = synth.batch_2d_u8(workers=min(16, os.cpu_count() or 1))
+    print(f"[case] batch C4, {len(specs)} fields", flush=True)
+    dev = [torch.from_numpy(s.data).cuda() for s in specs]
+    b = ctx.batch(dev, 256, connectivity=8)
+    b.run()
+    singles = [ctx.compute(d, 256, connectivity=8) for d in dev]
+    torch.cuda.synchronize()
+    for i in range(len(specs)):
+        for k in singles[i]:
+            assert torch.equal(b.outputs[i][k], singles[i][k]), (i, k)
+    sample = list(range(0, len(specs), len(specs) // 16))
+    check_batch([b.outputs[i] for i in sample], [(specs[i].data, 256, None, 8) for i in sample], "c4_full")
