@@ -149,11 +149,12 @@ ecc_status ecc_curves_compute(ecc_context ctx, const ecc_field *field, const ecc
  *     thread of the process) shares the array and keeps the last call's
  *     contents: calls that overlap on the device race; order them (one
  *     stream, or events).  The merge ticket is cleared by each call.
- *   - Limit: partials (workgroups x channels x n_levels x 4 bytes; the
- *     workgroups are 4 per CU in 2D, 2 per CU for large 3D volumes) plus
- *     totals (channels x n_levels x 8 bytes) plus 384 KiB must fit in
- *     ECC_NOALLOC_SCRATCH_BYTES, e.g. 8192^2 with 1024 levels takes 12 MiB and
- *     512^3 with 4096 levels 32 MiB; larger requests return
+ *   - Limit: the accumulators (16 x channels x n_levels x 8 bytes; 2D fields
+ *     and large 3D volumes) or, for small 3D volumes, per-workgroup partials
+ *     (workgroups x 4 x n_levels x 4 bytes), plus totals (channels x n_levels
+ *     x 8 bytes) plus 384 KiB must fit in ECC_NOALLOC_SCRATCH_BYTES: every 2D
+ *     field and every large volume fits (65535 levels take 34 MiB), a small
+ *     volume with tens of thousands of levels may not; those requests return
  *     ECC_ERR_UNSUPPORTED before any work is queued.
  *   - Kernel timing (ecc_profile_enable) does not record these launches.
  */

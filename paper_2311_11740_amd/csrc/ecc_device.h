@@ -486,6 +486,17 @@ __device__ __forceinline__ int64_t sum_bin_wave(const int32_t *__restrict__ src,
     return s;
 }
 
+// Accumulators of the atomic drain (kAccCopies, ecc_internal.h): a workgroup
+// adds into the copy of the XCD it runs on (its hardware XCC id), so that at
+// most the workgroups of one XCD contend for an address.
+__device__ __forceinline__ unsigned xcc_copy() {
+    return __builtin_amdgcn_s_getreg(20 | (0 << 6) | ((4 - 1) << 11)) & (kAccCopies - 1);
+}
+__device__ __forceinline__ void acc_add(int64_t *p, int64_t v) {
+    if (v) __hip_atomic_fetch_add((unsigned long long *)p, (unsigned long long)v, __ATOMIC_RELAXED,
+                                  __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // Running sums over levels of the per-level totals [nch][L] into the caller's
 // curves (channels with a NULL output skipped), by one whole workgroup of at
 // most 16 waves: each thread sums a chunk of levels, the chunk sums are

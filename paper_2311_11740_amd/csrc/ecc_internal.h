@@ -109,6 +109,8 @@ struct Launch2D {
     // timing (hipEvent_t or NULL): the first launch's start and the last
     // launch's end are recorded by the dispatches themselves
     void *ev_start = nullptr, *ev_stop = nullptr;
+    // atomic drain (curves only): int64 accumulators [kAccCopies][3][L] instead of partials
+    int64_t *acc = nullptr;
 };
 
 size_t lds_bytes_2d(int window, bool classes);
@@ -148,6 +150,8 @@ struct Launch3D {
     const uint32_t *crease_table;
     // timing, as in Launch2D
     void *ev_start = nullptr, *ev_stop = nullptr;
+    // atomic drain (z-marching kernel): int64 accumulators [kAccCopies][4][L]
+    int64_t *acc = nullptr;
 };
 
 // ---- batched 2D launch ----------------------------------------------------------
@@ -185,6 +189,18 @@ int launch_3d(const Launch3D &a, void *stream);
 int launch_merge(const int32_t *partial, int grid, int nch, int L, int64_t *const out[4],
                  int64_t *totals, unsigned *counter, void *stream);
 int launch_level_lut(const float *thr, int L, int n_values, uint16_t *lut, void *stream);
+// zero `bytes` (a multiple of 16) of device memory at p with a fill kernel
+int launch_zero(void *p, size_t bytes, void *stream);
+// copies of the atomic drain's accumulators, [kAccCopies][nch][L] int64
+constexpr int kAccCopies = 16;
+// accumulators [copies][nch][L] -> totals -> running sums into the curves;
+// leaves the accumulators at zero
+int launch_merge_acc(int64_t *acc, int copies, int nch, int L, int64_t *const out[4], int64_t *totals,
+                     unsigned *counter, void *stream);
+// whether the curve kernels (2D stream, 3D z-marching) drain their bins with
+// atomics into per-XCD accumulators (default) instead of writing per-workgroup
+// partials for a merge kernel to sum (environment ECC_DRAIN=partials)
+bool atomic_drain();
 
 // tile geometry used by the single-field kernels
 constexpr int kWavesPerWG = 4;

@@ -39,6 +39,24 @@ __device__ __forceinline__ void drain_3d(uint64_t *hist, uint32_t *hc, bool crea
     }
 }
 
+// the same bins added into the XCD's accumulator copy [4][L] (atomic drain)
+__device__ __forceinline__ void drain_3d_acc(const uint64_t *hist, const uint32_t *hc, bool crease, int W, int lo,
+                                             int L, int64_t *__restrict__ acc) {
+    int64_t *a = acc + (int64_t)xcc_copy() * 4 * L;
+    for (int b = threadIdx.x; b < W; b += blockDim.x) {
+        const uint64_t v = hist[b];
+        const int64_t n = (int64_t)(v >> kShiftCnt3);
+        if (n == 0) continue;
+        const int64_t surf = (int64_t)((v >> kShiftSurf3) & ((1ull << (kShiftCnt3 - kShiftSurf3)) - 1)) -
+                             kSurfBias3 * n;
+        const int64_t ec = (int64_t)(v & ((1ull << kShiftSurf3) - 1)) - kEcBias3 * n;
+        acc_add(a + lo + b, ec);
+        if (crease) acc_add(a + L + lo + b, (int64_t)hc[b] - kCreaseBias3 * n);
+        acc_add(a + 2 * L + lo + b, surf);
+        acc_add(a + 3 * L + lo + b, n);
+    }
+}
+
 // ---------------------------------------------------------------------------
 // 3D: slab decomposition, z-marching waves
 // ---------------------------------------------------------------------------
@@ -486,7 +504,7 @@ __global__ void __launch_bounds__(256)
     ecc3d_stream(const T *__restrict__ data, int64_t d, int64_t h, int64_t w, LevelArgs lv, int32_t lo,
                  int32_t hi, float cpass, const uint32_t *__restrict__ tables,
                  const uint32_t *__restrict__ crease_table, int32_t *__restrict__ partial, int64_t z_lo,
-                 int64_t z_hi, int accumulate, int prio) {
+                 int64_t z_hi, int accumulate, int prio, int64_t *acc) {
     constexpr int VEC = Elem3<T>::VEC;
     extern __shared__ uint64_t smem[];
     __shared__ uint32_t tl[256];
@@ -544,7 +562,10 @@ __global__ void __launch_bounds__(256)
         u += zb - za;
     }
     __syncthreads();
-    drain_3d(hist + kBinOff, CR ? hc + kBinOff : nullptr, CR, W, lo, L, G, wg, partial, accumulate == 0);
+    if (acc)
+        drain_3d_acc(hist + kBinOff, CR ? hc + kBinOff : nullptr, CR, W, lo, L, acc);
+    else
+        drain_3d(hist + kBinOff, CR ? hc + kBinOff : nullptr, CR, W, lo, L, G, wg, partial, accumulate == 0);
 }
 
 
@@ -760,7 +781,7 @@ static int launch_zm_t(const Launch3D &a, hipStream_t s) {
                               z0 == a.z_lo ? (hipEvent_t)a.ev_start : nullptr,
                               z1 == a.z_hi ? (hipEvent_t)a.ev_stop : nullptr, 0, (const T *)a.data, a.d, a.h, a.w,
                               a.lv, a.lo, a.hi, cpass, a.zm_tables, a.crease_table, a.partial, z0, z1, acc ? 1 : 0,
-                              progress_prio() ? 1 : 0);
+                              progress_prio() ? 1 : 0, a.acc);
         const int e = (int)hipGetLastError();
         if (e) return e;
     }

@@ -36,6 +36,38 @@ __global__ void __launch_bounds__(1024)
     if (threadIdx.x == 0) *counter = 0u;  // ready for the next merge
 }
 
+// Sums the accumulator copies of every bin into totals (and clears them),
+// one thread per bin; the last block to finish scans the totals into the
+// curves.
+__global__ void __launch_bounds__(1024)
+    ecc_merge_acc(int64_t *__restrict__ acc, int copies, int nch, int L, OutPtrs out, int64_t *__restrict__ totals,
+                  unsigned *__restrict__ counter) {
+    __shared__ bool last;
+    const int64_t n_bins = (int64_t)nch * L;
+    for (int64_t bin = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; bin < n_bins;
+         bin += (int64_t)gridDim.x * blockDim.x) {
+        int64_t s = 0;
+        for (int c = 0; c < copies; ++c) {
+            s += acc[c * n_bins + bin];
+            acc[c * n_bins + bin] = 0;
+        }
+        totals[bin] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0)
+        last = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT) == gridDim.x - 1;
+    __syncthreads();
+    if (!last) return;
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    scan_totals_block(totals, nch, L, out);
+    if (threadIdx.x == 0) *counter = 0u;
+}
+
+__global__ void ecc_zero(u32x4 *__restrict__ p, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = u32x4{0u, 0u, 0u, 0u};
+}
+
 // level index of every integer value from the thresholds (integer fields with
 // a threshold array)
 __global__ void ecc_level_lut(const float *__restrict__ thr, int L, int n_values,
@@ -70,6 +102,24 @@ int launch_merge(const int32_t *partial, int grid, int nch, int L, int64_t *cons
     const int blocks = (int)std::min<int64_t>(max_blocks, (bins + 15) / 16);
     hipLaunchKernelGGL(ecc_merge, dim3(blocks), dim3(1024), 0, (hipStream_t)stream, partial, grid, nch, L,
                        o, totals, counter);
+    return (int)hipGetLastError();
+}
+
+int launch_merge_acc(int64_t *acc, int copies, int nch, int L, int64_t *const out[4], int64_t *totals,
+                     unsigned *counter, void *stream) {
+    OutPtrs o;
+    for (int c = 0; c < 4; ++c) o.p[c] = c < nch ? out[c] : nullptr;
+    const int64_t bins = (int64_t)nch * L;
+    const int blocks = (int)std::min<int64_t>(64, (bins + 1023) / 1024);
+    hipLaunchKernelGGL(ecc_merge_acc, dim3(blocks), dim3(1024), 0, (hipStream_t)stream, acc, copies, nch, L, o,
+                       totals, counter);
+    return (int)hipGetLastError();
+}
+
+int launch_zero(void *p, size_t bytes, void *stream) {
+    const int64_t n = (int64_t)(bytes / 16);
+    const int blocks = (int)std::min<int64_t>(1024, std::max<int64_t>(1, (n + 255) / 256));
+    hipLaunchKernelGGL(ecc_zero, dim3(blocks), dim3(256), 0, (hipStream_t)stream, (u32x4 *)p, n);
     return (int)hipGetLastError();
 }
 

@@ -5,7 +5,8 @@
 //   [0, 256)                  merge ticket (kept at zero by the merge kernel)
 //   [kOffThr, +256 KiB)       the thresholds, staged from the context's pinned buffer
 //   [kOffLut, +128 KiB)       value -> level table of integer fields with thresholds
-//   [kOffTotals, ...)         per-level totals, then the per-workgroup partials
+//   [kOffTotals, ...)         per-level totals, then the atomic drain's accumulators
+//                             (or, for the 3D tile kernel, per-workgroup partials)
 // Host code never uses the array's name as a device address: set-up reads the
 // symbol's address on each device once and every launch takes that pointer.
 #include <hip/hip_runtime.h>
@@ -68,19 +69,23 @@ extern "C" ecc_status ecc_curves_compute_noalloc(ecc_context ctx, const ecc_fiel
     if (e) return hip_fail(e, "hipSetDevice");
     if (!ctx->scratch) return fail(ECC_ERR_DEVICE, "the context has no scratch array");
     const OnePlan p = plan_one(ctx, fi, curves);
+    const bool use_acc = atomic_drain() && (fi.ndim == 2 || p.zmarch);
+    const size_t acc_bytes = (size_t)kAccCopies * p.nch * fi.L * sizeof(int64_t);
     const size_t tot_off = kOffTotals;
     const size_t part_off = (tot_off + p.totals_bytes + 255) & ~size_t(255);
-    if (part_off + p.partial_bytes > kScratchBytes)
+    const size_t need = part_off + (use_acc ? acc_bytes : p.partial_bytes);
+    if (need > kScratchBytes)
         return fail(ECC_ERR_UNSUPPORTED,
-                    "ecc_curves_compute_noalloc: this field needs " + std::to_string(part_off + p.partial_bytes) +
+                    "ecc_curves_compute_noalloc: this field needs " + std::to_string(need) +
                         " bytes of scratch; the allocation-free entry point has " + std::to_string(kScratchBytes));
     unsigned char *base = ctx->scratch;
     hipStream_t st = (hipStream_t)stream;
     s = acquire_workspace(ctx, stream);  // orders this call after the context's other calls (tiny-field buffer)
     if (s != ECC_OK) return s;
-    // every word that must start at zero: the merge ticket
+    // everything that must start at zero: the merge ticket and the accumulators
     hipLaunchKernelGGL(ecc_zero_words, dim3(1), dim3(64), 0, st, (unsigned *)base, 64);
     e = (int)hipGetLastError();
+    if (!e && use_acc) e = launch_zero(base + part_off, acc_bytes, stream);
     if (e) return hip_fail(e, "scratch clear");
     LevelArgs lv;
     lv.L = fi.L;
@@ -115,7 +120,7 @@ extern "C" ecc_status ecc_curves_compute_noalloc(ecc_context ctx, const ecc_fiel
         }
     }
     s = compute_core(ctx, field, fi, curves, lv, p, (int32_t *)(base + part_off), (int64_t *)(base + tot_off),
-                     (unsigned *)base, stream, false);
+                     (unsigned *)base, stream, false, use_acc ? (int64_t *)(base + part_off) : nullptr);
     ecc_status s2 = release_workspace(ctx, stream);
     return s != ECC_OK ? s : s2;
 }

@@ -51,14 +51,16 @@ struct ThrEntry {
 };
 
 struct Workspace {
-    DevBuf partial, totals;
+    DevBuf partial, totals, acc;
     void release() {
         partial.release();
         totals.release();
+        acc.release();
     }
 };
 
-struct BatchState;  // ecc_batch.hip
+struct BatchState;   // ecc_batch.hip
+struct StreamState;  // ecc_streamed.hip
 
 }  // namespace ecc
 
@@ -81,6 +83,10 @@ struct ecc_context_s {
     void *ws_stream = nullptr;
     bool ws_used = false;
     ecc::BatchState *batch = nullptr;
+    ecc::StreamState *streamed = nullptr;  // ecc_streamed.hip
+    // the atomic drain's accumulators (ws.acc) hold sums of a call whose merge
+    // was never queued (an error path): they are cleared before the next use
+    bool acc_dirty = false;
     void *d_counter = nullptr;  // merge kernel's completion ticket (kept at zero)
     void *d_tiny = nullptr;     // 256 B: padded copy of fields smaller than one vector load
     // allocation-free entry point: this device's scratch array, and a pinned
@@ -121,7 +127,7 @@ struct OnePlan {
 OnePlan plan_one(ecc_context ctx, const FieldInfo &fi, const ecc_curves *c);
 ecc_status compute_core(ecc_context ctx, const ecc_field *f, const FieldInfo &fi, const ecc_curves *c,
                         const LevelArgs &lv, const OnePlan &p, int32_t *partial, int64_t *totals,
-                        unsigned *counter, void *stream, bool timing);
+                        unsigned *counter, void *stream, bool timing, int64_t *acc = nullptr);
 // address of the allocation-free entry point's scratch array on `device`
 // (looked up once per device; the device must be current)
 ecc_status noalloc_scratch(int device, unsigned char **out);
@@ -135,6 +141,10 @@ int grid_2d(ecc_context ctx, const FieldInfo &fi, int window, bool classes);
 int zm_wg_per_cu();
 ecc_status merge_and_scan(ecc_context ctx, int grid, int nch, int L, int64_t *const outs[4], void *stream);
 void destroy_batch_state(ecc_context ctx);
+void destroy_stream_state(ecc_context ctx);
+// the atomic drain's accumulators for nch channels of L levels (zero), grown
+// and cleared as needed (may synchronise the device when it grows)
+ecc_status acc_buffer(ecc_context ctx, int nch, int L, int64_t **acc, void *stream);
 // batched 2D scheduling (ecc_batch.hip), shared with the serving loop
 struct SchedField {
     int32_t slot;  // descriptor index the items refer to

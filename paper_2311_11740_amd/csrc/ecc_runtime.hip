@@ -263,6 +263,7 @@ extern "C" ecc_status ecc_destroy(ecc_context ctx) {
     if (ctx->stage_event) hipEventDestroy(ctx->stage_event);
     if (ctx->ws_event) hipEventDestroy(ctx->ws_event);
     destroy_batch_state(ctx);
+    destroy_stream_state(ctx);
     delete ctx;
     return ECC_OK;
 }
@@ -568,6 +569,14 @@ int wg_per_cu_default() {
     return v;
 }
 
+bool atomic_drain() {
+    static bool v = [] {
+        const char *e = std::getenv("ECC_DRAIN");
+        return !(e && std::strcmp(e, "partials") == 0);
+    }();
+    return v;
+}
+
 bool progress_prio() {
     static bool v = [] {
         const char *e = std::getenv("ECC_PRIO");
@@ -593,6 +602,24 @@ ecc_status merge_and_scan(ecc_context ctx, int grid, int nch, int L, int64_t *co
     int e = launch_merge((const int32_t *)ctx->ws.partial.ptr, grid, nch, L, outs,
                          (int64_t *)ctx->ws.totals.ptr, (unsigned *)ctx->d_counter, stream);
     if (e) return hip_fail(e, "merge kernel launch");
+    return ECC_OK;
+}
+
+ecc_status acc_buffer(ecc_context ctx, int nch, int L, int64_t **acc, void *stream) {
+    const size_t bytes = (size_t)kAccCopies * nch * L * sizeof(int64_t);
+    if (ctx->ws.acc.bytes < bytes) {
+        ecc_status s = grow(ctx, ctx->ws.acc, bytes, "accumulators");
+        if (s != ECC_OK) return s;
+        const int e = (int)hipMemset(ctx->ws.acc.ptr, 0, ctx->ws.acc.bytes);  // the merges keep them at zero
+        if (e) return hip_fail(e, "hipMemset(accumulators)");
+        ctx->acc_dirty = false;
+    }
+    if (ctx->acc_dirty) {
+        const int e = launch_zero(ctx->ws.acc.ptr, ctx->ws.acc.bytes, stream);
+        if (e) return hip_fail(e, "clearing the accumulators");
+        ctx->acc_dirty = false;
+    }
+    *acc = (int64_t *)ctx->ws.acc.ptr;
     return ECC_OK;
 }
 
@@ -655,7 +682,7 @@ OnePlan plan_one(ecc_context ctx, const FieldInfo &fi, const ecc_curves *c) {
 // zero word that the merge leaves at zero).  Allocates nothing.
 ecc_status compute_core(ecc_context ctx, const ecc_field *f, const FieldInfo &fi, const ecc_curves *c,
                         const LevelArgs &lv, const OnePlan &p, int32_t *partial, int64_t *totals,
-                        unsigned *counter, void *stream, bool timing) {
+                        unsigned *counter, void *stream, bool timing, int64_t *acc) {
     const int L = fi.L;
     int64_t *outs[4] = {c->ec, c->perimeter, c->area, fi.ndim == 3 ? c->volume : nullptr};
     // the kernels load whole blocks of 16 bytes (2D) or 4 elements (3D), clamped
@@ -680,6 +707,7 @@ ecc_status compute_core(ecc_context ctx, const ecc_field *f, const FieldInfo &fi
                        0, fi.h, false, false};
             a.ev_start = ev0;
             a.ev_stop = ev1;
+            a.acc = acc;
             int e = launch_2d(a, stream);
             if (e) return hip_fail(e, "2D kernel launch");
         } else {
@@ -688,11 +716,13 @@ ecc_status compute_core(ecc_context ctx, const ecc_field *f, const FieldInfo &fi
                        false, p.zmarch && p.crease ? ctx->d_crease3 : nullptr};
             a.ev_start = ev0;
             a.ev_stop = ev1;
+            a.acc = acc;
             int e = launch_3d(a, stream);
             if (e) return hip_fail(e, "3D kernel launch");
         }
     }
-    int e = launch_merge(partial, p.grid, p.nch, L, outs, totals, counter, stream);
+    int e = acc ? launch_merge_acc(acc, kAccCopies, p.nch, L, outs, totals, counter, stream)
+                : launch_merge(partial, p.grid, p.nch, L, outs, totals, counter, stream);
     if (e) return hip_fail(e, "merge kernel launch");
     return ECC_OK;
 }
@@ -707,8 +737,15 @@ ecc_status compute_one(ecc_context ctx, const ecc_field *f, const FieldInfo &fi,
     if (s != ECC_OK) return s;
     s = grow(ctx, ctx->ws.totals, p.totals_bytes, "totals");
     if (s != ECC_OK) return s;
+    int64_t *acc = nullptr;
+    if (atomic_drain() && (fi.ndim == 2 || p.zmarch)) {
+        s = acc_buffer(ctx, p.nch, fi.L, &acc, stream);
+        if (s != ECC_OK) return s;
+        ctx->acc_dirty = true;
+    }
     s = compute_core(ctx, f, fi, c, lv, p, (int32_t *)ctx->ws.partial.ptr, (int64_t *)ctx->ws.totals.ptr,
-                     (unsigned *)ctx->d_counter, stream, true);
+                     (unsigned *)ctx->d_counter, stream, true, acc);
+    if (acc && s == ECC_OK) ctx->acc_dirty = false;  // the merge that clears them is queued
     if (s != ECC_OK) return s;
     return note_threshold_use(ctx, lv, stream);
 }

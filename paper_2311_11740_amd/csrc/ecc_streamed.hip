@@ -6,42 +6,89 @@
 // (2D) or planes (3D).  Each slab is copied with one halo row or plane on each
 // side into one of two device buffers on a copy stream, while the slab before
 // it is histogrammed on the caller's stream; every slab adds to the same
-// per-workgroup partials, so the merge and scan run once at the end.  A cell
-// is counted by the slab that owns it, and its neighbours come from the halo,
-// so the curves are those of the whole field.
+// accumulators (or per-workgroup partials), so the merge and scan run once at
+// the end.  A cell is counted by the slab that owns it, and its neighbours
+// come from the halo, so the curves are those of the whole field.
+//
+// Pinned host memory is copied to the device directly.  Pageable memory is
+// first copied by host threads into one of two pinned bounce buffers (while
+// the previous bounce buffer's DMA and the slab before run), which is what
+// lets the copy engine run at the pinned rate.  The buffers, the copy stream,
+// the events and the copy threads live in the context and are reused by the
+// next call.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <cstring>
 
+#include "ecc_copier.h"
 #include "ecc_internal.h"
 #include "ecc_runtime.h"
 
 namespace ecc {
 
+struct StreamState {
+    DevBuf buf[2];  // device slab buffers
+    DevBuf curves;  // device curves of the call
+    char *bounce[2] = {nullptr, nullptr};  // pinned bounce buffers for pageable fields
+    size_t bounce_bytes = 0;
+    hipStream_t copy = nullptr;
+    // copied: a slab landed in buf[b]; computed: the kernels that read buf[b]
+    // are done; drained: the DMA out of bounce[b] is done
+    hipEvent_t copied[2] = {nullptr, nullptr}, computed[2] = {nullptr, nullptr}, drained[2] = {nullptr, nullptr};
+    Copier copier;
+};
+
+void destroy_stream_state(ecc_context ctx) {
+    StreamState *st = ctx->streamed;
+    if (!st) return;
+    if (st->copy) {
+        hipStreamSynchronize(st->copy);
+        hipStreamDestroy(st->copy);
+    }
+    for (int k = 0; k < 2; ++k) {
+        if (st->copied[k]) hipEventDestroy(st->copied[k]);
+        if (st->computed[k]) hipEventDestroy(st->computed[k]);
+        if (st->drained[k]) hipEventDestroy(st->drained[k]);
+        if (st->bounce[k]) hipHostFree(st->bounce[k]);
+        st->buf[k].release();
+    }
+    st->curves.release();
+    delete st;
+    ctx->streamed = nullptr;
+}
+
 namespace {
 
-// Buffers, copy stream and events of one call; released when the call returns
-// (after the work queued on both streams has finished, also on an error path).
-struct StreamRes {
-    DevBuf buf[2];
-    DevBuf curves;
-    hipStream_t caller = nullptr;
-    hipStream_t copy = nullptr;
-    hipEvent_t copied[2] = {nullptr, nullptr}, computed[2] = {nullptr, nullptr};
-    ~StreamRes() {
-        if (copy) hipStreamSynchronize(copy);
-        hipStreamSynchronize(caller);
-        for (int k = 0; k < 2; ++k) {
-            if (copied[k]) hipEventDestroy(copied[k]);
-            if (computed[k]) hipEventDestroy(computed[k]);
+ecc_status stream_state(ecc_context ctx, StreamState **out) {
+    if (!ctx->streamed) {
+        auto *st = new StreamState();
+        int e = (int)hipStreamCreateWithFlags(&st->copy, hipStreamNonBlocking);
+        for (int b = 0; b < 2 && !e; ++b) {
+            e = (int)hipEventCreateWithFlags(&st->copied[b], hipEventDisableTiming);
+            if (!e) e = (int)hipEventCreateWithFlags(&st->computed[b], hipEventDisableTiming);
+            if (!e) e = (int)hipEventCreateWithFlags(&st->drained[b], hipEventDisableTiming);
         }
-        if (copy) hipStreamDestroy(copy);
-        buf[0].release();
-        buf[1].release();
-        curves.release();
+        ctx->streamed = st;
+        if (e) {
+            destroy_stream_state(ctx);
+            return hip_fail(e, "streamed-path stream/events");
+        }
     }
-};
+    *out = ctx->streamed;
+    return ECC_OK;
+}
+
+// whether host memory at p is pinned (page-locked and known to the runtime)
+bool host_pinned(const void *p) {
+    hipPointerAttribute_t attr;
+    const hipError_t e = hipPointerGetAttributes(&attr, p);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    return attr.type == hipMemoryTypeHost;
+}
 
 ecc_status stream_field(ecc_context ctx, const ecc_field *f, const FieldInfo &fi, const ecc_curves *c,
                         size_t slab_bytes, void *stream) {
@@ -71,36 +118,54 @@ ecc_status stream_field(ecc_context ctx, const ecc_field *f, const FieldInfo &fi
         slab.h = R;
         grid = grid_2d(ctx, slab, win, false);
     }
+    StreamState *st = nullptr;
+    ecc_status s = stream_state(ctx, &st);
+    if (s != ECC_OK) return s;
     LevelArgs lv;
-    ecc_status s = level_args(ctx, f, fi, stream, &lv);
+    s = level_args(ctx, f, fi, stream, &lv);
     if (s != ECC_OK) return s;
-    s = grow(ctx, ctx->ws.partial, (size_t)grid * nch * L * sizeof(int32_t), "partials");
-    if (s != ECC_OK) return s;
-    int32_t *partial = (int32_t *)ctx->ws.partial.ptr;
-
-    StreamRes r;
-    r.caller = (hipStream_t)stream;
     // slab + halo at offset kPad, with kPad bytes after it: the kernels' vector
     // loads are clamped to the last whole vector of the field they are given
     // (here: up to the end of the buffer's units), which for a slab of fewer
     // cells than one vector starts up to 64 bytes before the slab
     constexpr size_t kPad = 256;
-    const size_t buf_bytes = (size_t)(R + 2) * (size_t)unit_bytes + 2 * kPad;
+    const size_t slab_copy = (size_t)(R + 2) * (size_t)unit_bytes;
+    const size_t buf_bytes = slab_copy + 2 * kPad;
+    const bool acc_drain = atomic_drain();
+    int32_t *partial = nullptr;
+    int64_t *acc = nullptr;
     for (int b = 0; b < 2; ++b) {
-        s = r.buf[b].ensure(buf_bytes, "slab buffer");
+        s = grow(ctx, st->buf[b], buf_bytes, "slab buffer");
         if (s != ECC_OK) return s;
     }
-    s = r.curves.ensure((size_t)nch * L * sizeof(int64_t), "curves");
+    s = grow(ctx, st->curves, (size_t)nch * L * sizeof(int64_t), "curves");
+    if (s == ECC_OK) s = grow(ctx, ctx->ws.totals, (size_t)nch * L * sizeof(int64_t), "totals");
     if (s != ECC_OK) return s;
-    int e = (int)hipStreamCreateWithFlags(&r.copy, hipStreamNonBlocking);
-    for (int b = 0; b < 2 && !e; ++b) {
-        e = (int)hipEventCreateWithFlags(&r.copied[b], hipEventDisableTiming);
-        if (!e) e = (int)hipEventCreateWithFlags(&r.computed[b], hipEventDisableTiming);
+    if (acc_drain) {
+        s = acc_buffer(ctx, nch, L, &acc, stream);
+        ctx->acc_dirty = s == ECC_OK;
+    } else {
+        s = grow(ctx, ctx->ws.partial, (size_t)grid * nch * L * sizeof(int32_t), "partials");
+        partial = (int32_t *)ctx->ws.partial.ptr;
     }
-    if (e) return hip_fail(e, "stream/event creation");
+    if (s != ECC_OK) return s;
+    const bool pinned = host_pinned(f->data);
+    if (!pinned && st->bounce_bytes < slab_copy) {
+        // rare: wait for the DMA that may still read the old bounce buffers
+        int e = (int)hipStreamSynchronize(st->copy);
+        for (int b = 0; b < 2 && !e; ++b) {
+            if (st->bounce[b]) hipHostFree(st->bounce[b]);
+            st->bounce[b] = nullptr;
+        }
+        st->bounce_bytes = 0;
+        for (int b = 0; b < 2 && !e; ++b) e = (int)hipHostMalloc(&st->bounce[b], slab_copy, 0);
+        if (e) return fail(ECC_ERR_OUT_OF_MEMORY, "hipHostMalloc(bounce buffers) failed");
+        st->bounce_bytes = slab_copy;
+    }
+    hipStream_t cs = (hipStream_t)stream;
     // the copy stream starts after the work already queued on the caller's stream
-    e = (int)hipEventRecord(r.computed[0], (hipStream_t)stream);
-    if (!e) e = (int)hipEventRecord(r.computed[1], (hipStream_t)stream);
+    int e = (int)hipEventRecord(st->computed[0], cs);
+    if (!e) e = (int)hipEventRecord(st->computed[1], cs);
     if (e) return hip_fail(e, "hipEventRecord");
 
     const char *host = (const char *)f->data;
@@ -109,13 +174,21 @@ ecc_status stream_field(ecc_context ctx, const ecc_field *f, const FieldInfo &fi
         const int64_t b = std::min(n_units, a + R);
         const int64_t u0 = a > 0 ? a - 1 : 0, u1 = std::min(n_units, b + 1);  // units in the buffer
         const int bi = slab & 1;
-        char *dev = (char *)r.buf[bi].ptr + kPad;
-        e = (int)hipStreamWaitEvent(r.copy, r.computed[bi], 0);
-        if (!e)
-            e = (int)hipMemcpyAsync(dev, host + u0 * unit_bytes, (size_t)(u1 - u0) * (size_t)unit_bytes,
-                                    hipMemcpyHostToDevice, r.copy);
-        if (!e) e = (int)hipEventRecord(r.copied[bi], r.copy);
-        if (!e) e = (int)hipStreamWaitEvent((hipStream_t)stream, r.copied[bi], 0);
+        const size_t n = (size_t)(u1 - u0) * (size_t)unit_bytes;
+        char *dev = (char *)st->buf[bi].ptr + kPad;
+        const char *src = host + u0 * unit_bytes;
+        if (!pinned) {
+            // stage the slab in a pinned bounce buffer once its previous DMA is done
+            e = (int)hipEventSynchronize(st->drained[bi]);
+            if (e) return hip_fail(e, "hipEventSynchronize");
+            st->copier.copy(st->bounce[bi], src, n);
+            src = st->bounce[bi];
+        }
+        e = (int)hipStreamWaitEvent(st->copy, st->computed[bi], 0);
+        if (!e) e = (int)hipMemcpyAsync(dev, src, n, hipMemcpyHostToDevice, st->copy);
+        if (!e) e = (int)hipEventRecord(st->copied[bi], st->copy);
+        if (!e && !pinned) e = (int)hipEventRecord(st->drained[bi], st->copy);
+        if (!e) e = (int)hipStreamWaitEvent(cs, st->copied[bi], 0);
         if (e) return hip_fail(e, "slab copy");
         // the buffer seen as the field's units [0, u1) (units below u0 are never read)
         const void *data_v = dev - u0 * unit_bytes;
@@ -124,30 +197,35 @@ ecc_status stream_field(ecc_context ctx, const ecc_field *f, const FieldInfo &fi
             if (is3) {
                 Launch3D la{data_v, fi.dtype, u1, fi.h, fi.w, lv, lo, hi, ctx->d_vtab3[k], partial, grid, false,
                             ctx->d_zm3[k], k == 1, a, b, slab > 0, false, crease ? ctx->d_crease3 : nullptr};
+                la.acc = acc;
                 e = launch_3d(la, stream);
             } else {
                 Launch2D la{data_v, fi.dtype, u1, fi.w, lv, lo, hi, ctx->d_delta2[k], partial, grid,
                             a, b, slab > 0, false};
+                la.acc = acc;
                 e = launch_2d(la, stream);
             }
             if (e) return hip_fail(e, "slab kernel launch");
         }
-        e = (int)hipEventRecord(r.computed[bi], (hipStream_t)stream);
+        e = (int)hipEventRecord(st->computed[bi], cs);
         if (e) return hip_fail(e, "hipEventRecord");
     }
-    int64_t *dc = (int64_t *)r.curves.ptr;
+    int64_t *dc = (int64_t *)st->curves.ptr;
     int64_t *host_out[4] = {c->ec, c->perimeter, c->area, is3 ? c->volume : nullptr};
     int64_t *outs[4];
     for (int ch = 0; ch < 4; ++ch) outs[ch] = host_out[ch] ? dc + (size_t)ch * L : nullptr;
-    s = merge_and_scan(ctx, grid, nch, L, outs, stream);
-    if (s != ECC_OK) return s;
+    e = acc ? launch_merge_acc(acc, kAccCopies, nch, L, outs, (int64_t *)ctx->ws.totals.ptr,
+                               (unsigned *)ctx->d_counter, stream)
+            : launch_merge(partial, grid, nch, L, outs, (int64_t *)ctx->ws.totals.ptr, (unsigned *)ctx->d_counter,
+                           stream);
+    if (e) return hip_fail(e, "merge kernel launch");
+    if (acc) ctx->acc_dirty = false;
     for (int ch = 0; ch < 4; ++ch) {
         if (!host_out[ch]) continue;
-        e = (int)hipMemcpyAsync(host_out[ch], outs[ch], (size_t)L * sizeof(int64_t), hipMemcpyDeviceToHost,
-                                (hipStream_t)stream);
+        e = (int)hipMemcpyAsync(host_out[ch], outs[ch], (size_t)L * sizeof(int64_t), hipMemcpyDeviceToHost, cs);
         if (e) return hip_fail(e, "curve copy");
     }
-    e = (int)hipStreamSynchronize((hipStream_t)stream);
+    e = (int)hipStreamSynchronize(cs);
     if (e) return hip_fail(e, "hipStreamSynchronize");
     return ECC_OK;
 }

@@ -2,8 +2,8 @@
 the C ABI, against ecc_curves_compute: bit-exact on every case, on two calls
 in a row whose second input is smaller than the first (the shared scratch
 array keeps the first call's contents), for each dtype and level mode and in
-2D and 3D; a request whose partials do not fit the scratch array is refused
-before any work is queued.
+2D and 3D, up to the largest level count; a request whose buffers do not fit
+the scratch array is refused before any work is queued.
 """
 from __future__ import annotations
 
@@ -70,12 +70,16 @@ def test_noalloc_3d_then_smaller(ctx):
     check_pair(ctx, cases, "3d")
 
 
-def test_noalloc_too_large_is_refused(ctx):
+def test_noalloc_most_levels_then_too_large(ctx):
+    """65535 levels (the most a field may have) fit for a 2D field; a small
+    volume on the tile kernel, whose per-workgroup partials take workgroups x
+    4 x 65535 x 4 bytes, does not, and is refused."""
     import torch
     from paper_2311_11740_amd import ecc
-    # 2D, 65535 levels: 1024 workgroups x 3 channels x 65535 x 4 bytes of partials
-    a = torch.zeros((4096, 4096), dtype=torch.uint16, device="cuda")
-    out = {k: torch.full((65535,), -7, dtype=torch.int64, device="cuda") for k in ("ec", "perimeter", "area")}
+    rng = np.random.default_rng(34)
+    check_pair(ctx, [(rng.integers(0, 65535, size=(700, 900)).astype(np.uint16), 65535, None, 8)], "2d_65535")
+    a = torch.zeros((64, 64, 64), dtype=torch.uint16, device="cuda")
+    out = {k: torch.full((65535,), -7, dtype=torch.int64, device="cuda") for k in ("ec", "area", "volume")}
     with pytest.raises(ecc.EccError) as ei:
         ctx.compute(a, 65535, out=out, noalloc=True)
     assert ei.value.status == ecc.ECC_ERR_UNSUPPORTED
