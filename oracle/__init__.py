@@ -44,7 +44,7 @@ def build_o2(force: bool = True) -> str:
     if force or not os.path.exists(_LIB):
         tmp = _LIB + ".tmp"
         subprocess.check_call(["gcc", "-O2", "-fopenmp", "-shared", "-fPIC", "-std=c11",
-                               "-Wall", "-o", tmp, _SRC, "-lm"])
+                               "-Wall", "-I", _HERE, "-o", tmp, _SRC, "-lm"])
         os.replace(tmp, _LIB)
         _lib = None
     return _LIB
@@ -59,19 +59,23 @@ def _load():
         f = lib.ecc_oracle_o2
         f.restype = ctypes.c_int
         f.argtypes = [ctypes.c_int, ctypes.POINTER(ctypes.c_int64), ctypes.c_int, ctypes.c_void_p,
-                      ctypes.c_int32, ctypes.c_void_p, ctypes.c_int32,
+                      ctypes.c_int32, ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
                       ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                       ctypes.c_int]
+        g = lib.ecc_oracle_compute
+        g.restype = ctypes.c_int
+        g.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32]
         _lib = lib
     return _lib
 
 
 def o2_curves(field, n_levels: int, thresholds=None, connectivity=None,
-              channels=("ec", "perimeter", "area", "volume"), n_threads: int = 1):
+              channels=("ec", "perimeter", "area", "volume"), n_threads: int = 1, superlevel: bool = False):
     """All-levels oracle.  Returns dict channel -> int64 curve of length n_levels.
 
     2D channels: ec, perimeter, area.  3D: ec, perimeter (crease), area
-    (surface), volume.
+    (surface), volume.  ``superlevel``: sets {value >= t_l} over
+    non-increasing thresholds (integer levels t_l = n_levels - 1 - l).
     """
     lib = _load()
     field = np.ascontiguousarray(field)
@@ -92,7 +96,7 @@ def o2_curves(field, n_levels: int, thresholds=None, connectivity=None,
 
     rc = lib.ecc_oracle_o2(nd, shape, _DT[field.dtype], field.ctypes.data, int(n_levels),
                            thr.ctypes.data if thr is not None else None, int(connectivity),
-                           ptr("ec"), ptr("perimeter"), ptr("area"), ptr("volume"),
+                           1 if superlevel else 0, ptr("ec"), ptr("perimeter"), ptr("area"), ptr("volume"),
                            int(n_threads))
     if rc != 0:
         raise ValueError(f"ecc_oracle_o2 rejected the arguments (code {rc})")

@@ -10,7 +10,11 @@ Framework for the Euler Characteristic", Methodology section):
 
 * Sublevel filtration, Eq. (2): at level c the active top cells (pixels in 2D,
   voxels in 3D) are those with value <= c.  A cell outside the field is never
-  active (the "collar" discussed right after Table 1).
+  active (the "collar" discussed right after Table 1).  The superlevel
+  filtration is the mirror of Eq. (2): value >= c, over falling c (the
+  paper writes its sublevel sets with a minus mark, g^-_c, the superlevel sets
+  being their counterpart); with integer levels the level index l stands for
+  c = L - 1 - l.
 * Including a face includes its edges and vertices (text after Eq. (2)), so the
   complex at a level is the union of the *closed* active cells
   (T-construction).  Its Euler characteristic is the alternating count of
@@ -55,14 +59,26 @@ __all__ = [
 # --------------------------------------------------------------------------
 # filtration
 # --------------------------------------------------------------------------
-def binarise(field: np.ndarray, level: int, thresholds=None) -> np.ndarray:
+def binarise(field: np.ndarray, level: int, thresholds=None, superlevel: bool = False,
+             n_levels=None) -> np.ndarray:
     """Active cells at filtration level ``level`` (Eq. (2): value <= c).
 
     With ``thresholds`` None the levels are the integers themselves (the paper
     uses pixel values 0..M directly as levels).  Otherwise level index l means
     the float32 threshold ``thresholds[l]`` and a cell is active when
     ``float32(value) <= thresholds[l]``; NaN is never active.
+
+    ``superlevel``: a cell is active when ``float32(value) >= thresholds[l]``
+    (thresholds non-increasing); with integer levels (``thresholds`` None,
+    ``n_levels`` given) when ``value >= n_levels - 1 - level``.
     """
+    if superlevel:
+        if thresholds is None:
+            if n_levels is None:
+                raise ValueError("integer superlevel levels need n_levels")
+            return field.astype(np.int64) >= (int(n_levels) - 1 - int(level))
+        t = np.float32(np.asarray(thresholds, dtype=np.float32)[level])
+        return field.astype(np.float32) >= t
     if thresholds is None:
         return field <= level
     t = np.float32(np.asarray(thresholds, dtype=np.float32)[level])
@@ -208,7 +224,7 @@ def crease_3d(b: np.ndarray) -> int:
 # curves
 # --------------------------------------------------------------------------
 def curves_per_level(field, n_levels: int, thresholds=None, connectivity=None,
-                     levels=None, channels=("ec", "perimeter", "area", "volume")):
+                     levels=None, channels=("ec", "perimeter", "area", "volume"), superlevel: bool = False):
     """Binarise at every requested level and count (O(N) work per level).
 
     Returns a dict channel -> int64 array over ``levels`` (all n_levels by
@@ -227,7 +243,7 @@ def curves_per_level(field, n_levels: int, thresholds=None, connectivity=None,
     want = [c for c in channels if not (nd == 2 and c == "volume")]
     out = {c: np.zeros(len(levels), dtype=np.int64) for c in want}
     for k, lvl in enumerate(levels):
-        b = binarise(field, lvl, thresholds)
+        b = binarise(field, lvl, thresholds, superlevel, n_levels)
         if nd == 2:
             if "ec" in out:
                 out["ec"][k] = ec_2d(b, connectivity)

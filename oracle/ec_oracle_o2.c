@@ -11,7 +11,10 @@
  *     (sublevel filtration, Eq. (2)); with identity levels t_l = l.  Cells
  *     outside the field and cells that never satisfy the test (values above
  *     the last threshold, NaN) are never active, the role of the paper's M+1
- *     sentinel in Algorithms 1 and 4.
+ *     sentinel in Algorithms 1 and 4.  Superlevel filtration (the mirror of
+ *     Eq. (2)): the first l with value >= t_l over non-increasing t; with
+ *     integer levels t_l = L - 1 - l.  Everything after the level index is
+ *     the same for both directions.
  *   - The complex at level l is the closure of the active closed cells (text
  *     after Eq. (2)).  A lattice k-cell belongs to it exactly when one of the
  *     top cells containing it is active, i.e. from level min(level index of
@@ -34,6 +37,8 @@
  * histogram per thread, summed at the end (no reordering of the arithmetic
  * beyond integer addition, which is exact).
  */
+#include "ecc_oracle.h"
+
 #include <math.h>
 #include <stdint.h>
 #include <stdlib.h>
@@ -67,18 +72,21 @@ static double value_at(const void *data, int dtype, int64_t i) {
     }
 }
 
-/* first level l with float32(x) <= t[l]; L when none (also for NaN) */
-static int32_t level_of(const void *data, int dtype, int64_t i, int32_t L, const float *t) {
+/* first level l with float32(x) <= t[l] (superlevel: float32(x) >= t[l]);
+ * L when none (also for NaN) */
+static int32_t level_of(const void *data, int dtype, int64_t i, int32_t L, const float *t, int super) {
     if (t == NULL) {
-        /* identity levels for integer fields: t_l = l */
         double v = value_at(data, dtype, i);
+        if (super) /* integer levels t_l = L - 1 - l: first l with v >= L - 1 - l */
+            return v >= (double)(L - 1) ? 0 : (int32_t)((double)(L - 1) - v);
+        /* identity levels for integer fields: t_l = l */
         return v < (double)L ? (int32_t)v : L;
     }
     float x = (float)value_at(data, dtype, i);
     int32_t lo = 0, hi = L;
     while (lo < hi) {
         int32_t mid = lo + (hi - lo) / 2;
-        if (x <= t[mid])
+        if (super ? (x >= t[mid]) : (x <= t[mid]))
             hi = mid;
         else
             lo = mid + 1;
@@ -264,13 +272,14 @@ static void run_3d(const int32_t *lam, int64_t d, int64_t h, int64_t w, int32_t 
 /*
  * Public entry.  Host pointers only.  shape is {h, w} (2D) or {d, h, w} (3D),
  * C order, last axis contiguous.  thresholds: NULL for identity levels
- * (integer dtypes only) or n_levels non-decreasing float32 values.  Output
- * pointers of length n_levels may be NULL when not wanted; volume and crease
- * are 3D only (perimeter holds the crease in 3D, area the surface).
+ * (integer dtypes only) or n_levels non-decreasing float32 values
+ * (non-increasing with superlevel != 0).  Output pointers of length n_levels
+ * may be NULL when not wanted; volume and crease are 3D only (perimeter holds
+ * the crease in 3D, area the surface).
  * Returns 0 on success, 1 on bad arguments, 3 when memory runs out.
  */
 int ecc_oracle_o2(int ndim, const int64_t *shape, int dtype, const void *data,
-                  int32_t n_levels, const float *thresholds, int32_t connectivity,
+                  int32_t n_levels, const float *thresholds, int32_t connectivity, int32_t superlevel,
                   int64_t *ec, int64_t *perimeter, int64_t *area, int64_t *volume,
                   int n_threads) {
     if (ndim != 2 && ndim != 3) return OR_BAD;
@@ -280,9 +289,13 @@ int ecc_oracle_o2(int ndim, const int64_t *shape, int dtype, const void *data,
     if (ndim == 2 && connectivity != 8 && connectivity != 4) return OR_BAD;
     if (ndim == 3 && connectivity != 26 && connectivity != 6) return OR_BAD;
     if (ndim == 2 && volume != NULL) return OR_BAD;
+    if (superlevel != 0 && superlevel != 1) return OR_BAD;
     if (thresholds)
-        for (int32_t l = 0; l < n_levels; ++l)
-            if (isnan(thresholds[l]) || (l > 0 && thresholds[l] < thresholds[l - 1])) return OR_BAD;
+        for (int32_t l = 0; l < n_levels; ++l) {
+            if (isnan(thresholds[l])) return OR_BAD;
+            if (l > 0 && !superlevel && thresholds[l] < thresholds[l - 1]) return OR_BAD;
+            if (l > 0 && superlevel && thresholds[l] > thresholds[l - 1]) return OR_BAD;
+        }
     int64_t d = ndim == 3 ? shape[0] : 1;
     int64_t h = shape[ndim - 2], w = shape[ndim - 1];
     if (d < 1 || h < 1 || w < 1) return OR_BAD;
@@ -305,7 +318,7 @@ int ecc_oracle_o2(int ndim, const int64_t *shape, int dtype, const void *data,
             for (int64_t j = 0; j < w; ++j) {
                 int64_t src = (k * h + i) * w + j;
                 int64_t dst = ndim == 3 ? ((k + 1) * ph + (i + 1)) * pw + (j + 1) : (i + 1) * pw + (j + 1);
-                lam[dst] = level_of(data, dtype, src, L, thresholds);
+                lam[dst] = level_of(data, dtype, src, L, thresholds, superlevel);
             }
 
     int64_t *hist = (int64_t *)calloc((size_t)n_threads * (size_t)(L + 1) * NCH, sizeof(int64_t));
@@ -339,4 +352,15 @@ int ecc_oracle_o2(int ndim, const int64_t *shape, int dtype, const void *data,
     }
     free(hist);
     return OR_OK;
+}
+
+int ecc_oracle_compute(const ecc_oracle_field *field, const ecc_oracle_curves *curves, int32_t n_threads) {
+    if (field == NULL || curves == NULL) return OR_BAD;
+    if (!curves->ec && !curves->perimeter && !curves->area && !curves->volume) return OR_BAD;
+    if (field->ndim != 2 && field->ndim != 3) return OR_BAD;
+    int32_t conn = field->connectivity;
+    if (conn == 0) conn = field->ndim == 2 ? 8 : 26;
+    return ecc_oracle_o2(field->ndim, field->shape, field->dtype, field->data, field->n_levels,
+                         field->thresholds, conn, field->filtration, curves->ec, curves->perimeter,
+                         curves->area, curves->volume, n_threads);
 }

@@ -67,7 +67,7 @@ def _quadrant_masks(b: np.ndarray) -> np.ndarray:
     return p[:-1, :-1] | (p[:-1, 1:] << 1) | (p[1:, :-1] << 2) | (p[1:, 1:] << 3)
 
 
-def vertex_classes_per_level(field, n_levels: int, thresholds=None) -> np.ndarray:
+def vertex_classes_per_level(field, n_levels: int, thresholds=None, superlevel: bool = False) -> np.ndarray:
     """[5, n_levels] int64: vertices per class at each level, by binarising at
     every level and classifying every quadrant."""
     field = np.asarray(field)
@@ -75,18 +75,31 @@ def vertex_classes_per_level(field, n_levels: int, thresholds=None) -> np.ndarra
         raise ValueError("vertex classes are defined here for 2D fields")
     out = np.zeros((5, n_levels), dtype=np.int64)
     for lvl in range(n_levels):
-        cls = _CLASS_OF_MASK[_quadrant_masks(binarise(field, lvl, thresholds))]
+        cls = _CLASS_OF_MASK[_quadrant_masks(binarise(field, lvl, thresholds, superlevel, n_levels))]
         for c in range(5):
             out[c, lvl] = int(np.count_nonzero(cls == c))
     return out
 
 
-def level_index(field, n_levels: int, thresholds=None) -> np.ndarray:
+def level_index(field, n_levels: int, thresholds=None, superlevel: bool = False) -> np.ndarray:
     """Level at which each pixel becomes active (Eq. (2)); n_levels for never.
 
     Integer levels: the value itself when below n_levels.  Thresholds: the
-    first l with float32(value) <= thresholds[l] (NaN never)."""
+    first l with float32(value) <= thresholds[l] (NaN never).  Superlevel: the
+    first l with value >= t_l (non-increasing thresholds; integer levels
+    t_l = n_levels - 1 - l)."""
     field = np.asarray(field)
+    if superlevel:
+        L = int(n_levels)
+        if thresholds is None:
+            v = field.astype(np.int64)
+            return np.maximum(L - 1 - v, 0)
+        t = np.asarray(thresholds, dtype=np.float32)
+        x = field.astype(np.float32)
+        lam = np.full(x.shape, L, dtype=np.int64)
+        for lvl in range(L - 1, -1, -1):  # the first (smallest) l that holds wins
+            lam[x >= t[lvl]] = lvl
+        return lam
     if thresholds is None:
         v = field.astype(np.int64)
         return np.where(v < n_levels, v, n_levels)
@@ -97,13 +110,13 @@ def level_index(field, n_levels: int, thresholds=None) -> np.ndarray:
     return lam
 
 
-def vertex_classes_2d(field, n_levels: int, thresholds=None) -> np.ndarray:
+def vertex_classes_2d(field, n_levels: int, thresholds=None, superlevel: bool = False) -> np.ndarray:
     """[5, n_levels] int64 class counts from the per-vertex class changes."""
     field = np.asarray(field)
     if field.ndim != 2:
         raise ValueError("vertex classes are defined here for 2D fields")
     L = int(n_levels)
-    lam = np.pad(level_index(field, L, thresholds), 1, mode="constant", constant_values=L)
+    lam = np.pad(level_index(field, L, thresholds, superlevel), 1, mode="constant", constant_values=L)
     # the four pixel levels around every vertex, in mask-bit order
     q = [lam[:-1, :-1].ravel(), lam[:-1, 1:].ravel(), lam[1:, :-1].ravel(), lam[1:, 1:].ravel()]
     hist = np.zeros((5, L + 1), dtype=np.int64)
@@ -174,7 +187,7 @@ def _octant_masks(b: np.ndarray) -> np.ndarray:
     return m
 
 
-def vertex_classes_3d_per_level(field, n_levels: int, thresholds=None) -> np.ndarray:
+def vertex_classes_3d_per_level(field, n_levels: int, thresholds=None, superlevel: bool = False) -> np.ndarray:
     """[21, n_levels] int64: vertices per octant class at each level, by
     binarising at every level and classifying every octant."""
     field = np.asarray(field)
@@ -182,19 +195,19 @@ def vertex_classes_3d_per_level(field, n_levels: int, thresholds=None) -> np.nda
         raise ValueError("3D field expected")
     out = np.zeros((N_CLASSES_3D, n_levels), dtype=np.int64)
     for lvl in range(n_levels):
-        cls = _CLASS_OF_OCTANT[_octant_masks(binarise(field, lvl, thresholds))]
+        cls = _CLASS_OF_OCTANT[_octant_masks(binarise(field, lvl, thresholds, superlevel, n_levels))]
         cnt = np.bincount(cls[cls >= 0].ravel(), minlength=N_CLASSES_3D)
         out[:, lvl] = cnt
     return out
 
 
-def vertex_classes_3d(field, n_levels: int, thresholds=None) -> np.ndarray:
+def vertex_classes_3d(field, n_levels: int, thresholds=None, superlevel: bool = False) -> np.ndarray:
     """[21, n_levels] int64 class counts from the per-vertex class changes."""
     field = np.asarray(field)
     if field.ndim != 3:
         raise ValueError("3D field expected")
     L = int(n_levels)
-    lam = np.pad(level_index(field, L, thresholds), 1, mode="constant", constant_values=L)
+    lam = np.pad(level_index(field, L, thresholds, superlevel), 1, mode="constant", constant_values=L)
     D, H, W = lam.shape
     q = []
     for dz in (0, 1):
@@ -217,8 +230,8 @@ def vertex_classes_3d(field, n_levels: int, thresholds=None) -> np.ndarray:
     return np.cumsum(hist[:, :L], axis=1)
 
 
-def class_counts(field, n_levels: int, thresholds=None) -> np.ndarray:
+def class_counts(field, n_levels: int, thresholds=None, superlevel: bool = False) -> np.ndarray:
     """Class counts of a 2D ([5, L]) or 3D ([21, L]) field."""
     field = np.asarray(field)
-    return (vertex_classes_2d if field.ndim == 2 else vertex_classes_3d)(field, n_levels, thresholds)
+    return (vertex_classes_2d if field.ndim == 2 else vertex_classes_3d)(field, n_levels, thresholds, superlevel)
 
