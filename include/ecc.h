@@ -49,6 +49,12 @@ typedef enum {
 
 typedef enum { ECC_U8 = 1, ECC_U16 = 2, ECC_F32 = 3 } ecc_dtype;
 
+/* Direction of the filtration (ecc_field.filtration).
+ *   ECC_SUBLEVEL    sets {x : f(x) <= c} over rising c, Eq. (2); the default (0).
+ *   ECC_SUPERLEVEL  sets {x : f(x) >= c} over falling c: the mirror of Eq. (2),
+ *                   the sublevel filtration of -f at -c. */
+typedef enum { ECC_SUBLEVEL = 0, ECC_SUPERLEVEL = 1 } ecc_filtration;
+
 typedef struct ecc_context_s *ecc_context;
 
 /*
@@ -73,6 +79,15 @@ typedef struct ecc_context_s *ecc_context;
  *                 3D: 26 (the paper's default) or 6 (derived: the same
  *                 construction as Table 1's 4-C column one dimension up).
  *                 0 selects the default.
+ *   filtration    ECC_SUBLEVEL (0: everything above) or ECC_SUPERLEVEL.  With
+ *                 ECC_SUPERLEVEL the thresholds must be non-increasing (and
+ *                 non-NaN) and a cell is active at level l when
+ *                 float32(value) >= thresholds[l]; NULL thresholds (integer
+ *                 fields) mean t_l = L - 1 - l, so level l holds the values
+ *                 >= L - 1 - l and every value enters (values >= L - 1 at
+ *                 level 0).  NaN never enters; +inf enters at level 0.  The
+ *                 curves equal those of the sublevel filtration of -value with
+ *                 thresholds -t_l, bit for bit.  Every entry point takes it.
  */
 typedef struct {
     int32_t ndim;
@@ -82,6 +97,7 @@ typedef struct {
     int32_t n_levels;
     int32_t connectivity;
     const float *thresholds;
+    int32_t filtration;
 } ecc_field;
 
 /*

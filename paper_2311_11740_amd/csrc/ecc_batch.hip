@@ -372,6 +372,7 @@ static ecc_status run_plan(ecc_context ctx, BatchState *bs, BatchPlan *p, int n,
             d.n_items = p->n_items_of[sl];
             d.conn_idx = fi[i].conn == 8 ? 0 : 1;
             d.inv_step = lv[i].inv_step;
+            d.neg = lv[i].neg;
             d.cpass = (float)(lv[i].u0d + kBinOff + 0.5);
             d.eps = lv[i].eps;
         }

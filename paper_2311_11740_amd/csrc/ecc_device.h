@@ -58,12 +58,19 @@ struct ThrGlobal {
     __device__ float operator[](int i) const { return p[i]; }
 };
 
+// the value the thresholds are compared with: x, or -x for the superlevel
+// filtration (neg = the sign bit)
+__device__ __forceinline__ float cmp_value(float x, uint32_t neg) {
+    return __uint_as_float(__float_as_uint(x) ^ neg);
+}
+
 template <int LM, typename TH>
-__device__ __forceinline__ uint32_t level_of_float(float x, const LevelArgs &a, const TH &thr) {
+__device__ __forceinline__ uint32_t level_of_float(float xin, const LevelArgs &a, const TH &thr) {
     const int L = a.L;
-    if (!(x == x)) return (uint32_t)L;  // NaN never enters
+    if (!(xin == xin)) return (uint32_t)L;  // NaN never enters
+    const float x = cmp_value(xin, a.neg);
     if constexpr (LM == LM_AFFINE) {
-        const float u = __builtin_fmaf(x, a.inv_step, a.u0);
+        const float u = __builtin_fmaf(xin, a.inv_step, a.u0);  // inv_step carries the sign
         const float fr = __builtin_amdgcn_fractf(u);
         const float uc = __builtin_amdgcn_fmed3f(u, -2.0f, (float)L + 2.0f);
         int g = (int)__builtin_floorf(uc) + 1;

@@ -84,6 +84,10 @@ struct LevelArgs {
                           // eps from an integer, floor(u)+1 is the exact level (the host
                           // bounds the grid deviation and the rounding of u by eps/2);
                           // elsewhere the level is settled against the thresholds
+    uint32_t neg;         // 0, or the sign bit for the superlevel filtration: thr holds
+                          // -t, every threshold comparison takes -x (x ^ neg), and
+                          // inv_step already carries the sign (fma(x, -s, u0) =
+                          // fma(-x, s, u0) exactly); level tables are built for -v
 };
 
 // bin of the first level of a pass window in the 2D kernels' LDS histograms
@@ -164,7 +168,8 @@ struct BatchField2D {
     uint32_t *done;       // items of this field finished; zero between launches
     const float *thr;     // LM_AFFINE / LM_SEARCH thresholds (device)
     const uint16_t *lut;  // LM_LUT level table (device)
-    int32_t L, n_items, conn_idx, pad0;  // conn_idx 0 = 8-C, 1 = 4-C
+    int32_t L, n_items, conn_idx;        // conn_idx 0 = 8-C, 1 = 4-C
+    uint32_t neg;                        // LevelArgs::neg
     float inv_step, cpass, eps, pad1;    // LM_AFFINE (cpass of the pass over all L <= 4096 levels)
 };
 // A work item: (strip, row) units [u0, u1) of one field, strip-major.
@@ -188,7 +193,7 @@ int launch_3d(const Launch3D &a, void *stream);
 // zero-initialised device word that the kernel leaves at zero
 int launch_merge(const int32_t *partial, int grid, int nch, int L, int64_t *const out[4],
                  int64_t *totals, unsigned *counter, void *stream);
-int launch_level_lut(const float *thr, int L, int n_values, uint16_t *lut, void *stream);
+int launch_level_lut(const float *thr, int L, int n_values, uint16_t *lut, bool neg, void *stream);
 // zero `bytes` (a multiple of 16) of device memory at p with a fill kernel
 int launch_zero(void *p, size_t bytes, void *stream);
 // copies of the atomic drain's accumulators, [kAccCopies][nch][L] int64

@@ -96,14 +96,14 @@ __device__ __forceinline__ void convert_row(const RawRow &raw_in, bool row_ok, b
                 // true level is within one of the estimate)
                 if (nr[i] && k >= kBinOff - 1 && k <= W + kBinOff) {
                     const int g0 = k + lo - kBinOff < 0 ? 0 : k + lo - kBinOff;
-                    const int g = (int)level_settle(__uint_as_float(raw.w[i]), (uint32_t)g0, lv.L, thr);
+                    const int g = (int)level_settle(__uint_as_float(raw.w[i] ^ lv.neg), (uint32_t)g0, lv.L, thr);
                     lam[i] = g < lo ? lb.below : (g >= lo + W ? never : (uint32_t)(g - lo + kBinOff));
                 }
             }
         }
     } else if constexpr (LM == LM_SEARCH) {
 #pragma unroll
-        for (int i = 0; i < VEC; ++i) lam[i] = bin_search(as_value<float>(raw.w[i]), lo, lo + W, thr, lb);
+        for (int i = 0; i < VEC; ++i) lam[i] = bin_search(__uint_as_float(raw.w[i] ^ lv.neg), lo, lo + W, thr, lb);
     } else {
 #pragma unroll
         for (int i = 0; i < VEC; ++i) {
@@ -415,6 +415,7 @@ __global__ void __launch_bounds__(256)
         lv.inv_step = f.inv_step;
         lv.u0d = 0.0;
         lv.eps = f.eps;
+        lv.neg = f.neg;
         const ThrLds thr{thr_s, -2};
         const LaneBins lb{(uint32_t)lane, (uint32_t)(L + kBinOff + lane)};
         const uint32_t h0 = lds_addr(hist);

@@ -193,13 +193,13 @@ __device__ __forceinline__ uint32_t bin3(uint32_t bits, const LevelArgs &lv, con
             const int k = (int)l;
             if (k >= kBinOff - 1 && k <= W + kBinOff) {
                 const int g0 = k + lo - kBinOff < 0 ? 0 : k + lo - kBinOff;
-                const int g = (int)level_settle(x, (uint32_t)g0, lv.L, thr);
+                const int g = (int)level_settle(cmp_value(x, lv.neg), (uint32_t)g0, lv.L, thr);
                 l = g < lo ? lb.below : (g >= lo + W ? lb.never : (uint32_t)(g - lo + kBinOff));
             }
         }
         return l;
     } else if constexpr (LM == LM_SEARCH) {
-        return bin_search(__uint_as_float(bits), lo, lo + W, thr, lb);
+        return bin_search(__uint_as_float(bits ^ lv.neg), lo, lo + W, thr, lb);
     } else {
         const int l = (int)level_of<T, LM>(as_value<T>(bits), lv, thr);
         return (uint32_t)min(max(l - lo + kBinOff, (int)lb.below), (int)lb.never);

@@ -69,12 +69,12 @@ __global__ void ecc_zero(u32x4 *__restrict__ p, int64_t n) {
 }
 
 // level index of every integer value from the thresholds (integer fields with
-// a threshold array)
-__global__ void ecc_level_lut(const float *__restrict__ thr, int L, int n_values,
+// a threshold array; superlevel: the thresholds are -t and the value -v)
+__global__ void ecc_level_lut(const float *__restrict__ thr, int L, int n_values, int neg,
                               uint16_t *__restrict__ lut) {
     const int v = blockIdx.x * blockDim.x + threadIdx.x;
     if (v >= n_values) return;
-    const float x = (float)v;
+    const float x = neg ? -(float)v : (float)v;
     int lo = 0, hi = L;
     while (lo < hi) {
         const int mid = (lo + hi) >> 1;
@@ -123,9 +123,9 @@ int launch_zero(void *p, size_t bytes, void *stream) {
     return (int)hipGetLastError();
 }
 
-int launch_level_lut(const float *thr, int L, int n_values, uint16_t *lut, void *stream) {
+int launch_level_lut(const float *thr, int L, int n_values, uint16_t *lut, bool neg, void *stream) {
     hipLaunchKernelGGL(ecc_level_lut, dim3((n_values + 255) / 256), dim3(256), 0,
-                       (hipStream_t)stream, thr, L, n_values, lut);
+                       (hipStream_t)stream, thr, L, n_values, neg ? 1 : 0, lut);
     return (int)hipGetLastError();
 }
 

@@ -96,12 +96,20 @@ extern "C" ecc_status ecc_curves_compute_noalloc(ecc_context ctx, const ecc_fiel
     lv.u0d = 0.0;
     lv.inv_step = 0.f;
     lv.eps = 0.f;
-    if (field->thresholds) {
+    lv.neg = 0u;
+    if (field->thresholds || fi.super) {
         // stage through the context's pinned buffer (reused once the previous
-        // staging copy has run)
+        // staging copy has run); superlevel levels as -t (integer identity:
+        // t_l = L - 1 - l), which the kernels compare -x against
         e = (int)hipEventSynchronize(ctx->stage_event);
         if (e) return hip_fail(e, "hipEventSynchronize(staging)");
-        std::memcpy(ctx->h_stage, field->thresholds, sizeof(float) * fi.L);
+        if (!fi.super)
+            std::memcpy(ctx->h_stage, field->thresholds, sizeof(float) * fi.L);
+        else if (field->thresholds)
+            negate_thresholds(field->thresholds, fi.L, ctx->h_stage);
+        else
+            for (int l = 0; l < fi.L; ++l) ctx->h_stage[l] = (float)(l - (fi.L - 1));
+        lv.neg = fi.super ? 0x80000000u : 0u;
         float *d_thr = (float *)(base + kOffThr);
         e = (int)hipMemcpyAsync(d_thr, ctx->h_stage, sizeof(float) * fi.L, hipMemcpyHostToDevice, st);
         if (!e) e = (int)hipEventRecord(ctx->stage_event, st);
@@ -109,12 +117,13 @@ extern "C" ecc_status ecc_curves_compute_noalloc(ecc_context ctx, const ecc_fiel
         lv.thr = d_thr;
         if (fi.dtype == ECC_U8 || fi.dtype == ECC_U16) {
             uint16_t *lut = (uint16_t *)(base + kOffLut);
-            e = launch_level_lut(d_thr, fi.L, fi.dtype == ECC_U8 ? 256 : 65536, lut, stream);
+            e = launch_level_lut(d_thr, fi.L, fi.dtype == ECC_U8 ? 256 : 65536, lut, fi.super, stream);
             if (e) return hip_fail(e, "level table kernel");
             lv.mode = LM_LUT;
             lv.lut = lut;
-        } else if (affine_levels(field->thresholds, fi.L, &lv.u0, &lv.u0d, &lv.inv_step, &lv.eps)) {
+        } else if (affine_levels(ctx->h_stage, fi.L, &lv.u0, &lv.u0d, &lv.inv_step, &lv.eps)) {
             lv.mode = LM_AFFINE;
+            if (fi.super) lv.inv_step = -lv.inv_step;
         } else {
             lv.mode = LM_SEARCH;
         }

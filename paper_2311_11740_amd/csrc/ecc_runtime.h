@@ -20,6 +20,7 @@ struct FieldInfo {
     int64_t d, h, w, cells;
     int L, conn;
     int elem_bytes;
+    bool super;  // superlevel filtration
 };
 
 struct DevBuf {
@@ -36,7 +37,8 @@ struct DevBuf {
 // for that work only.
 struct ThrEntry {
     int L = 0;
-    std::vector<float> host;
+    std::vector<float> host;  // the caller's thresholds (the cache key, with `neg`)
+    bool neg = false;         // superlevel: the device holds -t, the level tables map -v
     float *h_pinned = nullptr;
     float *d_thr = nullptr;
     uint16_t *d_lut8 = nullptr;
@@ -106,6 +108,14 @@ ecc_status hip_fail(int err, const char *what);
 ecc_status validate_field(const ecc_field *f, const ecc_curves *c, FieldInfo *info, bool curves_on_host);
 void free_thresholds(ThrEntry *t);
 ecc_status level_args(ecc_context ctx, const ecc_field *f, const FieldInfo &fi, void *stream, LevelArgs *lv);
+// The thresholds that define the field's levels: the caller's array, or for an
+// integer field with NULL thresholds under the superlevel filtration the
+// implied t_l = L - 1 - l (written into `tmp`); NULL for identity sublevel
+// levels.
+const float *field_thresholds(const ecc_field *f, std::vector<float> &tmp);
+// Superlevel thresholds as the device uses them: dst[l] = -t[l] (non-decreasing),
+// so that the level of x is the sublevel level of -x.
+void negate_thresholds(const float *t, int L, float *dst);
 // Makes room in the threshold cache for the distinct (by content) arrays of
 // `fields` that are not cached yet, so that fetching them all evicts none of
 // them; fails when they are more than the cache holds.

@@ -52,14 +52,19 @@ ecc_status validate_field(const ecc_field *f, const ecc_curves *c, FieldInfo *in
         return fail(ECC_ERR_INVALID_ARG, "2D connectivity must be 8 or 4");
     if (f->ndim == 3 && conn != 26 && conn != 6)
         return fail(ECC_ERR_INVALID_ARG, "3D connectivity must be 26 or 6");
+    if (f->filtration != ECC_SUBLEVEL && f->filtration != ECC_SUPERLEVEL)
+        return fail(ECC_ERR_INVALID_ARG, "filtration must be ECC_SUBLEVEL or ECC_SUPERLEVEL");
+    const bool super = f->filtration == ECC_SUPERLEVEL;
     if (f->dtype == ECC_F32 && !f->thresholds)
         return fail(ECC_ERR_INVALID_ARG, "float32 fields need a thresholds array");
     if (f->thresholds) {
         for (int l = 0; l < f->n_levels; ++l) {
             if (std::isnan(f->thresholds[l]))
                 return fail(ECC_ERR_INVALID_ARG, "thresholds must not be NaN");
-            if (l > 0 && f->thresholds[l] < f->thresholds[l - 1])
+            if (l > 0 && !super && f->thresholds[l] < f->thresholds[l - 1])
                 return fail(ECC_ERR_INVALID_ARG, "thresholds must be non-decreasing");
+            if (l > 0 && super && f->thresholds[l] > f->thresholds[l - 1])
+                return fail(ECC_ERR_INVALID_ARG, "superlevel thresholds must be non-increasing");
         }
     }
     if (f->ndim == 2 && c->volume) return fail(ECC_ERR_INVALID_ARG, "volume must be NULL for 2D fields");
@@ -83,7 +88,20 @@ ecc_status validate_field(const ecc_field *f, const ecc_curves *c, FieldInfo *in
     info->L = f->n_levels;
     info->conn = conn;
     info->elem_bytes = f->dtype == ECC_U8 ? 1 : (f->dtype == ECC_U16 ? 2 : 4);
+    info->super = super;
     return ECC_OK;
+}
+
+const float *field_thresholds(const ecc_field *f, std::vector<float> &tmp) {
+    if (f->thresholds || f->filtration != ECC_SUPERLEVEL) return f->thresholds;
+    const int L = f->n_levels;
+    tmp.resize(L);
+    for (int l = 0; l < L; ++l) tmp[l] = (float)(L - 1 - l);
+    return tmp.data();
+}
+
+void negate_thresholds(const float *t, int L, float *dst) {
+    for (int l = 0; l < L; ++l) dst[l] = -t[l];
 }
 
 }  // namespace ecc
@@ -319,13 +337,13 @@ void free_thresholds(ThrEntry *t) {
     delete t;
 }
 
-static bool same_thresholds(const ThrEntry *t, const float *thr, int L) {
-    return t->L == L && std::memcmp(t->host.data(), thr, sizeof(float) * L) == 0;
+static bool same_thresholds(const ThrEntry *t, const float *thr, int L, bool neg) {
+    return t->L == L && t->neg == neg && std::memcmp(t->host.data(), thr, sizeof(float) * L) == 0;
 }
 
-static ThrEntry *find_thresholds(ecc_context ctx, const float *thr, int L) {
+static ThrEntry *find_thresholds(ecc_context ctx, const float *thr, int L, bool neg) {
     for (auto *t : ctx->thr_cache)
-        if (same_thresholds(t, thr, L)) return t;
+        if (same_thresholds(t, thr, L, neg)) return t;
     return nullptr;
 }
 
@@ -379,9 +397,9 @@ bool affine_levels(const float *thr, int L, float *u0, double *u0d, float *inv_s
     return true;
 }
 
-ecc_status get_thresholds(ecc_context ctx, const float *thr, int L, int dtype, void *stream,
+ecc_status get_thresholds(ecc_context ctx, const float *thr, int L, bool neg, int dtype, void *stream,
                           const ThrEntry **out) {
-    ThrEntry *hit = find_thresholds(ctx, thr, L);
+    ThrEntry *hit = find_thresholds(ctx, thr, L, neg);
     hipStream_t st = (hipStream_t)stream;
     if (!hit) {
         if (ctx->thr_cache.size() >= kThrCacheMax) {
@@ -390,6 +408,7 @@ ecc_status get_thresholds(ecc_context ctx, const float *thr, int L, int dtype, v
         }
         auto *t = new ThrEntry();
         t->L = L;
+        t->neg = neg;
         t->host.assign(thr, thr + L);
         int e = (int)hipEventCreateWithFlags(&t->ready, hipEventDisableTiming);
         if (!e) e = (int)hipEventCreateWithFlags(&t->last_use, hipEventDisableTiming);
@@ -398,7 +417,10 @@ ecc_status get_thresholds(ecc_context ctx, const float *thr, int L, int dtype, v
             free_thresholds(t);
             return hip_fail(e, "threshold cache entry");
         }
-        std::memcpy(t->h_pinned, thr, sizeof(float) * L);
+        if (neg)
+            negate_thresholds(thr, L, t->h_pinned);
+        else
+            std::memcpy(t->h_pinned, thr, sizeof(float) * L);
         e = (int)hipMalloc(&t->d_thr, sizeof(float) * L);
         if (e) {
             free_thresholds(t);
@@ -411,7 +433,7 @@ ecc_status get_thresholds(ecc_context ctx, const float *thr, int L, int dtype, v
             return hip_fail(e, "hipMemcpyAsync(thresholds)");
         }
         t->ready_stream = stream;
-        t->affine = affine_levels(thr, L, &t->u0, &t->u0d, &t->inv_step, &t->eps);
+        t->affine = affine_levels(t->h_pinned, L, &t->u0, &t->u0d, &t->inv_step, &t->eps);
         ctx->thr_cache.push_back(t);
         hit = t;
     } else if (hit->ready_stream != stream) {
@@ -430,7 +452,7 @@ ecc_status get_thresholds(ecc_context ctx, const float *thr, int L, int dtype, v
             *dst = nullptr;
             return fail(ECC_ERR_OUT_OF_MEMORY, "hipMalloc(level table) failed");
         }
-        e = launch_level_lut(hit->d_thr, L, nv, *dst, stream);
+        e = launch_level_lut(hit->d_thr, L, nv, *dst, hit->neg, stream);
         if (!e) e = (int)hipEventRecord(hit->ready, st);
         if (e) return hip_fail(e, "level table kernel");
         hit->ready_stream = stream;
@@ -439,18 +461,28 @@ ecc_status get_thresholds(ecc_context ctx, const float *thr, int L, int dtype, v
     return ECC_OK;
 }
 
+// Distinct threshold arrays among `fields` (integer superlevel fields without
+// thresholds count by their level count; such a field and one whose caller
+// array has the same content count twice, which only overestimates).
 static int count_distinct(int n, const ecc_field *const *fields, ecc_context ctx, bool uncached_only) {
     int k = 0;
+    std::vector<float> tmp;
     for (int i = 0; i < n; ++i) {
         const ecc_field *f = fields[i];
-        if (!f->thresholds) continue;
+        const bool neg = f->filtration == ECC_SUPERLEVEL;
+        if (!f->thresholds && !neg) continue;
         bool seen = false;
-        for (int j = 0; j < i && !seen; ++j)
-            seen = fields[j]->thresholds && fields[j]->n_levels == f->n_levels &&
-                   (fields[j]->thresholds == f->thresholds ||
-                    std::memcmp(fields[j]->thresholds, f->thresholds, sizeof(float) * f->n_levels) == 0);
+        for (int j = 0; j < i && !seen; ++j) {
+            const ecc_field *g = fields[j];
+            if (g->n_levels != f->n_levels || (g->filtration == ECC_SUPERLEVEL) != neg) continue;
+            if (!f->thresholds || !g->thresholds)
+                seen = !f->thresholds && !g->thresholds;
+            else
+                seen = g->thresholds == f->thresholds ||
+                       std::memcmp(g->thresholds, f->thresholds, sizeof(float) * f->n_levels) == 0;
+        }
         if (seen) continue;
-        if (uncached_only && ctx && find_thresholds(ctx, f->thresholds, f->n_levels)) continue;
+        if (uncached_only && ctx && find_thresholds(ctx, field_thresholds(f, tmp), f->n_levels, neg)) continue;
         ++k;
     }
     return k;
@@ -465,9 +497,12 @@ ecc_status reserve_thresholds(ecc_context ctx, int n, const ecc_field *const *fi
         return fail(ECC_ERR_UNSUPPORTED, "one call may use at most 256 distinct threshold arrays");
     const int n_new = count_distinct(n, fields, ctx, true);
     std::vector<const ThrEntry *> keep;  // the arrays of this call that are cached already
+    std::vector<float> tmp;
     for (int i = 0; i < n; ++i)
-        if (fields[i]->thresholds)
-            if (const ThrEntry *t = find_thresholds(ctx, fields[i]->thresholds, fields[i]->n_levels)) keep.push_back(t);
+        if (const float *a = field_thresholds(fields[i], tmp))
+            if (const ThrEntry *t =
+                    find_thresholds(ctx, a, fields[i]->n_levels, fields[i]->filtration == ECC_SUPERLEVEL))
+                keep.push_back(t);
     while (ctx->thr_cache.size() + (size_t)n_new > kThrCacheMax) {
         ecc_status s = evict_threshold(ctx, keep);
         if (s != ECC_OK) return s;
@@ -496,14 +531,20 @@ ecc_status level_args(ecc_context ctx, const ecc_field *f, const FieldInfo &fi, 
     lv->u0d = 0.0;
     lv->inv_step = 0.f;
     lv->eps = 0.f;
-    if (!f->thresholds) {
+    lv->neg = 0u;
+    std::vector<float> tmp;
+    const float *thr = field_thresholds(f, tmp);
+    if (!thr) {
         lv->mode = LM_IDENTITY;
         return ECC_OK;
     }
     const ThrEntry *te = nullptr;
-    ecc_status s = get_thresholds(ctx, f->thresholds, fi.L, fi.dtype, stream, &te);
+    ecc_status s = get_thresholds(ctx, thr, fi.L, fi.super, fi.dtype, stream, &te);
     if (s != ECC_OK) return s;
     lv->thr = te->d_thr;
+    // superlevel: the device thresholds are -t and the kernels compare -x
+    // against them; the affine estimate takes the sign in its slope
+    lv->neg = fi.super ? 0x80000000u : 0u;
     if (fi.dtype == ECC_U8) {
         lv->mode = LM_LUT;
         lv->lut = te->d_lut8;
@@ -514,7 +555,7 @@ ecc_status level_args(ecc_context ctx, const ecc_field *f, const FieldInfo &fi, 
         lv->mode = LM_AFFINE;
         lv->u0 = te->u0;
         lv->u0d = te->u0d;
-        lv->inv_step = te->inv_step;
+        lv->inv_step = fi.super ? -te->inv_step : te->inv_step;
         lv->eps = te->eps;
     } else {
         lv->mode = LM_SEARCH;

@@ -217,7 +217,7 @@ ecc_status launch_ready(ecc_server srv, std::vector<std::pair<Request *, ecc_sta
     int n_thr = 0;
     for (Request *r : srv->ready) {
         bool take = batchable(r->fi) && li >= 0 && (int)batch2d.size() < srv->cfg.max_batch;
-        if (take && r->field.thresholds) {
+        if (take && (r->field.thresholds || r->fi.super)) {  // a threshold array (or implied superlevel one)
             thr_fields.push_back(&r->field);
             const int k = count_distinct_thresholds((int)thr_fields.size(), thr_fields.data());
             if (k > (int)kThrCacheMax) {
@@ -298,6 +298,7 @@ ecc_status launch_ready(ecc_server srv, std::vector<std::pair<Request *, ecc_sta
                 d.n_items = n_items_of[i];
                 d.conn_idx = r->fi.conn == 8 ? 0 : 1;
                 d.inv_step = lv[i].inv_step;
+                d.neg = lv[i].neg;
                 d.cpass = (float)(lv[i].u0d + kBinOff + 0.5);
                 d.eps = lv[i].eps;
             }

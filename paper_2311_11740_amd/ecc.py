@@ -16,6 +16,7 @@ LIB_PATH = os.path.join(HERE, "libecc.so")
 
 ECC_OK, ECC_ERR_INVALID_ARG, ECC_ERR_UNSUPPORTED, ECC_ERR_OUT_OF_MEMORY, ECC_ERR_DEVICE, ECC_ERR_BUSY = range(6)
 ECC_U8, ECC_U16, ECC_F32 = 1, 2, 3
+ECC_SUBLEVEL, ECC_SUPERLEVEL = 0, 1
 
 # public C entry points (kept in step with include/ecc.h)
 EXPORTS = (
@@ -43,7 +44,8 @@ class EccError(RuntimeError):
 class Field(ctypes.Structure):
     _fields_ = [("ndim", ctypes.c_int32), ("dtype", ctypes.c_int32), ("shape", ctypes.c_int64 * 3),
                 ("data", ctypes.c_void_p), ("n_levels", ctypes.c_int32),
-                ("connectivity", ctypes.c_int32), ("thresholds", ctypes.c_void_p)]
+                ("connectivity", ctypes.c_int32), ("thresholds", ctypes.c_void_p),
+                ("filtration", ctypes.c_int32)]
 
 
 class Curves(ctypes.Structure):
@@ -174,9 +176,10 @@ CHANNELS_2D = ("ec", "perimeter", "area")
 CHANNELS_3D = ("ec", "perimeter", "area", "volume")
 
 
-def make_field(t, n_levels: int, thresholds=None, connectivity: int = 0):
+def make_field(t, n_levels: int, thresholds=None, connectivity: int = 0, superlevel: bool = False):
     """Build the C field descriptor for a contiguous device tensor.  The returned
-    tuple keeps the host threshold buffer alive."""
+    tuple keeps the host threshold buffer alive.  `superlevel` selects the
+    filtration by {value >= t_l} over non-increasing thresholds."""
     import numpy as np
     if not t.is_contiguous():
         raise ValueError("field must be contiguous (C order)")
@@ -190,6 +193,7 @@ def make_field(t, n_levels: int, thresholds=None, connectivity: int = 0):
     f.data = t.data_ptr()
     f.n_levels = int(n_levels)
     f.connectivity = int(connectivity or 0)
+    f.filtration = ECC_SUPERLEVEL if superlevel else ECC_SUBLEVEL
     keep = None
     if thresholds is not None:
         keep = np.ascontiguousarray(np.asarray(thresholds, dtype=np.float32))
@@ -247,12 +251,14 @@ class Context:
         return ms.value, n.value
 
     def compute(self, field, n_levels: int, thresholds=None, connectivity: int = 0,
-                channels: Sequence[str] | None = None, stream=None, out=None, noalloc: bool = False):
+                channels: Sequence[str] | None = None, stream=None, out=None, noalloc: bool = False,
+                superlevel: bool = False):
         """Curves of one device field: dict channel -> int64 device tensor (async on `stream`).
         `out` may supply preallocated curves (dict channel -> int64 tensor of n_levels).
         `noalloc` calls ecc_curves_compute_noalloc (the library allocates no
-        device memory for the call; `out` avoids torch's allocation too)."""
-        f, keep = make_field(field, n_levels, thresholds, connectivity)
+        device memory for the call; `out` avoids torch's allocation too).
+        `superlevel` selects the superlevel filtration (ECC_SUPERLEVEL)."""
+        f, keep = make_field(field, n_levels, thresholds, connectivity, superlevel)
         if out is None:
             out, cv = alloc_curves(field.dim(), n_levels, field.device, channels)
         else:
@@ -265,7 +271,8 @@ class Context:
         return out
 
     def compute_streamed(self, field, n_levels: int, thresholds=None, connectivity: int = 0,
-                         channels: Sequence[str] | None = None, slab_bytes: int = 0, stream=None):
+                         channels: Sequence[str] | None = None, slab_bytes: int = 0, stream=None,
+                         superlevel: bool = False):
         """Curves of a field in host memory (numpy array), streamed through the
         device in slabs of at most `slab_bytes` (0: the library's default).
         Blocking; returns dict channel -> int64 numpy array."""
@@ -284,6 +291,7 @@ class Context:
         f.data = a.ctypes.data
         f.n_levels = int(n_levels)
         f.connectivity = int(connectivity or 0)
+        f.filtration = ECC_SUPERLEVEL if superlevel else ECC_SUBLEVEL
         keep = None
         if thresholds is not None:
             keep = np.ascontiguousarray(np.asarray(thresholds, dtype=np.float32))
@@ -301,13 +309,14 @@ class Context:
         del keep, a
         return out
 
-    def vertex_classes(self, field, n_levels: int, thresholds=None, stream=None, out=None):
+    def vertex_classes(self, field, n_levels: int, thresholds=None, stream=None, out=None,
+                       superlevel: bool = False):
         """Counts of lattice vertices per neighbourhood class and level: int64
         device tensor [5, n_levels] (2D, rows in VERTEX_CLASSES_2D order) or
         [21, n_levels] (3D, classes as vertex_class_table(3)), async on
         `stream`.  `out` may supply that tensor."""
         torch = _torch()
-        f, keep = make_field(field, n_levels, thresholds, 0)
+        f, keep = make_field(field, n_levels, thresholds, 0, superlevel)
         nc = 5 if field.dim() == 2 else 21
         if out is None:
             out = torch.empty((nc, n_levels), dtype=torch.int64, device=field.device)
@@ -318,38 +327,39 @@ class Context:
         del keep
         return out
 
-    def batch(self, fields, n_levels, thresholds=None, connectivity=0, channels=None):
+    def batch(self, fields, n_levels, thresholds=None, connectivity=0, channels=None, superlevel=False):
         """A reusable batched call over `fields` (device tensors); see Batch."""
-        return Batch(self, fields, n_levels, thresholds, connectivity, channels)
+        return Batch(self, fields, n_levels, thresholds, connectivity, channels, superlevel)
 
     def compute_batch(self, fields, n_levels, thresholds=None, connectivity=0,
-                      channels: Sequence[str] | None = None, stream=None):
+                      channels: Sequence[str] | None = None, stream=None, superlevel=False):
         """Curves of many device fields in one batched call; list of dicts."""
-        b = Batch(self, fields, n_levels, thresholds, connectivity, channels)
+        b = Batch(self, fields, n_levels, thresholds, connectivity, channels, superlevel)
         b.run(stream)
         return b.outputs
 
-    def tune_batch(self, fields, n_levels, thresholds=None, connectivity=0, stream=None):
+    def tune_batch(self, fields, n_levels, thresholds=None, connectivity=0, stream=None, superlevel=False):
         """Run the autotuner for this mix of fields (synchronises `stream`)."""
-        Batch(self, fields, n_levels, thresholds, connectivity, ()).tune(stream)
+        Batch(self, fields, n_levels, thresholds, connectivity, (), superlevel).tune(stream)
 
 
 class Batch:
     """Descriptors of a batched call, built once and run many times.
 
-    fields: device tensors (2D or 3D, any mix); n_levels, thresholds and
-    connectivity: one value for all fields or a list with one per field.
+    fields: device tensors (2D or 3D, any mix); n_levels, thresholds,
+    connectivity and superlevel: one value for all fields or a list with one
+    per field.
     `outputs[i]` maps each wanted channel to an int64 device tensor of that
     field's n_levels (views into one allocation)."""
 
-    def __init__(self, ctx, fields, n_levels, thresholds=None, connectivity=0, channels=None):
+    def __init__(self, ctx, fields, n_levels, thresholds=None, connectivity=0, channels=None, superlevel=False):
         torch = _torch()
         n = len(fields)
 
         def per(v):
             return list(v) if isinstance(v, (list, tuple)) else [v] * n
 
-        n_levels, connectivity = per(n_levels), per(connectivity)
+        n_levels, connectivity, superlevel = per(n_levels), per(connectivity), per(superlevel)
         if thresholds is None or not isinstance(thresholds, (list, tuple)):
             thresholds = [thresholds] * n
         self.ctx = ctx
@@ -370,7 +380,7 @@ class Batch:
         self.outputs = []
         off = 0
         for i, t in enumerate(self.fields):
-            f, keep = make_field(t, n_levels[i], thresholds[i], connectivity[i])
+            f, keep = make_field(t, n_levels[i], thresholds[i], connectivity[i], superlevel[i])
             self.farr[i] = f
             self._keep.append(keep)
             o = {}
@@ -421,7 +431,8 @@ class Server:
         self.handle = h
         self._pending = {}
 
-    def submit(self, array, n_levels: int, thresholds=None, connectivity: int = 0, channels=None):
+    def submit(self, array, n_levels: int, thresholds=None, connectivity: int = 0, channels=None,
+               superlevel: bool = False):
         """Submit a host numpy field; returns the ticket, or None when the server
         is full right now (retry after a poll)."""
         import numpy as np
@@ -437,6 +448,7 @@ class Server:
         f.data = a.ctypes.data
         f.n_levels = int(n_levels)
         f.connectivity = int(connectivity or 0)
+        f.filtration = ECC_SUPERLEVEL if superlevel else ECC_SUBLEVEL
         keep = None
         if thresholds is not None:
             keep = np.ascontiguousarray(np.asarray(thresholds, dtype=np.float32))

@@ -124,6 +124,34 @@ def test_validation_thresholds(lib):
     assert lib.ecc_validate_field(ctypes.byref(f), ctypes.byref(_curves())) == ecc.ECC_OK
 
 
+def test_validation_filtration(lib):
+    dec = (ctypes.c_float * 3)(2.0, 1.0, 1.0)  # non-increasing, with a tie
+    inc = (ctypes.c_float * 3)(0.0, 1.0, 2.0)
+    f = _field(dtype=ecc.ECC_F32, L=3, thr=ctypes.cast(dec, ctypes.c_void_p))
+    f.filtration = ecc.ECC_SUPERLEVEL
+    assert lib.ecc_validate_field(ctypes.byref(f), ctypes.byref(_curves())) == ecc.ECC_OK
+    f.filtration = ecc.ECC_SUBLEVEL  # the same array runs the wrong way for sublevel sets
+    assert lib.ecc_validate_field(ctypes.byref(f), ctypes.byref(_curves())) == ecc.ECC_ERR_INVALID_ARG
+    f = _field(dtype=ecc.ECC_F32, L=3, thr=ctypes.cast(inc, ctypes.c_void_p))
+    f.filtration = ecc.ECC_SUPERLEVEL
+    assert lib.ecc_validate_field(ctypes.byref(f), ctypes.byref(_curves())) == ecc.ECC_ERR_INVALID_ARG
+    assert "non-increasing" in lib.ecc_last_error().decode()
+    f = _field()  # integer levels without thresholds: both directions
+    f.filtration = ecc.ECC_SUPERLEVEL
+    assert lib.ecc_validate_field(ctypes.byref(f), ctypes.byref(_curves())) == ecc.ECC_OK
+    f.filtration = 2
+    assert lib.ecc_validate_field(ctypes.byref(f), ctypes.byref(_curves())) == ecc.ECC_ERR_INVALID_ARG
+    f = _field(dtype=ecc.ECC_F32)  # float fields need thresholds in both directions
+    f.filtration = ecc.ECC_SUPERLEVEL
+    assert lib.ecc_validate_field(ctypes.byref(f), ctypes.byref(_curves())) == ecc.ECC_ERR_INVALID_ARG
+
+
+def test_field_struct_layout():
+    """The binding's Field is laid out as the header's ecc_field (and as the
+    oracle's own descriptor): filtration after the thresholds pointer."""
+    assert ecc.Field.filtration.offset == 56 and ctypes.sizeof(ecc.Field) == 64
+
+
 def test_validation_channels(lib):
     f = _field()
     assert lib.ecc_validate_field(ctypes.byref(f), ctypes.byref(_curves(ec=None))) == ecc.ECC_ERR_INVALID_ARG

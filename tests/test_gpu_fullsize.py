@@ -8,6 +8,8 @@ benchmark times.
   binarises and counts cells at one level at a time.
 * A 3D volume whose z-marching launch is split along z (workgroup bins would
   otherwise see too many cells), against O2.
+* The 8192 x 8192 float32 field over its superlevel filtration (falling
+  thresholds), against O2 and sampled levels of O1.
 """
 from __future__ import annotations
 
@@ -86,6 +88,33 @@ def test_large_2d_f32(ctx):
     got = gpu_curves(ctx, spec, None)
     check_o2(spec, got, spec.meta["name"])
     check_o1_levels(spec, got, [0, 300, 511, 512, 700, 1023], spec.meta["name"])
+
+
+def test_large_2d_f32_superlevel(ctx):
+    """The same 8192 x 8192 float32 field over its superlevel filtration (the
+    1024 thresholds in falling order, sets {value >= t_l}) against O2's
+    superlevel route, and sampled levels against O1 binarising with >=."""
+    import torch
+    import oracle
+    from paper_2311_11740_amd import synth
+    spec = synth.large_2d_f32()
+    t = spec.thresholds[::-1].copy()
+    print(f"[case] {spec.meta['name']} superlevel", flush=True)
+    dev = torch.from_numpy(spec.data).cuda()
+    got = ctx.compute(dev, spec.n_levels, thresholds=t, superlevel=True)
+    torch.cuda.synchronize()
+    got = {k: v.cpu().numpy() for k, v in got.items()}
+    ref = oracle.o2_curves(spec.data, spec.n_levels, thresholds=t, channels=tuple(got), n_threads=NT,
+                           superlevel=True)
+    for k in got:
+        bad = np.nonzero(got[k] != ref[k])[0]
+        assert bad.size == 0, f"superlevel {k}: {bad.size} levels differ, first {bad[:1]}"
+    levels = [0, 400, 512, 1023]
+    ref1 = oracle.o1_curves(spec.data, spec.n_levels, thresholds=t, levels=levels, channels=tuple(got),
+                            superlevel=True)
+    for k in got:
+        for i, lv in enumerate(levels):
+            assert got[k][lv] == ref1[k][i], (k, lv)
 
 
 @pytest.mark.parametrize("channels", [("ec", "area", "volume"), None], ids=["no_crease", "all_channels"])
