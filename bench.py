@@ -333,7 +333,7 @@ def timed_calls(fn, steps):
     return t0.elapsed_time(t1) / steps, (time.perf_counter() - w0) * 1e3 / steps
 
 
-def measure_batch(ctx, specs, steps, warmup):
+def measure_batch(ctx, specs, steps, warmup, workload=None):
     """Batched call vs one call per field over the same fields (already in HBM)."""
     import numpy as np
     import torch
@@ -346,8 +346,9 @@ def measure_batch(ctx, specs, steps, warmup):
     dev = torch.from_numpy(host).cuda()
     views = [dev[int(offs[i]):int(offs[i + 1])].view(*specs[i].data.shape) for i in range(len(specs))]
     L = specs[0].n_levels
-    b = ctx.batch(views, L, connectivity=8)
-    ref = ctx.batch(views, L, connectivity=8)
+    conn = specs[0].connectivity
+    b = ctx.batch(views, L, connectivity=conn)
+    ref = ctx.batch(views, L, connectivity=conn)
     for _ in range(warmup):
         ref.run_per_field(torch.cuda.current_stream())
     pf_ms, pf_wall = timed_calls(ref.run_per_field, max(3, steps // 4))
@@ -376,13 +377,14 @@ def measure_batch(ctx, specs, steps, warmup):
     sample = list(range(0, len(specs), max(1, len(specs) // 16)))
     ok = True
     for i in sample:
-        r = oracle.o2_curves(specs[i].data, L, connectivity=8, channels=tuple(b.outputs[i]),
+        r = oracle.o2_curves(specs[i].data, L, connectivity=conn, channels=tuple(b.outputs[i]),
                              n_threads=min(16, os.cpu_count() or 1))
         ok &= all(np.array_equal(b.outputs[i][c].cpu().numpy(), r[c]) for c in r)
     px = float(sum(sizes))
     best = min(bd_ms, bt_ms)
     return dict(
-        workload=f"batch_{len(specs)}x_u8_side64-2048_L{L}", fields=len(specs), gpx=round(px / 1e9, 4),
+        workload=workload or f"batch_{len(specs)}x_u8_side64-2048_L{L}", fields=len(specs),
+        gpx=round(px / 1e9, 4),
         per_field_ms=round(pf_ms, 3), per_field_host_ms=round(pf_wall, 3),
         batched_ms=round(bd_ms, 3), batched_tuned_ms=round(bt_ms, 3), batched_host_ms=round(bt_wall, 3),
         per_field_gvox_s=round(px / pf_ms / 1e6, 2), batched_gvox_s=round(px / best / 1e6, 2),
@@ -561,6 +563,7 @@ def main():
     spec = make_workload(args.workload)
     sec_spec = make_workload("3d") if args.workload == "2d" and not args.no_secondary else None
     batch_specs = None if args.no_batch else synth.batch_2d_u8(workers=args.gen_workers)
+    grid_specs = None if args.no_batch else synth.batch_3d_grids(workers=args.gen_workers)
     pool = None if args.no_serving else synth.serving_pool(workers=args.gen_workers)
     print(f"[bench] inputs drawn in {time.perf_counter() - t_gen:.1f} s", file=sys.stderr, flush=True)
 
@@ -621,6 +624,12 @@ def main():
     if batch_specs is not None:
         line["batched"] = measure_batch(ctx, batch_specs, max(5, args.steps // 2), 2)
         print(f"[bench] batched: {line['batched']['batched_gvox_s']} Gvox/s", file=sys.stderr, flush=True)
+    if grid_specs is not None:
+        line["batched_3d"] = measure_batch(ctx, grid_specs, max(5, args.steps // 2), 2,
+                                           workload=f"batch_{len(grid_specs)}x_u8_20^3_L256_26c")
+        print(f"[bench] batched 3D: {line['batched_3d']['batched_gvox_s']} Gvox/s "
+              f"({line['batched_3d']['speedup']}x per-field)", file=sys.stderr, flush=True)
+        del grid_specs
     if not args.no_paper_workloads:
         line["paper_workloads"] = measure_paper_workloads(ctx, max(5, args.steps // 2))
         print("[bench] paper workloads done", file=sys.stderr, flush=True)

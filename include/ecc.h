@@ -204,10 +204,12 @@ ecc_status ecc_curves_compute_streamed(ecc_context ctx, const ecc_field *field, 
 /*
  * The same for n fields of any mix of shapes, dtypes, level counts and
  * connectivities (the paper's dispatch of many small images, Discussion of the
- * microscopy case).  fields[i] and curves[i] follow the single-field contract.
- * 2D fields with at most 4096 levels go into one persistent launch per (dtype,
- * level mode) group, replayed from a captured graph; other fields (3D, more
- * levels) run through the single-field path on the same stream after it.
+ * microscopy case, and of many small volumes, its molecular-dynamics case).
+ * fields[i] and curves[i] follow the single-field contract.  2D fields with at
+ * most 4096 levels, and volumes with at most 4096 levels and 2^22 voxels, go
+ * into one persistent launch per (dimension, dtype, level mode) group,
+ * replayed from a captured graph; other fields (larger volumes, more levels)
+ * run through the single-field path on the same stream after them.
  * The launch geometry comes from the context's tuning cache (see
  * ecc_batch_plan_tune), else defaults.
  * The threshold arrays of one call are uploaded once per distinct content; a
@@ -298,10 +300,11 @@ ecc_status ecc_profile_read(ecc_context ctx, double *total_ms, int64_t *launches
  * slot is free and its field plus curves fit in the arena (first fit); its field
  * is staged in pinned memory during the submit, copied to the device on a copy
  * stream, and computed as soon as it has landed:
- * all ready 2D requests (up to max_batch, and at most 256 distinct threshold
- * arrays; the rest join the next launch) in one launch of the batched kernel,
- * others (3D, more than 4096 levels) through the single-field path on a second
- * stream.  Requests submitted while earlier ones run join the next launch.
+ * all ready requests the batched kernels take (2D fields and volumes of at
+ * most 2^22 voxels with at most 4096 levels; up to max_batch, and at most 256
+ * distinct threshold arrays; the rest join the next launch) in one launch of
+ * the batched kernels, others (larger volumes, more than 4096 levels) through
+ * the single-field path on a second stream.  Requests submitted while earlier ones run join the next launch.
  * Results go back to pinned memory and then to the caller's host arrays, and
  * the request's slot and memory are released.
  * ------------------------------------------------------------------------- */

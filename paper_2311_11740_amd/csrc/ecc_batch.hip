@@ -1,10 +1,12 @@
 // Batched entry point and its autotuner.
 //
 // A batch call groups its fields by kernel class: 2D fields with at most
-// kBatchMaxLevels levels and kBatchMaxCells cells go to the persistent batched
-// kernel (one launch per (dtype, level mode) group, normally a single one);
-// every other field (3D, more levels, fewer cells than one vector load) runs
-// through the single-field path on the same stream after it.
+// kBatchMaxLevels levels and kBatchMaxCells cells go to the persistent 2D
+// batched kernel, volumes with at most kBatchMaxLevels levels and
+// kBatch3DMaxCells voxels to the persistent 3D batched kernel (one launch per
+// (dimension, dtype, level mode) group); every other field (more levels,
+// large volumes, fewer cells than one vector load) runs through the
+// single-field path on the same stream after them.
 //
 // The plan of a batch (work items, their assignment to workgroups, per-field
 // histograms and tickets, the captured graph) depends only on the shapes,
@@ -20,6 +22,7 @@
 #include <map>
 #include <queue>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "ecc_runtime.h"
@@ -27,7 +30,7 @@
 namespace ecc {
 
 struct BatchGroup {
-    int dtype = 0, lm = 0;
+    int ndim = 2, dtype = 0, lm = 0;
     std::vector<int> fields;  // descriptor slots
     int grid = 0, max_L = 0, n_items = 0;
     BatchItem *d_items = nullptr;
@@ -38,12 +41,14 @@ struct BatchPlan {
     std::string key;
     int item_cells = 0, wg_per_cu = 0;
     std::vector<BatchGroup> groups;
-    std::vector<int> slot_of;  // field index -> descriptor slot, -1 = single-field path
+    std::vector<int> kind;     // field index -> 2 or 3 (batched kernel), 0 = single-field path
+    std::vector<int> slot_of;  // field index -> slot in its kind's descriptors
     std::vector<int> others;   // fields on the single-field path
-    int n_desc = 0;
-    std::vector<int32_t> n_items_of;  // per slot
-    std::vector<int64_t> hist_off;    // per slot, in int32 elements
+    int n_desc = 0, n_desc3 = 0;
+    std::vector<int32_t> n_items_of;  // per field index
+    std::vector<int64_t> hist_off;    // per field index, in int32 elements
     BatchField2D *d_desc = nullptr, *h_desc = nullptr;
+    BatchField3D *d_desc3 = nullptr, *h_desc3 = nullptr;
     int32_t *d_hist = nullptr;
     uint32_t *d_done = nullptr;
     hipGraph_t graph = nullptr;
@@ -59,6 +64,7 @@ struct BatchState {
     hipStream_t capture = nullptr;
     uint64_t tick = 0;
     uint64_t *d_luts = nullptr;  // [2][256] packed 2D per-cell deltas, 8-C then 4-C
+    int64_t *d_vt3 = nullptr;    // [2][256] 3D per-octant tables, 26-C then 6-C
 };
 
 constexpr size_t kMaxPlans = 8;
@@ -75,6 +81,8 @@ static void free_plan(BatchPlan *p) {
     if (p->graph) hipGraphDestroy(p->graph);
     if (p->d_desc) hipFree(p->d_desc);
     if (p->h_desc) hipHostFree(p->h_desc);
+    if (p->d_desc3) hipFree(p->d_desc3);
+    if (p->h_desc3) hipHostFree(p->h_desc3);
     if (p->d_hist) hipFree(p->d_hist);
     if (p->d_done) hipFree(p->d_done);
     if (p->copy_done) hipEventDestroy(p->copy_done);
@@ -88,6 +96,7 @@ void destroy_batch_state(ecc_context ctx) {
     for (auto *p : b->plans) free_plan(p);
     if (b->capture) hipStreamDestroy(b->capture);
     if (b->d_luts) hipFree(b->d_luts);
+    if (b->d_vt3) hipFree(b->d_vt3);
     delete b;
     ctx->batch = nullptr;
 }
@@ -101,20 +110,26 @@ static ecc_status batch_state(ecc_context ctx, BatchState **out) {
             return hip_fail(e, "hipStreamCreate");
         }
         e = (int)hipMalloc(&b->d_luts, 2 * 256 * sizeof(uint64_t));
+        if (!e) e = (int)hipMalloc(&b->d_vt3, 2 * 256 * sizeof(int64_t));
         if (e) {
+            if (b->d_luts) hipFree(b->d_luts);
             hipStreamDestroy(b->capture);
             delete b;
             return fail(ECC_ERR_OUT_OF_MEMORY, "hipMalloc(batch tables) failed");
         }
-        for (int k = 0; k < 2; ++k) {
+        for (int k = 0; k < 2 && !e; ++k) {
             e = (int)hipMemcpy(b->d_luts + 256 * k, ctx->d_delta2[k], 256 * sizeof(uint64_t),
                                hipMemcpyDeviceToDevice);
-            if (e) {
-                hipFree(b->d_luts);
-                hipStreamDestroy(b->capture);
-                delete b;
-                return hip_fail(e, "hipMemcpy(batch tables)");
-            }
+            if (!e)
+                e = (int)hipMemcpy(b->d_vt3 + 256 * k, ctx->d_vtab3[k], 256 * sizeof(int64_t),
+                                   hipMemcpyDeviceToDevice);
+        }
+        if (e) {
+            hipFree(b->d_luts);
+            hipFree(b->d_vt3);
+            hipStreamDestroy(b->capture);
+            delete b;
+            return hip_fail(e, "hipMemcpy(batch tables)");
         }
         ctx->batch = b;
     }
@@ -122,11 +137,14 @@ static ecc_status batch_state(ecc_context ctx, BatchState **out) {
     return ECC_OK;
 }
 
-// fields the batched kernel takes
-bool batchable(const FieldInfo &fi) {
-    if (fi.ndim != 2 || fi.L > kBatchMaxLevels || fi.cells > kBatchMaxCells) return false;
-    return fi.cells >= vec_2d(fi.dtype);
+// the batched kernel that takes a field (2 or 3), or 0
+int batch_kind(const FieldInfo &fi) {
+    if (fi.L > kBatchMaxLevels) return 0;
+    if (fi.ndim == 2) return fi.cells <= kBatchMaxCells && fi.cells >= vec_2d(fi.dtype) ? 2 : 0;
+    return fi.cells <= kBatch3DMaxCells ? 3 : 0;
 }
+
+bool batchable(const FieldInfo &fi) { return batch_kind(fi) != 0; }
 
 static std::string plan_key(int n, const FieldInfo *fi, const LevelArgs *lv) {
     std::string k;
@@ -143,11 +161,38 @@ static std::string plan_key(int n, const FieldInfo *fi, const LevelArgs *lv) {
     return k;
 }
 
+// Deal items to `grid` workgroups, largest first, each to the least loaded
+// one; items come out grouped by workgroup (first: grid + 1 entries).
+static void deal_items(const std::vector<BatchItem> &items, const std::vector<int64_t> &cost, int64_t per_item,
+                       int grid, std::vector<BatchItem> &sorted, std::vector<int32_t> &first) {
+    std::vector<int> order(items.size());
+    for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
+    typedef std::pair<int64_t, int> Load;
+    std::priority_queue<Load, std::vector<Load>, std::greater<Load>> pq;
+    for (int wg = 0; wg < grid; ++wg) pq.push({0, wg});
+    std::vector<std::vector<int>> per_wg(grid);
+    for (int i : order) {
+        Load l = pq.top();
+        pq.pop();
+        per_wg[l.second].push_back(i);
+        l.first += cost[i] + per_item;  // + a fixed cost per item (drain, ticket)
+        pq.push(l);
+    }
+    sorted.clear();
+    sorted.reserve(items.size());
+    first.assign(grid + 1, 0);
+    for (int wg = 0; wg < grid; ++wg) {
+        first[wg] = (int32_t)sorted.size();
+        for (int i : per_wg[wg]) sorted.push_back(items[i]);
+    }
+    first[grid] = (int32_t)sorted.size();
+}
+
 // Cut fields into items of at most `item_cells` cells (counted as whole
 // strips of 62 lanes x VEC cells per row, the work a wave does per row), and
-// deal the items to workgroups, largest first, each to the least loaded one.
-// Returns the grid; items come out grouped by workgroup (wg_first, grid + 1
-// entries), n_items gets the item count of each field.
+// deal the items to workgroups.  Returns the grid; n_items gets the item count
+// of each field.
 int schedule_batch_2d(int n_cu, int dtype, int lm, int max_L, const std::vector<SchedField> &fields,
                       int item_cells, int wg_per_cu, std::vector<BatchItem> &sorted, std::vector<int32_t> &first,
                       std::vector<int32_t> &n_items) {
@@ -170,32 +215,89 @@ int schedule_batch_2d(int n_cu, int dtype, int lm, int max_L, const std::vector<
     const int fit = std::max<int>(1, (int)((160 * 1024) / lds));
     const int64_t G = std::min<int64_t>((int64_t)n_cu * std::min(wg_per_cu, fit), (int64_t)items.size());
     const int grid = (int)std::max<int64_t>(1, G);
-    std::vector<int> order(items.size());
-    for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
-    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
-    typedef std::pair<int64_t, int> Load;
-    std::priority_queue<Load, std::vector<Load>, std::greater<Load>> pq;
-    for (int wg = 0; wg < grid; ++wg) pq.push({0, wg});
-    std::vector<std::vector<int>> per_wg(grid);
-    for (int i : order) {
-        Load l = pq.top();
-        pq.pop();
-        per_wg[l.second].push_back(i);
-        l.first += cost[i] + 8;  // + a fixed cost per item (drain, ticket)
-        pq.push(l);
-    }
-    sorted.clear();
-    sorted.reserve(items.size());
-    first.assign(grid + 1, 0);
-    for (int wg = 0; wg < grid; ++wg) {
-        first[wg] = (int32_t)sorted.size();
-        for (int i : per_wg[wg]) sorted.push_back(items[i]);
-    }
-    first[grid] = (int32_t)sorted.size();
+    deal_items(items, cost, 8, grid, sorted, first);
     return grid;
 }
 
-// A cached plan: batchable fields grouped by (dtype, level mode), each group
+// 3D: items of whole tiles (kTile3DX x kTile3DY x kTile3DZ voxels, at most
+// kFlush3D voxels per item so that the packed LDS bins cannot overflow).
+int schedule_batch_3d(int n_cu, int max_L, const std::vector<SchedField> &fields, int item_cells, int wg_per_cu,
+                      std::vector<BatchItem> &sorted, std::vector<int32_t> &first, std::vector<int32_t> &n_items) {
+    constexpr int64_t tv = (int64_t)kTile3DX * kTile3DY * kTile3DZ;
+    const int64_t max_tiles = std::max<int64_t>(1, std::min<int64_t>(item_cells, kFlush3D) / tv);
+    std::vector<BatchItem> items;
+    std::vector<int64_t> cost;
+    n_items.assign(fields.size(), 0);
+    for (size_t f = 0; f < fields.size(); ++f) {
+        const int64_t tiles = ((fields[f].w + kTile3DX - 1) / kTile3DX) * ((fields[f].h + kTile3DY - 1) / kTile3DY) *
+                              ((fields[f].d + kTile3DZ - 1) / kTile3DZ);
+        const int64_t k = (tiles + max_tiles - 1) / max_tiles;
+        for (int64_t j = 0; j < k; ++j) {
+            const int64_t u0 = tiles * j / k, u1 = tiles * (j + 1) / k;
+            items.push_back(BatchItem{fields[f].slot, (int32_t)u0, (int32_t)u1, 0});
+            cost.push_back(u1 - u0);
+        }
+        n_items[f] = (int32_t)k;
+    }
+    const size_t lds = lds_bytes_batch_3d(max_L) + 22 * 1024;  // + window table, tile levels, scan
+    const int fit = std::max<int>(1, (int)((160 * 1024) / lds));
+    const int64_t G = std::min<int64_t>((int64_t)n_cu * std::min(wg_per_cu, fit), (int64_t)items.size());
+    const int grid = (int)std::max<int64_t>(1, G);
+    deal_items(items, cost, 1, grid, sorted, first);
+    return grid;
+}
+
+// descriptors of a field (everything but the plan's histogram, ticket and item count)
+void fill_desc_2d(BatchField2D &d, const ecc_field &f, const ecc_curves &c, const FieldInfo &fi,
+                  const LevelArgs &lv) {
+    std::memset(&d, 0, sizeof(d));
+    d.data = f.data;
+    d.h = fi.h;
+    d.w = fi.w;
+    d.out[0] = c.ec;
+    d.out[1] = c.perimeter;
+    d.out[2] = c.area;
+    d.thr = lv.thr;
+    d.lut = lv.lut;
+    d.L = fi.L;
+    d.conn_idx = fi.conn == 8 ? 0 : 1;
+    d.inv_step = lv.inv_step;
+    d.neg = lv.neg;
+    d.cpass = (float)(lv.u0d + kBinOff + 0.5);
+    d.eps = lv.eps;
+}
+
+void fill_desc_3d(BatchField3D &d, const ecc_field &f, const ecc_curves &c, const FieldInfo &fi,
+                  const LevelArgs &lv) {
+    std::memset(&d, 0, sizeof(d));
+    d.data = f.data;
+    d.d = fi.d;
+    d.h = fi.h;
+    d.w = fi.w;
+    d.out[0] = c.ec;
+    d.out[1] = c.perimeter;
+    d.out[2] = c.area;
+    d.out[3] = c.volume;
+    d.thr = lv.thr;
+    d.lut = lv.lut;
+    d.L = fi.L;
+    d.conn_idx = fi.conn == 26 ? 0 : 1;
+    d.neg = lv.neg;
+    d.u0 = lv.u0;
+    d.inv_step = lv.inv_step;
+    d.eps = lv.eps;
+    d.tiles_x = (int32_t)((fi.w + kTile3DX - 1) / kTile3DX);
+    d.tiles_y = (int32_t)((fi.h + kTile3DY - 1) / kTile3DY);
+}
+
+static int launch_group(const BatchState *bs, const BatchPlan *p, const BatchGroup &g, void *stream) {
+    if (g.ndim == 2)
+        return launch_batch_2d(g.dtype, g.lm, p->d_desc, g.d_items, g.d_wg_first, g.grid, bs->d_luts, g.max_L,
+                               stream);
+    return launch_batch_3d(g.dtype, g.lm, p->d_desc3, g.d_items, g.d_wg_first, g.grid, bs->d_vt3, g.max_L, stream);
+}
+
+// A cached plan: batchable fields grouped by (dimension, dtype, level mode), each group
 // scheduled as above, device copies of the schedules, per-field histograms
 // and tickets, and the group launches captured as a graph.
 static ecc_status build_plan(ecc_context ctx, BatchState *bs, int n, const FieldInfo *fi, const LevelArgs *lv,
@@ -205,30 +307,34 @@ static ecc_status build_plan(ecc_context ctx, BatchState *bs, int n, const Field
     p->item_cells = item_cells;
     p->wg_per_cu = wg_per_cu;
     p->slot_of.assign(n, -1);
-    std::map<std::pair<int, int>, int> group_of;
+    p->kind.assign(n, 0);
+    std::map<std::tuple<int, int, int>, int> group_of;
     for (int i = 0; i < n; ++i) {
-        if (!batchable(fi[i])) {
+        const int kd = batch_kind(fi[i]);
+        if (!kd) {
             p->others.push_back(i);
             continue;
         }
-        const auto gk = std::make_pair(fi[i].dtype, lv[i].mode);
+        const auto gk = std::make_tuple(kd, fi[i].dtype, lv[i].mode);
         auto it = group_of.find(gk);
         if (it == group_of.end()) {
             it = group_of.emplace(gk, (int)p->groups.size()).first;
             p->groups.emplace_back();
+            p->groups.back().ndim = kd;
             p->groups.back().dtype = fi[i].dtype;
             p->groups.back().lm = lv[i].mode;
         }
-        p->slot_of[i] = p->n_desc++;
+        p->kind[i] = kd;
+        p->slot_of[i] = kd == 2 ? p->n_desc++ : p->n_desc3++;
         p->groups[it->second].fields.push_back(i);
     }
-    p->n_items_of.assign(p->n_desc, 0);
-    p->hist_off.assign(p->n_desc, 0);
+    p->n_items_of.assign(n, 0);
+    p->hist_off.assign(n, 0);
     int64_t hist_total = 0;
     for (int i = 0; i < n; ++i)
-        if (p->slot_of[i] >= 0) {
-            p->hist_off[p->slot_of[i]] = hist_total;
-            hist_total += 3 * (int64_t)fi[i].L;
+        if (p->kind[i]) {
+            p->hist_off[i] = hist_total;
+            hist_total += (p->kind[i] == 2 ? 3 : 4) * (int64_t)fi[i].L;
         }
     auto cleanup = [&](ecc_status s) {
         free_plan(p);
@@ -238,15 +344,18 @@ static ecc_status build_plan(ecc_context ctx, BatchState *bs, int n, const Field
         std::vector<SchedField> sf;
         for (int i : g.fields) {
             g.max_L = std::max(g.max_L, fi[i].L);
-            sf.push_back(SchedField{p->slot_of[i], fi[i].h, fi[i].w});
+            sf.push_back(SchedField{p->slot_of[i], fi[i].h, fi[i].w, fi[i].d});
         }
         std::vector<BatchItem> sorted;
         std::vector<int32_t> first;
         std::vector<int32_t> n_items;
-        g.grid = schedule_batch_2d(ctx->n_cu, g.dtype, g.lm, g.max_L, sf, item_cells, wg_per_cu, sorted, first,
-                                   n_items);
+        if (g.ndim == 2)
+            g.grid = schedule_batch_2d(ctx->n_cu, g.dtype, g.lm, g.max_L, sf, item_cells, wg_per_cu, sorted, first,
+                                       n_items);
+        else
+            g.grid = schedule_batch_3d(ctx->n_cu, g.max_L, sf, item_cells, wg_per_cu, sorted, first, n_items);
         g.n_items = (int)sorted.size();
-        for (size_t j = 0; j < sf.size(); ++j) p->n_items_of[sf[j].slot] = n_items[j];
+        for (size_t j = 0; j < g.fields.size(); ++j) p->n_items_of[g.fields[j]] = n_items[j];
         int e = (int)hipMalloc(&g.d_items, sizeof(BatchItem) * std::max<size_t>(1, sorted.size()));
         if (e) return cleanup(fail(ECC_ERR_OUT_OF_MEMORY, "hipMalloc(batch items) failed"));
         e = (int)hipMalloc(&g.d_wg_first, sizeof(int32_t) * first.size());
@@ -260,13 +369,21 @@ static ecc_status build_plan(ecc_context ctx, BatchState *bs, int n, const Field
         if (e) return cleanup(fail(ECC_ERR_OUT_OF_MEMORY, "hipMalloc(batch descriptors) failed"));
         e = (int)hipHostMalloc(&p->h_desc, sizeof(BatchField2D) * p->n_desc, 0);
         if (e) return cleanup(hip_fail(e, "hipHostMalloc(batch descriptors)"));
-        e = (int)hipMalloc(&p->d_hist, sizeof(int32_t) * std::max<int64_t>(1, hist_total));
+    }
+    if (p->n_desc3 > 0) {
+        int e = (int)hipMalloc(&p->d_desc3, sizeof(BatchField3D) * p->n_desc3);
+        if (e) return cleanup(fail(ECC_ERR_OUT_OF_MEMORY, "hipMalloc(batch descriptors) failed"));
+        e = (int)hipHostMalloc(&p->h_desc3, sizeof(BatchField3D) * p->n_desc3, 0);
+        if (e) return cleanup(hip_fail(e, "hipHostMalloc(batch descriptors)"));
+    }
+    if (p->n_desc + p->n_desc3 > 0) {
+        int e = (int)hipMalloc(&p->d_hist, sizeof(int32_t) * std::max<int64_t>(1, hist_total));
         if (e) return cleanup(fail(ECC_ERR_OUT_OF_MEMORY, "hipMalloc(batch histograms) failed"));
-        e = (int)hipMalloc(&p->d_done, sizeof(uint32_t) * p->n_desc);
+        e = (int)hipMalloc(&p->d_done, sizeof(uint32_t) * n);
         if (e) return cleanup(fail(ECC_ERR_OUT_OF_MEMORY, "hipMalloc(batch tickets) failed"));
-        // the kernel leaves both at zero after every launch
+        // the kernels leave both at zero after every launch
         e = (int)hipMemset(p->d_hist, 0, sizeof(int32_t) * std::max<int64_t>(1, hist_total));
-        if (!e) e = (int)hipMemset(p->d_done, 0, sizeof(uint32_t) * p->n_desc);
+        if (!e) e = (int)hipMemset(p->d_done, 0, sizeof(uint32_t) * n);
         if (!e) e = (int)hipDeviceSynchronize();
         if (e) return cleanup(hip_fail(e, "hipMemset(batch workspace)"));
     }
@@ -278,9 +395,7 @@ static ecc_status build_plan(ecc_context ctx, BatchState *bs, int n, const Field
         bool ok = hipStreamBeginCapture(bs->capture, hipStreamCaptureModeRelaxed) == hipSuccess;
         bool launched = ok;
         for (auto &g : p->groups)
-            if (launched)
-                launched = launch_batch_2d(g.dtype, g.lm, p->d_desc, g.d_items, g.d_wg_first, g.grid, bs->d_luts,
-                                           g.max_L, bs->capture) == 0;
+            if (launched) launched = launch_group(bs, p, g, bs->capture) == 0;
         if (ok) ok = hipStreamEndCapture(bs->capture, &p->graph) == hipSuccess && launched;
         if (ok) ok = hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0) == hipSuccess;
         if (!ok) {
@@ -348,35 +463,34 @@ static ecc_status run_plan(ecc_context ctx, BatchState *bs, BatchPlan *p, int n,
         e = (int)hipStreamWaitEvent(st, p->last_use, 0);
         if (e) return hip_fail(e, "hipStreamWaitEvent");
     }
-    if (p->n_desc > 0) {
+    if (p->n_desc + p->n_desc3 > 0) {
         if (p->copy_pending) {  // the pinned descriptors may still be in flight
             e = (int)hipEventSynchronize(p->copy_done);
             if (e) return hip_fail(e, "hipEventSynchronize");
         }
         for (int i = 0; i < n; ++i) {
             const int sl = p->slot_of[i];
-            if (sl < 0) continue;
-            BatchField2D &d = p->h_desc[sl];
-            std::memset(&d, 0, sizeof(d));
-            d.data = fields[i].data;
-            d.h = fi[i].h;
-            d.w = fi[i].w;
-            d.out[0] = curves[i].ec;
-            d.out[1] = curves[i].perimeter;
-            d.out[2] = curves[i].area;
-            d.hist = p->d_hist + p->hist_off[sl];
-            d.done = p->d_done + sl;
-            d.thr = lv[i].thr;
-            d.lut = lv[i].lut;
-            d.L = fi[i].L;
-            d.n_items = p->n_items_of[sl];
-            d.conn_idx = fi[i].conn == 8 ? 0 : 1;
-            d.inv_step = lv[i].inv_step;
-            d.neg = lv[i].neg;
-            d.cpass = (float)(lv[i].u0d + kBinOff + 0.5);
-            d.eps = lv[i].eps;
+            if (p->kind[i] == 2) {
+                BatchField2D &d = p->h_desc[sl];
+                fill_desc_2d(d, fields[i], curves[i], fi[i], lv[i]);
+                d.hist = p->d_hist + p->hist_off[i];
+                d.done = p->d_done + i;
+                d.n_items = p->n_items_of[i];
+            } else if (p->kind[i] == 3) {
+                BatchField3D &d = p->h_desc3[sl];
+                fill_desc_3d(d, fields[i], curves[i], fi[i], lv[i]);
+                d.hist = p->d_hist + p->hist_off[i];
+                d.done = p->d_done + i;
+                d.n_items = p->n_items_of[i];
+            }
         }
-        e = (int)hipMemcpyAsync(p->d_desc, p->h_desc, sizeof(BatchField2D) * p->n_desc, hipMemcpyHostToDevice, st);
+        e = 0;
+        if (p->n_desc)
+            e = (int)hipMemcpyAsync(p->d_desc, p->h_desc, sizeof(BatchField2D) * p->n_desc, hipMemcpyHostToDevice,
+                                    st);
+        if (!e && p->n_desc3)
+            e = (int)hipMemcpyAsync(p->d_desc3, p->h_desc3, sizeof(BatchField3D) * p->n_desc3,
+                                    hipMemcpyHostToDevice, st);
         if (e) return hip_fail(e, "hipMemcpyAsync(batch descriptors)");
         e = (int)hipEventRecord(p->copy_done, st);
         if (e) return hip_fail(e, "hipEventRecord");
@@ -389,17 +503,16 @@ static ecc_status run_plan(ecc_context ctx, BatchState *bs, BatchPlan *p, int n,
             if (e) return hip_fail(e, "hipGraphLaunch");
         } else {
             for (auto &g : p->groups) {
-                e = launch_batch_2d(g.dtype, g.lm, p->d_desc, g.d_items, g.d_wg_first, g.grid, bs->d_luts, g.max_L,
-                                    stream);
+                e = launch_group(bs, p, g, stream);
                 if (e) return hip_fail(e, "batched kernel launch");
             }
         }
         s = prof_end(ctx, stream, slot);
         if (s != ECC_OK) return s;
         for (int i = 0; i < n; ++i) {  // the graph reads these threshold arrays
-            if (p->slot_of[i] < 0 || !lv[i].thr) continue;
+            if (!p->kind[i] || !lv[i].thr) continue;
             bool seen = false;
-            for (int j = 0; j < i && !seen; ++j) seen = p->slot_of[j] >= 0 && lv[j].thr == lv[i].thr;
+            for (int j = 0; j < i && !seen; ++j) seen = p->kind[j] && lv[j].thr == lv[i].thr;
             if (!seen) {
                 s = note_threshold_use(ctx, lv[i], stream);
                 if (s != ECC_OK) return s;

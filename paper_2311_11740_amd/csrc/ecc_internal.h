@@ -176,14 +176,34 @@ struct BatchField2D {
 struct BatchItem {
     int32_t field, u0, u1, pad;
 };
-// Largest field and level count the batched kernel takes (others go through
-// the single-field path).
+// A volume of a 3D batched launch (tiles of kTile3DX x kTile3DY x kTile3DZ).
+struct BatchField3D {
+    const void *data;
+    int64_t d, h, w;
+    int64_t *out[4];      // ec, perimeter (crease), area (surface), volume; NULL = not wanted
+    int32_t *hist;        // [4][L] per-level deltas; zero between launches
+    uint32_t *done;       // items of this field finished; zero between launches
+    const float *thr;     // LM_AFFINE / LM_SEARCH thresholds (device)
+    const uint16_t *lut;  // LM_LUT level table (device)
+    int32_t L, n_items, conn_idx;  // conn_idx 0 = 26-C, 1 = 6-C
+    uint32_t neg;                  // LevelArgs::neg
+    float u0, inv_step, eps;       // LM_AFFINE
+    int32_t tiles_x, tiles_y, pad;
+};
+// Largest field and level count the batched kernels take (others go through
+// the single-field path); volumes above kBatch3DMaxCells give the single-field
+// kernels enough work on their own.
 constexpr int64_t kBatchMaxCells = int64_t(1) << 28;
+constexpr int64_t kBatch3DMaxCells = int64_t(1) << 22;
 constexpr int kBatchMaxLevels = 4096;
 // Items of workgroup g are items[wg_first[g] .. wg_first[g+1]).
 int launch_batch_2d(int dtype, int lm, const BatchField2D *fields, const BatchItem *items,
                     const int32_t *wg_first, int grid, const uint64_t *luts, int max_L, void *stream);
 size_t lds_bytes_batch_2d(int lm, int max_L);
+// vt3: [2][256] per-octant tables, 26-C then 6-C
+int launch_batch_3d(int dtype, int lm, const BatchField3D *fields, const BatchItem *items,
+                    const int32_t *wg_first, int grid, const int64_t *vt3, int max_L, void *stream);
+size_t lds_bytes_batch_3d(int max_L);
 
 // device-side launchers (ecc_k2d.hip, ecc_k3d.hip, ecc_kmerge.hip); return a hipError_t as int
 int launch_2d(const Launch2D &a, void *stream);

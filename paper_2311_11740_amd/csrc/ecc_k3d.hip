@@ -587,9 +587,109 @@ __device__ __forceinline__ void drain_cls3(int32_t *hcls, int W, int lo, int L, 
 // ---------------------------------------------------------------------------
 // 3D (generic: every channel, table lookups over the 8 corner blocks)
 // ---------------------------------------------------------------------------
-// MODE 0: EC, surface, volume; 1: also the crease; 2: vertex class counts
-// (vtab then holds the class of each octant mask, -1 for empty, and each
-// corner adds +1 to its new class and -1 to its old one in the cell's bin).
+// One tile of TX x TY x TZ voxels: its levels and a one-voxel halo are staged
+// into LDS, then each of the 256 threads walks its (x, y) column up the
+// tile's planes with a 3x3x3 window.  MODE 0: EC, surface, volume; 1: also
+// the crease; 2: vertex class counts (vt then holds the class of each octant
+// mask, -1 for empty, and each corner adds +1 to its new class and -1 to its
+// old one in the cell's bin).  Cells whose level is outside the window
+// [lo, lo + W) add nothing.  Starts and ends with the workgroup in step.
+typedef uint16_t TileLevels[kTile3DZ + 2][kTile3DY + 2][kTile3DX + 2];
+
+template <typename T, int LM, int MODE>
+__device__ __forceinline__ void tile_3d(const T *__restrict__ data, int64_t d, int64_t h, int64_t w,
+                                        const LevelArgs &lv, int lo, int W, const int64_t *vt, TileLevels &lam,
+                                        uint64_t *hist, uint32_t *hc, int32_t *hcls, int64_t x0, int64_t y0,
+                                        int64_t z0) {
+    constexpr bool CREASE = MODE == 1;
+    constexpr int TX = kTile3DX, TY = kTile3DY, TZ = kTile3DZ;
+    constexpr int SX = TX + 2, SY = TY + 2, SZ = TZ + 2;
+    const int t = threadIdx.x;
+    const int L = lv.L;
+    const int lx = t % TX, ly = t / TX;
+    for (int e = t; e < SZ * SY * SX; e += 256) {
+        const int xx = e % SX, rest = e / SX;
+        const int yy = rest % SY, zz = rest / SY;
+        const int64_t x = x0 - 1 + xx, y = y0 - 1 + yy, z = z0 - 1 + zz;
+        uint32_t l = (uint32_t)L;
+        if (x >= 0 && x < w && y >= 0 && y < h && z >= 0 && z < d)
+            l = level_of<T, LM>(data[(z * h + y) * w + x], lv, ThrGlobal{lv.thr});
+        lam[zz][yy][xx] = (uint16_t)l;
+    }
+    __syncthreads();
+    if (x0 + lx < w && y0 + ly < h) {
+        // 3x3x3 window: win[k], k = (dz+1)*9 + (dy+1)*3 + (dx+1)
+        uint32_t win[27];
+#pragma unroll
+        for (int pz = 0; pz < 2; ++pz)
+#pragma unroll
+            for (int dy = 0; dy < 3; ++dy)
+#pragma unroll
+                for (int dx = 0; dx < 3; ++dx) win[9 + pz * 9 + dy * 3 + dx] = lam[pz][ly + dy][lx + dx];
+        const int planes = (int)(d - z0 < TZ ? d - z0 : TZ);
+        for (int z = 0; z < planes; ++z) {
+#pragma unroll
+            for (int k = 0; k < 18; ++k) win[k] = win[k + 9];
+#pragma unroll
+            for (int dy = 0; dy < 3; ++dy)
+#pragma unroll
+                for (int dx = 0; dx < 3; ++dx) win[18 + dy * 3 + dx] = lam[z + 2][ly + dy][lx + dx];
+            const uint32_t p = win[13];
+            if (p - (uint32_t)lo >= (uint32_t)W) continue;
+            // bit k set when neighbour k entered before p (earlier in memory
+            // order wins ties); the centre bit stands for p itself
+            uint32_t P = 1u << 13;
+#pragma unroll
+            for (int k = 0; k < 27; ++k) {
+                if (k == 13) continue;
+                const bool pr = k < 13 ? (win[k] <= p) : (win[k] < p);
+                P |= (uint32_t)pr << k;
+            }
+            // corner (cz,cy,cx) of p: its 2x2x2 block holds the neighbours
+            // with offsets in {c-1, c} per axis; gather them into the
+            // octant mask (bit bx + 2by + 4bz), with and without p
+            if constexpr (MODE == 2) {
+                int32_t *row = hcls + (p - lo) * kNumClasses3D;
+#pragma unroll
+                for (int c = 0; c < 8; ++c) {
+                    const int cx = c & 1, cy = c >> 1 & 1, cz = c >> 2;
+                    const uint32_t y = P >> (cz * 9 + cy * 3 + cx);
+                    const uint32_t m1 = (y & 3u) | ((y >> 1) & 0xCu) | ((y >> 5) & 0x30u) | ((y >> 6) & 0xC0u);
+                    const uint32_t m0 = m1 & ~(1u << (7 - c));
+                    const int cn = (int)vt[m1], co = (int)vt[m0];
+                    atomicAdd(&row[cn], 1);
+                    if (co >= 0) atomicAdd(&row[co], -1);
+                }
+                continue;
+            } else {
+                int64_t acc = 0;
+#pragma unroll
+                for (int c = 0; c < 8; ++c) {
+                    const int cx = c & 1, cy = c >> 1 & 1, cz = c >> 2;
+                    const uint32_t y = P >> (cz * 9 + cy * 3 + cx);
+                    const uint32_t m1 = (y & 3u) | ((y >> 1) & 0xCu) | ((y >> 5) & 0x30u) | ((y >> 6) & 0xC0u);
+                    const uint32_t m0 = m1 & ~(1u << (7 - c));
+                    acc += vt[m1] - vt[m0];
+                }
+                // four signed 16-bit fields, each eight times the cell's delta
+                const int64_t f0 = (int16_t)(acc & 0xFFFF);
+                acc = (acc - f0) >> 16;
+                const int64_t f1 = (int16_t)(acc & 0xFFFF);
+                acc = (acc - f1) >> 16;
+                const int64_t f2 = (int16_t)(acc & 0xFFFF);
+                const int64_t ec = f0 >> 3, cr = f1 >> 3, surf = f2 >> 3;
+                // (the volume field is 1 for every cell: it is the count field)
+                const uint64_t word = (uint64_t)(ec + kEcBias3) |
+                                      (uint64_t)(surf + kSurfBias3) << kShiftSurf3 |
+                                      1ull << kShiftCnt3;
+                atomicAdd((unsigned long long *)&hist[p - lo], (unsigned long long)word);
+                if (CREASE) atomicAdd(&hc[p - lo], (uint32_t)(cr + kCreaseBias3));
+            }
+        }
+    }
+    __syncthreads();
+}
+
 template <typename T, int LM, int MODE>
 __global__ void __launch_bounds__(256)
     ecc3d_tile(const T *__restrict__ data, int64_t d, int64_t h, int64_t w, LevelArgs lv,
@@ -597,11 +697,9 @@ __global__ void __launch_bounds__(256)
                int32_t *__restrict__ partial, int64_t tiles_x, int64_t tiles_y, int64_t n_tiles,
                int flush_tiles) {
     constexpr bool CREASE = MODE == 1;
-    constexpr int TX = kTile3DX, TY = kTile3DY, TZ = kTile3DZ;
-    constexpr int SX = TX + 2, SY = TY + 2, SZ = TZ + 2;
     extern __shared__ uint64_t smem[];
     __shared__ int64_t vt[256];
-    __shared__ uint16_t lam[SZ][SY][SX];
+    __shared__ TileLevels lam;
 
     const int t = threadIdx.x;
     const int W = hi - lo;
@@ -624,94 +722,13 @@ __global__ void __launch_bounds__(256)
     }
     bool first = true;
     int since = 0;
-    const int lx = t % TX, ly = t / TX;
     __syncthreads();
 
     for (int64_t tile = t_beg; tile < t_end; ++tile) {
-        const int64_t x0 = (tile % tiles_x) * TX;
-        const int64_t y0 = ((tile / tiles_x) % tiles_y) * TY;
-        const int64_t z0 = (tile / (tiles_x * tiles_y)) * TZ;
-        for (int e = t; e < SZ * SY * SX; e += 256) {
-            const int xx = e % SX, rest = e / SX;
-            const int yy = rest % SY, zz = rest / SY;
-            const int64_t x = x0 - 1 + xx, y = y0 - 1 + yy, z = z0 - 1 + zz;
-            uint32_t l = (uint32_t)L;
-            if (x >= 0 && x < w && y >= 0 && y < h && z >= 0 && z < d)
-                l = level_of<T, LM>(data[(z * h + y) * w + x], lv, ThrGlobal{lv.thr});
-            lam[zz][yy][xx] = (uint16_t)l;
-        }
-        __syncthreads();
-        if (x0 + lx < w && y0 + ly < h) {
-            // 3x3x3 window: win[k], k = (dz+1)*9 + (dy+1)*3 + (dx+1)
-            uint32_t win[27];
-#pragma unroll
-            for (int pz = 0; pz < 2; ++pz)
-#pragma unroll
-                for (int dy = 0; dy < 3; ++dy)
-#pragma unroll
-                    for (int dx = 0; dx < 3; ++dx) win[9 + pz * 9 + dy * 3 + dx] = lam[pz][ly + dy][lx + dx];
-            const int planes = (int)(d - z0 < TZ ? d - z0 : TZ);
-            for (int z = 0; z < planes; ++z) {
-#pragma unroll
-                for (int k = 0; k < 18; ++k) win[k] = win[k + 9];
-#pragma unroll
-                for (int dy = 0; dy < 3; ++dy)
-#pragma unroll
-                    for (int dx = 0; dx < 3; ++dx) win[18 + dy * 3 + dx] = lam[z + 2][ly + dy][lx + dx];
-                const uint32_t p = win[13];
-                if (p - (uint32_t)lo >= (uint32_t)W) continue;
-                // bit k set when neighbour k entered before p (earlier in memory
-                // order wins ties); the centre bit stands for p itself
-                uint32_t P = 1u << 13;
-#pragma unroll
-                for (int k = 0; k < 27; ++k) {
-                    if (k == 13) continue;
-                    const bool pr = k < 13 ? (win[k] <= p) : (win[k] < p);
-                    P |= (uint32_t)pr << k;
-                }
-                // corner (cz,cy,cx) of p: its 2x2x2 block holds the neighbours
-                // with offsets in {c-1, c} per axis; gather them into the
-                // octant mask (bit bx + 2by + 4bz), with and without p
-                if constexpr (MODE == 2) {
-                    int32_t *row = hcls + (p - lo) * kNumClasses3D;
-#pragma unroll
-                    for (int c = 0; c < 8; ++c) {
-                        const int cx = c & 1, cy = c >> 1 & 1, cz = c >> 2;
-                        const uint32_t y = P >> (cz * 9 + cy * 3 + cx);
-                        const uint32_t m1 = (y & 3u) | ((y >> 1) & 0xCu) | ((y >> 5) & 0x30u) | ((y >> 6) & 0xC0u);
-                        const uint32_t m0 = m1 & ~(1u << (7 - c));
-                        const int cn = (int)vt[m1], co = (int)vt[m0];
-                        atomicAdd(&row[cn], 1);
-                        if (co >= 0) atomicAdd(&row[co], -1);
-                    }
-                    continue;
-                }
-                int64_t acc = 0;
-#pragma unroll
-                for (int c = 0; c < 8; ++c) {
-                    const int cx = c & 1, cy = c >> 1 & 1, cz = c >> 2;
-                    const uint32_t y = P >> (cz * 9 + cy * 3 + cx);
-                    const uint32_t m1 = (y & 3u) | ((y >> 1) & 0xCu) | ((y >> 5) & 0x30u) | ((y >> 6) & 0xC0u);
-                    const uint32_t m0 = m1 & ~(1u << (7 - c));
-                    acc += vt[m1] - vt[m0];
-                }
-                // four signed 16-bit fields, each eight times the cell's delta
-                const int64_t f0 = (int16_t)(acc & 0xFFFF);
-                acc = (acc - f0) >> 16;
-                const int64_t f1 = (int16_t)(acc & 0xFFFF);
-                acc = (acc - f1) >> 16;
-                const int64_t f2 = (int16_t)(acc & 0xFFFF);
-                const int64_t f3 = (acc - f2) >> 16;
-                const int64_t ec = f0 >> 3, cr = f1 >> 3, surf = f2 >> 3;
-                (void)f3;  // volume delta is 1 for every cell; it is the count field
-                const uint64_t word = (uint64_t)(ec + kEcBias3) |
-                                      (uint64_t)(surf + kSurfBias3) << kShiftSurf3 |
-                                      1ull << kShiftCnt3;
-                atomicAdd((unsigned long long *)&hist[p - lo], (unsigned long long)word);
-                if (CREASE) atomicAdd(&hc[p - lo], (uint32_t)(cr + kCreaseBias3));
-            }
-        }
-        __syncthreads();
+        const int64_t x0 = (tile % tiles_x) * kTile3DX;
+        const int64_t y0 = ((tile / tiles_x) % tiles_y) * kTile3DY;
+        const int64_t z0 = (tile / (tiles_x * tiles_y)) * kTile3DZ;
+        tile_3d<T, LM, MODE>(data, d, h, w, lv, lo, W, vt, lam, hist, hc, hcls, x0, y0, z0);
         if (++since >= flush_tiles) {
             if constexpr (MODE == 2)
                 drain_cls3(hcls, W, lo, L, G, wg, partial, first);
@@ -729,9 +746,161 @@ __global__ void __launch_bounds__(256)
 }
 
 // ---------------------------------------------------------------------------
+// 3D batched: many volumes in one persistent launch
+// ---------------------------------------------------------------------------
+// The host cuts every volume into items of whole tiles and deals them to
+// workgroups (as for 2D fields).  A workgroup runs an item's tiles with the
+// generic kernel's tile pass into LDS bins over all of the field's levels
+// (at most kBatchMaxLevels, one pass), adds the bins into the field's int32
+// histogram [ec, crease, surface, count][L] with device atomics, and takes the
+// field's ticket; the workgroup that finishes the last item scans the
+// histogram into the curves and clears it and the ticket for the next launch.
+template <typename T, int LM>
+__global__ void __launch_bounds__(256)
+    ecc3d_batch(const BatchField3D *__restrict__ fields, const BatchItem *__restrict__ items,
+                const int32_t *__restrict__ wg_first, const int64_t *__restrict__ vt3) {
+    extern __shared__ uint64_t smem[];
+    __shared__ int64_t vt[2][256];
+    __shared__ TileLevels lam;
+    __shared__ int64_t part[256];
+    __shared__ int last;
+    const int tid = threadIdx.x;
+    vt[0][tid] = vt3[tid];
+    vt[1][tid] = vt3[256 + tid];
+    const int i_beg = wg_first[blockIdx.x], i_end = wg_first[blockIdx.x + 1];
+    for (int it = i_beg; it < i_end; ++it) {
+        const BatchItem item = items[it];
+        const BatchField3D &f = fields[item.field];
+        const int L = f.L;
+        const bool crease = f.out[1] != nullptr;
+        uint64_t *hist = smem;
+        uint32_t *hc = reinterpret_cast<uint32_t *>(smem + L);
+        for (int b = tid; b < L; b += 256) {
+            hist[b] = 0;
+            hc[b] = 0u;
+        }
+        __syncthreads();
+        LevelArgs lv;
+        lv.L = L;
+        lv.mode = LM;
+        lv.thr = f.thr;
+        lv.lut = f.lut;
+        lv.u0 = f.u0;
+        lv.inv_step = f.inv_step;
+        lv.u0d = 0.0;
+        lv.eps = f.eps;
+        lv.neg = f.neg;
+        const int64_t *vtab = vt[f.conn_idx];
+        for (int tile = item.u0; tile < item.u1; ++tile) {
+            const int64_t x0 = (int64_t)(tile % f.tiles_x) * kTile3DX;
+            const int64_t y0 = (int64_t)((tile / f.tiles_x) % f.tiles_y) * kTile3DY;
+            const int64_t z0 = (int64_t)(tile / (f.tiles_x * f.tiles_y)) * kTile3DZ;
+            if (crease)  // uniform
+                tile_3d<T, LM, 1>((const T *)f.data, f.d, f.h, f.w, lv, 0, L, vtab, lam, hist, hc, nullptr, x0,
+                                  y0, z0);
+            else
+                tile_3d<T, LM, 0>((const T *)f.data, f.d, f.h, f.w, lv, 0, L, vtab, lam, hist, hc, nullptr, x0,
+                                  y0, z0);
+        }
+        // bins -> the field's histogram (channels in curve order: ec, crease, surface, count)
+        for (int b = tid; b < L; b += 256) {
+            const uint64_t v = hist[b];
+            const int64_t n = (int64_t)(v >> kShiftCnt3);
+            if (n == 0) continue;
+            const int64_t surf = (int64_t)((v >> kShiftSurf3) & ((1ull << (kShiftCnt3 - kShiftSurf3)) - 1)) -
+                                 kSurfBias3 * n;
+            const int64_t ec = (int64_t)(v & ((1ull << kShiftSurf3) - 1)) - kEcBias3 * n;
+            int32_t *dst = f.hist + b;
+            if (ec) atomicAdd(dst, (int32_t)ec);
+            if (crease) {
+                const int64_t cr = (int64_t)hc[b] - kCreaseBias3 * n;
+                if (cr) atomicAdd(dst + L, (int32_t)cr);
+            }
+            if (surf) atomicAdd(dst + 2 * L, (int32_t)surf);
+            atomicAdd(dst + 3 * L, (int32_t)n);
+        }
+        // publish (every thread's atomics), take the field's ticket
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        __syncthreads();
+        if (tid == 0)
+            last = __hip_atomic_fetch_add(f.done, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT) ==
+                   (uint32_t)(f.n_items - 1);
+        __syncthreads();
+        if (last) {  // uniform: scan the field's histogram into its curves and clear it
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            const int per = (L + 255) / 256;
+            const int beg = tid * per, end = beg + per < L ? beg + per : L;
+            for (int ch = 0; ch < 4; ++ch) {
+                int32_t *src = f.hist + (int64_t)ch * L;
+                int64_t *dst = f.out[ch];
+                int64_t s = 0;
+                for (int i = beg; i < end; ++i) s += src[i];
+                part[tid] = s;
+                __syncthreads();
+                for (int off = 1; off < 256; off <<= 1) {  // inclusive scan of the chunk sums
+                    const int64_t v = tid >= off ? part[tid - off] : 0;
+                    __syncthreads();
+                    part[tid] += v;
+                    __syncthreads();
+                }
+                int64_t run = part[tid] - s;
+                for (int i = beg; i < end; ++i) {
+                    run += src[i];
+                    src[i] = 0;
+                    if (dst) dst[i] = run;
+                }
+                __syncthreads();
+            }
+            if (tid == 0) *f.done = 0u;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
 size_t lds_bytes_3d(int window, bool want_crease) { return (size_t)window * (want_crease ? 12 : 8); }
+
+size_t lds_bytes_batch_3d(int max_L) { return (size_t)max_L * 12; }
+
+template <typename T>
+static int launch_batch3_t(int lm, const BatchField3D *fields, const BatchItem *items, const int32_t *wg_first,
+                           int grid, const int64_t *vt3, size_t lds, hipStream_t s) {
+    switch (lm) {
+    case LM_IDENTITY:
+        if constexpr (sizeof(T) < 4)
+            hipLaunchKernelGGL((ecc3d_batch<T, LM_IDENTITY>), dim3(grid), dim3(256), lds, s, fields, items, wg_first,
+                               vt3);
+        break;
+    case LM_LUT:
+        if constexpr (sizeof(T) < 4)
+            hipLaunchKernelGGL((ecc3d_batch<T, LM_LUT>), dim3(grid), dim3(256), lds, s, fields, items, wg_first, vt3);
+        break;
+    case LM_AFFINE:
+        if constexpr (sizeof(T) == 4)
+            hipLaunchKernelGGL((ecc3d_batch<T, LM_AFFINE>), dim3(grid), dim3(256), lds, s, fields, items, wg_first,
+                               vt3);
+        break;
+    default:
+        if constexpr (sizeof(T) == 4)
+            hipLaunchKernelGGL((ecc3d_batch<T, LM_SEARCH>), dim3(grid), dim3(256), lds, s, fields, items, wg_first,
+                               vt3);
+        break;
+    }
+    return (int)hipGetLastError();
+}
+
+int launch_batch_3d(int dtype, int lm, const BatchField3D *fields, const BatchItem *items,
+                    const int32_t *wg_first, int grid, const int64_t *vt3, int max_L, void *stream) {
+    const size_t lds = lds_bytes_batch_3d(max_L);
+    hipStream_t s = (hipStream_t)stream;
+    if ((dtype == ECC_F32) != (lm == LM_AFFINE || lm == LM_SEARCH)) return (int)hipErrorInvalidValue;
+    switch (dtype) {
+    case ECC_U8: return launch_batch3_t<uint8_t>(lm, fields, items, wg_first, grid, vt3, lds, s);
+    case ECC_U16: return launch_batch3_t<uint16_t>(lm, fields, items, wg_first, grid, vt3, lds, s);
+    default: return launch_batch3_t<float>(lm, fields, items, wg_first, grid, vt3, lds, s);
+    }
+}
 
 template <typename T, int LM, int MODE>
 static int launch_3d_t(const Launch3D &a, hipStream_t s) {

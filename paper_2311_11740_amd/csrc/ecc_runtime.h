@@ -159,11 +159,19 @@ ecc_status acc_buffer(ecc_context ctx, int nch, int L, int64_t **acc, void *stre
 struct SchedField {
     int32_t slot;  // descriptor index the items refer to
     int64_t h, w;
+    int64_t d = 1;
 };
-bool batchable(const FieldInfo &fi);
+// the batched kernel that takes a field: 2, 3, or 0 for the single-field path
+int batch_kind(const FieldInfo &fi);
+bool batchable(const FieldInfo &fi);  // batch_kind(fi) != 0
 int schedule_batch_2d(int n_cu, int dtype, int lm, int max_L, const std::vector<SchedField> &fields,
                       int item_cells, int wg_per_cu, std::vector<BatchItem> &sorted, std::vector<int32_t> &first,
                       std::vector<int32_t> &n_items);
+int schedule_batch_3d(int n_cu, int max_L, const std::vector<SchedField> &fields, int item_cells, int wg_per_cu,
+                      std::vector<BatchItem> &sorted, std::vector<int32_t> &first, std::vector<int32_t> &n_items);
+// a field's batched-kernel descriptor without its histogram, ticket and item count
+void fill_desc_2d(BatchField2D &d, const ecc_field &f, const ecc_curves &c, const FieldInfo &fi, const LevelArgs &lv);
+void fill_desc_3d(BatchField3D &d, const ecc_field &f, const ecc_curves &c, const FieldInfo &fi, const LevelArgs &lv);
 // records the start event of a timed launch on `stream` (no-op unless profiling)
 ecc_status prof_begin(ecc_context ctx, void *stream, int *slot);
 ecc_status prof_end(ecc_context ctx, void *stream, int slot);

@@ -11,9 +11,9 @@
 // Work.  The submitting thread stages the field in its pinned range (large
 // fields with several copy threads).  A worker thread copies staged fields to
 // the device on a copy stream and launches every request whose copy has
-// landed, all at once: the 2D requests
-// the batched kernel takes go into one launch of that kernel (as many as are
-// ready, up to max_batch), the others (3D, more than 4096 levels) run the
+// landed, all at once: the 2D fields and the small volumes the batched
+// kernels take go into one launch of those kernels (as many as are ready, up
+// to max_batch), the others (large volumes, more than 4096 levels) run the
 // single-field path on a second compute stream; results come back to pinned
 // memory and then to the caller's arrays.  Requests submitted while earlier
 // ones are on the GPU are copied meanwhile and join the next launch, so
@@ -28,6 +28,7 @@
 #include <deque>
 #include <map>
 #include <thread>
+#include <tuple>
 #include <unordered_map>
 #include <vector>
 
@@ -110,15 +111,17 @@ struct ecc_server_s {
     char *d_arena = nullptr, *h_arena = nullptr;
     Arena dev;
     std::vector<int> free_slots;
-    int32_t *d_hist = nullptr;  // [slots][3][kBatchMaxLevels]
+    int32_t *d_hist = nullptr;  // [slots][4][kBatchMaxLevels]
     uint32_t *d_done = nullptr;  // [slots]
     uint64_t *d_luts = nullptr;  // [2][256]
+    int64_t *d_vt3 = nullptr;    // [2][256]
     // per-launch schedule buffers (device + pinned), reused once their launch is done
     struct Launch {
         BatchField2D *d_desc = nullptr, *h_desc = nullptr;
+        BatchField3D *d_desc3 = nullptr, *h_desc3 = nullptr;
         BatchItem *d_items = nullptr, *h_items = nullptr;
         int32_t *d_first = nullptr, *h_first = nullptr;
-        size_t cap_desc = 0, cap_items = 0, cap_first = 0;
+        size_t cap_desc = 0, cap_desc3 = 0, cap_items = 0, cap_first = 0;
         hipEvent_t done = nullptr;
         bool busy = false;
     };
@@ -245,35 +248,47 @@ ecc_status launch_ready(ecc_server srv, std::vector<std::pair<Request *, ecc_sta
         s = reserve_thresholds(ctx, (int)thr_fields.size(), thr_fields.data());
         for (size_t i = 0; i < batch2d.size() && s == ECC_OK; ++i)
             s = level_args(ctx, &batch2d[i]->field, batch2d[i]->fi, srv->s_2d, &lv[i]);
-        // group by (dtype, level mode); one schedule per group, items appended
-        std::map<std::pair<int, int>, std::vector<int>> groups;
-        for (size_t i = 0; i < batch2d.size(); ++i) groups[{batch2d[i]->fi.dtype, lv[i].mode}].push_back((int)i);
+        // group by (dimension, dtype, level mode); one schedule per group,
+        // items appended; a request's descriptor slot counts within its dimension
+        std::map<std::tuple<int, int, int>, std::vector<int>> groups;
+        std::vector<int> slot(batch2d.size());
+        int n2 = 0, n3 = 0;
+        for (size_t i = 0; i < batch2d.size(); ++i) {
+            const int kd = batch_kind(batch2d[i]->fi);
+            slot[i] = kd == 2 ? n2++ : n3++;
+            groups[std::make_tuple(kd, batch2d[i]->fi.dtype, lv[i].mode)].push_back((int)i);
+        }
         std::vector<BatchItem> all_items;
         std::vector<int32_t> all_first;
         struct G {
-            int dtype, lm, max_L, grid;
+            int kind, dtype, lm, max_L, grid;
             size_t item0, first0;
         };
         std::vector<G> gl;
         std::vector<int32_t> n_items_of(batch2d.size(), 0);
         for (auto &kv : groups) {
+            const int kd = std::get<0>(kv.first), dt = std::get<1>(kv.first), lm = std::get<2>(kv.first);
             std::vector<SchedField> sf;
             int max_L = 0;
             for (int i : kv.second) {
-                sf.push_back(SchedField{i, batch2d[i]->fi.h, batch2d[i]->fi.w});
-                max_L = std::max(max_L, batch2d[i]->fi.L);
+                const FieldInfo &f = batch2d[i]->fi;
+                sf.push_back(SchedField{slot[i], f.h, f.w, f.d});
+                max_L = std::max(max_L, f.L);
             }
             std::vector<BatchItem> items;
             std::vector<int32_t> first, n_items;
-            const int grid = schedule_batch_2d(ctx->n_cu, kv.first.first, kv.first.second, max_L, sf, 64 * 1024,
-                                               4, items, first, n_items);
-            for (size_t j = 0; j < sf.size(); ++j) n_items_of[sf[j].slot] = n_items[j];
-            gl.push_back(G{kv.first.first, kv.first.second, max_L, grid, all_items.size(), all_first.size()});
+            const int grid = kd == 2 ? schedule_batch_2d(ctx->n_cu, dt, lm, max_L, sf, 64 * 1024, 4, items, first,
+                                                         n_items)
+                                     : schedule_batch_3d(ctx->n_cu, max_L, sf, 64 * 1024, 4, items, first, n_items);
+            for (size_t j = 0; j < kv.second.size(); ++j) n_items_of[kv.second[j]] = n_items[j];
+            gl.push_back(G{kd, dt, lm, max_L, grid, all_items.size(), all_first.size()});
             all_items.insert(all_items.end(), items.begin(), items.end());
             all_first.insert(all_first.end(), first.begin(), first.end());
         }
-        if (s == ECC_OK) s = grow_pair((void **)&L.d_desc, (void **)&L.h_desc, &L.cap_desc,
-                                       sizeof(BatchField2D) * batch2d.size());
+        if (s == ECC_OK && n2)
+            s = grow_pair((void **)&L.d_desc, (void **)&L.h_desc, &L.cap_desc, sizeof(BatchField2D) * n2);
+        if (s == ECC_OK && n3)
+            s = grow_pair((void **)&L.d_desc3, (void **)&L.h_desc3, &L.cap_desc3, sizeof(BatchField3D) * n3);
         if (s == ECC_OK) s = grow_pair((void **)&L.d_items, (void **)&L.h_items, &L.cap_items,
                                        sizeof(BatchItem) * std::max<size_t>(1, all_items.size()));
         if (s == ECC_OK) s = grow_pair((void **)&L.d_first, (void **)&L.h_first, &L.cap_first,
@@ -281,38 +296,41 @@ ecc_status launch_ready(ecc_server srv, std::vector<std::pair<Request *, ecc_sta
         if (s == ECC_OK) {
             for (size_t i = 0; i < batch2d.size(); ++i) {
                 Request *r = batch2d[i];
-                BatchField2D &d = L.h_desc[i];
-                std::memset(&d, 0, sizeof(d));
                 const ecc_curves c = dev_curve_ptrs(srv, r);
-                d.data = r->field.data;
-                d.h = r->fi.h;
-                d.w = r->fi.w;
-                d.out[0] = c.ec;
-                d.out[1] = c.perimeter;
-                d.out[2] = c.area;
-                d.hist = srv->d_hist + (size_t)r->slot * 3 * kBatchMaxLevels;
-                d.done = srv->d_done + r->slot;
-                d.thr = lv[i].thr;
-                d.lut = lv[i].lut;
-                d.L = r->fi.L;
-                d.n_items = n_items_of[i];
-                d.conn_idx = r->fi.conn == 8 ? 0 : 1;
-                d.inv_step = lv[i].inv_step;
-                d.neg = lv[i].neg;
-                d.cpass = (float)(lv[i].u0d + kBinOff + 0.5);
-                d.eps = lv[i].eps;
+                int32_t *hist = srv->d_hist + (size_t)r->slot * 4 * kBatchMaxLevels;
+                if (batch_kind(r->fi) == 2) {
+                    BatchField2D &d = L.h_desc[slot[i]];
+                    fill_desc_2d(d, r->field, c, r->fi, lv[i]);
+                    d.hist = hist;
+                    d.done = srv->d_done + r->slot;
+                    d.n_items = n_items_of[i];
+                } else {
+                    BatchField3D &d = L.h_desc3[slot[i]];
+                    fill_desc_3d(d, r->field, c, r->fi, lv[i]);
+                    d.hist = hist;
+                    d.done = srv->d_done + r->slot;
+                    d.n_items = n_items_of[i];
+                }
             }
             std::memcpy(L.h_items, all_items.data(), sizeof(BatchItem) * all_items.size());
             std::memcpy(L.h_first, all_first.data(), sizeof(int32_t) * all_first.size());
-            int e = (int)hipMemcpyAsync(L.d_desc, L.h_desc, sizeof(BatchField2D) * batch2d.size(),
-                                        hipMemcpyHostToDevice, srv->s_2d);
+            int e = 0;
+            if (n2)
+                e = (int)hipMemcpyAsync(L.d_desc, L.h_desc, sizeof(BatchField2D) * n2, hipMemcpyHostToDevice,
+                                        srv->s_2d);
+            if (!e && n3)
+                e = (int)hipMemcpyAsync(L.d_desc3, L.h_desc3, sizeof(BatchField3D) * n3, hipMemcpyHostToDevice,
+                                        srv->s_2d);
             if (!e) e = (int)hipMemcpyAsync(L.d_items, L.h_items, sizeof(BatchItem) * all_items.size(),
                                             hipMemcpyHostToDevice, srv->s_2d);
             if (!e) e = (int)hipMemcpyAsync(L.d_first, L.h_first, sizeof(int32_t) * all_first.size(),
                                             hipMemcpyHostToDevice, srv->s_2d);
             for (size_t g = 0; g < gl.size() && !e; ++g)
-                e = launch_batch_2d(gl[g].dtype, gl[g].lm, L.d_desc, L.d_items + gl[g].item0,
-                                    L.d_first + gl[g].first0, gl[g].grid, srv->d_luts, gl[g].max_L, srv->s_2d);
+                e = gl[g].kind == 2
+                        ? launch_batch_2d(gl[g].dtype, gl[g].lm, L.d_desc, L.d_items + gl[g].item0,
+                                          L.d_first + gl[g].first0, gl[g].grid, srv->d_luts, gl[g].max_L, srv->s_2d)
+                        : launch_batch_3d(gl[g].dtype, gl[g].lm, L.d_desc3, L.d_items + gl[g].item0,
+                                          L.d_first + gl[g].first0, gl[g].grid, srv->d_vt3, gl[g].max_L, srv->s_2d);
             if (e) s = hip_fail(e, "serving batched launch");
             for (size_t i = 0; i < batch2d.size() && s == ECC_OK; ++i) {  // the launch reads these arrays
                 bool seen = false;
@@ -451,6 +469,8 @@ void release_server(ecc_server srv) {
     for (auto &L : srv->ring) {
         if (L.d_desc) hipFree(L.d_desc);
         if (L.h_desc) hipHostFree(L.h_desc);
+        if (L.d_desc3) hipFree(L.d_desc3);
+        if (L.h_desc3) hipHostFree(L.h_desc3);
         if (L.d_items) hipFree(L.d_items);
         if (L.h_items) hipHostFree(L.h_items);
         if (L.d_first) hipFree(L.d_first);
@@ -466,6 +486,7 @@ void release_server(ecc_server srv) {
     if (srv->d_hist) hipFree(srv->d_hist);
     if (srv->d_done) hipFree(srv->d_done);
     if (srv->d_luts) hipFree(srv->d_luts);
+    if (srv->d_vt3) hipFree(srv->d_vt3);
     if (srv->s_copy) hipStreamDestroy(srv->s_copy);
     if (srv->s_2d) hipStreamDestroy(srv->s_2d);
     if (srv->s_other) hipStreamDestroy(srv->s_other);
@@ -496,7 +517,7 @@ extern "C" ecc_status ecc_server_create(ecc_context ctx, const ecc_server_config
     e = (int)hipHostMalloc(&srv->h_arena, budget, 0);
     if (e) return bail(hip_fail(e, "hipHostMalloc(serving staging)"));
     srv->dev.init(budget);
-    const size_t hist = (size_t)cfg->max_slots * 3 * kBatchMaxLevels * sizeof(int32_t);
+    const size_t hist = (size_t)cfg->max_slots * 4 * kBatchMaxLevels * sizeof(int32_t);
     e = (int)hipMalloc(&srv->d_hist, hist);
     if (!e) e = (int)hipMalloc(&srv->d_done, (size_t)cfg->max_slots * sizeof(uint32_t));
     if (e) return bail(fail(ECC_ERR_OUT_OF_MEMORY, "hipMalloc(serving histograms) failed"));
@@ -504,8 +525,12 @@ extern "C" ecc_status ecc_server_create(ecc_context ctx, const ecc_server_config
     e = (int)hipMemset(srv->d_hist, 0, hist);
     if (!e) e = (int)hipMemset(srv->d_done, 0, (size_t)cfg->max_slots * sizeof(uint32_t));
     if (!e) e = (int)hipMalloc(&srv->d_luts, 2 * 256 * sizeof(uint64_t));
-    for (int k = 0; k < 2 && !e; ++k)
+    if (!e) e = (int)hipMalloc(&srv->d_vt3, 2 * 256 * sizeof(int64_t));
+    for (int k = 0; k < 2 && !e; ++k) {
         e = (int)hipMemcpy(srv->d_luts + 256 * k, ctx->d_delta2[k], 256 * sizeof(uint64_t), hipMemcpyDeviceToDevice);
+        if (!e)
+            e = (int)hipMemcpy(srv->d_vt3 + 256 * k, ctx->d_vtab3[k], 256 * sizeof(int64_t), hipMemcpyDeviceToDevice);
+    }
     if (!e) e = (int)hipDeviceSynchronize();
     if (e) return bail(hip_fail(e, "serving set-up"));
     e = (int)hipStreamCreateWithFlags(&srv->s_copy, hipStreamNonBlocking);

@@ -195,6 +195,19 @@ def batch_2d_u8(n: int = 4096, seed: int = 4, lo: int = 64, hi: int = 2048, work
             for k, (a, s) in enumerate(zip(data, sigmas))]
 
 
+def batch_3d_grids(n: int = 4096, side: int = 20, seed: int = 6, workers: int = 1):
+    """n uint8 volumes of side^3 voxels (smoothed GRFs, sigma ~ U[1, 3] voxels,
+    256 levels, 26-C): a stand-in for the paper's molecular-dynamics case, many
+    20 x 20 x 20 density grids translated to 0..255."""
+    ss = np.random.SeedSequence(seed).spawn(n)
+    rng = np.random.default_rng(seed + 1000)
+    sigmas = rng.uniform(1.0, 3.0, size=n)
+    data = _map(_quantised_grf, [((side, side, side), float(s), ss[k], 256) for k, s in enumerate(sigmas)],
+                workers)
+    return [FieldSpec(a, 256, None, 26, dict(name=f"grid{k}", sigma=float(s)))
+            for k, (a, s) in enumerate(zip(data, sigmas))]
+
+
 def serving_pool(n2d: int = 64, n3d: int = 32, seed: int = 5, max2d: int = 4096, max3d: int = 384,
                  workers: int = 1):
     """Pool of request fields: 2D uint8 (side log-uniform in [128, max2d], 256

@@ -1,11 +1,12 @@
 """Batched form: one call over many fields of uneven shapes.
 
 Each field's curves from the batched call must equal the oracle's and the
-single-field call's, bit for bit: for a mix the batched kernel takes (2D, any
-dtype and level mode, both connectivities) and one it hands to the
-single-field path (3D, more than 4096 levels, fields smaller than one vector
+single-field call's, bit for bit: for a mix the batched kernels take (2D, any
+dtype and level mode, both connectivities; small volumes) and one handed to
+the single-field path (more than 4096 levels, fields smaller than one vector
 load); on repeated calls (the captured graph replayed with new data, with
-other work between the calls); and after autotuning.
+other work between the calls); and after autotuning.  Volumes in more depth:
+test_gpu_batch3d.py.
 """
 from __future__ import annotations
 
@@ -97,7 +98,8 @@ def test_batch_mixed_kinds(ctx):
             specs.append((rng.normal(size=(h, w)).astype(np.float32), 77, thr_irr, conn))
         else:
             specs.append((rng.integers(0, 30, size=(h, w)).astype(np.uint8), 17, None, conn))
-    # single-field path: 3D, more than 4096 levels, smaller than one vector load
+    # small volumes (3D batched kernel), more than 4096 levels and smaller than
+    # one vector load (single-field path)
     specs.append((rng.integers(0, 40, size=(9, 20, 33)).astype(np.uint8), 36, None, 26))
     specs.append((rng.integers(0, 40, size=(7, 5, 300)).astype(np.uint16), 36, None, 6))
     specs.append((rng.integers(0, 9000, size=(50, 70)).astype(np.uint16), 9000, None, 8))
