@@ -176,7 +176,9 @@ struct BatchField2D {
 struct BatchItem {
     int32_t field, u0, u1, pad;
 };
-// A volume of a 3D batched launch (tiles of kTile3DX x kTile3DY x kTile3DZ).
+// A volume of a 3D batched launch, cut into tiles of tx x ty x tz voxels
+// chosen per volume (tile_shape_3d), whose levels plus a one-voxel halo fit
+// in kBatch3DTileElems LDS slots.
 struct BatchField3D {
     const void *data;
     int64_t d, h, w;
@@ -188,8 +190,11 @@ struct BatchField3D {
     int32_t L, n_items, conn_idx;  // conn_idx 0 = 26-C, 1 = 6-C
     uint32_t neg;                  // LevelArgs::neg
     float u0, inv_step, eps;       // LM_AFFINE
-    int32_t tiles_x, tiles_y, pad;
+    int32_t tiles_x, tiles_y;      // tiles along x and y
+    int32_t tx, ty, tz;            // tile shape
+    int32_t pad;
 };
+constexpr int kBatch3DTileElems = 12288;
 // Largest field and level count the batched kernels take (others go through
 // the single-field path); volumes above kBatch3DMaxCells give the single-field
 // kernels enough work on their own.

@@ -748,21 +748,152 @@ __global__ void __launch_bounds__(256)
 // ---------------------------------------------------------------------------
 // 3D batched: many volumes in one persistent launch
 // ---------------------------------------------------------------------------
-// The host cuts every volume into items of whole tiles and deals them to
-// workgroups (as for 2D fields).  A workgroup runs an item's tiles with the
-// generic kernel's tile pass into LDS bins over all of the field's levels
-// (at most kBatchMaxLevels, one pass), adds the bins into the field's int32
-// histogram [ec, crease, surface, count][L] with device atomics, and takes the
-// field's ticket; the workgroup that finishes the last item scans the
-// histogram into the curves and clears it and the ticket for the next launch.
+// q = floor(e / n) for 0 <= e < 2^15 and 1 <= n <= 2^15, from r = 1/n in
+// float32: (e + 0.5) r lies at least 0.5/n from an integer and its rounding
+// error is below 2^-8 of that
+__device__ __forceinline__ int small_div(int e, float r) { return (int)(((float)e + 0.5f) * r); }
+
+// One tile of tx x ty x tz voxels (shape chosen per volume): its levels and a
+// one-voxel halo are staged into `lam` ((tx+2) x (ty+2) x (planes+2) slots),
+// then the threads take the tile's (x, y) columns in rounds of 256 and walk
+// each up the planes with a 3x3x3 window, as in the generic tile pass.
+// Starts and ends with the workgroup in step.
+template <typename T, int LM, bool CREASE>
+__device__ __forceinline__ void tile_3d_flex(const T *__restrict__ data, int64_t d, int64_t h, int64_t w,
+                                             const LevelArgs &lv, const int64_t *vt, uint16_t *lam,
+                                             uint64_t *hist, uint32_t *hc, int64_t x0, int64_t y0, int64_t z0,
+                                             int tx, int ty, int tz) {
+    const int t = threadIdx.x;
+    const int L = lv.L;
+    const int sx = tx + 2, sy = ty + 2;
+    const int planes = (int)(d - z0 < tz ? d - z0 : tz);
+    const int n_st = sx * sy * (planes + 2);
+    const float rsx = 1.0f / (float)sx, rsy = 1.0f / (float)sy, rtx = 1.0f / (float)tx;
+    for (int e = t; e < n_st; e += 256) {
+        const int row = small_div(e, rsx), xx = e - row * sx;
+        const int zz = small_div(row, rsy), yy = row - zz * sy;
+        const int64_t x = x0 - 1 + xx, y = y0 - 1 + yy, z = z0 - 1 + zz;
+        uint32_t l = (uint32_t)L;
+        if (x >= 0 && x < w && y >= 0 && y < h && z >= 0 && z < d)
+            l = level_of<T, LM>(data[(z * h + y) * w + x], lv, ThrGlobal{lv.thr});
+        lam[e] = (uint16_t)l;
+    }
+    __syncthreads();
+    const int ps = sx * sy;  // plane stride
+    for (int c = t; c < tx * ty; c += 256) {
+        const int ly = small_div(c, rtx), lx = c - ly * tx;
+        if (x0 + lx >= w || y0 + ly >= h) continue;
+        const uint16_t *col = lam + ly * sx + lx;  // (dx, dy) = (-1, -1) corner of the column in plane 0
+        uint32_t win[27];
+#pragma unroll
+        for (int pz = 0; pz < 2; ++pz)
+#pragma unroll
+            for (int dy = 0; dy < 3; ++dy)
+#pragma unroll
+                for (int dx = 0; dx < 3; ++dx) win[9 + pz * 9 + dy * 3 + dx] = col[pz * ps + dy * sx + dx];
+        for (int z = 0; z < planes; ++z) {
+#pragma unroll
+            for (int k = 0; k < 18; ++k) win[k] = win[k + 9];
+            const uint16_t *pl = col + (z + 2) * ps;
+#pragma unroll
+            for (int dy = 0; dy < 3; ++dy)
+#pragma unroll
+                for (int dx = 0; dx < 3; ++dx) win[18 + dy * 3 + dx] = pl[dy * sx + dx];
+            const uint32_t p = win[13];
+            if (p >= (uint32_t)L) continue;
+            uint32_t P = 1u << 13;
+#pragma unroll
+            for (int k = 0; k < 27; ++k) {
+                if (k == 13) continue;
+                const bool pr = k < 13 ? (win[k] <= p) : (win[k] < p);
+                P |= (uint32_t)pr << k;
+            }
+            int64_t acc = 0;
+#pragma unroll
+            for (int cc = 0; cc < 8; ++cc) {
+                const int cx = cc & 1, cy = cc >> 1 & 1, cz = cc >> 2;
+                const uint32_t y = P >> (cz * 9 + cy * 3 + cx);
+                const uint32_t m1 = (y & 3u) | ((y >> 1) & 0xCu) | ((y >> 5) & 0x30u) | ((y >> 6) & 0xC0u);
+                const uint32_t m0 = m1 & ~(1u << (7 - cc));
+                acc += vt[m1] - vt[m0];
+            }
+            const int64_t f0 = (int16_t)(acc & 0xFFFF);
+            acc = (acc - f0) >> 16;
+            const int64_t f1 = (int16_t)(acc & 0xFFFF);
+            acc = (acc - f1) >> 16;
+            const int64_t f2 = (int16_t)(acc & 0xFFFF);
+            const int64_t ec = f0 >> 3, cr = f1 >> 3, surf = f2 >> 3;
+            const uint64_t word = (uint64_t)(ec + kEcBias3) | (uint64_t)(surf + kSurfBias3) << kShiftSurf3 |
+                                  1ull << kShiftCnt3;
+            atomicAdd((unsigned long long *)&hist[p], (unsigned long long)word);
+            if (CREASE) atomicAdd(&hc[p], (uint32_t)(cr + kCreaseBias3));
+        }
+    }
+    __syncthreads();
+}
+
+// Running sums over the L levels of a workgroup's LDS bins straight into the
+// field's curves (a field done by one item needs no global histogram).
+__device__ __forceinline__ void scan_bins_3d(const uint64_t *hist, const uint32_t *hc, bool crease, int L,
+                                             int64_t *const out[4], int64_t (*part)[256]) {
+    const int tid = threadIdx.x;
+    const int per = (L + 255) / 256;
+    const int beg = tid * per, end = beg + per < L ? beg + per : L;
+    int64_t s[4] = {0, 0, 0, 0};
+    for (int i = beg; i < end; ++i) {
+        const uint64_t v = hist[i];
+        const int64_t n = (int64_t)(v >> kShiftCnt3);
+        s[0] += (int64_t)(v & ((1ull << kShiftSurf3) - 1)) - kEcBias3 * n;
+        if (crease) s[1] += (int64_t)hc[i] - kCreaseBias3 * n;
+        s[2] += (int64_t)((v >> kShiftSurf3) & ((1ull << (kShiftCnt3 - kShiftSurf3)) - 1)) - kSurfBias3 * n;
+        s[3] += n;
+    }
+#pragma unroll
+    for (int c = 0; c < 4; ++c) part[c][tid] = s[c];
+    __syncthreads();
+    for (int off = 1; off < 256; off <<= 1) {  // inclusive scans of the chunk sums
+        int64_t v[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) v[c] = tid >= off ? part[c][tid - off] : 0;
+        __syncthreads();
+#pragma unroll
+        for (int c = 0; c < 4; ++c) part[c][tid] += v[c];
+        __syncthreads();
+    }
+    int64_t run[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) run[c] = part[c][tid] - s[c];
+    for (int i = beg; i < end; ++i) {
+        const uint64_t v = hist[i];
+        const int64_t n = (int64_t)(v >> kShiftCnt3);
+        run[0] += (int64_t)(v & ((1ull << kShiftSurf3) - 1)) - kEcBias3 * n;
+        if (crease) run[1] += (int64_t)hc[i] - kCreaseBias3 * n;
+        run[2] += (int64_t)((v >> kShiftSurf3) & ((1ull << (kShiftCnt3 - kShiftSurf3)) - 1)) - kSurfBias3 * n;
+        run[3] += n;
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+            if (out[c]) out[c][i] = run[c];
+    }
+    __syncthreads();
+}
+
+// The host cuts every volume into items of whole tiles (of the volume's tile
+// shape) and deals them to workgroups (as for 2D fields).  A workgroup runs an
+// item's tiles into LDS bins over all of the field's levels (at most
+// kBatchMaxLevels, one pass).  A field of one item is scanned from those bins
+// straight into its curves; otherwise the workgroup adds its bins into the
+// field's int32 histogram [ec, crease, surface, count][L] with device atomics
+// and takes the field's ticket, and the workgroup that finishes the last item
+// scans the histogram into the curves and clears it and the ticket for the
+// next launch.
 template <typename T, int LM>
 __global__ void __launch_bounds__(256)
     ecc3d_batch(const BatchField3D *__restrict__ fields, const BatchItem *__restrict__ items,
                 const int32_t *__restrict__ wg_first, const int64_t *__restrict__ vt3) {
     extern __shared__ uint64_t smem[];
     __shared__ int64_t vt[2][256];
-    __shared__ TileLevels lam;
-    __shared__ int64_t part[256];
+    __shared__ uint16_t lam[kBatch3DTileElems];
+    __shared__ int64_t part[4][256];
     __shared__ int last;
     const int tid = threadIdx.x;
     vt[0][tid] = vt3[tid];
@@ -792,15 +923,20 @@ __global__ void __launch_bounds__(256)
         lv.neg = f.neg;
         const int64_t *vtab = vt[f.conn_idx];
         for (int tile = item.u0; tile < item.u1; ++tile) {
-            const int64_t x0 = (int64_t)(tile % f.tiles_x) * kTile3DX;
-            const int64_t y0 = (int64_t)((tile / f.tiles_x) % f.tiles_y) * kTile3DY;
-            const int64_t z0 = (int64_t)(tile / (f.tiles_x * f.tiles_y)) * kTile3DZ;
+            const int64_t x0 = (int64_t)(tile % f.tiles_x) * f.tx;
+            const int64_t y0 = (int64_t)((tile / f.tiles_x) % f.tiles_y) * f.ty;
+            const int64_t z0 = (int64_t)(tile / (f.tiles_x * f.tiles_y)) * f.tz;
             if (crease)  // uniform
-                tile_3d<T, LM, 1>((const T *)f.data, f.d, f.h, f.w, lv, 0, L, vtab, lam, hist, hc, nullptr, x0,
-                                  y0, z0);
+                tile_3d_flex<T, LM, true>((const T *)f.data, f.d, f.h, f.w, lv, vtab, lam, hist, hc, x0, y0, z0,
+                                          f.tx, f.ty, f.tz);
             else
-                tile_3d<T, LM, 0>((const T *)f.data, f.d, f.h, f.w, lv, 0, L, vtab, lam, hist, hc, nullptr, x0,
-                                  y0, z0);
+                tile_3d_flex<T, LM, false>((const T *)f.data, f.d, f.h, f.w, lv, vtab, lam, hist, hc, x0, y0, z0,
+                                           f.tx, f.ty, f.tz);
+        }
+        if (f.n_items == 1) {  // uniform: the whole field is in this workgroup's bins
+            int64_t *const out[4] = {f.out[0], f.out[1], f.out[2], f.out[3]};
+            scan_bins_3d(hist, hc, crease, L, out, part);
+            continue;
         }
         // bins -> the field's histogram (channels in curve order: ec, crease, surface, count)
         for (int b = tid; b < L; b += 256) {
@@ -835,15 +971,15 @@ __global__ void __launch_bounds__(256)
                 int64_t *dst = f.out[ch];
                 int64_t s = 0;
                 for (int i = beg; i < end; ++i) s += src[i];
-                part[tid] = s;
+                part[0][tid] = s;
                 __syncthreads();
                 for (int off = 1; off < 256; off <<= 1) {  // inclusive scan of the chunk sums
-                    const int64_t v = tid >= off ? part[tid - off] : 0;
+                    const int64_t v = tid >= off ? part[0][tid - off] : 0;
                     __syncthreads();
-                    part[tid] += v;
+                    part[0][tid] += v;
                     __syncthreads();
                 }
-                int64_t run = part[tid] - s;
+                int64_t run = part[0][tid] - s;
                 for (int i = beg; i < end; ++i) {
                     run += src[i];
                     src[i] = 0;

@@ -167,6 +167,10 @@ bool batchable(const FieldInfo &fi);  // batch_kind(fi) != 0
 int schedule_batch_2d(int n_cu, int dtype, int lm, int max_L, const std::vector<SchedField> &fields,
                       int item_cells, int wg_per_cu, std::vector<BatchItem> &sorted, std::vector<int32_t> &first,
                       std::vector<int32_t> &n_items);
+struct TileShape {
+    int tx, ty, tz;
+};
+TileShape tile_shape_3d(int64_t d, int64_t h, int64_t w);
 int schedule_batch_3d(int n_cu, int max_L, const std::vector<SchedField> &fields, int item_cells, int wg_per_cu,
                       std::vector<BatchItem> &sorted, std::vector<int32_t> &first, std::vector<int32_t> &n_items);
 // a field's batched-kernel descriptor without its histogram, ticket and item count
