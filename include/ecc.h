@@ -220,6 +220,40 @@ ecc_status ecc_curves_compute_batch(ecc_context ctx, int32_t n, const ecc_field 
                                     const ecc_curves *curves, void *stream);
 
 /*
+ * A 4D field (the Conclusions name 4D data, such as hyperspectral images over
+ * time, as the next step; the definitions of the Methodology carry over).
+ *   dtype, data, n_levels, thresholds, filtration: as in ecc_field, with
+ *                 n_levels at most 4096.
+ *   shape         {a, d, h, w}, C order (w contiguous), each >= 1, at most
+ *                 2^31 cells.
+ *   connectivity  80 (the closure of the active hypercubes, the paper's
+ *                 construction one dimension up; the default, also 0) or 8
+ *                 (the complex of fully active blocks, as 4-C / 6-C).
+ */
+typedef struct {
+    int32_t dtype;
+    int64_t shape[4];
+    const void *data;
+    int32_t n_levels;
+    int32_t connectivity;
+    const float *thresholds;
+    int32_t filtration;
+} ecc_field4;
+
+/*
+ * Curves of a 4D field: ec (Eq. (1) over the cells of dimensions 0..4 of the
+ * complex at each level), boundary (unit 3-faces with exactly one active
+ * hypercube, the 4D counterpart of the perimeter and surface columns) and
+ * volume (active hypercubes).  DEVICE int64 arrays of n_levels, caller-owned;
+ * NULL = not wanted (at least one given).  Asynchronous on `stream`.
+ * Errors: ECC_ERR_INVALID_ARG for a broken rule above or of ecc_field,
+ * ECC_ERR_UNSUPPORTED for more than 4096 levels or 2^31 cells; nothing is
+ * queued then.
+ */
+ecc_status ecc_curves_compute_4d(ecc_context ctx, const ecc_field4 *field, int64_t *ec, int64_t *boundary,
+                                 int64_t *volume, void *stream);
+
+/*
  * Autotuner: times the batched launch over candidate tile shapes and work splits
  * for this mix of fields (data must be valid device memory; the outputs of the
  * trial runs are discarded) and stores the fastest in the context's cache, keyed by

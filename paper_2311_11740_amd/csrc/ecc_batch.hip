@@ -163,8 +163,8 @@ static std::string plan_key(int n, const FieldInfo *fi, const LevelArgs *lv) {
 
 // Deal items to `grid` workgroups, largest first, each to the least loaded
 // one; items come out grouped by workgroup (first: grid + 1 entries).
-static void deal_items(const std::vector<BatchItem> &items, const std::vector<int64_t> &cost, int64_t per_item,
-                       int grid, std::vector<BatchItem> &sorted, std::vector<int32_t> &first) {
+void deal_items(const std::vector<BatchItem> &items, const std::vector<int64_t> &cost, int64_t per_item, int grid,
+                std::vector<BatchItem> &sorted, std::vector<int32_t> &first) {
     std::vector<int> order(items.size());
     for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });

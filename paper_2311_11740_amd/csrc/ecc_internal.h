@@ -210,6 +210,26 @@ int launch_batch_3d(int dtype, int lm, const BatchField3D *fields, const BatchIt
                     const int32_t *wg_first, int grid, const int64_t *vt3, int max_L, void *stream);
 size_t lds_bytes_batch_3d(int max_L);
 
+// A 4D field's launch: the slab kernel over (virtual volume, tile range)
+// items, then the kernel that combines the passes and scans.
+struct Launch4D {
+    const void *data;
+    int dtype;
+    int64_t a, d, h, w;
+    LevelArgs lv;
+    bool faces;  // face-adjacency complex (8-C) instead of the closure (80-C)
+    const BatchItem *items;
+    const int32_t *wg_first;
+    int grid;
+    const int64_t *vtab;  // 3D per-octant table: 26-C (closure) or 6-C (faces)
+    int64_t *acc;         // [kAccCopies][6][L], zero; left at zero
+    int64_t *totals;      // [3][L] scratch
+    int64_t *out[3];      // ec, boundary, volume (NULL = not wanted)
+    int tx, ty, tz, tiles_x, tiles_y;
+};
+int launch_4d(const Launch4D &g, void *stream);
+size_t lds_bytes_4d(int L);
+
 // device-side launchers (ecc_k2d.hip, ecc_k3d.hip, ecc_kmerge.hip); return a hipError_t as int
 int launch_2d(const Launch2D &a, void *stream);
 int launch_3d(const Launch3D &a, void *stream);

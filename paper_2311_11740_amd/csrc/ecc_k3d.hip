@@ -753,18 +753,28 @@ __global__ void __launch_bounds__(256)
 // error is below 2^-8 of that
 __device__ __forceinline__ int small_div(int e, float r) { return (int)(((float)e + 0.5f) * r); }
 
-// One tile of tx x ty x tz voxels (shape chosen per volume): its levels and a
-// one-voxel halo are staged into `lam` ((tx+2) x (ty+2) x (planes+2) slots),
-// then the threads take the tile's (x, y) columns in rounds of 256 and walk
-// each up the planes with a 3x3x3 window, as in the generic tile pass.
-// Starts and ends with the workgroup in step.
-template <typename T, int LM, bool CREASE>
-__device__ __forceinline__ void tile_3d_flex(const T *__restrict__ data, int64_t d, int64_t h, int64_t w,
-                                             const LevelArgs &lv, const int64_t *vt, uint16_t *lam,
-                                             uint64_t *hist, uint32_t *hc, int64_t x0, int64_t y0, int64_t z0,
-                                             int tx, int ty, int tz) {
+// Levels of a volume in memory (d x h x w, C order).
+template <typename T, int LM>
+struct VolumeLevels {
+    const T *__restrict__ data;
+    int64_t h, w;
+    const LevelArgs &lv;
+    __device__ __forceinline__ uint32_t operator()(int64_t z, int64_t y, int64_t x) const {
+        return level_of<T, LM>(data[(z * h + y) * w + x], lv, ThrGlobal{lv.thr});
+    }
+};
+
+// One tile of tx x ty x tz voxels (shape chosen per volume) of the volume
+// whose levels `src(z, y, x)` gives (called for in-volume voxels only): its
+// levels and a one-voxel halo are staged into `lam` ((tx+2) x (ty+2) x
+// (planes+2) slots), then the threads take the tile's (x, y) columns in rounds
+// of 256 and walk each up the planes with a 3x3x3 window, as in the generic
+// tile pass.  Starts and ends with the workgroup in step.
+template <bool CREASE, typename Src>
+__device__ __forceinline__ void tile_3d_flex(const Src &src, int64_t d, int64_t h, int64_t w, int L,
+                                             const int64_t *vt, uint16_t *lam, uint64_t *hist, uint32_t *hc,
+                                             int64_t x0, int64_t y0, int64_t z0, int tx, int ty, int tz) {
     const int t = threadIdx.x;
-    const int L = lv.L;
     const int sx = tx + 2, sy = ty + 2;
     const int planes = (int)(d - z0 < tz ? d - z0 : tz);
     const int n_st = sx * sy * (planes + 2);
@@ -774,8 +784,7 @@ __device__ __forceinline__ void tile_3d_flex(const T *__restrict__ data, int64_t
         const int zz = small_div(row, rsy), yy = row - zz * sy;
         const int64_t x = x0 - 1 + xx, y = y0 - 1 + yy, z = z0 - 1 + zz;
         uint32_t l = (uint32_t)L;
-        if (x >= 0 && x < w && y >= 0 && y < h && z >= 0 && z < d)
-            l = level_of<T, LM>(data[(z * h + y) * w + x], lv, ThrGlobal{lv.thr});
+        if (x >= 0 && x < w && y >= 0 && y < h && z >= 0 && z < d) l = src(z, y, x);
         lam[e] = (uint16_t)l;
     }
     __syncthreads();
@@ -922,16 +931,15 @@ __global__ void __launch_bounds__(256)
         lv.eps = f.eps;
         lv.neg = f.neg;
         const int64_t *vtab = vt[f.conn_idx];
+        const VolumeLevels<T, LM> src{(const T *)f.data, f.h, f.w, lv};
         for (int tile = item.u0; tile < item.u1; ++tile) {
             const int64_t x0 = (int64_t)(tile % f.tiles_x) * f.tx;
             const int64_t y0 = (int64_t)((tile / f.tiles_x) % f.tiles_y) * f.ty;
             const int64_t z0 = (int64_t)(tile / (f.tiles_x * f.tiles_y)) * f.tz;
             if (crease)  // uniform
-                tile_3d_flex<T, LM, true>((const T *)f.data, f.d, f.h, f.w, lv, vtab, lam, hist, hc, x0, y0, z0,
-                                          f.tx, f.ty, f.tz);
+                tile_3d_flex<true>(src, f.d, f.h, f.w, L, vtab, lam, hist, hc, x0, y0, z0, f.tx, f.ty, f.tz);
             else
-                tile_3d_flex<T, LM, false>((const T *)f.data, f.d, f.h, f.w, lv, vtab, lam, hist, hc, x0, y0, z0,
-                                           f.tx, f.ty, f.tz);
+                tile_3d_flex<false>(src, f.d, f.h, f.w, L, vtab, lam, hist, hc, x0, y0, z0, f.tx, f.ty, f.tz);
         }
         if (f.n_items == 1) {  // uniform: the whole field is in this workgroup's bins
             int64_t *const out[4] = {f.out[0], f.out[1], f.out[2], f.out[3]};
@@ -993,6 +1001,114 @@ __global__ void __launch_bounds__(256)
 }
 
 // ---------------------------------------------------------------------------
+// 4D fields: slabs along the first axis
+// ---------------------------------------------------------------------------
+// The closure of the active hypercubes of a field of a slices (each a d x h x
+// w volume) splits, like the 3D one, into cells lying in the hyperplanes
+// between slices and cells spanning a slice: a cell in hyperplane t (between
+// slices t-1 and t, t = 0..a) is present exactly when its 3D counterpart is in
+// the closure of the union of those two slices (the "min image" M_t of their
+// levels; outside slices never enter), and a cell spanning slice t when its 3D
+// counterpart is in the closure of slice t, with one dimension more.  Hence
+//   chi80 = sum_t chi26(M_t) - sum_t chi26(slice t),
+// and for the face-adjacency complex (blocks of active cells)
+//   chi8 = sum_t chi6(slice t) - sum_t chi6(max image of slices t-1, t).
+// Boundary 3-faces: those spanning a slice are its 3D surface faces, those in
+// hyperplane t separate one active cell from an inactive one, counted from
+// the images as 2 |M_t| - |slice t-1| - |slice t| (closure) or
+// |slice t-1| + |slice t| - 2 |max image| (faces).  So one pass over the
+// "virtual volumes" (the slices, then the images) with the 3D tile pass gives
+// every curve: each item adds its bins (EC, surface, count) into per-pass
+// accumulators, and a finishing kernel combines and scans them.
+template <typename T, int LM>
+struct SlabLevels {
+    const T *__restrict__ data;
+    int64_t a, d, h, w;
+    const LevelArgs &lv;
+    int64_t t;  // slice or image index
+    int mode;   // 0: slice t; 1: min image of slices t-1, t; 2: max image
+    __device__ __forceinline__ uint32_t at(int64_t s, int64_t z, int64_t y, int64_t x) const {
+        if (s < 0 || s >= a) return (uint32_t)lv.L;
+        return level_of<T, LM>(data[((s * d + z) * h + y) * w + x], lv, ThrGlobal{lv.thr});
+    }
+    __device__ __forceinline__ uint32_t operator()(int64_t z, int64_t y, int64_t x) const {
+        if (mode == 0) return at(t, z, y, x);
+        const uint32_t l0 = at(t - 1, z, y, x), l1 = at(t, z, y, x);
+        return mode == 1 ? (l0 < l1 ? l0 : l1) : (l0 > l1 ? l0 : l1);
+    }
+};
+
+// items: (virtual volume, tile range); virtual volume v < a is slice v, else
+// image t = v - a (closure, t = 0..a) or t = v - a + 1 (faces, t = 1..a-1).
+// acc: [kAccCopies][pass][EC, surface, count][L] int64, pass 0 = slices.
+template <typename T, int LM>
+__global__ void __launch_bounds__(256)
+    ecc4d_slabs(const T *__restrict__ data, int64_t a, int64_t d, int64_t h, int64_t w, LevelArgs lv, int faces,
+                const BatchItem *__restrict__ items, const int32_t *__restrict__ wg_first,
+                const int64_t *__restrict__ vtab, int64_t *__restrict__ acc, int tx, int ty, int tz, int tiles_x,
+                int tiles_y) {
+    extern __shared__ uint64_t smem[];
+    __shared__ int64_t vt[256];
+    __shared__ uint16_t lam[kBatch3DTileElems];
+    const int tid = threadIdx.x;
+    const int L = lv.L;
+    vt[tid] = vtab[tid];
+    uint64_t *hist = smem;
+    int64_t *mine = acc + (int64_t)xcc_copy() * 6 * L;
+    const int i_beg = wg_first[blockIdx.x], i_end = wg_first[blockIdx.x + 1];
+    for (int it = i_beg; it < i_end; ++it) {
+        const BatchItem item = items[it];
+        for (int b = tid; b < L; b += 256) hist[b] = 0;
+        __syncthreads();
+        const int64_t v = item.field;
+        const bool slice = v < a;
+        const SlabLevels<T, LM> src{data, a, d, h, w, lv, slice ? v : (faces ? v - a + 1 : v - a),
+                                    slice ? 0 : (faces ? 2 : 1)};
+        for (int tile = item.u0; tile < item.u1; ++tile) {
+            const int64_t x0 = (int64_t)(tile % tiles_x) * tx;
+            const int64_t y0 = (int64_t)((tile / tiles_x) % tiles_y) * ty;
+            const int64_t z0 = (int64_t)(tile / (tiles_x * tiles_y)) * tz;
+            tile_3d_flex<false>(src, d, h, w, L, vt, lam, hist, nullptr, x0, y0, z0, tx, ty, tz);
+        }
+        int64_t *dst = mine + (slice ? 0 : 3 * L);
+        for (int b = tid; b < L; b += 256) {
+            const uint64_t bin = hist[b];
+            const int64_t n = (int64_t)(bin >> kShiftCnt3);
+            if (n == 0) continue;
+            const int64_t surf = (int64_t)((bin >> kShiftSurf3) & ((1ull << (kShiftCnt3 - kShiftSurf3)) - 1)) -
+                                 kSurfBias3 * n;
+            const int64_t ec = (int64_t)(bin & ((1ull << kShiftSurf3) - 1)) - kEcBias3 * n;
+            acc_add(dst + b, ec);
+            acc_add(dst + L + b, surf);
+            acc_add(dst + 2 * L + b, n);
+        }
+        __syncthreads();
+    }
+}
+
+// Combine the passes per level (see above), scan over levels into the curves
+// (NULL outputs skipped) and clear the accumulators; one block.
+__global__ void __launch_bounds__(1024)
+    ecc4d_finish(int64_t *__restrict__ acc, int L, int faces, OutPtrs out, int64_t *__restrict__ totals) {
+    for (int l = threadIdx.x; l < L; l += blockDim.x) {
+        int64_t v[6] = {0, 0, 0, 0, 0, 0};
+        for (int c = 0; c < kAccCopies; ++c)
+#pragma unroll
+            for (int k = 0; k < 6; ++k) {
+                int64_t *p = acc + ((int64_t)c * 6 + k) * L + l;
+                v[k] += *p;
+                *p = 0;
+            }
+        // v: slices (EC, surface, count), images (EC, surface, count)
+        totals[l] = faces ? v[0] - v[3] : v[3] - v[0];
+        totals[L + l] = faces ? v[1] + 2 * v[2] - 2 * v[5] : v[1] + 2 * v[5] - 2 * v[2];
+        totals[2 * L + l] = v[2];
+    }
+    __syncthreads();
+    scan_totals_block(totals, 3, L, out);
+}
+
+// ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
 size_t lds_bytes_3d(int window, bool want_crease) { return (size_t)window * (want_crease ? 12 : 8); }
@@ -1023,6 +1139,35 @@ static int launch_batch3_t(int lm, const BatchField3D *fields, const BatchItem *
                                vt3);
         break;
     }
+    return (int)hipGetLastError();
+}
+
+size_t lds_bytes_4d(int L) { return (size_t)L * 8; }
+
+template <typename T, int LM>
+static int launch_4d_t(const Launch4D &g, hipStream_t s) {
+    hipLaunchKernelGGL((ecc4d_slabs<T, LM>), dim3(g.grid), dim3(256), lds_bytes_4d(g.lv.L), s, (const T *)g.data,
+                       g.a, g.d, g.h, g.w, g.lv, g.faces ? 1 : 0, g.items, g.wg_first, g.vtab, g.acc, g.tx, g.ty,
+                       g.tz, g.tiles_x, g.tiles_y);
+    return (int)hipGetLastError();
+}
+
+int launch_4d(const Launch4D &g, void *stream) {
+    hipStream_t s = (hipStream_t)stream;
+    int e;
+    switch (g.dtype) {
+    case ECC_U8: e = g.lv.mode == LM_LUT ? launch_4d_t<uint8_t, LM_LUT>(g, s) : launch_4d_t<uint8_t, LM_IDENTITY>(g, s); break;
+    case ECC_U16:
+        e = g.lv.mode == LM_LUT ? launch_4d_t<uint16_t, LM_LUT>(g, s) : launch_4d_t<uint16_t, LM_IDENTITY>(g, s);
+        break;
+    default:
+        e = g.lv.mode == LM_AFFINE ? launch_4d_t<float, LM_AFFINE>(g, s) : launch_4d_t<float, LM_SEARCH>(g, s);
+        break;
+    }
+    if (e) return e;
+    OutPtrs o;
+    for (int c = 0; c < 4; ++c) o.p[c] = c < 3 ? g.out[c] : nullptr;
+    hipLaunchKernelGGL(ecc4d_finish, dim3(1), dim3(1024), 0, s, g.acc, g.lv.L, g.faces ? 1 : 0, o, g.totals);
     return (int)hipGetLastError();
 }
 

@@ -54,10 +54,13 @@ struct ThrEntry {
 
 struct Workspace {
     DevBuf partial, totals, acc;
+    DevBuf items, first;  // 4D work items and their split over workgroups
     void release() {
         partial.release();
         totals.release();
         acc.release();
+        items.release();
+        first.release();
     }
 };
 
@@ -167,6 +170,10 @@ bool batchable(const FieldInfo &fi);  // batch_kind(fi) != 0
 int schedule_batch_2d(int n_cu, int dtype, int lm, int max_L, const std::vector<SchedField> &fields,
                       int item_cells, int wg_per_cu, std::vector<BatchItem> &sorted, std::vector<int32_t> &first,
                       std::vector<int32_t> &n_items);
+// deal items (costs given, plus per_item each) to `grid` workgroups, largest
+// first onto the least loaded; out: items grouped by workgroup, first[grid + 1]
+void deal_items(const std::vector<BatchItem> &items, const std::vector<int64_t> &cost, int64_t per_item, int grid,
+                std::vector<BatchItem> &sorted, std::vector<int32_t> &first);
 struct TileShape {
     int tx, ty, tz;
 };

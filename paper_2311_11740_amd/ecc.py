@@ -22,6 +22,7 @@ ECC_SUBLEVEL, ECC_SUPERLEVEL = 0, 1
 EXPORTS = (
     "ecc_create", "ecc_destroy", "ecc_last_error", "ecc_status_string",
     "ecc_curves_compute", "ecc_curves_compute_noalloc", "ecc_curves_compute_streamed", "ecc_curves_compute_batch",
+    "ecc_curves_compute_4d",
     "ecc_batch_plan_tune",
     "ecc_vertex_table", "ecc_vertex_classes_compute", "ecc_vertex_class_table",
     "ecc_validate_field", "ecc_profile_enable", "ecc_profile_read",
@@ -45,6 +46,12 @@ class Field(ctypes.Structure):
     _fields_ = [("ndim", ctypes.c_int32), ("dtype", ctypes.c_int32), ("shape", ctypes.c_int64 * 3),
                 ("data", ctypes.c_void_p), ("n_levels", ctypes.c_int32),
                 ("connectivity", ctypes.c_int32), ("thresholds", ctypes.c_void_p),
+                ("filtration", ctypes.c_int32)]
+
+
+class Field4(ctypes.Structure):
+    _fields_ = [("dtype", ctypes.c_int32), ("shape", ctypes.c_int64 * 4), ("data", ctypes.c_void_p),
+                ("n_levels", ctypes.c_int32), ("connectivity", ctypes.c_int32), ("thresholds", ctypes.c_void_p),
                 ("filtration", ctypes.c_int32)]
 
 
@@ -87,6 +94,7 @@ def load(path: str = LIB_PATH):
         "ecc_curves_compute_batch": ([vp, i32, ctypes.POINTER(Field), ctypes.POINTER(Curves), vp],
                                      ctypes.c_int),
         "ecc_batch_plan_tune": ([vp, i32, ctypes.POINTER(Field), vp], ctypes.c_int),
+        "ecc_curves_compute_4d": ([vp, ctypes.POINTER(Field4), vp, vp, vp, vp], ctypes.c_int),
         "ecc_vertex_table": ([i32, i32, ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
         "ecc_vertex_classes_compute": ([vp, ctypes.POINTER(Field), vp, vp], ctypes.c_int),
         "ecc_vertex_class_table": ([i32, ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
@@ -324,6 +332,41 @@ class Context:
             raise ValueError(f"out must be a contiguous int64 tensor of shape ({nc}, n_levels)")
         check(self._lib.ecc_vertex_classes_compute(self.handle, ctypes.byref(f), out.data_ptr(),
                                                    _stream_ptr(stream)))
+        del keep
+        return out
+
+    def compute_4d(self, field, n_levels: int, thresholds=None, connectivity: int = 0,
+                   channels: Sequence[str] | None = None, stream=None, superlevel: bool = False):
+        """Curves of a 4D device field (a, d, h, w): dict with ec, boundary
+        (unit 3-faces with one active hypercube) and volume, int64 device
+        tensors (async on `stream`).  connectivity 80 (default) or 8."""
+        import numpy as np
+        torch = _torch()
+        if not field.is_contiguous() or field.dim() != 4:
+            raise ValueError("field must be a contiguous 4D tensor")
+        f = Field4()
+        f.dtype = _dtype_code(field)
+        for k in range(4):
+            f.shape[k] = int(field.shape[k])
+        f.data = field.data_ptr()
+        f.n_levels = int(n_levels)
+        f.connectivity = int(connectivity or 0)
+        f.filtration = ECC_SUPERLEVEL if superlevel else ECC_SUBLEVEL
+        keep = None
+        if thresholds is not None:
+            keep = np.ascontiguousarray(np.asarray(thresholds, dtype=np.float32))
+            if keep.size != n_levels:
+                raise ValueError("thresholds must have n_levels entries")
+            f.thresholds = keep.ctypes.data
+        names = ("ec", "boundary", "volume")
+        channels = names if channels is None else tuple(channels)
+        for c in channels:
+            if c not in names:
+                raise ValueError(f"channel {c!r} not available for 4D fields")
+        out = {c: torch.empty(int(n_levels), dtype=torch.int64, device=field.device) for c in channels}
+        ptr = [out[c].data_ptr() if c in out else None for c in names]
+        check(self._lib.ecc_curves_compute_4d(self.handle, ctypes.byref(f), ptr[0], ptr[1], ptr[2],
+                                              _stream_ptr(stream)))
         del keep
         return out
 

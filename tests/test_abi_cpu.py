@@ -150,6 +150,7 @@ def test_field_struct_layout():
     """The binding's Field is laid out as the header's ecc_field (and as the
     oracle's own descriptor): filtration after the thresholds pointer."""
     assert ecc.Field.filtration.offset == 56 and ctypes.sizeof(ecc.Field) == 64
+    assert ecc.Field4.data.offset == 40 and ecc.Field4.filtration.offset == 64 and ctypes.sizeof(ecc.Field4) == 72
 
 
 def test_validation_channels(lib):
