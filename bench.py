@@ -400,6 +400,29 @@ def measure_batch(ctx, specs, steps, warmup, workload=None):
 # Results, Tables 3 and 4), as context for the same inputs here.
 
 
+def measure_4d(ctx, spec, small, steps=10):
+    """A 4D field (a, d, h, w) per call, both constructions, field in HBM; a
+    small 4D field of the same recipe is checked against the any-dimension
+    oracle (the large one is too big for it)."""
+    import numpy as np
+    import torch
+    from oracle import ec_oracle_nd as ND
+    out = {"workload": spec.meta["name"], "cells": int(spec.data.size)}
+    dev = torch.from_numpy(spec.data).cuda()
+    sdev = torch.from_numpy(small.data).cuda()
+    for conn in (80, 8):
+        for _ in range(2):
+            ctx.compute_4d(dev, spec.n_levels, connectivity=conn)
+        ms, _ = timed_calls(lambda s: ctx.compute_4d(dev, spec.n_levels, connectivity=conn, stream=s), steps)
+        got = ctx.compute_4d(sdev, small.n_levels, connectivity=conn)
+        torch.cuda.synchronize()
+        ref = ND.curves_all_levels(small.data, small.n_levels, None, conn)
+        ok = all(np.array_equal(got[k].cpu().numpy(), ref[k]) for k in ref)
+        out[f"{conn}c"] = dict(ms_per_call=round(ms, 4), gcells_s=round(spec.data.size / ms / 1e6, 2),
+                               parity_vs_oracle_small=bool(ok), small_field=list(small.data.shape))
+    return out
+
+
 def measure_paper_workloads(ctx, steps):
     """Per-call throughput on the paper's white-noise inputs (field resident in
     HBM, all 256 levels, every output channel the paper computes: EC,
@@ -538,6 +561,7 @@ def main():
                     help="skip the host-resident (streamed in slabs) measurement")
     ap.add_argument("--no-vertex-classes", action="store_true",
                     help="skip the contribution-map (vertex class counts) measurement")
+    ap.add_argument("--no-4d", action="store_true", help="skip the 4D field measurement")
     ap.add_argument("--no-paper-workloads", action="store_true",
                     help="skip the paper's white-noise workloads (context against its CPU timings)")
     ap.add_argument("--serving-requests", type=int, default=2000)
@@ -564,6 +588,7 @@ def main():
     sec_spec = make_workload("3d") if args.workload == "2d" and not args.no_secondary else None
     batch_specs = None if args.no_batch else synth.batch_2d_u8(workers=args.gen_workers)
     grid_specs = None if args.no_batch else synth.batch_3d_grids(workers=args.gen_workers)
+    f4 = None if args.no_4d else (synth.field_4d(), synth.field_4d((6, 10, 14, 18), seed=8))
     pool = None if args.no_serving else synth.serving_pool(workers=args.gen_workers)
     print(f"[bench] inputs drawn in {time.perf_counter() - t_gen:.1f} s", file=sys.stderr, flush=True)
 
@@ -630,6 +655,10 @@ def main():
         print(f"[bench] batched 3D: {line['batched_3d']['batched_gvox_s']} Gvox/s "
               f"({line['batched_3d']['speedup']}x per-field)", file=sys.stderr, flush=True)
         del grid_specs
+    if f4 is not None:
+        line["field_4d"] = measure_4d(ctx, *f4)
+        print(f"[bench] 4D: {line['field_4d']['80c']['gcells_s']} Gcells/s (80-C)", file=sys.stderr, flush=True)
+        del f4
     if not args.no_paper_workloads:
         line["paper_workloads"] = measure_paper_workloads(ctx, max(5, args.steps // 2))
         print("[bench] paper workloads done", file=sys.stderr, flush=True)

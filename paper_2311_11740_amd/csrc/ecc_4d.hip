@@ -71,29 +71,12 @@ extern "C" ecc_status ecc_curves_compute_4d(ecc_context ctx, const ecc_field4 *f
     // items: (virtual volume, tile range); slices v < a, then the images
     const TileShape ts = tile_shape_3d(d, h, w);
     const int64_t tiles_x = (w + ts.tx - 1) / ts.tx, tiles_y = (h + ts.ty - 1) / ts.ty;
-    const int64_t tiles = tiles_x * tiles_y * ((d + ts.tz - 1) / ts.tz);
     const int64_t n_vol = a + (faces ? std::max<int64_t>(a - 1, 0) : a + 1);
-    const int64_t tv = (int64_t)ts.tx * ts.ty * ts.tz;
-    const int64_t per_item = std::max<int64_t>(1, std::min<int64_t>(64 * 1024, kFlush3D) / tv);
-    const int64_t k_items = (tiles + per_item - 1) / per_item;
-    if (n_vol * k_items > INT32_MAX / 2) return done(fail(ECC_ERR_UNSUPPORTED, "too many 4D work items"));
-    const int64_t tile_cost = (((int64_t)ts.tx * ts.ty + 255) / 256) * ts.tz + 2;
-    std::vector<BatchItem> items;
-    std::vector<int64_t> cost;
-    items.reserve((size_t)(n_vol * k_items));
-    for (int64_t v = 0; v < n_vol; ++v)
-        for (int64_t j = 0; j < k_items; ++j) {
-            const int64_t u0 = tiles * j / k_items, u1 = tiles * (j + 1) / k_items;
-            items.push_back(BatchItem{(int32_t)v, (int32_t)u0, (int32_t)u1, 0});
-            cost.push_back((u1 - u0) * tile_cost);
-        }
-    const size_t lds = lds_bytes_4d(L) + 2 * kBatch3DTileElems + 3 * 1024;
-    const int fit = std::max<int>(1, (int)((160 * 1024) / lds));
-    const int grid = (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)ctx->n_cu * std::min(4, fit),
-                                                                 (int64_t)items.size()));
+    if (n_vol * tiles_x * tiles_y * ((d + ts.tz - 1) / ts.tz) > (int64_t(1) << 30))
+        return done(fail(ECC_ERR_UNSUPPORTED, "too many 4D work items"));
     std::vector<BatchItem> sorted;
     std::vector<int32_t> first;
-    deal_items(items, cost, 4, grid, sorted, first);
+    const int grid = schedule_4d(ctx->n_cu, L, n_vol, d, h, w, ts, sorted, first);
 
     s = grow(ctx, ctx->ws.items, sizeof(BatchItem) * sorted.size(), "4D work items");
     if (s == ECC_OK) s = grow(ctx, ctx->ws.first, sizeof(int32_t) * first.size(), "4D work split");

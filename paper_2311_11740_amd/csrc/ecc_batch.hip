@@ -161,122 +161,6 @@ static std::string plan_key(int n, const FieldInfo *fi, const LevelArgs *lv) {
     return k;
 }
 
-// Deal items to `grid` workgroups, largest first, each to the least loaded
-// one; items come out grouped by workgroup (first: grid + 1 entries).
-void deal_items(const std::vector<BatchItem> &items, const std::vector<int64_t> &cost, int64_t per_item, int grid,
-                std::vector<BatchItem> &sorted, std::vector<int32_t> &first) {
-    std::vector<int> order(items.size());
-    for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
-    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
-    typedef std::pair<int64_t, int> Load;
-    std::priority_queue<Load, std::vector<Load>, std::greater<Load>> pq;
-    for (int wg = 0; wg < grid; ++wg) pq.push({0, wg});
-    std::vector<std::vector<int>> per_wg(grid);
-    for (int i : order) {
-        Load l = pq.top();
-        pq.pop();
-        per_wg[l.second].push_back(i);
-        l.first += cost[i] + per_item;  // + a fixed cost per item (drain, ticket)
-        pq.push(l);
-    }
-    sorted.clear();
-    sorted.reserve(items.size());
-    first.assign(grid + 1, 0);
-    for (int wg = 0; wg < grid; ++wg) {
-        first[wg] = (int32_t)sorted.size();
-        for (int i : per_wg[wg]) sorted.push_back(items[i]);
-    }
-    first[grid] = (int32_t)sorted.size();
-}
-
-// Cut fields into items of at most `item_cells` cells (counted as whole
-// strips of 62 lanes x VEC cells per row, the work a wave does per row), and
-// deal the items to workgroups.  Returns the grid; n_items gets the item count
-// of each field.
-int schedule_batch_2d(int n_cu, int dtype, int lm, int max_L, const std::vector<SchedField> &fields,
-                      int item_cells, int wg_per_cu, std::vector<BatchItem> &sorted, std::vector<int32_t> &first,
-                      std::vector<int32_t> &n_items) {
-    const int vec = vec_2d(dtype), ce = 62 * vec;
-    const int64_t max_units = std::max<int64_t>(1, std::min<int64_t>(item_cells, kFlush2D) / ce);
-    std::vector<BatchItem> items;
-    std::vector<int64_t> cost;
-    n_items.assign(fields.size(), 0);
-    for (size_t f = 0; f < fields.size(); ++f) {
-        const int64_t strips = (fields[f].w + ce - 1) / ce, units = strips * fields[f].h;
-        const int64_t k = (units + max_units - 1) / max_units;  // items of this field
-        for (int64_t j = 0; j < k; ++j) {
-            const int64_t u0 = units * j / k, u1 = units * (j + 1) / k;
-            items.push_back(BatchItem{fields[f].slot, (int32_t)u0, (int32_t)u1, 0});
-            cost.push_back(u1 - u0);
-        }
-        n_items[f] = (int32_t)k;
-    }
-    const size_t lds = lds_bytes_batch_2d(lm, max_L) + 6 * 1024;
-    const int fit = std::max<int>(1, (int)((160 * 1024) / lds));
-    const int64_t G = std::min<int64_t>((int64_t)n_cu * std::min(wg_per_cu, fit), (int64_t)items.size());
-    const int grid = (int)std::max<int64_t>(1, G);
-    deal_items(items, cost, 8, grid, sorted, first);
-    return grid;
-}
-
-// Tile shape of a batched volume: tx x ty columns (taken by the workgroup's
-// 256 threads in rounds) of tz planes, with (tx+2)(ty+2)(tz+2) <= the LDS
-// slots of a tile, chosen to minimise a cost model of the tile pass: per tile,
-// rounds x planes column steps (about 150 instructions each), the staged
-// slots over 256 threads (about 40 each) and a fixed cost per tile.  A 20^3
-// volume becomes one 20 x 20 x 20 tile (the generic kernel's 64 x 4 x 16 tiles
-// would take ten, a fifth of their slots in the volume).
-TileShape tile_shape_3d(int64_t d, int64_t h, int64_t w) {
-    TileShape best{std::min<int>(64, (int)w), 1, 1};
-    double best_cost = 1e300;
-    const int tx = (int)std::min<int64_t>(64, w);
-    for (int ty = 1; ty <= std::min<int64_t>(h, 256); ++ty) {
-        const int64_t sxy = (int64_t)(tx + 2) * (ty + 2);
-        const int64_t tz_max = kBatch3DTileElems / sxy - 2;
-        if (tz_max < 1) break;
-        const int tz = (int)std::min<int64_t>({d, tz_max, 64});
-        const int64_t tiles = ((w + tx - 1) / tx) * ((h + ty - 1) / ty) * ((d + tz - 1) / tz);
-        const int64_t rounds = ((int64_t)tx * ty + 255) / 256;
-        const double per_tile = 150.0 * rounds * tz + 40.0 * ((sxy * (tz + 2) + 255) / 256) + 300.0;
-        const double cost = (double)tiles * per_tile;
-        if (cost < best_cost) {
-            best_cost = cost;
-            best = TileShape{tx, ty, tz};
-        }
-    }
-    return best;
-}
-
-// 3D: items of whole tiles of each volume's tile shape (at most kFlush3D
-// voxels per item so that the packed LDS bins cannot overflow).
-int schedule_batch_3d(int n_cu, int max_L, const std::vector<SchedField> &fields, int item_cells, int wg_per_cu,
-                      std::vector<BatchItem> &sorted, std::vector<int32_t> &first, std::vector<int32_t> &n_items) {
-    std::vector<BatchItem> items;
-    std::vector<int64_t> cost;
-    n_items.assign(fields.size(), 0);
-    for (size_t f = 0; f < fields.size(); ++f) {
-        const TileShape ts = tile_shape_3d(fields[f].d, fields[f].h, fields[f].w);
-        const int64_t tv = (int64_t)ts.tx * ts.ty * ts.tz;
-        const int64_t max_tiles = std::max<int64_t>(1, std::min<int64_t>(item_cells, kFlush3D) / tv);
-        const int64_t tiles = ((fields[f].w + ts.tx - 1) / ts.tx) * ((fields[f].h + ts.ty - 1) / ts.ty) *
-                              ((fields[f].d + ts.tz - 1) / ts.tz);
-        const int64_t tile_cost = (((int64_t)ts.tx * ts.ty + 255) / 256) * ts.tz + 2;
-        const int64_t k = (tiles + max_tiles - 1) / max_tiles;
-        for (int64_t j = 0; j < k; ++j) {
-            const int64_t u0 = tiles * j / k, u1 = tiles * (j + 1) / k;
-            items.push_back(BatchItem{fields[f].slot, (int32_t)u0, (int32_t)u1, 0});
-            cost.push_back((u1 - u0) * tile_cost);
-        }
-        n_items[f] = (int32_t)k;
-    }
-    const size_t lds = lds_bytes_batch_3d(max_L) + 2 * kBatch3DTileElems + 13 * 1024;  // + tables, scan
-    const int fit = std::max<int>(1, (int)((160 * 1024) / lds));
-    const int64_t G = std::min<int64_t>((int64_t)n_cu * std::min(wg_per_cu, fit), (int64_t)items.size());
-    const int grid = (int)std::max<int64_t>(1, G);
-    deal_items(items, cost, 4, grid, sorted, first);
-    return grid;
-}
-
 // descriptors of a field (everything but the plan's histogram, ticket and item count)
 void fill_desc_2d(BatchField2D &d, const ecc_field &f, const ecc_curves &c, const FieldInfo &fi,
                   const LevelArgs &lv) {

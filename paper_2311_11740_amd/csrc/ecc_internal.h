@@ -204,11 +204,9 @@ constexpr int kBatchMaxLevels = 4096;
 // Items of workgroup g are items[wg_first[g] .. wg_first[g+1]).
 int launch_batch_2d(int dtype, int lm, const BatchField2D *fields, const BatchItem *items,
                     const int32_t *wg_first, int grid, const uint64_t *luts, int max_L, void *stream);
-size_t lds_bytes_batch_2d(int lm, int max_L);
 // vt3: [2][256] per-octant tables, 26-C then 6-C
 int launch_batch_3d(int dtype, int lm, const BatchField3D *fields, const BatchItem *items,
                     const int32_t *wg_first, int grid, const int64_t *vt3, int max_L, void *stream);
-size_t lds_bytes_batch_3d(int max_L);
 
 // A 4D field's launch: the slab kernel over (virtual volume, tile range)
 // items, then the kernel that combines the passes and scans.
@@ -228,7 +226,6 @@ struct Launch4D {
     int tx, ty, tz, tiles_x, tiles_y;
 };
 int launch_4d(const Launch4D &g, void *stream);
-size_t lds_bytes_4d(int L);
 
 // device-side launchers (ecc_k2d.hip, ecc_k3d.hip, ecc_kmerge.hip); return a hipError_t as int
 int launch_2d(const Launch2D &a, void *stream);
@@ -241,8 +238,10 @@ int launch_merge(const int32_t *partial, int grid, int nch, int L, int64_t *cons
 int launch_level_lut(const float *thr, int L, int n_values, uint16_t *lut, bool neg, void *stream);
 // zero `bytes` (a multiple of 16) of device memory at p with a fill kernel
 int launch_zero(void *p, size_t bytes, void *stream);
-// copies of the atomic drain's accumulators, [kAccCopies][nch][L] int64
-constexpr int kAccCopies = 16;
+// copies of the atomic drain's accumulators, [kAccCopies][nch][L] int64: one
+// per XCD of the MI355X (a workgroup takes copy XCC_ID mod kAccCopies; the
+// adds are device-scope atomics, so copies shared by XCDs stay exact)
+constexpr int kAccCopies = 8;
 // accumulators [copies][nch][L] -> totals -> running sums into the curves;
 // leaves the accumulators at zero
 int launch_merge_acc(int64_t *acc, int copies, int nch, int L, int64_t *const out[4], int64_t *totals,

@@ -1,6 +1,7 @@
 // 2D kernels: the single-field row-streaming kernel (curves and vertex class
 // counts) and the batched persistent kernel, with their launchers.
 #include "ecc_device.h"
+#include "ecc_schedule.h"
 
 namespace ecc {
 
@@ -555,10 +556,6 @@ int launch_2d(const Launch2D &a, void *stream) {
     case ECC_U16: return launch_2d_dt<uint16_t>(a, s);
     default: return launch_2d_dt<float>(a, s);
     }
-}
-size_t lds_bytes_batch_2d(int lm, int max_L) {
-    const bool thr = lm == LM_AFFINE || lm == LM_SEARCH;
-    return (size_t)(max_L + 2 * kBinOff) * 8 + (thr ? (size_t)(max_L + 3) * 4 : 0);
 }
 
 template <typename T>

@@ -2,6 +2,7 @@
 // kernel (curves with the crease measure, vertex class counts), with their
 // launchers.
 #include "ecc_device.h"
+#include "ecc_schedule.h"
 
 namespace ecc {
 
@@ -1092,13 +1093,17 @@ __global__ void __launch_bounds__(1024)
     ecc4d_finish(int64_t *__restrict__ acc, int L, int faces, OutPtrs out, int64_t *__restrict__ totals) {
     for (int l = threadIdx.x; l < L; l += blockDim.x) {
         int64_t v[6] = {0, 0, 0, 0, 0, 0};
-        for (int c = 0; c < kAccCopies; ++c)
 #pragma unroll
-            for (int k = 0; k < 6; ++k) {
-                int64_t *p = acc + ((int64_t)c * 6 + k) * L + l;
-                v[k] += *p;
-                *p = 0;
+        for (int k = 0; k < 6; ++k) {
+            int64_t x[kAccCopies];  // every copy's load in flight at once
+#pragma unroll
+            for (int c = 0; c < kAccCopies; ++c) x[c] = acc[((int64_t)c * 6 + k) * L + l];
+#pragma unroll
+            for (int c = 0; c < kAccCopies; ++c) {
+                v[k] += x[c];
+                acc[((int64_t)c * 6 + k) * L + l] = 0;
             }
+        }
         // v: slices (EC, surface, count), images (EC, surface, count)
         totals[l] = faces ? v[0] - v[3] : v[3] - v[0];
         totals[L + l] = faces ? v[1] + 2 * v[2] - 2 * v[5] : v[1] + 2 * v[5] - 2 * v[2];
@@ -1113,7 +1118,6 @@ __global__ void __launch_bounds__(1024)
 // ---------------------------------------------------------------------------
 size_t lds_bytes_3d(int window, bool want_crease) { return (size_t)window * (want_crease ? 12 : 8); }
 
-size_t lds_bytes_batch_3d(int max_L) { return (size_t)max_L * 12; }
 
 template <typename T>
 static int launch_batch3_t(int lm, const BatchField3D *fields, const BatchItem *items, const int32_t *wg_first,
@@ -1142,7 +1146,6 @@ static int launch_batch3_t(int lm, const BatchField3D *fields, const BatchItem *
     return (int)hipGetLastError();
 }
 
-size_t lds_bytes_4d(int L) { return (size_t)L * 8; }
 
 template <typename T, int LM>
 static int launch_4d_t(const Launch4D &g, hipStream_t s) {

@@ -36,19 +36,24 @@ __global__ void __launch_bounds__(1024)
     if (threadIdx.x == 0) *counter = 0u;  // ready for the next merge
 }
 
-// Sums the accumulator copies of every bin into totals (and clears them),
-// one thread per bin; the last block to finish scans the totals into the
-// curves.
+// Sums the kAccCopies accumulator copies of every bin into totals (and
+// clears them), one thread per bin; the last block to finish scans the
+// totals into the curves.
 __global__ void __launch_bounds__(1024)
-    ecc_merge_acc(int64_t *__restrict__ acc, int copies, int nch, int L, OutPtrs out, int64_t *__restrict__ totals,
+    ecc_merge_acc(int64_t *__restrict__ acc, int nch, int L, OutPtrs out, int64_t *__restrict__ totals,
                   unsigned *__restrict__ counter) {
     __shared__ bool last;
     const int64_t n_bins = (int64_t)nch * L;
     for (int64_t bin = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; bin < n_bins;
          bin += (int64_t)gridDim.x * blockDim.x) {
+        // all copies' loads in flight at once (one memory latency, not one per copy)
+        int64_t v[kAccCopies];
+#pragma unroll
+        for (int c = 0; c < kAccCopies; ++c) v[c] = acc[c * n_bins + bin];
         int64_t s = 0;
-        for (int c = 0; c < copies; ++c) {
-            s += acc[c * n_bins + bin];
+#pragma unroll
+        for (int c = 0; c < kAccCopies; ++c) {
+            s += v[c];
             acc[c * n_bins + bin] = 0;
         }
         totals[bin] = s;
@@ -111,8 +116,9 @@ int launch_merge_acc(int64_t *acc, int copies, int nch, int L, int64_t *const ou
     for (int c = 0; c < 4; ++c) o.p[c] = c < nch ? out[c] : nullptr;
     const int64_t bins = (int64_t)nch * L;
     const int blocks = (int)std::min<int64_t>(64, (bins + 1023) / 1024);
-    hipLaunchKernelGGL(ecc_merge_acc, dim3(blocks), dim3(1024), 0, (hipStream_t)stream, acc, copies, nch, L, o,
-                       totals, counter);
+    if (copies != kAccCopies) return (int)hipErrorInvalidValue;
+    hipLaunchKernelGGL(ecc_merge_acc, dim3(blocks), dim3(1024), 0, (hipStream_t)stream, acc, nch, L, o, totals,
+                       counter);
     return (int)hipGetLastError();
 }
 

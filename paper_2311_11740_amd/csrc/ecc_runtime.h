@@ -8,6 +8,7 @@
 #include <vector>
 
 #include "ecc_internal.h"
+#include "ecc_schedule.h"
 
 namespace ecc {
 
@@ -158,28 +159,9 @@ void destroy_stream_state(ecc_context ctx);
 // the atomic drain's accumulators for nch channels of L levels (zero), grown
 // and cleared as needed (may synchronise the device when it grows)
 ecc_status acc_buffer(ecc_context ctx, int nch, int L, int64_t **acc, void *stream);
-// batched 2D scheduling (ecc_batch.hip), shared with the serving loop
-struct SchedField {
-    int32_t slot;  // descriptor index the items refer to
-    int64_t h, w;
-    int64_t d = 1;
-};
 // the batched kernel that takes a field: 2, 3, or 0 for the single-field path
 int batch_kind(const FieldInfo &fi);
 bool batchable(const FieldInfo &fi);  // batch_kind(fi) != 0
-int schedule_batch_2d(int n_cu, int dtype, int lm, int max_L, const std::vector<SchedField> &fields,
-                      int item_cells, int wg_per_cu, std::vector<BatchItem> &sorted, std::vector<int32_t> &first,
-                      std::vector<int32_t> &n_items);
-// deal items (costs given, plus per_item each) to `grid` workgroups, largest
-// first onto the least loaded; out: items grouped by workgroup, first[grid + 1]
-void deal_items(const std::vector<BatchItem> &items, const std::vector<int64_t> &cost, int64_t per_item, int grid,
-                std::vector<BatchItem> &sorted, std::vector<int32_t> &first);
-struct TileShape {
-    int tx, ty, tz;
-};
-TileShape tile_shape_3d(int64_t d, int64_t h, int64_t w);
-int schedule_batch_3d(int n_cu, int max_L, const std::vector<SchedField> &fields, int item_cells, int wg_per_cu,
-                      std::vector<BatchItem> &sorted, std::vector<int32_t> &first, std::vector<int32_t> &n_items);
 // a field's batched-kernel descriptor without its histogram, ticket and item count
 void fill_desc_2d(BatchField2D &d, const ecc_field &f, const ecc_curves &c, const FieldInfo &fi, const LevelArgs &lv);
 void fill_desc_3d(BatchField3D &d, const ecc_field &f, const ecc_curves &c, const FieldInfo &fi, const LevelArgs &lv);

@@ -208,6 +208,13 @@ def batch_3d_grids(n: int = 4096, side: int = 20, seed: int = 6, workers: int = 
             for k, (a, s) in enumerate(zip(data, sigmas))]
 
 
+def field_4d(shape=(32, 96, 96, 96), seed: int = 7) -> FieldSpec:
+    """A 4D uint8 field (a smoothed GRF, sigma 3 cells, 256 levels, 80-C): a
+    stand-in for 4D data such as a time series of volumes."""
+    return FieldSpec(quantise(grf(shape, 3.0, seed), 256), 256, None, 80,
+                     dict(name="4d_" + "x".join(str(s) for s in shape) + "_u8_sigma3_L256"))
+
+
 def serving_pool(n2d: int = 64, n3d: int = 32, seed: int = 5, max2d: int = 4096, max3d: int = 384,
                  workers: int = 1):
     """Pool of request fields: 2D uint8 (side log-uniform in [128, max2d], 256
