@@ -466,7 +466,7 @@ static ecc_status prepare(ecc_context ctx, int n, const ecc_field *fields, const
     }
     std::vector<const ecc_field *> fp(n);
     for (int i = 0; i < n; ++i) fp[i] = &fields[i];
-    ecc_status s = reserve_thresholds(ctx, n, fp.data());
+    ecc_status s = reserve_thresholds(ctx, n, fp.data(), stream);
     if (s != ECC_OK) return s;
     for (int i = 0; i < n; ++i) {
         s = level_args(ctx, &fields[i], fi[i], stream, &lv[i]);

@@ -253,6 +253,10 @@ bool atomic_drain();
 
 // tile geometry used by the single-field kernels
 constexpr int kWavesPerWG = 4;
+// Waves per workgroup of the single-field 2D kernel: one 1024-thread
+// workgroup per CU whose 16 waves share one LDS histogram, so that one drain
+// per CU (not four) adds its bins into the accumulators.
+constexpr int kWaves2D = 16;
 constexpr int kTile3DX = 64, kTile3DY = 4, kTile3DZ = 16;
 // z-marching 3D kernel: strips of 64 lanes x 4 cells, blocks of kZmTY rows
 constexpr int kZmTY = 4, kZmStripX = 256, kZmCellsPerUnit = kZmStripX * kZmTY;

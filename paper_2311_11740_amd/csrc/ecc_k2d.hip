@@ -303,7 +303,7 @@ __device__ __forceinline__ void stream_run_2d(const T *__restrict__ data, int h,
 // are divided into equal contiguous ranges, one per wave (a range may run from
 // the end of one strip into the next).
 template <typename T, int LM, int AL, int PF, bool CLS>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(64 * kWaves2D)
     ecc2d_stream(const T *__restrict__ data, int64_t h, int64_t w, LevelArgs lv, int32_t lo,
                  int32_t hi, float cpass, const uint64_t *__restrict__ delta_lut, int32_t *__restrict__ partial,
                  int64_t row_lo, int64_t row_hi, int accumulate, int prio, int64_t *acc) {
@@ -324,19 +324,19 @@ __global__ void __launch_bounds__(256)
     float *thr_s = reinterpret_cast<float *>(smem + BW * n_bins);
     constexpr bool kThr = LM == LM_AFFINE || LM == LM_SEARCH;
     if (kThr)
-        for (int i = tid; i < W + 3; i += 256) {
+        for (int i = tid; i < W + 3; i += 64 * kWaves2D) {
             int k = lo - 2 + i;
             k = k < 0 ? 0 : (k >= L ? L - 1 : k);
             thr_s[i] = lv.thr[k];
         }
 #pragma unroll
-    for (int k = 0; k < BW; ++k) dl[256 * k + tid] = delta_lut[256 * k + tid];
-    for (int b = tid; b < BW * n_bins; b += 256) hist[b] = 0;
+    for (int k = tid; k < 256 * BW; k += 64 * kWaves2D) dl[k] = delta_lut[k];
+    for (int b = tid; b < BW * n_bins; b += 64 * kWaves2D) hist[b] = 0;
     __syncthreads();
 
     const int G = gridDim.x;
     const int wg = xcd_order(blockIdx.x, G);
-    const int64_t gw = (int64_t)wg * kWavesPerWG + wave, NW = (int64_t)G * kWavesPerWG;
+    const int64_t gw = (int64_t)wg * kWaves2D + wave, NW = (int64_t)G * kWaves2D;
     const int64_t H = row_hi - row_lo;
     const int64_t n_strips = (w + CE - 1) / CE;
     const int64_t units = n_strips * H;
@@ -498,8 +498,8 @@ int load_mode_2d(const void *data, int64_t h, int64_t w, int elem_bytes) {
 static int64_t max_wg_cells_2d(int64_t rows, int64_t w, int vec, int grid) {
     const int64_t ce = 62 * vec;
     const int64_t units = ((w + ce - 1) / ce) * rows;
-    const int64_t NW = (int64_t)grid * kWavesPerWG;
-    return kWavesPerWG * ((units + NW - 1) / NW + 1) * ce;
+    const int64_t NW = (int64_t)grid * kWaves2D;
+    return kWaves2D * ((units + NW - 1) / NW + 1) * ce;
 }
 
 template <typename T, int LM, int AL, bool CLS>
@@ -519,7 +519,7 @@ static int launch_2d_t(const Launch2D &a, hipStream_t s) {
     for (int64_t r0 = a.row_lo; r0 < a.row_hi; r0 += chunk) {
         const int64_t r1 = r0 + chunk < a.row_hi ? r0 + chunk : a.row_hi;
         const bool acc = a.accumulate || r0 > a.row_lo;
-        hipExtLaunchKernelGGL((ecc2d_stream<T, LM, AL, PF, CLS>), dim3(a.grid), dim3(256), lds, s,
+        hipExtLaunchKernelGGL((ecc2d_stream<T, LM, AL, PF, CLS>), dim3(a.grid), dim3(64 * kWaves2D), lds, s,
                               r0 == a.row_lo ? (hipEvent_t)a.ev_start : nullptr,
                               r1 == a.row_hi ? (hipEvent_t)a.ev_stop : nullptr, 0, (const T *)a.data, a.h, a.w,
                               a.lv, a.lo, a.hi, cpass, a.delta_lut, a.partial, r0, r1, acc ? 1 : 0,

@@ -68,6 +68,67 @@ __global__ void __launch_bounds__(1024)
     if (threadIdx.x == 0) *counter = 0u;
 }
 
+// The same for at most kMergeChMaxLevels levels, one block per channel: the
+// block sums the copies of its channel's bins (every load of a thread in
+// flight at once), clears them, keeps the per-level totals in LDS and writes
+// the running sums.  Blocks share nothing, so there is no ticket and no
+// device-scope fence.
+constexpr int kMergeChMaxLevels = 4096;
+constexpr int kMergeChThreads = 1024;
+__global__ void __launch_bounds__(kMergeChThreads)
+    ecc_merge_acc_ch(int64_t *__restrict__ acc, int nch, int L, OutPtrs out) {
+    constexpr int PER = kMergeChMaxLevels / kMergeChThreads;  // levels per thread and pass
+    __shared__ int64_t tot[kMergeChMaxLevels];
+    __shared__ int64_t wsum[kMergeChThreads / 64];
+    const int ch = blockIdx.x, t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const unsigned nb = (unsigned)(nch * L);  // 32-bit offsets from one base: scalar-base loads
+    int64_t *a = acc + (int64_t)ch * L;
+    // unconditional loads and stores at indices wrapped into [0, L) (a
+    // conditional load would be waited for before the next one is issued);
+    // wrapped duplicates are not counted, and they spread over the bins
+    unsigned lc[PER];
+#pragma unroll
+    for (int i = 0; i < PER; ++i) lc[i] = (unsigned)((i * kMergeChThreads + t) % L);
+    int64_t v[kAccCopies][PER];
+#pragma unroll
+    for (int c = 0; c < kAccCopies; ++c)
+#pragma unroll
+        for (int i = 0; i < PER; ++i) v[c][i] = __builtin_nontemporal_load(a + c * nb + lc[i]);
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+        int64_t s = 0;
+#pragma unroll
+        for (int c = 0; c < kAccCopies; ++c) s += v[c][i];
+        if (i * kMergeChThreads + t < L) tot[i * kMergeChThreads + t] = s;
+    }
+    __syncthreads();  // every thread has read its copies before any is cleared
+#pragma unroll
+    for (int c = 0; c < kAccCopies; ++c)
+#pragma unroll
+        for (int i = 0; i < PER; ++i) a[c * nb + lc[i]] = 0;
+    int64_t *dst = out.p[ch];
+    if (!dst) return;  // uniform
+    // thread t scans the levels [t * per, (t + 1) * per)
+    const int per = (L + kMergeChThreads - 1) / kMergeChThreads;
+    const int beg = t * per < L ? t * per : L, end = beg + per < L ? beg + per : L;
+    int64_t sum = 0;
+    for (int i = beg; i < end; ++i) sum += tot[i];
+    int64_t x = sum;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const int64_t y = __shfl_up(x, off);
+        if (lane >= off) x += y;
+    }
+    if (lane == 63) wsum[wave] = x;
+    __syncthreads();
+    int64_t run = x - sum;
+    for (int k = 0; k < wave; ++k) run += wsum[k];
+    for (int i = beg; i < end; ++i) {
+        run += tot[i];
+        dst[i] = run;
+    }
+}
+
 __global__ void ecc_zero(u32x4 *__restrict__ p, int64_t n) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
         p[i] = u32x4{0u, 0u, 0u, 0u};
@@ -114,9 +175,14 @@ int launch_merge_acc(int64_t *acc, int copies, int nch, int L, int64_t *const ou
                      unsigned *counter, void *stream) {
     OutPtrs o;
     for (int c = 0; c < 4; ++c) o.p[c] = c < nch ? out[c] : nullptr;
+    if (copies != kAccCopies) return (int)hipErrorInvalidValue;
+    if (L <= kMergeChMaxLevels && nch <= 4) {
+        hipLaunchKernelGGL(ecc_merge_acc_ch, dim3(nch), dim3(kMergeChThreads), 0, (hipStream_t)stream, acc, nch, L,
+                           o);
+        return (int)hipGetLastError();
+    }
     const int64_t bins = (int64_t)nch * L;
     const int blocks = (int)std::min<int64_t>(64, (bins + 1023) / 1024);
-    if (copies != kAccCopies) return (int)hipErrorInvalidValue;
     hipLaunchKernelGGL(ecc_merge_acc, dim3(blocks), dim3(1024), 0, (hipStream_t)stream, acc, nch, L, o, totals,
                        counter);
     return (int)hipGetLastError();

@@ -88,6 +88,14 @@ struct ecc_context_s {
     hipEvent_t ws_event = nullptr;
     void *ws_stream = nullptr;
     bool ws_used = false;
+    // While every call has queued its work on one stream (`solo_stream`),
+    // stream order alone keeps the workspace and the cached thresholds safe
+    // and no events are recorded per call (each record costs the device a
+    // fence between kernels).  The first call on another stream waits for the
+    // device once; from then on calls order their streams with events.
+    bool one_stream = true;
+    bool solo_set = false;
+    void *solo_stream = nullptr;
     ecc::BatchState *batch = nullptr;
     ecc::StreamState *streamed = nullptr;  // ecc_streamed.hip
     // the atomic drain's accumulators (ws.acc) hold sums of a call whose merge
@@ -123,11 +131,13 @@ void negate_thresholds(const float *t, int L, float *dst);
 // Makes room in the threshold cache for the distinct (by content) arrays of
 // `fields` that are not cached yet, so that fetching them all evicts none of
 // them; fails when they are more than the cache holds.
-ecc_status reserve_thresholds(ecc_context ctx, int n, const ecc_field *const *fields);
+ecc_status reserve_thresholds(ecc_context ctx, int n, const ecc_field *const *fields, void *stream);
 // the distinct threshold arrays (by content) among `fields`
 int count_distinct_thresholds(int n, const ecc_field *const *fields);
 // records on `stream` that the work queued so far reads lv's threshold arrays
 ecc_status note_threshold_use(ecc_context ctx, const LevelArgs &lv, void *stream);
+// to be called before a call queues work on `stream` (see one_stream)
+ecc_status use_stream(ecc_context ctx, void *stream);
 ecc_status acquire_workspace(ecc_context ctx, void *stream);
 ecc_status release_workspace(ecc_context ctx, void *stream);
 ecc_status grow(ecc_context ctx, DevBuf &b, size_t need, const char *what);
@@ -148,10 +158,9 @@ ecc_status noalloc_scratch(int device, unsigned char **out);
 // the affine level estimate of a threshold array, if it has one (host only)
 bool affine_levels(const float *thr, int L, float *u0, double *u0d, float *inv_step, float *eps);
 int pick_grid(ecc_context ctx, int64_t n_tiles, size_t lds_per_wg);
-// workgroups per CU of the 2D stream kernel and of the 3D z-marching kernel
-// (ECC_WG_PER_CU, ECC_ZM_WG_PER_CU; defaults 4 and 2)
-int wg_per_cu_default();
+// workgroups of the 2D stream kernel for a field
 int grid_2d(ecc_context ctx, const FieldInfo &fi, int window, bool classes);
+// workgroups per CU of the 3D z-marching kernel (ECC_ZM_WG_PER_CU, default 2)
 int zm_wg_per_cu();
 ecc_status merge_and_scan(ecc_context ctx, int grid, int nch, int L, int64_t *const outs[4], void *stream);
 void destroy_batch_state(ecc_context ctx);

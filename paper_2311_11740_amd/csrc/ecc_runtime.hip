@@ -350,7 +350,9 @@ static ThrEntry *find_thresholds(ecc_context ctx, const float *thr, int L, bool 
 // Frees the least recently fetched entry outside `keep`, preferring one that
 // no queued work reads any more; otherwise waits for the latest work that
 // reads it (never for the whole device).
-static ecc_status evict_threshold(ecc_context ctx, const std::vector<const ThrEntry *> &keep) {
+static ecc_status evict_threshold(ecc_context ctx, const std::vector<const ThrEntry *> &keep, void *stream) {
+    ecc_status s = use_stream(ctx, stream);
+    if (s != ECC_OK) return s;
     auto kept = [&keep](const ThrEntry *t) { return std::find(keep.begin(), keep.end(), t) != keep.end(); };
     auto idle = [](const ThrEntry *t) {
         return (!t->used || hipEventQuery(t->last_use) == hipSuccess) && hipEventQuery(t->ready) == hipSuccess;
@@ -364,8 +366,13 @@ static ecc_status evict_threshold(ecc_context ctx, const std::vector<const ThrEn
         }
     if (victim < 0) return fail(ECC_ERR_UNSUPPORTED, "threshold cache: nothing to evict");
     ThrEntry *t = ctx->thr_cache[victim];
-    int e = (int)hipEventSynchronize(t->ready);
-    if (!e && t->used) e = (int)hipEventSynchronize(t->last_use);
+    int e;
+    if (ctx->one_stream) {  // every use of the victim was queued on this one stream
+        e = (int)hipStreamSynchronize((hipStream_t)stream);
+    } else {
+        e = (int)hipEventSynchronize(t->ready);
+        if (!e && t->used) e = (int)hipEventSynchronize(t->last_use);
+    }
     if (e) return hip_fail(e, "hipEventSynchronize(thresholds)");
     free_thresholds(t);
     ctx->thr_cache.erase(ctx->thr_cache.begin() + victim);
@@ -403,7 +410,7 @@ ecc_status get_thresholds(ecc_context ctx, const float *thr, int L, bool neg, in
     hipStream_t st = (hipStream_t)stream;
     if (!hit) {
         if (ctx->thr_cache.size() >= kThrCacheMax) {
-            ecc_status s = evict_threshold(ctx, {});
+            ecc_status s = evict_threshold(ctx, {}, stream);
             if (s != ECC_OK) return s;
         }
         auto *t = new ThrEntry();
@@ -492,7 +499,7 @@ int count_distinct_thresholds(int n, const ecc_field *const *fields) {
     return count_distinct(n, fields, nullptr, false);
 }
 
-ecc_status reserve_thresholds(ecc_context ctx, int n, const ecc_field *const *fields) {
+ecc_status reserve_thresholds(ecc_context ctx, int n, const ecc_field *const *fields, void *stream) {
     if (count_distinct(n, fields, nullptr, false) > (int)kThrCacheMax)
         return fail(ECC_ERR_UNSUPPORTED, "one call may use at most 256 distinct threshold arrays");
     const int n_new = count_distinct(n, fields, ctx, true);
@@ -504,7 +511,7 @@ ecc_status reserve_thresholds(ecc_context ctx, int n, const ecc_field *const *fi
                     find_thresholds(ctx, a, fields[i]->n_levels, fields[i]->filtration == ECC_SUPERLEVEL))
                 keep.push_back(t);
     while (ctx->thr_cache.size() + (size_t)n_new > kThrCacheMax) {
-        ecc_status s = evict_threshold(ctx, keep);
+        ecc_status s = evict_threshold(ctx, keep, stream);
         if (s != ECC_OK) return s;
     }
     return ECC_OK;
@@ -512,6 +519,8 @@ ecc_status reserve_thresholds(ecc_context ctx, int n, const ecc_field *const *fi
 
 ecc_status note_threshold_use(ecc_context ctx, const LevelArgs &lv, void *stream) {
     if (!lv.thr) return ECC_OK;
+    ecc_status s = use_stream(ctx, stream);
+    if (s != ECC_OK || ctx->one_stream) return s;  // one stream: its order covers the use
     for (auto *t : ctx->thr_cache)
         if (t->d_thr == lv.thr) {
             int e = (int)hipEventRecord(t->last_use, (hipStream_t)stream);
@@ -564,7 +573,27 @@ ecc_status level_args(ecc_context ctx, const ecc_field *f, const FieldInfo &fi, 
 }
 
 // order work on `stream` after the previous use of the context's workspace
+ecc_status use_stream(ecc_context ctx, void *stream) {
+    if (!ctx->one_stream) return ECC_OK;
+    if (!ctx->solo_set) {
+        ctx->solo_set = true;
+        ctx->solo_stream = stream;
+        return ECC_OK;
+    }
+    if (stream == ctx->solo_stream) return ECC_OK;
+    // a second stream: everything queued so far (on the one stream) completes
+    // here, so no earlier use needs an event
+    int e = (int)hipDeviceSynchronize();
+    if (e) return hip_fail(e, "hipDeviceSynchronize");
+    ctx->one_stream = false;
+    ctx->ws_used = false;
+    for (auto *t : ctx->thr_cache) t->used = false;
+    return ECC_OK;
+}
+
 ecc_status acquire_workspace(ecc_context ctx, void *stream) {
+    ecc_status s = use_stream(ctx, stream);
+    if (s != ECC_OK) return s;
     if (ctx->ws_used && ctx->ws_stream != stream) {
         int e = (int)hipStreamWaitEvent((hipStream_t)stream, ctx->ws_event, 0);
         if (e) return hip_fail(e, "hipStreamWaitEvent");
@@ -573,8 +602,10 @@ ecc_status acquire_workspace(ecc_context ctx, void *stream) {
 }
 
 ecc_status release_workspace(ecc_context ctx, void *stream) {
-    int e = (int)hipEventRecord(ctx->ws_event, (hipStream_t)stream);
-    if (e) return hip_fail(e, "hipEventRecord");
+    if (!ctx->one_stream) {
+        int e = (int)hipEventRecord(ctx->ws_event, (hipStream_t)stream);
+        if (e) return hip_fail(e, "hipEventRecord");
+    }
     ctx->ws_used = true;
     ctx->ws_stream = stream;
     return ECC_OK;
@@ -598,16 +629,6 @@ int pick_grid(ecc_context ctx, int64_t n_tiles, size_t lds_per_wg) {
     if (g > n_tiles) g = n_tiles;
     if (g >= 8) g -= g % 8;
     return (int)std::max<int64_t>(1, g);
-}
-
-// Workgroups per CU for the field-reading kernels (environment ECC_WG_PER_CU overrides).
-int wg_per_cu_default() {
-    static int v = [] {
-        const char *e = std::getenv("ECC_WG_PER_CU");
-        int x = e ? std::atoi(e) : 4;
-        return x < 1 ? 1 : (x > 8 ? 8 : x);
-    }();
-    return v;
 }
 
 bool atomic_drain() {
@@ -664,17 +685,17 @@ ecc_status acc_buffer(ecc_context ctx, int nch, int L, int64_t **acc, void *stre
     return ECC_OK;
 }
 
-// Workgroups of the 2D stream kernel: wg_per_cu_default() per CU, fewer when
-// a workgroup's LDS (bins of a `window`-level pass, thresholds, tables) would
-// not let that many share a CU's 160 KB, and at most one per 32 (strip, row)
-// units of the field.
+// Workgroups of the 2D stream kernel (kWaves2D waves each): one per CU, and
+// at most one per 16 (strip, row) units per wave of the field.  (Its bins of
+// at most kMaxWindow levels plus thresholds and tables take under 50 KB of a
+// CU's 160 KB of LDS.)
 int grid_2d(ecc_context ctx, const FieldInfo &fi, int window, bool classes) {
+    (void)window;
+    (void)classes;
     const int vec = vec_2d(fi.dtype);
     const int64_t strips = (fi.w + 62 * vec - 1) / (62 * vec);
-    const size_t lds = lds_bytes_2d(window, classes) + (classes ? 4096 : 2048);
-    const int fit = std::max<int>(1, (int)((160 * 1024) / lds));
-    int grid = (int)std::min<int64_t>((int64_t)ctx->n_cu * std::min(wg_per_cu_default(), fit),
-                                      std::max<int64_t>(1, (strips * fi.h + 31) / 32));
+    int grid = (int)std::min<int64_t>((int64_t)ctx->n_cu,
+                                      std::max<int64_t>(1, (strips * fi.h + 16 * kWaves2D - 1) / (16 * kWaves2D)));
     if (grid >= 8) grid -= grid % 8;
     return grid;
 }

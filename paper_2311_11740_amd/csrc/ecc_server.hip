@@ -245,7 +245,7 @@ ecc_status launch_ready(ecc_server srv, std::vector<std::pair<Request *, ecc_sta
     if (!batch2d.empty()) {
         auto &L = srv->ring[li];
         std::vector<LevelArgs> lv(batch2d.size());
-        s = reserve_thresholds(ctx, (int)thr_fields.size(), thr_fields.data());
+        s = reserve_thresholds(ctx, (int)thr_fields.size(), thr_fields.data(), srv->s_2d);
         for (size_t i = 0; i < batch2d.size() && s == ECC_OK; ++i)
             s = level_args(ctx, &batch2d[i]->field, batch2d[i]->fi, srv->s_2d, &lv[i]);
         // group by (dimension, dtype, level mode); one schedule per group,

@@ -318,3 +318,65 @@ def test_first_call_of_fresh_context_on_side_stream():
         assert np.array_equal(ra[k].cpu().numpy(), oa[k]), k
     for k in rb:
         assert np.array_equal(rb[k].cpu().numpy(), ob[k]), k
+
+
+def test_stream_switch_keeps_calls_ordered():
+    """A context's calls on one stream record no ordering events; the first
+    call on a second stream (queued while the first stream is still busy) and
+    the calls that alternate between the two afterwards are all exact."""
+    import torch
+    import oracle
+    from paper_2311_11740_amd import ecc, synth
+    vol = synth.quantise(synth.grf((96, 128, 256), 3.0, 31), 4096)
+    imgs = [synth.quantise(synth.grf((700 + 37 * i, 900 - 41 * i), 4.0, 40 + i), 256) for i in range(5)]
+    print("[case] stream switch: 3D then 2D fields alternating over two streams", flush=True)
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    dv = torch.from_numpy(vol).cuda()
+    di = [torch.from_numpy(a).cuda() for a in imgs]
+    torch.cuda.synchronize()
+    c = ecc.Context(0)
+    try:
+        got = []
+        with torch.cuda.stream(s1):
+            got.append(c.compute(dv, 4096, connectivity=26, stream=s1, channels=("ec", "area", "volume")))
+            got.append(c.compute(di[0], 256, stream=s1))
+        for i in range(1, 5):  # no host synchronisation between the calls
+            s = s2 if i % 2 else s1
+            with torch.cuda.stream(s):
+                got.append(c.compute(di[i], 256, stream=s))
+        with torch.cuda.stream(s2):
+            got.append(c.compute(dv, 4096, connectivity=26, stream=s2, channels=("ec", "area", "volume")))
+        torch.cuda.synchronize()
+    finally:
+        c.close()
+    ref3 = oracle.o2_curves(vol, 4096, connectivity=26, channels=("ec", "area", "volume"))
+    refs = [ref3] + [oracle.o2_curves(a, 256) for a in imgs] + [ref3]
+    for k, (g, r) in enumerate(zip(got, refs)):
+        for ch in g:
+            assert np.array_equal(g[ch].cpu().numpy(), r[ch]), (k, ch)
+
+
+def test_threshold_cache_eviction_on_one_stream():
+    """More distinct threshold arrays than the cache holds, queued on one
+    stream with no host synchronisation: evictions wait for the stream, and
+    every result is exact."""
+    import torch
+    import oracle
+    from paper_2311_11740_amd import ecc
+    rng = np.random.default_rng(32)
+    n = 300
+    fields = [rng.normal(size=(40, 70)).astype(np.float32) for _ in range(n)]
+    thrs = [np.sort(rng.normal(size=12)).astype(np.float32) for _ in range(n)]
+    print(f"[case] {n} distinct threshold arrays on one stream", flush=True)
+    dev = [torch.from_numpy(a).cuda() for a in fields]
+    torch.cuda.synchronize()
+    c = ecc.Context(0)
+    try:
+        got = [c.compute(dev[i], 12, thresholds=thrs[i]) for i in range(n)]
+        torch.cuda.synchronize()
+    finally:
+        c.close()
+    for i in range(n):
+        ref = oracle.o2_curves(fields[i], 12, thresholds=thrs[i])
+        for ch in got[i]:
+            assert np.array_equal(got[i][ch].cpu().numpy(), ref[ch]), (i, ch)
