@@ -504,7 +504,9 @@ static int64_t max_wg_cells_2d(int64_t rows, int64_t w, int vec, int grid) {
 
 template <typename T, int LM, int AL, bool CLS>
 static int launch_2d_t(const Launch2D &a, hipStream_t s) {
-    constexpr int VEC = Elem<T>::VEC, PF = sizeof(T) == 1 ? 3 : 6;
+    // rows in flight per wave: fewer for the variants with the most registers
+    // per row (the 16-wave workgroup allows 128 VGPRs)
+    constexpr int VEC = Elem<T>::VEC, PF = (sizeof(T) == 1 || LM == LM_LUT) ? 3 : 6;
     const int W = a.hi - a.lo;
     // the packed LDS bins of one workgroup may see at most kFlush2D (class
     // counts: kFlushCls) cells: split tall fields into row chunks that respect

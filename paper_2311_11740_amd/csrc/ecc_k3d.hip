@@ -354,9 +354,14 @@ struct March3D {
     const uint32_t *tc;  // CR: per-plane crease deltas + 4
     uint32_t hc_base;    // CR: LDS address of the crease word of bin 0 (4 bytes per bin)
 
-    uint32_t R[3][NR][VEC + 1];  // level planes; R[(z - za + 1) % 3] holds plane z
-    uint32_t C[TY][VEC];         // carry from the voxel below each voxel of the current plane
-    RawRow3 ring[3][NR];         // raw rows of upcoming planes; ring[(z - za) % 3] holds plane z + 1
+    // Buffers rotate with period NB: three level planes with the crease
+    // channel (it needs plane z - 1), two without (one fewer plane and one
+    // fewer plane of loads in flight keep the registers under 168, three
+    // waves per SIMD)
+    static constexpr int NB = CR ? 3 : 2;
+    uint32_t R[NB][NR][VEC + 1];  // level planes; R[(z - za + 1) % NB] holds plane z
+    uint32_t C[TY][VEC];          // carry from the voxel below each voxel of the current plane
+    RawRow3 ring[NB][NR];         // raw rows of upcoming planes; ring[(z - za) % NB] holds plane z + 1
 
     __device__ __forceinline__ int clampz(int z) const { return z < 0 ? 0 : (z >= d ? d - 1 : z); }
     __device__ __forceinline__ int clampy(int y) const { return y < 0 ? 0 : (y >= (int)h ? (int)h - 1 : y); }
@@ -401,7 +406,7 @@ struct March3D {
             fetch_plane(za - 1, a);
             fetch_plane(za, b);
 #pragma unroll
-            for (int k = 0; k < 3; ++k) fetch_plane(za + 1 + k < zb ? za + 1 + k : zb, ring[k]);
+            for (int k = 0; k < NB; ++k) fetch_plane(za + 1 + k < zb ? za + 1 + k : zb, ring[k]);
             convert_plane(za - 1, a, R[0]);
             convert_plane(za, b, R[1]);
         }
@@ -424,11 +429,13 @@ struct March3D {
     // voxels of plane z, with K = (z - za) % 3
     template <int K>
     __device__ __forceinline__ void step(int z) {
-        uint32_t(&Pp)[NR][VEC + 1] = R[K];
-        uint32_t(&Pc)[NR][VEC + 1] = R[(K + 1) % 3];
-        uint32_t(&Pn)[NR][VEC + 1] = R[(K + 2) % 3];
+        // (with NB = 2, plane z + 1 replaces plane z - 1, which only the
+        // crease channel reads)
+        uint32_t(&Pp)[NR][VEC + 1] = R[K % NB];
+        uint32_t(&Pc)[NR][VEC + 1] = R[(K + 1) % NB];
+        uint32_t(&Pn)[NR][VEC + 1] = R[(K + 2) % NB];
         convert_plane(z + 1, ring[K], Pn);
-        fetch_plane(z + 4 < zb ? z + 4 : zb, ring[K]);
+        fetch_plane(z + 1 + NB < zb ? z + 1 + NB : zb, ring[K]);
         uint32_t M[NR][VEC + 1];
         image(Pc, Pn, M);
         (void)Pp;
@@ -487,21 +494,24 @@ struct March3D {
     __device__ __forceinline__ void run(int za, ProgressPrio &pp, int64_t done0) {
         prologue(za);
         int z = za;
-        for (; z + 3 <= zb; z += 3) {
+        for (; z + NB <= zb; z += NB) {
             pp.update(done0 + (z - za));
             step<0>(z);
             step<1>(z + 1);
-            step<2>(z + 2);
+            if constexpr (NB == 3) step<2>(z + 2);
         }
         if (z < zb) step<0>(z);
-        if (z + 1 < zb) step<1>(z + 1);
+        if constexpr (NB == 3)
+            if (z + 1 < zb) step<1>(z + 1);
     }
 };
 
 // Work split: units (column, z) with column = (strip, block of TY rows), z
-// fastest, in equal contiguous ranges per wave.
+// fastest, in equal contiguous ranges per wave.  Integer fields at aligned
+// addresses without the crease channel hold their registers to three waves
+// per SIMD (the other variants would spill).
 template <typename T, int LM, int AL, bool MAXIMG, bool CR, int TY>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(256, (!CR && sizeof(T) < 4 && AL == kLoadAligned) ? 3 : 2)
     ecc3d_stream(const T *__restrict__ data, int64_t d, int64_t h, int64_t w, LevelArgs lv, int32_t lo,
                  int32_t hi, float cpass, const uint32_t *__restrict__ tables,
                  const uint32_t *__restrict__ crease_table, int32_t *__restrict__ partial, int64_t z_lo,

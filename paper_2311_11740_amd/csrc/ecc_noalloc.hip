@@ -68,7 +68,7 @@ extern "C" ecc_status ecc_curves_compute_noalloc(ecc_context ctx, const ecc_fiel
     int e = (int)hipSetDevice(ctx->device);
     if (e) return hip_fail(e, "hipSetDevice");
     if (!ctx->scratch) return fail(ECC_ERR_DEVICE, "the context has no scratch array");
-    const OnePlan p = plan_one(ctx, fi, curves);
+    const OnePlan p = plan_one(ctx, fi, curves, field->data);
     const bool use_acc = atomic_drain() && (fi.ndim == 2 || p.zmarch);
     const size_t acc_bytes = (size_t)kAccCopies * p.nch * fi.L * sizeof(int64_t);
     const size_t tot_off = kOffTotals;

@@ -148,7 +148,7 @@ struct OnePlan {
     bool zmarch, crease;
     size_t partial_bytes, totals_bytes;
 };
-OnePlan plan_one(ecc_context ctx, const FieldInfo &fi, const ecc_curves *c);
+OnePlan plan_one(ecc_context ctx, const FieldInfo &fi, const ecc_curves *c, const void *data);
 ecc_status compute_core(ecc_context ctx, const ecc_field *f, const FieldInfo &fi, const ecc_curves *c,
                         const LevelArgs &lv, const OnePlan &p, int32_t *partial, int64_t *totals,
                         unsigned *counter, void *stream, bool timing, int64_t *acc = nullptr);
@@ -160,8 +160,9 @@ bool affine_levels(const float *thr, int L, float *u0, double *u0d, float *inv_s
 int pick_grid(ecc_context ctx, int64_t n_tiles, size_t lds_per_wg);
 // workgroups of the 2D stream kernel for a field
 int grid_2d(ecc_context ctx, const FieldInfo &fi, int window, bool classes);
-// workgroups per CU of the 3D z-marching kernel (ECC_ZM_WG_PER_CU, default 2)
-int zm_wg_per_cu();
+// workgroups per CU of the 3D z-marching kernel for a field (ECC_ZM_WG_PER_CU
+// overrides)
+int zm_wg_per_cu(int dtype, int64_t w, const void *data, bool crease);
 ecc_status merge_and_scan(ecc_context ctx, int grid, int nch, int L, int64_t *const outs[4], void *stream);
 void destroy_batch_state(ecc_context ctx);
 void destroy_stream_state(ecc_context ctx);

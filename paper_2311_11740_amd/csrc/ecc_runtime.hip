@@ -647,14 +647,22 @@ bool progress_prio() {
     return v;
 }
 
-// Workgroups per CU for the z-marching 3D kernel (environment ECC_ZM_WG_PER_CU overrides).
-int zm_wg_per_cu() {
-    static int v = [] {
+// Workgroups per CU for the z-marching 3D kernel: as many 4-wave workgroups
+// as its register use lets share a CU (three for integer fields at aligned
+// addresses without the crease channel, else two); environment
+// ECC_ZM_WG_PER_CU overrides.  `data` NULL stands for an aligned address.
+int zm_wg_per_cu(int dtype, int64_t w, const void *data, bool crease) {
+    static int env = [] {
         const char *e = std::getenv("ECC_ZM_WG_PER_CU");
-        int x = e ? std::atoi(e) : 2;
+        if (!e) return 0;
+        int x = std::atoi(e);
         return x < 1 ? 1 : (x > 8 ? 8 : x);
     }();
-    return v;
+    if (env) return env;
+    const int eb = dtype == ECC_U8 ? 1 : (dtype == ECC_U16 ? 2 : 4);
+    const int vb = 4 * eb;  // bytes of one lane's block
+    const bool aligned = (uintptr_t)data % vb == 0 && (w * eb) % vb == 0;
+    return (!crease && eb < 4 && aligned) ? 3 : 2;
 }
 
 ecc_status merge_and_scan(ecc_context ctx, int grid, int nch, int L, int64_t *const outs[4],
@@ -701,7 +709,7 @@ int grid_2d(ecc_context ctx, const FieldInfo &fi, int window, bool classes) {
 }
 
 // Launch geometry of one field on the single-field path.
-OnePlan plan_one(ecc_context ctx, const FieldInfo &fi, const ecc_curves *c) {
+OnePlan plan_one(ecc_context ctx, const FieldInfo &fi, const ecc_curves *c, const void *data) {
     OnePlan p;
     const int L = fi.L;
     p.nch = fi.ndim == 2 ? 3 : 4;
@@ -713,12 +721,12 @@ OnePlan plan_one(ecc_context ctx, const FieldInfo &fi, const ecc_curves *c) {
     if (fi.ndim == 2) {
         p.grid = grid_2d(ctx, fi, p.win, false);
     } else {
-        // z-marching kernel: at least ~16 planes per wave; its register use
-        // leaves room for two 4-wave workgroups per CU, so one round of
-        // 2 x CUs workgroups (fewer partials than more, smaller rounds); the
-        // crease channel, when wanted, comes along in the same kernel.
+        // z-marching kernel: at least ~16 planes per wave; one round of as
+        // many 4-wave workgroups as its register use lets share each CU
+        // (fewer drains than more, smaller rounds); the crease channel, when
+        // wanted, comes along in the same kernel.
         const int64_t units = (int64_t)zmarch_3d_columns(fi.h, fi.w) * fi.d;
-        p.grid = (int)std::min<int64_t>((int64_t)ctx->n_cu * zm_wg_per_cu(),
+        p.grid = (int)std::min<int64_t>((int64_t)ctx->n_cu * zm_wg_per_cu(fi.dtype, fi.w, data, p.crease),
                                         std::max<int64_t>(1, (units + 63) / 64));
         if (p.grid >= 8) p.grid -= p.grid % 8;
         // A volume too small to give every CU a z-marching workgroup (its
@@ -794,7 +802,7 @@ ecc_status compute_one(ecc_context ctx, const ecc_field *f, const FieldInfo &fi,
     LevelArgs lv;
     ecc_status s = level_args(ctx, f, fi, stream, &lv);
     if (s != ECC_OK) return s;
-    const OnePlan p = plan_one(ctx, fi, c);
+    const OnePlan p = plan_one(ctx, fi, c, f->data);
     s = grow(ctx, ctx->ws.partial, p.partial_bytes, "partials");
     if (s != ECC_OK) return s;
     s = grow(ctx, ctx->ws.totals, p.totals_bytes, "totals");

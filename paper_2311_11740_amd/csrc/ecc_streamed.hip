@@ -109,7 +109,9 @@ ecc_status stream_field(ecc_context ctx, const ecc_field *f, const FieldInfo &fi
     int grid;
     if (is3) {
         const int64_t units = (int64_t)zmarch_3d_columns(fi.h, fi.w) * R;
-        grid = (int)std::min<int64_t>((int64_t)ctx->n_cu * zm_wg_per_cu(), std::max<int64_t>(1, (units + 63) / 64));
+        // (the slab buffers are device allocations: aligned)
+        grid = (int)std::min<int64_t>((int64_t)ctx->n_cu * zm_wg_per_cu(fi.dtype, fi.w, nullptr, crease),
+                                      std::max<int64_t>(1, (units + 63) / 64));
         if (grid >= 8) grid -= grid % 8;
         if (!zmarch_3d_fits(fi.h, fi.w, grid))
             return fail(ECC_ERR_UNSUPPORTED, "streamed 3D fields: planes too large for the z-marching kernel");
