@@ -504,6 +504,62 @@ __device__ __forceinline__ void acc_add(int64_t *p, int64_t v) {
                                   __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Fields of a batched launch split over several workgroups: each workgroup
+// adds its bins into the field's int32 histogram [nch][L] with device-scope
+// atomics, then takes the field's ticket; the workgroup that takes the last
+// one scans.  Those adds are atomics, performed where every XCD sees them, so
+// a workgroup only waits until its own have completed before it takes the
+// ticket (no L2 write-back, which per work item cost more than the item), and
+// the elected workgroup reads and clears the histogram with device-scope
+// exchanges, which see every completed add.
+__device__ __forceinline__ bool take_field_ticket(uint32_t *done, int n_items) {
+    __shared__ int s_last;
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    __builtin_amdgcn_s_waitcnt(0);  // this thread's adds have completed
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    __syncthreads();
+    if (threadIdx.x == 0)
+        s_last = __hip_atomic_fetch_add(done, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ==
+                 (uint32_t)(n_items - 1);
+    __syncthreads();
+    return s_last != 0;
+}
+
+// The elected workgroup (256 threads): the field's histogram [nch][L] ->
+// running sums over levels into out[ch] (NULL: skipped), histogram and ticket
+// left at zero.  `stage` is LDS for L int64, `part` LDS for 256 int64.
+__device__ __forceinline__ void scan_field_hist(int32_t *__restrict__ hist, int nch, int L, int64_t *const *out,
+                                                int64_t *stage, int64_t *part, uint32_t *done) {
+    const int tid = threadIdx.x;
+    const int per = (L + 255) / 256;
+    const int beg = tid * per < L ? tid * per : L, end = beg + per < L ? beg + per : L;
+    for (int ch = 0; ch < nch; ++ch) {
+        int *src = reinterpret_cast<int *>(hist) + (int64_t)ch * L;
+        for (int l = tid; l < L; l += 256)
+            stage[l] = __hip_atomic_exchange(src + l, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __syncthreads();
+        int64_t *dst = out[ch];
+        int64_t s = 0;
+        for (int i = beg; i < end; ++i) s += stage[i];
+        part[tid] = s;
+        __syncthreads();
+        for (int off = 1; off < 256; off <<= 1) {  // inclusive scan of the chunk sums
+            const int64_t v = tid >= off ? part[tid - off] : 0;
+            __syncthreads();
+            part[tid] += v;
+            __syncthreads();
+        }
+        int64_t run = part[tid] - s;
+        if (dst)  // uniform
+            for (int i = beg; i < end; ++i) {
+                run += stage[i];
+                dst[i] = run;
+            }
+        __syncthreads();  // stage and part are reused
+    }
+    if (tid == 0) __hip_atomic_store(done, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // Running sums over levels of the per-level totals [nch][L] into the caller's
 // curves (channels with a NULL output skipped), by one whole workgroup of at
 // most 16 waves: each thread sums a chunk of levels, the chunk sums are

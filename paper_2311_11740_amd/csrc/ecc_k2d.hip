@@ -384,7 +384,6 @@ __global__ void __launch_bounds__(256)
     extern __shared__ uint64_t smem[];
     __shared__ uint64_t dl[2][256];
     __shared__ int64_t part[256];
-    __shared__ int last;
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     dl[0][tid] = luts[tid];
@@ -445,40 +444,10 @@ __global__ void __launch_bounds__(256)
             if (per) atomicAdd(dst + L, (int32_t)per);
             atomicAdd(dst + 2 * L, (int32_t)cnt);
         }
-        // publish (every thread's atomics), take the field's ticket
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-        __syncthreads();
-        if (tid == 0)
-            last = __hip_atomic_fetch_add(f.done, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT) ==
-                   (uint32_t)(f.n_items - 1);
-        __syncthreads();
-        if (last) {  // uniform: scan the field's histogram into its curves and clear it
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-            const int per = (L + 255) / 256;
-            const int beg = tid * per, end = beg + per < L ? beg + per : L;
-            for (int ch = 0; ch < 3; ++ch) {
-                int32_t *src = f.hist + (int64_t)ch * L;
-                int64_t *dst = f.out[ch];
-                int64_t s = 0;
-                for (int i = beg; i < end; ++i) s += src[i];
-                part[tid] = s;
-                __syncthreads();
-                for (int off = 1; off < 256; off <<= 1) {  // inclusive scan of the chunk sums
-                    const int64_t v = tid >= off ? part[tid - off] : 0;
-                    __syncthreads();
-                    part[tid] += v;
-                    __syncthreads();
-                }
-                int64_t run = part[tid] - s;
-                for (int i = beg; i < end; ++i) {
-                    run += src[i];
-                    src[i] = 0;
-                    if (dst) dst[i] = run;
-                }
-                __syncthreads();
-            }
-            if (tid == 0) *f.done = 0u;
-        }
+        // the workgroup that adds last scans the field's histogram into its
+        // curves (and clears it)
+        if (take_field_ticket(f.done, f.n_items))  // uniform
+            scan_field_hist(f.hist, 3, L, f.out, reinterpret_cast<int64_t *>(smem), part, f.done);
     }
 }
 
