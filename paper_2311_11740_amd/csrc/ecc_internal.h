@@ -31,7 +31,6 @@ void crease_delta_table_2d(int32_t delta[256]);
 // orbits under the cube's 48 symmetries ordered by (voxels, smallest mask)
 int octant_class_3d(int mask);
 constexpr int kNumClasses3D = 21;
-constexpr int kClsWindow3D = 512;  // levels per pass of the 3D class-count kernel
 // The kernels index per-cell tables by a permuted pattern: index bit i (i < 4)
 // is neighbour 2i and bit 4+i neighbour 2i+1 of kNbr2.  Returns the kNbr2-order
 // pattern of kernel index n.
@@ -146,9 +145,6 @@ struct Launch3D {
     // whether to add to the partials instead of overwriting them
     int64_t z_lo, z_hi;
     bool accumulate;
-    // vertex class counts (tile kernel): vtab holds the class of each octant
-    // mask and partial is [kNumClasses3D][L][grid]
-    bool classes;
     // z-marching kernel: the per-plane crease table when the crease channel
     // is wanted (it then comes along in the same launch), else NULL
     const uint32_t *crease_table;
@@ -157,6 +153,26 @@ struct Launch3D {
     // atomic drain (z-marching kernel): int64 accumulators [kAccCopies][4][L]
     int64_t *acc = nullptr;
 };
+
+// 3D vertex class counts (ecc_k3d_cls.hip): one pass over the levels [lo, hi)
+// of a volume; each workgroup adds its bins into the accumulator copy of its
+// XCD.
+struct Launch3DClasses {
+    const void *data;
+    int dtype;
+    int64_t d, h, w;
+    LevelArgs lv;
+    int32_t lo, hi;
+    const uint16_t *trans;  // device, [8][256]: corner c, block mask -> new class | old class << 8 (0xFF empty)
+    int64_t *acc;           // device, [kAccCopies][kNumClasses3D][L] int64
+    int grid;
+    void *ev_start = nullptr, *ev_stop = nullptr;
+};
+int launch_classes_3d(const Launch3DClasses &a, void *stream);
+// LDS of the class-count kernel besides its W x kNumClasses3D int32 bins
+size_t lds_fixed_classes_3d();
+// per-corner class transitions of the class-count kernel, [8][256] (host)
+void class_transitions_3d(uint16_t out[8][256]);
 
 // ---- batched 2D launch ----------------------------------------------------------
 // One descriptor per field of the batch (device memory, rewritten every call).
@@ -246,6 +262,8 @@ constexpr int kAccCopies = 8;
 // leaves the accumulators at zero
 int launch_merge_acc(int64_t *acc, int copies, int nch, int L, int64_t *const out[4], int64_t *totals,
                      unsigned *counter, void *stream);
+// the same for up to 64 channels of at most 4096 levels, into rows[ch][L]
+int launch_merge_acc_rows(int64_t *acc, int nch, int L, int64_t *rows, void *stream);
 // whether the curve kernels (2D stream, 3D z-marching) drain their bins with
 // atomics into per-XCD accumulators (default) instead of writing per-workgroup
 // partials for a merge kernel to sum (environment ECC_DRAIN=partials)

@@ -580,37 +580,20 @@ __global__ void __launch_bounds__(256, (!CR && sizeof(T) < 4 && AL == kLoadAlign
 }
 
 
-// 3D class-count bins [level][class] (int32) -> partials [class][level][workgroup]
-__device__ __forceinline__ void drain_cls3(int32_t *hcls, int W, int lo, int L, int G, int wg,
-                                           int32_t *__restrict__ partial, bool first) {
-    for (int i = threadIdx.x; i < W * kNumClasses3D; i += blockDim.x) {
-        const int b = i / kNumClasses3D, c = i - b * kNumClasses3D;
-        const int32_t v = hcls[i];
-        hcls[i] = 0;
-        const int64_t idx = ((int64_t)c * L + lo + b) * G + wg;
-        if (first)
-            partial[idx] = v;
-        else
-            partial[idx] += v;
-    }
-}
-
 // ---------------------------------------------------------------------------
 // 3D (generic: every channel, table lookups over the 8 corner blocks)
 // ---------------------------------------------------------------------------
 // One tile of TX x TY x TZ voxels: its levels and a one-voxel halo are staged
 // into LDS, then each of the 256 threads walks its (x, y) column up the
 // tile's planes with a 3x3x3 window.  MODE 0: EC, surface, volume; 1: also
-// the crease; 2: vertex class counts (vt then holds the class of each octant
-// mask, -1 for empty, and each corner adds +1 to its new class and -1 to its
-// old one in the cell's bin).  Cells whose level is outside the window
-// [lo, lo + W) add nothing.  Starts and ends with the workgroup in step.
+// the crease.  Cells whose level is outside the window [lo, lo + W) add
+// nothing.  Starts and ends with the workgroup in step.
 typedef uint16_t TileLevels[kTile3DZ + 2][kTile3DY + 2][kTile3DX + 2];
 
 template <typename T, int LM, int MODE>
 __device__ __forceinline__ void tile_3d(const T *__restrict__ data, int64_t d, int64_t h, int64_t w,
                                         const LevelArgs &lv, int lo, int W, const int64_t *vt, TileLevels &lam,
-                                        uint64_t *hist, uint32_t *hc, int32_t *hcls, int64_t x0, int64_t y0,
+                                        uint64_t *hist, uint32_t *hc, int64_t x0, int64_t y0,
                                         int64_t z0) {
     constexpr bool CREASE = MODE == 1;
     constexpr int TX = kTile3DX, TY = kTile3DY, TZ = kTile3DZ;
@@ -659,20 +642,7 @@ __device__ __forceinline__ void tile_3d(const T *__restrict__ data, int64_t d, i
             // corner (cz,cy,cx) of p: its 2x2x2 block holds the neighbours
             // with offsets in {c-1, c} per axis; gather them into the
             // octant mask (bit bx + 2by + 4bz), with and without p
-            if constexpr (MODE == 2) {
-                int32_t *row = hcls + (p - lo) * kNumClasses3D;
-#pragma unroll
-                for (int c = 0; c < 8; ++c) {
-                    const int cx = c & 1, cy = c >> 1 & 1, cz = c >> 2;
-                    const uint32_t y = P >> (cz * 9 + cy * 3 + cx);
-                    const uint32_t m1 = (y & 3u) | ((y >> 1) & 0xCu) | ((y >> 5) & 0x30u) | ((y >> 6) & 0xC0u);
-                    const uint32_t m0 = m1 & ~(1u << (7 - c));
-                    const int cn = (int)vt[m1], co = (int)vt[m0];
-                    atomicAdd(&row[cn], 1);
-                    if (co >= 0) atomicAdd(&row[co], -1);
-                }
-                continue;
-            } else {
+            {
                 int64_t acc = 0;
 #pragma unroll
                 for (int c = 0; c < 8; ++c) {
@@ -717,19 +687,14 @@ __global__ void __launch_bounds__(256)
     const int L = lv.L;
     uint64_t *hist = smem;
     uint32_t *hc = reinterpret_cast<uint32_t *>(smem + W);
-    int32_t *hcls = reinterpret_cast<int32_t *>(smem);  // MODE 2: [W][kNumClasses3D]
     const int G = gridDim.x;
     const int wg = xcd_order(blockIdx.x, G);
     const int64_t t_beg = n_tiles * wg / G, t_end = n_tiles * (wg + 1) / G;
 
     vt[t] = vtab[t];
-    if constexpr (MODE == 2) {
-        for (int b = t; b < W * kNumClasses3D; b += 256) hcls[b] = 0;
-    } else {
-        for (int b = t; b < W; b += 256) {
-            hist[b] = 0;
-            if (CREASE) hc[b] = 0;
-        }
+    for (int b = t; b < W; b += 256) {
+        hist[b] = 0;
+        if (CREASE) hc[b] = 0;
     }
     bool first = true;
     int since = 0;
@@ -739,21 +704,15 @@ __global__ void __launch_bounds__(256)
         const int64_t x0 = (tile % tiles_x) * kTile3DX;
         const int64_t y0 = ((tile / tiles_x) % tiles_y) * kTile3DY;
         const int64_t z0 = (tile / (tiles_x * tiles_y)) * kTile3DZ;
-        tile_3d<T, LM, MODE>(data, d, h, w, lv, lo, W, vt, lam, hist, hc, hcls, x0, y0, z0);
+        tile_3d<T, LM, MODE>(data, d, h, w, lv, lo, W, vt, lam, hist, hc, x0, y0, z0);
         if (++since >= flush_tiles) {
-            if constexpr (MODE == 2)
-                drain_cls3(hcls, W, lo, L, G, wg, partial, first);
-            else
-                drain_3d(hist, hc, CREASE, W, lo, L, G, wg, partial, first);
+            drain_3d(hist, hc, CREASE, W, lo, L, G, wg, partial, first);
             first = false;
             since = 0;
             __syncthreads();
         }
     }
-    if constexpr (MODE == 2)
-        drain_cls3(hcls, W, lo, L, G, wg, partial, first);
-    else
-        drain_3d(hist, hc, CREASE, W, lo, L, G, wg, partial, first);
+    drain_3d(hist, hc, CREASE, W, lo, L, G, wg, partial, first);
 }
 
 // ---------------------------------------------------------------------------
@@ -1173,7 +1132,7 @@ static int launch_3d_t(const Launch3D &a, hipStream_t s) {
     const int64_t n_tiles = tiles_x * tiles_y * tiles_z;
     const int flush = (int)(kFlush3D / (kTile3DX * kTile3DY * kTile3DZ));
     const int W = a.hi - a.lo;
-    const size_t lds = MODE == 2 ? (size_t)W * kNumClasses3D * 4 : lds_bytes_3d(W, MODE == 1);
+    const size_t lds = lds_bytes_3d(W, MODE == 1);
     hipExtLaunchKernelGGL((ecc3d_tile<T, LM, MODE>), dim3(a.grid), dim3(256), lds, s, (hipEvent_t)a.ev_start,
                           (hipEvent_t)a.ev_stop, 0, (const T *)a.data, a.d, a.h, a.w, a.lv, a.lo, a.hi, a.vtab,
                           a.partial, tiles_x, tiles_y, n_tiles, flush);
@@ -1234,7 +1193,6 @@ static int launch_zm_al(const Launch3D &a, hipStream_t s) {
 
 template <typename T, int LM>
 static int launch_3d_cr(const Launch3D &a, hipStream_t s) {
-    if (a.classes) return launch_3d_t<T, LM, 2>(a, s);
     if (a.zm_tables) return a.conn6 ? launch_zm_al<T, LM, true>(a, s) : launch_zm_al<T, LM, false>(a, s);
     return a.want_crease ? launch_3d_t<T, LM, 1>(a, s) : launch_3d_t<T, LM, 0>(a, s);
 }

@@ -36,96 +36,71 @@ __global__ void __launch_bounds__(1024)
     if (threadIdx.x == 0) *counter = 0u;  // ready for the next merge
 }
 
-// Sums the kAccCopies accumulator copies of every bin into totals (and
-// clears them), one thread per bin; the last block to finish scans the
-// totals into the curves.
-__global__ void __launch_bounds__(1024)
-    ecc_merge_acc(int64_t *__restrict__ acc, int nch, int L, OutPtrs out, int64_t *__restrict__ totals,
-                  unsigned *__restrict__ counter) {
-    __shared__ bool last;
-    const int64_t n_bins = (int64_t)nch * L;
-    for (int64_t bin = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; bin < n_bins;
-         bin += (int64_t)gridDim.x * blockDim.x) {
-        // all copies' loads in flight at once (one memory latency, not one per copy)
-        int64_t v[kAccCopies];
-#pragma unroll
-        for (int c = 0; c < kAccCopies; ++c) v[c] = acc[c * n_bins + bin];
-        int64_t s = 0;
-#pragma unroll
-        for (int c = 0; c < kAccCopies; ++c) {
-            s += v[c];
-            acc[c * n_bins + bin] = 0;
-        }
-        totals[bin] = s;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0)
-        last = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT) == gridDim.x - 1;
-    __syncthreads();
-    if (!last) return;
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    scan_totals_block(totals, nch, L, out);
-    if (threadIdx.x == 0) *counter = 0u;
-}
-
-// The same for at most kMergeChMaxLevels levels, one block per channel: the
-// block sums the copies of its channel's bins (every load of a thread in
-// flight at once), clears them, keeps the per-level totals in LDS and writes
-// the running sums.  Blocks share nothing, so there is no ticket and no
-// device-scope fence.
-constexpr int kMergeChMaxLevels = 4096;
+// Sums the kAccCopies accumulator copies of every bin (and clears them) and
+// scans, one block per channel: the block sums the copies of its
+// channel's bins in chunks of kMergeChChunk levels (every load of a thread in
+// flight at once), clears them, keeps the chunk's per-level totals in LDS and
+// writes the running sums, carried from chunk to chunk.  Blocks share nothing,
+// so there is no ticket and no device-scope fence.
+constexpr int kMergeChChunk = 4096;
 constexpr int kMergeChThreads = 1024;
 __global__ void __launch_bounds__(kMergeChThreads)
-    ecc_merge_acc_ch(int64_t *__restrict__ acc, int nch, int L, OutPtrs out) {
-    constexpr int PER = kMergeChMaxLevels / kMergeChThreads;  // levels per thread and pass
-    __shared__ int64_t tot[kMergeChMaxLevels];
+    ecc_merge_acc_ch(int64_t *__restrict__ acc, int nch, int L, OutPtrs out, int64_t *__restrict__ rows) {
+    constexpr int PER = kMergeChChunk / kMergeChThreads;  // levels per thread and chunk
+    __shared__ int64_t tot[kMergeChChunk];
     __shared__ int64_t wsum[kMergeChThreads / 64];
     const int ch = blockIdx.x, t = threadIdx.x, lane = t & 63, wave = t >> 6;
     const unsigned nb = (unsigned)(nch * L);  // 32-bit offsets from one base: scalar-base loads
     int64_t *a = acc + (int64_t)ch * L;
-    // unconditional loads and stores at indices wrapped into [0, L) (a
-    // conditional load would be waited for before the next one is issued);
-    // wrapped duplicates are not counted, and they spread over the bins
-    unsigned lc[PER];
+    int64_t *dst = rows ? rows + (int64_t)ch * L : out.p[ch];
+    int64_t carry = 0;  // running sum of the earlier chunks
+    for (int l0 = 0; l0 < L; l0 += kMergeChChunk) {
+        const int n = L - l0 < kMergeChChunk ? L - l0 : kMergeChChunk;
+        // unconditional loads and stores at indices wrapped into the chunk (a
+        // conditional load would be waited for before the next one is
+        // issued); wrapped duplicates are not counted
+        unsigned lc[PER];
 #pragma unroll
-    for (int i = 0; i < PER; ++i) lc[i] = (unsigned)((i * kMergeChThreads + t) % L);
-    int64_t v[kAccCopies][PER];
+        for (int i = 0; i < PER; ++i) lc[i] = (unsigned)(l0 + (i * kMergeChThreads + t) % n);
+        int64_t v[kAccCopies][PER];
 #pragma unroll
-    for (int c = 0; c < kAccCopies; ++c)
+        for (int c = 0; c < kAccCopies; ++c)
 #pragma unroll
-        for (int i = 0; i < PER; ++i) v[c][i] = __builtin_nontemporal_load(a + c * nb + lc[i]);
+            for (int i = 0; i < PER; ++i) v[c][i] = __builtin_nontemporal_load(a + c * nb + lc[i]);
 #pragma unroll
-    for (int i = 0; i < PER; ++i) {
-        int64_t s = 0;
+        for (int i = 0; i < PER; ++i) {
+            int64_t s = 0;
 #pragma unroll
-        for (int c = 0; c < kAccCopies; ++c) s += v[c][i];
-        if (i * kMergeChThreads + t < L) tot[i * kMergeChThreads + t] = s;
-    }
-    __syncthreads();  // every thread has read its copies before any is cleared
+            for (int c = 0; c < kAccCopies; ++c) s += v[c][i];
+            if (i * kMergeChThreads + t < n) tot[i * kMergeChThreads + t] = s;
+        }
+        __syncthreads();  // every thread has read its copies before any is cleared
 #pragma unroll
-    for (int c = 0; c < kAccCopies; ++c)
+        for (int c = 0; c < kAccCopies; ++c)
 #pragma unroll
-        for (int i = 0; i < PER; ++i) a[c * nb + lc[i]] = 0;
-    int64_t *dst = out.p[ch];
-    if (!dst) return;  // uniform
-    // thread t scans the levels [t * per, (t + 1) * per)
-    const int per = (L + kMergeChThreads - 1) / kMergeChThreads;
-    const int beg = t * per < L ? t * per : L, end = beg + per < L ? beg + per : L;
-    int64_t sum = 0;
-    for (int i = beg; i < end; ++i) sum += tot[i];
-    int64_t x = sum;
+            for (int i = 0; i < PER; ++i) a[c * nb + lc[i]] = 0;
+        // thread t scans the chunk's levels [t * per, (t + 1) * per)
+        const int per = (n + kMergeChThreads - 1) / kMergeChThreads;
+        const int beg = t * per < n ? t * per : n, end = beg + per < n ? beg + per : n;
+        int64_t sum = 0;
+        for (int i = beg; i < end; ++i) sum += tot[i];
+        int64_t x = sum;
 #pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-        const int64_t y = __shfl_up(x, off);
-        if (lane >= off) x += y;
-    }
-    if (lane == 63) wsum[wave] = x;
-    __syncthreads();
-    int64_t run = x - sum;
-    for (int k = 0; k < wave; ++k) run += wsum[k];
-    for (int i = beg; i < end; ++i) {
-        run += tot[i];
-        dst[i] = run;
+        for (int off = 1; off < 64; off <<= 1) {
+            const int64_t y = __shfl_up(x, off);
+            if (lane >= off) x += y;
+        }
+        if (lane == 63) wsum[wave] = x;
+        __syncthreads();
+        int64_t run = carry + x - sum;
+        for (int k = 0; k < wave; ++k) run += wsum[k];
+        if (dst)  // uniform
+            for (int i = beg; i < end; ++i) {
+                run += tot[i];
+                dst[l0 + i] = run;
+            }
+        for (int k = 0; k < kMergeChThreads / 64; ++k) carry += wsum[k];
+        __syncthreads();  // tot and wsum are reused by the next chunk
     }
 }
 
@@ -175,16 +150,19 @@ int launch_merge_acc(int64_t *acc, int copies, int nch, int L, int64_t *const ou
                      unsigned *counter, void *stream) {
     OutPtrs o;
     for (int c = 0; c < 4; ++c) o.p[c] = c < nch ? out[c] : nullptr;
-    if (copies != kAccCopies) return (int)hipErrorInvalidValue;
-    if (L <= kMergeChMaxLevels && nch <= 4) {
-        hipLaunchKernelGGL(ecc_merge_acc_ch, dim3(nch), dim3(kMergeChThreads), 0, (hipStream_t)stream, acc, nch, L,
-                           o);
-        return (int)hipGetLastError();
-    }
-    const int64_t bins = (int64_t)nch * L;
-    const int blocks = (int)std::min<int64_t>(64, (bins + 1023) / 1024);
-    hipLaunchKernelGGL(ecc_merge_acc, dim3(blocks), dim3(1024), 0, (hipStream_t)stream, acc, nch, L, o, totals,
-                       counter);
+    (void)totals;
+    (void)counter;
+    if (copies != kAccCopies || nch > 4) return (int)hipErrorInvalidValue;
+    hipLaunchKernelGGL(ecc_merge_acc_ch, dim3(nch), dim3(kMergeChThreads), 0, (hipStream_t)stream, acc, nch, L, o,
+                       (int64_t *)nullptr);
+    return (int)hipGetLastError();
+}
+
+int launch_merge_acc_rows(int64_t *acc, int nch, int L, int64_t *rows, void *stream) {
+    if (nch > 64) return (int)hipErrorInvalidValue;
+    OutPtrs o{{nullptr, nullptr, nullptr, nullptr}};
+    hipLaunchKernelGGL(ecc_merge_acc_ch, dim3(nch), dim3(kMergeChThreads), 0, (hipStream_t)stream, acc, nch, L, o,
+                       rows);
     return (int)hipGetLastError();
 }
 

@@ -80,7 +80,8 @@ struct ecc_context_s {
     int64_t *d_vtab3[2] = {nullptr, nullptr};    // 3D per-vertex table, 26-C and 6-C
     uint32_t *d_zm3[2] = {nullptr, nullptr};     // 3D z-marching tables, 26-C and 6-C
     uint64_t *d_cls2 = nullptr;                  // 2D per-cell class-count deltas, 2 x 256 words
-    int64_t *d_cls3 = nullptr;                   // 3D class of each octant mask (-1 empty)
+    uint16_t *d_trans3 = nullptr;                // 3D class transitions per corner and octant mask, [8][256]
+    size_t max_lds = 0;                          // LDS bytes one workgroup may use
     uint32_t *d_crease3 = nullptr;               // 3D crease by z-marching: per-plane deltas + 4
     std::vector<ecc::ThrEntry *> thr_cache;
     uint64_t thr_tick = 0;

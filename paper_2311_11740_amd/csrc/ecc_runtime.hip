@@ -135,6 +135,7 @@ extern "C" ecc_status ecc_create(int device, ecc_context *out) {
     auto *ctx = new ecc_context_s();
     ctx->device = device;
     ctx->n_cu = prop.multiProcessorCount;
+    ctx->max_lds = prop.sharedMemPerBlock;
     ctx->arch = prop.gcnArchName;
     // per-cell delta tables (2D) and per-vertex tables (3D)
     for (int k = 0; k < 2; ++k) {
@@ -204,9 +205,9 @@ extern "C" ecc_status ecc_create(int device, ecc_context *out) {
             ecc_destroy(ctx);
             return s;
         }
-        int64_t c3[256];  // class of each 3D octant mask, -1 for empty
-        for (int m = 0; m < 256; ++m) c3[m] = octant_class_3d(m);
-        s = upload((void **)&ctx->d_cls3, c3, sizeof(c3));
+        uint16_t t3[8][256];  // 3D class transitions of the corners of an entering voxel
+        class_transitions_3d(t3);
+        s = upload((void **)&ctx->d_trans3, t3, sizeof(t3));
         if (s != ECC_OK) {
             ecc_destroy(ctx);
             return s;
@@ -266,7 +267,7 @@ extern "C" ecc_status ecc_destroy(ecc_context ctx) {
         if (ctx->d_zm3[k]) hipFree(ctx->d_zm3[k]);
     }
     if (ctx->d_cls2) hipFree(ctx->d_cls2);
-    if (ctx->d_cls3) hipFree(ctx->d_cls3);
+    if (ctx->d_trans3) hipFree(ctx->d_trans3);
     if (ctx->d_crease3) hipFree(ctx->d_crease3);
     for (auto *t : ctx->thr_cache) free_thresholds(t);
     ctx->thr_cache.clear();
@@ -783,7 +784,7 @@ ecc_status compute_core(ecc_context ctx, const ecc_field *f, const FieldInfo &fi
         } else {
             Launch3D a{data, fi.dtype, fi.d, fi.h, fi.w, lv, lo, hi, ctx->d_vtab3[k], partial, p.grid,
                        p.zmarch ? false : p.crease, p.zmarch ? ctx->d_zm3[k] : nullptr, k == 1, 0, fi.d, false,
-                       false, p.zmarch && p.crease ? ctx->d_crease3 : nullptr};
+                       p.zmarch && p.crease ? ctx->d_crease3 : nullptr};
             a.ev_start = ev0;
             a.ev_stop = ev1;
             a.acc = acc;
@@ -837,45 +838,40 @@ static ecc_status merge_classes(ecc_context ctx, int grid, int nch, int L, int64
     return ECC_OK;
 }
 
-// workgroups per CU of the 3D class-count kernel (ECC_CLS3_WG_PER_CU, default 2)
-static int cls3_wg_per_cu() {
-    const char *e = std::getenv("ECC_CLS3_WG_PER_CU");
-    const int x = e ? std::atoi(e) : 2;
-    return x < 1 ? 1 : (x > 3 ? 3 : x);
-}
-
-// Class counts of a 3D field: the tile kernel in class-count mode, passes of
-// kClsWindow3D levels (the class bins take kNumClasses3D x 4 bytes per level
-// of LDS), then the merges.
+// Class counts of a 3D field: passes over windows of as many levels as one
+// workgroup's LDS holds bins for (21 int32 per level, next to the staged tile),
+// one 1024-thread workgroup per CU adding into the per-XCD accumulators, then
+// one merge that scans every class.
 static ecc_status compute_classes_3d(ecc_context ctx, const ecc_field *f, const FieldInfo &fi, int64_t *counts,
                                      void *stream) {
     LevelArgs lv;
     ecc_status s = level_args(ctx, f, fi, stream, &lv);
     if (s != ECC_OK) return s;
     const int L = fi.L, nch = kNumClasses3D;
-    const int win = std::min(L, kClsWindow3D);
-    const int64_t n_tiles = ((fi.w + kTile3DX - 1) / kTile3DX) * ((fi.h + kTile3DY - 1) / kTile3DY) *
-                            ((fi.d + kTile3DZ - 1) / kTile3DZ);
-    // two workgroups per CU (the class bins of a 512-level pass take 43 KB of LDS)
-    int grid = (int)std::min<int64_t>((int64_t)ctx->n_cu * cls3_wg_per_cu(), n_tiles);
-    if (grid < 1) grid = 1;
-    s = grow(ctx, ctx->ws.partial, (size_t)grid * nch * L * sizeof(int32_t), "partials");
+    const size_t fixed = lds_fixed_classes_3d() + 64 * sizeof(int32_t);
+    const int win_max = ctx->max_lds > fixed ? (int)((ctx->max_lds - fixed) / (nch * sizeof(int32_t))) : 0;
+    if (win_max < 1) return fail(ECC_ERR_DEVICE, "3D class counts: not enough LDS per workgroup");
+    const int passes = (L + win_max - 1) / win_max;
+    const int win = (L + passes - 1) / passes;
+    int64_t *acc = nullptr;
+    s = acc_buffer(ctx, nch, L, &acc, stream);
     if (s != ECC_OK) return s;
-    int32_t *partial = (int32_t *)ctx->ws.partial.ptr;
+    ctx->acc_dirty = true;
+    const int64_t n_tiles = ((fi.w + 63) / 64) * ((fi.h + 7) / 8) * ((fi.d + 15) / 16);
+    const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(ctx->n_cu, n_tiles));
     for (int lo = 0; lo < L; lo += win) {
-        const int hi = std::min(L, lo + win);
-        Launch3D a{f->data, fi.dtype, fi.d, fi.h, fi.w, lv, lo, hi, ctx->d_cls3, partial, grid, false,
-                   nullptr, false, 0, fi.d, false, true, nullptr};
+        Launch3DClasses a{f->data, fi.dtype, fi.d, fi.h, fi.w, lv, lo, std::min(L, lo + win), ctx->d_trans3, acc, grid};
         hipEvent_t ev0, ev1;
         s = prof_events(ctx, &ev0, &ev1);
         if (s != ECC_OK) return s;
         a.ev_start = ev0;
         a.ev_stop = ev1;
-        int e = launch_3d(a, stream);
+        int e = launch_classes_3d(a, stream);
         if (e) return hip_fail(e, "3D class-count kernel launch");
     }
-    s = merge_classes(ctx, grid, nch, L, counts, stream);
-    if (s != ECC_OK) return s;
+    int e = launch_merge_acc_rows(acc, nch, L, counts, stream);
+    if (e) return hip_fail(e, "class merge kernel launch");
+    ctx->acc_dirty = false;  // the merge that clears them is queued
     return note_threshold_use(ctx, lv, stream);
 }
 

@@ -198,7 +198,7 @@ ecc_status stream_field(ecc_context ctx, const ecc_field *f, const FieldInfo &fi
             const int hi = std::min(L, lo + win);
             if (is3) {
                 Launch3D la{data_v, fi.dtype, u1, fi.h, fi.w, lv, lo, hi, ctx->d_vtab3[k], partial, grid, false,
-                            ctx->d_zm3[k], k == 1, a, b, slab > 0, false, crease ? ctx->d_crease3 : nullptr};
+                            ctx->d_zm3[k], k == 1, a, b, slab > 0, crease ? ctx->d_crease3 : nullptr};
                 la.acc = acc;
                 e = launch_3d(la, stream);
             } else {

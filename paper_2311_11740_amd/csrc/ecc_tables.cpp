@@ -152,6 +152,17 @@ int octant_class_3d(int mask) {
     return table[mask & 255];
 }
 
+// For each corner c = cx + 2 cy + 4 cz of a voxel and each octant mask m of
+// the 2x2x2 block at that corner (the voxel is bit 7 - c of it): the class of
+// m and of m without the voxel (0xFF when that block is empty).
+void class_transitions_3d(uint16_t out[8][256]) {
+    for (int c = 0; c < 8; ++c)
+        for (int m = 0; m < 256; ++m) {
+            const int cn = octant_class_3d(m), co = octant_class_3d(m & ~(1 << (7 - c)));
+            out[c][m] = (uint16_t)((cn < 0 ? 0 : cn) | (co < 0 ? 0xFF : co) << 8);
+        }
+}
+
 void class_delta_table_2d(int32_t delta[256][5]) {
     // the four vertices at the corners (cr, cc) of pixel p = (0,0), as in
     // cell_delta_table_2d: one class leaves (unless the quadrant was empty)
