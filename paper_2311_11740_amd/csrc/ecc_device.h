@@ -156,6 +156,15 @@ struct Elem<float> {
     __device__ static uint32_t get(const uint32_t (&w)[4], int i) { return w[i]; }
 };
 
+// the bits of one element (float bits, or the integer value)
+template <typename T>
+__device__ __forceinline__ uint32_t elem_bits(const T *p) {
+    if constexpr (sizeof(T) == 4)
+        return __float_as_uint(*p);
+    else
+        return (uint32_t)*p;
+}
+
 template <typename T>
 __device__ __forceinline__ T as_value(uint32_t bits) {
     if constexpr (sizeof(T) == 4)

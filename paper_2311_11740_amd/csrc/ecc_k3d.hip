@@ -95,14 +95,6 @@ struct RawRow3 {
 };
 
 template <typename T>
-__device__ __forceinline__ uint32_t elem_bits(const T *p) {
-    if constexpr (sizeof(T) == 4)
-        return __float_as_uint(*p);
-    else
-        return (uint32_t)*p;
-}
-
-template <typename T>
 __device__ __forceinline__ uint32_t elem3(const RawRow3 &r, int i) {
     if constexpr (sizeof(T) == 1) return (r.w[0] >> (8 * i)) & 0xFFu;
     else if constexpr (sizeof(T) == 2) return (r.w[i >> 1] >> (16 * (i & 1))) & 0xFFFFu;

@@ -54,20 +54,90 @@ __global__ void __launch_bounds__(kCls3Threads)
     uint16_t *q = queue[wave];
     __syncthreads();
 
-    for (int64_t tile = t_beg; tile < t_end; ++tile) {
-        const int64_t x0 = (tile % tiles_x) * kCls3TX;
-        const int64_t y0 = ((tile / tiles_x) % tiles_y) * kCls3TY;
-        const int64_t z0 = (tile / (tiles_x * tiles_y)) * kCls3TZ;
-        // levels of the tile and its halo; outside the field: never (L)
-        for (int e = t; e < kCls3SZ * kCls3SY * kCls3SX; e += kCls3Threads) {
-            const int xx = e % kCls3SX, rest = e / kCls3SX;
-            const int yy = rest % kCls3SY, zz = rest / kCls3SY;
-            const int64_t x = x0 - 1 + xx, y = y0 - 1 + yy, z = z0 - 1 + zz;
-            uint32_t l = (uint32_t)L;
-            if (x >= 0 && x < w && y >= 0 && y < h && z >= 0 && z < d)
-                l = level_of<T, LM>(data[(z * h + y) * w + x], lv, ThrGlobal{lv.thr});
-            (&lam[0][0][0])[e] = (uint16_t)l;
+    // Staging: the staged tile is kCls3SZ x kCls3SY rows of kCls3SX levels;
+    // wave w loads the 64 interior columns of rows w, w + 16, ... (one element
+    // per lane, coalesced) and threads 0..359 the two halo columns.  Every load
+    // is unconditional, at coordinates clamped into the field (cells outside
+    // it are set to "never" when stored), and a tile's loads are issued while
+    // the previous tile is processed.
+    // Tile coordinates step through the workgroup's range (x fastest) without
+    // divisions; rows of the staged tile are addressed by (z h + y) w from
+    // clamped coordinates.
+    constexpr int kRows = kCls3SZ * kCls3SY, kRowIt = (kRows + kCls3Waves - 1) / kCls3Waves;
+    struct TileXYZ {
+        int64_t x0, y0, z0;
+    };
+    auto step = [&](TileXYZ c) {
+        c.x0 += kCls3TX;
+        if (c.x0 >= tiles_x * kCls3TX) {
+            c.x0 = 0;
+            c.y0 += kCls3TY;
+            if (c.y0 >= tiles_y * kCls3TY) {
+                c.y0 = 0;
+                c.z0 += kCls3TZ;
+            }
         }
+        return c;
+    };
+    uint32_t raw[kRowIt + 1];
+    auto clampi = [](int64_t v, int64_t n) { return v < 0 ? 0 : (v >= n ? n - 1 : v); };
+    // offsets of this wave's staged rows from the staged corner (tiles away
+    // from the y and z faces of the field need no clamping)
+    int64_t roff[kRowIt];
+#pragma unroll
+    for (int i = 0; i < kRowIt; ++i) {
+        const int r = min(wave + kCls3Waves * i, kRows - 1);
+        roff[i] = ((int64_t)(r / kCls3SY) * h + r % kCls3SY) * w;
+    }
+    auto load_tile = [&](const TileXYZ &c) {
+        const int64_t x = clampi(c.x0 + lane, w);
+        if (c.y0 >= 1 && c.y0 - 1 + kCls3SY <= h && c.z0 >= 1 && c.z0 - 1 + kCls3SZ <= d) {  // uniform
+            const T *base = data + ((c.z0 - 1) * h + (c.y0 - 1)) * w + x;
+#pragma unroll
+            for (int i = 0; i < kRowIt; ++i) raw[i] = elem_bits(base + roff[i]);
+        } else {
+#pragma unroll
+            for (int i = 0; i < kRowIt; ++i) {
+                const int r = min(wave + kCls3Waves * i, kRows - 1);  // uniform
+                const int64_t y = clampi(c.y0 - 1 + r % kCls3SY, h), z = clampi(c.z0 - 1 + r / kCls3SY, d);
+                raw[i] = elem_bits(data + (z * h + y) * w + x);
+            }
+        }
+        const int r = min(t >> 1, kRows - 1);
+        const int64_t y = clampi(c.y0 - 1 + r % kCls3SY, h), z = clampi(c.z0 - 1 + r / kCls3SY, d);
+        raw[kRowIt] = elem_bits(data + (z * h + y) * w + clampi((t & 1) ? c.x0 + kCls3TX : c.x0 - 1, w));
+    };
+    auto store_tile = [&](const TileXYZ &c) {
+        auto level = [&](uint32_t bits, bool in) {
+            return in ? (uint32_t)level_of<T, LM>(as_value<T>(bits), lv, ThrGlobal{lv.thr}) : (uint32_t)L;
+        };
+        const bool x_in = c.x0 + lane < w;
+#pragma unroll
+        for (int i = 0; i < kRowIt; ++i) {
+            const int r = wave + kCls3Waves * i;
+            if (r < kRows) {  // uniform
+                const int yy = r % kCls3SY, zz = r / kCls3SY;
+                const int64_t y = c.y0 - 1 + yy, z = c.z0 - 1 + zz;
+                const bool yz_in = y >= 0 && y < h && z >= 0 && z < d;  // uniform
+                lam[zz][yy][lane + 1] = (uint16_t)level(raw[i], x_in && yz_in);
+            }
+        }
+        if (t < 2 * kRows) {
+            const int r = t >> 1, yy = r % kCls3SY, zz = r / kCls3SY;
+            const int xx = (t & 1) ? kCls3SX - 1 : 0;
+            const int64_t x = c.x0 - 1 + xx, y = c.y0 - 1 + yy, z = c.z0 - 1 + zz;
+            lam[zz][yy][xx] = (uint16_t)level(raw[kRowIt], x >= 0 && x < w && y >= 0 && y < h && z >= 0 && z < d);
+        }
+    };
+    TileXYZ cur{(t_beg % tiles_x) * kCls3TX, ((t_beg / tiles_x) % tiles_y) * kCls3TY,
+                (t_beg / (tiles_x * tiles_y)) * kCls3TZ};
+    if (t_beg < t_end) load_tile(cur);
+
+    for (int64_t tile = t_beg; tile < t_end; ++tile) {
+        const int64_t x0 = cur.x0, y0 = cur.y0, z0 = cur.z0;
+        store_tile(cur);
+        cur = step(cur);
+        if (tile + 1 < t_end) load_tile(cur);  // in flight while this tile is processed
         __syncthreads();
         int qn = 0;  // voxels waiting in this wave's queue (wave-uniform)
         // voxel v of the tile: x = v % 64 (the lane), y = v / 64 % 8, z = v / 512
@@ -88,15 +158,25 @@ __global__ void __launch_bounds__(kCls3Threads)
                 if (act) {
                     const int v = q[lane];
                     const int x = v & 63, y = (v >> 6) & 7, z = v >> 9;
-                    const uint16_t *b = &lam[z][y][x];  // corner (-1, -1, -1) of the 3x3x3 window
+                    // the 3x3x3 window, one pair of dwords per row of three
+                    // (rows are an even number of levels apart, so the first
+                    // level of every row has the parity of the corner's)
+                    static_assert(kCls3SX % 2 == 0, "rows must start on whole dwords");
+                    const int e = (z * kCls3SY + y) * kCls3SX + x;  // corner (-1, -1, -1) of the window
+                    const uint32_t *lw = reinterpret_cast<const uint32_t *>(&lam[0][0][0]) + (e >> 1);
+                    const uint32_t sh = (uint32_t)(e & 1) * 16u;
                     uint32_t win[27];
 #pragma unroll
                     for (int dz = 0; dz < 3; ++dz)
 #pragma unroll
-                        for (int dy = 0; dy < 3; ++dy)
-#pragma unroll
-                            for (int dx = 0; dx < 3; ++dx)
-                                win[dz * 9 + dy * 3 + dx] = b[dz * kCls3SY * kCls3SX + dy * kCls3SX + dx];
+                        for (int dy = 0; dy < 3; ++dy) {
+                            const int o = (dz * kCls3SY * kCls3SX + dy * kCls3SX) / 2;
+                            const uint32_t a = lw[o], c = lw[o + 1];
+                            const uint32_t ab = __builtin_amdgcn_alignbit(c, a, sh);  // levels x-1 and x
+                            win[dz * 9 + dy * 3 + 0] = ab & 0xFFFFu;
+                            win[dz * 9 + dy * 3 + 1] = ab >> 16;
+                            win[dz * 9 + dy * 3 + 2] = (c >> sh) & 0xFFFFu;
+                        }
                     const uint32_t p = win[13];
                     // bit k: neighbour k entered before p (earlier in memory
                     // order wins ties); bit 13 is p itself
