@@ -62,11 +62,13 @@ __global__ void __launch_bounds__(kMergeChThreads)
         unsigned lc[PER];
 #pragma unroll
         for (int i = 0; i < PER; ++i) lc[i] = (unsigned)(l0 + (i * kMergeChThreads + t) % n);
+        // (groups i of 1024 levels past the chunk's end are skipped: uniform)
         int64_t v[kAccCopies][PER];
 #pragma unroll
         for (int c = 0; c < kAccCopies; ++c)
 #pragma unroll
-            for (int i = 0; i < PER; ++i) v[c][i] = __builtin_nontemporal_load(a + c * nb + lc[i]);
+            for (int i = 0; i < PER; ++i)
+                v[c][i] = i * kMergeChThreads < n ? __builtin_nontemporal_load(a + c * nb + lc[i]) : 0;
 #pragma unroll
         for (int i = 0; i < PER; ++i) {
             int64_t s = 0;
@@ -78,7 +80,8 @@ __global__ void __launch_bounds__(kMergeChThreads)
 #pragma unroll
         for (int c = 0; c < kAccCopies; ++c)
 #pragma unroll
-            for (int i = 0; i < PER; ++i) a[c * nb + lc[i]] = 0;
+            for (int i = 0; i < PER; ++i)
+                if (i * kMergeChThreads < n) a[c * nb + lc[i]] = 0;
         // thread t scans the chunk's levels [t * per, (t + 1) * per)
         const int per = (n + kMergeChThreads - 1) / kMergeChThreads;
         const int beg = t * per < n ? t * per : n, end = beg + per < n ? beg + per : n;

@@ -695,16 +695,17 @@ ecc_status acc_buffer(ecc_context ctx, int nch, int L, int64_t **acc, void *stre
 }
 
 // Workgroups of the 2D stream kernel (kWaves2D waves each): one per CU, and
-// at most one per 16 (strip, row) units per wave of the field.  (Its bins of
-// at most kMaxWindow levels plus thresholds and tables take under 50 KB of a
-// CU's 160 KB of LDS.)
+// at most one per 4 (strip, row) units per wave of the field, so that fields
+// of a few million cells still spread over every CU.  (Its bins of at most
+// kMaxWindow levels plus thresholds and tables take under 90 KB of a CU's
+// 160 KB of LDS.)
 int grid_2d(ecc_context ctx, const FieldInfo &fi, int window, bool classes) {
     (void)window;
     (void)classes;
     const int vec = vec_2d(fi.dtype);
     const int64_t strips = (fi.w + 62 * vec - 1) / (62 * vec);
     int grid = (int)std::min<int64_t>((int64_t)ctx->n_cu,
-                                      std::max<int64_t>(1, (strips * fi.h + 16 * kWaves2D - 1) / (16 * kWaves2D)));
+                                      std::max<int64_t>(1, (strips * fi.h + 4 * kWaves2D - 1) / (4 * kWaves2D)));
     if (grid >= 8) grid -= grid % 8;
     return grid;
 }
