@@ -206,9 +206,16 @@ struct LaneDst {
 // pass window and every cell of a halo lane land in bins that are never
 // drained; the atomics stay unconditional, so all table reads of a group are
 // issued before its atomics.
+//
+// The north relation of a pair is the south relation of the pair above it,
+// complemented: up - (mid + 1) = ~(mid - up) per 16-bit half.  So `sc` carries
+// each pair's south difference from one row to the next and enters the
+// pattern in the north position as it is; the tables are indexed with the
+// north bit complemented (kNorthFlip2D).
 template <int VEC, bool CLS>
 __device__ __forceinline__ void emit_row(const uint32_t (&up)[VEC + 1], const uint32_t (&mid)[VEC + 1],
-                                         const uint32_t (&dn)[VEC + 1], const LaneDst &ld, const uint64_t *dl) {
+                                         const uint32_t (&dn)[VEC + 1], uint32_t (&sc)[VEC / 2],
+                                         const LaneDst &ld, const uint64_t *dl) {
     // groups of up to 4 cell pairs: all table reads of a group are issued
     // before its atomics, so the atomics wait for one LDS round trip, not one each
     constexpr int NP = VEC / 2, GP = CLS ? (NP < 2 ? NP : 2) : (NP < 4 ? NP : 4);
@@ -220,10 +227,12 @@ __device__ __forceinline__ void emit_row(const uint32_t (&up)[VEC + 1], const ui
         for (int q = 0; q < GP; ++q) {
             const int j = 2 * (g0 + q) + 1;
             const uint32_t self = mid[j], self1 = self + 0x00010001u;
-            const uint32_t acc = gather_offsets<3>(pk_diff(up[j - 1], self1), pk_diff(up[j], self1),
+            const uint32_t south = pk_diff(dn[j], self);
+            const uint32_t acc = gather_offsets<3>(pk_diff(up[j - 1], self1), sc[g0 + q],
                                                    pk_diff(up[j + 1], self1), pk_diff(mid[j - 1], self1),
-                                                   pk_diff(mid[j + 1], self), pk_diff(dn[j - 1], self),
-                                                   pk_diff(dn[j], self), pk_diff(dn[j + 1], self));
+                                                   pk_diff(mid[j + 1], self), pk_diff(dn[j - 1], self), south,
+                                                   pk_diff(dn[j + 1], self));
+            sc[g0 + q] = south;
             addr[2 * q] = mad_lo16(self, ld.mb, ld.base);
             addr[2 * q + 1] = mad_hi16(self, ld.mb, ld.base);
             dv[2 * q] = lut_lo<uint64_t, 3>(dl, acc);
@@ -260,6 +269,7 @@ __device__ __forceinline__ void stream_run_2d(const T *__restrict__ data, int h,
     const int64_t last_block = (int64_t)h * w > VEC ? (int64_t)h * w - VEC : 0;
 
     uint32_t R[3][VEC + 1];  // R[r % 3] holds row r (relative to ra)
+    uint32_t sc[VEC / 2];    // south differences of the row above (see emit_row)
     RawRow ring[PF];
     {
         RawRow r0, r1;
@@ -273,28 +283,33 @@ __device__ __forceinline__ void stream_run_2d(const T *__restrict__ data, int h,
         }
         convert_row<T, LM>(r0, ra - 1 >= 0, full, lv, thr, lo, W, cpass, lb, R[2]);
         convert_row<T, LM>(r1, true, full, lv, thr, lo, W, cpass, lb, R[0]);
+#pragma unroll
+        for (int q = 0; q < VEC / 2; ++q) sc[q] = pk_diff(R[0][2 * q + 1], R[2][2 * q + 1]);
     }
     int r0 = ra;
-    // full blocks of PF rows: no conditional loads, so PF loads stay in flight
-    for (; r0 + PF <= rb; r0 += PF) {
+    // full blocks of PF rows: no conditional loads, so PF loads stay in flight;
+    // the field's last row (whose row below is outside the field) is left to
+    // the remainder, so that here every row below lies inside the field
+    const int rb_full = rb == h ? rb - 1 : rb;
+    for (; r0 + PF <= rb_full; r0 += PF) {
         pp.update(done0 + (r0 - ra));
 #pragma unroll
         for (int k = 0; k < PF; ++k) {
             const int r = r0 + k;  // current row (buffer k%3); ring[k] holds row r + 1
-            convert_row<T, LM>(ring[k], r + 1 < h, full, lv, thr, lo, W, cpass, lb, R[(k + 1) % 3]);
+            convert_row<T, LM>(ring[k], true, full, lv, thr, lo, W, cpass, lb, R[(k + 1) % 3]);
             const int nx = r + 1 + PF < rb ? r + 1 + PF : rb;
             fetch_row<T, AL>(data, clamp_row(nx), w, x0, last_block, ring[k]);
-            emit_row<VEC, CLS>(R[(k + 2) % 3], R[k % 3], R[(k + 1) % 3], ld, dl);
+            emit_row<VEC, CLS>(R[(k + 2) % 3], R[k % 3], R[(k + 1) % 3], sc, ld, dl);
         }
     }
-    // remaining rows (fewer than PF); here r - ra = r0 - ra + k with r0 - ra
+    // remaining rows (at most PF); here r - ra = r0 - ra + k with r0 - ra
     // a multiple of PF, so the buffer roles are those of k again
 #pragma unroll
     for (int k = 0; k < PF; ++k) {
         const int r = r0 + k;
         if (r < rb) {
             convert_row<T, LM>(ring[k], r + 1 < h, full, lv, thr, lo, W, cpass, lb, R[(k + 1) % 3]);
-            emit_row<VEC, CLS>(R[(k + 2) % 3], R[k % 3], R[(k + 1) % 3], ld, dl);
+            emit_row<VEC, CLS>(R[(k + 2) % 3], R[k % 3], R[(k + 1) % 3], sc, ld, dl);
         }
     }
 }

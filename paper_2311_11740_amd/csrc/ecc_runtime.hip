@@ -142,9 +142,9 @@ extern "C" ecc_status ecc_create(int device, ecc_context *out) {
         const int conn2 = k == 0 ? 8 : 4;
         int32_t dt[256][3];
         cell_delta_table_2d(conn2, dt);
-        uint64_t packed[256];  // in the kernels' index order
+        uint64_t packed[256];  // in the 2D kernels' index order
         for (int n = 0; n < 256; ++n) {
-            const int p = pattern_of_index(n);
+            const int p = pattern_of_index(n ^ kNorthFlip2D);
             packed[n] = (uint64_t)(dt[p][0] + kEcBias2) |
                         (uint64_t)(dt[p][1] + kPerBias2) << kShiftPer2 | 1ull << kShiftCnt2;
         }
@@ -189,12 +189,12 @@ extern "C" ecc_status ecc_create(int device, ecc_context *out) {
         }
     }
     {
-        // class-count deltas, two words per pattern in the kernels' index order
+        // class-count deltas, two words per pattern in the 2D kernels' index order
         int32_t ct[256][5];
         class_delta_table_2d(ct);
         uint64_t packed[512];
         for (int n = 0; n < 256; ++n) {
-            const int p = pattern_of_index(n);
+            const int p = pattern_of_index(n ^ kNorthFlip2D);
             packed[n] = (uint64_t)(ct[p][0] + kClsBias) | (uint64_t)(ct[p][1] + kClsBias) << kClsShift1 |
                         1ull << kClsShift2;
             packed[256 + n] = (uint64_t)(ct[p][2] + kClsBias) | (uint64_t)(ct[p][3] + kClsBias) << kClsShift1 |
