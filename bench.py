@@ -42,21 +42,22 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def load_traffic(kernel: str, workload: str):
-    """HBM bytes per launch from committed rocprofv3 counter runs, if they were
-    taken on the current kernel source."""
+def load_profile(kernel: str, workload: str):
+    """HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE runs) and the
+    kernel's average duration under rocprofv3 --kernel-trace, from the
+    committed profiles, if they were taken on the current kernel source."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
-        return None
+        return None, None
     try:
         with open(path) as f:
             d = json.load(f)
         e = d.get(workload, {})
         if e.get("kernel") == kernel and e.get("source_hash") == kernel_source_hash():
-            return e.get("bytes_per_launch")
+            return e.get("bytes_per_launch"), e.get("kernel_avg_us")
     except (OSError, ValueError):
         pass
-    return None
+    return None, None
 
 
 def make_workload(name: str):
@@ -177,7 +178,7 @@ def measure(ctx, spec, steps, warmup, copies, with_cpu):
     alg_bytes = cells * elem  # the field-reading kernel reads every cell once per step
     launches_per_step = r["kernel_launches"] / max(1, steps)
     achieved = alg_bytes / (r["kernel_ms_per_step"] / 1e3) / 1e9
-    traffic = load_traffic(kernel, spec.meta["name"])
+    traffic, prof_us = load_profile(kernel, spec.meta["name"])
     out = dict(
         workload=spec.meta["name"], cells=cells, bytes=alg_bytes,
         gvox_s=round(value, 3), ms_per_step=round(r["ms_per_step"], 4),
@@ -185,8 +186,11 @@ def measure(ctx, spec, steps, warmup, copies, with_cpu):
         roofline=dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                       frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic, kernel=kernel,
                       kernel_ms_per_launch=round(r["kernel_ms"], 4),
-                      timing="HIP events recorded by the kernel's own dispatch (start and end of the "
-                             "kernel, no launch overhead), on its stream",
+                      timing="HIP events passed to the kernel's own dispatch (hipExtLaunchKernel) on its "
+                             "stream; the interval also holds the marker packets HIP adds for the events "
+                             "(rocprofv3 shows them as 4-5 us between dispatches), so it is longer than "
+                             "the kernel's duration under rocprofv3 (rocprof_kernel_us)",
+                      rocprof_kernel_us=prof_us,
                       launches_per_step=launches_per_step,
                       alg_bytes_per_launch=int(alg_bytes / launches_per_step)),
         spec=spec, curves=r["curves"])

@@ -959,15 +959,25 @@ extern "C" ecc_status ecc_validate_field(const ecc_field *field, const ecc_curve
 }
 
 namespace ecc {
+// Timing events are created without the system-scope fence (a cache
+// write-back and invalidate when the event is recorded), which would run
+// inside the measured interval and hold back the work after it.  They are only
+// read for elapsed times, never to order memory.
+static ecc_status timing_event_pair(hipEvent_t *a, hipEvent_t *b) {
+    int e = (int)hipEventCreateWithFlags(a, hipEventDisableSystemFence);
+    if (e) return hip_fail(e, "hipEventCreateWithFlags");
+    e = (int)hipEventCreateWithFlags(b, hipEventDisableSystemFence);
+    if (e) return hip_fail(e, "hipEventCreateWithFlags");
+    return ECC_OK;
+}
+
 ecc_status prof_begin(ecc_context ctx, void *stream, int *slot) {
     *slot = -1;
     if (!ctx->prof_on) return ECC_OK;
     if (ctx->prof_used == ctx->prof_events.size()) {
         hipEvent_t a, b;
-        int e = (int)hipEventCreate(&a);
-        if (e) return hip_fail(e, "hipEventCreate");
-        e = (int)hipEventCreate(&b);
-        if (e) return hip_fail(e, "hipEventCreate");
+        ecc_status s = timing_event_pair(&a, &b);
+        if (s != ECC_OK) return s;
         ctx->prof_events.push_back({a, b});
     }
     *slot = (int)ctx->prof_used++;
@@ -988,10 +998,8 @@ ecc_status prof_events(ecc_context ctx, hipEvent_t *start, hipEvent_t *stop) {
     if (!ctx->prof_on) return ECC_OK;
     if (ctx->prof_used == ctx->prof_events.size()) {
         hipEvent_t a, b;
-        int e = (int)hipEventCreate(&a);
-        if (e) return hip_fail(e, "hipEventCreate");
-        e = (int)hipEventCreate(&b);
-        if (e) return hip_fail(e, "hipEventCreate");
+        ecc_status s = timing_event_pair(&a, &b);
+        if (s != ECC_OK) return s;
         ctx->prof_events.push_back({a, b});
     }
     const size_t slot = ctx->prof_used++;
