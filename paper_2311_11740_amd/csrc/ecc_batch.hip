@@ -177,7 +177,7 @@ void fill_desc_2d(BatchField2D &d, const ecc_field &f, const ecc_curves &c, cons
     d.conn_idx = fi.conn == 8 ? 0 : 1;
     d.inv_step = lv.inv_step;
     d.neg = lv.neg;
-    d.cpass = (float)(lv.u0d + kBinOff + 0.5);
+    d.cpass = pass_constant(lv.u0d, 0);
     d.eps = lv.eps;
 }
 

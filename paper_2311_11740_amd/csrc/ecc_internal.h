@@ -84,10 +84,11 @@ struct LevelArgs {
     const uint16_t *lut;  // device, 256 or 65536 entries (LM_LUT)
     float u0, inv_step;   // LM_AFFINE: u = fma(x, inv_step, u0) ~ (x - t_0) / step
     double u0d;           // LM_AFFINE: u0 before rounding to float
-    float eps;            // LM_AFFINE: where the fractional part of u is farther than
-                          // eps from an integer, floor(u)+1 is the exact level (the host
-                          // bounds the grid deviation and the rounding of u by eps/2);
-                          // elsewhere the level is settled against the thresholds
+    float eps;            // LM_AFFINE: where the estimate is farther than eps from a
+                          // level boundary it is the exact level; elsewhere the level is
+                          // settled against the thresholds (level form, and bin form of
+                          // the pass window at level 0)
+    float eps_far;        // LM_AFFINE: the same for the bin form of any pass window
     uint32_t neg;         // 0, or the sign bit for the superlevel filtration: thr holds
                           // -t, every threshold comparison takes -x (x ^ neg), and
                           // inv_step already carries the sign (fma(x, -s, u0) =

@@ -1,6 +1,7 @@
 // 2D kernels: the single-field row-streaming kernel (curves and vertex class
 // counts) and the batched persistent kernel, with their launchers.
 #include "ecc_device.h"
+#include "ecc_levels.h"
 #include "ecc_schedule.h"
 
 namespace ecc {
@@ -430,6 +431,7 @@ __global__ void __launch_bounds__(256)
         lv.inv_step = f.inv_step;
         lv.u0d = 0.0;
         lv.eps = f.eps;
+        lv.eps_far = f.eps;  // one pass window, starting at level 0
         lv.neg = f.neg;
         const ThrLds thr{thr_s, -2};
         const LaneBins lb{(uint32_t)lane, (uint32_t)(L + kBinOff + lane)};
@@ -499,8 +501,11 @@ static int launch_2d_t(const Launch2D &a, hipStream_t s) {
     int64_t chunk = a.row_hi - a.row_lo;
     while (chunk > 1 && max_wg_cells_2d(chunk, a.w, VEC, a.grid) > flush) chunk = (chunk + 1) / 2;
     if (max_wg_cells_2d(chunk, a.w, VEC, a.grid) > flush) return (int)hipErrorInvalidValue;
-    // affine levels: the pass constant -t0/step + kBinOff + 0.5 - lo, rounded once
-    const float cpass = (float)(a.lv.u0d + kBinOff + 0.5 - a.lo);
+    // affine levels: the pass constant -t0/step + kBinOff + 0.5 - lo, rounded
+    // once, and the margin that holds for it
+    const float cpass = pass_constant(a.lv.u0d, a.lo);
+    LevelArgs lv = a.lv;
+    if (a.lo != 0) lv.eps = lv.eps_far;
     const size_t lds = lds_bytes_2d(W, CLS);
     for (int64_t r0 = a.row_lo; r0 < a.row_hi; r0 += chunk) {
         const int64_t r1 = r0 + chunk < a.row_hi ? r0 + chunk : a.row_hi;
@@ -508,7 +513,7 @@ static int launch_2d_t(const Launch2D &a, hipStream_t s) {
         hipExtLaunchKernelGGL((ecc2d_stream<T, LM, AL, PF, CLS>), dim3(a.grid), dim3(64 * kWaves2D), lds, s,
                               r0 == a.row_lo ? (hipEvent_t)a.ev_start : nullptr,
                               r1 == a.row_hi ? (hipEvent_t)a.ev_stop : nullptr, 0, (const T *)a.data, a.h, a.w,
-                              a.lv, a.lo, a.hi, cpass, a.delta_lut, a.partial, r0, r1, acc ? 1 : 0,
+                              lv, a.lo, a.hi, cpass, a.delta_lut, a.partial, r0, r1, acc ? 1 : 0,
                               progress_prio() ? 1 : 0, CLS ? nullptr : a.acc);
         const int e = (int)hipGetLastError();
         if (e) return e;

@@ -2,6 +2,7 @@
 // kernel (curves with the crease measure, vertex class counts), with their
 // launchers.
 #include "ecc_device.h"
+#include "ecc_levels.h"
 #include "ecc_schedule.h"
 
 namespace ecc {
@@ -890,6 +891,7 @@ __global__ void __launch_bounds__(256)
         lv.inv_step = f.inv_step;
         lv.u0d = 0.0;
         lv.eps = f.eps;
+        lv.eps_far = f.eps;
         lv.neg = f.neg;
         const int64_t *vtab = vt[f.conn_idx];
         const VolumeLevels<T, LM> src{(const T *)f.data, f.h, f.w, lv};
@@ -1155,7 +1157,9 @@ static int launch_zm_t(const Launch3D &a, hipStream_t s) {
     int64_t chunk = a.z_hi - a.z_lo;
     while (chunk > 1 && max_wg_cells_3d(cols, chunk, a.grid) > kFlush3D) chunk = (chunk + 1) / 2;
     if (max_wg_cells_3d(cols, chunk, a.grid) > kFlush3D) return (int)hipErrorInvalidValue;
-    const float cpass = (float)(a.lv.u0d + kBinOff + 0.5 - a.lo);
+    const float cpass = pass_constant(a.lv.u0d, a.lo);  // and the margin that holds for it
+    LevelArgs lv = a.lv;
+    if (a.lo != 0) lv.eps = lv.eps_far;
     const size_t lds = (size_t)(W + 2 * kBinOff) * (CR ? 12 : 8) + (kThr ? (size_t)(W + 3) * 4 : 0);
     for (int64_t z0 = a.z_lo; z0 < a.z_hi; z0 += chunk) {
         const int64_t z1 = z0 + chunk < a.z_hi ? z0 + chunk : a.z_hi;
@@ -1163,7 +1167,7 @@ static int launch_zm_t(const Launch3D &a, hipStream_t s) {
         hipExtLaunchKernelGGL((ecc3d_stream<T, LM, AL, MAXIMG, CR, kZmTY>), dim3(a.grid), dim3(256), lds, s,
                               z0 == a.z_lo ? (hipEvent_t)a.ev_start : nullptr,
                               z1 == a.z_hi ? (hipEvent_t)a.ev_stop : nullptr, 0, (const T *)a.data, a.d, a.h, a.w,
-                              a.lv, a.lo, a.hi, cpass, a.zm_tables, a.crease_table, a.partial, z0, z1, acc ? 1 : 0,
+                              lv, a.lo, a.hi, cpass, a.zm_tables, a.crease_table, a.partial, z0, z1, acc ? 1 : 0,
                               progress_prio() ? 1 : 0, a.acc);
         const int e = (int)hipGetLastError();
         if (e) return e;

@@ -96,6 +96,7 @@ extern "C" ecc_status ecc_curves_compute_noalloc(ecc_context ctx, const ecc_fiel
     lv.u0d = 0.0;
     lv.inv_step = 0.f;
     lv.eps = 0.f;
+    lv.eps_far = 0.f;
     lv.neg = 0u;
     if (field->thresholds || fi.super) {
         // stage through the context's pinned buffer (reused once the previous
@@ -121,8 +122,13 @@ extern "C" ecc_status ecc_curves_compute_noalloc(ecc_context ctx, const ecc_fiel
             if (e) return hip_fail(e, "level table kernel");
             lv.mode = LM_LUT;
             lv.lut = lut;
-        } else if (affine_levels(ctx->h_stage, fi.L, &lv.u0, &lv.u0d, &lv.inv_step, &lv.eps)) {
+        } else if (AffineFit fit; affine_levels(ctx->h_stage, fi.L, &fit)) {
             lv.mode = LM_AFFINE;
+            lv.u0 = fit.u0;
+            lv.u0d = fit.u0d;
+            lv.inv_step = fit.inv_step;
+            lv.eps = fit.eps;
+            lv.eps_far = fit.eps_far;
             if (fi.super) lv.inv_step = -lv.inv_step;
         } else {
             lv.mode = LM_SEARCH;

@@ -8,6 +8,7 @@
 #include <vector>
 
 #include "ecc_internal.h"
+#include "ecc_levels.h"
 #include "ecc_schedule.h"
 
 namespace ecc {
@@ -45,7 +46,7 @@ struct ThrEntry {
     uint16_t *d_lut8 = nullptr;
     uint16_t *d_lut16 = nullptr;
     bool affine = false;
-    float u0 = 0.f, inv_step = 0.f, eps = 0.f;
+    float u0 = 0.f, inv_step = 0.f, eps = 0.f, eps_far = 0.f;
     double u0d = 0.0;
     hipEvent_t ready = nullptr, last_use = nullptr;
     void *ready_stream = nullptr;
@@ -156,8 +157,6 @@ ecc_status compute_core(ecc_context ctx, const ecc_field *f, const FieldInfo &fi
 // address of the allocation-free entry point's scratch array on `device`
 // (looked up once per device; the device must be current)
 ecc_status noalloc_scratch(int device, unsigned char **out);
-// the affine level estimate of a threshold array, if it has one (host only)
-bool affine_levels(const float *thr, int L, float *u0, double *u0d, float *inv_step, float *eps);
 int pick_grid(ecc_context ctx, int64_t n_tiles, size_t lds_per_wg);
 // workgroups of the 2D stream kernel for a field
 int grid_2d(ecc_context ctx, const FieldInfo &fi, int window, bool classes);

@@ -380,31 +380,6 @@ static ecc_status evict_threshold(ecc_context ctx, const std::vector<const ThrEn
     return ECC_OK;
 }
 
-// Affine check: the level is estimated from u = fma(x, 1/step, -t0/step) in
-// float32; where the fractional part of u is farther than eps from an
-// integer, floor(u)+1 is the exact level.  eps/2 bounds the thresholds'
-// deviation from the grid t0 + l*step (in steps) plus the rounding of u:
-// 1/step and -t0/step are rounded once each and the fma once, which for
-// |u| <= L + 2 moves u by at most (2 (L + 2) + |t0/step|) 2^-24 (with a 1 %
-// margin).
-bool affine_levels(const float *thr, int L, float *u0, double *u0d, float *inv_step, float *eps) {
-    if (L < 2) return false;
-    const double t0 = thr[0], step = ((double)thr[L - 1] - t0) / (L - 1);
-    if (!(step > 0 && std::isfinite(step) && std::isfinite(t0) && std::isfinite((double)thr[L - 1]))) return false;
-    double dev = 0;
-    for (int l = 0; l < L; ++l) dev = std::max(dev, std::fabs(thr[l] - (t0 + l * step)) / step);
-    const float inv_f = (float)(1.0 / step);
-    const double u0_d = -t0 * (double)inv_f;
-    const double round_u = (2.0 * (L + 2.0) + std::fabs(t0 / step) + 2.0) * 1.01 * std::ldexp(1.0, -24);
-    const double e = 2.0 * (dev + round_u) + 1e-6;
-    if (!(e < 0.25)) return false;
-    *u0 = (float)u0_d;
-    *u0d = u0_d;
-    *inv_step = inv_f;
-    *eps = (float)e;
-    return true;
-}
-
 ecc_status get_thresholds(ecc_context ctx, const float *thr, int L, bool neg, int dtype, void *stream,
                           const ThrEntry **out) {
     ThrEntry *hit = find_thresholds(ctx, thr, L, neg);
@@ -441,7 +416,13 @@ ecc_status get_thresholds(ecc_context ctx, const float *thr, int L, bool neg, in
             return hip_fail(e, "hipMemcpyAsync(thresholds)");
         }
         t->ready_stream = stream;
-        t->affine = affine_levels(t->h_pinned, L, &t->u0, &t->u0d, &t->inv_step, &t->eps);
+        AffineFit fit;
+        t->affine = affine_levels(t->h_pinned, L, &fit);
+        t->u0 = fit.u0;
+        t->u0d = fit.u0d;
+        t->inv_step = fit.inv_step;
+        t->eps = fit.eps;
+        t->eps_far = fit.eps_far;
         ctx->thr_cache.push_back(t);
         hit = t;
     } else if (hit->ready_stream != stream) {
@@ -541,6 +522,7 @@ ecc_status level_args(ecc_context ctx, const ecc_field *f, const FieldInfo &fi, 
     lv->u0d = 0.0;
     lv->inv_step = 0.f;
     lv->eps = 0.f;
+    lv->eps_far = 0.f;
     lv->neg = 0u;
     std::vector<float> tmp;
     const float *thr = field_thresholds(f, tmp);
@@ -567,6 +549,7 @@ ecc_status level_args(ecc_context ctx, const ecc_field *f, const FieldInfo &fi, 
         lv->u0d = te->u0d;
         lv->inv_step = fi.super ? -te->inv_step : te->inv_step;
         lv->eps = te->eps;
+        lv->eps_far = te->eps_far;
     } else {
         lv->mode = LM_SEARCH;
     }
