@@ -386,7 +386,7 @@ def measure_batch(ctx, specs, steps, warmup, workload=None):
         ok &= all(np.array_equal(b.outputs[i][c].cpu().numpy(), r[c]) for c in r)
     px = float(sum(sizes))
     best = min(bd_ms, bt_ms)
-    return dict(
+    return dict(lane_occupancy=lane_occupancy(specs), **dict(
         workload=workload or f"batch_{len(specs)}x_u8_side64-2048_L{L}", fields=len(specs),
         gpx=round(px / 1e9, 4),
         per_field_ms=round(pf_ms, 3), per_field_host_ms=round(pf_wall, 3),
@@ -396,7 +396,26 @@ def measure_batch(ctx, specs, steps, warmup, workload=None):
         batched_kernel_ms=round((kt_ms / max(kt_n, 1)) if bt_ms <= bd_ms else (k_ms / max(k_n, 1)), 4),
         hbm_frac_batched=round(px / best / 1e6 / HBM_PEAK_GBS, 4),
         tune_seconds=round(tune_s, 2), equal_to_per_field=equal, parity_vs_oracle_sample=bool(ok),
-        oracle_sample_fields=len(sample))
+        oracle_sample_fields=len(sample)))
+
+
+def lane_occupancy(specs):
+    """Share of the batched kernels' lane slots that hold cells of the fields.
+    2D: a wave covers a strip of 64 lanes x one 16-byte block per row (lanes 0
+    and 63 only load the neighbouring columns), so a field of width w fills
+    w / (ceil(w / (62 VEC)) * 64 VEC) of its lane slots (VEC cells per 16
+    bytes).  3D: tiles of the tile pass; reported for 2D batches only."""
+    cells = slots = 0
+    for s in specs:
+        a = s.data
+        if a.ndim != 2:
+            return None
+        vec = 16 // a.dtype.itemsize
+        h, w = a.shape
+        strips = -(-w // (62 * vec))
+        cells += h * w
+        slots += h * strips * 64 * vec
+    return round(cells / slots, 4) if slots else None
 
 
 # The paper's own synthetic workloads (white noise translated to 0..255, 8-C

@@ -35,9 +35,10 @@ constexpr int kNumClasses3D = 21;
 // is neighbour 2i and bit 4+i neighbour 2i+1 of kNbr2.  Returns the kNbr2-order
 // pattern of kernel index n.
 int pattern_of_index(int n);
-// The 2D kernels (ecc2d_stream, ecc2d_batch) form that index with the north
-// bit complemented (the north relation enters as the complemented south
-// relation of the row above): their tables hold at index n the entry of
+// The 2D kernels (ecc2d_stream, ecc2d_batch) and the z-marching 3D kernel
+// (its layer and image patterns) form that index with the north bit
+// complemented (the north relation enters as the complemented south relation
+// of the row above): their tables hold at index n the entry of
 // pattern_of_index(n ^ kNorthFlip2D).
 constexpr int kNorthFlip2D = 1 << 4;
 extern const int kNbr2[8][2];

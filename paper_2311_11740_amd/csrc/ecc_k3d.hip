@@ -275,14 +275,20 @@ __device__ __forceinline__ void convert_row3(const RawRow3 &raw_in, bool row_ok,
 
 // 8-neighbour "entered before" pattern of the two cells of pair j (low / high
 // half), rows u (above), m (current), d (below), as offsets into tables of
-// 4-byte entries (lut_lo / lut_hi)
+// 4-byte entries (lut_lo / lut_hi).  The north relation comes in as
+// sn = self - up per 16-bit half: that is the south difference of the row
+// above, complemented (up - (self + 1) = ~(self - up)), so the rows of a
+// column hand it down instead of subtracting again; the tables are indexed
+// with the north bit complemented (kNorthFlip2D).  `south` returns this row's
+// south difference.
 template <int VEC>
-__device__ __forceinline__ uint32_t pattern_pair(const uint32_t (&u)[VEC + 1], const uint32_t (&m)[VEC + 1],
-                                                 const uint32_t (&d)[VEC + 1], int j) {
+__device__ __forceinline__ uint32_t pattern_pair_sn(const uint32_t (&u)[VEC + 1], const uint32_t (&m)[VEC + 1],
+                                                    const uint32_t (&d)[VEC + 1], int j, uint32_t sn,
+                                                    uint32_t &south) {
     const uint32_t self = m[j], self1 = self + 0x00010001u;
-    return gather_offsets<2>(pk_diff(u[j - 1], self1), pk_diff(u[j], self1), pk_diff(u[j + 1], self1),
-                             pk_diff(m[j - 1], self1), pk_diff(m[j + 1], self), pk_diff(d[j - 1], self),
-                             pk_diff(d[j], self), pk_diff(d[j + 1], self));
+    south = pk_diff(d[j], self);
+    return gather_offsets<2>(pk_diff(u[j - 1], self1), sn, pk_diff(u[j + 1], self1), pk_diff(m[j - 1], self1),
+                             pk_diff(m[j + 1], self), pk_diff(d[j - 1], self), south, pk_diff(d[j + 1], self));
 }
 
 // pattern of the two cells of `self` from their 8 neighbours in one plane:
@@ -405,11 +411,14 @@ struct March3D {
         }
         uint32_t M[NR][VEC + 1];
         image(R[0], R[1], M);
+        uint32_t snm[VEC / 2];  // north relations of the image rows (see pattern_pair_sn)
+#pragma unroll
+        for (int q = 0; q < VEC / 2; ++q) snm[q] = pk_diff(M[1][2 * q + 1], M[0][2 * q + 1]);
 #pragma unroll
         for (int t = 0; t < TY; ++t)
 #pragma unroll
             for (int j = 1; j < VEC + 1; j += 2) {
-                const uint32_t pm = pattern_pair<VEC>(M[t], M[t + 1], M[t + 2], j);
+                const uint32_t pm = pattern_pair_sn<VEC>(M[t], M[t + 1], M[t + 2], j, snm[j / 2], snm[j / 2]);
                 // voxel za (upper) against voxel za - 1: the upper one is
                 // later in memory, so it precedes only when strictly lower
                 const uint32_t dz = pk_diff(R[1][t + 1][j], R[0][t + 1][j]);
@@ -432,6 +441,13 @@ struct March3D {
         uint32_t M[NR][VEC + 1];
         image(Pc, Pn, M);
         (void)Pp;
+        // north relations of the layer and image rows, handed down the column
+        uint32_t snl[VEC / 2], snm[VEC / 2];
+#pragma unroll
+        for (int q = 0; q < VEC / 2; ++q) {
+            snl[q] = pk_diff(Pc[1][2 * q + 1], Pc[0][2 * q + 1]);
+            snm[q] = pk_diff(M[1][2 * q + 1], M[0][2 * q + 1]);
+        }
 #pragma unroll
         for (int t = 0; t < TY; ++t) {
             // table reads of the row's VEC voxels first, then their atomics
@@ -441,8 +457,8 @@ struct March3D {
             for (int q = 0; q < VEC / 2; ++q) {
                 const int j = 2 * q + 1;
                 const uint32_t self = Pc[t + 1][j];
-                const uint32_t pl = pattern_pair<VEC>(Pc[t], Pc[t + 1], Pc[t + 2], j);
-                const uint32_t pm = pattern_pair<VEC>(M[t], M[t + 1], M[t + 2], j);
+                const uint32_t pl = pattern_pair_sn<VEC>(Pc[t], Pc[t + 1], Pc[t + 2], j, snl[q], snl[q]);
+                const uint32_t pm = pattern_pair_sn<VEC>(M[t], M[t + 1], M[t + 2], j, snm[q], snm[q]);
                 // the voxel above (z+1) is later in memory: it entered first
                 // only when strictly lower
                 dz[q] = pk_diff(Pn[t + 1][j], self);
@@ -459,9 +475,10 @@ struct March3D {
                     const uint32_t pxz = plane_pattern(Pp[t + 1][j - 1], Pp[t + 1][j], Pp[t + 1][j + 1],
                                                        Pc[t + 1][j - 1], Pc[t + 1][j + 1], Pn[t + 1][j - 1],
                                                        Pn[t + 1][j], Pn[t + 1][j + 1], self);
-                    crv[2 * q] = lut_lo<uint32_t, 2>(tc, pl) + lut_lo<uint32_t, 2>(tc, pyz) +
+                    // (the layer pattern indexes the north-flipped half of tc)
+                    crv[2 * q] = lut_lo<uint32_t, 2>(tc + 256, pl) + lut_lo<uint32_t, 2>(tc, pyz) +
                                  lut_lo<uint32_t, 2>(tc, pxz);
-                    crv[2 * q + 1] = lut_hi<uint32_t, 2>(tc, pl) + lut_hi<uint32_t, 2>(tc, pyz) +
+                    crv[2 * q + 1] = lut_hi<uint32_t, 2>(tc + 256, pl) + lut_hi<uint32_t, 2>(tc, pyz) +
                                      lut_hi<uint32_t, 2>(tc, pxz);
                 }
             }
@@ -513,7 +530,7 @@ __global__ void __launch_bounds__(256, (!CR && sizeof(T) < 4 && AL == kLoadAlign
     extern __shared__ uint64_t smem[];
     __shared__ uint32_t tl[256];
     __shared__ uint32_t tm[256];
-    __shared__ uint32_t tc[CR ? 256 : 1];
+    __shared__ uint32_t tc[CR ? 512 : 1];
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int W = hi - lo;
@@ -533,7 +550,10 @@ __global__ void __launch_bounds__(256, (!CR && sizeof(T) < 4 && AL == kLoadAlign
         }
     tl[tid] = tables[tid];
     tm[tid] = tables[256 + tid];
-    if constexpr (CR) tc[tid] = crease_table[tid];
+    if constexpr (CR) {
+        tc[tid] = crease_table[tid];
+        tc[256 + tid] = crease_table[256 + tid];
+    }
     for (int b = tid; b < n_bins; b += 256) {
         hist[b] = 0;
         if constexpr (CR) hc[b] = 0;

@@ -175,8 +175,8 @@ extern "C" ecc_status ecc_create(int device, ecc_context *out) {
         uint32_t zt[512];
         const int sgn = k == 0 ? -1 : 1;
         const uint32_t two_faces = 2u << kShiftSurf3;
-        for (int n = 0; n < 256; ++n) {  // in the kernels' index order
-            const int p = pattern_of_index(n);
+        for (int n = 0; n < 256; ++n) {  // in the kernels' index order, north bit complemented
+            const int p = pattern_of_index(n ^ kNorthFlip2D);
             const int per = 4 - 2 * __builtin_popcount(p & 0x5A);  // N, W, E, S bits
             zt[n] = (uint32_t)(sgn * dt[p][0] + kEcBias3) + ((uint32_t)(per + 8) << kShiftSurf3) -
                     (k == 0 ? two_faces : 0u);
@@ -212,11 +212,16 @@ extern "C" ecc_status ecc_create(int device, ecc_context *out) {
             ecc_destroy(ctx);
             return s;
         }
-        // per-plane crease deltas + 4, in the kernels' index order
+        // per-plane crease deltas + 4, in the kernels' index order: [0, 256)
+        // for the yz and xz plane patterns, [256, 512) with the north bit
+        // complemented for the layer pattern
         int32_t cd[256];
         crease_delta_table_2d(cd);
-        uint32_t tc[256];
-        for (int n = 0; n < 256; ++n) tc[n] = (uint32_t)(cd[pattern_of_index(n)] + 4);
+        uint32_t tc[512];
+        for (int n = 0; n < 256; ++n) {
+            tc[n] = (uint32_t)(cd[pattern_of_index(n)] + 4);
+            tc[256 + n] = (uint32_t)(cd[pattern_of_index(n ^ kNorthFlip2D)] + 4);
+        }
         s = upload((void **)&ctx->d_crease3, tc, sizeof(tc));
         if (s != ECC_OK) {
             ecc_destroy(ctx);
