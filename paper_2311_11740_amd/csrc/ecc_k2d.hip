@@ -315,9 +315,14 @@ __device__ __forceinline__ void stream_run_2d(const T *__restrict__ data, int h,
     }
 }
 
-// Work split: the (strip, row) units of rows [row_lo, row_hi), strip-major,
-// are divided into equal contiguous ranges, one per wave (a range may run from
-// the end of one strip into the next).
+// Work split: the (strip, row) units of rows [row_lo, row_hi) are ordered by
+// bands of B rows, then strip, then row, and divided into equal contiguous
+// ranges, one per wave (a range may run from one strip of a band into the
+// next).  B is the units per wave, so a wave mostly takes one strip of one
+// band, and the waves of a workgroup take neighbouring strips of the same
+// rows: the cache line where two strips meet (each wave's row load reaches 16
+// bytes into the next strip's first line) is fetched once from HBM and then
+// found in the XCD's L2 by the neighbour.
 template <typename T, int LM, int AL, int PF, bool CLS>
 __global__ void __launch_bounds__(64 * kWaves2D)
     ecc2d_stream(const T *__restrict__ data, int64_t h, int64_t w, LevelArgs lv, int32_t lo,
@@ -363,11 +368,15 @@ __global__ void __launch_bounds__(64 * kWaves2D)
     const LaneDst ld{halo ? 0u : 8u * BW, halo ? h0 + 8u * BW * lb.never : h0};
     const ThrLds thr{thr_s, lo - 2};
     const int64_t u_beg = units * gw / NW;
+    const int64_t B = (units + NW - 1) / NW < H ? (units + NW - 1) / NW : H;  // rows per band
+    const int64_t BU = n_strips * B;                                         // units per full band
     ProgressPrio pp;
     pp.init(prio != 0, u_end - u_beg);
     for (int64_t u = u_beg; u < u_end;) {
-        const int64_t strip = u / H, ra = u % H;
-        const int64_t rb = ra + (u_end - u) < H ? ra + (u_end - u) : H;
+        const int64_t band = u / BU, r0 = band * B;
+        const int64_t hb = H - r0 < B ? H - r0 : B;  // rows of this band (the last may be short)
+        const int64_t rem = u - band * BU, strip = rem / hb, ra = r0 + rem % hb;
+        const int64_t rb = ra + (u_end - u) < r0 + hb ? ra + (u_end - u) : r0 + hb;
         stream_run_2d<T, LM, AL, PF, CLS>(data, (int)h, w, lv, thr, lo, W, cpass, dl, strip, (int)(row_lo + ra),
                                           (int)(row_lo + rb), lane, lb, ld, pp, u - u_beg);
         u += rb - ra;
