@@ -266,7 +266,9 @@ int launch_zero(void *p, size_t bytes, void *stream);
 // adds are device-scope atomics, so copies shared by XCDs stay exact)
 constexpr int kAccCopies = 8;
 // accumulators [copies][nch][L] -> totals -> running sums into the curves;
-// leaves the accumulators at zero
+// leaves the accumulators at zero.  `totals` (device, at least nch x L int64,
+// or NULL) holds the chunk totals when L is above 1024 and the merge runs as
+// two kernels
 int launch_merge_acc(int64_t *acc, int copies, int nch, int L, int64_t *const out[4], int64_t *totals,
                      unsigned *counter, void *stream);
 // the same for up to 64 channels of at most 4096 levels, into rows[ch][L]

@@ -107,6 +107,63 @@ __global__ void __launch_bounds__(kMergeChThreads)
     }
 }
 
+// The same for more than kMergeSplit levels, in two short kernels instead of
+// one block walking every chunk of a channel in turn: block (ch, k) sums and
+// clears the copies of levels [k kMergeSplit, (k + 1) kMergeSplit), one level
+// per thread, writes the chunk's own running sums and its total
+// (chunk_tot[ch][k]); ecc_merge_carry then adds to every chunk the totals of
+// the chunks before it.
+constexpr int kMergeSplit = kMergeChThreads;
+__global__ void __launch_bounds__(kMergeChThreads)
+    ecc_merge_acc_split(int64_t *__restrict__ acc, int nch, int L, OutPtrs out, int64_t *__restrict__ chunk_tot) {
+    __shared__ int64_t wsum[kMergeChThreads / 64];
+    const int ch = blockIdx.x, k = blockIdx.y, t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const unsigned nb = (unsigned)(nch * L);
+    int64_t *a = acc + (int64_t)ch * L;
+    const int l0 = k * kMergeSplit, n = L - l0 < kMergeSplit ? L - l0 : kMergeSplit;
+    const bool in = t < n;
+    // unconditional loads; a thread past the chunk's end re-reads level l0 and
+    // discards it, and only the thread that owns a level clears it
+    const unsigned li = (unsigned)(l0 + (in ? t : 0));
+    int64_t v[kAccCopies];
+#pragma unroll
+    for (int c = 0; c < kAccCopies; ++c) v[c] = __builtin_nontemporal_load(a + c * nb + li);
+    int64_t x = 0;
+#pragma unroll
+    for (int c = 0; c < kAccCopies; ++c) x += v[c];
+    if (!in) x = 0;
+    if (in)
+#pragma unroll
+        for (int c = 0; c < kAccCopies; ++c) a[c * nb + li] = 0;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const int64_t y = __shfl_up(x, off);
+        if (lane >= off) x += y;
+    }
+    if (lane == 63) wsum[wave] = x;
+    __syncthreads();
+    int64_t run = x, tot = 0;
+    for (int w = 0; w < kMergeChThreads / 64; ++w) {
+        const int64_t ws = wsum[w];
+        if (w < wave) run += ws;
+        tot += ws;
+    }
+    int64_t *dst = out.p[ch];
+    if (in && dst) dst[l0 + t] = run;
+    if (t == 0) chunk_tot[ch * gridDim.y + k] = tot;
+}
+
+__global__ void __launch_bounds__(kMergeChThreads)
+    ecc_merge_carry(int L, int n_chunks, OutPtrs out, const int64_t *__restrict__ chunk_tot) {
+    const int ch = blockIdx.x, k = blockIdx.y + 1;
+    int64_t *dst = out.p[ch];
+    if (!dst) return;  // uniform
+    int64_t carry = 0;
+    for (int j = 0; j < k; ++j) carry += chunk_tot[ch * n_chunks + j];
+    const int l = k * kMergeSplit + (int)threadIdx.x;
+    if (l < L) dst[l] += carry;
+}
+
 __global__ void ecc_zero(u32x4 *__restrict__ p, int64_t n) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
         p[i] = u32x4{0u, 0u, 0u, 0u};
@@ -153,11 +210,22 @@ int launch_merge_acc(int64_t *acc, int copies, int nch, int L, int64_t *const ou
                      unsigned *counter, void *stream) {
     OutPtrs o;
     for (int c = 0; c < 4; ++c) o.p[c] = c < nch ? out[c] : nullptr;
-    (void)totals;
     (void)counter;
     if (copies != kAccCopies || nch > 4) return (int)hipErrorInvalidValue;
-    hipLaunchKernelGGL(ecc_merge_acc_ch, dim3(nch), dim3(kMergeChThreads), 0, (hipStream_t)stream, acc, nch, L, o,
-                       (int64_t *)nullptr);
+    if (L <= kMergeSplit || !totals) {
+        hipLaunchKernelGGL(ecc_merge_acc_ch, dim3(nch), dim3(kMergeChThreads), 0, (hipStream_t)stream, acc, nch, L,
+                           o, (int64_t *)nullptr);
+        return (int)hipGetLastError();
+    }
+    // more levels: chunks of kMergeSplit levels side by side, then the carries
+    // (the chunk totals take nch x chunks words of the caller's nch x L totals)
+    const int n_chunks = (L + kMergeSplit - 1) / kMergeSplit;
+    hipLaunchKernelGGL(ecc_merge_acc_split, dim3(nch, n_chunks), dim3(kMergeChThreads), 0, (hipStream_t)stream, acc,
+                       nch, L, o, totals);
+    int e = (int)hipGetLastError();
+    if (e) return e;
+    hipLaunchKernelGGL(ecc_merge_carry, dim3(nch, n_chunks - 1), dim3(kMergeChThreads), 0, (hipStream_t)stream, L,
+                       n_chunks, o, (const int64_t *)totals);
     return (int)hipGetLastError();
 }
 
