@@ -212,18 +212,19 @@ int launch_merge_acc(int64_t *acc, int copies, int nch, int L, int64_t *const ou
     for (int c = 0; c < 4; ++c) o.p[c] = c < nch ? out[c] : nullptr;
     (void)counter;
     if (copies != kAccCopies || nch > 4) return (int)hipErrorInvalidValue;
-    if (L <= kMergeSplit || !totals) {
+    if (!totals) {
         hipLaunchKernelGGL(ecc_merge_acc_ch, dim3(nch), dim3(kMergeChThreads), 0, (hipStream_t)stream, acc, nch, L,
                            o, (int64_t *)nullptr);
         return (int)hipGetLastError();
     }
-    // more levels: chunks of kMergeSplit levels side by side, then the carries
-    // (the chunk totals take nch x chunks words of the caller's nch x L totals)
+    // chunks of kMergeSplit levels side by side, then (more than one chunk)
+    // the carries; the chunk totals take nch x chunks words of the caller's
+    // nch x L totals
     const int n_chunks = (L + kMergeSplit - 1) / kMergeSplit;
     hipLaunchKernelGGL(ecc_merge_acc_split, dim3(nch, n_chunks), dim3(kMergeChThreads), 0, (hipStream_t)stream, acc,
                        nch, L, o, totals);
     int e = (int)hipGetLastError();
-    if (e) return e;
+    if (e || n_chunks == 1) return e;
     hipLaunchKernelGGL(ecc_merge_carry, dim3(nch, n_chunks - 1), dim3(kMergeChThreads), 0, (hipStream_t)stream, L,
                        n_chunks, o, (const int64_t *)totals);
     return (int)hipGetLastError();
