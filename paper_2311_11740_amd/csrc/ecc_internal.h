@@ -159,7 +159,16 @@ struct Launch3D {
     void *ev_start = nullptr, *ev_stop = nullptr;
     // atomic drain (z-marching kernel): int64 accumulators [kAccCopies][4][L]
     int64_t *acc = nullptr;
+    // surface and voxel count drained as one word into channel 2 (see
+    // kPackSurf3); the merge must be told the same
+    bool pack_surf = false;
 };
+// Packed drain of volumes below 2^28 voxels: channel 2 of the accumulators
+// takes (surface + kSurfBias3 n) + (n << kPackShift3) in one atomic, which
+// stays exact for any sum over workgroups and copies (surface + 6n <= 12n <
+// 2^36, n < 2^28); channel 3 is left unused.
+constexpr int kPackShift3 = 36;
+constexpr int64_t kPackMaxCells3 = (int64_t)1 << 28;
 
 // 3D vertex class counts (ecc_k3d_cls.hip): one pass over the levels [lo, hi)
 // of a volume; each workgroup adds its bins into the accumulator copy of its
@@ -270,7 +279,7 @@ constexpr int kAccCopies = 8;
 // or NULL) holds the chunk totals when L is above 1024 and the merge runs as
 // two kernels
 int launch_merge_acc(int64_t *acc, int copies, int nch, int L, int64_t *const out[4], int64_t *totals,
-                     unsigned *counter, void *stream);
+                     unsigned *counter, void *stream, int pack_ch = -1);
 // the same for up to 64 channels of at most 4096 levels, into rows[ch][L]
 int launch_merge_acc_rows(int64_t *acc, int nch, int L, int64_t *rows, void *stream);
 // whether the curve kernels (2D stream, 3D z-marching) drain their bins with

@@ -43,7 +43,7 @@ __device__ __forceinline__ void drain_3d(uint64_t *hist, uint32_t *hc, bool crea
 
 // the same bins added into the XCD's accumulator copy [4][L] (atomic drain)
 __device__ __forceinline__ void drain_3d_acc(const uint64_t *hist, const uint32_t *hc, bool crease, int W, int lo,
-                                             int L, int64_t *__restrict__ acc) {
+                                             int L, int64_t *__restrict__ acc, bool pack) {
     int64_t *a = acc + (int64_t)xcc_copy() * 4 * L;
     for (int b = threadIdx.x; b < W; b += blockDim.x) {
         const uint64_t v = hist[b];
@@ -54,8 +54,12 @@ __device__ __forceinline__ void drain_3d_acc(const uint64_t *hist, const uint32_
         const int64_t ec = (int64_t)(v & ((1ull << kShiftSurf3) - 1)) - kEcBias3 * n;
         acc_add(a + lo + b, ec);
         if (crease) acc_add(a + L + lo + b, (int64_t)hc[b] - kCreaseBias3 * n);
-        acc_add(a + 2 * L + lo + b, surf);
-        acc_add(a + 3 * L + lo + b, n);
+        if (pack) {  // uniform
+            acc_add(a + 2 * L + lo + b, surf + kSurfBias3 * n + (n << kPackShift3));
+        } else {
+            acc_add(a + 2 * L + lo + b, surf);
+            acc_add(a + 3 * L + lo + b, n);
+        }
     }
 }
 
@@ -525,7 +529,7 @@ __global__ void __launch_bounds__(256, (!CR && sizeof(T) < 4 && AL == kLoadAlign
     ecc3d_stream(const T *__restrict__ data, int64_t d, int64_t h, int64_t w, LevelArgs lv, int32_t lo,
                  int32_t hi, float cpass, const uint32_t *__restrict__ tables,
                  const uint32_t *__restrict__ crease_table, int32_t *__restrict__ partial, int64_t z_lo,
-                 int64_t z_hi, int accumulate, int prio, int64_t *acc) {
+                 int64_t z_hi, int accumulate, int prio, int64_t *acc, int pack_surf) {
     constexpr int VEC = Elem3<T>::VEC;
     extern __shared__ uint64_t smem[];
     __shared__ uint32_t tl[256];
@@ -587,7 +591,7 @@ __global__ void __launch_bounds__(256, (!CR && sizeof(T) < 4 && AL == kLoadAlign
     }
     __syncthreads();
     if (acc)
-        drain_3d_acc(hist + kBinOff, CR ? hc + kBinOff : nullptr, CR, W, lo, L, acc);
+        drain_3d_acc(hist + kBinOff, CR ? hc + kBinOff : nullptr, CR, W, lo, L, acc, pack_surf != 0);
     else
         drain_3d(hist + kBinOff, CR ? hc + kBinOff : nullptr, CR, W, lo, L, G, wg, partial, accumulate == 0);
 }
@@ -1188,7 +1192,7 @@ static int launch_zm_t(const Launch3D &a, hipStream_t s) {
                               z0 == a.z_lo ? (hipEvent_t)a.ev_start : nullptr,
                               z1 == a.z_hi ? (hipEvent_t)a.ev_stop : nullptr, 0, (const T *)a.data, a.d, a.h, a.w,
                               lv, a.lo, a.hi, cpass, a.zm_tables, a.crease_table, a.partial, z0, z1, acc ? 1 : 0,
-                              progress_prio() ? 1 : 0, a.acc);
+                              progress_prio() ? 1 : 0, a.acc, a.acc && a.pack_surf ? 1 : 0);
         const int e = (int)hipGetLastError();
         if (e) return e;
     }

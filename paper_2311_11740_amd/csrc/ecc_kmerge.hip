@@ -114,10 +114,17 @@ __global__ void __launch_bounds__(kMergeChThreads)
 // (chunk_tot[ch][k]); ecc_merge_carry then adds to every chunk the totals of
 // the chunks before it.
 constexpr int kMergeSplit = kMergeChThreads;
+// With pack_ch >= 0, channel pack_ch holds surface and count packed as the 3D
+// drain writes them (kPackShift3): its block writes both curves (pack_ch and
+// pack_ch + 1) and both chunk totals, and the block of pack_ch + 1 has nothing
+// to do.
 __global__ void __launch_bounds__(kMergeChThreads)
-    ecc_merge_acc_split(int64_t *__restrict__ acc, int nch, int L, OutPtrs out, int64_t *__restrict__ chunk_tot) {
-    __shared__ int64_t wsum[kMergeChThreads / 64];
+    ecc_merge_acc_split(int64_t *__restrict__ acc, int nch, int L, OutPtrs out, int64_t *__restrict__ chunk_tot,
+                        int pack_ch) {
+    __shared__ int64_t wsum[kMergeChThreads / 64], wsum2[kMergeChThreads / 64];
     const int ch = blockIdx.x, k = blockIdx.y, t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    if (pack_ch >= 0 && ch == pack_ch + 1) return;  // uniform: its curve comes from pack_ch
+    const bool packed = ch == pack_ch;
     const unsigned nb = (unsigned)(nch * L);
     int64_t *a = acc + (int64_t)ch * L;
     const int l0 = k * kMergeSplit, n = L - l0 < kMergeSplit ? L - l0 : kMergeSplit;
@@ -128,29 +135,48 @@ __global__ void __launch_bounds__(kMergeChThreads)
     int64_t v[kAccCopies];
 #pragma unroll
     for (int c = 0; c < kAccCopies; ++c) v[c] = __builtin_nontemporal_load(a + c * nb + li);
-    int64_t x = 0;
+    uint64_t sum = 0;
 #pragma unroll
-    for (int c = 0; c < kAccCopies; ++c) x += v[c];
-    if (!in) x = 0;
+    for (int c = 0; c < kAccCopies; ++c) sum += (uint64_t)v[c];
+    if (!in) sum = 0;
     if (in)
 #pragma unroll
         for (int c = 0; c < kAccCopies; ++c) a[c * nb + li] = 0;
+    // packed: surface + 6n in the low kPackShift3 bits, n above
+    const int64_t cnt = packed ? (int64_t)(sum >> kPackShift3) : 0;
+    int64_t x = packed ? (int64_t)(sum & ((1ull << kPackShift3) - 1)) - kSurfBias3 * cnt : (int64_t)sum;
+    int64_t x2 = cnt;
 #pragma unroll
     for (int off = 1; off < 64; off <<= 1) {
-        const int64_t y = __shfl_up(x, off);
-        if (lane >= off) x += y;
+        const int64_t y = __shfl_up(x, off), y2 = __shfl_up(x2, off);
+        if (lane >= off) {
+            x += y;
+            x2 += y2;
+        }
     }
-    if (lane == 63) wsum[wave] = x;
+    if (lane == 63) {
+        wsum[wave] = x;
+        wsum2[wave] = x2;
+    }
     __syncthreads();
-    int64_t run = x, tot = 0;
+    int64_t run = x, tot = 0, run2 = x2, tot2 = 0;
     for (int w = 0; w < kMergeChThreads / 64; ++w) {
-        const int64_t ws = wsum[w];
-        if (w < wave) run += ws;
+        const int64_t ws = wsum[w], ws2 = wsum2[w];
+        if (w < wave) {
+            run += ws;
+            run2 += ws2;
+        }
         tot += ws;
+        tot2 += ws2;
     }
     int64_t *dst = out.p[ch];
     if (in && dst) dst[l0 + t] = run;
     if (t == 0) chunk_tot[ch * gridDim.y + k] = tot;
+    if (packed) {  // uniform
+        int64_t *dst2 = out.p[ch + 1];
+        if (in && dst2) dst2[l0 + t] = run2;
+        if (t == 0) chunk_tot[(ch + 1) * gridDim.y + k] = tot2;
+    }
 }
 
 __global__ void __launch_bounds__(kMergeChThreads)
@@ -207,11 +233,12 @@ int launch_merge(const int32_t *partial, int grid, int nch, int L, int64_t *cons
 }
 
 int launch_merge_acc(int64_t *acc, int copies, int nch, int L, int64_t *const out[4], int64_t *totals,
-                     unsigned *counter, void *stream) {
+                     unsigned *counter, void *stream, int pack_ch) {
     OutPtrs o;
     for (int c = 0; c < 4; ++c) o.p[c] = c < nch ? out[c] : nullptr;
     (void)counter;
     if (copies != kAccCopies || nch > 4) return (int)hipErrorInvalidValue;
+    if (pack_ch >= 0 && (!totals || pack_ch + 1 >= nch)) return (int)hipErrorInvalidValue;
     if (!totals) {
         hipLaunchKernelGGL(ecc_merge_acc_ch, dim3(nch), dim3(kMergeChThreads), 0, (hipStream_t)stream, acc, nch, L,
                            o, (int64_t *)nullptr);
@@ -222,7 +249,7 @@ int launch_merge_acc(int64_t *acc, int copies, int nch, int L, int64_t *const ou
     // nch x L totals
     const int n_chunks = (L + kMergeSplit - 1) / kMergeSplit;
     hipLaunchKernelGGL(ecc_merge_acc_split, dim3(nch, n_chunks), dim3(kMergeChThreads), 0, (hipStream_t)stream, acc,
-                       nch, L, o, totals);
+                       nch, L, o, totals, pack_ch);
     int e = (int)hipGetLastError();
     if (e || n_chunks == 1) return e;
     hipLaunchKernelGGL(ecc_merge_carry, dim3(nch, n_chunks - 1), dim3(kMergeChThreads), 0, (hipStream_t)stream, L,
