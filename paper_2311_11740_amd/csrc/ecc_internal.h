@@ -121,6 +121,7 @@ struct Launch2D {
     void *ev_start = nullptr, *ev_stop = nullptr;
     // atomic drain (curves only): int64 accumulators [kAccCopies][3][L] instead of partials
     int64_t *acc = nullptr;
+    bool pack = false;  // packed perimeter and count (acc only, fields below kPackMaxCells)
 };
 
 size_t lds_bytes_2d(int window, bool classes);
@@ -163,12 +164,14 @@ struct Launch3D {
     // kPackSurf3); the merge must be told the same
     bool pack_surf = false;
 };
-// Packed drain of volumes below 2^28 voxels: channel 2 of the accumulators
-// takes (surface + kSurfBias3 n) + (n << kPackShift3) in one atomic, which
-// stays exact for any sum over workgroups and copies (surface + 6n <= 12n <
-// 2^36, n < 2^28); channel 3 is left unused.
-constexpr int kPackShift3 = 36;
-constexpr int64_t kPackMaxCells3 = (int64_t)1 << 28;
+// Packed drain of fields below 2^28 cells: the boundary channel of the
+// accumulators (2D perimeter, channel 1; 3D surface, channel 2) takes
+// (m + kPackBias n) + (n << kPackShift) in one atomic, m the boundary measure
+// and n the cell count of the bin, and the count channel after it is left
+// unused.  A cell changes the boundary by -4..4 (2D) or -6..6 (3D), so every
+// sum over workgroups and copies stays exact: m + 6n <= 12n < 2^36, n < 2^28.
+constexpr int kPackShift = 36, kPackBias = 6;
+constexpr int64_t kPackMaxCells = (int64_t)1 << 28;
 
 // 3D vertex class counts (ecc_k3d_cls.hip): one pass over the levels [lo, hi)
 // of a volume; each workgroup adds its bins into the accumulator copy of its

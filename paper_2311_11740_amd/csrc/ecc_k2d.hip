@@ -153,7 +153,8 @@ __device__ __forceinline__ void drain_2d(const uint64_t *hist, int W, int lo, in
 }
 
 // the same bins added into the XCD's accumulator copy [3][L] (atomic drain)
-__device__ __forceinline__ void drain_2d_acc(const uint64_t *hist, int W, int lo, int L, int64_t *__restrict__ acc) {
+__device__ __forceinline__ void drain_2d_acc(const uint64_t *hist, int W, int lo, int L, int64_t *__restrict__ acc,
+                                             bool pack) {
     int64_t *a = acc + (int64_t)xcc_copy() * 3 * L;
     for (int b = threadIdx.x; b < W; b += blockDim.x) {
         const uint64_t v = hist[b];
@@ -163,8 +164,12 @@ __device__ __forceinline__ void drain_2d_acc(const uint64_t *hist, int W, int lo
                             kPerBias2 * n;
         const int64_t ec = (int64_t)(v & ((1ull << kShiftPer2) - 1)) - kEcBias2 * n;
         acc_add(a + lo + b, ec);
-        acc_add(a + L + lo + b, per);
-        acc_add(a + 2 * L + lo + b, n);
+        if (pack) {  // uniform
+            acc_add(a + L + lo + b, per + kPackBias * n + (n << kPackShift));
+        } else {
+            acc_add(a + L + lo + b, per);
+            acc_add(a + 2 * L + lo + b, n);
+        }
     }
 }
 
@@ -327,7 +332,7 @@ template <typename T, int LM, int AL, int PF, bool CLS>
 __global__ void __launch_bounds__(64 * kWaves2D)
     ecc2d_stream(const T *__restrict__ data, int64_t h, int64_t w, LevelArgs lv, int32_t lo,
                  int32_t hi, float cpass, const uint64_t *__restrict__ delta_lut, int32_t *__restrict__ partial,
-                 int64_t row_lo, int64_t row_hi, int accumulate, int prio, int64_t *acc) {
+                 int64_t row_lo, int64_t row_hi, int accumulate, int prio, int64_t *acc, int pack) {
     constexpr int VEC = Elem<T>::VEC;
     constexpr int CE = 62 * VEC;
     constexpr int BW = CLS ? 2 : 1;  // words per bin
@@ -385,7 +390,7 @@ __global__ void __launch_bounds__(64 * kWaves2D)
     if constexpr (CLS)
         drain_cls(hist + 2 * kBinOff, W, lo, L, G, wg, partial, accumulate == 0);
     else if (acc)
-        drain_2d_acc(hist + kBinOff, W, lo, L, acc);
+        drain_2d_acc(hist + kBinOff, W, lo, L, acc, pack != 0);
     else
         drain_2d(hist + kBinOff, W, lo, L, G, wg, partial, accumulate == 0);
 }
@@ -523,7 +528,7 @@ static int launch_2d_t(const Launch2D &a, hipStream_t s) {
                               r0 == a.row_lo ? (hipEvent_t)a.ev_start : nullptr,
                               r1 == a.row_hi ? (hipEvent_t)a.ev_stop : nullptr, 0, (const T *)a.data, a.h, a.w,
                               lv, a.lo, a.hi, cpass, a.delta_lut, a.partial, r0, r1, acc ? 1 : 0,
-                              progress_prio() ? 1 : 0, CLS ? nullptr : a.acc);
+                              progress_prio() ? 1 : 0, CLS ? nullptr : a.acc, !CLS && a.acc && a.pack ? 1 : 0);
         const int e = (int)hipGetLastError();
         if (e) return e;
     }

@@ -55,7 +55,7 @@ __device__ __forceinline__ void drain_3d_acc(const uint64_t *hist, const uint32_
         acc_add(a + lo + b, ec);
         if (crease) acc_add(a + L + lo + b, (int64_t)hc[b] - kCreaseBias3 * n);
         if (pack) {  // uniform
-            acc_add(a + 2 * L + lo + b, surf + kSurfBias3 * n + (n << kPackShift3));
+            acc_add(a + 2 * L + lo + b, surf + kPackBias * n + (n << kPackShift));
         } else {
             acc_add(a + 2 * L + lo + b, surf);
             acc_add(a + 3 * L + lo + b, n);

@@ -114,8 +114,8 @@ __global__ void __launch_bounds__(kMergeChThreads)
 // (chunk_tot[ch][k]); ecc_merge_carry then adds to every chunk the totals of
 // the chunks before it.
 constexpr int kMergeSplit = kMergeChThreads;
-// With pack_ch >= 0, channel pack_ch holds surface and count packed as the 3D
-// drain writes them (kPackShift3): its block writes both curves (pack_ch and
+// With pack_ch >= 0, channel pack_ch holds the boundary measure and the count
+// packed as the atomic drains write them (kPackShift): its block writes both curves (pack_ch and
 // pack_ch + 1) and both chunk totals, and the block of pack_ch + 1 has nothing
 // to do.
 __global__ void __launch_bounds__(kMergeChThreads)
@@ -142,9 +142,9 @@ __global__ void __launch_bounds__(kMergeChThreads)
     if (in)
 #pragma unroll
         for (int c = 0; c < kAccCopies; ++c) a[c * nb + li] = 0;
-    // packed: surface + 6n in the low kPackShift3 bits, n above
-    const int64_t cnt = packed ? (int64_t)(sum >> kPackShift3) : 0;
-    int64_t x = packed ? (int64_t)(sum & ((1ull << kPackShift3) - 1)) - kSurfBias3 * cnt : (int64_t)sum;
+    // packed: boundary + kPackBias n in the low kPackShift bits, n above
+    const int64_t cnt = packed ? (int64_t)(sum >> kPackShift) : 0;
+    int64_t x = packed ? (int64_t)(sum & ((1ull << kPackShift) - 1)) - kPackBias * cnt : (int64_t)sum;
     int64_t x2 = cnt;
 #pragma unroll
     for (int off = 1; off < 64; off <<= 1) {

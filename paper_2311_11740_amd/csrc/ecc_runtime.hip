@@ -757,8 +757,8 @@ ecc_status compute_core(ecc_context ctx, const ecc_field *f, const FieldInfo &fi
         data = ctx->d_tiny;
     }
     const int k = p.k;
-    // volumes below 2^28 voxels drain surface and count as one word
-    const bool pack = fi.ndim == 3 && acc && fi.cells < kPackMaxCells3;
+    // fields below 2^28 cells drain the boundary measure and the count as one word
+    const bool pack = acc && fi.cells < kPackMaxCells;
     for (int lo = 0; lo < L; lo += p.win) {
         const int hi = std::min(L, lo + p.win);
         hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -770,6 +770,7 @@ ecc_status compute_core(ecc_context ctx, const ecc_field *f, const FieldInfo &fi
             a.ev_start = ev0;
             a.ev_stop = ev1;
             a.acc = acc;
+            a.pack = pack;
             int e = launch_2d(a, stream);
             if (e) return hip_fail(e, "2D kernel launch");
         } else {
@@ -784,7 +785,7 @@ ecc_status compute_core(ecc_context ctx, const ecc_field *f, const FieldInfo &fi
             if (e) return hip_fail(e, "3D kernel launch");
         }
     }
-    int e = acc ? launch_merge_acc(acc, kAccCopies, p.nch, L, outs, totals, counter, stream, pack ? 2 : -1)
+    int e = acc ? launch_merge_acc(acc, kAccCopies, p.nch, L, outs, totals, counter, stream, pack ? (fi.ndim == 3 ? 2 : 1) : -1)
                 : launch_merge(partial, p.grid, p.nch, L, outs, totals, counter, stream);
     if (e) return hip_fail(e, "merge kernel launch");
     return ECC_OK;

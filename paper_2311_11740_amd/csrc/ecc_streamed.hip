@@ -200,12 +200,13 @@ ecc_status stream_field(ecc_context ctx, const ecc_field *f, const FieldInfo &fi
                 Launch3D la{data_v, fi.dtype, u1, fi.h, fi.w, lv, lo, hi, ctx->d_vtab3[k], partial, grid, false,
                             ctx->d_zm3[k], k == 1, a, b, slab > 0, crease ? ctx->d_crease3 : nullptr};
                 la.acc = acc;
-                la.pack_surf = acc && fi.cells < kPackMaxCells3;
+                la.pack_surf = acc && fi.cells < kPackMaxCells;
                 e = launch_3d(la, stream);
             } else {
                 Launch2D la{data_v, fi.dtype, u1, fi.w, lv, lo, hi, ctx->d_delta2[k], partial, grid,
                             a, b, slab > 0, false};
                 la.acc = acc;
+                la.pack = acc && fi.cells < kPackMaxCells;
                 e = launch_2d(la, stream);
             }
             if (e) return hip_fail(e, "slab kernel launch");
@@ -218,7 +219,7 @@ ecc_status stream_field(ecc_context ctx, const ecc_field *f, const FieldInfo &fi
     int64_t *outs[4];
     for (int ch = 0; ch < 4; ++ch) outs[ch] = host_out[ch] ? dc + (size_t)ch * L : nullptr;
     e = acc ? launch_merge_acc(acc, kAccCopies, nch, L, outs, (int64_t *)ctx->ws.totals.ptr,
-                               (unsigned *)ctx->d_counter, stream, is3 && fi.cells < kPackMaxCells3 ? 2 : -1)
+                               (unsigned *)ctx->d_counter, stream, acc && fi.cells < kPackMaxCells ? (is3 ? 2 : 1) : -1)
             : launch_merge(partial, grid, nch, L, outs, (int64_t *)ctx->ws.totals.ptr, (unsigned *)ctx->d_counter,
                            stream);
     if (e) return hip_fail(e, "merge kernel launch");
